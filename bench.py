@@ -1,0 +1,139 @@
+"""Benchmark of the sensitivity pass + sensitivity sampling on one MI355X.
+
+Workload: the scene-scale configuration: 1,000,000 Gaussians (64 anisotropic
+clusters + 10% uniform background, SH degree 3) seen from 100 jittered-orbit
+views at 1280x720, coreset of m = 100,000 (10%).  One step = one call of
+gs_sensitivity (projection, depth sort, tile binning, both compositing
+passes with the per-Gaussian max-share reduction) followed by one call of
+gs_sample_coreset (quantised CDF, Philox draws, weights), with the scene
+already resident in device memory.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects for the
+dominant kernel's fraction of the VALU issue peak and the FP64 CPU oracle's
+time on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue peak of an MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# non-packed lane operations per second (packed FP32 doubles the FP32 peak to
+# 157.3 TFLOP/s counting an FMA as 2 flops; this path uses no packed math).
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU slots per live ray-Gaussian pair in pass 2: offset (2),
+# quadratic form (5), cutoff select (1), rho (1), c rho (1), share (2),
+# transmittance update (1), running max (1), plus exp2 counted as 4 slots
+# (quarter-rate transcendental).
+OPS_PASS2 = 14 + 4
+OPS_PASS1 = 12 + 4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, views, n_views_total):
+    """FP64 oracle on one of the views (all of its rays), scaled to the full
+    view count.  Runs on all host cores."""
+    from oracle import oracle as ora
+    ora.build(force=False)
+    v1 = views.subset([0])
+    t0 = time.perf_counter()
+    r = ora.sensitivity(scene, v1)
+    dt = time.perf_counter() - t0
+    return {"value": dt * n_views_total * 1e3, "unit": "ms", "cores": os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"1 of {n_views_total} views ({int(v1.size[0,0])}x{int(v1.size[0,1])}, all rays), "
+                      f"{dt:.2f} s measured, scaled x{n_views_total}",
+            "sample_pairs": r["pairs"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--views", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the sensitivity pass would shard views across GPUs and combine "
+              "sensitivities with an element-wise max all-reduce)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_02721_amd as gs
+    import synth
+
+    torch.cuda.set_device(0)
+    log("generating scene ...")
+    scene = synth.make_cluster_scene(1_000_000, 1, 3)
+    views = synth.make_orbit_views(args.views, 101)
+    m, seed = 100_000, 0
+    dsc = gs.DeviceScene.from_scene(scene)
+    torch.cuda.synchronize()
+
+    def step(stats=False, count_pairs=False, scene_dev=dsc):
+        s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs)
+        counts, w, sup = gs.sample_coreset(s, m, seed)
+        return s, st, w
+
+    log("warmup ...")
+    for _ in range(args.warmup):
+        step(stats=True)
+    torch.cuda.synchronize()
+    log("timed steps ...")
+    stage = {"ms_project": 0.0, "ms_sort": 0.0, "ms_bin": 0.0, "ms_pass1": 0.0, "ms_pass2": 0.0}
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s, st, w = step(stats=True)
+        for key in stage:
+            stage[key] += st[key] / args.steps
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"exact: {ms:.2f} ms/step  stages {json.dumps({k: round(v, 3) for k, v in stage.items()})}")
+
+    log("counting pairs (untimed) ...")
+    _, cst, _ = step(stats=True, count_pairs=True)
+    live = cst["n_live_pairs"]
+    dom_ms = stage["ms_pass2"]
+    achieved = live * OPS_PASS2 / (dom_ms * 1e-3)
+    roofline = {"kernel": "k_pass2 (compositing pass 2 + max-share reduction)", "bound": "alu",
+                "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                "work": f"{live} live pairs x {OPS_PASS2} VALU slots",
+                "pass1_frac": live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / PEAK_LANE_OPS}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on one view) ...")
+        cpu = cpu_baseline(scene, views, args.views)
+
+    out = {
+        "metric": "sensitivity pass ms (1M G x 100 views): exact vs learned/BF16 at <=1% err",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "scene1m: 1M Gaussians (64 clusters + 10% uniform, SH deg 3), "
+                               f"{args.views} orbit views 1280x720, m=100000, Philox seed 0"},
+        "stages_ms": stage,
+        "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],
+                  "entries": cst["n_entries"], "projected": cst["n_projected"]},
+        "live_pairs_per_s": live / (ms * 1e-3),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

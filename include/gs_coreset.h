@@ -1,0 +1,177 @@
+/*
+ * gs_coreset.h - C ABI of the MI355X (gfx950) sensitivity pass and
+ * sensitivity sampler for coreset pruning of 3D Gaussian Splatting scenes
+ * (Mousa & Maalouf, "Provable Pruning for Efficient 3D Gaussian Splatting via
+ * Coresets").
+ *
+ * Plain C: fixed-width integers, plain pointers, no C++ or HIP types.  A
+ * stream argument is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Memory: every array argument documented "device" must be device memory on
+ * the current HIP device; "host" arrays are read during the call only.  The
+ * caller owns all of them; the library never frees caller memory.  The
+ * library keeps a grow-only scratch arena per device (released by
+ * gs_release_workspace or at process exit).  Calls are serialised by a
+ * library-wide lock, so two host threads never share scratch at once.
+ *
+ * Errors: every call returns a gs_status.  Argument errors are detected on the
+ * host before any work is queued.  HIP failures return GS_ERR_DEVICE; the text
+ * of the last error of the calling thread is in gs_last_error().
+ *
+ * Query set and conventions (the paper leaves these open; this library fixes
+ * them): a query is one ray = (view, pixel); pixel (px, py) has its centre at
+ * (px + 1/2, py + 1/2); camera axes are x right, y down, z forward; the
+ * projected kernel is the local-affine (EWA) projection of Sigma, dilated by
+ * `dilation` px^2, truncated to the Mahalanobis ellipse d^2 <= r^2 (boundary
+ * included); Gaussians with camera depth z <= z_near are absent; the
+ * front-to-back order is ascending float32-rounded camera depth with ties
+ * broken by index; colour is real SH of degree <= 3 at the direction from the
+ * camera centre to the mean, plus 1/2, clamped at 0; the per-ray objective
+ * sums the three channels (GS_QUERY_RGBSUM) or uses colour 1
+ * (GS_QUERY_NOCOLOR, the paper's "nocolor" score variant).
+ */
+#ifndef GS_CORESET_H
+#define GS_CORESET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARGUMENT = 1,      /* bad size, null pointer, unknown enum, ... */
+    GS_ERR_UNSUPPORTED = 2,           /* valid but outside what this build handles */
+    GS_ERR_OUT_OF_MEMORY = 3,         /* scratch could not be allocated */
+    GS_ERR_NO_POSITIVE_SENSITIVITY = 4, /* sampler: every sensitivity is 0 */
+    GS_ERR_INVALID_DATA = 5,          /* non-finite attributes or zero quaternion */
+    GS_ERR_DEVICE = 6                 /* a HIP runtime call failed */
+} gs_status;
+
+typedef enum { GS_ATTR_F32 = 0, GS_ATTR_MIXED16 = 1 } gs_attr_format;
+typedef enum { GS_QUERY_RGBSUM = 0, GS_QUERY_NOCOLOR = 1 } gs_query_mode;
+typedef enum { GS_OBJ_FULL = 0, GS_OBJ_FIXED = 1, GS_OBJ_TRUE = 2 } gs_objective;
+/* GS_FLAG_COUNT_PAIRS: gs_sensitivity fills the pair counters of gs_stats
+ * (a pass-2 variant that counts; without it those counters read 0). */
+typedef enum { GS_FLAG_COUNT_PAIRS = 1 } gs_flag;
+
+/* Scene G = {(mu_i, Sigma_i, alpha_i, c_i)} (Section 3, "3DGS scene"), as
+ * structure-of-arrays planes in device memory, n Gaussians.
+ *   GS_ATTR_F32:     every plane float32.
+ *   GS_ATTR_MIXED16: mean, log_scale and sh bfloat16; quat and opacity
+ *                    float16 (IEEE binary16).
+ * Planes: mean [3][n] (x, y, z); log_scale [3][n] (Sigma = R(q) diag(exp(2 l))
+ * R(q)^T); quat [4][n] (w, x, y, z, normalised internally); opacity [n]
+ * (alpha in [0, 1]); sh [(sh_degree+1)^2][3][n] (coefficient-major, then
+ * R, G, B). */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree; /* 0..3 */
+    int32_t format;    /* gs_attr_format */
+    const void *mean;
+    const void *log_scale;
+    const void *quat;
+    const void *opacity;
+    const void *sh;
+} gs_scene;
+
+/* The finite query set's cameras (Section 3.2, "finite query set"), host
+ * arrays.  world_to_cam [n_views][12] row-major [R | t] with p_cam = R p + t
+ * and R in SO(3); intrinsics [n_views][4] = fx, fy, cx, cy in pixels;
+ * size [n_views][2] = width, height.  Rays are numbered view-major, then
+ * row-major inside a view. */
+typedef struct {
+    int32_t n_views;
+    const double *world_to_cam;
+    const double *intrinsics;
+    const int32_t *size;
+} gs_views;
+
+typedef struct {
+    float footprint_sigma;    /* r of the truncated footprint; default 3 */
+    float dilation;           /* delta added to the 2D covariance, px^2; default 0.3 */
+    float z_near;             /* > 0; default 0.2 */
+    float share_floor;        /* a ray stops once T * c_max < floor * A; 0 = never; default 1e-12 */
+    int32_t query_mode;       /* gs_query_mode */
+    int32_t max_views_per_chunk; /* 0 = as many as the scratch budget allows */
+    int32_t flags;            /* GS_FLAG_* bits */
+    const uint32_t *ray_mask; /* device bitset over all rays (bit r%32 of word r/32), NULL = all */
+} gs_params;
+
+/* Filled only when a non-NULL pointer is passed (the call then synchronises
+ * the stream once at its end and times each stage with HIP events on the
+ * call's stream).  The pair counters need GS_FLAG_COUNT_PAIRS. */
+typedef struct {
+    int64_t n_projected;      /* (view, Gaussian) pairs in front of the camera and on screen */
+    int64_t n_entries;        /* (tile, Gaussian) list entries */
+    int64_t n_pairs;          /* pass-2 ray-Gaussian pairs inside the footprint on scored rays */
+    int64_t n_live_pairs;     /* ... of which the ray still needed (T c_max >= floor A before the pair) */
+    int64_t n_lane_pairs;     /* pass-2 (pixel, entry) evaluations by the lanes, inside or not */
+    int64_t n_rays_positive;  /* scored rays with A > 0 */
+    int64_t n_invalid_gaussians; /* non-finite attributes or zero quaternion (treated as absent) */
+    double total_sensitivity; /* S = sum_i s_i, fixed-order reduction */
+    double ms_project, ms_sort, ms_bin, ms_pass1, ms_pass2; /* device time per stage, summed over chunks */
+} gs_stats;
+
+typedef struct {
+    int64_t n_invalid_pairs;  /* pairs with w_i rho_i >= 1 (Definition 2 violated) */
+    double gamma_max;         /* max |log T - log T_w| over contributing retained pairs on valid rays */
+} gs_render_diag;
+
+/* Sensitivity pass (Algorithm 1, steps 1-3; Section 3.2, Eq. sen):
+ *   s_i = max over rays q with A(q) > 0 of a(G, g_i, q) / A(G, q),
+ * with a = c rho T and A = sum a (Section 3, scalar rendering function).
+ * sens: device float[n], written (0 for Gaussians that never contribute).
+ * Rays outside params->ray_mask are not scored.  Rays stop once the largest
+ * possible remaining share is below params->share_floor, so every s_i below
+ * that floor may read 0.  Synchronises the stream once per view chunk (to
+ * size the tile lists).  stats may be NULL. */
+gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_params *params,
+                         float *sens, gs_stats *stats, void *stream);
+
+/* Sensitivity sampling (Algorithm 1, steps 3-5; proof of Theorem 2):
+ * p_i is realised exactly as q_i / Q with q_i = ceil(s_i 2^40) (0 iff s_i = 0)
+ * and Q = sum_i q_i; draw t in [0, m) takes the Philox4x32-10 block of
+ * key (seed low, seed high) and counter (t low, t high, 0, 0) as a 128-bit u
+ * (word 0 least significant), and picks the first i whose inclusive prefix
+ * sum exceeds floor(u Q / 2^128).  counts[i] = number of draws of i;
+ * weights[i] = counts[i] Q / (m q_i) in IEEE double (0 if not drawn);
+ * support[0] = number of distinct drawn i.
+ * sens: device float[n], all >= 0 and finite, n < 2^24.  counts: device
+ * uint32[n]; weights: device double[n]; support: device int64[1]; 1 <= m < 2^31.
+ * Returns GS_ERR_NO_POSITIVE_SENSITIVITY (outputs zeroed) if Q = 0.
+ * Synchronises the stream once (to read Q). */
+gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t seed,
+                            uint32_t *counts, double *weights, int64_t *support, void *stream);
+
+/* Objectives of a weighted pruned scene (Section 3: A, the fixed relaxation
+ * A^th_w = sum_i w_i a(G, g_i, q), and the true reduced render
+ * A_w = sum_i w_i c_i rho_i T_w with T_w = prod_{j before i} (1 - w_j rho_j)).
+ * weights: device double[n] (NULL only for GS_OBJ_FULL).
+ * per_ray: device float[rays] (nullable): the chosen objective, 0 on rays
+ *   that are masked or have A = 0.
+ * per_view: device double[n_views][3] (nullable): sums over scored rays of
+ *   A, A^th_w and A_w (the last two 0 when weights is NULL).
+ * diag (nullable, host): validity violations and the log-transmittance gap
+ *   (Definition 2, Assumption 1); the call synchronises the stream when set.
+ * No share-floor stop is applied here. */
+gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, const gs_params *params,
+                              const double *weights, int32_t objective, float *per_ray,
+                              double *per_view, gs_render_diag *diag, void *stream);
+
+/* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum). */
+void gs_default_params(gs_params *params);
+
+/* Frees the calling device's scratch arena (waits for the device first). */
+gs_status gs_release_workspace(void);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *gs_last_error(void);
+const char *gs_status_string(gs_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_CORESET_H */

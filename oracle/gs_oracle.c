@@ -345,9 +345,11 @@ static void *sens_worker_main(void *arg)
         double *A = (double *)calloc((size_t)npix, sizeof(double));
         uint8_t *sel = (uint8_t *)malloc((size_t)npix);
         uint8_t *flag = (uint8_t *)calloc((size_t)npix, 1);
+        uint8_t row_on[16] = {0};
         int any = 0;
         for (int64_t p = 0; p < npix; ++p) {
             sel[p] = (uint8_t)ray_selected(w->ray_mask, base + p);
+            row_on[p / W] |= sel[p];
             any |= sel[p];
             T[p] = 1.0;
         }
@@ -361,7 +363,8 @@ static void *sens_worker_main(void *arg)
                 if (ylo < y0) ylo = y0;
                 if (yhi > y1 - 1) yhi = y1 - 1;
                 pixel_range(o->mx, o->rx, W, &xlo, &xhi);
-                for (int32_t py = ylo; py <= yhi; ++py)
+                for (int32_t py = ylo; py <= yhi; ++py) {
+                    if (!row_on[py - y0]) continue;
                     for (int32_t px = xlo; px <= xhi; ++px) {
                         int64_t p = (int64_t)(py - y0) * W + px;
                         if (!sel[p]) continue;
@@ -374,6 +377,7 @@ static void *sens_worker_main(void *arg)
                         A[p] += o->cbar * rho * T[p];
                         T[p] *= (1.0 - rho);
                     }
+                }
             }
             /* Pass 2: shares a/A on rays with A > 0; running maxima. */
             for (int64_t p = 0; p < npix; ++p) {
@@ -389,7 +393,8 @@ static void *sens_worker_main(void *arg)
                 if (ylo < y0) ylo = y0;
                 if (yhi > y1 - 1) yhi = y1 - 1;
                 pixel_range(o->mx, o->rx, W, &xlo, &xhi);
-                for (int32_t py = ylo; py <= yhi; ++py)
+                for (int32_t py = ylo; py <= yhi; ++py) {
+                    if (!row_on[py - y0]) continue;
                     for (int32_t px = xlo; px <= xhi; ++px) {
                         int64_t p = (int64_t)(py - y0) * W + px;
                         if (!sel[p] || !(A[p] > 0.0)) continue;
@@ -404,6 +409,7 @@ static void *sens_worker_main(void *arg)
                         if (T[p] * S->cbar_max >= w->prm->share_floor * A[p]) w->live_pairs++;
                         T[p] *= (1.0 - rho);
                     }
+                }
             }
         }
         for (int64_t p = 0; p < npix; ++p) {
@@ -415,9 +421,12 @@ static void *sens_worker_main(void *arg)
     return NULL;
 }
 
-/* Projection of one view with n_threads threads, then the depth order. */
+/* Projection of one view with n_threads threads, then the depth order of the
+ * present Gaussians whose pixel range meets a row band that holds a selected
+ * ray (band_used[b] for rows [16 b, 16 b + 16)); the order of that subset is
+ * the full order restricted to it, so skipping the others changes nothing. */
 static void setup_view_threaded(const ora_scene *g, const ora_views *vw, const ora_params *prm,
-                                int32_t v, int nt, ora_view_setup *s)
+                                int32_t v, int nt, const uint8_t *band_used, ora_view_setup *s)
 {
     s->proj = (ora_proj *)malloc(sizeof(ora_proj) * (size_t)g->n);
     s->order = (ora_order *)malloc(sizeof(ora_order) * (size_t)g->n);
@@ -432,12 +441,17 @@ static void setup_view_threaded(const ora_scene *g, const ora_views *vw, const o
     free(ws); free(th);
     s->n_present = 0;
     s->cbar_max = 0.0;
+    const int32_t H = vw->size[2 * v + 1];
     for (int64_t i = 0; i < g->n; ++i)
         if (s->proj[i].present) {
+            int32_t ylo, yhi, use = 0;
+            pixel_range(s->proj[i].my, s->proj[i].ry, H, &ylo, &yhi);
+            if (s->proj[i].cbar > s->cbar_max) s->cbar_max = s->proj[i].cbar;
+            for (int32_t b = ylo / 16; b <= yhi / 16 && !use; ++b) use = band_used[b];
+            if (!use) continue;
             s->order[s->n_present].key = s->proj[i].key;
             s->order[s->n_present].idx = i;
             s->n_present++;
-            if (s->proj[i].cbar > s->cbar_max) s->cbar_max = s->proj[i].cbar;
         }
     qsort(s->order, (size_t)s->n_present, sizeof(ora_order), order_cmp);
 }
@@ -459,19 +473,27 @@ int ora_sensitivity(const ora_scene *g, const ora_views *vw, const ora_params *p
     int64_t ray_base = 0;
     for (int32_t v = 0; v < V; ++v) {
         const int64_t nrays = (int64_t)vw->size[2 * v] * vw->size[2 * v + 1];
-        /* skip views with no selected ray */
-        int any = ray_mask == NULL;
-        for (int64_t p = 0; p < nrays && !any; ++p) any = ray_selected(ray_mask, ray_base + p);
+        /* skip views with no selected ray; note which row bands hold one */
+        const int32_t W = vw->size[2 * v], H = vw->size[2 * v + 1];
+        uint8_t *band_used = (uint8_t *)calloc((size_t)(H / 16 + 1), 1);
+        int any = 0;
+        for (int32_t y = 0; y < H; ++y) {
+            int row_any = ray_mask == NULL;
+            for (int32_t x = 0; x < W && !row_any; ++x) row_any = ray_selected(ray_mask, ray_base + (int64_t)y * W + x);
+            if (row_any) { band_used[y / 16] = 1; any = 1; }
+        }
         if (!any) {
             for (int64_t p = 0; p < nrays; ++p) {
                 if (A) A[ray_base + p] = 0.0;
                 if (ray_flag) ray_flag[ray_base + p] = 0;
             }
             ray_base += nrays;
+            free(band_used);
             continue;
         }
         ora_view_setup S;
-        setup_view_threaded(g, vw, prm, v, nt, &S);
+        setup_view_threaded(g, vw, prm, v, nt, band_used, &S);
+        free(band_used);
         for (int t = 0; t < nt; ++t) {
             sens_worker *w = &ws[t];
             w->g = g; w->vw = vw; w->prm = prm; w->ray_mask = ray_mask; w->view = v;
@@ -503,7 +525,9 @@ int ora_sensitivity(const ora_scene *g, const ora_views *vw, const ora_params *p
  * Validity (Definition 2): pairs with w_i rho_i >= 1 are counted.
  * Log-transmittance gap (Assumption 1): gamma = max |log T - log T_w| over
  * contributing pairs (rho > 0) of retained Gaussians (w > 0), on rays where
- * every factor 1 - w rho stays positive.                                     */
+ * every factor 1 - w rho stays positive.  log T and log T_w are kept as sums
+ * of log(1 - rho_j) and log(1 - w_j rho_j), which equal the logs of the
+ * products but do not underflow on long rays.                                */
 int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm,
                   const uint32_t *ray_mask, const double *w,
                   double *A_full, double *A_fixed, double *A_true, /* [rays] each, nullable */
@@ -524,6 +548,8 @@ int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm
         double *Ax = (double *)calloc((size_t)npix, sizeof(double));
         double *At = (double *)calloc((size_t)npix, sizeof(double));
         double *gq = (double *)calloc((size_t)npix, sizeof(double));
+        double *LT = (double *)calloc((size_t)npix, sizeof(double));  /* log T as a sum */
+        double *LTw = (double *)calloc((size_t)npix, sizeof(double)); /* log T_w as a sum */
         uint8_t *bad = (uint8_t *)calloc((size_t)npix, 1);
         for (int64_t p = 0; p < npix; ++p) { T[p] = 1.0; Tw[p] = 1.0; }
         for (int64_t k = 0; k < S.n_present; ++k) {
@@ -547,12 +573,14 @@ int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm
                     if (wi > 0.0) {
                         At[p] += wi * o->cbar * rho * Tw[p];
                         if (!bad[p] && rho > 0.0) {
-                            double gap = fabs(log(T[p]) - log(Tw[p]));
+                            double gap = fabs(LT[p] - LTw[p]);
                             if (gap > gq[p]) gq[p] = gap;
                         }
                         if (wi * rho >= 1.0) { invalid++; bad[p] = 1; }
+                        if (!bad[p]) LTw[p] += log1p(-wi * rho);
                         Tw[p] *= (1.0 - wi * rho);
                     }
+                    LT[p] += log1p(-rho);
                     T[p] *= (1.0 - rho);
                 }
         }
@@ -568,7 +596,7 @@ int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm
             }
         }
         if (view_sums) { view_sums[3 * v] = sf; view_sums[3 * v + 1] = sx; view_sums[3 * v + 2] = st; }
-        free(T); free(Tw); free(Af); free(Ax); free(At); free(gq); free(bad);
+        free(T); free(Tw); free(Af); free(Ax); free(At); free(gq); free(LT); free(LTw); free(bad);
         free_view(&S);
         ray0 += npix;
     }

@@ -1,0 +1,183 @@
+"""MI355X-native sensitivity pass and sensitivity sampler for coreset pruning
+of 3D Gaussian Splatting scenes (Mousa & Maalouf, "Provable Pruning for
+Efficient 3D Gaussian Splatting via Coresets").
+
+Python surface over the C ABI in include/gs_coreset.h.  The functions here
+only marshal arguments: torch provides device memory and the current stream,
+and all computation runs in the library's HIP kernels for gfx950.
+
+    scene = DeviceScene.from_arrays(mean, log_scale, quat, opacity, sh, sh_degree)
+    s, st = sensitivity(scene, views)                  # Algorithm 1, steps 1-3
+    counts, w, support = sample_coreset(s, m, seed)    # Algorithm 1, steps 3-5
+    out = render_objective(scene, views, w)            # A, A^th_w, A_w
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (ATTR_F32, ATTR_MIXED16, GsError, OBJ_FIXED, OBJ_FULL, OBJ_TRUE,
+                   QUERY_NOCOLOR, QUERY_RGBSUM, load)
+
+__all__ = ["DeviceScene", "sensitivity", "sample_coreset", "render_objective", "GsError",
+           "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "ATTR_F32",
+           "ATTR_MIXED16", "load", "release_workspace"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceScene:
+    """SoA scene planes resident in device memory (torch tensors).
+
+    format ATTR_F32: float32 planes.  ATTR_MIXED16: bfloat16 mean, log_scale
+    and sh; float16 quat and opacity."""
+
+    def __init__(self, mean, log_scale, quat, opacity, sh, sh_degree, fmt=ATTR_F32):
+        self.mean, self.log_scale, self.quat, self.opacity, self.sh = mean, log_scale, quat, opacity, sh
+        self.sh_degree = int(sh_degree)
+        self.format = int(fmt)
+        self.n = int(opacity.shape[0])
+        for t in (mean, log_scale, quat, opacity, sh):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("scene planes must be contiguous device tensors")
+
+    @classmethod
+    def from_arrays(cls, mean, log_scale, quat, opacity, sh, sh_degree, device="cuda",
+                    fmt=ATTR_F32):
+        torch = _torch()
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device)
+        planes = [f(mean), f(log_scale), f(quat), f(opacity), f(sh)]
+        if fmt == ATTR_MIXED16:
+            planes = [planes[0].to(torch.bfloat16), planes[1].to(torch.bfloat16),
+                      planes[2].to(torch.float16), planes[3].to(torch.float16),
+                      planes[4].to(torch.bfloat16)]
+        return cls(*[p.contiguous() for p in planes], sh_degree, fmt)
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda", fmt=ATTR_F32):
+        """From any object with mean/log_scale/quat/opacity/sh arrays and sh_degree."""
+        return cls.from_arrays(scene.mean, scene.log_scale, scene.quat, scene.opacity, scene.sh,
+                               scene.sh_degree, device, fmt)
+
+    def c_struct(self):
+        return _lib.Scene(self.n, self.sh_degree, self.format, self.mean.data_ptr(),
+                          self.log_scale.data_ptr(), self.quat.data_ptr(), self.opacity.data_ptr(),
+                          self.sh.data_ptr())
+
+    def attribute_bytes(self):
+        return sum(t.numel() * t.element_size()
+                   for t in (self.mean, self.log_scale, self.quat, self.opacity, self.sh))
+
+
+def _views(views):
+    if isinstance(views, _lib.HostViews):
+        return views
+    return _lib.HostViews(views.world_to_cam, views.intrinsics, views.size)
+
+
+def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
+            max_views_per_chunk, flags=0):
+    p = _lib.default_params()
+    p.flags = flags
+    p.footprint_sigma = footprint_sigma
+    p.dilation = dilation
+    p.z_near = z_near
+    p.share_floor = share_floor
+    p.query_mode = query_mode
+    p.max_views_per_chunk = max_views_per_chunk
+    if ray_mask is not None:
+        if not ray_mask.is_cuda or ray_mask.dtype.itemsize != 4:
+            raise ValueError("ray_mask must be a device tensor of 32-bit words")
+        p.ray_mask = ray_mask.data_ptr()
+    return p
+
+
+def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
+                share_floor=1e-12, query_mode=QUERY_RGBSUM, ray_mask=None,
+                max_views_per_chunk=0, stats=False, count_pairs=False, out=None, stream=None):
+    """Per-Gaussian sensitivities (float32 device tensor [n]); with stats=True
+    also a dict of counters and per-stage device milliseconds (pair counters
+    need count_pairs=True)."""
+    torch = _torch()
+    lib = load()
+    hv = _views(views)
+    p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
+                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0)
+    if out is None:
+        out = torch.empty(scene.n, dtype=torch.float32, device=scene.opacity.device)
+    sc = scene.c_struct()
+    st = _lib.Stats() if stats else None
+    status = lib.gs_sensitivity(C.byref(sc), C.byref(hv.c), C.byref(p), C.c_void_p(out.data_ptr()),
+                                C.byref(st) if st is not None else None, _stream_handle(stream))
+    _lib.check(status)
+    return out, (st.as_dict() if st is not None else None)
+
+
+def sample_coreset(sens, m: int, seed: int, stream=None):
+    """Counts (int32 view of uint32), float64 weights and support (int64 [1])."""
+    torch = _torch()
+    lib = load()
+    if sens.dtype != torch.float32 or not sens.is_cuda or not sens.is_contiguous():
+        raise ValueError("sens must be a contiguous float32 device tensor")
+    n = sens.numel()
+    counts = torch.empty(n, dtype=torch.int32, device=sens.device)
+    weights = torch.empty(n, dtype=torch.float64, device=sens.device)
+    support = torch.empty(1, dtype=torch.int64, device=sens.device)
+    status = lib.gs_sample_coreset(C.c_void_p(sens.data_ptr()), n, int(m), C.c_uint64(seed & (2**64 - 1)),
+                                   C.c_void_p(counts.data_ptr()), C.c_void_p(weights.data_ptr()),
+                                   C.c_void_p(support.data_ptr()), _stream_handle(stream))
+    _lib.check(status)
+    return counts, weights, support
+
+
+def render_objective(scene: DeviceScene, views, weights=None, objective=OBJ_FULL, *,
+                     footprint_sigma=3.0, dilation=0.3, z_near=0.2, query_mode=QUERY_RGBSUM,
+                     ray_mask=None, max_views_per_chunk=0, per_ray=True, per_view=True,
+                     diag=True, stream=None):
+    """Objective of a weighted pruned scene: per-ray values (float32 [rays]),
+    per-view sums of (A, A^th_w, A_w) (float64 [V, 3]) and diagnostics."""
+    torch = _torch()
+    lib = load()
+    hv = _views(views)
+    p = _params(footprint_sigma, dilation, z_near, 0.0, query_mode, ray_mask, max_views_per_chunk)
+    dev = scene.opacity.device
+    pr = torch.zeros(hv.n_rays, dtype=torch.float32, device=dev) if per_ray else None
+    pv = torch.zeros((hv.size.shape[0], 3), dtype=torch.float64, device=dev) if per_view else None
+    if weights is not None and (weights.dtype != torch.float64 or not weights.is_cuda):
+        raise ValueError("weights must be a float64 device tensor")
+    dg = _lib.RenderDiag() if diag else None
+    sc = scene.c_struct()
+    status = lib.gs_render_objective(
+        C.byref(sc), C.byref(hv.c), C.byref(p),
+        C.c_void_p(weights.data_ptr()) if weights is not None else None, int(objective),
+        C.c_void_p(pr.data_ptr()) if pr is not None else None,
+        C.c_void_p(pv.data_ptr()) if pv is not None else None,
+        C.byref(dg) if dg is not None else None, _stream_handle(stream))
+    _lib.check(status)
+    out = {"per_ray": pr, "per_view": pv}
+    if dg is not None:
+        out["n_invalid_pairs"] = int(dg.n_invalid_pairs)
+        out["gamma_max"] = float(dg.gamma_max)
+    return out
+
+
+def release_workspace():
+    _lib.check(load().gs_release_workspace())
+
+
+def coreset_error(per_view):
+    """E = max over views of |sum A^th_w - sum A| / sum A (per-image fixed objective)."""
+    pv = per_view.detach().cpu().numpy() if hasattr(per_view, "detach") else np.asarray(per_view)
+    on = pv[:, 0] > 0
+    return float(np.max(np.abs(pv[on, 1] - pv[on, 0]) / pv[on, 0])) if on.any() else 0.0

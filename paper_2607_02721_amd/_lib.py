@@ -1,0 +1,125 @@
+"""ctypes binding of libgscoreset.so (include/gs_coreset.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  There is no fallback: if the library cannot be loaded, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgscoreset.so")
+
+GS_OK = 0
+STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory",
+                4: "no positive sensitivity", 5: "invalid data", 6: "device error"}
+EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_default_params",
+            "gs_release_workspace", "gs_last_error", "gs_status_string"]
+
+OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
+FLAG_COUNT_PAIRS = 1
+QUERY_RGBSUM, QUERY_NOCOLOR = 0, 1
+ATTR_F32, ATTR_MIXED16 = 0, 1
+
+
+class GsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Scene(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("format", C.c_int32),
+                ("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class Views(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("world_to_cam", C.c_void_p),
+                ("intrinsics", C.c_void_p), ("size", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("footprint_sigma", C.c_float), ("dilation", C.c_float), ("z_near", C.c_float),
+                ("share_floor", C.c_float), ("query_mode", C.c_int32),
+                ("max_views_per_chunk", C.c_int32), ("flags", C.c_int32), ("ray_mask", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_projected", C.c_int64), ("n_entries", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_live_pairs", C.c_int64), ("n_lane_pairs", C.c_int64), ("n_rays_positive", C.c_int64),
+                ("n_invalid_gaussians", C.c_int64), ("total_sensitivity", C.c_double),
+                ("ms_project", C.c_double), ("ms_sort", C.c_double), ("ms_bin", C.c_double),
+                ("ms_pass1", C.c_double), ("ms_pass2", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RenderDiag(C.Structure):
+    _fields_ = [("n_invalid_pairs", C.c_int64), ("gamma_max", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing; build it with paper_2607_02721_amd/build.py")
+        lib = C.CDLL(path)
+        P = C.c_void_p
+        lib.gs_sensitivity.argtypes = [P, P, P, P, P, P]
+        lib.gs_sensitivity.restype = C.c_int
+        lib.gs_sample_coreset.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, P, P, P, P]
+        lib.gs_sample_coreset.restype = C.c_int
+        lib.gs_render_objective.argtypes = [P, P, P, P, C.c_int32, P, P, P, P]
+        lib.gs_render_objective.restype = C.c_int
+        lib.gs_default_params.argtypes = [P]
+        lib.gs_default_params.restype = None
+        lib.gs_release_workspace.argtypes = []
+        lib.gs_release_workspace.restype = C.c_int
+        lib.gs_last_error.argtypes = []
+        lib.gs_last_error.restype = C.c_char_p
+        lib.gs_status_string.argtypes = [C.c_int]
+        lib.gs_status_string.restype = C.c_char_p
+        _lib = lib
+    return _lib
+
+
+def check(status):
+    if status != GS_OK:
+        raise GsError(status, load().gs_last_error().decode())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().gs_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "ray_mask":
+            p.ray_mask = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class HostViews:
+    """Keeps the float64/int32 camera arrays alive and exposes the C struct."""
+
+    def __init__(self, world_to_cam, intrinsics, size):
+        self.w2c = np.ascontiguousarray(world_to_cam, np.float64).reshape(-1, 12)
+        self.intr = np.ascontiguousarray(intrinsics, np.float64).reshape(-1, 4)
+        self.size = np.ascontiguousarray(size, np.int32).reshape(-1, 2)
+        self.c = Views(self.size.shape[0], self.w2c.ctypes.data, self.intr.ctypes.data,
+                       self.size.ctypes.data)
+
+    @property
+    def n_rays(self):
+        return int(np.sum(self.size[:, 0].astype(np.int64) * self.size[:, 1]))

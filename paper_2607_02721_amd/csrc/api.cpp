@@ -1,0 +1,593 @@
+// Host side of the C ABI declared in include/gs_coreset.h: argument checks,
+// view chunking, scratch arenas and kernel sequencing.
+#include "../../include/gs_coreset.h"
+#include "gs_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_last_error;
+std::mutex g_lock;
+
+gs_status fail(gs_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+gs_status fail(gs_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(GS_ERR_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                          \
+    } while (0)
+
+// Grow-only device arena, one per device and purpose.
+struct Arena {
+    void *base = nullptr;
+    size_t cap = 0;
+    int device = -1;
+};
+constexpr int kMaxDevices = 16;
+Arena g_work[kMaxDevices], g_lists[kMaxDevices];
+
+hipError_t arena_reserve(Arena &a, size_t bytes) {
+    if (a.base && a.cap >= bytes) return hipSuccess;
+    if (a.base) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        hipFree(a.base);
+        a.base = nullptr;
+        a.cap = 0;
+    }
+    size_t want = std::max(bytes + bytes / 8, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&a.base, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&a.base, bytes);
+        if (e != hipSuccess) {
+            a.base = nullptr;
+            return e;
+        }
+        want = bytes;
+    }
+    a.cap = want;
+    return hipSuccess;
+}
+
+// Bump allocator over an arena (256-byte aligned sub-buffers).
+struct Carve {
+    char *p;
+    size_t off = 0;
+    explicit Carve(void *base) : p((char *)base) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *r = (T *)(p + off);
+        off += count * sizeof(T);
+        return r;
+    }
+};
+
+struct ChunkPlan {
+    int v0, vc;                 // first view, views in chunk
+    int64_t rays;               // rays in chunk
+    int total_tiles;
+};
+
+struct Setup {
+    int64_t N;
+    int nchunks;
+    std::vector<int> tiles_x, tiles_y;
+    std::vector<int64_t> ray_base;
+};
+
+size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
+    const int64_t N = S.N;
+    const int64_t nb = (N + kSortTile - 1) / kSortTile;
+    const int64_t nbins = (int64_t)c.total_tiles * S.nchunks;
+    size_t b = 0;
+    auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
+    add(3 * sizeof(float4) * (size_t)c.vc * N);      // records
+    for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)c.vc * N);
+    add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
+    add(2 * sizeof(uint32_t) * (size_t)c.vc);
+    add(sizeof(uint32_t) * nbins);
+    add(sizeof(uint32_t) * nbins);
+    add(sizeof(uint64_t) * (nbins + 1));
+    add(sizeof(uint64_t) * scan_tmp_elems(nbins + 1));
+    add(sizeof(float) * (size_t)c.rays);
+    add(sizeof(uint64_t) * CNT_SLOTS);
+    add(sizeof(ViewDev) * c.vc);
+    add(sizeof(int32_t) * c.total_tiles);
+    add(sizeof(double) * ((N + 4095) / 4096 + 2));
+    add(sizeof(double) * 3 * 4 * (size_t)c.total_tiles);   // objective partials
+    add(sizeof(double) * 3 * (size_t)c.vc);
+    return b + (64 << 10);  // slack for the per-buffer alignment
+}
+
+gs_status check_scene(const gs_scene *s) {
+    if (!s) return fail(GS_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (s->n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "scene->n must be >= 1 (got %lld)", (long long)s->n);
+    if (s->n >= (int64_t)kIndexMask)
+        return fail(GS_ERR_UNSUPPORTED, "scene->n must be < 2^28 (got %lld)", (long long)s->n);
+    if (s->sh_degree < 0 || s->sh_degree > 3)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sh_degree must be in 0..3 (got %d)", s->sh_degree);
+    if (s->format != GS_ATTR_F32 && s->format != GS_ATTR_MIXED16)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown attribute format %d", s->format);
+    if (!s->mean || !s->log_scale || !s->quat || !s->opacity || !s->sh)
+        return fail(GS_ERR_INVALID_ARGUMENT, "scene attribute pointer is NULL");
+    return GS_OK;
+}
+
+gs_status check_views(const gs_views *v, Setup &S) {
+    if (!v) return fail(GS_ERR_INVALID_ARGUMENT, "views is NULL");
+    if (v->n_views < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n_views must be >= 1");
+    if (!v->world_to_cam || !v->intrinsics || !v->size)
+        return fail(GS_ERR_INVALID_ARGUMENT, "views array pointer is NULL");
+    S.tiles_x.resize(v->n_views);
+    S.tiles_y.resize(v->n_views);
+    S.ray_base.resize(v->n_views + 1);
+    S.ray_base[0] = 0;
+    for (int i = 0; i < v->n_views; ++i) {
+        const int W = v->size[2 * i], H = v->size[2 * i + 1];
+        if (W < 1 || H < 1 || W > 16384 || H > 16384)
+            return fail(GS_ERR_INVALID_ARGUMENT, "view %d: size %dx%d outside 1..16384", i, W, H);
+        const double *in = v->intrinsics + 4 * i;
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(in[k])) return fail(GS_ERR_INVALID_ARGUMENT, "view %d: non-finite intrinsics", i);
+        if (in[0] <= 0 || in[1] <= 0) return fail(GS_ERR_INVALID_ARGUMENT, "view %d: focal lengths must be > 0", i);
+        for (int k = 0; k < 12; ++k)
+            if (!std::isfinite(v->world_to_cam[12 * i + k]))
+                return fail(GS_ERR_INVALID_ARGUMENT, "view %d: non-finite extrinsics", i);
+        S.tiles_x[i] = (W + kTile - 1) / kTile;
+        S.tiles_y[i] = (H + kTile - 1) / kTile;
+        if (S.tiles_x[i] * S.tiles_y[i] > kMaxTilesPerView)
+            return fail(GS_ERR_UNSUPPORTED, "view %d: %dx%d needs more than %d tiles of 16x16", i, W, H,
+                        kMaxTilesPerView);
+        S.ray_base[i + 1] = S.ray_base[i] + (int64_t)W * H;
+    }
+    return GS_OK;
+}
+
+gs_status check_params(const gs_params *p) {
+    if (!p) return fail(GS_ERR_INVALID_ARGUMENT, "params is NULL");
+    if (!(p->footprint_sigma > 0.0f) || !std::isfinite(p->footprint_sigma))
+        return fail(GS_ERR_INVALID_ARGUMENT, "footprint_sigma must be > 0");
+    if (!(p->dilation >= 0.0f) || !std::isfinite(p->dilation))
+        return fail(GS_ERR_INVALID_ARGUMENT, "dilation must be >= 0");
+    if (!(p->z_near > 0.0f) || !std::isfinite(p->z_near))
+        return fail(GS_ERR_INVALID_ARGUMENT, "z_near must be finite and > 0");
+    if (!(p->share_floor >= 0.0f) || !std::isfinite(p->share_floor))
+        return fail(GS_ERR_INVALID_ARGUMENT, "share_floor must be >= 0");
+    if (p->query_mode != GS_QUERY_RGBSUM && p->query_mode != GS_QUERY_NOCOLOR)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown query_mode %d", p->query_mode);
+    if (p->max_views_per_chunk < 0) return fail(GS_ERR_INVALID_ARGUMENT, "max_views_per_chunk must be >= 0");
+    if (p->flags & ~GS_FLAG_COUNT_PAIRS) return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", p->flags);
+    return GS_OK;
+}
+
+size_t scratch_budget() {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = (size_t)16 << 30;
+    }
+    size_t budget = (size_t)(0.45 * (double)free_b);
+    if (const char *e = getenv("GS_SCRATCH_GB")) budget = (size_t)(atof(e) * (double)(1ull << 30));
+    return std::max(budget, (size_t)256 << 20);
+}
+
+std::vector<ChunkPlan> plan_chunks(const gs_views *v, const Setup &S, const gs_params *p, size_t budget) {
+    std::vector<ChunkPlan> out;
+    int v0 = 0;
+    while (v0 < v->n_views) {
+        ChunkPlan c{v0, 0, 0, 0};
+        while (v0 + c.vc < v->n_views) {
+            const int i = v0 + c.vc;
+            ChunkPlan t = c;
+            t.vc += 1;
+            t.rays += S.ray_base[i + 1] - S.ray_base[i];
+            t.total_tiles += S.tiles_x[i] * S.tiles_y[i];
+            if (c.vc > 0 && chunk_scratch_bytes(S, t) > budget) break;
+            if (p->max_views_per_chunk > 0 && t.vc > p->max_views_per_chunk) break;
+            if (t.vc > 65535) break;
+            c = t;
+        }
+        out.push_back(c);
+        v0 += c.vc;
+    }
+    return out;
+}
+
+struct Timer {
+    hipEvent_t ev[6];
+    bool on;
+    explicit Timer(bool enable) : on(enable) {
+        if (on)
+            for (auto &e : ev) hipEventCreate(&e);
+    }
+    ~Timer() {
+        if (on)
+            for (auto &e : ev) hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t st) {
+        if (on) hipEventRecord(ev[i], st);
+    }
+    float ms(int a, int b) {
+        float t = 0;
+        if (on) hipEventElapsedTime(&t, ev[a], ev[b]);
+        return t;
+    }
+};
+
+// Projection + sort + binning of one chunk.  Leaves the tile lists ready for
+// the compositing kernels.  Synchronises once (to size the lists).
+struct ChunkRun {
+    ChunkBufs b{};
+    ViewDev *views_dev = nullptr;
+    int32_t *tile_view = nullptr;
+    uint32_t *sorted_g = nullptr;
+    uint64_t *scan_tmp = nullptr;
+    double *sum_tmp = nullptr;
+    double *tile_sums = nullptr;
+    double *view_sums = nullptr;
+    int64_t n_entries = 0;
+};
+
+gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_params *p, const Setup &S,
+                    const ChunkPlan &c, hipStream_t st, int dev, std::vector<ViewDev> &hv,
+                    std::vector<int32_t> &htv, ChunkRun &r, Timer &tm, double *ms_acc, bool zero_counters) {
+    const int64_t N = S.N;
+    const int64_t nbins = (int64_t)c.total_tiles * S.nchunks;
+    size_t need = chunk_scratch_bytes(S, c);
+    HIP_TRY(arena_reserve(g_work[dev], need));
+    Carve cv(g_work[dev].base);
+    ChunkBufs &b = r.b;
+    b.R0 = cv.take<float4>((size_t)c.vc * N);
+    b.R1 = cv.take<float4>((size_t)c.vc * N);
+    b.R2 = cv.take<float4>((size_t)c.vc * N);
+    b.key0 = cv.take<uint32_t>((size_t)c.vc * N);
+    b.val0 = cv.take<uint32_t>((size_t)c.vc * N);
+    b.key1 = cv.take<uint32_t>((size_t)c.vc * N);
+    b.val1 = cv.take<uint32_t>((size_t)c.vc * N);
+    const int64_t nb = (N + kSortTile - 1) / kSortTile;
+    b.hist = cv.take<uint32_t>((size_t)c.vc * 256 * nb);
+    b.nvis = cv.take<uint32_t>(2 * (size_t)c.vc);
+    b.cmax = b.nvis + c.vc;
+    b.bin_count = cv.take<uint32_t>(nbins);
+    b.bin_fill = cv.take<uint32_t>(nbins);
+    b.bin_off = cv.take<uint64_t>(nbins + 1);
+    r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(nbins + 1));
+    b.ray_A = cv.take<float>(c.rays);
+    b.counters = cv.take<uint64_t>(CNT_SLOTS);
+    r.views_dev = cv.take<ViewDev>(c.vc);
+    r.tile_view = cv.take<int32_t>(c.total_tiles);
+    r.sum_tmp = cv.take<double>((N + 4095) / 4096 + 2);
+    r.tile_sums = cv.take<double>(3 * 4 * (size_t)c.total_tiles);
+    r.view_sums = cv.take<double>(3 * (size_t)c.vc);
+
+    hv.assign(c.vc, ViewDev{});
+    htv.assign(c.total_tiles, 0);
+    int tb = 0;
+    for (int k = 0; k < c.vc; ++k) {
+        const int i = c.v0 + k;
+        ViewDev &V = hv[k];
+        const double *P = views->world_to_cam + 12 * i;
+        for (int a = 0; a < 3; ++a) {
+            for (int bb = 0; bb < 3; ++bb) V.R[3 * a + bb] = P[4 * a + bb];
+            V.t[a] = P[4 * a + 3];
+        }
+        for (int a = 0; a < 3; ++a) V.cam[a] = -(V.R[a] * V.t[0] + V.R[3 + a] * V.t[1] + V.R[6 + a] * V.t[2]);
+        V.fx = views->intrinsics[4 * i];
+        V.fy = views->intrinsics[4 * i + 1];
+        V.cx = views->intrinsics[4 * i + 2];
+        V.cy = views->intrinsics[4 * i + 3];
+        V.W = views->size[2 * i];
+        V.H = views->size[2 * i + 1];
+        V.tiles_x = S.tiles_x[i];
+        V.tiles_y = S.tiles_y[i];
+        V.ray_base = S.ray_base[i];
+        V.ray_local = S.ray_base[i] - S.ray_base[c.v0];
+        V.tile_base = tb;
+        for (int t = 0; t < V.tiles_x * V.tiles_y; ++t) htv[tb + t] = k;
+        tb += V.tiles_x * V.tiles_y;
+    }
+    HIP_TRY(hipMemcpyAsync(r.views_dev, hv.data(), sizeof(ViewDev) * c.vc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r.tile_view, htv.data(), sizeof(int32_t) * c.total_tiles, hipMemcpyHostToDevice, st));
+    launch_fill_u32(b.nvis, 0u, 2 * (int64_t)c.vc, st);
+    launch_fill_u32(b.bin_count, 0u, nbins, st);
+    launch_fill_u32(b.bin_fill, 0u, nbins, st);
+    if (zero_counters) launch_fill_u64(b.counters, 0ull, CNT_SLOTS, st);
+
+    SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
+                scene->quat, scene->opacity, scene->sh};
+    ProjParams pp{p->footprint_sigma, p->dilation, p->z_near, p->query_mode};
+    tm.mark(0, st);
+    launch_project(sd, r.views_dev, c.vc, pp, b, st);
+    HIP_TRY(hipGetLastError());
+    tm.mark(1, st);
+    uint32_t *skeys = nullptr;
+    HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, &skeys, &r.sorted_g, st));
+    tm.mark(2, st);
+    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, r.sorted_g, kMaxTilesPerView, st);
+    scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, nbins, r.scan_tmp, st);
+    HIP_TRY(hipGetLastError());
+    uint64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, b.bin_off + nbins, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    r.n_entries = (int64_t)total;
+    HIP_TRY(arena_reserve(g_lists[dev], std::max<size_t>(total, 1) * sizeof(uint32_t)));
+    b.lists = (uint32_t *)g_lists[dev].base;
+    launch_bin_scatter(r.views_dev, c.vc, N, S.nchunks, b, r.sorted_g, kMaxTilesPerView, st);
+    launch_segment_sort(c.total_tiles, S.nchunks, b, r.sorted_g, r.tile_view, N, st);
+    HIP_TRY(hipGetLastError());
+    tm.mark(3, st);
+    if (tm.on) {
+        HIP_TRY(hipEventSynchronize(tm.ev[3]));
+        ms_acc[0] += tm.ms(0, 1);
+        ms_acc[1] += tm.ms(1, 2);
+        ms_acc[2] += tm.ms(2, 3);
+    }
+    return GS_OK;
+}
+
+int current_device(gs_status *st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *st = fail(GS_ERR_DEVICE, "no usable HIP device (device %d)", dev);
+        return -1;
+    }
+    *st = GS_OK;
+    return dev;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gs_default_params(gs_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->footprint_sigma = 3.0f;
+    p->dilation = 0.3f;
+    p->z_near = 0.2f;
+    p->share_floor = 1e-12f;
+    p->query_mode = GS_QUERY_RGBSUM;
+    p->max_views_per_chunk = 0;
+    p->flags = 0;
+    p->ray_mask = nullptr;
+}
+
+const char *gs_last_error(void) { return g_last_error.c_str(); }
+
+const char *gs_status_string(gs_status s) {
+    switch (s) {
+        case GS_OK: return "ok";
+        case GS_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case GS_ERR_UNSUPPORTED: return "unsupported";
+        case GS_ERR_OUT_OF_MEMORY: return "out of memory";
+        case GS_ERR_NO_POSITIVE_SENSITIVITY: return "no positive sensitivity";
+        case GS_ERR_INVALID_DATA: return "invalid data";
+        case GS_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+gs_status gs_release_workspace(void) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    gs_status s;
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    HIP_TRY(hipDeviceSynchronize());
+    for (Arena *a : {&g_work[dev], &g_lists[dev]}) {
+        if (a->base) hipFree(a->base);
+        a->base = nullptr;
+        a->cap = 0;
+    }
+    return GS_OK;
+}
+
+gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_params *params, float *sens,
+                         gs_stats *stats, void *stream) {
+    g_last_error.clear();
+    gs_status s;
+    if ((s = check_scene(scene)) != GS_OK) return s;
+    Setup S;
+    if ((s = check_views(views, S)) != GS_OK) return s;
+    if ((s = check_params(params)) != GS_OK) return s;
+    if (!sens) return fail(GS_ERR_INVALID_ARGUMENT, "sens is NULL");
+    std::lock_guard<std::mutex> lk(g_lock);
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    S.N = scene->n;
+    S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
+    const auto chunks = plan_chunks(views, S, params, scratch_budget());
+    launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
+    HIP_TRY(hipGetLastError());
+    Timer tm(stats != nullptr);
+    double ms[5] = {0, 0, 0, 0, 0};
+    std::vector<ViewDev> hv;
+    std::vector<int32_t> htv;
+    int64_t entries = 0, projected = 0;
+    ChunkRun r;
+    const float log2e = 1.4426950408889634f;
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        const ChunkPlan &c = chunks[ci];
+        if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, ci == 0)) != GS_OK) return s;
+        entries += r.n_entries;
+        CompositeArgs a{};
+        a.views = r.views_dev;
+        a.tile_view = r.tile_view;
+        a.total_tiles = c.total_tiles;
+        a.nchunks = S.nchunks;
+        a.N = S.N;
+        a.r2_log2 = -0.5f * log2e * params->footprint_sigma * params->footprint_sigma;
+        a.share_floor = params->share_floor;
+        a.ray_mask = params->ray_mask;
+        a.sens_bits = (uint32_t *)sens;
+        a.query_mode = params->query_mode;
+        tm.mark(3, st);
+        launch_composite_pass1(a, r.b, st);
+        HIP_TRY(hipGetLastError());
+        tm.mark(4, st);
+        launch_composite_pass2(a, r.b, (params->flags & GS_FLAG_COUNT_PAIRS) != 0, st);
+        HIP_TRY(hipGetLastError());
+        tm.mark(5, st);
+        if (stats) {
+            std::vector<uint32_t> nv(c.vc);
+            HIP_TRY(hipMemcpyAsync(nv.data(), r.b.nvis, sizeof(uint32_t) * c.vc, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            for (uint32_t x : nv) projected += x;
+            ms[3] += tm.ms(3, 4);
+            ms[4] += tm.ms(4, 5);
+        }
+    }
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        double S_total = 0.0;
+        uint64_t cnt[CNT_SLOTS];
+        launch_sum_f32_to_f64(sens, S.N, r.sum_tmp + (S.N + 4095) / 4096, r.sum_tmp, st);
+        HIP_TRY(hipMemcpyAsync(&S_total, r.sum_tmp + (S.N + 4095) / 4096, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(cnt, r.b.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        stats->n_projected = projected;
+        stats->n_entries = entries;
+        stats->n_pairs = (int64_t)cnt[CNT_PAIRS];
+        stats->n_live_pairs = (int64_t)cnt[CNT_LIVE];
+        stats->n_lane_pairs = (int64_t)cnt[CNT_LANE_PAIRS];
+        stats->n_rays_positive = (int64_t)cnt[CNT_RAYS_POS];
+        stats->n_invalid_gaussians = (int64_t)cnt[CNT_INVALID];
+        stats->total_sensitivity = S_total;
+        stats->ms_project = ms[0];
+        stats->ms_sort = ms[1];
+        stats->ms_bin = ms[2];
+        stats->ms_pass1 = ms[3];
+        stats->ms_pass2 = ms[4];
+        if (cnt[CNT_INVALID]) return fail(GS_ERR_INVALID_DATA, "%llu Gaussians have non-finite attributes",
+                                          (unsigned long long)cnt[CNT_INVALID]);
+    }
+    return GS_OK;
+}
+
+gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, const gs_params *params,
+                              const double *weights, int32_t objective, float *per_ray, double *per_view,
+                              gs_render_diag *diag, void *stream) {
+    g_last_error.clear();
+    gs_status s;
+    if ((s = check_scene(scene)) != GS_OK) return s;
+    Setup S;
+    if ((s = check_views(views, S)) != GS_OK) return s;
+    if ((s = check_params(params)) != GS_OK) return s;
+    if (objective != GS_OBJ_FULL && objective != GS_OBJ_FIXED && objective != GS_OBJ_TRUE)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown objective %d", objective);
+    if (objective != GS_OBJ_FULL && !weights)
+        return fail(GS_ERR_INVALID_ARGUMENT, "weights are required for the fixed and true objectives");
+    std::lock_guard<std::mutex> lk(g_lock);
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    S.N = scene->n;
+    S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
+    const auto chunks = plan_chunks(views, S, params, scratch_budget());
+    Timer tm(false);
+    double ms[5] = {0, 0, 0, 0, 0};
+    std::vector<ViewDev> hv;
+    std::vector<int32_t> htv;
+    ChunkRun r;
+    const float log2e = 1.4426950408889634f;
+    uint64_t inv_total = 0;
+    uint32_t gamma_bits = 0;
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        const ChunkPlan &c = chunks[ci];
+        if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, true)) != GS_OK) return s;
+        CompositeArgs a{};
+        a.views = r.views_dev;
+        a.tile_view = r.tile_view;
+        a.total_tiles = c.total_tiles;
+        a.nchunks = S.nchunks;
+        a.N = S.N;
+        a.r2_log2 = -0.5f * log2e * params->footprint_sigma * params->footprint_sigma;
+        a.share_floor = 0.0f;
+        a.ray_mask = params->ray_mask;
+        a.query_mode = params->query_mode;
+        ObjectiveArgs o{weights, objective, per_ray, r.tile_sums};
+        launch_fill_u64((uint64_t *)r.tile_sums, 0ull, 3 * 4 * (int64_t)c.total_tiles, st);
+        launch_objective(a, o, r.b, st);
+        HIP_TRY(hipGetLastError());
+        if (per_view) {
+            launch_view_sums(r.tile_sums, r.views_dev, c.vc, per_view + 3 * (int64_t)c.v0, st);
+            HIP_TRY(hipGetLastError());
+        }
+        if (diag) {
+            uint64_t cnt[CNT_SLOTS];
+            HIP_TRY(hipMemcpyAsync(cnt, r.b.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            inv_total += cnt[CNT_INVALID_PAIRS];
+            gamma_bits = std::max(gamma_bits, (uint32_t)cnt[CNT_GAMMA_BITS]);
+        }
+    }
+    if (diag) {
+        diag->n_invalid_pairs = (int64_t)inv_total;
+        float g;
+        memcpy(&g, &gamma_bits, sizeof g);
+        diag->gamma_max = g;
+    }
+    return GS_OK;
+}
+
+gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t seed, uint32_t *counts,
+                            double *weights, int64_t *support, void *stream) {
+    g_last_error.clear();
+    if (!sens || !counts || !weights || !support) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (n >= ((int64_t)1 << 24)) return fail(GS_ERR_UNSUPPORTED, "n must be < 2^24 so that Q fits 64 bits");
+    if (m < 1) return fail(GS_ERR_INVALID_ARGUMENT, "m must be >= 1");
+    if (m >= ((int64_t)1 << 31)) return fail(GS_ERR_UNSUPPORTED, "m must be < 2^31");
+    std::lock_guard<std::mutex> lk(g_lock);
+    gs_status s;
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = 2 * sizeof(uint64_t) * (size_t)n + sizeof(uint64_t) * (scan_tmp_elems(n) + 2) + 1024;
+    HIP_TRY(arena_reserve(g_work[dev], need));
+    Carve cv(g_work[dev].base);
+    uint64_t *q = cv.take<uint64_t>(n);
+    uint64_t *C = cv.take<uint64_t>(n);
+    uint64_t *tmp = cv.take<uint64_t>(scan_tmp_elems(n) + 2);
+    launch_quantize(sens, n, q, st);
+    scan_u64_inclusive(q, C, n, tmp, st);
+    launch_fill_u32(counts, 0u, n, st);
+    launch_fill_u64((uint64_t *)weights, 0ull, n, st);
+    launch_fill_u64((uint64_t *)support, 0ull, 1, st);
+    HIP_TRY(hipGetLastError());
+    uint64_t Q = 0;
+    HIP_TRY(hipMemcpyAsync(&Q, C + n - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (Q == 0) return fail(GS_ERR_NO_POSITIVE_SENSITIVITY, "every sensitivity is 0");
+    launch_draws(C, n, m, seed, counts, st);
+    launch_weights(counts, q, C, n, m, weights, support, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+}  // extern "C"

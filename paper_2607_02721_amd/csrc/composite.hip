@@ -1,0 +1,379 @@
+// Front-to-back compositing along every ray (Section 3, scalar rendering
+// function: rho = alpha k, T = prod (1 - rho) over earlier Gaussians,
+// a = c rho T, A = sum a) and the per-Gaussian maximum share
+// (Section 3.2, Eq. sen: s_i = max_q a_i(q) / A(q), rays with A = 0 skipped).
+//
+// Work decomposition: one wave (64 lanes) per 8x8 quadrant of a 16x16 bin
+// tile, one lane per pixel.  Waves are independent: each walks its tile's
+// front-to-back list in slices of 64 entries, keeps the entries whose pixel
+// range touches its quadrant (bit 28+q of the entry), stages their records
+// in wave-private LDS and then composites them from LDS broadcasts.  A ray
+// stops once T * c_max < floor * A (no later Gaussian can reach a share of
+// `floor`); a wave stops when all of its rays have stopped.
+//
+// Pass 1 writes A per ray.  Pass 2 repeats the walk with the same arithmetic,
+// forms shares a / A, reduces each entry's share over the wave's 64 pixels
+// with a transposed butterfly (32 entries at a time; lane L ends with the
+// maximum of entry L/2), and raises s with an atomic maximum on the float
+// bits (order-free, so the result is deterministic).
+#include "gs_internal.hpp"
+
+namespace gs {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint64_t lanemask_lt64() {
+    const unsigned lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of quadrants so that neighbouring quadrants (which share list entries
+// and records) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblk_padded) {
+    const int per = nblk_padded >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+struct WaveSetup {
+    int v, gt, quad, px, py;
+    bool inside;
+    float xl, yl, qx0, qy0;
+    int64_t ray_local, ray_global;
+    uint64_t start, end;
+    uint32_t qbit;
+    int W;
+};
+
+__device__ __forceinline__ bool setup_wave(const CompositeArgs &a, const uint64_t *bin_off, WaveSetup &w) {
+    const int nblk = a.total_tiles * 4;
+    const int padded = (nblk + 7) & ~7;
+    const int logical = xcd_remap(blockIdx.x, padded);
+    if (logical >= nblk) return false;
+    w.gt = logical >> 2;
+    w.quad = logical & 3;
+    w.v = a.tile_view[w.gt];
+    const ViewDev &V = a.views[w.v];
+    const int tl = w.gt - V.tile_base;
+    const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
+    const int qx0 = tx * kTile + (w.quad & 1) * kQuad;
+    const int qy0 = ty * kTile + (w.quad >> 1) * kQuad;
+    if (qx0 >= V.W || qy0 >= V.H) return false;
+    const int lane = threadIdx.x;
+    w.px = qx0 + (lane & 7);
+    w.py = qy0 + (lane >> 3);
+    w.inside = w.px < V.W && w.py < V.H;
+    w.xl = (float)(lane & 7) + 0.5f;
+    w.yl = (float)(lane >> 3) + 0.5f;
+    w.qx0 = (float)qx0;
+    w.qy0 = (float)qy0;
+    w.W = V.W;
+    w.ray_local = V.ray_local + (int64_t)w.py * V.W + w.px;
+    w.ray_global = V.ray_base + (int64_t)w.py * V.W + w.px;
+    w.start = bin_off[(int64_t)w.gt * a.nchunks];
+    w.end = bin_off[(int64_t)(w.gt + 1) * a.nchunks];
+    w.qbit = 1u << (28 + w.quad);
+    return true;
+}
+
+__device__ __forceinline__ bool ray_selected(const uint32_t *mask, int64_t ray) {
+    return mask == nullptr || ((mask[ray >> 5] >> (ray & 31)) & 1u);
+}
+
+// Stage the slice's entries that touch this quadrant; returns how many.
+// geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
+// col = (g', alpha, cbar, extra).
+template <int kExtra>  // 0: none, 1: s_old + index, 2: weight
+__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, const uint32_t *__restrict__ lists,
+                                           const float4 *__restrict__ R0, const float4 *__restrict__ R1,
+                                           const float4 *__restrict__ R2, int64_t vbase, float4 *geo, float4 *col,
+                                           uint32_t *sid, float *sold, const uint32_t *__restrict__ sens_bits,
+                                           const double *__restrict__ weights) {
+    const int lane = threadIdx.x;
+    const uint64_t e = e0 + lane;
+    const uint32_t raw = e < w.end ? lists[e] : 0u;
+    const bool touch = (raw & w.qbit) != 0u;
+    const uint64_t bal = __ballot(touch);
+    if (touch) {
+        const int slot = __popcll(bal & lanemask_lt64());
+        const uint32_t g = raw & kIndexMask;
+        const int64_t o = vbase + g;
+        const float4 r0 = R0[o];
+        const float4 r1 = R1[o];
+        const float cb = R2[o].x;
+        const float mx = (r0.x - w.qx0) + r0.z;
+        const float my = (r0.y - w.qy0) + r0.w;
+        geo[slot] = make_float4(mx, my, r1.x, r1.y);
+        float extra = 0.0f;
+        if (kExtra == 1) {
+            sid[slot] = g;
+            sold[slot] = __uint_as_float(sens_bits[g]);
+        }
+        if (kExtra == 2) extra = (float)weights[g];
+        col[slot] = make_float4(r1.z, r1.w, cb, extra);
+    }
+    return __popcll(bal);
+}
+
+// exp2 argument of the kernel for this lane's pixel; rho = alpha exp2(P)
+// inside the footprint (P >= cut), else 0.
+__device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, float xl, float yl, float cut,
+                                          bool &in_fp) {
+    const float dx = xl - G.x;
+    const float dy = yl - G.y;
+    const float u = fmaf(G.z, dy, dx);
+    const float t = Cc.x * (dy * dy);
+    const float P = fmaf(G.w * u, u, t);
+    const float E = __builtin_amdgcn_exp2f(P);
+    in_fp = P >= cut;
+    return in_fp ? Cc.y * E : 0.0f;
+}
+
+__global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a, const uint64_t *__restrict__ bin_off,
+                                                 const uint32_t *__restrict__ lists, const float4 *__restrict__ R0,
+                                                 const float4 *__restrict__ R1, const float4 *__restrict__ R2,
+                                                 const uint32_t *__restrict__ cmax_bits, float *__restrict__ ray_A) {
+    __shared__ float4 geo[kWave], col[kWave];
+    WaveSetup w;
+    if (!setup_wave(a, bin_off, w)) return;
+    const bool scored = w.inside && ray_selected(a.ray_mask, w.ray_global);
+    const float cmax = __uint_as_float(cmax_bits[w.v]);
+    const int64_t vbase = (int64_t)w.v * a.N;
+    float T = 1.0f, A = 0.0f;
+    bool done = !scored;
+    for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
+        if (__all(done)) break;
+        const int n = stage_slice<0>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr, nullptr);
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            const float4 G = geo[j], Cc = col[j];
+            bool in_fp;
+            const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+            const float cr = Cc.z * rho;
+            A = fmaf(cr, T, A);
+            T = fmaf(-rho, T, T);
+        }
+        done = done || (T * cmax < a.share_floor * A);
+        __syncthreads();
+    }
+    if (w.inside) ray_A[w.ray_local] = scored ? A : 0.0f;
+}
+
+// Transposed butterfly over 64 lanes for 32 values: afterwards lane L holds
+// the maximum over all lanes of value (L >> 1).
+__device__ __forceinline__ float wave_transpose_max32(float (&v)[32]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int lvl = 0; lvl < 5; ++lvl) {
+        const int half = 16 >> lvl;
+        const int mask = 32 >> lvl;
+        const bool up = (lane & mask) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const float keep = up ? v[half + k] : v[k];
+            const float send = up ? v[k] : v[half + k];
+            const float recv = __shfl_xor(send, mask);
+            v[k] = fmaxf(keep, recv);
+        }
+    }
+    return fmaxf(v[0], __shfl_xor(v[0], 1));
+}
+
+template <bool kStats>
+__global__ __launch_bounds__(kWave) void k_pass2(CompositeArgs a, const uint64_t *__restrict__ bin_off,
+                                                 const uint32_t *__restrict__ lists, const float4 *__restrict__ R0,
+                                                 const float4 *__restrict__ R1, const float4 *__restrict__ R2,
+                                                 const uint32_t *__restrict__ cmax_bits,
+                                                 const float *__restrict__ ray_A, uint64_t *__restrict__ counters) {
+    __shared__ float4 geo[kWave], col[kWave];
+    __shared__ uint32_t sid[kWave];
+    __shared__ float sold[kWave];
+    WaveSetup w;
+    if (!setup_wave(a, bin_off, w)) return;
+    const bool scored = w.inside && ray_selected(a.ray_mask, w.ray_global);
+    const float Af = scored ? ray_A[w.ray_local] : 0.0f;
+    const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
+    const float cmax = __uint_as_float(cmax_bits[w.v]);
+    const int64_t vbase = (int64_t)w.v * a.N;
+    const int lane = threadIdx.x;
+    float T = 1.0f;
+    bool done = invA == 0.0f;
+    uint32_t n_in = 0, n_live = 0, n_eval = 0;
+    const float live_bar = a.share_floor * Af;
+    for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
+        if (__all(done)) break;
+        const int n = stage_slice<1>(w, e0, lists, R0, R1, R2, vbase, geo, col, sid, sold, a.sens_bits, nullptr);
+        __syncthreads();
+        for (int jb = 0; jb < n; jb += 32) {
+            float sh[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const int j = jb + k;
+                if (j < n) {
+                    const float4 G = geo[j], Cc = col[j];
+                    bool in_fp;
+                    const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+                    const float cr = Cc.z * rho;
+                    sh[k] = (cr * T) * invA;
+                    if (kStats) {
+                        n_in += in_fp ? 1u : 0u;
+                        n_live += (in_fp && T * cmax >= live_bar) ? 1u : 0u;
+                    }
+                    T = fmaf(-rho, T, T);
+                } else {
+                    sh[k] = 0.0f;
+                }
+            }
+            if (kStats) n_eval += (uint32_t)min(32, n - jb);
+            const float m = wave_transpose_max32(sh);
+            const int j = jb + (lane >> 1);
+            if ((lane & 1) == 0 && j < n && m > sold[j]) atomicMax(&a.sens_bits[sid[j]], __float_as_uint(m));
+        }
+        done = done || (T * cmax < a.share_floor * Af);
+        __syncthreads();
+    }
+    if (kStats) {
+        uint64_t pin = invA > 0.0f ? n_in : 0u;
+        uint64_t plive = invA > 0.0f ? n_live : 0u;
+        uint64_t pos = invA > 0.0f ? 1u : 0u;
+        for (int off = 32; off > 0; off >>= 1) {
+            pin += __shfl_xor(pin, off);
+            plive += __shfl_xor(plive, off);
+            pos += __shfl_xor(pos, off);
+        }
+        if (lane == 0) {
+            atomicAdd((unsigned long long *)&counters[CNT_PAIRS], (unsigned long long)pin);
+            atomicAdd((unsigned long long *)&counters[CNT_LIVE], (unsigned long long)plive);
+            atomicAdd((unsigned long long *)&counters[CNT_RAYS_POS], (unsigned long long)pos);
+            atomicAdd((unsigned long long *)&counters[CNT_LANE_PAIRS], (unsigned long long)n_eval * 64ull);
+        }
+    }
+}
+
+static inline unsigned composite_grid(int total_tiles) { return (unsigned)(((total_tiles * 4) + 7) & ~7); }
+
+void launch_composite_pass1(const CompositeArgs &a, const ChunkBufs &b, hipStream_t st) {
+    hipLaunchKernelGGL(k_pass1, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, b.bin_off, b.lists,
+                       b.R0, b.R1, b.R2, b.cmax, b.ray_A);
+}
+
+void launch_composite_pass2(const CompositeArgs &a, const ChunkBufs &b, bool stats, hipStream_t st) {
+    if (stats)
+        hipLaunchKernelGGL(k_pass2<true>, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, b.bin_off,
+                           b.lists, b.R0, b.R1, b.R2, b.cmax, b.ray_A, b.counters);
+    else
+        hipLaunchKernelGGL(k_pass2<false>, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, b.bin_off,
+                           b.lists, b.R0, b.R1, b.R2, b.cmax, b.ray_A, b.counters);
+}
+
+// ---------------------------------------------------------------------------
+// Objectives of a weighted pruned scene (Section 3): full A, the fixed
+// relaxation A^th_w = sum w_i a_i (full-scene T), and the true reduced render
+// A_w with T_w = prod (1 - w_j rho_j) over retained Gaussians.  Also counts
+// pairs with w rho >= 1 (Definition 2) and tracks the log-transmittance gap
+// |log T - log T_w| = |sum log(1 - rho_j) - log(1 - w_j rho_j)| at every
+// contributing retained pair (Assumption 1), on rays that stay valid.
+__global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveArgs o,
+                                                     const uint64_t *__restrict__ bin_off,
+                                                     const uint32_t *__restrict__ lists,
+                                                     const float4 *__restrict__ R0, const float4 *__restrict__ R1,
+                                                     const float4 *__restrict__ R2,
+                                                     uint64_t *__restrict__ counters) {
+    __shared__ float4 geo[kWave], col[kWave];
+    WaveSetup w;
+    if (!setup_wave(a, bin_off, w)) return;
+    const bool scored = w.inside && ray_selected(a.ray_mask, w.ray_global);
+    const int64_t vbase = (int64_t)w.v * a.N;
+    const bool has_w = o.weights != nullptr;
+    float T = 1.0f, A = 0.0f, Ax = 0.0f, Tw = 1.0f, At = 0.0f, gap = 0.0f, gmax = 0.0f;
+    bool bad = false;
+    uint32_t n_bad = 0;
+    for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
+        if (__all(!scored)) break;
+        const int n = has_w ? stage_slice<2>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr,
+                                             o.weights)
+                            : stage_slice<0>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr,
+                                             nullptr);
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            const float4 G = geo[j], Cc = col[j];
+            bool in_fp;
+            const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+            const float cr = Cc.z * rho;
+            const float aT = cr * T;
+            A += aT;
+            if (has_w) {
+                const float wi = Cc.w;
+                Ax = fmaf(wi, aT, Ax);
+                if (wi > 0.0f) {
+                    const float wr = wi * rho;
+                    At = fmaf(wi * cr, Tw, At);
+                    if (rho > 0.0f && !bad) gmax = fmaxf(gmax, fabsf(gap));
+                    if (wr >= 1.0f) {
+                        bad = true;
+                        n_bad += scored ? 1u : 0u;
+                    }
+                    if (!bad) gap += log1pf(-rho) - log1pf(-wr);
+                    Tw = fmaf(-wr, Tw, Tw);
+                } else if (!bad) {
+                    gap += log1pf(-rho);
+                }
+            }
+            T = fmaf(-rho, T, T);
+        }
+        __syncthreads();
+    }
+    const bool on = scored && A > 0.0f;
+    if (w.inside && o.per_ray) {
+        float val = o.objective == 0 ? A : (o.objective == 1 ? Ax : At);
+        o.per_ray[w.ray_global] = on ? val : 0.0f;
+    }
+    double s0 = on ? (double)A : 0.0, s1 = on ? (double)Ax : 0.0, s2 = on ? (double)At : 0.0;
+    float gm = (on && !bad) ? gmax : 0.0f;
+    uint64_t nb = n_bad;
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_xor(s0, off);
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+        gm = fmaxf(gm, __shfl_xor(gm, off));
+        nb += __shfl_xor(nb, off);
+    }
+    if (threadIdx.x == 0) {
+        const int64_t slot = ((int64_t)w.gt * 4 + w.quad) * 3;
+        o.tile_sums[slot + 0] = s0;
+        o.tile_sums[slot + 1] = s1;
+        o.tile_sums[slot + 2] = s2;
+        if (nb) atomicAdd((unsigned long long *)&counters[CNT_INVALID_PAIRS], (unsigned long long)nb);
+        if (gm > 0.0f) atomicMax((unsigned long long *)&counters[CNT_GAMMA_BITS], (unsigned long long)__float_as_uint(gm));
+    }
+}
+
+void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, const ChunkBufs &b, hipStream_t st) {
+    hipLaunchKernelGGL(k_objective, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, o, b.bin_off,
+                       b.lists, b.R0, b.R1, b.R2, b.counters);
+}
+
+// Per-view sums of the per-wave partials, in a fixed order.
+__global__ void k_view_sums(const double *__restrict__ tile_sums, const ViewDev *__restrict__ views, int Vc,
+                            double *__restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Vc) return;
+    const ViewDev &V = views[v];
+    const int64_t lo = (int64_t)V.tile_base * 4, hi = lo + (int64_t)V.tiles_x * V.tiles_y * 4;
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t k = lo; k < hi; ++k) {
+        s0 += tile_sums[3 * k];
+        s1 += tile_sums[3 * k + 1];
+        s2 += tile_sums[3 * k + 2];
+    }
+    out[3 * v] = s0;
+    out[3 * v + 1] = s1;
+    out[3 * v + 2] = s2;
+}
+
+void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_view_sums, dim3((Vc + 63) / 64), dim3(64), 0, st, tile_sums, views_dev, Vc, per_view_out);
+}
+
+}  // namespace gs

@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP kernels and the host-side C ABI.
+// Not part of the public interface (that is include/gs_coreset.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kTile = 16;          // binning tile edge (pixels)
+constexpr int kQuad = 8;           // compositing quadrant edge: one wave per 8x8 quadrant
+constexpr int kChunkBits = 15;     // depth ranks are binned in chunks of 2^15
+constexpr int kMaxTilesPerView = 8160;  // two u32 LDS arrays of this size fit 64 KiB
+constexpr int kSortTile = 4096;    // radix sort: keys per block (4 waves x 16 rounds x 64 lanes)
+constexpr int kBinPositions = 2048; // binning: depth-sorted positions per block
+constexpr uint32_t kInvisibleKey = 0xFFFFFFFFu;
+constexpr uint32_t kIndexMask = 0x0FFFFFFFu; // list entry = gaussian | quadrant mask << 28
+
+// One camera of the current chunk, as the kernels see it.
+struct ViewDev {
+    double R[9];     // world-to-camera rotation, row-major
+    double t[3];
+    double cam[3];   // camera centre in world coordinates (-R^T t)
+    double fx, fy, cx, cy;
+    int32_t W, H, tiles_x, tiles_y;
+    int64_t ray_base;   // global index of the view's first ray
+    int64_t ray_local;  // index of the view's first ray inside this chunk's ray buffers
+    int32_t tile_base;  // first tile of this view inside the chunk
+    int32_t pad;
+};
+
+struct SceneDev {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t format;     // 0 = f32, 1 = mixed16 (bf16 mean/log_scale/sh, f16 quat/opacity)
+    const void *mean, *log_scale, *quat, *opacity, *sh;
+};
+
+struct ProjParams {
+    float footprint_sigma, dilation, z_near;
+    int32_t query_mode;
+};
+
+// Per-chunk device pointers produced by projection and binning.
+struct ChunkBufs {
+    float4 *R0;          // [Vc*N] mean2d hi.x, hi.y, lo.x, lo.y
+    float4 *R1;          // [Vc*N] beta, a', g', alpha   (d^2 form, see project.hip)
+    float4 *R2;          // [Vc*N] cbar, x-range, y-range (int16 pairs as bits), z
+    uint32_t *key0, *val0, *key1, *val1;  // [Vc*N] sort ping-pong
+    uint32_t *hist;      // radix histograms [Vc][256][nb]
+    uint32_t *nvis;      // [Vc] visible Gaussians per view
+    uint32_t *cmax;      // [Vc] largest query colour per view (float bits)
+    uint32_t *bin_count; // [Vc*tiles_total ... ] per (tile, chunk) entry counts
+    uint64_t *bin_off;   // exclusive scan of bin_count (+1 trailing total)
+    uint32_t *bin_fill;  // scatter cursors (zeroed)
+    uint32_t *lists;     // [D] entries
+    float *ray_A;        // [rays in chunk] pass-1 render
+    uint64_t *counters;  // device statistics
+};
+
+// counters[] slots
+enum : int {
+    CNT_PAIRS = 0, CNT_LANE_PAIRS = 1, CNT_RAYS_POS = 2, CNT_INVALID = 3, CNT_INVALID_PAIRS = 4,
+    CNT_GAMMA_BITS = 5, CNT_LIVE = 6, CNT_SLOTS = 8
+};
+
+// ---- launchers (each enqueues on `st`) -------------------------------------
+void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
+                    const ChunkBufs &b, hipStream_t st);
+hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1,
+                               uint32_t *hist, int64_t n_per_seg, int n_segs, bool vals_are_iota,
+                               uint32_t **key_out, uint32_t **val_out, hipStream_t st);
+void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
+                      const uint32_t *sorted_g, int max_tiles_per_view, hipStream_t st);
+void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
+                        const uint32_t *sorted_g, int max_tiles_per_view, hipStream_t st);
+void launch_segment_sort(int total_tiles, int nchunks, const ChunkBufs &b, const uint32_t *sorted_g,
+                         const int32_t *tile_view, int64_t N, hipStream_t st);
+void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
+                               hipStream_t st);
+void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp, hipStream_t st);
+int64_t scan_tmp_elems(int64_t n);
+
+struct CompositeArgs {
+    const ViewDev *views;
+    const int32_t *tile_view;    // [total_tiles] view of each tile in the chunk
+    int32_t total_tiles;
+    int32_t nchunks;
+    int64_t N;
+    float r2_log2;               // -0.5 log2(e) r^2  (cut on the exp2 argument)
+    float share_floor;
+    const uint32_t *ray_mask;    // global bitset or null
+    uint32_t *sens_bits;         // pass 2: float bits, atomicMax
+    int query_mode;
+};
+void launch_composite_pass1(const CompositeArgs &a, const ChunkBufs &b, hipStream_t st);
+void launch_composite_pass2(const CompositeArgs &a, const ChunkBufs &b, bool stats, hipStream_t st);
+
+struct ObjectiveArgs {
+    const double *weights;
+    int objective;
+    float *per_ray;             // global, nullable
+    double *tile_sums;          // [total_tiles*4][3] per-wave partial sums
+};
+void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, const ChunkBufs &b, hipStream_t st);
+void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
+                      hipStream_t st);
+
+// Sampler
+void launch_quantize(const float *sens, int64_t n, uint64_t *q, hipStream_t st);
+void launch_draws(const uint64_t *C, int64_t n, int64_t m, uint64_t seed, uint32_t *counts, hipStream_t st);
+void launch_weights(const uint32_t *counts, const uint64_t *q, const uint64_t *C, int64_t n, int64_t m,
+                    double *weights, int64_t *support, hipStream_t st);
+
+// Small utilities
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+void launch_sum_f32_to_f64(const float *x, int64_t n, double *out, double *block_tmp, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,211 @@
+// Projection of every Gaussian into every view of a chunk (Section 3:
+// camera map p -> R p + t, projected kernel k, attenuation rho = alpha k,
+// front-to-back order by view depth).
+//
+// One thread per Gaussian loads its attributes once (coalesced SoA planes)
+// and loops over the chunk's views; per view it writes a 48-byte record and
+// a depth key.  Set-up runs in FP64 (the vector FP64 rate equals the
+// non-packed FP32 rate on CDNA4), so the float32 record fields carry only
+// their own rounding.
+//
+// Record (all float32 unless noted):
+//   R0 = mean2d as float hi + float lo (x_hi, y_hi, x_lo, y_lo)
+//   R1 = (beta, a', g', alpha) with, for Delta = pixel centre - mean,
+//        u = Delta_x + beta Delta_y and P = a' u^2 + g' Delta_y^2,
+//        P = -(log2 e / 2) d^2 exactly in real arithmetic, so that
+//        k = exp(-d^2/2) = exp2(P).  This is the Cholesky form of the
+//        conic: both terms are non-negative multiples of -1, so P has no
+//        cancellation between them.
+//   R2 = (cbar, x-range, y-range, z): the inclusive pixel ranges whose
+//        centres can fall inside the r-ellipse, packed as int16 (lo | hi << 16).
+#include "gs_internal.hpp"
+
+#include <hip/hip_fp16.h>
+
+namespace gs {
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float load_attr(const void *base, int64_t idx, int f16kind) {
+    // f16kind: 0 = f32, 1 = bf16, 2 = ieee f16
+    if (f16kind == 0) return static_cast<const float *>(base)[idx];
+    uint16_t b = static_cast<const uint16_t *>(base)[idx];
+    if (f16kind == 1) return bf16_bits_to_f32(b);
+    return __half2float(__ushort_as_half(b));
+}
+
+// Real spherical harmonics (orthonormal, degree <= 3) at unit direction d.
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y) {
+    const double k00 = 0.28209479177387814;       // 1/(2 sqrt(pi))
+    const double k1 = 0.48860251190291992;        // sqrt(3/(4 pi))
+    const double k2a = 1.0925484305920792;        // 1/2 sqrt(15/pi)
+    const double k20 = 0.31539156525252005;       // 1/4 sqrt(5/pi)
+    const double k22 = 0.54627421529603959;       // 1/4 sqrt(15/pi)
+    const double k33 = 0.59004358992664352;       // 1/4 sqrt(35/(2 pi))
+    const double k32 = 2.8906114426405538;        // 1/2 sqrt(105/pi)
+    const double k31 = 0.45704579946446572;       // 1/4 sqrt(21/(2 pi))
+    const double k30 = 0.37317633259011540;       // 1/4 sqrt(7/pi)
+    const double k32b = 1.4453057213202769;       // 1/4 sqrt(105/pi)
+    Y[0] = k00;
+    Y[1] = k1 * y;
+    Y[2] = k1 * z;
+    Y[3] = k1 * x;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = k2a * x * y;
+    Y[5] = k2a * y * z;
+    Y[6] = k20 * (3.0 * zz - 1.0);
+    Y[7] = k2a * x * z;
+    Y[8] = k22 * (xx - yy);
+    Y[9] = k33 * y * (3.0 * xx - yy);
+    Y[10] = k32 * x * y * z;
+    Y[11] = k31 * y * (5.0 * zz - 1.0);
+    Y[12] = k30 * z * (5.0 * zz - 3.0);
+    Y[13] = k31 * x * (5.0 * zz - 1.0);
+    Y[14] = k32b * z * (xx - yy);
+    Y[15] = k33 * x * (xx - 3.0 * yy);
+}
+
+__device__ __forceinline__ uint32_t pack_range(int lo, int hi) {
+    return (uint32_t)(uint16_t)(int16_t)lo | ((uint32_t)(uint16_t)(int16_t)hi << 16);
+}
+
+__global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
+                                                 ProjParams pp, float4 *__restrict__ R0,
+                                                 float4 *__restrict__ R1, float4 *__restrict__ R2,
+                                                 uint32_t *__restrict__ keys, uint32_t *__restrict__ nvis,
+                                                 uint32_t *__restrict__ cmax_bits,
+                                                 uint64_t *__restrict__ counters) {
+    const int64_t n = sc.n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in_range = g < n;
+    const int64_t gi = in_range ? g : 0;
+    const int kf = sc.format == 1 ? 1 : 0;   // bf16 planes
+    const int kh = sc.format == 1 ? 2 : 0;   // f16 planes
+
+    double mu[3], ls[3], q[4];
+    for (int c = 0; c < 3; ++c) mu[c] = load_attr(sc.mean, c * n + gi, kf);
+    for (int c = 0; c < 3; ++c) ls[c] = load_attr(sc.log_scale, c * n + gi, kf);
+    for (int c = 0; c < 4; ++c) q[c] = load_attr(sc.quat, c * n + gi, kh);
+    const float alpha = load_attr(sc.opacity, gi, kh);
+    const int K = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+    float shc[48];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) shc[k] = k < 3 * K ? load_attr(sc.sh, (int64_t)k * n + gi, kf) : 0.0f;
+
+    bool valid = in_range;
+    double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    bool finite = isfinite(qn2) && qn2 > 0.0 && isfinite(alpha);
+    for (int c = 0; c < 3; ++c) finite = finite && isfinite(mu[c]) && isfinite(ls[c]);
+    for (int k = 0; k < 48; ++k) finite = finite && isfinite(shc[k]);
+    if (in_range && !finite) atomicAdd((unsigned long long *)&counters[CNT_INVALID], 1ull);
+    valid = valid && finite;
+
+    // 3D covariance Sigma = R(q) diag(exp(2 l)) R(q)^T (upper triangle).
+    double S3[6] = {0, 0, 0, 0, 0, 0};
+    if (valid) {
+        const double inv = 1.0 / sqrt(qn2);
+        const double w = q[0] * inv, x = q[1] * inv, y = q[2] * inv, z = q[3] * inv;
+        const double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                              2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                              2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        const double s2[3] = {exp(2.0 * ls[0]), exp(2.0 * ls[1]), exp(2.0 * ls[2])};
+        int k = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) {
+                double acc = 0.0;
+                for (int c = 0; c < 3; ++c) acc += Rq[3 * a + c] * s2[c] * Rq[3 * b + c];
+                S3[k++] = acc;
+            }
+    }
+    const double r = pp.footprint_sigma;
+    const float cut_pad = 0.01f;
+
+    for (int v = 0; v < Vc; ++v) {
+        const ViewDev &V = views[v];
+        const double *R = V.R;
+        const double px = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + V.t[0];
+        const double py = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + V.t[1];
+        const double pz = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + V.t[2];
+        bool vis = valid && pz > (double)pp.z_near;
+        float4 r0 = make_float4(0, 0, 0, 0), r1 = make_float4(0, 0, 0, 0), r2 = make_float4(0, 0, 0, 0);
+        float cbar = 0.0f;
+        if (vis) {
+            const double iz = 1.0 / pz;
+            // T = J R (2x3), J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]]
+            const double j00 = V.fx * iz, j02 = -V.fx * px * iz * iz;
+            const double j11 = V.fy * iz, j12 = -V.fy * py * iz * iz;
+            double T0[3], T1[3];
+            for (int c = 0; c < 3; ++c) {
+                T0[c] = j00 * R[c] + j02 * R[6 + c];
+                T1[c] = j11 * R[3 + c] + j12 * R[6 + c];
+            }
+            // Sigma_2d = T S3 T^T + delta I
+            const double S[3][3] = {{S3[0], S3[1], S3[2]}, {S3[1], S3[3], S3[4]}, {S3[2], S3[4], S3[5]}};
+            double u0[3], u1[3];
+            for (int a = 0; a < 3; ++a) {
+                u0[a] = S[a][0] * T0[0] + S[a][1] * T0[1] + S[a][2] * T0[2];
+                u1[a] = S[a][0] * T1[0] + S[a][1] * T1[1] + S[a][2] * T1[2];
+            }
+            const double sxx = T0[0] * u0[0] + T0[1] * u0[1] + T0[2] * u0[2] + (double)pp.dilation;
+            const double sxy = T0[0] * u1[0] + T0[1] * u1[1] + T0[2] * u1[2];
+            const double syy = T1[0] * u1[0] + T1[1] * u1[1] + T1[2] * u1[2] + (double)pp.dilation;
+            const double det = sxx * syy - sxy * sxy;
+            const double mx = V.fx * px * iz + V.cx;
+            const double my = V.fy * py * iz + V.cy;
+            const double rx = r * sqrt(sxx), ry = r * sqrt(syy);
+            double xl = ceil(mx - rx - 0.5 - cut_pad), xh = floor(mx + rx - 0.5 + cut_pad);
+            double yl = ceil(my - ry - 0.5 - cut_pad), yh = floor(my + ry - 0.5 + cut_pad);
+            xl = fmax(xl, 0.0); yl = fmax(yl, 0.0);
+            xh = fmin(xh, (double)(V.W - 1)); yh = fmin(yh, (double)(V.H - 1));
+            vis = det > 0.0 && syy > 0.0 && xl <= xh && yl <= yh;
+            if (vis) {
+                const double log2e = 1.4426950408889634;
+                const double beta = -sxy / syy;
+                const double a = syy / det;
+                const double gm = 1.0 / syy;
+                const float hx = (float)mx, hy = (float)my;
+                r0 = make_float4(hx, hy, (float)(mx - (double)hx), (float)(my - (double)hy));
+                r1 = make_float4((float)beta, (float)(-0.5 * log2e * a), (float)(-0.5 * log2e * gm), alpha);
+                // colour at the direction camera centre -> mean
+                double d0 = mu[0] - V.cam[0], d1 = mu[1] - V.cam[1], d2 = mu[2] - V.cam[2];
+                const double dn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                double Y[16];
+                sh_basis(d0 * dn, d1 * dn, d2 * dn, Y);
+                double csum = 0.0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double acc = 0.0;
+                    for (int k = 0; k < K; ++k) acc += Y[k] * (double)shc[3 * k + ch];
+                    acc += 0.5;
+                    csum += acc > 0.0 ? acc : 0.0;
+                }
+                cbar = pp.query_mode == 1 ? 1.0f : (float)csum;
+                r2 = make_float4(cbar, __uint_as_float(pack_range((int)xl, (int)xh)),
+                                 __uint_as_float(pack_range((int)yl, (int)yh)), (float)pz);
+            }
+        }
+        const int64_t o = (int64_t)v * n + gi;
+        if (in_range) {
+            R0[o] = r0;
+            R1[o] = r1;
+            R2[o] = r2;
+            keys[o] = vis ? __float_as_uint((float)pz) : kInvisibleKey;
+        }
+        // per-view visible count and colour maximum (wave-reduced first)
+        const uint64_t bal = __ballot(vis);
+        float cm = vis ? cbar : 0.0f;
+        for (int off = 32; off > 0; off >>= 1) cm = fmaxf(cm, __shfl_xor(cm, off));
+        if ((threadIdx.x & 63) == 0) {
+            if (bal) atomicAdd(&nvis[v], (uint32_t)__popcll(bal));
+            if (cm > 0.0f) atomicMax(&cmax_bits[v], __float_as_uint(cm));
+        }
+    }
+}
+
+void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
+                    const ChunkBufs &b, hipStream_t st) {
+    const int64_t blocks = (sc.n + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0, b.R1,
+                       b.R2, b.key0, b.nvis, b.cmax, b.counters);
+}
+
+}  // namespace gs

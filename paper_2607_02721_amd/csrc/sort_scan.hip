@@ -1,0 +1,318 @@
+// Segmented LSD radix sort of (u32 key, u32 value) pairs, exclusive/inclusive
+// prefix sums, fills and a fixed-order float sum.
+//
+// Radix sort: each of n_segs segments of n_per_seg items (one segment per
+// view) is sorted independently and stably by key, 8 bits per pass, 4
+// passes.  Blocks never straddle segments.  Per pass:
+//   hist:    per block, per digit counts -> hist[seg][digit][block]
+//   offsets: per segment exclusive scan of hist in (digit, block) order
+//   scatter: each wave ranks its 1024 keys in 16 rounds of 64 with ballot
+//            matching (wave-private LDS digit counters, so no block barrier
+//            inside the rounds); waves then add the counts of the waves
+//            before them, which keeps the sort stable.
+#include "gs_internal.hpp"
+
+namespace gs {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = kSortTile / kSortThreads;  // 16
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const unsigned lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lanes (among `active`) holding the same 8-bit digit as this lane.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
+    uint64_t m = active;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_per_seg,
+                                                              int nb, int shift, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[4][256];
+    const int seg = blockIdx.y, b = blockIdx.x;
+    const int w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)seg * n_per_seg;
+    const int64_t lo = (int64_t)b * kSortTile;
+    const int64_t hi = min(lo + (int64_t)kSortTile, n_per_seg);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) {
+        const uint32_t d = (keys[base + i] >> shift) & 255u;
+        atomicAdd(&cnt[w][d], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    const uint32_t tot = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+    hist[((int64_t)seg * 256 + d) * nb + b] = tot;
+}
+
+// One block per segment: exclusive scan over 256*nb counts (digit-major).
+__global__ __launch_bounds__(1024) void k_radix_offsets(uint32_t *__restrict__ hist, int nb) {
+    __shared__ uint32_t part[1024];
+    const int seg = blockIdx.x;
+    uint32_t *h = hist + (int64_t)seg * 256 * nb;
+    const int64_t total = (int64_t)256 * nb;
+    const int64_t per = (total + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per, hi = min(lo + per, total);
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += h[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t c = h[i];
+        h[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                                 const uint32_t *__restrict__ vin,
+                                                                 uint32_t *__restrict__ kout,
+                                                                 uint32_t *__restrict__ vout, int64_t n_per_seg,
+                                                                 int nb, int shift, int vals_are_iota,
+                                                                 const uint32_t *__restrict__ offs) {
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t wbase[4][256];
+    const int seg = blockIdx.y, b = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)seg * n_per_seg;
+    const int64_t wlo = (int64_t)b * kSortTile + (int64_t)w * (kSortRounds * 64);
+    uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+#pragma unroll
+    for (int k = 0; k < kSortRounds; ++k) {
+        const int64_t i = wlo + k * 64 + lane;
+        const bool ok = i < n_per_seg;
+        key[k] = ok ? kin[base + i] : 0u;
+        val[k] = ok ? (vals_are_iota ? (uint32_t)i : vin[base + i]) : 0u;
+        const uint32_t d = (key[k] >> shift) & 255u;
+        const uint64_t active = __ballot(ok);
+        const uint64_t peers = match_digit(d, active);
+        const uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
+        const uint32_t run = ok ? wcnt[w][d] : 0u;
+        rank[k] = run + before;
+        // the last peer advances the wave's counter for this digit
+        if (ok && (peers >> lane) == 1ull) wcnt[w][d] = run + before + 1u;
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t g = offs[((int64_t)seg * 256 + d) * nb + b];
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            wbase[ww][d] = g;
+            g += wcnt[ww][d];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortRounds; ++k) {
+        const int64_t i = wlo + k * 64 + lane;
+        if (i < n_per_seg) {
+            const uint32_t d = (key[k] >> shift) & 255u;
+            const uint32_t dst = wbase[w][d] + rank[k];
+            kout[base + dst] = key[k];
+            vout[base + dst] = val[k];
+        }
+    }
+}
+
+hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1, uint32_t *hist,
+                               int64_t n_per_seg, int n_segs, bool vals_are_iota, uint32_t **key_out,
+                               uint32_t **val_out, hipStream_t st) {
+    const int nb = (int)((n_per_seg + kSortTile - 1) / kSortTile);
+    uint32_t *ki = key0, *vi = val0, *ko = key1, *vo = val1;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, n_per_seg, nb, shift,
+                           hist);
+        hipLaunchKernelGGL(k_radix_offsets, dim3(n_segs), dim3(1024), 0, st, hist, nb);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_per_seg,
+                           nb, shift, (pass == 0 && vals_are_iota) ? 1 : 0, hist);
+        uint32_t *t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    *key_out = ki;
+    *val_out = vi;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Prefix sums over u64 (inputs u32 or u64), three phases with 2048-item blocks.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+template <typename T>
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *sh, uint64_t *total) {
+    // sh: kScanThreads entries
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        uint64_t x = t >= off ? sh[t - off] : 0ull;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    const uint64_t incl = sh[t];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *__restrict__ in, int64_t n,
+                                                               uint64_t *__restrict__ partial) {
+    __shared__ uint64_t sh[kScanThreads];
+    const int64_t lo = (int64_t)blockIdx.x * kScanBlock;
+    uint64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = lo + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) s += (uint64_t)in[i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Exclusive scan of the block partials in place (single block); partial[nblk] = total.
+__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ partial, int64_t nblk) {
+    __shared__ uint64_t sh[1024];
+    const int64_t per = (nblk + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per, hi = min(lo + per, nblk);
+    uint64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += partial[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint64_t x = threadIdx.x >= off ? sh[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        sh[threadIdx.x] += x;
+        __syncthreads();
+    }
+    uint64_t run = threadIdx.x ? sh[threadIdx.x - 1] : 0ull;
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint64_t c = partial[i];
+        partial[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) partial[nblk] = sh[1023];
+}
+
+template <typename T, bool kInclusive>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T *__restrict__ in, int64_t n,
+                                                              const uint64_t *__restrict__ partial,
+                                                              uint64_t *__restrict__ out) {
+    __shared__ uint64_t sh[kScanThreads];
+    const int64_t lo = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = lo + k;
+        v[k] = i < n ? (uint64_t)in[i] : 0ull;
+        s += v[k];
+    }
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<T>(s, sh, &total) + partial[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = lo + k;
+        if (kInclusive) run += v[k];
+        if (i < n) out[i] = run;
+        if (!kInclusive) run += v[k];
+    }
+}
+
+// out[i] = sum_{j<i} in[j] for i in [0, n]; out has n+1 entries.
+void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t st) {
+    const int64_t nblk = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_reduce<uint32_t>, dim3((unsigned)nblk), dim3(kScanThreads), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp, nblk);
+    hipLaunchKernelGGL((k_scan_apply<uint32_t, false>), dim3((unsigned)nblk), dim3(kScanThreads), 0, st, in, n,
+                       tmp, out);
+    // trailing total
+    hipMemcpyAsync(out + n, tmp + nblk, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+}
+
+void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t st) {
+    const int64_t nblk = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_reduce<uint64_t>, dim3((unsigned)nblk), dim3(kScanThreads), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp, nblk);
+    hipLaunchKernelGGL((k_scan_apply<uint64_t, true>), dim3((unsigned)nblk), dim3(kScanThreads), 0, st, in, n,
+                       tmp, out);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    const int64_t blocks = min((n + 255) / 256, (int64_t)65536);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+}
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    const int64_t blocks = min((n + 255) / 256, (int64_t)65536);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+}
+
+// Fixed-order sum: per-block tree sums in double, then a sequential sum of
+// the block results, so the total does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_sum_blocks(const float *__restrict__ x, int64_t n, double *partial) {
+    __shared__ double sh[256];
+    const int64_t lo = (int64_t)blockIdx.x * 4096;
+    double s = 0.0;
+    for (int k = 0; k < 16; ++k) {
+        const int64_t i = lo + (int64_t)k * 256 + threadIdx.x;
+        if (i < n) s += (double)x[i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+__global__ void k_sum_final(const double *partial, int64_t nblk, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int64_t i = 0; i < nblk; ++i) s += partial[i];
+        *out = s;
+    }
+}
+void launch_sum_f32_to_f64(const float *x, int64_t n, double *out, double *tmp, hipStream_t st) {
+    const int64_t nblk = (n + 4095) / 4096;
+    hipLaunchKernelGGL(k_sum_blocks, dim3((unsigned)nblk), dim3(256), 0, st, x, n, tmp);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, st, tmp, nblk, out);
+}
+
+}  // namespace gs

@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Floating point: |s_gpu - s_oracle| <= 1e-5 s_oracle + 1e-12 for every
+Gaussian, and per-ray A within 1e-5 relative, on the rays the oracle does not
+flag as ambiguous (a pair within 1e-5 r^2 of the footprint cutoff, or an
+order key within 2^-40 of a float32 rounding midpoint); both sides score
+exactly the same unflagged rays through the ray mask.  Sampling: bit-exact
+counts, weights and support given the same float32 sensitivities.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+REL, ABS = 1e-5, 1e-12
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_02721_amd as gs
+    gs.load()
+    return gs
+
+
+def _mask_tensor(bits):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(bits, np.uint32).view(np.int32)).cuda()
+
+
+def _parity(gs, ora, sc, vw, label, **kw):
+    ref_all = ora.sensitivity(sc, vw, ora.default_params(**{k: v for k, v in kw.items()
+                                                            if k in ("query_mode", "dilation")}))
+    keep = ~ref_all["flag"]
+    bits = synth.pack_bits(keep)
+    ref = ora.sensitivity(sc, vw, ora.default_params(**{k: v for k, v in kw.items()
+                                                        if k in ("query_mode", "dilation")}), bits)
+    dsc = gs.DeviceScene.from_scene(sc)
+    s, st = gs.sensitivity(dsc, vw, ray_mask=_mask_tensor(bits), stats=True, count_pairs=True, **kw)
+    s = s.cpu().numpy().astype(np.float64)
+    excess = np.abs(s - ref["s"]) - (REL * ref["s"] + ABS)
+    worst = int(np.argmax(excess))
+    print(f"[{label}] n={sc.n} flagged rays={int(ref_all['flag'].sum())}/{vw.n_rays} "
+          f"max rel err={np.max(np.abs(s - ref['s']) / np.maximum(ref['s'], 1e-30)):.2e} "
+          f"worst excess={excess[worst]:.2e} (s_ref={ref['s'][worst]:.3e})", flush=True)
+    assert excess.max() <= 0, f"{label}: Gaussian {worst}: gpu {s[worst]!r} oracle {ref['s'][worst]!r}"
+    return s, ref, st, bits
+
+
+def test_tiny_scene_sensitivity_parity(gs, ora):
+    sc, vw, _, _ = synth.make_config("tiny")
+    s, ref, st, _ = _parity(gs, ora, sc, vw, "tiny")
+    assert st["n_rays_positive"] == ref["rays_positive"]
+    assert abs(st["total_sensitivity"] - ref["s"].sum()) <= 1e-5 * ref["s"].sum()
+
+
+def _ragged():
+    sc = synth.make_cluster_scene(20_000, 7, 3)
+    vw = synth.make_orbit_views(3, 17, 200, 136)
+    return sc, vw
+
+
+def test_ragged_cluster_scene_parity(gs, ora):
+    """Several tiles with a ragged right/bottom edge (200x136 is 12.5 x 8.5
+    tiles of 16), SH degree 3, clustered means."""
+    sc, vw = _ragged()
+    _parity(gs, ora, sc, vw, "ragged")
+
+
+def test_nocolor_mode_parity(gs, ora):
+    sc, vw = _ragged()
+    _parity(gs, ora, sc, vw, "nocolor", query_mode=gs.QUERY_NOCOLOR)
+
+
+def test_pair_count_matches_without_stop(gs, ora):
+    """share_floor = 0 evaluates every pair: in-footprint pair counts agree."""
+    sc, vw, _, _ = synth.make_config("tiny")
+    s, ref, st, _ = _parity(gs, ora, sc, vw, "tiny-nostop", share_floor=0.0)
+    assert st["n_pairs"] == ref["pairs"]
+
+
+def test_live_pair_count_close_to_oracle(gs, ora):
+    """Pairs a ray still needs (T c_max >= floor A): float32 vs float64 prefix
+    transmittance decide only a handful of boundary pairs differently."""
+    sc, vw, _, _ = synth.make_config("tiny")
+    s, ref, st, _ = _parity(gs, ora, sc, vw, "tiny-live")
+    assert abs(st["n_live_pairs"] - ref["live_pairs"]) <= 1e-4 * ref["live_pairs"] + 5
+
+
+def test_determinism_and_chunking(gs):
+    sc, vw = _ragged()
+    dsc = gs.DeviceScene.from_scene(sc)
+    a, _ = gs.sensitivity(dsc, vw)
+    b, _ = gs.sensitivity(dsc, vw)
+    c, _ = gs.sensitivity(dsc, vw, max_views_per_chunk=1)
+    a, b, c = (x.cpu().numpy().view(np.uint32) for x in (a, b, c))
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+def test_render_full_matches_oracle(gs, ora):
+    sc, vw = _ragged()
+    ref = ora.sensitivity(sc, vw)
+    out = gs.render_objective(gs.DeviceScene.from_scene(sc), vw)
+    A = out["per_ray"].cpu().numpy().astype(np.float64)
+    ok = ~ref["flag"]
+    err = np.abs(A[ok] - ref["A"][ok]) - REL * ref["A"][ok]
+    assert err.max() <= 1e-30, f"max A excess {err.max():.3e}"
+    assert np.array_equal(A[ok] > 0, ref["A"][ok] > 0)
+
+
+@pytest.mark.parametrize("n,m,seed", [(2000, 200, 0), (100_000, 10_000, 123456789012345),
+                                      (257, 5000, 2 ** 63 + 11)])
+def test_sampler_bit_exact(gs, ora, n, m, seed):
+    import torch
+    rng = np.random.default_rng(n)
+    s = rng.uniform(0, 1, n).astype(np.float32)
+    s[rng.uniform(size=n) < 0.2] = 0
+    s[:3] = [1.0, 2.0 ** -40, 3 * 2.0 ** -40]
+    ref = ora.sample(s, m, seed)
+    counts, w, sup = gs.sample_coreset(torch.as_tensor(s).cuda(), m, seed)
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), ref["counts"])
+    assert np.array_equal(w.cpu().numpy().view(np.uint64), ref["weights"].view(np.uint64))
+    assert int(sup.item()) == ref["support"]
+
+
+def test_sampler_small_integer_cdf(gs, ora):
+    import torch
+    k = np.array([1, 2, 0, 3, 1, 4], np.float64)
+    s = (k * 2.0 ** -40).astype(np.float32)
+    ref = ora.sample(s, 4000, 5)
+    counts, w, sup = gs.sample_coreset(torch.as_tensor(s).cuda(), 4000, 5)
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), ref["counts"])
+    assert np.array_equal(w.cpu().numpy(), ref["weights"])
+
+
+def test_sampler_rejects_all_zero(gs):
+    import torch
+    with pytest.raises(gs.GsError) as e:
+        gs.sample_coreset(torch.zeros(100, device="cuda"), 10, 0)
+    assert e.value.status == 4
+
+
+def test_objective_parity(gs, ora):
+    import torch
+    sc, vw = _ragged()
+    ref_s = ora.sensitivity(sc, vw)
+    bits = synth.pack_bits(~ref_s["flag"])
+    dsc = gs.DeviceScene.from_scene(sc)
+    s, _ = gs.sensitivity(dsc, vw)
+    w_ref = ora.sample(s.cpu().numpy(), sc.n // 10, 3)["weights"]
+    w = torch.as_tensor(w_ref).cuda()
+    ob = ora.objective(sc, vw, w_ref, None, bits)
+    for obj, key in ((gs.OBJ_FULL, "A"), (gs.OBJ_FIXED, "A_fixed"), (gs.OBJ_TRUE, "A_true")):
+        out = gs.render_objective(dsc, vw, w, obj, ray_mask=_mask_tensor(bits))
+        got = out["per_ray"].cpu().numpy().astype(np.float64)
+        want = ob[key]
+        scale = np.maximum(np.abs(want), ob["A"])
+        err = np.abs(got - want) / np.maximum(scale, 1e-30)
+        tol = 1e-5 if obj != gs.OBJ_TRUE else 1e-4
+        assert err.max() <= tol, f"{key}: max rel err {err.max():.3e}"
+        pv = out["per_view"].cpu().numpy()
+        assert np.allclose(pv, ob["view_sums"], rtol=1e-5 if obj != gs.OBJ_TRUE else 1e-4)
+        assert out["n_invalid_pairs"] == ob["n_invalid"]
+        if ob["gamma"] > 0:
+            assert abs(out["gamma_max"] - ob["gamma"]) <= 1e-4 * ob["gamma"] + 1e-5
+
+
+def test_single_gaussian_scores_one(gs):
+    sc = synth.make_explicit_scene([(0.0, 0.0, 0.0)], [math.log(0.02)] * 3, (1, 0, 0, 0), 0.8,
+                                   [[0.3, 0.6, 0.2]])
+    vw = synth.make_camera_set([(-4.0, 0.0, 0.0)], [(0.0, 0.0, 0.0)], 37, 29, 60.0)
+    s, st = gs.sensitivity(gs.DeviceScene.from_scene(sc), vw, stats=True)
+    assert abs(float(s[0]) - 1.0) <= 2e-7
+    assert st["n_projected"] == 1
+
+
+def test_nothing_visible(gs):
+    """All Gaussians behind the camera: s = 0 and sampling reports it."""
+    sc, vw, _, _ = synth.make_config("tiny")
+    far = synth.make_camera_set([(0.0, 0.0, 5.0)], [(0.0, 0.0, 10.0)], 64, 64, 60.0, up=(1, 0, 0))
+    s, st = gs.sensitivity(gs.DeviceScene.from_scene(sc), far, stats=True)
+    assert float(s.abs().max()) == 0.0 and st["n_projected"] == 0
+    with pytest.raises(gs.GsError):
+        gs.sample_coreset(s, 10, 0)
+
+
+def test_masking_every_ray_gives_zero(gs):
+    sc, vw, _, _ = synth.make_config("tiny")
+    bits = synth.pack_bits(np.zeros(vw.n_rays, bool))
+    s, _ = gs.sensitivity(gs.DeviceScene.from_scene(sc), vw, ray_mask=_mask_tensor(bits))
+    assert float(s.abs().max()) == 0.0
+
+
+def test_nan_attribute_reported(gs):
+    sc, vw, _, _ = synth.make_config("tiny")
+    sc.mean[0, 5] = np.nan
+    with pytest.raises(gs.GsError) as e:
+        gs.sensitivity(gs.DeviceScene.from_scene(sc), vw, stats=True)
+    assert e.value.status == 5
+
+
+def test_mixed_view_sizes_in_one_call(gs, ora):
+    sc = synth.make_cluster_scene(5000, 9, 1)
+    vw = synth.make_orbit_views(4, 21, resolutions=[(64, 48), (97, 61), (33, 130)])
+    _parity(gs, ora, sc, vw, "mixed-sizes")
