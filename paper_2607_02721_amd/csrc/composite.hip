@@ -160,27 +160,54 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a, const uint64_t
 }
 
 // Transposed butterfly over 64 lanes for 32 values: afterwards lane L holds
-// the maximum over all lanes of value (L >> 1).
+// the maximum over all 64 lanes of value (L >> 1) & 31.  Each level pairs
+// every lane with a partner on the other side of one lane-index bit and
+// keeps half of the values:
+//   bit 5: v_permlane32_swap (upper 32 lanes of one register <-> lower 32 of another)
+//   bit 4: v_permlane16_swap (odd 16-lane rows <-> even rows)
+//   bit 3: DPP row_mirror (i <-> 15-i in a row), bit 2: row_half_mirror (i <-> 7-i),
+//   bit 1: quad_perm [2,3,0,1], bit 0: quad_perm [1,0,3,2]
+// Every index is a compile-time constant, so the values stay in registers.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_max(float x) {
+    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, false));
+    return fmaxf(x, y);
+}
+
 __device__ __forceinline__ float wave_transpose_max32(float (&v)[32]) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int lvl = 0; lvl < 5; ++lvl) {
-        const int half = 16 >> lvl;
-        const int mask = 32 >> lvl;
-        const bool up = (lane & mask) != 0;
-#pragma unroll
-        for (int k = 0; k < half; ++k) {
-            const float keep = up ? v[half + k] : v[k];
-            const float send = up ? v[k] : v[half + k];
-            const float recv = __shfl_xor(send, mask);
-            v[k] = fmaxf(keep, recv);
-        }
+    for (int k = 0; k < 16; ++k) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 16]),
+                                                        false, false);
+        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
     }
-    return fmaxf(v[0], __shfl_xor(v[0], 1));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 8]),
+                                                        false, false);
+        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    }
+    const bool s3 = (lane & 8) != 0, s2 = (lane & 4) != 0, s1 = (lane & 2) != 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float m0 = dpp_max<0x140>(v[k]), m1 = dpp_max<0x140>(v[k + 4]);
+        v[k] = s3 ? m1 : m0;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float m0 = dpp_max<0x141>(v[k]), m1 = dpp_max<0x141>(v[k + 2]);
+        v[k] = s2 ? m1 : m0;
+    }
+    {
+        const float m0 = dpp_max<0x4E>(v[0]), m1 = dpp_max<0x4E>(v[1]);
+        v[0] = s1 ? m1 : m0;
+    }
+    return dpp_max<0xB1>(v[0]);
 }
 
 template <bool kStats>
-__global__ __launch_bounds__(kWave) void k_pass2(CompositeArgs a, const uint64_t *__restrict__ bin_off,
+__global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, const uint64_t *__restrict__ bin_off,
                                                  const uint32_t *__restrict__ lists, const float4 *__restrict__ R0,
                                                  const float4 *__restrict__ R1, const float4 *__restrict__ R2,
                                                  const uint32_t *__restrict__ cmax_bits,

@@ -9,7 +9,7 @@ namespace gs {
 
 constexpr int kTile = 16;          // binning tile edge (pixels)
 constexpr int kQuad = 8;           // compositing quadrant edge: one wave per 8x8 quadrant
-constexpr int kChunkBits = 15;     // depth ranks are binned in chunks of 2^15
+constexpr int kChunkBits = 11;     // depth ranks are binned in chunks of 2^11 (one binning block)
 constexpr int kMaxTilesPerView = 8160;  // two u32 LDS arrays of this size fit 64 KiB
 constexpr int kSortTile = 4096;    // radix sort: keys per block (4 waves x 16 rounds x 64 lanes)
 constexpr int kBinPositions = 2048; // binning: depth-sorted positions per block
