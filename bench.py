@@ -103,6 +103,32 @@ def main():
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     log(f"exact: {ms:.2f} ms/step  stages {json.dumps({k: round(v, 3) for k, v in stage.items()})}")
 
+    # the same pass on the scene stored as bf16 (mean, log-scale, SH) + f16
+    # (quaternion, opacity): half the attribute bytes, same arithmetic
+    d16 = gs.DeviceScene.from_scene(scene, fmt=gs.ATTR_MIXED16)
+    for _ in range(args.warmup):
+        step(stats=True, scene_dev=d16)
+    torch.cuda.synchronize()
+    stage16 = {k: 0.0 for k in stage}
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s16, st16, w16 = step(stats=True, scene_dev=d16)
+        for key in stage16:
+            stage16[key] += st16[key] / args.steps
+    torch.cuda.synchronize()
+    ms16 = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"mixed16: {ms16:.2f} ms/step  stages {json.dumps({k: round(v, 3) for k, v in stage16.items()})}")
+
+    # coreset-objective error E (max over views of |sum A^th_w - sum A| / sum A)
+    # on a 1% ray subsample, for the weights each variant drew, judged on the
+    # float32 scene
+    sub = torch.as_tensor(synth.ray_subsample_mask(views, 1).view(np.int32)).cuda()
+    errs = {}
+    for name, w_ in (("exact", w), ("mixed16", w16)):
+        ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
+        errs[name] = gs.coreset_error(ob["per_view"])
+    log(f"E: {errs}")
+
     log("counting pairs (untimed) ...")
     _, cst, _ = step(stats=True, count_pairs=True)
     live = cst["n_live_pairs"]
@@ -127,6 +153,10 @@ def main():
         "config": {"workload": "scene1m: 1M Gaussians (64 clusters + 10% uniform, SH deg 3), "
                                f"{args.views} orbit views 1280x720, m=100000, Philox seed 0"},
         "stages_ms": stage,
+        "variants": {"exact_f32": {"ms": ms, "coreset_err": errs["exact"]},
+                     "mixed16": {"ms": ms16, "coreset_err": errs["mixed16"], "stages_ms": stage16,
+                                 "attribute_bytes": d16.attribute_bytes()}},
+        "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on a 1% ray subsample, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],
                   "entries": cst["n_entries"], "projected": cst["n_projected"]},
         "live_pairs_per_s": live / (ms * 1e-3),

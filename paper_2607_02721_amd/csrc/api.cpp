@@ -315,7 +315,6 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(hipMemcpyAsync(r.tile_view, htv.data(), sizeof(int32_t) * c.total_tiles, hipMemcpyHostToDevice, st));
     launch_fill_u32(b.nvis, 0u, 2 * (int64_t)c.vc, st);
     launch_fill_u32(b.bin_count, 0u, nbins, st);
-    launch_fill_u32(b.bin_fill, 0u, nbins, st);
     if (zero_counters) launch_fill_u64(b.counters, 0ull, CNT_SLOTS, st);
 
     SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
@@ -328,17 +327,24 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     uint32_t *skeys = nullptr;
     HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, &skeys, &r.sorted_g, st));
     tm.mark(2, st);
-    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, r.sorted_g, kMaxTilesPerView, st);
+    // after 4 radix passes the sorted pairs are back in (key0, val0); key1/val1 are free
+    uint32_t *xr = b.key1, *yr = b.val1;
+    launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
+    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, st);
     scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, nbins, r.scan_tmp, st);
     HIP_TRY(hipGetLastError());
     uint64_t total = 0;
     HIP_TRY(hipMemcpyAsync(&total, b.bin_off + nbins, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     r.n_entries = (int64_t)total;
-    HIP_TRY(arena_reserve(g_lists[dev], std::max<size_t>(total, 1) * sizeof(uint32_t)));
+    // lists, then the work list of segments longer than 64 entries (at most total/65 of them)
+    const int64_t big_cap = (int64_t)(total / 65) + 1;
+    const size_t list_bytes = ((std::max<size_t>(total, 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
+    HIP_TRY(arena_reserve(g_lists[dev], list_bytes + sizeof(uint64_t) * (1 + 2 * (size_t)big_cap)));
     b.lists = (uint32_t *)g_lists[dev].base;
-    launch_bin_scatter(r.views_dev, c.vc, N, S.nchunks, b, r.sorted_g, kMaxTilesPerView, st);
-    launch_segment_sort(c.total_tiles, S.nchunks, b, r.sorted_g, r.tile_view, N, st);
+    uint64_t *big = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
+    launch_bin_scatter(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, st);
+    launch_segment_sort(c.total_tiles, S.nchunks, b, r.sorted_g, r.tile_view, N, big, big_cap, st);
     HIP_TRY(hipGetLastError());
     tm.mark(3, st);
     if (tm.on) {

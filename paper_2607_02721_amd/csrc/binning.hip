@@ -45,10 +45,11 @@ __device__ __forceinline__ uint32_t quad_mask(int tx, int ty, int xl, int xh, in
 template <bool kScatter>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__ views, int64_t N, int nchunks,
                                                      const uint32_t *__restrict__ nvis,
-                                                     const uint32_t *__restrict__ sorted_g,
-                                                     const float4 *__restrict__ R2, uint32_t *__restrict__ bin_count,
+                                                     const uint32_t *__restrict__ xr_in,
+                                                     const uint32_t *__restrict__ yr_in,
+                                                     uint32_t *__restrict__ bin_count,
                                                      const uint64_t *__restrict__ bin_off,
-                                                     uint32_t *__restrict__ bin_fill, uint32_t *__restrict__ lists) {
+                                                     uint32_t *__restrict__ lists) {
     extern __shared__ uint32_t lds[];
     uint32_t *cnt = lds;                              // [tiles]
     uint32_t *base = lds + kMaxTilesPerView;          // [tiles] (scatter only)
@@ -63,11 +64,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
     for (int t = threadIdx.x; t < ntiles; t += kBinThreads) cnt[t] = 0;
     __syncthreads();
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBinThreads) {
-        const uint32_t g = sorted_g[(int64_t)v * N + p];
-        const float4 r2 = R2[(int64_t)v * N + g];
         int xl, xh, yl, yh;
-        unpack_range(r2.y, xl, xh);
-        unpack_range(r2.z, yl, yh);
+        unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
+        unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
         for (int ty = yl >> 4; ty <= (yh >> 4); ++ty)
             for (int tx = xl >> 4; tx <= (xh >> 4); ++tx) atomicAdd(&cnt[ty * V.tiles_x + tx], 1u);
     }
@@ -89,11 +88,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
     __syncthreads();
     uint32_t *vl = lists + vlist;
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBinThreads) {
-        const uint32_t g = sorted_g[(int64_t)v * N + p];
-        const float4 r2 = R2[(int64_t)v * N + g];
         int xl, xh, yl, yh;
-        unpack_range(r2.y, xl, xh);
-        unpack_range(r2.z, yl, yh);
+        unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
+        unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
         for (int ty = yl >> 4; ty <= (yh >> 4); ++ty)
             for (int tx = xl >> 4; tx <= (xh >> 4); ++tx) {
                 const int t = ty * V.tiles_x + tx;
@@ -104,19 +101,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
 }
 
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                      const uint32_t *sorted_g, int max_tiles_per_view, hipStream_t st) {
-    (void)max_tiles_per_view;
+                      const uint32_t *xr, const uint32_t *yr, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     hipLaunchKernelGGL(k_bin<false>, dim3(nb, Vc), dim3(kBinThreads), kMaxTilesPerView * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, sorted_g, b.R2, b.bin_count, b.bin_off, b.bin_fill, b.lists);
+                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists);
 }
 
 void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                        const uint32_t *sorted_g, int max_tiles_per_view, hipStream_t st) {
-    (void)max_tiles_per_view;
+                        const uint32_t *xr, const uint32_t *yr, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     hipLaunchKernelGGL(k_bin<true>, dim3(nb, Vc), dim3(kBinThreads), 2 * kMaxTilesPerView * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, sorted_g, b.R2, b.bin_count, b.bin_off, b.bin_fill, b.lists);
+                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists);
 }
 
 // One wave per tile: sort every (tile, chunk) segment by depth position.
@@ -142,11 +137,24 @@ __device__ __forceinline__ uint32_t bitonic64(uint32_t key, int lane) {
 
 __device__ __forceinline__ uint32_t entry_key(uint32_t raw) { return ((raw & kIndexMask) << 4) | (raw >> 28); }
 
+// Append the first nbig lanes' queued segments to the work list.
+__device__ __forceinline__ void flush_big(uint64_t *big, int64_t big_cap, uint64_t start, uint64_t meta, int nbig,
+                                          int lane) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long *)&big[0], (unsigned long long)nbig);
+    base = __shfl(base, 0);
+    const int64_t k = (int64_t)base + lane;
+    if (lane < nbig && k < big_cap) {
+        big[1 + 2 * k] = start;
+        big[2 + 2 * k] = meta;
+    }
+}
+
 __global__ __launch_bounds__(kSortWave) void k_segment_sort(int nchunks, const uint64_t *__restrict__ bin_off,
                                                             uint32_t *__restrict__ lists,
                                                             const uint32_t *__restrict__ sorted_g,
-                                                            const int32_t *__restrict__ tile_view, int64_t N) {
-    __shared__ uint32_t big[kSegSize];
+                                                            const int32_t *__restrict__ tile_view, int64_t N,
+                                                            uint64_t *__restrict__ big, int64_t big_cap) {
     const int gt = blockIdx.x;
     const int lane = threadIdx.x;
     const uint32_t *gv = sorted_g + (int64_t)tile_view[gt] * N;
@@ -154,59 +162,109 @@ __global__ __launch_bounds__(kSortWave) void k_segment_sort(int nchunks, const u
     const uint64_t e_end = bo[nchunks];
     uint64_t e0 = bo[0];
     int si = 0;  // e0 == bo[si]
+    uint64_t b = (1 <= nchunks - lane) ? bo[1 + lane] : ~0ull;   // boundaries bo[si+1 ..]
+    // software pipeline: the previous slice's gathered entries are stored one
+    // iteration late, so its gather overlaps the next slice's loads
+    uint64_t pend_at = 0;
+    uint32_t pend_val = 0;
+    bool pend = false;
+    int nbig = 0;
+    uint64_t my_start = 0, my_meta = 0;
     while (e0 < e_end) {
-        const int s = si + 1 + lane;
-        const uint64_t b = s <= nchunks ? bo[s] : ~0ull;
         const uint64_t fit = __ballot(b <= e0 + kSortWave);
         const int nseg = __popcll(fit);
         if (nseg > 0) {
             const uint64_t slice_end = __shfl(b, nseg - 1);
             const int n = (int)(slice_end - e0);
+            const uint32_t raw = lane < n ? lists[e0 + lane] : 0u;
+            const int s = si + nseg + 1 + lane;
+            const uint64_t bn = s <= nchunks ? bo[s] : ~0ull;
+            if (pend) lists[pend_at] = pend_val;
+            pend = false;
             if (n > 0) {
-                uint32_t key = lane < n ? entry_key(lists[e0 + lane]) : 0xFFFFFFFFu;
+                uint32_t key = lane < n ? entry_key(raw) : 0xFFFFFFFFu;
                 key = bitonic64(key, lane);
-                if (lane < n) lists[e0 + lane] = gv[key >> 4] | ((key & 15u) << 28);
+                if (lane < n) {
+                    pend_at = e0 + lane;
+                    pend_val = gv[key >> 4] | ((key & 15u) << 28);
+                    pend = true;
+                }
             }
             e0 = slice_end;
             si += nseg;
+            b = bn;
         } else {
-            // segment si alone holds more than 64 (and at most 2^11) entries
-            const uint64_t seg_end = bo[si + 1];
-            const int n = (int)(seg_end - e0);
-            int pad = 128;
-            while (pad < n) pad <<= 1;
-            for (int i = lane; i < pad; i += kSortWave) big[i] = i < n ? entry_key(lists[e0 + i]) : 0xFFFFFFFFu;
-            __syncthreads();
-            for (int k = 2; k <= pad; k <<= 1)
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int i = lane; i < pad; i += kSortWave) {
-                        const int ixj = i ^ j;
-                        if (ixj > i) {
-                            const uint32_t x = big[i], y = big[ixj];
-                            const bool up = (i & k) == 0;
-                            if ((x > y) == up) {
-                                big[i] = y;
-                                big[ixj] = x;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            for (int i = lane; i < n; i += kSortWave) {
-                const uint32_t key = big[i];
-                lists[e0 + i] = gv[key >> 4] | ((key & 15u) << 28);
+            // segment si alone holds more than 64 (and at most 2^11) entries:
+            // queue it for the LDS sorter (lane nbig of this wave keeps it;
+            // the wave appends 64 at a time with one atomic)
+            const uint64_t seg_end = __shfl(b, 0);
+            if (lane == nbig) {
+                my_start = e0;
+                my_meta = (uint64_t)(seg_end - e0) | ((uint64_t)gt << 32);
             }
-            __syncthreads();
+            if (++nbig == kSortWave) {
+                flush_big(big, big_cap, my_start, my_meta, nbig, lane);
+                nbig = 0;
+            }
             e0 = seg_end;
             si += 1;
+            const int s = si + 1 + lane;
+            b = s <= nchunks ? bo[s] : ~0ull;
         }
+    }
+    if (nbig) flush_big(big, big_cap, my_start, my_meta, nbig, lane);
+    if (pend) lists[pend_at] = pend_val;
+}
+
+// Segments of more than 64 entries: one wave per segment (the waves loop
+// over the work list), bitonic sort in LDS.
+__global__ __launch_bounds__(kSortWave) void k_big_segment_sort(uint32_t *__restrict__ lists,
+                                                                const uint32_t *__restrict__ sorted_g,
+                                                                const int32_t *__restrict__ tile_view, int64_t N,
+                                                                const uint64_t *__restrict__ big, int64_t big_cap) {
+    __shared__ uint32_t keys[kSegSize];
+    const int64_t count = min((int64_t)big[0], big_cap);
+    const int lane = threadIdx.x;
+    for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
+        const uint64_t e0 = big[1 + 2 * w];
+        const uint64_t meta = big[2 + 2 * w];
+        const int n = (int)(meta & 0xFFFFFFFFull);
+        const int gt = (int)(meta >> 32);
+        const uint32_t *gv = sorted_g + (int64_t)tile_view[gt] * N;
+        int pad = 128;
+        while (pad < n) pad <<= 1;
+        for (int i = lane; i < pad; i += kSortWave) keys[i] = i < n ? entry_key(lists[e0 + i]) : 0xFFFFFFFFu;
+        __syncthreads();
+        for (int k = 2; k <= pad; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < pad; i += kSortWave) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint32_t x = keys[i], y = keys[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            keys[i] = y;
+                            keys[ixj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int i = lane; i < n; i += kSortWave) {
+            const uint32_t key = keys[i];
+            lists[e0 + i] = gv[key >> 4] | ((key & 15u) << 28);
+        }
+        __syncthreads();
     }
 }
 
 void launch_segment_sort(int total_tiles, int nchunks, const ChunkBufs &b, const uint32_t *sorted_g,
-                         const int32_t *tile_view, int64_t N, hipStream_t st) {
+                         const int32_t *tile_view, int64_t N, uint64_t *big, int64_t big_cap, hipStream_t st) {
+    launch_fill_u64(big, 0ull, 1, st);
     hipLaunchKernelGGL(k_segment_sort, dim3(total_tiles), dim3(kSortWave), 0, st, nchunks, b.bin_off, b.lists,
-                       sorted_g, tile_view, N);
+                       sorted_g, tile_view, N, big, big_cap);
+    hipLaunchKernelGGL(k_big_segment_sort, dim3(8192), dim3(kSortWave), 0, st, b.lists, sorted_g, tile_view, N,
+                       big, big_cap);
 }
 
 }  // namespace gs

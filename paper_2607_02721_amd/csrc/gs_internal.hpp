@@ -70,12 +70,15 @@ void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const 
 hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1,
                                uint32_t *hist, int64_t n_per_seg, int n_segs, bool vals_are_iota,
                                uint32_t **key_out, uint32_t **val_out, hipStream_t st);
+void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
+                            uint32_t *yr, hipStream_t st);
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                      const uint32_t *sorted_g, int max_tiles_per_view, hipStream_t st);
+                      const uint32_t *xr, const uint32_t *yr, hipStream_t st);
 void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                        const uint32_t *sorted_g, int max_tiles_per_view, hipStream_t st);
+                        const uint32_t *xr, const uint32_t *yr, hipStream_t st);
+// big: work list of segments with more than 64 entries ([0] = count, then (start, n) pairs)
 void launch_segment_sort(int total_tiles, int nchunks, const ChunkBufs &b, const uint32_t *sorted_g,
-                         const int32_t *tile_view, int64_t N, hipStream_t st);
+                         const int32_t *tile_view, int64_t N, uint64_t *big, int64_t big_cap, hipStream_t st);
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
                                hipStream_t st);
 void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp, hipStream_t st);

@@ -69,6 +69,7 @@ __device__ __forceinline__ uint32_t pack_range(int lo, int hi) {
     return (uint32_t)(uint16_t)(int16_t)lo | ((uint32_t)(uint16_t)(int16_t)hi << 16);
 }
 
+template <int kDeg, int kFmt>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
                                                  ProjParams pp, float4 *__restrict__ R0,
                                                  float4 *__restrict__ R1, float4 *__restrict__ R2,
@@ -79,24 +80,25 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in_range = g < n;
     const int64_t gi = in_range ? g : 0;
-    const int kf = sc.format == 1 ? 1 : 0;   // bf16 planes
-    const int kh = sc.format == 1 ? 2 : 0;   // f16 planes
+    constexpr int kf = kFmt == 1 ? 1 : 0;   // bf16 planes
+    constexpr int kh = kFmt == 1 ? 2 : 0;   // f16 planes
 
     double mu[3], ls[3], q[4];
     for (int c = 0; c < 3; ++c) mu[c] = load_attr(sc.mean, c * n + gi, kf);
     for (int c = 0; c < 3; ++c) ls[c] = load_attr(sc.log_scale, c * n + gi, kf);
     for (int c = 0; c < 4; ++c) q[c] = load_attr(sc.quat, c * n + gi, kh);
     const float alpha = load_attr(sc.opacity, gi, kh);
-    const int K = (sc.sh_degree + 1) * (sc.sh_degree + 1);
-    float shc[48];
+    constexpr int K = (kDeg + 1) * (kDeg + 1);
+    float shc[3 * K];
 #pragma unroll
-    for (int k = 0; k < 48; ++k) shc[k] = k < 3 * K ? load_attr(sc.sh, (int64_t)k * n + gi, kf) : 0.0f;
+    for (int k = 0; k < 3 * K; ++k) shc[k] = load_attr(sc.sh, (int64_t)k * n + gi, kf);
 
     bool valid = in_range;
     double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     bool finite = isfinite(qn2) && qn2 > 0.0 && isfinite(alpha);
     for (int c = 0; c < 3; ++c) finite = finite && isfinite(mu[c]) && isfinite(ls[c]);
-    for (int k = 0; k < 48; ++k) finite = finite && isfinite(shc[k]);
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) finite = finite && isfinite(shc[k]);
     if (in_range && !finite) atomicAdd((unsigned long long *)&counters[CNT_INVALID], 1ull);
     valid = valid && finite;
 
@@ -172,8 +174,10 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                 double Y[16];
                 sh_basis(d0 * dn, d1 * dn, d2 * dn, Y);
                 double csum = 0.0;
+#pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     double acc = 0.0;
+#pragma unroll
                     for (int k = 0; k < K; ++k) acc += Y[k] * (double)shc[3 * k + ch];
                     acc += 0.5;
                     csum += acc > 0.0 ? acc : 0.0;
@@ -201,11 +205,42 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
     }
 }
 
+template <int kDeg, int kFmt>
+static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp, const ChunkBufs &b,
+                     hipStream_t st) {
+    const int64_t blocks = (sc.n + 255) / 256;
+    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0,
+                       b.R1, b.R2, b.key0, b.nvis, b.cmax, b.counters);
+}
+
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
                     const ChunkBufs &b, hipStream_t st) {
-    const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0, b.R1,
-                       b.R2, b.key0, b.nvis, b.cmax, b.counters);
+    using L = void (*)(const SceneDev &, const ViewDev *, int, const ProjParams &, const ChunkBufs &, hipStream_t);
+    static const L table[2][4] = {{launch_t<0, 0>, launch_t<1, 0>, launch_t<2, 0>, launch_t<3, 0>},
+                                  {launch_t<0, 1>, launch_t<1, 1>, launch_t<2, 1>, launch_t<3, 1>}};
+    table[sc.format == 1 ? 1 : 0][sc.sh_degree](sc, views_dev, Vc, pp, b, st);
+}
+
+// Depth-ordered copy of each visible Gaussian's pixel ranges, so that the
+// binning kernels read them with unit stride: xr/yr[v*N + p] for position p
+// of view v's front-to-back order.
+__global__ __launch_bounds__(256) void k_ranges_in_order(const uint32_t *__restrict__ sorted_g,
+                                                         const float4 *__restrict__ R2,
+                                                         const uint32_t *__restrict__ nvis, int64_t N,
+                                                         uint32_t *__restrict__ xr, uint32_t *__restrict__ yr) {
+    const int v = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)nvis[v]) return;
+    const int64_t o = (int64_t)v * N;
+    const float4 r = R2[o + sorted_g[o + p]];
+    xr[o + p] = __float_as_uint(r.y);
+    yr[o + p] = __float_as_uint(r.z);
+}
+
+void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
+                            uint32_t *yr, hipStream_t st) {
+    hipLaunchKernelGGL(k_ranges_in_order, dim3((unsigned)((N + 255) / 256), Vc), dim3(256), 0, st, sorted_g, b.R2,
+                       b.nvis, N, xr, yr);
 }
 
 }  // namespace gs
