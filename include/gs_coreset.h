@@ -161,6 +161,47 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
                               const double *weights, int32_t objective, float *per_ray,
                               double *per_view, gs_render_diag *diag, void *stream);
 
+/* ---- Learned sampling proposal ------------------------------------------
+ * A proposal distribution for sensitivity sampling: the sampler's
+ * unbiasedness (proof of Theorem 2) holds for any p with p_i > 0 wherever
+ * a_i can be > 0, so a cheap predictor of s, mixed with a uniform floor, can
+ * replace the exact pass; the fixed objective then judges the draw.
+ * MLP 64 -> 256 -> 256 -> 256 -> 1 with SiLU, predicting ln(max(s, 1e-12)).
+ * Parameters are float32 in PyTorch Linear layout, concatenated:
+ *   W1[256][64] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] w4[256] b4
+ * (gs_mlp_param_count() floats).  Products run in BF16 on the matrix cores
+ * with FP32 accumulation; hidden activations are stored in BF16. */
+int64_t gs_mlp_param_count(void);
+
+/* Uniform(-a, a) weights with a = sqrt(6 / (fan_in + fan_out)) from `seed`,
+ * zero biases.  params: device float[gs_mlp_param_count()]. */
+gs_status gs_mlp_init(float *params, uint64_t seed, void *stream);
+
+/* Per-Gaussian features, device float[n][64]: mean (3), log-scale (3),
+ * quaternion normalised with w >= 0 (4), logit(alpha) (1), SH coefficients
+ * padded to 48, then over the 16 nearest other means (exact, ties by
+ * index): log mean distance, log 16th distance, mean and max neighbour
+ * alpha, log(sum of alphas / volume of the 16th-neighbour ball).
+ * Synchronises the stream once (grid sizing). */
+gs_status gs_features(const gs_scene *scene, float *features, void *stream);
+
+/* Column means and 1/std of device float[n][64] into device float[2][64]. */
+gs_status gs_feature_stats(const float *features, int64_t n, float *norm, void *stream);
+
+/* Predicted ln s for n rows of raw features (standardised with `norm`):
+ * out device float[n]. */
+gs_status gs_mlp_forward(const float *params, const float *features, const float *norm, int64_t n,
+                         float *out, void *stream);
+
+/* One batch (1 <= n <= 65536 rows): loss = mean((yhat - targets)^2) into
+ * device float[1]; gradient of the loss into `grad` (device float[P],
+ * nullable); if `adam` (device float[2][P]: first then second moments) is
+ * non-NULL, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
+ * with `step` >= 1) updates `params` in place. */
+gs_status gs_mlp_train_step(float *params, float *adam, int64_t step, float lr, const float *features,
+                            const float *norm, const float *targets, int64_t n, float *loss, float *grad,
+                            void *stream);
+
 /* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum). */
 void gs_default_params(gs_params *params);
 

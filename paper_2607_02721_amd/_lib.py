@@ -19,7 +19,8 @@ GS_OK = 0
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory",
                 4: "no positive sensitivity", 5: "invalid data", 6: "device error"}
 EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_default_params",
-            "gs_release_workspace", "gs_last_error", "gs_status_string"]
+            "gs_release_workspace", "gs_last_error", "gs_status_string", "gs_mlp_param_count",
+            "gs_mlp_init", "gs_features", "gs_feature_stats", "gs_mlp_forward", "gs_mlp_train_step"]
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 FLAG_COUNT_PAIRS = 1
@@ -90,6 +91,16 @@ def load(path: str = LIB_PATH):
         lib.gs_last_error.restype = C.c_char_p
         lib.gs_status_string.argtypes = [C.c_int]
         lib.gs_status_string.restype = C.c_char_p
+        lib.gs_mlp_param_count.argtypes = []
+        lib.gs_mlp_param_count.restype = C.c_int64
+        lib.gs_mlp_init.argtypes = [P, C.c_uint64, P]
+        lib.gs_features.argtypes = [P, P, P]
+        lib.gs_feature_stats.argtypes = [P, C.c_int64, P, P]
+        lib.gs_mlp_forward.argtypes = [P, P, P, C.c_int64, P, P]
+        lib.gs_mlp_train_step.argtypes = [P, P, C.c_int64, C.c_float, P, P, P, C.c_int64, P, P, P]
+        for f in (lib.gs_mlp_init, lib.gs_features, lib.gs_feature_stats, lib.gs_mlp_forward,
+                  lib.gs_mlp_train_step):
+            f.restype = C.c_int
         _lib = lib
     return _lib
 

@@ -48,6 +48,20 @@ struct Arena {
 };
 constexpr int kMaxDevices = 16;
 Arena g_work[kMaxDevices], g_lists[kMaxDevices];
+// Recorded at the end of every call on the call's stream; the next call waits
+// for it on its own stream, so the shared arenas are never used by two
+// streams at once.
+hipEvent_t g_done[kMaxDevices];
+
+hipError_t order_after_previous(int dev, hipStream_t st) {
+    if (!g_done[dev]) {
+        hipError_t e = hipEventCreateWithFlags(&g_done[dev], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        return hipSuccess;
+    }
+    return hipStreamWaitEvent(st, g_done[dev], 0);
+}
+hipError_t mark_done(int dev, hipStream_t st) { return hipEventRecord(g_done[dev], st); }
 
 hipError_t arena_reserve(Arena &a, size_t bytes) {
     if (a.base && a.cap >= bytes) return hipSuccess;
@@ -356,6 +370,14 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     return GS_OK;
 }
 
+struct DoneGuard {
+    int dev;
+    hipStream_t st;
+    ~DoneGuard() {
+        if (dev >= 0) (void)mark_done(dev, st);
+    }
+};
+
 int current_device(gs_status *st) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
@@ -425,6 +447,8 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     const int dev = current_device(&s);
     if (dev < 0) return s;
     hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(order_after_previous(dev, st));
+    DoneGuard done_guard{dev, st};
     S.N = scene->n;
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
@@ -512,6 +536,8 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
     const int dev = current_device(&s);
     if (dev < 0) return s;
     hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(order_after_previous(dev, st));
+    DoneGuard done_guard{dev, st};
     S.N = scene->n;
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
@@ -574,6 +600,8 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
     const int dev = current_device(&s);
     if (dev < 0) return s;
     hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(order_after_previous(dev, st));
+    DoneGuard done_guard{dev, st};
     const size_t need = 2 * sizeof(uint64_t) * (size_t)n + sizeof(uint64_t) * (scan_tmp_elems(n) + 2) + 1024;
     HIP_TRY(arena_reserve(g_work[dev], need));
     Carve cv(g_work[dev].base);
@@ -592,6 +620,107 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
     if (Q == 0) return fail(GS_ERR_NO_POSITIVE_SENSITIVITY, "every sensitivity is 0");
     launch_draws(C, n, m, seed, counts, st);
     launch_weights(counts, q, C, n, m, weights, support, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned proposal.
+constexpr int64_t kMlpRows = 65536;
+
+int64_t gs_mlp_param_count(void) { return kMlpParams; }
+
+static gs_status begin_call(int *dev_out, hipStream_t st) {
+    gs_status s;
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    HIP_TRY(order_after_previous(dev, st));
+    *dev_out = dev;
+    return GS_OK;
+}
+
+gs_status gs_mlp_init(float *params, uint64_t seed, void *stream) {
+    g_last_error.clear();
+    if (!params) return fail(GS_ERR_INVALID_ARGUMENT, "params is NULL");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    mlp_init(params, seed, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status gs_features(const gs_scene *scene, float *features, void *stream) {
+    g_last_error.clear();
+    gs_status s;
+    if ((s = check_scene(scene)) != GS_OK) return s;
+    if (!features) return fail(GS_ERR_INVALID_ARGUMENT, "features is NULL");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    if ((s = begin_call(&dev, st)) != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    HIP_TRY(arena_reserve(g_work[dev], knn_scratch_bytes(scene->n)));
+    SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
+                scene->quat, scene->opacity, scene->sh};
+    HIP_TRY(knn_features(sd, features, g_work[dev].base, st));
+    return GS_OK;
+}
+
+gs_status gs_feature_stats(const float *features, int64_t n, float *norm, void *stream) {
+    g_last_error.clear();
+    if (!features || !norm) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    feature_stats(features, n, norm, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status gs_mlp_forward(const float *params, const float *features, const float *norm, int64_t n, float *out,
+                         void *stream) {
+    g_last_error.clear();
+    if (!params || !features || !norm || !out) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    const int64_t rows = std::min<int64_t>(kMlpRows, (n + 63) / 64 * 64);
+    HIP_TRY(arena_reserve(g_work[dev], mlp_scratch_bytes(rows)));
+    mlp_forward(params, features, norm, n, out, g_work[dev].base, rows, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status gs_mlp_train_step(float *params, float *adam, int64_t step, float lr, const float *features,
+                            const float *norm, const float *targets, int64_t n, float *loss, float *grad,
+                            void *stream) {
+    g_last_error.clear();
+    if (!params || !features || !norm || !targets || !loss)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1 || n > kMlpRows) return fail(GS_ERR_INVALID_ARGUMENT, "batch rows must be in 1..65536");
+    if (adam && step < 1) return fail(GS_ERR_INVALID_ARGUMENT, "step must be >= 1");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(GS_ERR_INVALID_ARGUMENT, "lr must be >= 0");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    const int64_t rows = (n + 63) / 64 * 64;
+    HIP_TRY(arena_reserve(g_work[dev], mlp_scratch_bytes(rows)));
+    mlp_train_step(params, adam, step, lr, features, norm, targets, n, loss, grad, g_work[dev].base, rows, st);
     HIP_TRY(hipGetLastError());
     return GS_OK;
 }

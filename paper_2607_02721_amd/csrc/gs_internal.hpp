@@ -16,6 +16,11 @@ constexpr int kBinPositions = 2048; // binning: depth-sorted positions per block
 constexpr uint32_t kInvisibleKey = 0xFFFFFFFFu;
 constexpr uint32_t kIndexMask = 0x0FFFFFFFu; // list entry = gaussian | quadrant mask << 28
 
+// MLP proposal: 64 -> 256 -> 256 -> 256 -> 1; offsets into the FP32 parameter vector.
+constexpr int kMlpIn = 64, kMlpH = 256;
+constexpr int64_t kOffW1 = 0, kOffB1 = 16384, kOffW2 = 16640, kOffB2 = 82176, kOffW3 = 82432, kOffB3 = 147968,
+                  kOffW4 = 148224, kOffB4 = 148480, kMlpParams = 148481;
+
 // One camera of the current chunk, as the kernels see it.
 struct ViewDev {
     double R[9];     // world-to-camera rotation, row-major
@@ -114,6 +119,18 @@ void launch_quantize(const float *sens, int64_t n, uint64_t *q, hipStream_t st);
 void launch_draws(const uint64_t *C, int64_t n, int64_t m, uint64_t seed, uint32_t *counts, hipStream_t st);
 void launch_weights(const uint32_t *counts, const uint64_t *q, const uint64_t *C, int64_t n, int64_t m,
                     double *weights, int64_t *support, hipStream_t st);
+
+// MLP proposal and features
+size_t mlp_scratch_bytes(int64_t rows);
+void mlp_init(float *params, uint64_t seed, hipStream_t st);
+void mlp_forward(const float *P, const float *feat, const float *norm, int64_t n, float *y, void *scratch,
+                 int64_t rows, hipStream_t st);
+void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *feat, const float *norm,
+                    const float *y, int64_t n, float *loss, float *grad_out, void *scratch, int64_t rows,
+                    hipStream_t st);
+size_t knn_scratch_bytes(int64_t n);
+hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStream_t st);
+void feature_stats(const float *feat, int64_t n, float *norm, hipStream_t st);
 
 // Small utilities
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);

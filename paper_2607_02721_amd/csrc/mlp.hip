@@ -1,0 +1,398 @@
+// Learned sampling proposal: an MLP 64 -> 256 -> 256 -> 256 -> 1 with SiLU
+// that predicts log-sensitivity from per-Gaussian features.  The products run
+// on the BF16 matrix cores of gfx950 (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation); activations are kept in BF16 between layers and in FP32
+// (pre-activation) for the backward pass; parameters and Adam moments are
+// FP32.
+//
+// Parameter vector (FP32, PyTorch Linear layout [out][in]):
+//   W1[256][64] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] w4[256] b4
+#include "gs_internal.hpp"
+
+#include <math.h>
+
+namespace gs {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// C[M][N] = A[M][K] * B[N][K]^T (row-major bf16, K contiguous), FP32 accumulate.
+// Block = 4 waves computing a 64x64 tile (each wave 32x32 = 2x2 MFMA tiles of
+// 16x16, K in steps of 32).  Fragment layout of v_mfma_f32_16x16x32_bf16:
+// lane l holds row (l % 16) of A and column (l % 16) of B^T for the 8
+// consecutive k at 8 (l / 16); the 16x16 result gives lane l the 4 rows
+// 4 (l / 16) + r of column l % 16.
+// Epilogues: 0 = store FP32 C; 1 = Z = C + bias -> store Z (FP32) and
+// SiLU(Z) (BF16); 2 = store only SiLU(C + bias) (BF16).
+// Requires M, N multiples of 64 and K a multiple of 32 (checked by the host).
+template <int kEpi>
+__global__ __launch_bounds__(256) void k_gemm_nt(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
+                                                 int ldb, int K, float *__restrict__ C, int ldc,
+                                                 const float *__restrict__ bias, __bf16 *__restrict__ H, int ldh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * 64 + (w & 1) * 32;
+    const int col0 = blockIdx.y * 64 + (w >> 1) * 32;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __bf16 *a0 = A + (int64_t)(row0 + fr) * lda + fk;
+    const __bf16 *a1 = A + (int64_t)(row0 + 16 + fr) * lda + fk;
+    const __bf16 *b0 = B + (int64_t)(col0 + fr) * ldb + fk;
+    const __bf16 *b1 = B + (int64_t)(col0 + 16 + fr) * ldb + fk;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 fa0 = *reinterpret_cast<const bf16x8 *>(a0 + k0);
+        const bf16x8 fa1 = *reinterpret_cast<const bf16x8 *>(a1 + k0);
+        const bf16x8 fb0 = *reinterpret_cast<const bf16x8 *>(b0 + k0);
+        const bf16x8 fb1 = *reinterpret_cast<const bf16x8 *>(b1 + k0);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + i * 16 + (lane >> 4) * 4 + r;
+                const int col = col0 + j * 16 + fr;
+                float v = acc[i][j][r];
+                if (kEpi == 0) {
+                    C[(int64_t)row * ldc + col] = v;
+                } else {
+                    v += bias[col];
+                    if (kEpi == 1) C[(int64_t)row * ldc + col] = v;
+                    H[(int64_t)row * ldh + col] = (__bf16)silu(v);
+                }
+            }
+}
+
+static void gemm_nt(int epi, const __bf16 *A, int lda, const __bf16 *B, int ldb, int M, int N, int K, float *C,
+                    int ldc, const float *bias, __bf16 *H, int ldh, hipStream_t st) {
+    dim3 grid(M / 64, N / 64);
+    if (epi == 0)
+        hipLaunchKernelGGL(k_gemm_nt<0>, grid, dim3(256), 0, st, A, lda, B, ldb, K, C, ldc, bias, H, ldh);
+    else if (epi == 1)
+        hipLaunchKernelGGL(k_gemm_nt<1>, grid, dim3(256), 0, st, A, lda, B, ldb, K, C, ldc, bias, H, ldh);
+    else
+        hipLaunchKernelGGL(k_gemm_nt<2>, grid, dim3(256), 0, st, A, lda, B, ldb, K, C, ldc, bias, H, ldh);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and small kernels.
+
+// X0[r][c] = bf16((feat[r][c] - mean[c]) * inv_std[c]); rows >= n are zero.
+__global__ void k_standardize(const float *__restrict__ feat, const float *__restrict__ norm, int64_t n,
+                              int64_t rows, __bf16 *__restrict__ X0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * kMlpIn) return;
+    const int64_t r = i / kMlpIn;
+    const int c = (int)(i % kMlpIn);
+    const float v = r < n ? (feat[i] - norm[c]) * norm[kMlpIn + c] : 0.0f;
+    X0[i] = (__bf16)v;
+}
+
+// bf16 copies of the weights: Wk[out][in] and their transposes Wk^T[in][out].
+__global__ void k_weights_bf16(const float *__restrict__ P, __bf16 *__restrict__ W1, __bf16 *__restrict__ W2,
+                               __bf16 *__restrict__ W3, __bf16 *__restrict__ W2t, __bf16 *__restrict__ W3t,
+                               __bf16 *__restrict__ W1t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMlpH * kMlpIn) {
+        const int o = i / kMlpIn, c = i % kMlpIn;
+        const __bf16 v = (__bf16)P[kOffW1 + i];
+        W1[i] = v;
+        W1t[c * kMlpH + o] = v;
+    }
+    if (i < kMlpH * kMlpH) {
+        const int o = i / kMlpH, c = i % kMlpH;
+        const __bf16 v2 = (__bf16)P[kOffW2 + i], v3 = (__bf16)P[kOffW3 + i];
+        W2[i] = v2;
+        W3[i] = v3;
+        W2t[c * kMlpH + o] = v2;
+        W3t[c * kMlpH + o] = v3;
+    }
+}
+
+// y[r] = H3[r] . w4 + b4 (w4 rounded to bf16 like the other weights), one wave per row.
+__global__ __launch_bounds__(256) void k_head(const __bf16 *__restrict__ H3, const float *__restrict__ P, int64_t n,
+                                              float *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMlpH / 64; ++k) {
+        const int c = k * 64 + lane;
+        acc += (float)H3[r * kMlpH + c] * (float)(__bf16)P[kOffW4 + c];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) y[r] = acc + P[kOffB4];
+}
+
+// Loss and head backward.  dy = 2 (yhat - y) / n; per row r < n:
+//   dZ3[r][c] = dy w4[c] silu'(Z3[r][c])  (bf16, also transposed into dZ3t)
+// grad(w4)[c] += sum_r dy H3[r][c], grad(b4) += sum_r dy, loss += (yhat - y)^2 / n.
+__global__ __launch_bounds__(256) void k_head_backward(const float *__restrict__ yhat, const float *__restrict__ y,
+                                                       int64_t n, int64_t rows, const float *__restrict__ Z3,
+                                                       const __bf16 *__restrict__ H3, const float *__restrict__ P,
+                                                       __bf16 *__restrict__ dZ3, __bf16 *__restrict__ dZ3t,
+                                                       float *__restrict__ G, float *__restrict__ loss) {
+    // one block per 64 rows; thread c handles column c of those rows
+    const int c = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const float w4 = (float)(__bf16)P[kOffW4 + c];
+    float gw = 0.0f, gb = 0.0f, ls = 0.0f;
+    for (int k = 0; k < 64; ++k) {
+        const int64_t r = r0 + k;
+        float dz = 0.0f;
+        if (r < n) {
+            const float e = yhat[r] - y[r];
+            const float dy = 2.0f * e / (float)n;
+            dz = dy * w4 * silu_grad(Z3[r * kMlpH + c]);
+            gw += dy * (float)H3[r * kMlpH + c];
+            if (c == 0) {
+                gb += dy;
+                ls += e * e / (float)n;
+            }
+        }
+        const __bf16 b = (__bf16)dz;
+        dZ3[r * kMlpH + c] = b;
+        dZ3t[(int64_t)c * rows + r] = b;
+    }
+    atomicAdd(&G[kOffW4 + c], gw);
+    if (c == 0) {
+        atomicAdd(&G[kOffB4], gb);
+        atomicAdd(loss, ls);
+    }
+}
+
+// dZ = dH * silu'(Z) for a hidden layer; writes bf16 dZ and its transpose.
+__global__ void k_act_backward(const float *__restrict__ dH, const float *__restrict__ Z, int64_t n, int64_t rows,
+                               __bf16 *__restrict__ dZ, __bf16 *__restrict__ dZt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * kMlpH) return;
+    const int64_t r = i / kMlpH;
+    const int c = (int)(i % kMlpH);
+    const float v = r < n ? dH[i] * silu_grad(Z[i]) : 0.0f;
+    const __bf16 b = (__bf16)v;
+    dZ[i] = b;
+    dZt[(int64_t)c * rows + r] = b;
+}
+
+// out[c][r] = in[r][c] for a rows x cols bf16 matrix.
+__global__ void k_transpose_bf16(const __bf16 *__restrict__ in, int64_t rows, int cols, __bf16 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * cols) return;
+    const int64_t r = i / cols;
+    const int c = (int)(i % cols);
+    out[(int64_t)c * rows + r] = in[i];
+}
+
+// grad(b)[c] += sum_r dZt[c][r]: one block per output c.
+__global__ __launch_bounds__(256) void k_bias_grad(const __bf16 *__restrict__ dZt, int64_t rows, float *__restrict__ g) {
+    __shared__ float sh[256];
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) s += (float)dZt[(int64_t)c * rows + r];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g[c] += sh[0];
+}
+
+__global__ void k_add_f32(float *__restrict__ dst, const float *__restrict__ src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] += src[i];
+}
+
+// Adam (Kingma & Ba) with bias correction; m and v follow P in `adam`.
+__global__ void k_adam(float *__restrict__ P, float *__restrict__ adam, const float *__restrict__ G, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = G[i];
+    const float m = b1 * adam[i] + (1.0f - b1) * g;
+    const float v = b2 * adam[n + i] + (1.0f - b2) * g * g;
+    adam[i] = m;
+    adam[n + i] = v;
+    P[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// Deterministic initialisation: uniform(-a, a) with a = sqrt(6 / (fan_in + fan_out))
+// for weights (Philox of (index, layer) with the given seed), zero biases.
+__device__ __forceinline__ uint32_t mix32(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return (uint32_t)x;
+}
+__global__ void k_mlp_init(float *__restrict__ P, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kMlpParams) return;
+    float fan_in = 0, fan_out = 0;
+    bool weight = true;
+    if (i < kOffB1) { fan_in = kMlpIn; fan_out = kMlpH; }
+    else if (i < kOffW2) weight = false;
+    else if (i < kOffB2) { fan_in = kMlpH; fan_out = kMlpH; }
+    else if (i < kOffW3) weight = false;
+    else if (i < kOffB3) { fan_in = kMlpH; fan_out = kMlpH; }
+    else if (i < kOffW4) weight = false;
+    else if (i < kOffB4) { fan_in = kMlpH; fan_out = 1; }
+    else weight = false;
+    if (!weight) {
+        P[i] = 0.0f;
+        return;
+    }
+    const float a = sqrtf(6.0f / (fan_in + fan_out));
+    const float u = (float)(mix32(seed * 0x9E3779B97F4A7C15ull + (uint64_t)i) >> 8) * (1.0f / 16777216.0f);
+    P[i] = (2.0f * u - 1.0f) * a;
+}
+
+// ---------------------------------------------------------------------------
+size_t mlp_scratch_bytes(int64_t rows) {
+    const size_t h = (size_t)rows * kMlpH;
+    size_t b = 0;
+    b += 2 * (size_t)kMlpH * kMlpIn * 2 + 4 * (size_t)kMlpH * kMlpH * 2;  // bf16 weights and transposes
+    b += (size_t)rows * kMlpIn * 2 * 2;                                   // X0, X0t
+    b += 3 * h * 4;                                                       // Z1..Z3
+    b += 4 * h * 2;                                                       // H1..H3, transposed H
+    b += (size_t)rows * 4;                                                // yhat
+    b += 2 * h * 2 + h * 4;                                               // dZ, dZt, dH
+    b += (size_t)kMlpParams * 4;                                          // gradient buffer
+    b += (size_t)kMlpH * kMlpH * 4;                                       // weight-gradient temp
+    return b + 64 * 256;
+}
+
+struct MlpBufs {
+    __bf16 *W1, *W1t, *W2, *W3, *W2t, *W3t, *X0, *X0t, *H1, *H2, *H3, *Ht, *dZ, *dZt;
+    float *Z1, *Z2, *Z3, *yhat, *dH, *G, *Gtmp;
+};
+
+static MlpBufs carve_mlp(void *base, int64_t rows) {
+    char *p = (char *)base;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        void *r = p + off;
+        off += bytes;
+        return r;
+    };
+    const size_t h = (size_t)rows * kMlpH;
+    MlpBufs m;
+    m.W1 = (__bf16 *)take((size_t)kMlpH * kMlpIn * 2);
+    m.W1t = (__bf16 *)take((size_t)kMlpH * kMlpIn * 2);
+    m.W2 = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
+    m.W3 = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
+    m.W2t = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
+    m.W3t = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
+    m.X0 = (__bf16 *)take((size_t)rows * kMlpIn * 2);
+    m.X0t = (__bf16 *)take((size_t)rows * kMlpIn * 2);
+    m.Z1 = (float *)take(h * 4);
+    m.Z2 = (float *)take(h * 4);
+    m.Z3 = (float *)take(h * 4);
+    m.H1 = (__bf16 *)take(h * 2);
+    m.H2 = (__bf16 *)take(h * 2);
+    m.H3 = (__bf16 *)take(h * 2);
+    m.Ht = (__bf16 *)take(h * 2);
+    m.yhat = (float *)take((size_t)rows * 4);
+    m.dZ = (__bf16 *)take(h * 2);
+    m.dZt = (__bf16 *)take(h * 2);
+    m.dH = (float *)take(h * 4);
+    m.G = (float *)take((size_t)kMlpParams * 4);
+    m.Gtmp = (float *)take((size_t)kMlpH * kMlpH * 4);
+    return m;
+}
+
+static inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+static void mlp_forward_rows(const float *P, const MlpBufs &m, int64_t rows, bool keep_z, hipStream_t st) {
+    const int H = kMlpH;
+    if (keep_z) {
+        gemm_nt(1, m.X0, kMlpIn, m.W1, kMlpIn, rows, H, kMlpIn, m.Z1, H, P + kOffB1, m.H1, H, st);
+        gemm_nt(1, m.H1, H, m.W2, H, rows, H, H, m.Z2, H, P + kOffB2, m.H2, H, st);
+        gemm_nt(1, m.H2, H, m.W3, H, rows, H, H, m.Z3, H, P + kOffB3, m.H3, H, st);
+    } else {
+        gemm_nt(2, m.X0, kMlpIn, m.W1, kMlpIn, rows, H, kMlpIn, nullptr, H, P + kOffB1, m.H1, H, st);
+        gemm_nt(2, m.H1, H, m.W2, H, rows, H, H, nullptr, H, P + kOffB2, m.H2, H, st);
+        gemm_nt(2, m.H2, H, m.W3, H, rows, H, H, nullptr, H, P + kOffB3, m.H3, H, st);
+    }
+}
+
+void mlp_init(float *params, uint64_t seed, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_init, dim3(blocks_for(kMlpParams)), dim3(256), 0, st, params, seed);
+}
+
+// Predictions for n rows of raw features, in batches of `rows` (multiple of 64).
+void mlp_forward(const float *P, const float *feat, const float *norm, int64_t n, float *y, void *scratch,
+                 int64_t rows, hipStream_t st) {
+    const MlpBufs m = carve_mlp(scratch, rows);
+    hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3, m.W2t,
+                       m.W3t, m.W1t);
+    for (int64_t r0 = 0; r0 < n; r0 += rows) {
+        const int64_t nb = n - r0 < rows ? n - r0 : rows;
+        const int64_t padded = (nb + 63) / 64 * 64;
+        hipLaunchKernelGGL(k_standardize, dim3(blocks_for(padded * kMlpIn)), dim3(256), 0, st,
+                           feat + r0 * kMlpIn, norm, nb, padded, m.X0);
+        mlp_forward_rows(P, m, padded, false, st);
+        hipLaunchKernelGGL(k_head, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, m.H3, P, nb, y + r0);
+    }
+}
+
+// Loss and gradient on one batch of n <= rows rows; if adam != nullptr also
+// applies one Adam step (step >= 1).  grad_out (optional) receives the gradient.
+void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *feat, const float *norm,
+                    const float *y, int64_t n, float *loss, float *grad_out, void *scratch, int64_t rows,
+                    hipStream_t st) {
+    const MlpBufs m = carve_mlp(scratch, rows);
+    const int H = kMlpH;
+    const int64_t R = (n + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3, m.W2t,
+                       m.W3t, m.W1t);
+    hipLaunchKernelGGL(k_standardize, dim3(blocks_for(R * kMlpIn)), dim3(256), 0, st, feat, norm, n, R, m.X0);
+    mlp_forward_rows(P, m, R, true, st);
+    hipLaunchKernelGGL(k_head, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, m.H3, P, R, m.yhat);
+    launch_fill_u32((uint32_t *)m.G, 0u, kMlpParams, st);
+    launch_fill_u32((uint32_t *)loss, 0u, 1, st);
+    hipLaunchKernelGGL(k_head_backward, dim3((unsigned)(R / 64)), dim3(256), 0, st, m.yhat, y, n, R, m.Z3, m.H3, P,
+                       m.dZ, m.dZt, m.G, loss);
+    // layer 3: grad W3 = dZ3^T H2, grad b3, dH2 = dZ3 W3
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H2, R, H, m.Ht);
+    gemm_nt(0, m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.G + kOffW3, H, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB3);
+    gemm_nt(0, m.dZ, H, m.W3t, H, R, H, H, m.dH, H, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_act_backward, dim3(blocks_for(R * H)), dim3(256), 0, st, m.dH, m.Z2, n, R, m.dZ, m.dZt);
+    // layer 2
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H1, R, H, m.Ht);
+    gemm_nt(0, m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.G + kOffW2, H, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB2);
+    gemm_nt(0, m.dZ, H, m.W2t, H, R, H, H, m.dH, H, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_act_backward, dim3(blocks_for(R * H)), dim3(256), 0, st, m.dH, m.Z1, n, R, m.dZ, m.dZt);
+    // layer 1: grad W1 = dZ1^T X0
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(R * kMlpIn)), dim3(256), 0, st, m.X0, R, kMlpIn, m.X0t);
+    gemm_nt(0, m.dZt, (int)R, m.X0t, (int)R, H, kMlpIn, (int)R, m.G + kOffW1, kMlpIn, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB1);
+    if (grad_out) hipMemcpyAsync(grad_out, m.G, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, st);
+    if (adam) {
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(kMlpParams)), dim3(256), 0, st, P, adam, m.G, (int64_t)kMlpParams,
+                           lr, b1, b2, eps, c1, c2);
+    }
+}
+
+}  // namespace gs

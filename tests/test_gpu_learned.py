@@ -1,0 +1,173 @@
+"""Learned proposal on the GPU: MFMA MLP forward/gradient against the FP64
+reference (same bf16-rounded weights and inputs), kNN features against a
+k-d tree, training, the gain over uniform sampling, and the fallback."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_02721_amd as gs
+    gs.load()
+    return gs
+
+
+@pytest.fixture(scope="module")
+def L(gs):
+    from paper_2607_02721_amd import learned
+    return learned
+
+
+def _bf16(t):
+    import torch
+    return t.to(torch.bfloat16).to(torch.float32)
+
+
+def _ref_inputs(prop, feat):
+    """Parameters and standardised inputs exactly as the BF16 kernels see them."""
+    import torch
+    from oracle import mlp_ref  # noqa: F401
+    P = prop.params.detach().clone()
+    for a, b in ((0, 16384), (16640, 82176), (82432, 147968), (148224, 148480)):
+        P[a:b] = _bf16(P[a:b])
+    X = _bf16((feat - prop.norm[0]) * prop.norm[1])
+    return P.double().cpu().numpy(), X.double().cpu().numpy()
+
+
+def _random_batch(n, seed=0):
+    import torch
+    g = torch.Generator().manual_seed(seed)
+    feat = (torch.randn(n, 64, generator=g) * 2 + 0.5).cuda()
+    y = torch.randn(n, generator=g).cuda() * 3 - 5
+    return feat, y
+
+
+def test_forward_matches_reference(gs, L):
+    from oracle import mlp_ref
+    feat, _ = _random_batch(1000)
+    prop = L.Proposal(seed=3)
+    prop.set_norm(L.feature_stats(feat))
+    got = prop.predict(feat).double().cpu().numpy()
+    P, X = _ref_inputs(prop, feat)
+    want = mlp_ref.forward(P, X)[0]
+    err = np.abs(got - want)
+    print(f"[mlp fwd] max abs {err.max():.3e} (output std {want.std():.3e})")
+    assert err.max() <= 2e-2 * max(want.std(), 1e-3) + 1e-3
+
+
+def test_gradient_matches_reference(gs, L):
+    from oracle import mlp_ref
+    feat, y = _random_batch(4096, seed=1)
+    prop = L.Proposal(seed=5)
+    prop.set_norm(L.feature_stats(feat))
+    loss, grad = prop.gradient(feat, y)
+    P, X = _ref_inputs(prop, feat)
+    l_ref, g_ref = mlp_ref.loss_and_grad(P, X, y.double().cpu().numpy())
+    g = grad.double().cpu().numpy()
+    cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
+    rel = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+    print(f"[mlp grad] loss {float(loss.item()):.6f} vs {l_ref:.6f}; cos {cos:.6f} rel-L2 {rel:.3e}")
+    assert abs(float(loss.item()) - l_ref) <= 1e-3 * l_ref
+    assert cos >= 0.999 and rel <= 1e-2
+    # per-block checks: every layer's gradient agrees, not only the total
+    for a, b in ((0, 16384), (16640, 82176), (82432, 147968), (148224, 148480)):
+        r = np.linalg.norm(g[a:b] - g_ref[a:b]) / np.linalg.norm(g_ref[a:b])
+        assert r <= 2e-2, (a, b, r)
+
+
+def test_knn_features_match_kdtree(gs, L):
+    from scipy.spatial import cKDTree
+    sc = synth.make_cluster_scene(20_000, 11, 3)
+    f = L.features(gs.DeviceScene.from_scene(sc)).cpu().numpy().astype(np.float64)
+    pts = sc.mean.T.astype(np.float64)
+    d, idx = cKDTree(pts).query(pts, k=17)
+    d, idx = d[:, 1:], idx[:, 1:]
+    al = sc.opacity.astype(np.float64)
+    mean_d = d.mean(1)
+    d16 = d[:, -1]
+    na = al[idx]
+    dens = na.sum(1) / (4.0 / 3.0 * np.pi * d16 ** 3)
+    assert np.allclose(f[:, 0:3], pts, atol=0)
+    assert np.allclose(f[:, 59], np.log(mean_d), atol=1e-4)
+    assert np.allclose(f[:, 60], np.log(d16), atol=1e-4)
+    ok = np.abs(f[:, 61] - na.mean(1)) < 1e-5
+    assert ok.mean() > 0.999            # neighbour sets agree except for float32 near-ties
+    assert np.allclose(f[:, 63], np.log(dens), atol=1e-3)
+    sh = sc.sh.reshape(-1, sc.n).T
+    assert np.array_equal(f[:, 11:59], sh.astype(np.float64))
+
+
+def _train_scenes(n_scenes=3, n=60_000, views=20):
+    out = []
+    for k in range(n_scenes):
+        sc = synth.make_cluster_scene(n, 500 + k, 3)
+        vw = synth.make_orbit_views(views, 600 + k, 320, 180)
+        out.append((sc, vw))
+    return out
+
+
+@pytest.fixture(scope="module")
+def trained(gs, L):
+    import torch
+    feats, targets = [], []
+    for sc, vw in _train_scenes():
+        d = gs.DeviceScene.from_scene(sc)
+        s, _ = gs.sensitivity(d, vw)
+        feats.append(L.features(d))
+        targets.append(L.log_targets(s))
+    prop = L.Proposal(seed=0)
+    losses = prop.fit(feats, targets, epochs=12, batch=8192, lr=2e-3)
+    torch.cuda.synchronize()
+    return prop, losses
+
+
+def test_training_reduces_loss(trained):
+    prop, losses = trained
+    print("[train] losses", [round(x, 3) for x in losses])
+    assert losses[-1] < 0.6 * losses[0]
+
+
+def test_learned_proposal_beats_uniform(gs, L, trained):
+    """Held-out scene, equal m: the MLP mixture has a smaller coreset-objective
+    error than uniform sampling (averaged over seeds)."""
+    import torch
+    prop, _ = trained
+    sc = synth.make_cluster_scene(60_000, 777, 3)
+    vw = synth.make_orbit_views(20, 778, 320, 180)
+    d = gs.DeviceScene.from_scene(sc)
+    feat = L.features(d)
+    scores = L.mixture(prop.predict(feat))
+    uni = torch.ones(sc.n, device="cuda")
+    s_exact, _ = gs.sensitivity(d, vw)
+    m = sc.n // 10
+    errs = {"learned": [], "uniform": [], "exact": []}
+    for seed in range(4):
+        for name, sc_ in (("learned", scores), ("uniform", uni), ("exact", s_exact)):
+            _, w, _ = gs.sample_coreset(sc_, m, seed)
+            ob = gs.render_objective(d, vw, w, gs.OBJ_FIXED, per_ray=False, diag=False)
+            errs[name].append(gs.coreset_error(ob["per_view"]))
+    mean = {k: float(np.mean(v)) for k, v in errs.items()}
+    print("[gain] mean E", mean)
+    assert mean["learned"] < mean["uniform"]
+
+
+def test_fallback_runs_exact_pass(gs, L, trained):
+    prop, _ = trained
+    sc = synth.make_cluster_scene(30_000, 901, 3)
+    vw = synth.make_orbit_views(8, 902, 160, 96)
+    d = gs.DeviceScene.from_scene(sc)
+    mask = None
+    out = L.sample_with_fallback(d, vw, sc.n // 10, 1, prop, mask, err_bound=0.0)
+    assert out["fallback"] and "E_exact" in out
+    s, _ = gs.sensitivity(d, vw)
+    _, w_exact, _ = gs.sample_coreset(s, sc.n // 10, 1)
+    assert np.array_equal(out["weights"].cpu().numpy(), w_exact.cpu().numpy())
+    out2 = L.sample_with_fallback(d, vw, sc.n // 10, 1, prop, mask, err_bound=1e9)
+    assert not out2["fallback"]
