@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--views", type=int, default=100)
+    ap.add_argument("--train-scenes", type=int, default=8)
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -120,14 +122,76 @@ def main():
     log(f"mixed16: {ms16:.2f} ms/step  stages {json.dumps({k: round(v, 3) for k, v in stage16.items()})}")
 
     # coreset-objective error E (max over views of |sum A^th_w - sum A| / sum A)
-    # on a 1% ray subsample, for the weights each variant drew, judged on the
-    # float32 scene
-    sub = torch.as_tensor(synth.ray_subsample_mask(views, 1).view(np.int32)).cuda()
+    # on a 1% ray subsample (whole 8x8 pixel blocks, so the judge costs ~1% of
+    # a pass), for the weights each variant drew, judged on the float32 scene
+    sub = torch.as_tensor(synth.block_subsample_mask(views, 1).view(np.int32)).cuda()
     errs = {}
     for name, w_ in (("exact", w), ("mixed16", w16)):
         ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
         errs[name] = gs.coreset_error(ob["per_view"])
     log(f"E: {errs}")
+
+    learned = None
+    if not args.no_learned:
+        from paper_2607_02721_amd import learned as L
+        # training data: exact sensitivities of other scenes from the same generator
+        log(f"training the proposal on {args.train_scenes} scenes (untimed) ...")
+        t_tr = time.perf_counter()
+        feats, targets = [], []
+        for k in range(args.train_scenes):
+            tsc = synth.make_cluster_scene(1_000_000, 4000 + k, 3)
+            tvw = synth.make_orbit_views(args.views, 4100 + k)
+            td = gs.DeviceScene.from_scene(tsc)
+            ts, _ = gs.sensitivity(td, tvw)
+            feats.append(L.features(td))
+            targets.append(L.log_targets(ts))
+            del td
+        prop = L.Proposal(seed=0)
+        losses = prop.fit(feats, targets, epochs=8, batch=16384, lr=2e-3,
+                          log=lambda m_: log("  " + m_))
+        del feats, targets
+        torch.cuda.synchronize()
+        t_tr = time.perf_counter() - t_tr
+
+        def learned_step():
+            feat = L.features(dsc)
+            scores = L.mixture(prop.predict(feat))
+            _, wl, _ = gs.sample_coreset(scores, m, seed)
+            return scores, wl
+
+        for _ in range(args.warmup):
+            learned_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            scores, wl = learned_step()
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        ob = gs.render_objective(dsc, views, wl, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
+        errs["learned"] = gs.coreset_error(ob["per_view"])
+        torch.cuda.synchronize()
+        ms_judge = (time.perf_counter() - t0) * 1e3
+        learned = {"ms": ms_l, "coreset_err": errs["learned"], "ms_judge": ms_judge,
+                   "fallback": errs["learned"] > 0.01,
+                   "ms_with_fallback": ms_l + ms_judge + (ms if errs["learned"] > 0.01 else 0.0),
+                   "train": {"scenes": args.train_scenes, "gaussians": args.train_scenes * 1_000_000,
+                             "epochs": len(losses), "final_loss": losses[-1], "seconds": t_tr}}
+        log(f"learned: {ms_l:.2f} ms/step, judge {ms_judge:.1f} ms, E {errs['learned']:.4f}")
+        scores_learned = scores
+
+    # E against m for each proposal (same judge rays)
+    scan = {}
+    props = {"exact": s, "mixed16": s16, "uniform": torch.ones_like(s)}
+    if learned is not None:
+        props["learned"] = scores_learned
+    for name, sc_ in props.items():
+        scan[name] = {}
+        for mm in (100_000, 200_000, 400_000, 800_000):
+            _, w_, _ = gs.sample_coreset(sc_, mm, seed)
+            ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
+            scan[name][str(mm)] = gs.coreset_error(ob["per_view"])
+    log(f"E vs m: {json.dumps(scan)}")
 
     log("counting pairs (untimed) ...")
     _, cst, _ = step(stats=True, count_pairs=True)
@@ -155,8 +219,10 @@ def main():
         "stages_ms": stage,
         "variants": {"exact_f32": {"ms": ms, "coreset_err": errs["exact"]},
                      "mixed16": {"ms": ms16, "coreset_err": errs["mixed16"], "stages_ms": stage16,
-                                 "attribute_bytes": d16.attribute_bytes()}},
-        "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on a 1% ray subsample, m=100000",
+                                 "attribute_bytes": d16.attribute_bytes()},
+                     "learned": learned},
+        "coreset_err_vs_m": scan,
+        "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on 1% of the 8x8 pixel blocks, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],
                   "entries": cst["n_entries"], "projected": cst["n_projected"]},
         "live_pairs_per_s": live / (ms * 1e-3),

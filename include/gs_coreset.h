@@ -156,7 +156,10 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
  *   A, A^th_w and A_w (the last two 0 when weights is NULL).
  * diag (nullable, host): validity violations and the log-transmittance gap
  *   (Definition 2, Assumption 1); the call synchronises the stream when set.
- * No share-floor stop is applied here. */
+ * For GS_OBJ_FULL and GS_OBJ_FIXED a ray stops once T c_max w_max < 1e-9 A
+ * (no later term can move A or A^th_w by more than 1e-9 A), so the A_w
+ * column of per_view and the diagnostics are complete only for GS_OBJ_TRUE,
+ * which walks every ray to its end. */
 gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, const gs_params *params,
                               const double *weights, int32_t objective, float *per_ray,
                               double *per_view, gs_render_diag *diag, void *stream);

@@ -132,9 +132,10 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint64_t) * CNT_SLOTS);
     add(sizeof(ViewDev) * c.vc);
     add(sizeof(int32_t) * c.total_tiles);
+    add(c.total_tiles);                                     // tile activity
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
     add(sizeof(double) * 3 * 4 * (size_t)c.total_tiles);   // objective partials
-    add(sizeof(double) * 3 * (size_t)c.vc);
+    add(sizeof(double) * (3 * (size_t)c.vc + 1));
     return b + (64 << 10);  // slack for the per-buffer alignment
 }
 
@@ -295,9 +296,10 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.counters = cv.take<uint64_t>(CNT_SLOTS);
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
+    b.tile_active = p->ray_mask ? cv.take<uint8_t>(c.total_tiles) : nullptr;
     r.sum_tmp = cv.take<double>((N + 4095) / 4096 + 2);
     r.tile_sums = cv.take<double>(3 * 4 * (size_t)c.total_tiles);
-    r.view_sums = cv.take<double>(3 * (size_t)c.vc);
+    r.view_sums = cv.take<double>(3 * (size_t)c.vc + 1);
 
     hv.assign(c.vc, ViewDev{});
     htv.assign(c.total_tiles, 0);
@@ -341,6 +343,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     uint32_t *skeys = nullptr;
     HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, &skeys, &r.sorted_g, st));
     tm.mark(2, st);
+    if (b.tile_active) launch_tile_active(r.views_dev, r.tile_view, c.total_tiles, p->ray_mask, b.tile_active, st);
     // after 4 radix passes the sorted pairs are back in (key0, val0); key1/val1 are free
     uint32_t *xr = b.key1, *yr = b.val1;
     launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
@@ -562,7 +565,20 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
         a.share_floor = 0.0f;
         a.ray_mask = params->ray_mask;
         a.query_mode = params->query_mode;
-        ObjectiveArgs o{weights, objective, per_ray, r.tile_sums};
+        ObjectiveArgs o{weights, objective, per_ray, r.tile_sums, nullptr, 1e-9f};
+        if (objective != GS_OBJ_TRUE) {
+            // w_max (1 without weights) bounds every later fixed-objective term
+            uint64_t *wmax = (uint64_t *)(r.view_sums + 3 * (size_t)c.vc);
+            if (weights) {
+                launch_max_f64(weights, S.N, wmax, st);
+            } else {
+                const double one = 1.0;
+                uint64_t bits;
+                memcpy(&bits, &one, sizeof bits);
+                launch_fill_u64(wmax, bits, 1, st);
+            }
+            o.wmax_bits = wmax;
+        }
         launch_fill_u64((uint64_t *)r.tile_sums, 0ull, 3 * 4 * (int64_t)c.total_tiles, st);
         launch_objective(a, o, r.b, st);
         HIP_TRY(hipGetLastError());

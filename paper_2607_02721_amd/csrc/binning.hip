@@ -49,10 +49,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
                                                      const uint32_t *__restrict__ yr_in,
                                                      uint32_t *__restrict__ bin_count,
                                                      const uint64_t *__restrict__ bin_off,
-                                                     uint32_t *__restrict__ lists) {
+                                                     uint32_t *__restrict__ lists,
+                                                     const uint8_t *__restrict__ active) {
     extern __shared__ uint32_t lds[];
     uint32_t *cnt = lds;                              // [tiles]
     uint32_t *base = lds + kMaxTilesPerView;          // [tiles] (scatter only)
+    // Bit 31 of cnt[t] marks a tile without any selected ray (no entries);
+    // the counts themselves stay below 2^31.
+    constexpr uint32_t kOff = 0x80000000u;
     const int v = blockIdx.y;
     const ViewDev &V = views[v];
     const int64_t nv = nvis[v];
@@ -61,20 +65,25 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
     const int64_t hi = min(lo + (int64_t)kBinPositions, nv);
     const int chunk = (int)(lo >> kSegBits);
     const int ntiles = V.tiles_x * V.tiles_y;
-    for (int t = threadIdx.x; t < ntiles; t += kBinThreads) cnt[t] = 0;
+    for (int t = threadIdx.x; t < ntiles; t += kBinThreads)
+        cnt[t] = (active && !active[V.tile_base + t]) ? kOff : 0u;
     __syncthreads();
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBinThreads) {
         int xl, xh, yl, yh;
         unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
         unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
         for (int ty = yl >> 4; ty <= (yh >> 4); ++ty)
-            for (int tx = xl >> 4; tx <= (xh >> 4); ++tx) atomicAdd(&cnt[ty * V.tiles_x + tx], 1u);
+            for (int tx = xl >> 4; tx <= (xh >> 4); ++tx) {
+                const int t = ty * V.tiles_x + tx;
+                if (cnt[t] & kOff) continue;
+                atomicAdd(&cnt[t], 1u);
+            }
     }
     __syncthreads();
     if (!kScatter) {
         // this block is the only writer of (tile, chunk) for every tile of the view
         for (int t = threadIdx.x; t < ntiles; t += kBinThreads)
-            bin_count[(int64_t)(V.tile_base + t) * nchunks + chunk] = cnt[t];
+            bin_count[(int64_t)(V.tile_base + t) * nchunks + chunk] = cnt[t] & ~kOff;
         return;
     }
     // Start of this block's segment of each tile, relative to the view's first
@@ -82,8 +91,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
     // below reads only LDS.
     const uint64_t vlist = bin_off[(int64_t)V.tile_base * nchunks];
     for (int t = threadIdx.x; t < ntiles; t += kBinThreads) {
-        if (cnt[t]) base[t] = (uint32_t)(bin_off[(int64_t)(V.tile_base + t) * nchunks + chunk] - vlist);
-        cnt[t] = 0;
+        const uint32_t c = cnt[t];
+        if (c & ~kOff) base[t] = (uint32_t)(bin_off[(int64_t)(V.tile_base + t) * nchunks + chunk] - vlist);
+        cnt[t] = c & kOff;
     }
     __syncthreads();
     uint32_t *vl = lists + vlist;
@@ -94,6 +104,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
         for (int ty = yl >> 4; ty <= (yh >> 4); ++ty)
             for (int tx = xl >> 4; tx <= (xh >> 4); ++tx) {
                 const int t = ty * V.tiles_x + tx;
+                if (cnt[t] & kOff) continue;
                 const uint32_t slot = atomicAdd(&cnt[t], 1u);
                 vl[base[t] + slot] = (uint32_t)p | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
             }
@@ -104,14 +115,41 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
                       const uint32_t *xr, const uint32_t *yr, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     hipLaunchKernelGGL(k_bin<false>, dim3(nb, Vc), dim3(kBinThreads), kMaxTilesPerView * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists);
+                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists, b.tile_active);
 }
 
 void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                         const uint32_t *xr, const uint32_t *yr, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     hipLaunchKernelGGL(k_bin<true>, dim3(nb, Vc), dim3(kBinThreads), 2 * kMaxTilesPerView * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists);
+                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists, b.tile_active);
+}
+
+// A tile is active when at least one of its rays is selected by the ray mask;
+// inactive tiles get empty lists.  One wave per tile, 4 rays per lane.
+__global__ __launch_bounds__(64) void k_tile_active(const ViewDev *__restrict__ views,
+                                                    const int32_t *__restrict__ tile_view,
+                                                    const uint32_t *__restrict__ mask, uint8_t *__restrict__ active) {
+    const int gt = blockIdx.x;
+    const ViewDev &V = views[tile_view[gt]];
+    const int tl = gt - V.tile_base;
+    const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
+    bool any = false;
+    for (int k = 0; k < 4; ++k) {
+        const int r = threadIdx.x * 4 + k;             // 0..255 inside the tile
+        const int px = tx * kTile + (r & 15), py = ty * kTile + (r >> 4);
+        if (px < V.W && py < V.H) {
+            const int64_t ray = V.ray_base + (int64_t)py * V.W + px;
+            any = any || ((mask[ray >> 5] >> (ray & 31)) & 1u);
+        }
+    }
+    const bool a = __any(any);
+    if (threadIdx.x == 0) active[gt] = a ? 1 : 0;
+}
+
+void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
+                        uint8_t *active, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_active, dim3(total_tiles), dim3(64), 0, st, views_dev, tile_view, mask, active);
 }
 
 // One wave per tile: sort every (tile, chunk) segment by depth position.

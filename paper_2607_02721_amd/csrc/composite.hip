@@ -301,6 +301,7 @@ void launch_composite_pass2(const CompositeArgs &a, const ChunkBufs &b, bool sta
 // |log T - log T_w| = |sum log(1 - rho_j) - log(1 - w_j rho_j)| at every
 // contributing retained pair (Assumption 1), on rays that stay valid.
 __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveArgs o,
+                                                     const uint32_t *__restrict__ cmax_bits,
                                                      const uint64_t *__restrict__ bin_off,
                                                      const uint32_t *__restrict__ lists,
                                                      const float4 *__restrict__ R0, const float4 *__restrict__ R1,
@@ -315,8 +316,18 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     float T = 1.0f, A = 0.0f, Ax = 0.0f, Tw = 1.0f, At = 0.0f, gap = 0.0f, gmax = 0.0f;
     bool bad = false;
     uint32_t n_bad = 0;
+    // Optional stop for the full and fixed objectives: every later term of
+    // A^th_w is w_i c_i rho_i T_i <= w_max c_max T, so once
+    // T c_max w_max < stop_rel A the rest changes A and A^th_w by less than
+    // stop_rel A.  (A_w has its own transmittance and gets no stop.)
+    float stop_scale = 0.0f;
+    if (o.wmax_bits) {
+        const double wm = __longlong_as_double((long long)*o.wmax_bits);
+        stop_scale = (float)wm * __uint_as_float(cmax_bits[w.v]);
+    }
+    bool done = !scored;
     for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
-        if (__all(!scored)) break;
+        if (__all(done)) break;
         const int n = has_w ? stage_slice<2>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr,
                                              o.weights)
                             : stage_slice<0>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr,
@@ -348,6 +359,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
             }
             T = fmaf(-rho, T, T);
         }
+        if (o.wmax_bits) done = done || (T * stop_scale < o.stop_rel * A);
         __syncthreads();
     }
     const bool on = scored && A > 0.0f;
@@ -376,31 +388,58 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
 }
 
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, const ChunkBufs &b, hipStream_t st) {
-    hipLaunchKernelGGL(k_objective, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, o, b.bin_off,
-                       b.lists, b.R0, b.R1, b.R2, b.counters);
+    hipLaunchKernelGGL(k_objective, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, o, b.cmax,
+                       b.bin_off, b.lists, b.R0, b.R1, b.R2, b.counters);
 }
 
-// Per-view sums of the per-wave partials, in a fixed order.
-__global__ void k_view_sums(const double *__restrict__ tile_sums, const ViewDev *__restrict__ views, int Vc,
-                            double *__restrict__ out) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= Vc) return;
+// Largest value of a non-negative double array (as bits: monotone for x >= 0).
+__global__ void k_max_f64(const double *__restrict__ x, int64_t n, unsigned long long *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = i < n ? (unsigned long long)__double_as_longlong(fmax(x[i], 0.0)) : 0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicMax(out, v);
+}
+
+void launch_max_f64(const double *x, int64_t n, uint64_t *out_bits, hipStream_t st) {
+    launch_fill_u64(out_bits, 0ull, 1, st);
+    hipLaunchKernelGGL(k_max_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n,
+                       (unsigned long long *)out_bits);
+}
+
+// Per-view sums of the per-wave partials: one block per view, each thread
+// sums a fixed strided subset, then a fixed tree; the order never depends on
+// scheduling.
+__global__ __launch_bounds__(256) void k_view_sums(const double *__restrict__ tile_sums,
+                                                   const ViewDev *__restrict__ views, int Vc,
+                                                   double *__restrict__ out) {
+    __shared__ double sh[3][256];
+    const int v = blockIdx.x;
     const ViewDev &V = views[v];
     const int64_t lo = (int64_t)V.tile_base * 4, hi = lo + (int64_t)V.tiles_x * V.tiles_y * 4;
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int64_t k = lo; k < hi; ++k) {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
         s0 += tile_sums[3 * k];
         s1 += tile_sums[3 * k + 1];
         s2 += tile_sums[3 * k + 2];
     }
-    out[3 * v] = s0;
-    out[3 * v + 1] = s1;
-    out[3 * v + 2] = s2;
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    sh[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[3 * v + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
                       hipStream_t st) {
-    hipLaunchKernelGGL(k_view_sums, dim3((Vc + 63) / 64), dim3(64), 0, st, tile_sums, views_dev, Vc, per_view_out);
+    hipLaunchKernelGGL(k_view_sums, dim3(Vc), dim3(256), 0, st, tile_sums, views_dev, Vc, per_view_out);
 }
 
 }  // namespace gs

@@ -60,6 +60,7 @@ struct ChunkBufs {
     uint32_t *bin_fill;  // scatter cursors (zeroed)
     uint32_t *lists;     // [D] entries
     float *ray_A;        // [rays in chunk] pass-1 render
+    uint8_t *tile_active; // [tiles in chunk] tiles holding a selected ray (null: all)
     uint64_t *counters;  // device statistics
 };
 
@@ -77,6 +78,8 @@ hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, u
                                uint32_t **key_out, uint32_t **val_out, hipStream_t st);
 void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
                             uint32_t *yr, hipStream_t st);
+void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
+                        uint8_t *active, hipStream_t st);
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                       const uint32_t *xr, const uint32_t *yr, hipStream_t st);
 void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
@@ -109,7 +112,10 @@ struct ObjectiveArgs {
     int objective;
     float *per_ray;             // global, nullable
     double *tile_sums;          // [total_tiles*4][3] per-wave partial sums
+    const uint64_t *wmax_bits;  // largest weight (double bits); null = no early stop
+    float stop_rel;             // stop a ray once T c_max w_max < stop_rel A
 };
+void launch_max_f64(const double *x, int64_t n, uint64_t *out_bits, hipStream_t st);
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, const ChunkBufs &b, hipStream_t st);
 void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
                       hipStream_t st);

@@ -25,7 +25,10 @@ from . import (DeviceScene, OBJ_FIXED, coreset_error, load, render_objective, sa
                sensitivity, _stream_handle)
 
 N_FEATURES = 64
-LOG_FLOOR = 1e-12
+# Targets are ln(max(s, 1e-6)): below that a Gaussian's share of the proposal
+# is negligible, and the floor keeps never-contributing Gaussians from
+# dominating the squared error.
+LOG_FLOOR = 1e-6
 
 
 def _torch():
@@ -51,7 +54,7 @@ def feature_stats(feat, stream=None):
 
 
 def log_targets(sens):
-    """ln(max(s, 1e-12)), computed by torch on device (target preparation)."""
+    """ln(max(s, 1e-6)), computed by torch on device (target preparation)."""
     torch = _torch()
     return torch.log(torch.clamp(sens, min=LOG_FLOOR)).float().contiguous()
 

@@ -7,11 +7,11 @@ compositing, no sensitivities, no sampling).
 """
 from .scenes import (Scene, Views, make_tiny_scene, make_tiny_views,
                      make_cluster_scene, make_orbit_views, make_config,
-                     look_at, ray_subsample_mask, splitmix64, SH_C0,
+                     look_at, ray_subsample_mask, block_subsample_mask, splitmix64, SH_C0,
                      pack_bits, unpack_bits, make_explicit_scene,
                      make_camera_set)
 
 __all__ = ["Scene", "Views", "make_tiny_scene", "make_tiny_views",
            "make_cluster_scene", "make_orbit_views", "make_config", "look_at",
-           "ray_subsample_mask", "splitmix64", "SH_C0", "pack_bits", "unpack_bits",
+           "ray_subsample_mask", "block_subsample_mask", "splitmix64", "SH_C0", "pack_bits", "unpack_bits",
            "make_explicit_scene", "make_camera_set"]

@@ -228,6 +228,23 @@ def ray_subsample_mask(views: Views, seed: int, modulus: int = 100) -> np.ndarra
     return pack_bits(keep)
 
 
+def block_subsample_mask(views: Views, seed: int, modulus: int = 100, block: int = 8) -> np.ndarray:
+    """Bitset over all rays keeping whole block x block pixel squares (aligned
+    to multiples of `block` in each view): square b (numbered view by view,
+    row-major) is kept when splitmix64(seed xor b) mod `modulus` == 0."""
+    keep_all = []
+    b0 = 0
+    for v in range(views.n_views):
+        W, H = int(views.size[v, 0]), int(views.size[v, 1])
+        bx, by = (W + block - 1) // block, (H + block - 1) // block
+        ids = np.arange(bx * by, dtype=np.uint64) + np.uint64(b0)
+        kb = ((splitmix64(ids ^ np.uint64(seed)) % np.uint64(modulus)) == 0).reshape(by, bx)
+        b0 += bx * by
+        ys, xs = np.mgrid[0:H, 0:W]
+        keep_all.append(kb[ys // block, xs // block].reshape(-1))
+    return pack_bits(np.concatenate(keep_all))
+
+
 def pack_bits(keep: np.ndarray) -> np.ndarray:
     """Pack a boolean ray array into little-endian uint32 words (bit r%32 of word r//32)."""
     keep = np.asarray(keep, dtype=bool)
