@@ -164,12 +164,74 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
                               const double *weights, int32_t objective, float *per_ray,
                               double *per_view, gs_render_diag *diag, void *stream);
 
+/* ---- Batched plans -------------------------------------------------------
+ * A plan runs the sensitivity pass (Algorithm 1, steps 1-3) of several
+ * scenes, each with its own views, as one sequence with no host
+ * synchronisation: list capacities are fixed when the plan is created (a
+ * counting pass over the current attributes, plus 1/64 + 1024 entries of
+ * slack per scene), every buffer is owned by the plan, and the sequence is
+ * captured into a HIP graph that later calls replay.  Scenes are packed into
+ * groups that fit the scratch budget; in each group one compositing launch
+ * per pass covers the tiles of all the group's scenes.  Each scene's output
+ * equals that of gs_sensitivity with the same params and no ray mask. */
+typedef struct gs_plan gs_plan;
+
+/* Launch shape of the compositing kernels.  persistent = 1: a fixed grid of
+ * 4096 one-wave workgroups takes 8x8 quadrants from an atomic counter;
+ * persistent = 0: one workgroup per quadrant, and xcd_remap = 1 renumbers
+ * workgroups so that consecutive quadrants of a tile row land on one XCD
+ * (shared L2).  Default {0, 1}. */
+typedef struct {
+    int32_t persistent;
+    int32_t xcd_remap;
+} gs_plan_config;
+
+typedef struct {
+    int32_t n_scenes, n_groups;
+    gs_plan_config config;
+    int32_t graph_captured;   /* 1 once the sequence runs as a HIP graph */
+    int64_t device_bytes;     /* plan-owned device memory */
+    int64_t list_capacity;    /* tile-list entries reserved over all scenes */
+} gs_plan_info;
+
+/* scenes, views: host arrays of n_scenes (the attribute arrays they point to
+ * are device memory and must stay valid, at the same addresses, for the
+ * plan's life; their values may change between runs).  params: ray_mask must
+ * be NULL and flags 0.  Synchronises the stream.  *out = NULL on error. */
+gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t n_scenes,
+                         const gs_params *params, gs_plan **out, void *stream);
+
+/* Changes the compositing launch shape (the next run re-captures). */
+gs_status gs_plan_set_config(gs_plan *plan, const gs_plan_config *config);
+
+/* Times each launch shape ({0,1}, {0,0}, {1,0}) over `reps` >= 1 runs into
+ * sens and keeps the fastest; ms (host float[3], nullable) receives the mean
+ * time per run of each.  Synchronises the stream. */
+gs_status gs_plan_tune(gs_plan *plan, float *const *sens, int32_t reps, gs_plan_config *best, float *ms,
+                       void *stream);
+
+gs_status gs_plan_get_info(const gs_plan *plan, gs_plan_info *info);
+
+/* sens: host array of n_scenes device float pointers, sens[i] of length
+ * scenes[i].n.  Queues the whole pass; no host synchronisation.  A new set
+ * of output pointers re-captures the graph (and synchronises once). */
+gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream);
+
+/* Synchronises the stream and returns GS_ERR_INVALID_DATA if, in any run
+ * since creation, a scene needed more tile-list entries than its capacity
+ * (that scene's output of that run is then all zeros). */
+gs_status gs_plan_status(gs_plan *plan, void *stream);
+
+/* Waits for the device and frees the plan (NULL is ignored). */
+void gs_plan_destroy(gs_plan *plan);
+
 /* ---- Learned sampling proposal ------------------------------------------
  * A proposal distribution for sensitivity sampling: the sampler's
  * unbiasedness (proof of Theorem 2) holds for any p with p_i > 0 wherever
  * a_i can be > 0, so a cheap predictor of s, mixed with a uniform floor, can
  * replace the exact pass; the fixed objective then judges the draw.
- * MLP 64 -> 256 -> 256 -> 256 -> 1 with SiLU, predicting ln(max(s, 1e-12)).
+ * MLP 64 -> 256 -> 256 -> 256 -> 1 with SiLU; the Python layer trains it to
+ * predict ln(max(s, 1e-6)).
  * Parameters are float32 in PyTorch Linear layout, concatenated:
  *   W1[256][64] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] w4[256] b4
  * (gs_mlp_param_count() floats).  Products run in BF16 on the matrix cores

@@ -23,7 +23,7 @@ from ._lib import (ATTR_F32, ATTR_MIXED16, GsError, OBJ_FIXED, OBJ_FULL, OBJ_TRU
 
 __all__ = ["DeviceScene", "sensitivity", "sample_coreset", "render_objective", "GsError",
            "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "ATTR_F32",
-           "ATTR_MIXED16", "load", "release_workspace"]
+           "ATTR_MIXED16", "load", "release_workspace", "Plan"]
 
 
 def _torch():
@@ -122,6 +122,79 @@ def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3,
                                 C.byref(st) if st is not None else None, _stream_handle(stream))
     _lib.check(status)
     return out, (st.as_dict() if st is not None else None)
+
+
+class Plan:
+    """Batched sensitivity pass over several scenes (gs_plan_* in the C ABI):
+    capacities fixed at creation, the whole pass queued without host
+    synchronisation and replayed as a HIP graph.  The scenes' attribute
+    tensors must stay alive, at the same addresses, while the plan exists."""
+
+    def __init__(self, scenes, views, *, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
+                 share_floor=1e-12, query_mode=QUERY_RGBSUM, stream=None):
+        if len(scenes) != len(views) or not scenes:
+            raise ValueError("need one views set per scene")
+        lib = load()
+        self.scenes = list(scenes)
+        self._hv = [_views(v) for v in views]
+        sc = (_lib.Scene * len(scenes))(*[s.c_struct() for s in scenes])
+        vw = (_lib.Views * len(scenes))(*[h.c for h in self._hv])
+        p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, None, 0)
+        h = C.c_void_p()
+        _lib.check(lib.gs_plan_create(sc, vw, len(scenes), C.byref(p), C.byref(h), _stream_handle(stream)))
+        self._h = h
+        self._outs = None
+
+    def _ptrs(self, outs):
+        return (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+
+    def outputs(self):
+        """Output tensors reused across runs (one float32 [n] per scene)."""
+        torch = _torch()
+        if self._outs is None:
+            self._outs = [torch.empty(s.n, dtype=torch.float32, device=s.opacity.device) for s in self.scenes]
+        return self._outs
+
+    def run(self, outs=None, stream=None):
+        outs = self.outputs() if outs is None else outs
+        _lib.check(load().gs_plan_sensitivity(self._h, self._ptrs(outs), _stream_handle(stream)))
+        return outs
+
+    def set_config(self, persistent: int, xcd_remap: int):
+        cfg = _lib.PlanConfig(persistent, xcd_remap)
+        _lib.check(load().gs_plan_set_config(self._h, C.byref(cfg)))
+
+    def tune(self, reps=3, outs=None, stream=None):
+        """Times the launch shapes on this plan, keeps the fastest; returns
+        (best config dict, mean ms per run of {0,1}, {0,0}, {1,0})."""
+        outs = self.outputs() if outs is None else outs
+        best = _lib.PlanConfig()
+        ms = (C.c_float * 3)()
+        _lib.check(load().gs_plan_tune(self._h, self._ptrs(outs), int(reps), C.byref(best), ms,
+                                       _stream_handle(stream)))
+        return {"persistent": best.persistent, "xcd_remap": best.xcd_remap}, list(ms)
+
+    def info(self):
+        i = _lib.PlanInfo()
+        _lib.check(load().gs_plan_get_info(self._h, C.byref(i)))
+        return {"n_scenes": i.n_scenes, "n_groups": i.n_groups, "persistent": i.config.persistent,
+                "xcd_remap": i.config.xcd_remap, "graph_captured": i.graph_captured,
+                "device_bytes": i.device_bytes, "list_capacity": i.list_capacity}
+
+    def status(self, stream=None):
+        """Raises GsError if some run overflowed a scene's list capacity."""
+        _lib.check(load().gs_plan_status(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().gs_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sample_coreset(sens, m: int, seed: int, stream=None):

@@ -20,7 +20,9 @@ STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of mem
                 4: "no positive sensitivity", 5: "invalid data", 6: "device error"}
 EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_default_params",
             "gs_release_workspace", "gs_last_error", "gs_status_string", "gs_mlp_param_count",
-            "gs_mlp_init", "gs_features", "gs_feature_stats", "gs_mlp_forward", "gs_mlp_train_step"]
+            "gs_mlp_init", "gs_features", "gs_feature_stats", "gs_mlp_forward", "gs_mlp_train_step",
+            "gs_plan_create", "gs_plan_set_config", "gs_plan_tune", "gs_plan_get_info",
+            "gs_plan_sensitivity", "gs_plan_status", "gs_plan_destroy"]
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 FLAG_COUNT_PAIRS = 1
@@ -62,6 +64,16 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PlanConfig(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("xcd_remap", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n_scenes", C.c_int32), ("n_groups", C.c_int32), ("config", PlanConfig),
+                ("graph_captured", C.c_int32), ("device_bytes", C.c_int64),
+                ("list_capacity", C.c_int64)]
+
+
 class RenderDiag(C.Structure):
     _fields_ = [("n_invalid_pairs", C.c_int64), ("gamma_max", C.c_double)]
 
@@ -98,8 +110,17 @@ def load(path: str = LIB_PATH):
         lib.gs_feature_stats.argtypes = [P, C.c_int64, P, P]
         lib.gs_mlp_forward.argtypes = [P, P, P, C.c_int64, P, P]
         lib.gs_mlp_train_step.argtypes = [P, P, C.c_int64, C.c_float, P, P, P, C.c_int64, P, P, P]
+        lib.gs_plan_create.argtypes = [P, P, C.c_int32, P, P, P]
+        lib.gs_plan_set_config.argtypes = [P, P]
+        lib.gs_plan_tune.argtypes = [P, P, C.c_int32, P, P, P]
+        lib.gs_plan_get_info.argtypes = [P, P]
+        lib.gs_plan_sensitivity.argtypes = [P, P, P]
+        lib.gs_plan_status.argtypes = [P, P]
+        lib.gs_plan_destroy.argtypes = [P]
+        lib.gs_plan_destroy.restype = None
         for f in (lib.gs_mlp_init, lib.gs_features, lib.gs_feature_stats, lib.gs_mlp_forward,
-                  lib.gs_mlp_train_step):
+                  lib.gs_mlp_train_step, lib.gs_plan_create, lib.gs_plan_set_config, lib.gs_plan_tune,
+                  lib.gs_plan_get_info, lib.gs_plan_sensitivity, lib.gs_plan_status):
             f.restype = C.c_int
         _lib = lib
     return _lib

@@ -125,7 +125,6 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
     add(2 * sizeof(uint32_t) * (size_t)c.vc);
     add(sizeof(uint32_t) * nbins);
-    add(sizeof(uint32_t) * nbins);
     add(sizeof(uint64_t) * (nbins + 1));
     add(sizeof(uint64_t) * scan_tmp_elems(nbins + 1));
     add(sizeof(float) * (size_t)c.rays);
@@ -133,6 +132,8 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(ViewDev) * c.vc);
     add(sizeof(int32_t) * c.total_tiles);
     add(c.total_tiles);                                     // tile activity
+    add(sizeof(int32_t) * c.total_tiles);                   // tile -> scene slot
+    add(sizeof(SceneSlot) + 256);                           // slot + work counter
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
     add(sizeof(double) * 3 * 4 * (size_t)c.total_tiles);   // objective partials
     add(sizeof(double) * (3 * (size_t)c.vc + 1));
@@ -258,6 +259,10 @@ struct Timer {
 // the compositing kernels.  Synchronises once (to size the lists).
 struct ChunkRun {
     ChunkBufs b{};
+    SceneSlot host_slot{};
+    SceneSlot *slot_dev = nullptr;
+    int32_t *tile_scene = nullptr;
+    uint32_t *work = nullptr;
     ViewDev *views_dev = nullptr;
     int32_t *tile_view = nullptr;
     uint32_t *sorted_g = nullptr;
@@ -270,7 +275,8 @@ struct ChunkRun {
 
 gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_params *p, const Setup &S,
                     const ChunkPlan &c, hipStream_t st, int dev, std::vector<ViewDev> &hv,
-                    std::vector<int32_t> &htv, ChunkRun &r, Timer &tm, double *ms_acc, bool zero_counters) {
+                    std::vector<int32_t> &htv, ChunkRun &r, Timer &tm, double *ms_acc, bool zero_counters,
+                    uint32_t *sens_bits) {
     const int64_t N = S.N;
     const int64_t nbins = (int64_t)c.total_tiles * S.nchunks;
     size_t need = chunk_scratch_bytes(S, c);
@@ -289,7 +295,6 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.nvis = cv.take<uint32_t>(2 * (size_t)c.vc);
     b.cmax = b.nvis + c.vc;
     b.bin_count = cv.take<uint32_t>(nbins);
-    b.bin_fill = cv.take<uint32_t>(nbins);
     b.bin_off = cv.take<uint64_t>(nbins + 1);
     r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(nbins + 1));
     b.ray_A = cv.take<float>(c.rays);
@@ -297,6 +302,9 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
     b.tile_active = p->ray_mask ? cv.take<uint8_t>(c.total_tiles) : nullptr;
+    r.tile_scene = cv.take<int32_t>(c.total_tiles);
+    r.slot_dev = cv.take<SceneSlot>(1);
+    r.work = cv.take<uint32_t>(64);
     r.sum_tmp = cv.take<double>((N + 4095) / 4096 + 2);
     r.tile_sums = cv.take<double>(3 * 4 * (size_t)c.total_tiles);
     r.view_sums = cv.take<double>(3 * (size_t)c.vc + 1);
@@ -360,9 +368,14 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(arena_reserve(g_lists[dev], list_bytes + sizeof(uint64_t) * (1 + 2 * (size_t)big_cap)));
     b.lists = (uint32_t *)g_lists[dev].base;
     uint64_t *big = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
-    launch_bin_scatter(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, st);
+    launch_bin_scatter(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, (uint64_t)total, st);
     launch_segment_sort(c.total_tiles, S.nchunks, b, r.sorted_g, r.tile_view, N, big, big_cap, st);
     HIP_TRY(hipGetLastError());
+    // the compositing launch sees this chunk as a single scene slot
+    r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.bin_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
+                            N, S.nchunks, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(r.slot_dev, &r.host_slot, sizeof(SceneSlot), hipMemcpyHostToDevice, st));
+    launch_fill_u32((uint32_t *)r.tile_scene, 0u, c.total_tiles, st);
     tm.mark(3, st);
     if (tm.on) {
         HIP_TRY(hipEventSynchronize(tm.ev[3]));
@@ -371,6 +384,21 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         ms_acc[2] += tm.ms(2, 3);
     }
     return GS_OK;
+}
+
+CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params *p, float share_floor) {
+    CompositeArgs a{};
+    a.views = r.views_dev;
+    a.tile_view = r.tile_view;
+    a.tile_scene = r.tile_scene;
+    a.slots = r.slot_dev;
+    a.total_tiles = total_tiles;
+    a.query_mode = p->query_mode;
+    a.r2_log2 = -0.5f * 1.4426950408889634f * p->footprint_sigma * p->footprint_sigma;
+    a.share_floor = share_floor;
+    a.work = nullptr;
+    a.xcd_remap = 1;
+    return a;
 }
 
 struct DoneGuard {
@@ -466,24 +494,16 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     const float log2e = 1.4426950408889634f;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const ChunkPlan &c = chunks[ci];
-        if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, ci == 0)) != GS_OK) return s;
+        if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, ci == 0, (uint32_t *)sens)) !=
+            GS_OK)
+            return s;
         entries += r.n_entries;
-        CompositeArgs a{};
-        a.views = r.views_dev;
-        a.tile_view = r.tile_view;
-        a.total_tiles = c.total_tiles;
-        a.nchunks = S.nchunks;
-        a.N = S.N;
-        a.r2_log2 = -0.5f * log2e * params->footprint_sigma * params->footprint_sigma;
-        a.share_floor = params->share_floor;
-        a.ray_mask = params->ray_mask;
-        a.sens_bits = (uint32_t *)sens;
-        a.query_mode = params->query_mode;
+        CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor);
         tm.mark(3, st);
-        launch_composite_pass1(a, r.b, st);
+        launch_composite_pass1(a, st);
         HIP_TRY(hipGetLastError());
         tm.mark(4, st);
-        launch_composite_pass2(a, r.b, (params->flags & GS_FLAG_COUNT_PAIRS) != 0, st);
+        launch_composite_pass2(a, (params->flags & GS_FLAG_COUNT_PAIRS) != 0, r.b.counters, st);
         HIP_TRY(hipGetLastError());
         tm.mark(5, st);
         if (stats) {
@@ -554,17 +574,9 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
     uint32_t gamma_bits = 0;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const ChunkPlan &c = chunks[ci];
-        if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, true)) != GS_OK) return s;
-        CompositeArgs a{};
-        a.views = r.views_dev;
-        a.tile_view = r.tile_view;
-        a.total_tiles = c.total_tiles;
-        a.nchunks = S.nchunks;
-        a.N = S.N;
-        a.r2_log2 = -0.5f * log2e * params->footprint_sigma * params->footprint_sigma;
-        a.share_floor = 0.0f;
-        a.ray_mask = params->ray_mask;
-        a.query_mode = params->query_mode;
+        if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, true, nullptr)) != GS_OK)
+            return s;
+        CompositeArgs a = composite_args(r, c.total_tiles, params, 0.0f);
         ObjectiveArgs o{weights, objective, per_ray, r.tile_sums, nullptr, 1e-9f};
         if (objective != GS_OBJ_TRUE) {
             // w_max (1 without weights) bounds every later fixed-objective term
@@ -580,7 +592,7 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
             o.wmax_bits = wmax;
         }
         launch_fill_u64((uint64_t *)r.tile_sums, 0ull, 3 * 4 * (int64_t)c.total_tiles, st);
-        launch_objective(a, o, r.b, st);
+        launch_objective(a, o, r.b.counters, st);
         HIP_TRY(hipGetLastError());
         if (per_view) {
             launch_view_sums(r.tile_sums, r.views_dev, c.vc, per_view + 3 * (int64_t)c.v0, st);
@@ -739,6 +751,481 @@ gs_status gs_mlp_train_step(float *params, float *adam, int64_t step, float lr, 
     mlp_train_step(params, adam, step, lr, features, norm, targets, n, loss, grad, g_work[dev].base, rows, st);
     HIP_TRY(hipGetLastError());
     return GS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched plans: several scenes (each with its own views) in one sequence
+// with capacities fixed at creation, so that the whole sequence has no host
+// synchronisation and can be captured into a hipGraph.  Scenes are packed
+// into groups that fit the scratch budget; in each group every scene is
+// projected, sorted and binned, then one compositing launch per pass covers
+// the tiles of all the group's scenes.
+struct PlanScene {
+    gs_scene sc{};
+    Setup S;
+    ChunkPlan c{};
+    std::vector<ViewDev> hv;
+    std::vector<int32_t> htv;     // tile -> scene-local view
+    ChunkBufs b{};
+    ViewDev *views_dev = nullptr; // slice of the group's view table
+    int32_t *tile_view_local = nullptr;
+    uint32_t *sorted_g = nullptr, *xr = nullptr, *yr = nullptr;
+    uint64_t *scan_tmp = nullptr, *big = nullptr;
+    uint32_t *over = nullptr;
+    int64_t nbins = 0, big_cap = 0;
+    uint64_t cap = 0;
+    int group = 0, view0 = 0, tile0 = 0;
+};
+
+struct PlanGroup {
+    std::vector<int> scenes;
+    void *buf = nullptr, *lists = nullptr;
+    ViewDev *views = nullptr;
+    int32_t *tile_view = nullptr, *tile_scene = nullptr;
+    SceneSlot *slots = nullptr;
+    uint32_t *work = nullptr;
+    int total_tiles = 0, total_views = 0;
+    size_t bytes = 0, list_bytes = 0;
+};
+
+}  // namespace
+
+struct gs_plan {
+    int dev = -1;
+    gs_params p{};
+    std::vector<PlanScene> scenes;
+    std::vector<PlanGroup> groups;
+    uint32_t *flag = nullptr;   // device: 1 if some list capacity was exceeded
+    gs_plan_config cfg{0, 1};
+    hipStream_t cap = nullptr;  // stream the sequence is captured on (the null stream cannot capture)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<float *> bound;  // output pointers baked into the graph
+    int use_graph = 1;
+    int graph_ok = 0;
+};
+
+namespace {
+
+size_t scene_buffer_bytes(const PlanScene &ps) {
+    const int64_t N = ps.S.N;
+    const int64_t nb = (N + kSortTile - 1) / kSortTile;
+    size_t b = 0;
+    auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
+    add(3 * sizeof(float4) * (size_t)ps.c.vc * N);
+    for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)ps.c.vc * N);
+    add(sizeof(uint32_t) * (size_t)ps.c.vc * 256 * nb);
+    add(2 * sizeof(uint32_t) * (size_t)ps.c.vc);
+    add(sizeof(uint32_t) * ps.nbins);
+    add(sizeof(uint64_t) * (ps.nbins + 1));
+    add(sizeof(uint64_t) * scan_tmp_elems(ps.nbins + 1));
+    add(sizeof(float) * (size_t)ps.c.rays);
+    add(sizeof(uint64_t) * CNT_SLOTS);
+    add(sizeof(int32_t) * ps.c.total_tiles);
+    add(256);
+    return b;
+}
+
+void carve_scene(PlanScene &ps, Carve &cv) {
+    const int64_t N = ps.S.N;
+    const int64_t nb = (N + kSortTile - 1) / kSortTile;
+    ChunkBufs &b = ps.b;
+    b.R0 = cv.take<float4>((size_t)ps.c.vc * N);
+    b.R1 = cv.take<float4>((size_t)ps.c.vc * N);
+    b.R2 = cv.take<float4>((size_t)ps.c.vc * N);
+    b.key0 = cv.take<uint32_t>((size_t)ps.c.vc * N);
+    b.val0 = cv.take<uint32_t>((size_t)ps.c.vc * N);
+    b.key1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
+    b.val1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
+    b.hist = cv.take<uint32_t>((size_t)ps.c.vc * 256 * nb);
+    b.nvis = cv.take<uint32_t>(2 * (size_t)ps.c.vc);
+    b.cmax = b.nvis + ps.c.vc;
+    b.bin_count = cv.take<uint32_t>(ps.nbins);
+    b.bin_off = cv.take<uint64_t>(ps.nbins + 1);
+    ps.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(ps.nbins + 1));
+    b.ray_A = cv.take<float>(ps.c.rays);
+    b.counters = cv.take<uint64_t>(CNT_SLOTS);
+    ps.tile_view_local = cv.take<int32_t>(ps.c.total_tiles);
+    ps.over = cv.take<uint32_t>(64);
+    b.tile_active = nullptr;
+}
+
+// Projection, depth sort and the count of the lists of one plan scene.
+void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
+    const int64_t N = ps.S.N;
+    ChunkBufs &b = ps.b;
+    launch_fill_u32(b.nvis, 0u, 2 * (int64_t)ps.c.vc, st);
+    launch_fill_u32(b.bin_count, 0u, ps.nbins, st);
+    launch_fill_u64(b.counters, 0ull, CNT_SLOTS, st);
+    SceneDev sd{ps.sc.n, ps.sc.sh_degree, ps.sc.format, ps.sc.mean, ps.sc.log_scale,
+                ps.sc.quat, ps.sc.opacity, ps.sc.sh};
+    ProjParams pp{P->p.footprint_sigma, P->p.dilation, P->p.z_near, P->p.query_mode};
+    launch_project(sd, ps.views_dev, ps.c.vc, pp, b, st);
+    uint32_t *skeys = nullptr;
+    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, &skeys, &ps.sorted_g, st);
+    ps.xr = b.key1;
+    ps.yr = b.val1;
+    launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);
+    launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, st);
+    scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, ps.nbins, ps.scan_tmp, st);
+}
+
+void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
+    const float log2e = 1.4426950408889634f;
+    for (PlanGroup &G : P->groups) {
+        for (int si : G.scenes) {
+            PlanScene &ps = P->scenes[si];
+            enqueue_front(P, ps, st);
+            launch_list_guard(ps.b.bin_off, ps.nbins, ps.cap, ps.over, P->flag, st);
+            launch_bin_scatter(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.cap, st);
+            launch_segment_sort(ps.c.total_tiles, ps.S.nchunks, ps.b, ps.sorted_g, ps.tile_view_local, ps.S.N,
+                                ps.big, ps.big_cap, st);
+            launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
+        }
+        CompositeArgs a{};
+        a.views = G.views;
+        a.tile_view = G.tile_view;
+        a.tile_scene = G.tile_scene;
+        a.slots = G.slots;
+        a.total_tiles = G.total_tiles;
+        a.query_mode = P->p.query_mode;
+        a.r2_log2 = -0.5f * log2e * P->p.footprint_sigma * P->p.footprint_sigma;
+        a.share_floor = P->p.share_floor;
+        a.work = P->cfg.persistent ? G.work : nullptr;
+        a.xcd_remap = P->cfg.xcd_remap;
+        launch_composite_pass1(a, st);
+        launch_composite_pass2(a, false, nullptr, st);
+    }
+}
+
+void plan_free(gs_plan *P) {
+    if (P->exec) hipGraphExecDestroy(P->exec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    for (PlanGroup &G : P->groups) {
+        if (G.buf) hipFree(G.buf);
+        if (G.lists) hipFree(G.lists);
+    }
+    if (P->flag) hipFree(P->flag);
+    if (P->cap) hipStreamDestroy(P->cap);
+    delete P;
+}
+
+
+// Groups, buffers, tables and list capacities of a new plan.
+gs_status plan_allocate(gs_plan *P, hipStream_t st) {
+    const int n_scenes = (int)P->scenes.size();
+    // pack scenes into groups under half the scratch budget (the rest is for lists)
+    const size_t budget = scratch_budget() / 2;
+    for (int i = 0; i < n_scenes; ++i) {
+        const size_t need = scene_buffer_bytes(P->scenes[i]);
+        if (need > budget) {
+            return fail(GS_ERR_UNSUPPORTED, "scene %d needs %zu bytes of scratch, more than the %zu budget", i,
+                        need, budget);
+        }
+        if (P->groups.empty() || P->groups.back().bytes + need > budget) P->groups.push_back(PlanGroup{});
+        PlanGroup &G = P->groups.back();
+        G.scenes.push_back(i);
+        G.bytes += need;
+        P->scenes[i].group = (int)P->groups.size() - 1;
+    }
+    if (hipMalloc((void **)&P->flag, 256) != hipSuccess) {
+        return fail(GS_ERR_OUT_OF_MEMORY, "plan flag");
+    }
+    launch_fill_u32(P->flag, 0u, 1, st);
+    std::vector<std::vector<ViewDev>> group_views(P->groups.size());
+    std::vector<std::vector<int32_t>> group_tv(P->groups.size()), group_ts(P->groups.size());
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        PlanGroup &G = P->groups[gi];
+        for (int si : G.scenes) {
+            PlanScene &ps = P->scenes[si];
+            ps.view0 = G.total_views;
+            ps.tile0 = G.total_tiles;
+            G.total_views += ps.c.vc;
+            G.total_tiles += ps.c.total_tiles;
+        }
+        const size_t table_bytes = sizeof(ViewDev) * G.total_views + 2 * sizeof(int32_t) * G.total_tiles +
+                                   sizeof(SceneSlot) * G.scenes.size() + 4096;
+        if (hipMalloc(&G.buf, G.bytes + table_bytes + 65536) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GS_ERR_OUT_OF_MEMORY, "plan group %zu: %zu bytes", gi, G.bytes + table_bytes);
+        }
+        Carve cv(G.buf);
+        for (int si : G.scenes) carve_scene(P->scenes[si], cv);
+        G.views = cv.take<ViewDev>(G.total_views);
+        G.tile_view = cv.take<int32_t>(G.total_tiles);
+        G.tile_scene = cv.take<int32_t>(G.total_tiles);
+        G.slots = cv.take<SceneSlot>(G.scenes.size());
+        G.work = cv.take<uint32_t>(64);
+        auto &gv = group_views[gi];
+        auto &gtv = group_tv[gi];
+        auto &gts = group_ts[gi];
+        for (size_t k = 0; k < G.scenes.size(); ++k) {
+            PlanScene &ps = P->scenes[G.scenes[k]];
+            ps.views_dev = G.views + ps.view0;
+            gv.insert(gv.end(), ps.hv.begin(), ps.hv.end());
+            for (int t = 0; t < ps.c.total_tiles; ++t) {
+                gtv.push_back(ps.view0 + ps.htv[t]);
+                gts.push_back((int32_t)k);
+            }
+            HIP_TRY(hipMemcpyAsync(ps.tile_view_local, ps.htv.data(), sizeof(int32_t) * ps.c.total_tiles,
+                                   hipMemcpyHostToDevice, st));
+        }
+        HIP_TRY(hipMemcpyAsync(G.views, gv.data(), sizeof(ViewDev) * gv.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(G.tile_view, gtv.data(), sizeof(int32_t) * gtv.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(G.tile_scene, gts.data(), sizeof(int32_t) * gts.size(), hipMemcpyHostToDevice, st));
+        // count pre-pass: list sizes of every scene of the group
+        std::vector<uint64_t> totals(G.scenes.size());
+        for (size_t k = 0; k < G.scenes.size(); ++k) {
+            PlanScene &ps = P->scenes[G.scenes[k]];
+            enqueue_front(P, ps, st);
+            HIP_TRY(hipMemcpyAsync(&totals[k], ps.b.bin_off + ps.nbins, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        size_t lb = 0;
+        for (size_t k = 0; k < G.scenes.size(); ++k) {
+            PlanScene &ps = P->scenes[G.scenes[k]];
+            ps.cap = totals[k] + totals[k] / 64 + 1024;
+            ps.big_cap = (int64_t)(ps.cap / 65) + 1;
+            lb += ((ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255) +
+                  ((sizeof(uint64_t) * (1 + 2 * (size_t)ps.big_cap) + 255) & ~(size_t)255);
+        }
+        if (hipMalloc(&G.lists, lb + 4096) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GS_ERR_OUT_OF_MEMORY, "plan group %zu lists: %zu bytes", gi, lb);
+        }
+        G.list_bytes = lb;
+        Carve lc(G.lists);
+        for (int si : G.scenes) {
+            PlanScene &ps = P->scenes[si];
+            ps.b.lists = lc.take<uint32_t>(ps.cap);
+            ps.big = lc.take<uint64_t>(1 + 2 * (size_t)ps.big_cap);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return GS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t n_scenes, const gs_params *params,
+                         gs_plan **out, void *stream) {
+    g_last_error.clear();
+    if (!out) return fail(GS_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!scenes || !views || n_scenes < 1) return fail(GS_ERR_INVALID_ARGUMENT, "need n_scenes >= 1 scenes and views");
+    gs_status s;
+    if ((s = check_params(params)) != GS_OK) return s;
+    if (params->ray_mask) return fail(GS_ERR_UNSUPPORTED, "plans do not take a ray mask");
+    if (params->flags) return fail(GS_ERR_UNSUPPORTED, "plans do not count pairs");
+    gs_plan *P = new gs_plan();
+    P->p = *params;
+    P->scenes.resize(n_scenes);
+    for (int i = 0; i < n_scenes; ++i) {
+        PlanScene &ps = P->scenes[i];
+        if ((s = check_scene(&scenes[i])) != GS_OK || (s = check_views(&views[i], ps.S)) != GS_OK) {
+            delete P;
+            return s;
+        }
+        ps.sc = scenes[i];
+        ps.S.N = scenes[i].n;
+        ps.S.nchunks = (int)((ps.S.N + (1 << kChunkBits) - 1) >> kChunkBits);
+        ps.c = ChunkPlan{0, views[i].n_views, ps.S.ray_base[views[i].n_views], 0};
+        for (int v = 0; v < views[i].n_views; ++v) ps.c.total_tiles += ps.S.tiles_x[v] * ps.S.tiles_y[v];
+        if (views[i].n_views > 65535) {
+            delete P;
+            return fail(GS_ERR_UNSUPPORTED, "scene %d: more than 65535 views", i);
+        }
+        ps.nbins = (int64_t)ps.c.total_tiles * ps.S.nchunks;
+        // host view table (tile_base and ray numbering local to the scene)
+        ps.hv.assign(ps.c.vc, ViewDev{});
+        ps.htv.assign(ps.c.total_tiles, 0);
+        int tb = 0;
+        for (int k = 0; k < ps.c.vc; ++k) {
+            ViewDev &V = ps.hv[k];
+            const double *Pm = views[i].world_to_cam + 12 * k;
+            for (int a = 0; a < 3; ++a) {
+                for (int bb = 0; bb < 3; ++bb) V.R[3 * a + bb] = Pm[4 * a + bb];
+                V.t[a] = Pm[4 * a + 3];
+            }
+            for (int a = 0; a < 3; ++a) V.cam[a] = -(V.R[a] * V.t[0] + V.R[3 + a] * V.t[1] + V.R[6 + a] * V.t[2]);
+            V.fx = views[i].intrinsics[4 * k];
+            V.fy = views[i].intrinsics[4 * k + 1];
+            V.cx = views[i].intrinsics[4 * k + 2];
+            V.cy = views[i].intrinsics[4 * k + 3];
+            V.W = views[i].size[2 * k];
+            V.H = views[i].size[2 * k + 1];
+            V.tiles_x = ps.S.tiles_x[k];
+            V.tiles_y = ps.S.tiles_y[k];
+            V.ray_base = ps.S.ray_base[k];
+            V.ray_local = ps.S.ray_base[k];
+            V.tile_base = tb;
+            for (int t = 0; t < V.tiles_x * V.tiles_y; ++t) ps.htv[tb + t] = k;
+            tb += V.tiles_x * V.tiles_y;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    if ((s = begin_call(&dev, st)) != GS_OK) {
+        delete P;
+        return s;
+    }
+    DoneGuard done_guard{dev, st};
+    P->dev = dev;
+    s = plan_allocate(P, st);
+    if (s != GS_OK) {
+        plan_free(P);
+        return s;
+    }
+    *out = P;
+    return GS_OK;
+}
+
+gs_status gs_plan_set_config(gs_plan *plan, const gs_plan_config *cfg) {
+    g_last_error.clear();
+    if (!plan || !cfg) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if ((cfg->persistent != 0 && cfg->persistent != 1) || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1))
+        return fail(GS_ERR_INVALID_ARGUMENT, "config fields are 0 or 1");
+    std::lock_guard<std::mutex> lk(g_lock);
+    if (plan->cfg.persistent != cfg->persistent || plan->cfg.xcd_remap != cfg->xcd_remap) {
+        plan->cfg = *cfg;
+        plan->bound.clear();  // forces a new capture
+    }
+    return GS_OK;
+}
+
+gs_status gs_plan_get_info(const gs_plan *plan, gs_plan_info *info) {
+    g_last_error.clear();
+    if (!plan || !info) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    memset(info, 0, sizeof(*info));
+    info->n_scenes = (int32_t)plan->scenes.size();
+    info->n_groups = (int32_t)plan->groups.size();
+    info->config = plan->cfg;
+    info->graph_captured = plan->graph_ok;
+    for (const PlanGroup &G : plan->groups) info->device_bytes += (int64_t)(G.bytes + G.list_bytes);
+    for (const PlanScene &ps : plan->scenes) info->list_capacity += (int64_t)ps.cap;
+    return GS_OK;
+}
+
+gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
+    g_last_error.clear();
+    if (!plan || !sens) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    for (size_t i = 0; i < plan->scenes.size(); ++i)
+        if (!sens[i]) return fail(GS_ERR_INVALID_ARGUMENT, "sens[%zu] is NULL", i);
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    if (dev != plan->dev) return fail(GS_ERR_INVALID_ARGUMENT, "plan was created on device %d", plan->dev);
+    const std::vector<float *> want(sens, sens + plan->scenes.size());
+    if (want != plan->bound) {
+        // (re)bind the outputs: slot tables, then a fresh capture
+        for (PlanGroup &G : plan->groups) {
+            std::vector<SceneSlot> hs;
+            for (int si : G.scenes) {
+                PlanScene &ps = plan->scenes[si];
+                hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.bin_off, ps.b.cmax, ps.b.ray_A,
+                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.S.nchunks, ps.view0, ps.tile0, 0});
+            }
+            HIP_TRY(hipMemcpyAsync(G.slots, hs.data(), sizeof(SceneSlot) * hs.size(), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (plan->exec) hipGraphExecDestroy(plan->exec);
+        if (plan->graph) hipGraphDestroy(plan->graph);
+        plan->exec = nullptr;
+        plan->graph = nullptr;
+        plan->graph_ok = 0;
+        if (plan->use_graph) {
+            hipError_t e = hipSuccess;
+            if (!plan->cap) e = hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                enqueue_plan(plan, plan->cap, sens);
+                e = hipStreamEndCapture(plan->cap, &plan->graph);
+                if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                plan->use_graph = 0;
+                if (plan->graph) hipGraphDestroy(plan->graph);
+                plan->graph = nullptr;
+                plan->exec = nullptr;
+            } else {
+                plan->graph_ok = 1;
+            }
+        }
+        plan->bound = want;
+    }
+    if (plan->graph_ok) {
+        HIP_TRY(hipGraphLaunch(plan->exec, st));
+    } else {
+        enqueue_plan(plan, st, sens);
+        HIP_TRY(hipGetLastError());
+    }
+    return GS_OK;
+}
+
+gs_status gs_plan_tune(gs_plan *plan, float *const *sens, int32_t reps, gs_plan_config *best, float *ms,
+                       void *stream) {
+    g_last_error.clear();
+    if (!plan || !sens) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (reps < 1) return fail(GS_ERR_INVALID_ARGUMENT, "reps must be >= 1");
+    const gs_plan_config cand[3] = {{0, 1}, {0, 0}, {1, 0}};
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(GS_ERR_DEVICE, "hipEventCreate failed");
+    }
+    float t[3] = {0, 0, 0};
+    gs_status s = GS_OK;
+    for (int k = 0; k < 3 && s == GS_OK; ++k) {
+        if ((s = gs_plan_set_config(plan, &cand[k])) != GS_OK) break;
+        if ((s = gs_plan_sensitivity(plan, sens, stream)) != GS_OK) break;  // capture + warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) s = fail(GS_ERR_DEVICE, "hipEventRecord failed");
+        for (int r = 0; r < reps && s == GS_OK; ++r) s = gs_plan_sensitivity(plan, sens, stream);
+        if (s == GS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t[k], e0, e1) != hipSuccess))
+            s = fail(GS_ERR_DEVICE, "timing the plan failed");
+        t[k] /= (float)reps;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != GS_OK) return s;
+    int b = 0;
+    for (int k = 1; k < 3; ++k)
+        if (t[k] < t[b]) b = k;
+    if ((s = gs_plan_set_config(plan, &cand[b])) != GS_OK) return s;
+    if (best) *best = cand[b];
+    if (ms)
+        for (int k = 0; k < 3; ++k) ms[k] = t[k];
+    return GS_OK;
+}
+
+gs_status gs_plan_status(gs_plan *plan, void *stream) {
+    g_last_error.clear();
+    if (!plan) return fail(GS_ERR_INVALID_ARGUMENT, "plan is NULL");
+    uint32_t f = 0;
+    HIP_TRY(hipMemcpyAsync(&f, plan->flag, sizeof f, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    if (f) return fail(GS_ERR_INVALID_DATA, "a scene produced more tile-list entries than at plan creation; "
+                                           "its lists were emptied (recreate the plan)");
+    return GS_OK;
+}
+
+void gs_plan_destroy(gs_plan *plan) {
+    if (!plan) return;
+    std::lock_guard<std::mutex> lk(g_lock);
+    (void)hipDeviceSynchronize();
+    plan_free(plan);
 }
 
 }  // extern "C"

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
                                                      uint32_t *__restrict__ bin_count,
                                                      const uint64_t *__restrict__ bin_off,
                                                      uint32_t *__restrict__ lists,
-                                                     const uint8_t *__restrict__ active) {
+                                                     const uint8_t *__restrict__ active, uint64_t cap) {
     extern __shared__ uint32_t lds[];
     uint32_t *cnt = lds;                              // [tiles]
     uint32_t *base = lds + kMaxTilesPerView;          // [tiles] (scatter only)
@@ -106,7 +106,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewDev *__restrict__
                 const int t = ty * V.tiles_x + tx;
                 if (cnt[t] & kOff) continue;
                 const uint32_t slot = atomicAdd(&cnt[t], 1u);
-                vl[base[t] + slot] = (uint32_t)p | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
+                const uint64_t at = vlist + base[t] + slot;
+                if (at < cap) vl[base[t] + slot] = (uint32_t)p | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
             }
     }
 }
@@ -115,14 +116,34 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
                       const uint32_t *xr, const uint32_t *yr, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     hipLaunchKernelGGL(k_bin<false>, dim3(nb, Vc), dim3(kBinThreads), kMaxTilesPerView * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists, b.tile_active);
+                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists, b.tile_active,
+                       (uint64_t)0);
 }
 
 void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                        const uint32_t *xr, const uint32_t *yr, hipStream_t st) {
+                        const uint32_t *xr, const uint32_t *yr, uint64_t cap, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     hipLaunchKernelGGL(k_bin<true>, dim3(nb, Vc), dim3(kBinThreads), 2 * kMaxTilesPerView * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists, b.tile_active);
+                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.bin_off, b.lists, b.tile_active, cap);
+}
+
+// Capacity guard for lists sized in advance (plans): if the counted entries
+// exceed the capacity, flag it and empty every list of the scene so that no
+// later kernel reads past the buffer.
+__global__ void k_guard_check(const uint64_t *__restrict__ bin_off, int64_t nbins, uint64_t cap,
+                              uint32_t *__restrict__ over, uint32_t *__restrict__ flag) {
+    const bool o = bin_off[nbins] > cap;
+    *over = o ? 1u : 0u;
+    if (o) atomicOr(flag, 1u);
+}
+__global__ void k_guard_apply(uint64_t *__restrict__ bin_off, int64_t nbins, const uint32_t *__restrict__ over) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (*over && i <= nbins) bin_off[i] = 0;
+}
+void launch_list_guard(uint64_t *bin_off, int64_t nbins, uint64_t cap, uint32_t *over, uint32_t *flag,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_guard_check, dim3(1), dim3(1), 0, st, bin_off, nbins, cap, over, flag);
+    hipLaunchKernelGGL(k_guard_apply, dim3((unsigned)((nbins + 256) / 256)), dim3(256), 0, st, bin_off, nbins, over);
 }
 
 // A tile is active when at least one of its rays is selected by the ray mask;

@@ -16,6 +16,11 @@
 // with a transposed butterfly (32 entries at a time; lane L ends with the
 // maximum of entry L/2), and raises s with an atomic maximum on the float
 // bits (order-free, so the result is deterministic).
+//
+// A launch may cover several scenes (batched plans): each tile of the launch
+// names its scene slot (records, lists, outputs) and its view.  In the
+// persistent form a fixed grid of waves takes quadrants from an atomic work
+// counter until none are left.
 #include "gs_internal.hpp"
 
 namespace gs {
@@ -43,18 +48,20 @@ struct WaveSetup {
     uint64_t start, end;
     uint32_t qbit;
     int W;
+    const SceneSlot *S;
+    int64_t vbase;
 };
 
-__device__ __forceinline__ bool setup_wave(const CompositeArgs &a, const uint64_t *bin_off, WaveSetup &w) {
-    const int nblk = a.total_tiles * 4;
-    const int padded = (nblk + 7) & ~7;
-    const int logical = xcd_remap(blockIdx.x, padded);
-    if (logical >= nblk) return false;
+__device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles * 4; }
+
+// Quadrant `logical` of the launch -> this wave's pixels, list range and scene.
+__device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, WaveSetup &w) {
     w.gt = logical >> 2;
     w.quad = logical & 3;
     w.v = a.tile_view[w.gt];
+    w.S = &a.slots[a.tile_scene[w.gt]];
     const ViewDev &V = a.views[w.v];
-    const int tl = w.gt - V.tile_base;
+    const int tl = w.gt - w.S->tile0 - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
     const int qx0 = tx * kTile + (w.quad & 1) * kQuad;
     const int qy0 = ty * kTile + (w.quad >> 1) * kQuad;
@@ -70,10 +77,27 @@ __device__ __forceinline__ bool setup_wave(const CompositeArgs &a, const uint64_
     w.W = V.W;
     w.ray_local = V.ray_local + (int64_t)w.py * V.W + w.px;
     w.ray_global = V.ray_base + (int64_t)w.py * V.W + w.px;
-    w.start = bin_off[(int64_t)w.gt * a.nchunks];
-    w.end = bin_off[(int64_t)(w.gt + 1) * a.nchunks];
+    const int64_t st = (int64_t)(w.gt - w.S->tile0) * w.S->nchunks;
+    w.start = w.S->bin_off[st];
+    w.end = w.S->bin_off[st + w.S->nchunks];
     w.qbit = 1u << (28 + w.quad);
+    w.vbase = (int64_t)(w.v - w.S->view0) * w.S->N;
     return true;
+}
+
+// Next quadrant for this wave: the block's own (remapped) index in the flat
+// form, or the next item of the work counter in the persistent form.
+__device__ __forceinline__ int next_quad(const CompositeArgs &a, int &iter) {
+    const int nq = quad_count(a);
+    if (a.work == nullptr) {
+        if (iter++) return nq;
+        if (!a.xcd_remap) return blockIdx.x;
+        const int padded = (nq + 7) & ~7;
+        return xcd_remap(blockIdx.x, padded);
+    }
+    int q = 0;
+    if (threadIdx.x == 0) q = (int)atomicAdd(a.work, 1u);
+    return __shfl(q, 0);
 }
 
 __device__ __forceinline__ bool ray_selected(const uint32_t *mask, int64_t ray) {
@@ -84,14 +108,15 @@ __device__ __forceinline__ bool ray_selected(const uint32_t *mask, int64_t ray) 
 // geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
 // col = (g', alpha, cbar, extra).
 template <int kExtra>  // 0: none, 1: s_old + index, 2: weight
-__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, const uint32_t *__restrict__ lists,
-                                           const float4 *__restrict__ R0, const float4 *__restrict__ R1,
-                                           const float4 *__restrict__ R2, int64_t vbase, float4 *geo, float4 *col,
-                                           uint32_t *sid, float *sold, const uint32_t *__restrict__ sens_bits,
-                                           const double *__restrict__ weights) {
+__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float4 *geo, float4 *col,
+                                           uint32_t *sid, float *sold, const double *__restrict__ weights) {
     const int lane = threadIdx.x;
     const uint64_t e = e0 + lane;
-    const uint32_t raw = e < w.end ? lists[e] : 0u;
+    const uint32_t raw = e < w.end ? w.S->lists[e] : 0u;
+    const float4 *__restrict__ R0 = w.S->R0;
+    const float4 *__restrict__ R1 = w.S->R1;
+    const float4 *__restrict__ R2 = w.S->R2;
+    const int64_t vbase = w.vbase;
     const bool touch = (raw & w.qbit) != 0u;
     const uint64_t bal = __ballot(touch);
     if (touch) {
@@ -107,7 +132,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, cons
         float extra = 0.0f;
         if (kExtra == 1) {
             sid[slot] = g;
-            sold[slot] = __uint_as_float(sens_bits[g]);
+            sold[slot] = __uint_as_float(w.S->sens_bits[g]);
         }
         if (kExtra == 2) extra = (float)weights[g];
         col[slot] = make_float4(r1.z, r1.w, cb, extra);
@@ -129,34 +154,34 @@ __device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, flo
     return in_fp ? Cc.y * E : 0.0f;
 }
 
-__global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a, const uint64_t *__restrict__ bin_off,
-                                                 const uint32_t *__restrict__ lists, const float4 *__restrict__ R0,
-                                                 const float4 *__restrict__ R1, const float4 *__restrict__ R2,
-                                                 const uint32_t *__restrict__ cmax_bits, float *__restrict__ ray_A) {
+__global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
     __shared__ float4 geo[kWave], col[kWave];
-    WaveSetup w;
-    if (!setup_wave(a, bin_off, w)) return;
-    const bool scored = w.inside && ray_selected(a.ray_mask, w.ray_global);
-    const float cmax = __uint_as_float(cmax_bits[w.v]);
-    const int64_t vbase = (int64_t)w.v * a.N;
-    float T = 1.0f, A = 0.0f;
-    bool done = !scored;
-    for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
-        if (__all(done)) break;
-        const int n = stage_slice<0>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr, nullptr);
-        __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            const float4 G = geo[j], Cc = col[j];
-            bool in_fp;
-            const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
-            const float cr = Cc.z * rho;
-            A = fmaf(cr, T, A);
-            T = fmaf(-rho, T, T);
+    const int nq = quad_count(a);
+    int iter = 0;
+    for (int qi = next_quad(a, iter); qi < nq; qi = next_quad(a, iter)) {
+        WaveSetup w;
+        if (!setup_quad(a, qi, w)) continue;
+        const bool scored = w.inside && ray_selected(w.S->ray_mask, w.ray_global);
+        const float cmax = __uint_as_float(w.S->cmax[w.v - w.S->view0]);
+        float T = 1.0f, A = 0.0f;
+        bool done = !scored;
+        for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
+            if (__all(done)) break;
+            const int n = stage_slice<0>(w, e0, geo, col, nullptr, nullptr, nullptr);
+            __syncthreads();
+            for (int j = 0; j < n; ++j) {
+                const float4 G = geo[j], Cc = col[j];
+                bool in_fp;
+                const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+                const float cr = Cc.z * rho;
+                A = fmaf(cr, T, A);
+                T = fmaf(-rho, T, T);
+            }
+            done = done || (T * cmax < a.share_floor * A);
+            __syncthreads();
         }
-        done = done || (T * cmax < a.share_floor * A);
-        __syncthreads();
+        if (w.inside) w.S->ray_A[w.ray_local] = scored ? A : 0.0f;
     }
-    if (w.inside) ray_A[w.ray_local] = scored ? A : 0.0f;
 }
 
 // Transposed butterfly over 64 lanes for 32 values: afterwards lane L holds
@@ -207,62 +232,66 @@ __device__ __forceinline__ float wave_transpose_max32(float (&v)[32]) {
 }
 
 template <bool kStats>
-__global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, const uint64_t *__restrict__ bin_off,
-                                                 const uint32_t *__restrict__ lists, const float4 *__restrict__ R0,
-                                                 const float4 *__restrict__ R1, const float4 *__restrict__ R2,
-                                                 const uint32_t *__restrict__ cmax_bits,
-                                                 const float *__restrict__ ray_A, uint64_t *__restrict__ counters) {
+__global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     __shared__ float4 geo[kWave], col[kWave];
     __shared__ uint32_t sid[kWave];
     __shared__ float sold[kWave];
-    WaveSetup w;
-    if (!setup_wave(a, bin_off, w)) return;
-    const bool scored = w.inside && ray_selected(a.ray_mask, w.ray_global);
-    const float Af = scored ? ray_A[w.ray_local] : 0.0f;
-    const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
-    const float cmax = __uint_as_float(cmax_bits[w.v]);
-    const int64_t vbase = (int64_t)w.v * a.N;
     const int lane = threadIdx.x;
-    float T = 1.0f;
-    bool done = invA == 0.0f;
-    uint32_t n_in = 0, n_live = 0, n_eval = 0;
-    const float live_bar = a.share_floor * Af;
-    for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
-        if (__all(done)) break;
-        const int n = stage_slice<1>(w, e0, lists, R0, R1, R2, vbase, geo, col, sid, sold, a.sens_bits, nullptr);
-        __syncthreads();
-        for (int jb = 0; jb < n; jb += 32) {
-            float sh[32];
+    const int nq = quad_count(a);
+    int iter = 0;
+    uint64_t pin = 0, plive = 0, pos = 0, peval = 0;
+    for (int qi = next_quad(a, iter); qi < nq; qi = next_quad(a, iter)) {
+        WaveSetup w;
+        if (!setup_quad(a, qi, w)) continue;
+        const bool scored = w.inside && ray_selected(w.S->ray_mask, w.ray_global);
+        const float Af = scored ? w.S->ray_A[w.ray_local] : 0.0f;
+        const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
+        const float cmax = __uint_as_float(w.S->cmax[w.v - w.S->view0]);
+        uint32_t *sens_bits = w.S->sens_bits;
+        float T = 1.0f;
+        bool done = invA == 0.0f;
+        uint32_t n_in = 0, n_live = 0, n_eval = 0;
+        const float live_bar = a.share_floor * Af;
+        for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
+            if (__all(done)) break;
+            const int n = stage_slice<1>(w, e0, geo, col, sid, sold, nullptr);
+            __syncthreads();
+            for (int jb = 0; jb < n; jb += 32) {
+                float sh[32];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                const int j = jb + k;
-                if (j < n) {
-                    const float4 G = geo[j], Cc = col[j];
-                    bool in_fp;
-                    const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
-                    const float cr = Cc.z * rho;
-                    sh[k] = (cr * T) * invA;
-                    if (kStats) {
-                        n_in += in_fp ? 1u : 0u;
-                        n_live += (in_fp && T * cmax >= live_bar) ? 1u : 0u;
+                for (int k = 0; k < 32; ++k) {
+                    const int j = jb + k;
+                    if (j < n) {
+                        const float4 G = geo[j], Cc = col[j];
+                        bool in_fp;
+                        const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+                        const float cr = Cc.z * rho;
+                        sh[k] = (cr * T) * invA;
+                        if (kStats) {
+                            n_in += in_fp ? 1u : 0u;
+                            n_live += (in_fp && T * cmax >= live_bar) ? 1u : 0u;
+                        }
+                        T = fmaf(-rho, T, T);
+                    } else {
+                        sh[k] = 0.0f;
                     }
-                    T = fmaf(-rho, T, T);
-                } else {
-                    sh[k] = 0.0f;
                 }
+                if (kStats) n_eval += (uint32_t)min(32, n - jb);
+                const float m = wave_transpose_max32(sh);
+                const int j = jb + (lane >> 1);
+                if ((lane & 1) == 0 && j < n && m > sold[j]) atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
             }
-            if (kStats) n_eval += (uint32_t)min(32, n - jb);
-            const float m = wave_transpose_max32(sh);
-            const int j = jb + (lane >> 1);
-            if ((lane & 1) == 0 && j < n && m > sold[j]) atomicMax(&a.sens_bits[sid[j]], __float_as_uint(m));
+            done = done || (T * cmax < a.share_floor * Af);
+            __syncthreads();
         }
-        done = done || (T * cmax < a.share_floor * Af);
-        __syncthreads();
+        if (kStats) {
+            pin += invA > 0.0f ? n_in : 0u;
+            plive += invA > 0.0f ? n_live : 0u;
+            pos += invA > 0.0f ? 1u : 0u;
+            peval += (uint64_t)n_eval;
+        }
     }
     if (kStats) {
-        uint64_t pin = invA > 0.0f ? n_in : 0u;
-        uint64_t plive = invA > 0.0f ? n_live : 0u;
-        uint64_t pos = invA > 0.0f ? 1u : 0u;
         for (int off = 32; off > 0; off >>= 1) {
             pin += __shfl_xor(pin, off);
             plive += __shfl_xor(plive, off);
@@ -272,25 +301,29 @@ __global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, const uint6
             atomicAdd((unsigned long long *)&counters[CNT_PAIRS], (unsigned long long)pin);
             atomicAdd((unsigned long long *)&counters[CNT_LIVE], (unsigned long long)plive);
             atomicAdd((unsigned long long *)&counters[CNT_RAYS_POS], (unsigned long long)pos);
-            atomicAdd((unsigned long long *)&counters[CNT_LANE_PAIRS], (unsigned long long)n_eval * 64ull);
+            atomicAdd((unsigned long long *)&counters[CNT_LANE_PAIRS], (unsigned long long)peval * 64ull);
         }
     }
 }
 
-static inline unsigned composite_grid(int total_tiles) { return (unsigned)(((total_tiles * 4) + 7) & ~7); }
-
-void launch_composite_pass1(const CompositeArgs &a, const ChunkBufs &b, hipStream_t st) {
-    hipLaunchKernelGGL(k_pass1, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, b.bin_off, b.lists,
-                       b.R0, b.R1, b.R2, b.cmax, b.ray_A);
+// Flat form: one wave per quadrant (rounded up to a multiple of 8 for the XCD
+// remap).  Persistent form: 256 CUs x 16 waves taking quadrants from a counter.
+static inline unsigned composite_grid(const CompositeArgs &a) {
+    if (a.work) return 256u * 16u;
+    return (unsigned)(((a.total_tiles * 4) + 7) & ~7);
 }
 
-void launch_composite_pass2(const CompositeArgs &a, const ChunkBufs &b, bool stats, hipStream_t st) {
+void launch_composite_pass1(const CompositeArgs &a, hipStream_t st) {
+    if (a.work) launch_fill_u32(a.work, 0u, 1, st);
+    hipLaunchKernelGGL(k_pass1, dim3(composite_grid(a)), dim3(kWave), 0, st, a);
+}
+
+void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
+    if (a.work) launch_fill_u32(a.work, 0u, 1, st);
     if (stats)
-        hipLaunchKernelGGL(k_pass2<true>, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, b.bin_off,
-                           b.lists, b.R0, b.R1, b.R2, b.cmax, b.ray_A, b.counters);
+        hipLaunchKernelGGL(k_pass2<true>, dim3(composite_grid(a)), dim3(kWave), 0, st, a, counters);
     else
-        hipLaunchKernelGGL(k_pass2<false>, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, b.bin_off,
-                           b.lists, b.R0, b.R1, b.R2, b.cmax, b.ray_A, b.counters);
+        hipLaunchKernelGGL(k_pass2<false>, dim3(composite_grid(a)), dim3(kWave), 0, st, a, counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,17 +334,20 @@ void launch_composite_pass2(const CompositeArgs &a, const ChunkBufs &b, bool sta
 // |log T - log T_w| = |sum log(1 - rho_j) - log(1 - w_j rho_j)| at every
 // contributing retained pair (Assumption 1), on rays that stay valid.
 __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveArgs o,
-                                                     const uint32_t *__restrict__ cmax_bits,
-                                                     const uint64_t *__restrict__ bin_off,
-                                                     const uint32_t *__restrict__ lists,
-                                                     const float4 *__restrict__ R0, const float4 *__restrict__ R1,
-                                                     const float4 *__restrict__ R2,
                                                      uint64_t *__restrict__ counters) {
     __shared__ float4 geo[kWave], col[kWave];
+    const int nq = quad_count(a);
+    int iter = 0;
+    for (int qi = next_quad(a, iter); qi < nq; qi = next_quad(a, iter)) {
     WaveSetup w;
-    if (!setup_wave(a, bin_off, w)) return;
-    const bool scored = w.inside && ray_selected(a.ray_mask, w.ray_global);
-    const int64_t vbase = (int64_t)w.v * a.N;
+    if (!setup_quad(a, qi, w)) {
+        if (threadIdx.x == 0) {
+            const int64_t slot = (int64_t)qi * 3;
+            o.tile_sums[slot] = o.tile_sums[slot + 1] = o.tile_sums[slot + 2] = 0.0;
+        }
+        continue;
+    }
+    const bool scored = w.inside && ray_selected(w.S->ray_mask, w.ray_global);
     const bool has_w = o.weights != nullptr;
     float T = 1.0f, A = 0.0f, Ax = 0.0f, Tw = 1.0f, At = 0.0f, gap = 0.0f, gmax = 0.0f;
     bool bad = false;
@@ -323,15 +359,13 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     float stop_scale = 0.0f;
     if (o.wmax_bits) {
         const double wm = __longlong_as_double((long long)*o.wmax_bits);
-        stop_scale = (float)wm * __uint_as_float(cmax_bits[w.v]);
+        stop_scale = (float)wm * __uint_as_float(w.S->cmax[w.v - w.S->view0]);
     }
     bool done = !scored;
     for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
         if (__all(done)) break;
-        const int n = has_w ? stage_slice<2>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr,
-                                             o.weights)
-                            : stage_slice<0>(w, e0, lists, R0, R1, R2, vbase, geo, col, nullptr, nullptr, nullptr,
-                                             nullptr);
+        const int n = has_w ? stage_slice<2>(w, e0, geo, col, nullptr, nullptr, o.weights)
+                            : stage_slice<0>(w, e0, geo, col, nullptr, nullptr, nullptr);
         __syncthreads();
         for (int j = 0; j < n; ++j) {
             const float4 G = geo[j], Cc = col[j];
@@ -385,11 +419,12 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
         if (nb) atomicAdd((unsigned long long *)&counters[CNT_INVALID_PAIRS], (unsigned long long)nb);
         if (gm > 0.0f) atomicMax((unsigned long long *)&counters[CNT_GAMMA_BITS], (unsigned long long)__float_as_uint(gm));
     }
+    }
 }
 
-void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, const ChunkBufs &b, hipStream_t st) {
-    hipLaunchKernelGGL(k_objective, dim3(composite_grid(a.total_tiles)), dim3(kWave), 0, st, a, o, b.cmax,
-                       b.bin_off, b.lists, b.R0, b.R1, b.R2, b.counters);
+void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st) {
+    if (a.work) launch_fill_u32(a.work, 0u, 1, st);
+    hipLaunchKernelGGL(k_objective, dim3(composite_grid(a)), dim3(kWave), 0, st, a, o, counters);
 }
 
 // Largest value of a non-negative double array (as bits: monotone for x >= 0).

@@ -57,7 +57,6 @@ struct ChunkBufs {
     uint32_t *cmax;      // [Vc] largest query colour per view (float bits)
     uint32_t *bin_count; // [Vc*tiles_total ... ] per (tile, chunk) entry counts
     uint64_t *bin_off;   // exclusive scan of bin_count (+1 trailing total)
-    uint32_t *bin_fill;  // scatter cursors (zeroed)
     uint32_t *lists;     // [D] entries
     float *ray_A;        // [rays in chunk] pass-1 render
     uint8_t *tile_active; // [tiles in chunk] tiles holding a selected ray (null: all)
@@ -83,7 +82,9 @@ void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int 
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                       const uint32_t *xr, const uint32_t *yr, hipStream_t st);
 void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                        const uint32_t *xr, const uint32_t *yr, hipStream_t st);
+                        const uint32_t *xr, const uint32_t *yr, uint64_t cap, hipStream_t st);
+void launch_list_guard(uint64_t *bin_off, int64_t nbins, uint64_t cap, uint32_t *over, uint32_t *flag,
+                       hipStream_t st);
 // big: work list of segments with more than 64 entries ([0] = count, then (start, n) pairs)
 void launch_segment_sort(int total_tiles, int nchunks, const ChunkBufs &b, const uint32_t *sorted_g,
                          const int32_t *tile_view, int64_t N, uint64_t *big, int64_t big_cap, hipStream_t st);
@@ -92,20 +93,37 @@ void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uin
 void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp, hipStream_t st);
 int64_t scan_tmp_elems(int64_t n);
 
-struct CompositeArgs {
-    const ViewDev *views;
-    const int32_t *tile_view;    // [total_tiles] view of each tile in the chunk
-    int32_t total_tiles;
-    int32_t nchunks;
+// One scene of a compositing launch (a launch may cover several scenes).
+struct SceneSlot {
+    const float4 *R0, *R1, *R2;   // records [views of the scene][N]
+    const uint32_t *lists;        // tile lists; bin_off values index this array
+    const uint64_t *bin_off;      // [scene tiles * nchunks + 1]
+    const uint32_t *cmax;         // [views of the scene] largest query colour (float bits)
+    float *ray_A;                 // pass-1 render of the scene's rays (indexed by ViewDev::ray_local)
+    uint32_t *sens_bits;          // sensitivities (float bits, atomicMax) [N]
+    const uint32_t *ray_mask;     // bitset over the scene's rays (ViewDev::ray_base numbering) or null
     int64_t N;
+    int32_t nchunks;
+    int32_t view0;                // first view of the scene in the launch's view table
+    int32_t tile0;                // first tile of the scene in the launch's tile table
+    int32_t pad;
+};
+
+struct CompositeArgs {
+    const ViewDev *views;        // view table of the launch (tile_base is scene-local)
+    const int32_t *tile_view;    // [total_tiles] view of each tile
+    const int32_t *tile_scene;   // [total_tiles] scene slot of each tile
+    const SceneSlot *slots;
+    int32_t total_tiles;
+    int32_t query_mode;
     float r2_log2;               // -0.5 log2(e) r^2  (cut on the exp2 argument)
     float share_floor;
-    const uint32_t *ray_mask;    // global bitset or null
-    uint32_t *sens_bits;         // pass 2: float bits, atomicMax
-    int query_mode;
+    uint32_t *work;              // persistent form: work counter (zeroed before the launch); null = one wave per quadrant
+    int32_t xcd_remap;           // 1: give each XCD a contiguous range of quadrants
+    int32_t pad;
 };
-void launch_composite_pass1(const CompositeArgs &a, const ChunkBufs &b, hipStream_t st);
-void launch_composite_pass2(const CompositeArgs &a, const ChunkBufs &b, bool stats, hipStream_t st);
+void launch_composite_pass1(const CompositeArgs &a, hipStream_t st);
+void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st);
 
 struct ObjectiveArgs {
     const double *weights;
@@ -116,7 +134,7 @@ struct ObjectiveArgs {
     float stop_rel;             // stop a ray once T c_max w_max < stop_rel A
 };
 void launch_max_f64(const double *x, int64_t n, uint64_t *out_bits, hipStream_t st);
-void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, const ChunkBufs &b, hipStream_t st);
+void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st);
 void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
                       hipStream_t st);
 
@@ -141,6 +159,7 @@ void feature_stats(const float *feat, int64_t n, float *norm, hipStream_t st);
 // Small utilities
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+void launch_copy_u64(uint64_t *dst, const uint64_t *src, int64_t n, hipStream_t st);
 void launch_sum_f32_to_f64(const float *x, int64_t n, double *out, double *block_tmp, hipStream_t st);
 
 }  // namespace gs

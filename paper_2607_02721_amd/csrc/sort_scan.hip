@@ -252,8 +252,9 @@ void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uin
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp, nblk);
     hipLaunchKernelGGL((k_scan_apply<uint32_t, false>), dim3((unsigned)nblk), dim3(kScanThreads), 0, st, in, n,
                        tmp, out);
-    // trailing total
-    hipMemcpyAsync(out + n, tmp + nblk, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+    // trailing total (a kernel rather than a copy, so that the sequence can be
+    // captured into a graph)
+    launch_copy_u64(out + n, tmp + nblk, 1, st);
 }
 
 void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t st) {
@@ -272,6 +273,14 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
 __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+__global__ void k_copy_u64(uint64_t *dst, const uint64_t *src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+void launch_copy_u64(uint64_t *dst, const uint64_t *src, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
 }
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return;

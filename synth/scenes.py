@@ -277,6 +277,28 @@ def make_config(name: str):
     raise KeyError(name)
 
 
+def make_batch_specs(n_scenes: int = 16, seed: int = 2, n_lo: int = 50_000, n_hi: int = 2_000_000,
+                     v_lo: int = 24, v_hi: int = 200,
+                     resolutions=((640, 360), (1280, 720), (1920, 1080))):
+    """Sizes of a batch of uneven scenes: Gaussian counts log-uniform in
+    [n_lo, n_hi], view counts uniform in [v_lo, v_hi]; each view's resolution
+    is drawn from `resolutions`.  Returns [(n, n_views, scene_seed, view_seed)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_scenes):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        nv = int(rng.integers(v_lo, v_hi + 1))
+        out.append((n, nv, 10_000 + 2 * k + seed * 1000, 10_001 + 2 * k + seed * 1000))
+    return out
+
+
+def make_batch(specs, resolutions=((640, 360), (1280, 720), (1920, 1080))):
+    """(scene, views) pairs for make_batch_specs output (cluster scenes, SH
+    degree 3, jittered orbits at mixed resolutions)."""
+    return [(make_cluster_scene(n, ss, 3), make_orbit_views(nv, vs, resolutions=resolutions))
+            for n, nv, ss, vs in specs]
+
+
 def make_explicit_scene(means, log_scales, quats, opacity, colours=None, sh=None,
                         sh_degree: int = 0) -> Scene:
     """Scene from explicit per-Gaussian rows: means [n,3], log_scales [n,3],

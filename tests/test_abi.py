@@ -113,3 +113,30 @@ def test_default_params(lib):
     p = _lib.default_params()
     assert p.footprint_sigma == 3.0 and abs(p.dilation - 0.3) < 1e-7 and abs(p.z_near - 0.2) < 1e-7
     assert abs(p.share_floor - 1e-12) < 1e-18 and p.query_mode == 0 and p.ray_mask is None
+
+
+def test_plan_argument_errors(lib):
+    from paper_2607_02721_amd import _lib
+    sc, vw, p = _scene(), _views(), _lib.default_params()
+    scenes = (_lib.Scene * 1)(sc)
+    views = (_lib.Views * 1)(vw.c)
+    h = C.c_void_p(0x1234)
+    f = lib.gs_plan_create
+    assert f(scenes, views, 0, C.byref(p), C.byref(h), None) == 1 and h.value is None
+    assert f(scenes, views, 1, C.byref(p), None, None) == 1
+    assert f(None, views, 1, C.byref(p), C.byref(h), None) == 1
+    p.ray_mask = 0x1000
+    assert f(scenes, views, 1, C.byref(p), C.byref(h), None) == 2      # no ray masks in plans
+    p = _lib.default_params()
+    p.flags = 1
+    assert f(scenes, views, 1, C.byref(p), C.byref(h), None) == 2      # no pair counting in plans
+    p = _lib.default_params()
+    bad = (_lib.Scene * 1)(_scene(n=0))
+    assert f(bad, views, 1, C.byref(p), C.byref(h), None) == 1
+    cfg = _lib.PlanConfig(0, 1)
+    assert lib.gs_plan_set_config(None, C.byref(cfg)) == 1
+    assert lib.gs_plan_sensitivity(None, None, None) == 1
+    assert lib.gs_plan_tune(None, None, 3, None, None, None) == 1
+    assert lib.gs_plan_get_info(None, None) == 1
+    assert lib.gs_plan_status(None, None) == 1
+    lib.gs_plan_destroy(None)

@@ -1,0 +1,184 @@
+"""Batched plans (several scenes in one captured sequence) against the
+per-scene entry point: every scene's sensitivities must be bit-identical to
+gs_sensitivity with the same parameters, for every launch shape, on graph
+replays, after in-place attribute updates, and across scene groups.  (The
+per-scene entry point is itself held to the FP64 oracle by the parity tests,
+so bit-identity carries that parity over.)  The list-capacity guard is
+exercised by growing the footprints in place."""
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_02721_amd as gs
+    gs.load()
+    return gs
+
+
+SPECS = [  # (n, seed, sh degree, views, width, height)
+    (20_000, 11, 3, 6, 160, 96),
+    (7_001, 12, 1, 3, 200, 136),
+    (33_333, 13, 3, 9, 128, 128),
+]
+
+
+def _batch(gs, specs=SPECS):
+    out = []
+    for n, seed, deg, nv, W, H in specs:
+        sc = synth.make_cluster_scene(n, seed, deg)
+        vw = synth.make_orbit_views(nv, seed + 100, W, H)
+        out.append((gs.DeviceScene.from_scene(sc), vw))
+    return out
+
+
+def _reference(gs, batch):
+    return [gs.sensitivity(d, vw)[0].clone() for d, vw in batch]
+
+
+def _same(a, b):
+    import torch
+    return torch.equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def batch(gs):
+    return _batch(gs)
+
+
+@pytest.fixture(scope="module")
+def ref(gs, batch):
+    return _reference(gs, batch)
+
+
+def test_plan_matches_per_scene_calls(gs, batch, ref):
+    import torch
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    outs = plan.run()
+    torch.cuda.synchronize()
+    info = plan.info()
+    print("[plan]", info)
+    assert info["n_scenes"] == 3 and info["n_groups"] == 1
+    plan.status()
+    for k, (o, r) in enumerate(zip(outs, ref)):
+        assert float(r.max()) > 0.0
+        assert _same(o, r), (k, float((o - r).abs().max()))
+    plan.close()
+
+
+def test_graph_replays_equal_eager(gs, batch, ref):
+    """Each replay, with unrelated eager work and synchronisations between
+    replays, reproduces the per-scene results; new output tensors re-capture."""
+    import torch
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    for rep in range(4):
+        outs = plan.run()
+        x = torch.randn(1 << 20, device="cuda")
+        y = (x * 2).sum()            # eager work between replays
+        torch.cuda.synchronize()
+        assert y.isfinite()
+        for k, (o, r) in enumerate(zip(outs, ref)):
+            assert _same(o, r), (rep, k)
+    assert plan.info()["graph_captured"] == 1
+    fresh = [torch.full((d.n,), -1.0, device="cuda") for d, _ in batch]
+    plan.run(fresh)
+    torch.cuda.synchronize()
+    for o, r in zip(fresh, ref):
+        assert _same(o, r)
+    plan.status()
+    plan.close()
+
+
+@pytest.mark.parametrize("persistent,xcd", [(0, 1), (0, 0), (1, 0), (1, 1)])
+def test_launch_shapes_agree(gs, batch, ref, persistent, xcd):
+    import torch
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    plan.set_config(persistent, xcd)
+    outs = plan.run()
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert _same(o, r)
+    plan.close()
+
+
+def test_tuner_picks_a_shape(gs, batch, ref):
+    import torch
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    best, ms = plan.tune(reps=2)
+    print("[tune]", best, ms)
+    assert best in ({"persistent": 0, "xcd_remap": 1}, {"persistent": 0, "xcd_remap": 0},
+                    {"persistent": 1, "xcd_remap": 0})
+    assert all(t > 0 for t in ms)
+    info = plan.info()
+    assert (info["persistent"], info["xcd_remap"]) == (best["persistent"], best["xcd_remap"])
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert _same(o, r)
+    plan.close()
+
+
+def test_in_place_attribute_update(gs):
+    """Opacities change in place (same addresses, same footprints): the next
+    run sees the new values."""
+    import torch
+    batch = _batch(gs, SPECS[:2])
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    plan.run()
+    batch[0][0].opacity.mul_(0.5)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    ref = _reference(gs, batch)
+    for o, r in zip(outs, ref):
+        assert _same(o, r)
+    plan.status()
+    plan.close()
+
+
+def test_capacity_guard(gs):
+    """Larger footprints than at creation overflow the list capacity of one
+    scene: its output is zero, the other scene is unaffected, and the plan's
+    status reports it."""
+    import torch
+    batch = _batch(gs, SPECS[:2])
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    plan.run()
+    torch.cuda.synchronize()
+    plan.status()
+    batch[0][0].log_scale.add_(1.0)     # e-times larger axes: many more tile entries
+    outs = plan.run()
+    torch.cuda.synchronize()
+    with pytest.raises(gs.GsError) as e:
+        plan.status()
+    assert e.value.status == 5
+    assert float(outs[0].abs().max()) == 0.0
+    ref1 = gs.sensitivity(*batch[1])[0]
+    assert _same(outs[1], ref1)
+    plan.close()
+
+
+def test_scenes_split_into_groups(gs, monkeypatch):
+    """With a small scratch budget the plan packs the scenes into several
+    groups (one compositing launch each); results are unchanged."""
+    import torch
+    monkeypatch.setenv("GS_SCRATCH_GB", "0.25")
+    specs = [(100_000, 21, 3, 12, 96, 64), (100_000, 22, 3, 12, 96, 64), (5_000, 23, 0, 2, 64, 64)]
+    batch = _batch(gs, specs)
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    info = plan.info()
+    print("[groups]", info)
+    assert info["n_groups"] >= 2
+    outs = plan.run()
+    torch.cuda.synchronize()
+    monkeypatch.delenv("GS_SCRATCH_GB")
+    ref = _reference(gs, batch)
+    for o, r in zip(outs, ref):
+        assert _same(o, r)
+    plan.close()
