@@ -57,6 +57,57 @@ def cpu_baseline(scene, views, n_views_total):
             "sample_pairs": r["pairs"]}
 
 
+def batch_leg(gs, synth, torch, args):
+    """16 scenes of uneven sizes (50k-2M Gaussians, log-uniform; 24-200 views
+    each at 640x360 / 1280x720 / 1920x1080) as one plan: capacities fixed at
+    creation, the launch shape picked by the plan's tuner, each step one HIP
+    graph replay.  The same scenes through one gs_sensitivity call each are
+    timed beside it."""
+    specs = synth.make_batch_specs(16, 2)
+    log(f"batch: generating {len(specs)} scenes ...")
+    batch = synth.make_batch(specs)
+    dev = [gs.DeviceScene.from_scene(sc) for sc, _ in batch]
+    views = [vw for _, vw in batch]
+    del batch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = gs.Plan(dev, views)
+    t_create = time.perf_counter() - t0
+    best, tune_ms = plan.tune(reps=1)
+    info = plan.info()
+    log(f"batch: plan {info}, tuner {best} {tune_ms}")
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs = plan.run()
+    torch.cuda.synchronize()
+    ms_plan = (time.perf_counter() - t0) * 1e3 / args.steps
+    plan.status()
+    plan_out = [o.clone() for o in outs]
+    plan.close()
+    del plan
+    t0 = time.perf_counter()
+    same = True
+    for d, vw, o in zip(dev, views, plan_out):
+        s_, _ = gs.sensitivity(d, vw)
+        same = same and bool(torch.equal(s_, o))
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3
+    gv = sum(n * nv for n, nv, _, _ in specs)
+    rays = sum(int(np.sum(vw.size[:, 0].astype(np.int64) * vw.size[:, 1])) for vw in views)
+    log(f"batch: plan {ms_plan:.1f} ms/step, per-scene calls {ms_seq:.1f} ms, identical={same}")
+    return {"workload": "16 scenes, 50k-2M Gaussians (log-uniform), 24-200 views each at "
+                        "640x360/1280x720/1920x1080 mixed",
+            "scenes": [{"gaussians": n, "views": nv} for n, nv, _, _ in specs],
+            "ms_per_step": ms_plan, "ms_per_scene_calls": ms_seq, "identical_to_per_scene": same,
+            "gaussian_views_per_s": gv / (ms_plan * 1e-3), "rays": rays,
+            "tuner": {"best": best, "ms": dict(zip(["flat_xcd", "flat", "persistent"], tune_ms))},
+            "groups": info["n_groups"], "device_bytes": info["device_bytes"],
+            "graph": info["graph_captured"], "create_s": t_create}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +117,7 @@ def main():
     ap.add_argument("--views", type=int, default=100)
     ap.add_argument("--train-scenes", type=int, default=8)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -193,6 +245,10 @@ def main():
             scan[name][str(mm)] = gs.coreset_error(ob["per_view"])
     log(f"E vs m: {json.dumps(scan)}")
 
+    batching = None
+    if not args.no_batch:
+        batching = batch_leg(gs, synth, torch, args)
+
     log("counting pairs (untimed) ...")
     _, cst, _ = step(stats=True, count_pairs=True)
     live = cst["n_live_pairs"]
@@ -226,6 +282,7 @@ def main():
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],
                   "entries": cst["n_entries"], "projected": cst["n_projected"]},
         "live_pairs_per_s": live / (ms * 1e-3),
+        "batching": batching,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -355,21 +355,19 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     // after 4 radix passes the sorted pairs are back in (key0, val0); key1/val1 are free
     uint32_t *xr = b.key1, *yr = b.val1;
     launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
-    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, st);
+    int max_tiles = 1;
+    for (const ViewDev &V : hv) max_tiles = std::max(max_tiles, V.tiles_x * V.tiles_y);
+    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, max_tiles, st);
     scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, nbins, r.scan_tmp, st);
     HIP_TRY(hipGetLastError());
     uint64_t total = 0;
     HIP_TRY(hipMemcpyAsync(&total, b.bin_off + nbins, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     r.n_entries = (int64_t)total;
-    // lists, then the work list of segments longer than 64 entries (at most total/65 of them)
-    const int64_t big_cap = (int64_t)(total / 65) + 1;
     const size_t list_bytes = ((std::max<size_t>(total, 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
-    HIP_TRY(arena_reserve(g_lists[dev], list_bytes + sizeof(uint64_t) * (1 + 2 * (size_t)big_cap)));
+    HIP_TRY(arena_reserve(g_lists[dev], list_bytes));
     b.lists = (uint32_t *)g_lists[dev].base;
-    uint64_t *big = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
-    launch_bin_scatter(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, (uint64_t)total, st);
-    launch_segment_sort(c.total_tiles, S.nchunks, b, r.sorted_g, r.tile_view, N, big, big_cap, st);
+    launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tiles, (uint64_t)total, st);
     HIP_TRY(hipGetLastError());
     // the compositing launch sees this chunk as a single scene slot
     r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.bin_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
@@ -772,11 +770,11 @@ struct PlanScene {
     std::vector<int32_t> htv;     // tile -> scene-local view
     ChunkBufs b{};
     ViewDev *views_dev = nullptr; // slice of the group's view table
-    int32_t *tile_view_local = nullptr;
     uint32_t *sorted_g = nullptr, *xr = nullptr, *yr = nullptr;
-    uint64_t *scan_tmp = nullptr, *big = nullptr;
+    uint64_t *scan_tmp = nullptr;
     uint32_t *over = nullptr;
-    int64_t nbins = 0, big_cap = 0;
+    int64_t nbins = 0;
+    int max_tiles = 1;
     uint64_t cap = 0;
     int group = 0, view0 = 0, tile0 = 0;
 };
@@ -825,7 +823,6 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     add(sizeof(uint64_t) * scan_tmp_elems(ps.nbins + 1));
     add(sizeof(float) * (size_t)ps.c.rays);
     add(sizeof(uint64_t) * CNT_SLOTS);
-    add(sizeof(int32_t) * ps.c.total_tiles);
     add(256);
     return b;
 }
@@ -849,7 +846,6 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     ps.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(ps.nbins + 1));
     b.ray_A = cv.take<float>(ps.c.rays);
     b.counters = cv.take<uint64_t>(CNT_SLOTS);
-    ps.tile_view_local = cv.take<int32_t>(ps.c.total_tiles);
     ps.over = cv.take<uint32_t>(64);
     b.tile_active = nullptr;
 }
@@ -870,7 +866,7 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ps.xr = b.key1;
     ps.yr = b.val1;
     launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);
-    launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, st);
+    launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, ps.max_tiles, st);
     scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, ps.nbins, ps.scan_tmp, st);
 }
 
@@ -881,9 +877,8 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
             PlanScene &ps = P->scenes[si];
             enqueue_front(P, ps, st);
             launch_list_guard(ps.b.bin_off, ps.nbins, ps.cap, ps.over, P->flag, st);
-            launch_bin_scatter(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.cap, st);
-            launch_segment_sort(ps.c.total_tiles, ps.S.nchunks, ps.b, ps.sorted_g, ps.tile_view_local, ps.S.N,
-                                ps.big, ps.big_cap, st);
+            launch_bin_emit(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.sorted_g,
+                            ps.max_tiles, ps.cap, st);
             launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
         }
         CompositeArgs a{};
@@ -971,8 +966,6 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
                 gtv.push_back(ps.view0 + ps.htv[t]);
                 gts.push_back((int32_t)k);
             }
-            HIP_TRY(hipMemcpyAsync(ps.tile_view_local, ps.htv.data(), sizeof(int32_t) * ps.c.total_tiles,
-                                   hipMemcpyHostToDevice, st));
         }
         HIP_TRY(hipMemcpyAsync(G.views, gv.data(), sizeof(ViewDev) * gv.size(), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(G.tile_view, gtv.data(), sizeof(int32_t) * gtv.size(), hipMemcpyHostToDevice, st));
@@ -989,9 +982,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         for (size_t k = 0; k < G.scenes.size(); ++k) {
             PlanScene &ps = P->scenes[G.scenes[k]];
             ps.cap = totals[k] + totals[k] / 64 + 1024;
-            ps.big_cap = (int64_t)(ps.cap / 65) + 1;
-            lb += ((ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255) +
-                  ((sizeof(uint64_t) * (1 + 2 * (size_t)ps.big_cap) + 255) & ~(size_t)255);
+            lb += ((ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255);
         }
         if (hipMalloc(&G.lists, lb + 4096) != hipSuccess) {
             (void)hipGetLastError();
@@ -1002,7 +993,6 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         for (int si : G.scenes) {
             PlanScene &ps = P->scenes[si];
             ps.b.lists = lc.take<uint32_t>(ps.cap);
-            ps.big = lc.take<uint64_t>(1 + 2 * (size_t)ps.big_cap);
         }
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -1064,6 +1054,7 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
             V.ray_base = ps.S.ray_base[k];
             V.ray_local = ps.S.ray_base[k];
             V.tile_base = tb;
+            ps.max_tiles = std::max(ps.max_tiles, V.tiles_x * V.tiles_y);
             for (int t = 0; t < V.tiles_x * V.tiles_y; ++t) ps.htv[tb + t] = k;
             tb += V.tiles_x * V.tiles_y;
         }

@@ -23,6 +23,8 @@
 // counter until none are left.
 #include "gs_internal.hpp"
 
+#include <algorithm>
+
 namespace gs {
 
 constexpr int kWave = 64;
@@ -48,8 +50,14 @@ struct WaveSetup {
     uint64_t start, end;
     uint32_t qbit;
     int W;
-    const SceneSlot *S;
     int64_t vbase;
+    // the scene slot's fields, read once per quadrant
+    const float4 *R0, *R1, *R2;
+    const uint32_t *lists;
+    uint32_t *sens_bits;
+    const uint32_t *ray_mask;
+    float *ray_A;
+    float cmax;
 };
 
 __device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles * 4; }
@@ -59,9 +67,9 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.gt = logical >> 2;
     w.quad = logical & 3;
     w.v = a.tile_view[w.gt];
-    w.S = &a.slots[a.tile_scene[w.gt]];
+    const SceneSlot &S = a.slots[a.tile_scene[w.gt]];
     const ViewDev &V = a.views[w.v];
-    const int tl = w.gt - w.S->tile0 - V.tile_base;
+    const int tl = w.gt - S.tile0 - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
     const int qx0 = tx * kTile + (w.quad & 1) * kQuad;
     const int qy0 = ty * kTile + (w.quad >> 1) * kQuad;
@@ -77,19 +85,30 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.W = V.W;
     w.ray_local = V.ray_local + (int64_t)w.py * V.W + w.px;
     w.ray_global = V.ray_base + (int64_t)w.py * V.W + w.px;
-    const int64_t st = (int64_t)(w.gt - w.S->tile0) * w.S->nchunks;
-    w.start = w.S->bin_off[st];
-    w.end = w.S->bin_off[st + w.S->nchunks];
+    const int64_t st = (int64_t)(w.gt - S.tile0) * S.nchunks;
+    w.start = S.bin_off[st];
+    w.end = S.bin_off[st + S.nchunks];
     w.qbit = 1u << (28 + w.quad);
-    w.vbase = (int64_t)(w.v - w.S->view0) * w.S->N;
+    w.vbase = (int64_t)(w.v - S.view0) * S.N;
+    w.R0 = S.R0;
+    w.R1 = S.R1;
+    w.R2 = S.R2;
+    w.lists = S.lists;
+    w.sens_bits = S.sens_bits;
+    w.ray_mask = S.ray_mask;
+    w.ray_A = S.ray_A;
+    w.cmax = __uint_as_float(S.cmax[w.v - S.view0]);
     return true;
 }
 
 // Next quadrant for this wave: the block's own (remapped) index in the flat
-// form, or the next item of the work counter in the persistent form.
+// form, or the next item of the work counter in the persistent form.  The
+// form is a template parameter so that the flat kernels keep every
+// per-quadrant value in scalar registers without a loop around them.
+template <bool kPersistent>
 __device__ __forceinline__ int next_quad(const CompositeArgs &a, int &iter) {
     const int nq = quad_count(a);
-    if (a.work == nullptr) {
+    if (!kPersistent) {
         if (iter++) return nq;
         if (!a.xcd_remap) return blockIdx.x;
         const int padded = (nq + 7) & ~7;
@@ -97,7 +116,8 @@ __device__ __forceinline__ int next_quad(const CompositeArgs &a, int &iter) {
     }
     int q = 0;
     if (threadIdx.x == 0) q = (int)atomicAdd(a.work, 1u);
-    return __shfl(q, 0);
+    // lane 0's value, as a wave-uniform (scalar) quantity
+    return __builtin_amdgcn_readfirstlane(q);
 }
 
 __device__ __forceinline__ bool ray_selected(const uint32_t *mask, int64_t ray) {
@@ -112,10 +132,10 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
                                            uint32_t *sid, float *sold, const double *__restrict__ weights) {
     const int lane = threadIdx.x;
     const uint64_t e = e0 + lane;
-    const uint32_t raw = e < w.end ? w.S->lists[e] : 0u;
-    const float4 *__restrict__ R0 = w.S->R0;
-    const float4 *__restrict__ R1 = w.S->R1;
-    const float4 *__restrict__ R2 = w.S->R2;
+    const uint32_t raw = e < w.end ? w.lists[e] : 0u;
+    const float4 *__restrict__ R0 = w.R0;
+    const float4 *__restrict__ R1 = w.R1;
+    const float4 *__restrict__ R2 = w.R2;
     const int64_t vbase = w.vbase;
     const bool touch = (raw & w.qbit) != 0u;
     const uint64_t bal = __ballot(touch);
@@ -132,7 +152,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         float extra = 0.0f;
         if (kExtra == 1) {
             sid[slot] = g;
-            sold[slot] = __uint_as_float(w.S->sens_bits[g]);
+            sold[slot] = __uint_as_float(w.sens_bits[g]);
         }
         if (kExtra == 2) extra = (float)weights[g];
         col[slot] = make_float4(r1.z, r1.w, cb, extra);
@@ -154,15 +174,16 @@ __device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, flo
     return in_fp ? Cc.y * E : 0.0f;
 }
 
+template <bool kPersistent>
 __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
     __shared__ float4 geo[kWave], col[kWave];
     const int nq = quad_count(a);
     int iter = 0;
-    for (int qi = next_quad(a, iter); qi < nq; qi = next_quad(a, iter)) {
+    for (int qi = next_quad<kPersistent>(a, iter); qi < nq; qi = next_quad<kPersistent>(a, iter)) {
         WaveSetup w;
         if (!setup_quad(a, qi, w)) continue;
-        const bool scored = w.inside && ray_selected(w.S->ray_mask, w.ray_global);
-        const float cmax = __uint_as_float(w.S->cmax[w.v - w.S->view0]);
+        const bool scored = w.inside && ray_selected(w.ray_mask, w.ray_global);
+        const float cmax = w.cmax;
         float T = 1.0f, A = 0.0f;
         bool done = !scored;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
@@ -180,7 +201,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
             done = done || (T * cmax < a.share_floor * A);
             __syncthreads();
         }
-        if (w.inside) w.S->ray_A[w.ray_local] = scored ? A : 0.0f;
+        if (w.inside) w.ray_A[w.ray_local] = scored ? A : 0.0f;
     }
 }
 
@@ -231,7 +252,7 @@ __device__ __forceinline__ float wave_transpose_max32(float (&v)[32]) {
     return dpp_max<0xB1>(v[0]);
 }
 
-template <bool kStats>
+template <bool kStats, bool kPersistent>
 __global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     __shared__ float4 geo[kWave], col[kWave];
     __shared__ uint32_t sid[kWave];
@@ -240,14 +261,14 @@ __global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *_
     const int nq = quad_count(a);
     int iter = 0;
     uint64_t pin = 0, plive = 0, pos = 0, peval = 0;
-    for (int qi = next_quad(a, iter); qi < nq; qi = next_quad(a, iter)) {
+    for (int qi = next_quad<kPersistent>(a, iter); qi < nq; qi = next_quad<kPersistent>(a, iter)) {
         WaveSetup w;
         if (!setup_quad(a, qi, w)) continue;
-        const bool scored = w.inside && ray_selected(w.S->ray_mask, w.ray_global);
-        const float Af = scored ? w.S->ray_A[w.ray_local] : 0.0f;
+        const bool scored = w.inside && ray_selected(w.ray_mask, w.ray_global);
+        const float Af = scored ? w.ray_A[w.ray_local] : 0.0f;
         const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
-        const float cmax = __uint_as_float(w.S->cmax[w.v - w.S->view0]);
-        uint32_t *sens_bits = w.S->sens_bits;
+        const float cmax = w.cmax;
+        uint32_t *sens_bits = w.sens_bits;
         float T = 1.0f;
         bool done = invA == 0.0f;
         uint32_t n_in = 0, n_live = 0, n_eval = 0;
@@ -307,23 +328,48 @@ __global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *_
 }
 
 // Flat form: one wave per quadrant (rounded up to a multiple of 8 for the XCD
-// remap).  Persistent form: 256 CUs x 16 waves taking quadrants from a counter.
-static inline unsigned composite_grid(const CompositeArgs &a) {
-    if (a.work) return 256u * 16u;
-    return (unsigned)(((a.total_tiles * 4) + 7) & ~7);
+// remap).  Persistent form: as many waves as the chip holds at once for the
+// kernel (its occupancy times the CU count), taking quadrants from a counter.
+template <typename K>
+static unsigned resident_waves(K kernel) {
+    int dev = 0, cus = 256, per_cu = 8;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 256;
+        per_cu = 8;
+    }
+    return (unsigned)std::max(1, cus) * (unsigned)std::max(1, per_cu);
 }
 
+static inline unsigned flat_grid(const CompositeArgs &a) { return (unsigned)(((a.total_tiles * 4) + 7) & ~7); }
+
 void launch_composite_pass1(const CompositeArgs &a, hipStream_t st) {
-    if (a.work) launch_fill_u32(a.work, 0u, 1, st);
-    hipLaunchKernelGGL(k_pass1, dim3(composite_grid(a)), dim3(kWave), 0, st, a);
+    if (a.work) {
+        static const unsigned grid = resident_waves(k_pass1<true>);
+        launch_fill_u32(a.work, 0u, 1, st);
+        hipLaunchKernelGGL(k_pass1<true>, dim3(grid), dim3(kWave), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_pass1<false>, dim3(flat_grid(a)), dim3(kWave), 0, st, a);
+    }
 }
 
 void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
-    if (a.work) launch_fill_u32(a.work, 0u, 1, st);
-    if (stats)
-        hipLaunchKernelGGL(k_pass2<true>, dim3(composite_grid(a)), dim3(kWave), 0, st, a, counters);
-    else
-        hipLaunchKernelGGL(k_pass2<false>, dim3(composite_grid(a)), dim3(kWave), 0, st, a, counters);
+    if (a.work) {
+        launch_fill_u32(a.work, 0u, 1, st);
+        if (stats) {
+            static const unsigned grid = resident_waves(k_pass2<true, true>);
+            hipLaunchKernelGGL((k_pass2<true, true>), dim3(grid), dim3(kWave), 0, st, a, counters);
+        } else {
+            static const unsigned grid = resident_waves(k_pass2<false, true>);
+            hipLaunchKernelGGL((k_pass2<false, true>), dim3(grid), dim3(kWave), 0, st, a, counters);
+        }
+    } else if (stats) {
+        hipLaunchKernelGGL((k_pass2<true, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    } else {
+        hipLaunchKernelGGL((k_pass2<false, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +384,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     __shared__ float4 geo[kWave], col[kWave];
     const int nq = quad_count(a);
     int iter = 0;
-    for (int qi = next_quad(a, iter); qi < nq; qi = next_quad(a, iter)) {
+    for (int qi = next_quad<false>(a, iter); qi < nq; qi = next_quad<false>(a, iter)) {
     WaveSetup w;
     if (!setup_quad(a, qi, w)) {
         if (threadIdx.x == 0) {
@@ -347,7 +393,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
         }
         continue;
     }
-    const bool scored = w.inside && ray_selected(w.S->ray_mask, w.ray_global);
+    const bool scored = w.inside && ray_selected(w.ray_mask, w.ray_global);
     const bool has_w = o.weights != nullptr;
     float T = 1.0f, A = 0.0f, Ax = 0.0f, Tw = 1.0f, At = 0.0f, gap = 0.0f, gmax = 0.0f;
     bool bad = false;
@@ -359,7 +405,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     float stop_scale = 0.0f;
     if (o.wmax_bits) {
         const double wm = __longlong_as_double((long long)*o.wmax_bits);
-        stop_scale = (float)wm * __uint_as_float(w.S->cmax[w.v - w.S->view0]);
+        stop_scale = (float)wm * w.cmax;
     }
     bool done = !scored;
     for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
@@ -422,9 +468,9 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     }
 }
 
+// Always the flat form (a.work is ignored).
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st) {
-    if (a.work) launch_fill_u32(a.work, 0u, 1, st);
-    hipLaunchKernelGGL(k_objective, dim3(composite_grid(a)), dim3(kWave), 0, st, a, o, counters);
+    hipLaunchKernelGGL(k_objective, dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
 }
 
 // Largest value of a non-negative double array (as bits: monotone for x >= 0).

@@ -80,14 +80,14 @@ void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
                         uint8_t *active, hipStream_t st);
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                      const uint32_t *xr, const uint32_t *yr, hipStream_t st);
-void launch_bin_scatter(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                        const uint32_t *xr, const uint32_t *yr, uint64_t cap, hipStream_t st);
+                      const uint32_t *xr, const uint32_t *yr, int max_tiles, hipStream_t st);
+// Writes every list entry (g | quadrant mask << 28) in its final, sorted
+// place; entries at list index >= cap are dropped.
+void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
+                     const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles, uint64_t cap,
+                     hipStream_t st);
 void launch_list_guard(uint64_t *bin_off, int64_t nbins, uint64_t cap, uint32_t *over, uint32_t *flag,
                        hipStream_t st);
-// big: work list of segments with more than 64 entries ([0] = count, then (start, n) pairs)
-void launch_segment_sort(int total_tiles, int nchunks, const ChunkBufs &b, const uint32_t *sorted_g,
-                         const int32_t *tile_view, int64_t N, uint64_t *big, int64_t big_cap, hipStream_t st);
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
                                hipStream_t st);
 void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp, hipStream_t st);
