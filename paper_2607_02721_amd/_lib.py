@@ -87,6 +87,12 @@ def load(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing; build it with paper_2607_02721_amd/build.py")
+        try:
+            # share torch's HIP runtime: loading it first makes the library's
+            # libamdhip64 dependency resolve to the copy torch already holds
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(path)
         P = C.c_void_p
         lib.gs_sensitivity.argtypes = [P, P, P, P, P, P]

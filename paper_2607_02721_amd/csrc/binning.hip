@@ -8,10 +8,11 @@
 //             entries per tile in LDS and stores them at (tile, chunk);
 //   2. scan:  exclusive prefix sum -> segment offsets (tile-major,
 //             chunk-minor), so a tile's list is its chunks' segments in order;
-//   3. emit:  one wave per chunk walks its positions in order and hands each
-//             position's tiles to the lanes; every tile's next slot comes
-//             from a wave-private LDS cursor, so each (tile, chunk) segment
-//             is written already sorted by p, as g | quadrant mask << 28.
+//   3. emit:  one wave per chunk expands its positions, in order, into
+//             (position, tile) items packed 64 to a batch; every tile's next
+//             slot comes from a wave-private LDS cursor (atomic add, executed
+//             in issue order), so each (tile, chunk) segment is written
+//             already sorted by p, as g | quadrant mask << 28.
 // Bit q of the mask says whether the Gaussian's pixel range touches 8x8
 // quadrant q of the 16x16 tile.
 #include "gs_internal.hpp"
@@ -79,15 +80,25 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
         bin_count[(int64_t)(V.tile_base + t) * nchunks + chunk] = cnt[t] & ~kOff;
 }
 
-// Ordered emission.  One wave per (chunk, view); lane j of a round holds
-// position base + j, and the wave then takes the round's positions one at a
-// time (in order), spreading that position's tile rectangle over its lanes.
-// Distinct lanes touch distinct tiles, and a later position reads a cursor
-// only after the earlier one's update (a wave's LDS operations complete in
-// order), so each segment receives its entries in increasing p.
+// Ordered emission.  One wave per (chunk, view) takes the chunk's positions
+// 64 at a time (a round; lane j holds position base + j) and expands them
+// into (position, tile) items in position order: a wave prefix sum of the
+// rectangle sizes numbers the items, and each 64-item batch finds every
+// item's owner by a binary search over the exclusive prefix.  A tile's slot
+// comes from an LDS atomic add on its cursor.  Items of one batch that hit
+// distinct tiles are independent; when two of them hit the same tile (an LDS
+// claim byte per tile detects it) the batch takes its owners one at a time
+// in order.  A wave's LDS operations execute in issue order, so later
+// positions always receive later slots and every (tile, chunk) segment is
+// filled in increasing p.
 constexpr int kEmitWave = 64;
-constexpr uint32_t kSkipTile = 0xFFFFFFFFu;
 
+template <bool kMasked>
+__device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
+    return !kMasked || ((act[t >> 5] >> (t & 31)) & 1u);
+}
+
+template <bool kMasked>
 __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restrict__ views, int64_t N, int nchunks,
                                                         const uint32_t *__restrict__ nvis,
                                                         const uint32_t *__restrict__ xr_in,
@@ -95,62 +106,111 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                                                         const uint32_t *__restrict__ sorted_g,
                                                         const uint64_t *__restrict__ bin_off,
                                                         uint32_t *__restrict__ lists,
-                                                        const uint8_t *__restrict__ active, uint64_t cap) {
-    // next free slot of (tile, this chunk), relative to the view's first entry
-    extern __shared__ uint32_t cur[];
+                                                        const uint8_t *__restrict__ active, uint64_t cap,
+                                                        int max_tiles) {
+    extern __shared__ uint32_t lds[];
+    uint32_t *cur = lds;                                 // [tiles] next slot, relative to the view's first entry
+    uint32_t *pre = cur + max_tiles;                     // [65] exclusive item prefix of the round (+ sentinel)
+    uint32_t *rx = pre + kEmitWave + 1;                  // [64] the round's pixel ranges and indices
+    uint32_t *ry = rx + kEmitWave;
+    uint32_t *rg = ry + kEmitWave;
+    uint8_t *claim = (uint8_t *)(rg + kEmitWave);        // [tiles] lane that last claimed the tile
+    uint32_t *act = (uint32_t *)(claim + ((max_tiles + 3) & ~3));  // [tiles / 32] (masked form only)
     const int v = blockIdx.y;
     const int lane = threadIdx.x;
     const ViewDev &V = views[v];
     const int64_t nv = nvis[v];
     const int64_t lo = (int64_t)blockIdx.x * kBinPositions;
     if (lo >= nv) return;
-    const int64_t hi = min(lo + (int64_t)kBinPositions, nv);
+    const int hi = (int)(min(lo + (int64_t)kBinPositions, nv) - lo);
     const int chunk = (int)(lo >> kSegBits);
     const int ntiles = V.tiles_x * V.tiles_y;
     const int tiles_x = V.tiles_x;
     const uint64_t vlist = bin_off[(int64_t)V.tile_base * nchunks];
     for (int t = lane; t < ntiles; t += kEmitWave)
-        cur[t] = (active && !active[V.tile_base + t])
-                     ? kSkipTile
-                     : (uint32_t)(bin_off[(int64_t)(V.tile_base + t) * nchunks + chunk] - vlist);
+        cur[t] = (uint32_t)(bin_off[(int64_t)(V.tile_base + t) * nchunks + chunk] - vlist);
+    if (kMasked) {
+        for (int w = lane; w < (ntiles + 31) / 32; w += kEmitWave) {
+            uint32_t bits = 0;
+            for (int b = 0; b < 32; ++b) {
+                const int t = 32 * w + b;
+                bits |= (t < ntiles && active[V.tile_base + t]) ? (1u << b) : 0u;
+            }
+            act[w] = bits;
+        }
+    }
+    if (lane == 0) pre[kEmitWave] = 0xFFFFFFFFu;
     __syncthreads();
     // entries at or past `room` would fall outside the list buffer
     const uint64_t room = cap > vlist ? cap - vlist : 0ull;
     uint32_t *__restrict__ vl = lists + vlist;
-    const int64_t o = (int64_t)v * N;
-    for (int64_t base = lo; base < hi; base += kEmitWave) {
-        const int64_t p = base + lane;
+    const int64_t o = (int64_t)v * N + lo;
+    for (int base = 0; base < hi; base += kEmitWave) {
+        const int p = base + lane;
         uint32_t ux = 0, uy = 0, ug = 0;
+        int k = 0;
         if (p < hi) {
             ux = xr_in[o + p];
             uy = yr_in[o + p];
             ug = sorted_g[o + p];
-        }
-        const int n = (int)min((int64_t)kEmitWave, hi - base);
-        for (int i = 0; i < n; ++i) {
-            const uint32_t rx = __builtin_amdgcn_readlane(ux, i);
-            const uint32_t ry = __builtin_amdgcn_readlane(uy, i);
-            const uint32_t g = __builtin_amdgcn_readlane(ug, i);
             int xl, xh, yl, yh;
-            unpack_range(__uint_as_float(rx), xl, xh);
-            unpack_range(__uint_as_float(ry), yl, yh);
+            unpack_range(__uint_as_float(ux), xl, xh);
+            unpack_range(__uint_as_float(uy), yl, yh);
+            k = ((xh >> 4) - (xl >> 4) + 1) * ((yh >> 4) - (yl >> 4) + 1);
+        }
+        // inclusive prefix sum of k over the wave
+        int incl = k;
+#pragma unroll
+        for (int d = 1; d < kEmitWave; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        const int K = __shfl(incl, kEmitWave - 1);
+        pre[lane] = (uint32_t)(incl - k);
+        rx[lane] = ux;
+        ry[lane] = uy;
+        rg[lane] = ug;
+        __syncthreads();
+        for (int i0 = 0; i0 < K; i0 += kEmitWave) {
+            const int i = i0 + lane;
+            const bool item = i < K;
+            // owner: the last lane whose exclusive prefix is <= i (pre[0] = 0)
+            int L = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (pre[L + st] <= (uint32_t)i) L += st;
+            const int j = i - (int)pre[L];
+            int xl, xh, yl, yh;
+            unpack_range(__uint_as_float(rx[L]), xl, xh);
+            unpack_range(__uint_as_float(ry[L]), yl, yh);
+            const uint32_t g = rg[L];
             const int tx0 = xl >> 4, ty0 = yl >> 4;
             const int nx = (xh >> 4) - tx0 + 1;
-            const int k = nx * ((yh >> 4) - ty0 + 1);
-            // j / nx as floor((j + 1/2) * fl(1/nx)): exact for j < nx * ny with
-            // nx * ny <= 8160 (checked exhaustively on the host)
-            const float rnx = 1.0f / (float)nx;
-            for (int j = lane; j < k; j += kEmitWave) {
-                const int dy = (int)(((float)j + 0.5f) * rnx);
-                const int dx = j - dy * nx;
-                const int tx = tx0 + dx, ty = ty0 + dy;
-                const int t = ty * tiles_x + tx;
-                const uint32_t c = cur[t];
-                if (c != kSkipTile) {
-                    cur[t] = c + 1u;
-                    if ((uint64_t)c < room) vl[c] = g | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
+            // j / nx as floor((j + 1/2) r) with r within one ulp of 1/nx:
+            // exact for nx * ny <= 8160 (checked exhaustively on the host)
+            const int dy = (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
+            const int tx = tx0 + (j - dy * nx), ty = ty0 + dy;
+            const int t = item ? ty * tiles_x + tx : 0;
+            const bool on = item && tile_on<kMasked>(act, t);
+            if (on) claim[t] = (uint8_t)lane;
+            __syncthreads();
+            const bool clash = on && claim[t] != (uint8_t)lane;
+            uint32_t c = 0;
+            if (__ballot(clash) == 0ull) {
+                if (on) c = atomicAdd(&cur[t], 1u);
+            } else {
+                // owners in increasing order; one owner's tiles are distinct
+                uint64_t rem = __ballot(on);
+                while (rem) {
+                    const int first = __ffsll((long long)rem) - 1;
+                    const int owner = __shfl(L, first);
+                    const bool mine = on && L == owner;
+                    if (mine) c = atomicAdd(&cur[t], 1u);
+                    rem &= ~__ballot(mine);
                 }
             }
+            if (on && (uint64_t)c < room) vl[c] = g | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
+            __syncthreads();
         }
     }
 }
@@ -166,8 +226,16 @@ void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, c
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles, uint64_t cap,
                      hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
-    hipLaunchKernelGGL(k_bin_emit, dim3(nb, Vc), dim3(kEmitWave), (size_t)max_tiles * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap);
+    // cursors, prefix (+ sentinel), three round arrays, claim bytes, tile bitmap
+    const size_t lds = sizeof(uint32_t) * ((size_t)max_tiles + (kEmitWave + 1) + 3 * kEmitWave) +
+                       (((size_t)max_tiles + 3) & ~(size_t)3) +
+                       (b.tile_active ? sizeof(uint32_t) * ((size_t)max_tiles + 31) / 32 : 0);
+    if (b.tile_active)
+        hipLaunchKernelGGL(k_bin_emit<true>, dim3(nb, Vc), dim3(kEmitWave), lds, st, views_dev, N, nchunks, b.nvis,
+                           xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, max_tiles);
+    else
+        hipLaunchKernelGGL(k_bin_emit<false>, dim3(nb, Vc), dim3(kEmitWave), lds, st, views_dev, N, nchunks, b.nvis,
+                           xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, max_tiles);
 }
 
 // Capacity guard for lists sized in advance (plans): if the counted entries
