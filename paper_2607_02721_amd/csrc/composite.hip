@@ -124,11 +124,43 @@ __device__ __forceinline__ bool ray_selected(const uint32_t *mask, int64_t ray) 
     return mask == nullptr || ((mask[ray >> 5] >> (ray & 31)) & 1u);
 }
 
-// Stage the slice's entries that touch this quadrant; returns how many.
+// Can a pixel centre of the quadrant pass the footprint test P >= cut?
+// P = a' u^2 + g' dy^2 (a', g' < 0), u = dx + beta dy, with (dx, dy) the
+// centre minus the mean and centres at 0.5 ... 7.5 in quadrant coordinates.
+// The minimum of -P over the continuous square [0.5, 7.5]^2 bounds the
+// centres' values from below; it sits at the mean if the mean is inside,
+// else on an edge (a one-dimensional quadratic, clamped).  An entry is
+// dropped only when that minimum exceeds -cut by more than `err`, a bound
+// (with a wide safety factor) on the float32 rounding of this test and of
+// the per-pixel one, so a dropped entry contributes exactly nothing anyway:
+// pass 1, pass 2 and the objectives give bit-identical results either way.
+__device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float ap, float gp, float cut) {
+    const float A = -ap, G = -gp, C = -cut;
+    const float x0 = 0.5f - mx, x1 = 7.5f - mx, y0 = 0.5f - my, y1 = 7.5f - my;
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+    auto q = [&](float dx, float dy) {
+        const float u = fmaf(beta, dy, dx);
+        return (A * u) * u + (G * dy) * dy;
+    };
+    // edges dy = y0, y1: best dx = -beta dy
+    float best = fminf(q(fminf(fmaxf(-beta * y0, x0), x1), y0), q(fminf(fmaxf(-beta * y1, x0), x1), y1));
+    // edges dx = x0, x1: best dy = -A beta dx / (A beta^2 + G)
+    const float k = -(A * beta) * __builtin_amdgcn_rcpf(fmaf(A * beta, beta, G));
+    best = fminf(best, q(x0, fminf(fmaxf(k * x0, y0), y1)));
+    best = fminf(best, q(x1, fminf(fmaxf(k * x1, y0), y1)));
+    const float S = fabsf(mx) + fabsf(my) + 16.0f;
+    const float err = 3.814697265625e-6f /* 2^-18 */ * S *
+                          ((1.0f + fabsf(beta)) * sqrtf(A * C) + sqrtf(G * C)) +
+                      1e-4f * C;
+    return best <= C + err;
+}
+
+// Stage the slice's entries whose footprint reaches this quadrant (pixel
+// range bit, then the exact test above); returns how many.
 // geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
 // col = (g', alpha, cbar, extra).
 template <int kExtra>  // 0: none, 1: s_old + index, 2: weight
-__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float4 *geo, float4 *col,
+__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
                                            uint32_t *sid, float *sold, const double *__restrict__ weights) {
     const int lane = threadIdx.x;
     const uint64_t e = e0 + lane;
@@ -137,17 +169,22 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
     const float4 *__restrict__ R1 = w.R1;
     const float4 *__restrict__ R2 = w.R2;
     const int64_t vbase = w.vbase;
-    const bool touch = (raw & w.qbit) != 0u;
+    bool touch = (raw & w.qbit) != 0u;
+    const uint32_t g = raw & kIndexMask;
+    const int64_t o = vbase + g;
+    float4 r1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float mx = 0.0f, my = 0.0f;
+    if (touch) {
+        const float4 r0 = R0[o];
+        r1 = R1[o];
+        mx = (r0.x - w.qx0) + r0.z;
+        my = (r0.y - w.qy0) + r0.w;
+        touch = quad_hit(mx, my, r1.x, r1.y, r1.z, cut);
+    }
     const uint64_t bal = __ballot(touch);
     if (touch) {
         const int slot = __popcll(bal & lanemask_lt64());
-        const uint32_t g = raw & kIndexMask;
-        const int64_t o = vbase + g;
-        const float4 r0 = R0[o];
-        const float4 r1 = R1[o];
         const float cb = R2[o].x;
-        const float mx = (r0.x - w.qx0) + r0.z;
-        const float my = (r0.y - w.qy0) + r0.w;
         geo[slot] = make_float4(mx, my, r1.x, r1.y);
         float extra = 0.0f;
         if (kExtra == 1) {
@@ -188,7 +225,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
         bool done = !scored;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<0>(w, e0, geo, col, nullptr, nullptr, nullptr);
+            const int n = stage_slice<0>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr);
             __syncthreads();
             for (int j = 0; j < n; ++j) {
                 const float4 G = geo[j], Cc = col[j];
@@ -275,7 +312,7 @@ __global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *_
         const float live_bar = a.share_floor * Af;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<1>(w, e0, geo, col, sid, sold, nullptr);
+            const int n = stage_slice<1>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr);
             __syncthreads();
             for (int jb = 0; jb < n; jb += 32) {
                 float sh[32];
@@ -410,8 +447,8 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     bool done = !scored;
     for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
         if (__all(done)) break;
-        const int n = has_w ? stage_slice<2>(w, e0, geo, col, nullptr, nullptr, o.weights)
-                            : stage_slice<0>(w, e0, geo, col, nullptr, nullptr, nullptr);
+        const int n = has_w ? stage_slice<2>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, o.weights)
+                            : stage_slice<0>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr);
         __syncthreads();
         for (int j = 0; j < n; ++j) {
             const float4 G = geo[j], Cc = col[j];
