@@ -355,8 +355,12 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     // after 4 radix passes the sorted pairs are back in (key0, val0); key1/val1 are free
     uint32_t *xr = b.key1, *yr = b.val1;
     launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
-    int max_tiles = 1;
-    for (const ViewDev &V : hv) max_tiles = std::max(max_tiles, V.tiles_x * V.tiles_y);
+    int max_tiles = 1, max_tx = 1, max_ty = 1;
+    for (const ViewDev &V : hv) {
+        max_tiles = std::max(max_tiles, V.tiles_x * V.tiles_y);
+        max_tx = std::max(max_tx, V.tiles_x);
+        max_ty = std::max(max_ty, V.tiles_y);
+    }
     launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, max_tiles, st);
     scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, nbins, r.scan_tmp, st);
     HIP_TRY(hipGetLastError());
@@ -367,7 +371,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     const size_t list_bytes = ((std::max<size_t>(total, 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
     HIP_TRY(arena_reserve(g_lists[dev], list_bytes));
     b.lists = (uint32_t *)g_lists[dev].base;
-    launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tiles, (uint64_t)total, st);
+    launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, st);
     HIP_TRY(hipGetLastError());
     // the compositing launch sees this chunk as a single scene slot
     r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.bin_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
@@ -774,7 +778,7 @@ struct PlanScene {
     uint64_t *scan_tmp = nullptr;
     uint32_t *over = nullptr;
     int64_t nbins = 0;
-    int max_tiles = 1;
+    int max_tiles = 1, max_tx = 1, max_ty = 1;
     uint64_t cap = 0;
     int group = 0, view0 = 0, tile0 = 0;
 };
@@ -878,7 +882,7 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
             enqueue_front(P, ps, st);
             launch_list_guard(ps.b.bin_off, ps.nbins, ps.cap, ps.over, P->flag, st);
             launch_bin_emit(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.sorted_g,
-                            ps.max_tiles, ps.cap, st);
+                            ps.max_tx, ps.max_ty, ps.cap, st);
             launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
         }
         CompositeArgs a{};
@@ -1055,6 +1059,8 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
             V.ray_local = ps.S.ray_base[k];
             V.tile_base = tb;
             ps.max_tiles = std::max(ps.max_tiles, V.tiles_x * V.tiles_y);
+            ps.max_tx = std::max(ps.max_tx, V.tiles_x);
+            ps.max_ty = std::max(ps.max_ty, V.tiles_y);
             for (int t = 0; t < V.tiles_x * V.tiles_y; ++t) ps.htv[tb + t] = k;
             tb += V.tiles_x * V.tiles_y;
         }

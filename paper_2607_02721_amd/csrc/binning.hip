@@ -8,11 +8,12 @@
 //             entries per tile in LDS and stores them at (tile, chunk);
 //   2. scan:  exclusive prefix sum -> segment offsets (tile-major,
 //             chunk-minor), so a tile's list is its chunks' segments in order;
-//   3. emit:  one wave per chunk expands its positions, in order, into
-//             (position, tile) items packed 64 to a batch; every tile's next
-//             slot comes from a wave-private LDS cursor (atomic add, executed
-//             in issue order), so each (tile, chunk) segment is written
-//             already sorted by p, as g | quadrant mask << 28.
+//   3. emit:  one wave per (chunk, group of tile rows) expands the chunk's
+//             positions that meet its rows, in order, into (position, tile)
+//             items packed 64 to a batch; every tile's next slot comes from a
+//             wave-private LDS cursor (atomic add, executed in issue order),
+//             so each (tile, chunk) segment is written already sorted by p,
+//             as g | quadrant mask << 28.
 // Bit q of the mask says whether the Gaussian's pixel range touches 8x8
 // quadrant q of the 16x16 tile.
 #include "gs_internal.hpp"
@@ -80,18 +81,28 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
         bin_count[(int64_t)(V.tile_base + t) * nchunks + chunk] = cnt[t] & ~kOff;
 }
 
-// Ordered emission.  One wave per (chunk, view) takes the chunk's positions
-// 64 at a time (a round; lane j holds position base + j) and expands them
-// into (position, tile) items in position order: a wave prefix sum of the
-// rectangle sizes numbers the items, and each 64-item batch finds every
-// item's owner by a binary search over the exclusive prefix.  A tile's slot
-// comes from an LDS atomic add on its cursor.  Items of one batch that hit
-// distinct tiles are independent; when two of them hit the same tile (an LDS
-// claim byte per tile detects it) the batch takes its owners one at a time
-// in order.  A wave's LDS operations execute in issue order, so later
-// positions always receive later slots and every (tile, chunk) segment is
-// filled in increasing p.
+// Ordered emission.  One wave per (group of kEmitRows tile rows, chunk,
+// view).  The wave first compacts, in order, the chunk's positions whose
+// rectangle meets its rows (an LDS queue), then takes them 64 at a time and
+// expands them into (position, tile) items in position order: a wave prefix
+// sum of the per-position item counts numbers the items, and each 64-item
+// batch finds every item's owner by a binary search over the exclusive
+// prefix.  A tile's slot comes from an LDS atomic add on its cursor.  Items
+// of one batch that hit distinct tiles are independent; when two of them hit
+// the same tile (an LDS claim byte per tile detects it) the batch takes its
+// owners one at a time in order.  A wave's LDS operations execute in issue
+// order, so later positions always receive later slots and every (tile,
+// chunk) segment is filled in increasing p.  Splitting a chunk by rows keeps
+// the wave's cursors small (high occupancy) and the list lines being written
+// at any moment few, so partial lines merge in the caches before they reach
+// HBM.
 constexpr int kEmitWave = 64;
+constexpr int kEmitRows = 4;
+
+__device__ __forceinline__ uint64_t lanemask_lt64_bin() {
+    const unsigned lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
 
 template <bool kMasked>
 __device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
@@ -100,65 +111,84 @@ __device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
 
 template <bool kMasked>
 __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restrict__ views, int64_t N, int nchunks,
-                                                        const uint32_t *__restrict__ nvis,
+                                                        int row_groups, const uint32_t *__restrict__ nvis,
                                                         const uint32_t *__restrict__ xr_in,
                                                         const uint32_t *__restrict__ yr_in,
                                                         const uint32_t *__restrict__ sorted_g,
                                                         const uint64_t *__restrict__ bin_off,
                                                         uint32_t *__restrict__ lists,
                                                         const uint8_t *__restrict__ active, uint64_t cap,
-                                                        int max_tiles) {
+                                                        int group_tiles) {
     extern __shared__ uint32_t lds[];
-    uint32_t *cur = lds;                                 // [tiles] next slot, relative to the view's first entry
-    uint32_t *pre = cur + max_tiles;                     // [65] exclusive item prefix of the round (+ sentinel)
-    uint32_t *rx = pre + kEmitWave + 1;                  // [64] the round's pixel ranges and indices
+    uint32_t *cur = lds;                                  // [group tiles] next slot, relative to the view's first entry
+    uint32_t *pre = cur + group_tiles;                    // [65] exclusive item prefix of the round
+    uint32_t *rx = pre + kEmitWave + 1;                   // [64] the round's pixel ranges and indices
     uint32_t *ry = rx + kEmitWave;
     uint32_t *rg = ry + kEmitWave;
-    uint8_t *claim = (uint8_t *)(rg + kEmitWave);        // [tiles] lane that last claimed the tile
-    uint32_t *act = (uint32_t *)(claim + ((max_tiles + 3) & ~3));  // [tiles / 32] (masked form only)
+    uint16_t *queue = (uint16_t *)(rg + kEmitWave);       // [2048] chunk-local positions meeting the rows
+    uint8_t *claim = (uint8_t *)(queue + kBinPositions);  // [group tiles] lane that last claimed the tile
+    uint32_t *act = (uint32_t *)(claim + ((group_tiles + 3) & ~3));  // [group tiles / 32] (masked form only)
     const int v = blockIdx.y;
+    const int grp = blockIdx.x % row_groups;
+    const int chunk = blockIdx.x / row_groups;
     const int lane = threadIdx.x;
     const ViewDev &V = views[v];
     const int64_t nv = nvis[v];
-    const int64_t lo = (int64_t)blockIdx.x * kBinPositions;
-    if (lo >= nv) return;
+    const int64_t lo = (int64_t)chunk * kBinPositions;
+    const int r0 = grp * kEmitRows;
+    if (lo >= nv || r0 >= V.tiles_y) return;
+    const int r1 = min(r0 + kEmitRows, V.tiles_y);    // rows [r0, r1)
     const int hi = (int)(min(lo + (int64_t)kBinPositions, nv) - lo);
-    const int chunk = (int)(lo >> kSegBits);
-    const int ntiles = V.tiles_x * V.tiles_y;
     const int tiles_x = V.tiles_x;
+    const int ntiles = (r1 - r0) * tiles_x;           // this wave's tiles: t = tile_base + r0 * tiles_x + local
+    const int64_t t0 = (int64_t)V.tile_base + (int64_t)r0 * tiles_x;
     const uint64_t vlist = bin_off[(int64_t)V.tile_base * nchunks];
-    for (int t = lane; t < ntiles; t += kEmitWave)
-        cur[t] = (uint32_t)(bin_off[(int64_t)(V.tile_base + t) * nchunks + chunk] - vlist);
+    for (int t = lane; t < ntiles; t += kEmitWave) cur[t] = (uint32_t)(bin_off[(t0 + t) * nchunks + chunk] - vlist);
     if (kMasked) {
         for (int w = lane; w < (ntiles + 31) / 32; w += kEmitWave) {
             uint32_t bits = 0;
             for (int b = 0; b < 32; ++b) {
                 const int t = 32 * w + b;
-                bits |= (t < ntiles && active[V.tile_base + t]) ? (1u << b) : 0u;
+                bits |= (t < ntiles && active[t0 + t]) ? (1u << b) : 0u;
             }
             act[w] = bits;
         }
     }
     if (lane == 0) pre[kEmitWave] = 0xFFFFFFFFu;
-    __syncthreads();
     // entries at or past `room` would fall outside the list buffer
     const uint64_t room = cap > vlist ? cap - vlist : 0ull;
     uint32_t *__restrict__ vl = lists + vlist;
     const int64_t o = (int64_t)v * N + lo;
+    // 1. positions whose rows meet [r0, r1), in order
+    int nq = 0;
     for (int base = 0; base < hi; base += kEmitWave) {
         const int p = base + lane;
+        bool meets = false;
+        if (p < hi) {
+            int yl, yh;
+            unpack_range(__uint_as_float(yr_in[o + p]), yl, yh);
+            meets = (yl >> 4) < r1 && (yh >> 4) >= r0;
+        }
+        const uint64_t bal = __ballot(meets);
+        if (meets) queue[nq + __popcll(bal & lanemask_lt64_bin())] = (uint16_t)p;
+        nq += __popcll(bal);
+    }
+    __syncthreads();
+    // 2. expansion of the queued positions against this wave's tiles
+    for (int base = 0; base < nq; base += kEmitWave) {
+        const int qi = base + lane;
         uint32_t ux = 0, uy = 0, ug = 0;
         int k = 0;
-        if (p < hi) {
+        if (qi < nq) {
+            const int p = queue[qi];
             ux = xr_in[o + p];
             uy = yr_in[o + p];
             ug = sorted_g[o + p];
             int xl, xh, yl, yh;
             unpack_range(__uint_as_float(ux), xl, xh);
             unpack_range(__uint_as_float(uy), yl, yh);
-            k = ((xh >> 4) - (xl >> 4) + 1) * ((yh >> 4) - (yl >> 4) + 1);
+            k = ((xh >> 4) - (xl >> 4) + 1) * (min(yh >> 4, r1 - 1) - max(yl >> 4, r0) + 1);
         }
-        // inclusive prefix sum of k over the wave
         int incl = k;
 #pragma unroll
         for (int d = 1; d < kEmitWave; d <<= 1) {
@@ -184,13 +214,13 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             unpack_range(__uint_as_float(rx[L]), xl, xh);
             unpack_range(__uint_as_float(ry[L]), yl, yh);
             const uint32_t g = rg[L];
-            const int tx0 = xl >> 4, ty0 = yl >> 4;
+            const int tx0 = xl >> 4, ty0 = max(yl >> 4, r0);
             const int nx = (xh >> 4) - tx0 + 1;
             // j / nx as floor((j + 1/2) r) with r within one ulp of 1/nx:
             // exact for nx * ny <= 8160 (checked exhaustively on the host)
             const int dy = (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
             const int tx = tx0 + (j - dy * nx), ty = ty0 + dy;
-            const int t = item ? ty * tiles_x + tx : 0;
+            const int t = item ? (ty - r0) * tiles_x + tx : 0;
             const bool on = item && tile_on<kMasked>(act, t);
             if (on) claim[t] = (uint8_t)lane;
             __syncthreads();
@@ -223,19 +253,22 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
 }
 
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                     const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles, uint64_t cap,
-                     hipStream_t st) {
+                     const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
+                     int max_tiles_y, uint64_t cap, hipStream_t st) {
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
-    // cursors, prefix (+ sentinel), three round arrays, claim bytes, tile bitmap
-    const size_t lds = sizeof(uint32_t) * ((size_t)max_tiles + (kEmitWave + 1) + 3 * kEmitWave) +
-                       (((size_t)max_tiles + 3) & ~(size_t)3) +
-                       (b.tile_active ? sizeof(uint32_t) * ((size_t)max_tiles + 31) / 32 : 0);
+    const int row_groups = (max_tiles_y + kEmitRows - 1) / kEmitRows;
+    const int group_tiles = kEmitRows * max_tiles_x;
+    // cursors, prefix (+ sentinel), three round arrays, queue, claim bytes, tile bitmap
+    const size_t lds = sizeof(uint32_t) * ((size_t)group_tiles + (kEmitWave + 1) + 3 * kEmitWave) +
+                       sizeof(uint16_t) * kBinPositions + (((size_t)group_tiles + 3) & ~(size_t)3) +
+                       (b.tile_active ? sizeof(uint32_t) * ((size_t)group_tiles + 31) / 32 : 0);
+    const dim3 grid((unsigned)(nb * row_groups), (unsigned)Vc);
     if (b.tile_active)
-        hipLaunchKernelGGL(k_bin_emit<true>, dim3(nb, Vc), dim3(kEmitWave), lds, st, views_dev, N, nchunks, b.nvis,
-                           xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, max_tiles);
+        hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, N, nchunks, row_groups,
+                           b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, group_tiles);
     else
-        hipLaunchKernelGGL(k_bin_emit<false>, dim3(nb, Vc), dim3(kEmitWave), lds, st, views_dev, N, nchunks, b.nvis,
-                           xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, max_tiles);
+        hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, N, nchunks, row_groups,
+                           b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, group_tiles);
 }
 
 // Capacity guard for lists sized in advance (plans): if the counted entries

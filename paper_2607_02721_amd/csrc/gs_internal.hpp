@@ -84,8 +84,8 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
 // Writes every list entry (g | quadrant mask << 28) in its final, sorted
 // place; entries at list index >= cap are dropped.
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                     const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles, uint64_t cap,
-                     hipStream_t st);
+                     const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
+                     int max_tiles_y, uint64_t cap, hipStream_t st);
 void launch_list_guard(uint64_t *bin_off, int64_t nbins, uint64_t cap, uint32_t *over, uint32_t *flag,
                        hipStream_t st);
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
