@@ -35,10 +35,57 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # (quarter-rate transcendental).
 OPS_PASS2 = 14 + 4
 OPS_PASS1 = 12 + 4
+# HBM peak of an MI355X (bytes/s).
+PEAK_HBM = 8.0e12
+# Algorithmic bytes of the tile-list emission kernel: per visible (view,
+# Gaussian) position its two packed pixel ranges and its index are read once
+# (12 B); per (tile, chunk) segment its start offset is read once (8 B); per
+# list entry one 4-byte word is written.
+EMIT_BYTES_POSITION, EMIT_BYTES_BIN, EMIT_BYTES_ENTRY = 12, 8, 4
+# Measured HBM traffic of the dominant kernels (rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE, scaled by a plain copy of known size), with the hash of the
+# kernel source the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene1m_100views.md")
+KERNEL_SOURCES = {"k_pass2": "paper_2607_02721_amd/csrc/composite.hip",
+                  "k_bin_emit": "paper_2607_02721_amd/csrc/binning.hip"}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none or the kernel's source changed since."""
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", text, re.S)
+    if not m:
+        return None
+    entry = json.loads(m.group(1)).get(kernel)
+    if not entry or entry.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(torch):
+    """Three device-to-device copies of 1 GiB: the reference dispatch that
+    scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_baseline(scene, views, n_views_total):
@@ -118,6 +165,8 @@ def main():
     ap.add_argument("--train-scenes", type=int, default=8)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 1 GiB device copies (reference dispatch for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -147,7 +196,7 @@ def main():
         step(stats=True)
     torch.cuda.synchronize()
     log("timed steps ...")
-    stage = {"ms_project": 0.0, "ms_sort": 0.0, "ms_bin": 0.0, "ms_pass1": 0.0, "ms_pass2": 0.0}
+    stage = {"ms_project": 0.0, "ms_sort": 0.0, "ms_bin": 0.0, "ms_emit": 0.0, "ms_pass1": 0.0, "ms_pass2": 0.0}
     t0 = time.perf_counter()
     for k in range(args.steps):
         s, st, w = step(stats=True)
@@ -252,13 +301,28 @@ def main():
     log("counting pairs (untimed) ...")
     _, cst, _ = step(stats=True, count_pairs=True)
     live = cst["n_live_pairs"]
-    dom_ms = stage["ms_pass2"]
-    achieved = live * OPS_PASS2 / (dom_ms * 1e-3)
-    roofline = {"kernel": "k_pass2 (compositing pass 2 + max-share reduction)", "bound": "alu",
-                "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                "work": f"{live} live pairs x {OPS_PASS2} VALU slots",
-                "pass1_frac": live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / PEAK_LANE_OPS}
+    if args.copy_calibration:
+        copy_calibration(torch)
+    # rooflines of the two heavy kernels, each from its own HIP-event time
+    p2 = {"kernel": "k_pass2 (compositing pass 2 + max-share reduction)", "bound": "alu",
+          "achieved": live * OPS_PASS2 / (stage["ms_pass2"] * 1e-3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+          "unit": "TOP/s", "ms": stage["ms_pass2"],
+          "work": f"{live} live pairs x {OPS_PASS2} VALU slots",
+          "traffic": measured_traffic("k_pass2")}
+    p2["frac"] = p2["achieved"] / p2["peak"]
+    emit_bytes = (EMIT_BYTES_POSITION * cst["n_projected"] + EMIT_BYTES_BIN * cst["n_bins"]
+                  + EMIT_BYTES_ENTRY * cst["n_entries"])
+    em = {"kernel": "k_bin_emit (ordered tile-list emission)", "bound": "hbm",
+          "achieved": emit_bytes / (stage["ms_emit"] * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+          "ms": stage["ms_emit"],
+          "work": f"{cst['n_projected']} positions x {EMIT_BYTES_POSITION} B + {cst['n_bins']} segments x "
+                  f"{EMIT_BYTES_BIN} B + {cst['n_entries']} entries x {EMIT_BYTES_ENTRY} B",
+          "traffic": measured_traffic("k_bin_emit")}
+    em["frac"] = em["achieved"] / em["peak"]
+    ranked = sorted([p2, em], key=lambda r: -r["ms"])
+    roofline = dict(ranked[0])
+    roofline["pass1_frac"] = live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / PEAK_LANE_OPS
+    others = ranked[1:]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -280,10 +344,10 @@ def main():
         "coreset_err_vs_m": scan,
         "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on 1% of the 8x8 pixel blocks, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],
-                  "entries": cst["n_entries"], "projected": cst["n_projected"]},
+                  "entries": cst["n_entries"], "projected": cst["n_projected"], "bins": cst["n_bins"]},
         "live_pairs_per_s": live / (ms * 1e-3),
         "batching": batching,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "roofline_other_kernels": others, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -113,6 +113,8 @@ typedef struct {
     int64_t n_invalid_gaussians; /* non-finite attributes or zero quaternion (treated as absent) */
     double total_sensitivity; /* S = sum_i s_i, fixed-order reduction */
     double ms_project, ms_sort, ms_bin, ms_pass1, ms_pass2; /* device time per stage, summed over chunks */
+    double ms_emit;           /* the tile-list emission kernel alone (part of ms_bin) */
+    int64_t n_bins;           /* (tile, chunk) segments: tiles x chunks of 2048 depth positions */
 } gs_stats;
 
 typedef struct {

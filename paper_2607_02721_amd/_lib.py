@@ -58,7 +58,8 @@ class Stats(C.Structure):
                 ("n_live_pairs", C.c_int64), ("n_lane_pairs", C.c_int64), ("n_rays_positive", C.c_int64),
                 ("n_invalid_gaussians", C.c_int64), ("total_sensitivity", C.c_double),
                 ("ms_project", C.c_double), ("ms_sort", C.c_double), ("ms_bin", C.c_double),
-                ("ms_pass1", C.c_double), ("ms_pass2", C.c_double)]
+                ("ms_pass1", C.c_double), ("ms_pass2", C.c_double), ("ms_emit", C.c_double),
+                ("n_bins", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -235,7 +235,7 @@ std::vector<ChunkPlan> plan_chunks(const gs_views *v, const Setup &S, const gs_p
 }
 
 struct Timer {
-    hipEvent_t ev[6];
+    hipEvent_t ev[8];
     bool on;
     explicit Timer(bool enable) : on(enable) {
         if (on)
@@ -371,8 +371,10 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     const size_t list_bytes = ((std::max<size_t>(total, 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
     HIP_TRY(arena_reserve(g_lists[dev], list_bytes));
     b.lists = (uint32_t *)g_lists[dev].base;
+    tm.mark(6, st);
     launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, st);
     HIP_TRY(hipGetLastError());
+    tm.mark(7, st);
     // the compositing launch sees this chunk as a single scene slot
     r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.bin_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
                             N, S.nchunks, 0, 0, 0};
@@ -384,6 +386,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         ms_acc[0] += tm.ms(0, 1);
         ms_acc[1] += tm.ms(1, 2);
         ms_acc[2] += tm.ms(2, 3);
+        ms_acc[5] += tm.ms(6, 7);
     }
     return GS_OK;
 }
@@ -488,7 +491,8 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
     HIP_TRY(hipGetLastError());
     Timer tm(stats != nullptr);
-    double ms[5] = {0, 0, 0, 0, 0};
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t n_bins = 0;
     std::vector<ViewDev> hv;
     std::vector<int32_t> htv;
     int64_t entries = 0, projected = 0;
@@ -500,6 +504,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
             GS_OK)
             return s;
         entries += r.n_entries;
+        n_bins += (int64_t)c.total_tiles * S.nchunks;
         CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor);
         tm.mark(3, st);
         launch_composite_pass1(a, st);
@@ -538,6 +543,8 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         stats->ms_bin = ms[2];
         stats->ms_pass1 = ms[3];
         stats->ms_pass2 = ms[4];
+        stats->ms_emit = ms[5];
+        stats->n_bins = n_bins;
         if (cnt[CNT_INVALID]) return fail(GS_ERR_INVALID_DATA, "%llu Gaussians have non-finite attributes",
                                           (unsigned long long)cnt[CNT_INVALID]);
     }
@@ -567,7 +574,7 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
     Timer tm(false);
-    double ms[5] = {0, 0, 0, 0, 0};
+    double ms[6] = {0, 0, 0, 0, 0, 0};
     std::vector<ViewDev> hv;
     std::vector<int32_t> htv;
     ChunkRun r;

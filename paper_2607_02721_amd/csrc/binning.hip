@@ -86,8 +86,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
 // rectangle meets its rows (an LDS queue), then takes them 64 at a time and
 // expands them into (position, tile) items in position order: a wave prefix
 // sum of the per-position item counts numbers the items, and each 64-item
-// batch finds every item's owner by a binary search over the exclusive
-// prefix.  A tile's slot comes from an LDS atomic add on its cursor.  Items
+// batch finds every item's owner with one LDS write of run heads and a
+// max-scan.  A tile's slot comes from an LDS atomic add on its cursor.  Items
 // of one batch that hit distinct tiles are independent; when two of them hit
 // the same tile (an LDS claim byte per tile detects it) the batch takes its
 // owners one at a time in order.  A wave's LDS operations execute in issue
@@ -102,6 +102,35 @@ constexpr int kEmitRows = 4;
 __device__ __forceinline__ uint64_t lanemask_lt64_bin() {
     const unsigned lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Wave-wide inclusive scans over the 64 lanes with DPP: shifts by 1, 2, 4, 8
+// inside each row of 16 lanes, then row_bcast:15 (row r-1's last lane into
+// rows 1 and 3) and row_bcast:31 (lane 31 into rows 2 and 3).  Lanes without
+// a source take the identity.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_src(int identity, int x) {
+    return __builtin_amdgcn_update_dpp(identity, x, kCtrl, kRowMask, 0xF, false);
+}
+
+__device__ __forceinline__ int wave_scan_add(int v) {
+    v += dpp_src<0x111, 0xF>(0, v);
+    v += dpp_src<0x112, 0xF>(0, v);
+    v += dpp_src<0x114, 0xF>(0, v);
+    v += dpp_src<0x118, 0xF>(0, v);
+    v += dpp_src<0x142, 0xA>(0, v);
+    v += dpp_src<0x143, 0xC>(0, v);
+    return v;
+}
+
+__device__ __forceinline__ int wave_scan_max(int v) {  // identity -1
+    v = max(v, dpp_src<0x111, 0xF>(-1, v));
+    v = max(v, dpp_src<0x112, 0xF>(-1, v));
+    v = max(v, dpp_src<0x114, 0xF>(-1, v));
+    v = max(v, dpp_src<0x118, 0xF>(-1, v));
+    v = max(v, dpp_src<0x142, 0xA>(-1, v));
+    v = max(v, dpp_src<0x143, 0xC>(-1, v));
+    return v;
 }
 
 template <bool kMasked>
@@ -121,8 +150,8 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                                                         int group_tiles) {
     extern __shared__ uint32_t lds[];
     uint32_t *cur = lds;                                  // [group tiles] next slot, relative to the view's first entry
-    uint32_t *pre = cur + group_tiles;                    // [65] exclusive item prefix of the round
-    uint32_t *rx = pre + kEmitWave + 1;                   // [64] the round's pixel ranges and indices
+    int32_t *head = (int32_t *)(cur + group_tiles);        // [64] lane owning the item that starts a run
+    uint32_t *rx = (uint32_t *)head + kEmitWave;           // [64] the round's pixel ranges and indices
     uint32_t *ry = rx + kEmitWave;
     uint32_t *rg = ry + kEmitWave;
     uint16_t *queue = (uint16_t *)(rg + kEmitWave);       // [2048] chunk-local positions meeting the rows
@@ -154,7 +183,6 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             act[w] = bits;
         }
     }
-    if (lane == 0) pre[kEmitWave] = 0xFFFFFFFFu;
     // entries at or past `room` would fall outside the list buffer
     const uint64_t room = cap > vlist ? cap - vlist : 0ull;
     uint32_t *__restrict__ vl = lists + vlist;
@@ -189,14 +217,9 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             unpack_range(__uint_as_float(uy), yl, yh);
             k = ((xh >> 4) - (xl >> 4) + 1) * (min(yh >> 4, r1 - 1) - max(yl >> 4, r0) + 1);
         }
-        int incl = k;
-#pragma unroll
-        for (int d = 1; d < kEmitWave; d <<= 1) {
-            const int y = __shfl_up(incl, d);
-            if (lane >= d) incl += y;
-        }
-        const int K = __shfl(incl, kEmitWave - 1);
-        pre[lane] = (uint32_t)(incl - k);
+        const int incl = wave_scan_add(k);
+        const int K = __builtin_amdgcn_readlane(incl, kEmitWave - 1);
+        const int excl = incl - k;   // first item of this lane's position
         rx[lane] = ux;
         ry[lane] = uy;
         rg[lane] = ug;
@@ -204,12 +227,17 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
         for (int i0 = 0; i0 < K; i0 += kEmitWave) {
             const int i = i0 + lane;
             const bool item = i < K;
-            // owner: the last lane whose exclusive prefix is <= i (pre[0] = 0)
-            int L = 0;
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1)
-                if (pre[L + st] <= (uint32_t)i) L += st;
-            const int j = i - (int)pre[L];
+            // owner of item i: the last position lane whose first item is <= i.
+            // Item i0's owner is the highest lane with excl <= i0; a lane whose
+            // run starts inside the batch marks its first item, and a max-scan
+            // over the marks carries each owner forward.
+            const uint64_t started = __ballot(excl <= i0);
+            const int carry = 63 - __builtin_clzll(started);
+            head[lane] = -1;
+            if (k > 0 && excl > i0 && excl < i0 + kEmitWave) head[excl - i0] = lane;
+            __syncthreads();
+            const int L = max(carry, wave_scan_max(head[lane]));
+            const int j = i - __shfl(excl, L);
             int xl, xh, yl, yh;
             unpack_range(__uint_as_float(rx[L]), xl, xh);
             unpack_range(__uint_as_float(ry[L]), yl, yh);
@@ -220,8 +248,10 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             // exact for nx * ny <= 8160 (checked exhaustively on the host)
             const int dy = (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
             const int tx = tx0 + (j - dy * nx), ty = ty0 + dy;
-            const int t = item ? (ty - r0) * tiles_x + tx : 0;
-            const bool on = item && tile_on<kMasked>(act, t);
+            const int tc = (ty - r0) * tiles_x + tx;
+            const bool in = item && (unsigned)tc < (unsigned)ntiles;
+            const int t = in ? tc : 0;
+            const bool on = in && tile_on<kMasked>(act, t);
             if (on) claim[t] = (uint8_t)lane;
             __syncthreads();
             const bool clash = on && claim[t] != (uint8_t)lane;
@@ -258,8 +288,8 @@ void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, c
     const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     const int row_groups = (max_tiles_y + kEmitRows - 1) / kEmitRows;
     const int group_tiles = kEmitRows * max_tiles_x;
-    // cursors, prefix (+ sentinel), three round arrays, queue, claim bytes, tile bitmap
-    const size_t lds = sizeof(uint32_t) * ((size_t)group_tiles + (kEmitWave + 1) + 3 * kEmitWave) +
+    // cursors, run heads, three round arrays, queue, claim bytes, tile bitmap
+    const size_t lds = sizeof(uint32_t) * ((size_t)group_tiles + kEmitWave + 3 * kEmitWave) +
                        sizeof(uint16_t) * kBinPositions + (((size_t)group_tiles + 3) & ~(size_t)3) +
                        (b.tile_active ? sizeof(uint32_t) * ((size_t)group_tiles + 31) / 32 : 0);
     const dim3 grid((unsigned)(nb * row_groups), (unsigned)Vc);

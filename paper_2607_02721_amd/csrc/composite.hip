@@ -28,6 +28,7 @@
 namespace gs {
 
 constexpr int kWave = 64;
+constexpr int kBlock = 4;   // pairs per unguarded step of the pass-2 loop
 
 __device__ __forceinline__ uint64_t lanemask_lt64() {
     const unsigned lane = threadIdx.x & 63;
@@ -156,10 +157,12 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
 }
 
 // Stage the slice's entries whose footprint reaches this quadrant (pixel
-// range bit, then the exact test above); returns how many.
+// range bit, then the exact test above); returns how many.  With kPad > 1
+// the slots up to the next multiple of kPad hold null entries, so a loop can
+// run in unguarded blocks of kPad pairs.
 // geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
 // col = (g', alpha, cbar, extra).
-template <int kExtra>  // 0: none, 1: s_old + index, 2: weight
+template <int kExtra, int kPad = 1>  // kExtra 0: none, 1: s_old + index, 2: weight
 __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
                                            uint32_t *sid, float *sold, const double *__restrict__ weights) {
     const int lane = threadIdx.x;
@@ -182,6 +185,16 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         touch = quad_hit(mx, my, r1.x, r1.y, r1.z, cut);
     }
     const uint64_t bal = __ballot(touch);
+    const int n = __popcll(bal);
+    if (kPad > 1 && !touch) {
+        // null entries (alpha = 0: rho = 0, so A, T and every share are
+        // unchanged) fill the slots up to a multiple of kPad
+        const int slot = n + __popcll(~bal & lanemask_lt64());
+        if (slot < ((n + kPad - 1) & ~(kPad - 1))) {
+            geo[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            col[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
     if (touch) {
         const int slot = __popcll(bal & lanemask_lt64());
         const float cb = R2[o].x;
@@ -194,7 +207,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         if (kExtra == 2) extra = (float)weights[g];
         col[slot] = make_float4(r1.z, r1.w, cb, extra);
     }
-    return __popcll(bal);
+    return n;
 }
 
 // exp2 argument of the kernel for this lane's pixel; rho = alpha exp2(P)
@@ -289,8 +302,38 @@ __device__ __forceinline__ float wave_transpose_max32(float (&v)[32]) {
     return dpp_max<0xB1>(v[0]);
 }
 
+// The same network for 16 values: four halving levels (lane bits 5..2)
+// and two plain reductions (bits 1, 0); afterwards lane L holds the maximum
+// over all 64 lanes of value (L >> 2) & 15.
+__device__ __forceinline__ float wave_transpose_max16(float (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 8]),
+                                                        false, false);
+        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 4]),
+                                                        false, false);
+        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    }
+    const bool s3 = (lane & 8) != 0, s2 = (lane & 4) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float m0 = dpp_max<0x140>(v[k]), m1 = dpp_max<0x140>(v[k + 2]);
+        v[k] = s3 ? m1 : m0;
+    }
+    {
+        const float m0 = dpp_max<0x141>(v[0]), m1 = dpp_max<0x141>(v[1]);
+        v[0] = s2 ? m1 : m0;
+    }
+    return dpp_max<0xB1>(dpp_max<0x4E>(v[0]));
+}
+
 template <bool kStats, bool kPersistent>
-__global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
+__global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     __shared__ float4 geo[kWave], col[kWave];
     __shared__ uint32_t sid[kWave];
     __shared__ float sold[kWave];
@@ -312,32 +355,37 @@ __global__ __launch_bounds__(kWave, 4) void k_pass2(CompositeArgs a, uint64_t *_
         const float live_bar = a.share_floor * Af;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<1>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr);
+            const int n = stage_slice<1, kBlock>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr);
             __syncthreads();
-            for (int jb = 0; jb < n; jb += 32) {
-                float sh[32];
+            for (int jb = 0; jb < n; jb += 16) {
+                float sh[16];
 #pragma unroll
-                for (int k = 0; k < 32; ++k) {
-                    const int j = jb + k;
-                    if (j < n) {
-                        const float4 G = geo[j], Cc = col[j];
-                        bool in_fp;
-                        const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
-                        const float cr = Cc.z * rho;
-                        sh[k] = (cr * T) * invA;
-                        if (kStats) {
-                            n_in += in_fp ? 1u : 0u;
-                            n_live += (in_fp && T * cmax >= live_bar) ? 1u : 0u;
+                for (int k0 = 0; k0 < 16; k0 += kBlock) {
+                    if (jb + k0 < n) {
+#pragma unroll
+                        for (int q = 0; q < kBlock; ++q) {
+                            const int j = jb + k0 + q;
+                            const float4 G = geo[j], Cc = col[j];
+                            bool in_fp;
+                            const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+                            const float cr = Cc.z * rho;
+                            sh[k0 + q] = (cr * T) * invA;
+                            if (kStats) {
+                                const bool real = j < n;
+                                n_in += (real && in_fp) ? 1u : 0u;
+                                n_live += (real && in_fp && T * cmax >= live_bar) ? 1u : 0u;
+                            }
+                            T = fmaf(-rho, T, T);
                         }
-                        T = fmaf(-rho, T, T);
                     } else {
-                        sh[k] = 0.0f;
+#pragma unroll
+                        for (int q = 0; q < kBlock; ++q) sh[k0 + q] = 0.0f;
                     }
                 }
-                if (kStats) n_eval += (uint32_t)min(32, n - jb);
-                const float m = wave_transpose_max32(sh);
-                const int j = jb + (lane >> 1);
-                if ((lane & 1) == 0 && j < n && m > sold[j]) atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
+                if (kStats) n_eval += (uint32_t)min(16, n - jb);
+                const float m = wave_transpose_max16(sh);
+                const int j = jb + (lane >> 2);
+                if ((lane & 3) == 0 && j < n && m > sold[j]) atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
             }
             done = done || (T * cmax < a.share_floor * Af);
             __syncthreads();
