@@ -21,6 +21,8 @@
 namespace gs {
 
 constexpr int kBinThreads = 256;
+constexpr int kCountGroup = 32;        // chunks per XCD run (multiples of the 16 counts in a 64-byte line)
+constexpr int kEmitGroupChunks = 16;   // chunks (times the row groups) per XCD run
 constexpr int kSegBits = kChunkBits;
 constexpr int kSegSize = 1 << kSegBits;          // positions per chunk
 
@@ -30,6 +32,17 @@ __device__ __forceinline__ void unpack_range(float f, int &lo, int &hi) {
     const uint32_t u = __float_as_uint(f);
     lo = (int)(int16_t)(u & 0xFFFFu);
     hi = (int)(int16_t)(u >> 16);
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin.  Renumbering hands out
+// logical blocks in runs of `group` per XCD (run k to XCD k mod 8), so
+// neighbouring chunks (which write neighbouring words of the same lines) and
+// the row groups of one chunk (which read the same positions) share one L2,
+// while all XCDs stay on nearby chunks of one view.  The grid size must be a
+// multiple of 8 * group.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t group) {
+    const int64_t xcd = b & 7, slot = b >> 3;
+    return ((slot / group) * 8 + xcd) * group + slot % group;
 }
 
 __device__ __forceinline__ uint32_t quad_mask(int tx, int ty, int xl, int xh, int yl, int yh) {
@@ -43,8 +56,9 @@ __device__ __forceinline__ uint32_t quad_mask(int tx, int ty, int xl, int xh, in
     return m;
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__restrict__ views, int64_t N,
-                                                           int nchunks, const uint32_t *__restrict__ nvis,
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__restrict__ views, int n_views,
+                                                           int64_t N, int nchunks,
+                                                           const uint32_t *__restrict__ nvis,
                                                            const uint32_t *__restrict__ xr_in,
                                                            const uint32_t *__restrict__ yr_in,
                                                            uint32_t *__restrict__ bin_count,
@@ -53,10 +67,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
     // Bit 31 of cnt[t] marks a tile without any selected ray (no entries);
     // the counts themselves stay below 2^31.
     constexpr uint32_t kOff = 0x80000000u;
-    const int v = blockIdx.y;
+    const int64_t lb = xcd_block(blockIdx.x, kCountGroup);   // logical block: chunk + nchunks * view
+    const int v = (int)(lb / nchunks);
+    if (v >= n_views) return;
     const ViewDev &V = views[v];
     const int64_t nv = nvis[v];
-    const int64_t lo = (int64_t)blockIdx.x * kBinPositions;
+    const int64_t lo = (lb - (int64_t)v * nchunks) * kBinPositions;
     if (lo >= nv) return;
     const int64_t hi = min(lo + (int64_t)kBinPositions, nv);
     const int chunk = (int)(lo >> kSegBits);
@@ -139,8 +155,9 @@ __device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
 }
 
 template <bool kMasked>
-__global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restrict__ views, int64_t N, int nchunks,
-                                                        int row_groups, const uint32_t *__restrict__ nvis,
+__global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restrict__ views, int n_views, int64_t N,
+                                                        int nchunks, int row_groups,
+                                                        const uint32_t *__restrict__ nvis,
                                                         const uint32_t *__restrict__ xr_in,
                                                         const uint32_t *__restrict__ yr_in,
                                                         const uint32_t *__restrict__ sorted_g,
@@ -157,9 +174,13 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
     uint16_t *queue = (uint16_t *)(rg + kEmitWave);       // [2048] chunk-local positions meeting the rows
     uint8_t *claim = (uint8_t *)(queue + kBinPositions);  // [group tiles] lane that last claimed the tile
     uint32_t *act = (uint32_t *)(claim + ((group_tiles + 3) & ~3));  // [group tiles / 32] (masked form only)
-    const int v = blockIdx.y;
-    const int grp = blockIdx.x % row_groups;
-    const int chunk = blockIdx.x / row_groups;
+    // logical block: row group + row_groups * (chunk + nchunks * view)
+    const int64_t lb = xcd_block(blockIdx.x, (int64_t)kEmitGroupChunks * row_groups);
+    const int64_t per_view = (int64_t)row_groups * nchunks;
+    const int v = (int)(lb / per_view);
+    if (v >= n_views) return;
+    const int grp = (int)(lb % row_groups);
+    const int chunk = (int)((lb - (int64_t)v * per_view) / row_groups);
     const int lane = threadIdx.x;
     const ViewDev &V = views[v];
     const int64_t nv = nvis[v];
@@ -277,27 +298,29 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
 
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                       const uint32_t *xr, const uint32_t *yr, int max_tiles, hipStream_t st) {
-    const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
-    hipLaunchKernelGGL(k_bin_count, dim3(nb, Vc), dim3(kBinThreads), (size_t)max_tiles * sizeof(uint32_t), st,
-                       views_dev, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active);
+    const int64_t run = 8 * kCountGroup;
+    const int64_t blocks = ((int64_t)nchunks * Vc + run - 1) / run * run;
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)blocks), dim3(kBinThreads), (size_t)max_tiles * sizeof(uint32_t),
+                       st, views_dev, Vc, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active);
 }
 
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
                      int max_tiles_y, uint64_t cap, hipStream_t st) {
-    const int nb = (int)((N + kBinPositions - 1) / kBinPositions);
     const int row_groups = (max_tiles_y + kEmitRows - 1) / kEmitRows;
+    const int64_t run = 8 * (int64_t)kEmitGroupChunks * row_groups;
+    const int64_t blocks = ((int64_t)row_groups * nchunks * Vc + run - 1) / run * run;
     const int group_tiles = kEmitRows * max_tiles_x;
     // cursors, run heads, three round arrays, queue, claim bytes, tile bitmap
     const size_t lds = sizeof(uint32_t) * ((size_t)group_tiles + kEmitWave + 3 * kEmitWave) +
                        sizeof(uint16_t) * kBinPositions + (((size_t)group_tiles + 3) & ~(size_t)3) +
                        (b.tile_active ? sizeof(uint32_t) * ((size_t)group_tiles + 31) / 32 : 0);
-    const dim3 grid((unsigned)(nb * row_groups), (unsigned)Vc);
+    const dim3 grid((unsigned)blocks);
     if (b.tile_active)
-        hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, N, nchunks, row_groups,
+        hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
                            b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, group_tiles);
     else
-        hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, N, nchunks, row_groups,
+        hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
                            b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, group_tiles);
 }
 
