@@ -125,8 +125,9 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
     add(2 * sizeof(uint32_t) * (size_t)c.vc);
     add(sizeof(uint32_t) * nbins);
-    add(sizeof(uint64_t) * (nbins + 1));
-    add(sizeof(uint64_t) * scan_tmp_elems(nbins + 1));
+    add(sizeof(uint32_t) * c.total_tiles);
+    add(sizeof(uint64_t) * (c.total_tiles + 1));
+    add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
     add(sizeof(float) * (size_t)c.rays);
     add(sizeof(uint64_t) * CNT_SLOTS);
     add(sizeof(ViewDev) * c.vc);
@@ -295,8 +296,9 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.nvis = cv.take<uint32_t>(2 * (size_t)c.vc);
     b.cmax = b.nvis + c.vc;
     b.bin_count = cv.take<uint32_t>(nbins);
-    b.bin_off = cv.take<uint64_t>(nbins + 1);
-    r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(nbins + 1));
+    b.tile_tot = cv.take<uint32_t>(c.total_tiles);
+    b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
+    r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
     b.ray_A = cv.take<float>(c.rays);
     b.counters = cv.take<uint64_t>(CNT_SLOTS);
     r.views_dev = cv.take<ViewDev>(c.vc);
@@ -362,10 +364,11 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         max_ty = std::max(max_ty, V.tiles_y);
     }
     launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, max_tiles, st);
-    scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, nbins, r.scan_tmp, st);
+    launch_chunk_prefix(r.views_dev, c.vc, S.nchunks, b, max_tiles, st);
+    scan_u32_to_u64_exclusive(b.tile_tot, b.tile_off, c.total_tiles, r.scan_tmp, st);
     HIP_TRY(hipGetLastError());
     uint64_t total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, b.bin_off + nbins, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&total, b.tile_off + c.total_tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     r.n_entries = (int64_t)total;
     const size_t list_bytes = ((std::max<size_t>(total, 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
@@ -376,8 +379,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(hipGetLastError());
     tm.mark(7, st);
     // the compositing launch sees this chunk as a single scene slot
-    r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.bin_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
-                            N, S.nchunks, 0, 0, 0};
+    r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
+                            N, 0, 0};
     HIP_TRY(hipMemcpyAsync(r.slot_dev, &r.host_slot, sizeof(SceneSlot), hipMemcpyHostToDevice, st));
     launch_fill_u32((uint32_t *)r.tile_scene, 0u, c.total_tiles, st);
     tm.mark(3, st);
@@ -830,8 +833,9 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     add(sizeof(uint32_t) * (size_t)ps.c.vc * 256 * nb);
     add(2 * sizeof(uint32_t) * (size_t)ps.c.vc);
     add(sizeof(uint32_t) * ps.nbins);
-    add(sizeof(uint64_t) * (ps.nbins + 1));
-    add(sizeof(uint64_t) * scan_tmp_elems(ps.nbins + 1));
+    add(sizeof(uint32_t) * ps.c.total_tiles);
+    add(sizeof(uint64_t) * (ps.c.total_tiles + 1));
+    add(sizeof(uint64_t) * scan_tmp_elems(ps.c.total_tiles + 1));
     add(sizeof(float) * (size_t)ps.c.rays);
     add(sizeof(uint64_t) * CNT_SLOTS);
     add(256);
@@ -853,8 +857,9 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.nvis = cv.take<uint32_t>(2 * (size_t)ps.c.vc);
     b.cmax = b.nvis + ps.c.vc;
     b.bin_count = cv.take<uint32_t>(ps.nbins);
-    b.bin_off = cv.take<uint64_t>(ps.nbins + 1);
-    ps.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(ps.nbins + 1));
+    b.tile_tot = cv.take<uint32_t>(ps.c.total_tiles);
+    b.tile_off = cv.take<uint64_t>(ps.c.total_tiles + 1);
+    ps.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(ps.c.total_tiles + 1));
     b.ray_A = cv.take<float>(ps.c.rays);
     b.counters = cv.take<uint64_t>(CNT_SLOTS);
     ps.over = cv.take<uint32_t>(64);
@@ -878,7 +883,8 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ps.yr = b.val1;
     launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);
     launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, ps.max_tiles, st);
-    scan_u32_to_u64_exclusive(b.bin_count, b.bin_off, ps.nbins, ps.scan_tmp, st);
+    launch_chunk_prefix(ps.views_dev, ps.c.vc, ps.S.nchunks, b, ps.max_tiles, st);
+    scan_u32_to_u64_exclusive(b.tile_tot, b.tile_off, ps.c.total_tiles, ps.scan_tmp, st);
 }
 
 void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
@@ -887,7 +893,7 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
         for (int si : G.scenes) {
             PlanScene &ps = P->scenes[si];
             enqueue_front(P, ps, st);
-            launch_list_guard(ps.b.bin_off, ps.nbins, ps.cap, ps.over, P->flag, st);
+            launch_list_guard(ps.b.tile_off, ps.c.total_tiles, ps.cap, ps.over, P->flag, st);
             launch_bin_emit(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.sorted_g,
                             ps.max_tx, ps.max_ty, ps.cap, st);
             launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
@@ -986,7 +992,8 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         for (size_t k = 0; k < G.scenes.size(); ++k) {
             PlanScene &ps = P->scenes[G.scenes[k]];
             enqueue_front(P, ps, st);
-            HIP_TRY(hipMemcpyAsync(&totals[k], ps.b.bin_off + ps.nbins, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&totals[k], ps.b.tile_off + ps.c.total_tiles, sizeof(uint64_t),
+                                   hipMemcpyDeviceToHost, st));
         }
         HIP_TRY(hipStreamSynchronize(st));
         size_t lb = 0;
@@ -1135,8 +1142,8 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
             std::vector<SceneSlot> hs;
             for (int si : G.scenes) {
                 PlanScene &ps = plan->scenes[si];
-                hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.bin_off, ps.b.cmax, ps.b.ray_A,
-                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.S.nchunks, ps.view0, ps.tile0, 0});
+                hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
+                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0});
             }
             HIP_TRY(hipMemcpyAsync(G.slots, hs.data(), sizeof(SceneSlot) * hs.size(), hipMemcpyHostToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));

@@ -5,9 +5,10 @@
 // stable and starts from index order).  A list entry is keyed by (tile, p)
 // and the lists are built by a counting sort on that key:
 //   1. count: one block per chunk of 2^11 consecutive positions counts its
-//             entries per tile in LDS and stores them at (tile, chunk);
-//   2. scan:  exclusive prefix sum -> segment offsets (tile-major,
-//             chunk-minor), so a tile's list is its chunks' segments in order;
+//             entries per tile in LDS and stores them, one row per chunk;
+//   2. scan:  per tile, the exclusive prefix over chunks (in place) and the
+//             tile's total; a scan of the totals gives each tile's list start,
+//             so a tile's list is its chunks' segments in order;
 //   3. emit:  one wave per (chunk, group of tile rows) expands the chunk's
 //             positions that meet its rows, in order, into (position, tile)
 //             items packed 64 to a batch; every tile's next slot comes from a
@@ -93,8 +94,39 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
     }
     __syncthreads();
     // this block is the only writer of (tile, chunk) for every tile of the view
-    for (int t = threadIdx.x; t < ntiles; t += kBinThreads)
-        bin_count[(int64_t)(V.tile_base + t) * nchunks + chunk] = cnt[t] & ~kOff;
+    uint32_t *row = bin_count + (int64_t)V.tile_base * nchunks + (int64_t)chunk * ntiles;
+    for (int t = threadIdx.x; t < ntiles; t += kBinThreads) row[t] = cnt[t] & ~kOff;
+}
+
+// Column pass over one view's [chunk][tile] counts: each thread owns one tile
+// and replaces its counts, chunk by chunk, with their exclusive prefix (the
+// tile's segment offsets inside its list); the tile's total goes to tile_tot.
+__global__ __launch_bounds__(kBinThreads) void k_chunk_prefix(const ViewDev *__restrict__ views, int nchunks,
+                                                              uint32_t *__restrict__ bin_count,
+                                                              uint32_t *__restrict__ tile_tot) {
+    const ViewDev &V = views[blockIdx.y];
+    const int ntiles = V.tiles_x * V.tiles_y;
+    const int t = blockIdx.x * kBinThreads + threadIdx.x;
+    if (t >= ntiles) return;
+    uint32_t *col = bin_count + (int64_t)V.tile_base * nchunks + t;
+    uint32_t run = 0;
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = col[(int64_t)(c + k) * ntiles];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            col[(int64_t)(c + k) * ntiles] = run;
+            run += x[k];
+        }
+    }
+    for (; c < nchunks; ++c) {
+        const uint32_t x = col[(int64_t)c * ntiles];
+        col[(int64_t)c * ntiles] = run;
+        run += x;
+    }
+    tile_tot[V.tile_base + t] = run;
 }
 
 // Ordered emission.  One wave per (group of kEmitRows tile rows, chunk,
@@ -161,7 +193,8 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                                                         const uint32_t *__restrict__ xr_in,
                                                         const uint32_t *__restrict__ yr_in,
                                                         const uint32_t *__restrict__ sorted_g,
-                                                        const uint64_t *__restrict__ bin_off,
+                                                        const uint32_t *__restrict__ bin_count,
+                                                        const uint64_t *__restrict__ tile_off,
                                                         uint32_t *__restrict__ lists,
                                                         const uint8_t *__restrict__ active, uint64_t cap,
                                                         int group_tiles) {
@@ -192,8 +225,12 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
     const int tiles_x = V.tiles_x;
     const int ntiles = (r1 - r0) * tiles_x;           // this wave's tiles: t = tile_base + r0 * tiles_x + local
     const int64_t t0 = (int64_t)V.tile_base + (int64_t)r0 * tiles_x;
-    const uint64_t vlist = bin_off[(int64_t)V.tile_base * nchunks];
-    for (int t = lane; t < ntiles; t += kEmitWave) cur[t] = (uint32_t)(bin_off[(t0 + t) * nchunks + chunk] - vlist);
+    const uint64_t vlist = tile_off[V.tile_base];
+    // segment start of each of the wave's tiles for this chunk, relative to
+    // the view's first entry: the tile's list start plus the tile's prefix
+    const uint32_t *pre = bin_count + (int64_t)V.tile_base * nchunks + (int64_t)chunk * (V.tiles_x * V.tiles_y) +
+                          (int64_t)r0 * tiles_x;
+    for (int t = lane; t < ntiles; t += kEmitWave) cur[t] = (uint32_t)(tile_off[t0 + t] - vlist) + pre[t];
     if (kMasked) {
         for (int w = lane; w < (ntiles + 31) / 32; w += kEmitWave) {
             uint32_t bits = 0;
@@ -304,6 +341,12 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
                        st, views_dev, Vc, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active);
 }
 
+void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const ChunkBufs &b, int max_tiles,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_chunk_prefix, dim3((unsigned)((max_tiles + kBinThreads - 1) / kBinThreads), (unsigned)Vc),
+                       dim3(kBinThreads), 0, st, views_dev, nchunks, b.bin_count, b.tile_tot);
+}
+
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
                      int max_tiles_y, uint64_t cap, hipStream_t st) {
@@ -318,29 +361,32 @@ void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, c
     const dim3 grid((unsigned)blocks);
     if (b.tile_active)
         hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
-                           b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, group_tiles);
+                           b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
+                           group_tiles);
     else
         hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
-                           b.nvis, xr, yr, sorted_g, b.bin_off, b.lists, b.tile_active, cap, group_tiles);
+                           b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
+                           group_tiles);
 }
 
 // Capacity guard for lists sized in advance (plans): if the counted entries
 // exceed the capacity, flag it and empty every list of the scene so that no
 // later kernel reads past the buffer.
-__global__ void k_guard_check(const uint64_t *__restrict__ bin_off, int64_t nbins, uint64_t cap,
+__global__ void k_guard_check(const uint64_t *__restrict__ tile_off, int64_t ntiles, uint64_t cap,
                               uint32_t *__restrict__ over, uint32_t *__restrict__ flag) {
-    const bool o = bin_off[nbins] > cap;
+    const bool o = tile_off[ntiles] > cap;
     *over = o ? 1u : 0u;
     if (o) atomicOr(flag, 1u);
 }
-__global__ void k_guard_apply(uint64_t *__restrict__ bin_off, int64_t nbins, const uint32_t *__restrict__ over) {
+__global__ void k_guard_apply(uint64_t *__restrict__ tile_off, int64_t ntiles, const uint32_t *__restrict__ over) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (*over && i <= nbins) bin_off[i] = 0;
+    if (*over && i <= ntiles) tile_off[i] = 0;
 }
-void launch_list_guard(uint64_t *bin_off, int64_t nbins, uint64_t cap, uint32_t *over, uint32_t *flag,
+void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag,
                        hipStream_t st) {
-    hipLaunchKernelGGL(k_guard_check, dim3(1), dim3(1), 0, st, bin_off, nbins, cap, over, flag);
-    hipLaunchKernelGGL(k_guard_apply, dim3((unsigned)((nbins + 256) / 256)), dim3(256), 0, st, bin_off, nbins, over);
+    hipLaunchKernelGGL(k_guard_check, dim3(1), dim3(1), 0, st, tile_off, ntiles, cap, over, flag);
+    hipLaunchKernelGGL(k_guard_apply, dim3((unsigned)((ntiles + 256) / 256)), dim3(256), 0, st, tile_off, ntiles,
+                       over);
 }
 
 // A tile is active when at least one of its rays is selected by the ray mask;

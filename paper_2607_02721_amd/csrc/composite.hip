@@ -86,9 +86,8 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.W = V.W;
     w.ray_local = V.ray_local + (int64_t)w.py * V.W + w.px;
     w.ray_global = V.ray_base + (int64_t)w.py * V.W + w.px;
-    const int64_t st = (int64_t)(w.gt - S.tile0) * S.nchunks;
-    w.start = S.bin_off[st];
-    w.end = S.bin_off[st + S.nchunks];
+    w.start = S.tile_off[w.gt - S.tile0];
+    w.end = S.tile_off[w.gt - S.tile0 + 1];
     w.qbit = 1u << (28 + w.quad);
     w.vbase = (int64_t)(w.v - S.view0) * S.N;
     w.R0 = S.R0;

@@ -55,8 +55,12 @@ struct ChunkBufs {
     uint32_t *hist;      // radix histograms [Vc][256][nb]
     uint32_t *nvis;      // [Vc] visible Gaussians per view
     uint32_t *cmax;      // [Vc] largest query colour per view (float bits)
-    uint32_t *bin_count; // [Vc*tiles_total ... ] per (tile, chunk) entry counts
-    uint64_t *bin_off;   // exclusive scan of bin_count (+1 trailing total)
+    // per (tile, chunk) entry counts, chunk-major inside each view (view v at
+    // tile_base(v) * nchunks, then [chunk][tile of v]); turned in place into
+    // each tile's exclusive prefix over chunks
+    uint32_t *bin_count;
+    uint32_t *tile_tot;  // [tiles in chunk] entries per tile
+    uint64_t *tile_off;  // exclusive scan of tile_tot (+1 trailing total): the tile's list
     uint32_t *lists;     // [D] entries
     float *ray_A;        // [rays in chunk] pass-1 render
     uint8_t *tile_active; // [tiles in chunk] tiles holding a selected ray (null: all)
@@ -81,12 +85,15 @@ void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int 
                         uint8_t *active, hipStream_t st);
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                       const uint32_t *xr, const uint32_t *yr, int max_tiles, hipStream_t st);
+// bin_count -> per-tile prefix over chunks (in place) and tile_tot.
+void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const ChunkBufs &b, int max_tiles,
+                         hipStream_t st);
 // Writes every list entry (g | quadrant mask << 28) in its final, sorted
 // place; entries at list index >= cap are dropped.
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
                      int max_tiles_y, uint64_t cap, hipStream_t st);
-void launch_list_guard(uint64_t *bin_off, int64_t nbins, uint64_t cap, uint32_t *over, uint32_t *flag,
+void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag,
                        hipStream_t st);
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
                                hipStream_t st);
@@ -96,17 +103,15 @@ int64_t scan_tmp_elems(int64_t n);
 // One scene of a compositing launch (a launch may cover several scenes).
 struct SceneSlot {
     const float4 *R0, *R1, *R2;   // records [views of the scene][N]
-    const uint32_t *lists;        // tile lists; bin_off values index this array
-    const uint64_t *bin_off;      // [scene tiles * nchunks + 1]
+    const uint32_t *lists;        // tile lists; tile_off values index this array
+    const uint64_t *tile_off;     // [scene tiles + 1] start of each tile's list
     const uint32_t *cmax;         // [views of the scene] largest query colour (float bits)
     float *ray_A;                 // pass-1 render of the scene's rays (indexed by ViewDev::ray_local)
     uint32_t *sens_bits;          // sensitivities (float bits, atomicMax) [N]
     const uint32_t *ray_mask;     // bitset over the scene's rays (ViewDev::ray_base numbering) or null
     int64_t N;
-    int32_t nchunks;
     int32_t view0;                // first view of the scene in the launch's view table
     int32_t tile0;                // first tile of the scene in the launch's tile table
-    int32_t pad;
 };
 
 struct CompositeArgs {
