@@ -129,7 +129,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint64_t) * (c.total_tiles + 1));
     add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
     add(sizeof(float) * (size_t)c.rays);
-    add(sizeof(uint64_t) * CNT_SLOTS);
+    add(sizeof(uint64_t) * CNT_WORDS);
     add(sizeof(ViewDev) * c.vc);
     add(sizeof(int32_t) * c.total_tiles);
     add(c.total_tiles);                                     // tile activity
@@ -300,7 +300,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
     r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
     b.ray_A = cv.take<float>(c.rays);
-    b.counters = cv.take<uint64_t>(CNT_SLOTS);
+    b.counters = cv.take<uint64_t>(CNT_WORDS);
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
     b.tile_active = p->ray_mask ? cv.take<uint8_t>(c.total_tiles) : nullptr;
@@ -341,7 +341,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(hipMemcpyAsync(r.tile_view, htv.data(), sizeof(int32_t) * c.total_tiles, hipMemcpyHostToDevice, st));
     launch_fill_u32(b.nvis, 0u, 2 * (int64_t)c.vc, st);
     launch_fill_u32(b.bin_count, 0u, nbins, st);
-    if (zero_counters) launch_fill_u64(b.counters, 0ull, CNT_SLOTS, st);
+    if (zero_counters) launch_fill_u64(b.counters, 0ull, CNT_WORDS, st);
 
     SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
                 scene->quat, scene->opacity, scene->sh};
@@ -528,17 +528,20 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         double S_total = 0.0;
-        uint64_t cnt[CNT_SLOTS];
+        uint64_t cnt[CNT_WORDS];
         launch_sum_f32_to_f64(sens, S.N, r.sum_tmp + (S.N + 4095) / 4096, r.sum_tmp, st);
         HIP_TRY(hipMemcpyAsync(&S_total, r.sum_tmp + (S.N + 4095) / 4096, sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(cnt, r.b.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         stats->n_projected = projected;
         stats->n_entries = entries;
-        stats->n_pairs = (int64_t)cnt[CNT_PAIRS];
-        stats->n_live_pairs = (int64_t)cnt[CNT_LIVE];
-        stats->n_lane_pairs = (int64_t)cnt[CNT_LANE_PAIRS];
-        stats->n_rays_positive = (int64_t)cnt[CNT_RAYS_POS];
+        uint64_t spread[4] = {0, 0, 0, 0};
+        for (int k = 0; k < 4; ++k)
+            for (int i = 0; i < kCntSpread; ++i) spread[k] += cnt[CNT_SLOTS + k * kCntSpread + i];
+        stats->n_pairs = (int64_t)spread[0];
+        stats->n_live_pairs = (int64_t)spread[1];
+        stats->n_rays_positive = (int64_t)spread[2];
+        stats->n_lane_pairs = (int64_t)spread[3];
         stats->n_invalid_gaussians = (int64_t)cnt[CNT_INVALID];
         stats->total_sensitivity = S_total;
         stats->ms_project = ms[0];
@@ -837,7 +840,7 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     add(sizeof(uint64_t) * (ps.c.total_tiles + 1));
     add(sizeof(uint64_t) * scan_tmp_elems(ps.c.total_tiles + 1));
     add(sizeof(float) * (size_t)ps.c.rays);
-    add(sizeof(uint64_t) * CNT_SLOTS);
+    add(sizeof(uint64_t) * CNT_WORDS);
     add(256);
     return b;
 }
@@ -861,7 +864,7 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.tile_off = cv.take<uint64_t>(ps.c.total_tiles + 1);
     ps.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(ps.c.total_tiles + 1));
     b.ray_A = cv.take<float>(ps.c.rays);
-    b.counters = cv.take<uint64_t>(CNT_SLOTS);
+    b.counters = cv.take<uint64_t>(CNT_WORDS);
     ps.over = cv.take<uint32_t>(64);
     b.tile_active = nullptr;
 }
@@ -872,7 +875,7 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ChunkBufs &b = ps.b;
     launch_fill_u32(b.nvis, 0u, 2 * (int64_t)ps.c.vc, st);
     launch_fill_u32(b.bin_count, 0u, ps.nbins, st);
-    launch_fill_u64(b.counters, 0ull, CNT_SLOTS, st);
+    launch_fill_u64(b.counters, 0ull, CNT_WORDS, st);
     SceneDev sd{ps.sc.n, ps.sc.sh_degree, ps.sc.format, ps.sc.mean, ps.sc.log_scale,
                 ps.sc.quat, ps.sc.opacity, ps.sc.sh};
     ProjParams pp{P->p.footprint_sigma, P->p.dilation, P->p.z_near, P->p.query_mode};

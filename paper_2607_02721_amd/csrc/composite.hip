@@ -403,10 +403,11 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeA
             pos += __shfl_xor(pos, off);
         }
         if (lane == 0) {
-            atomicAdd((unsigned long long *)&counters[CNT_PAIRS], (unsigned long long)pin);
-            atomicAdd((unsigned long long *)&counters[CNT_LIVE], (unsigned long long)plive);
-            atomicAdd((unsigned long long *)&counters[CNT_RAYS_POS], (unsigned long long)pos);
-            atomicAdd((unsigned long long *)&counters[CNT_LANE_PAIRS], (unsigned long long)peval * 64ull);
+            unsigned long long *c = (unsigned long long *)counters + CNT_SLOTS + (blockIdx.x % kCntSpread);
+            atomicAdd(c + 0 * kCntSpread, (unsigned long long)pin);
+            atomicAdd(c + 1 * kCntSpread, (unsigned long long)plive);
+            atomicAdd(c + 2 * kCntSpread, (unsigned long long)pos);
+            atomicAdd(c + 3 * kCntSpread, (unsigned long long)peval * 64ull);
         }
     }
 }

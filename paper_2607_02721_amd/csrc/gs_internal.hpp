@@ -72,6 +72,12 @@ enum : int {
     CNT_PAIRS = 0, CNT_LANE_PAIRS = 1, CNT_RAYS_POS = 2, CNT_INVALID = 3, CNT_INVALID_PAIRS = 4,
     CNT_GAMMA_BITS = 5, CNT_LIVE = 6, CNT_SLOTS = 8
 };
+// The pass-2 pair counters (pairs, live pairs, positive rays, lane
+// evaluations) are each spread over kCntSpread words after the CNT_SLOTS
+// words (word CNT_SLOTS + k * kCntSpread + (block mod kCntSpread)), so that
+// the per-wave additions do not all meet on one address; the host sums them.
+constexpr int kCntSpread = 64;
+constexpr int CNT_WORDS = CNT_SLOTS + 4 * kCntSpread;
 
 // ---- launchers (each enqueues on `st`) -------------------------------------
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
