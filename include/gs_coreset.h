@@ -269,6 +269,17 @@ gs_status gs_mlp_train_step(float *params, float *adam, int64_t step, float lr, 
                             const float *norm, const float *targets, int64_t n, float *loss, float *grad,
                             void *stream);
 
+/* Learned proposal for sensitivity sampling: p_i = (1 - floor) e_i / sum e +
+ * floor / n with e_i = exp(log_s[i] - max log_s), from predicted ln s
+ * (0 < floor <= 1; every p_i >= floor / n, so the sampler stays unbiased,
+ * proof of Theorem 2).  log_s, p: device float[n] (p may alias nothing else);
+ * deterministic (order-free maximum, fixed-order FP64 sum). */
+gs_status gs_proposal_mixture(const float *log_s, int64_t n, float floor, float *p, void *stream);
+
+/* Regression targets ln(max(s_i, floor)) from exact sensitivities (floor > 0):
+ * device float[n] in and out. */
+gs_status gs_log_targets(const float *sens, int64_t n, float floor, float *out, void *stream);
+
 /* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum). */
 void gs_default_params(gs_params *params);
 

@@ -728,6 +728,39 @@ gs_status gs_feature_stats(const float *features, int64_t n, float *norm, void *
     return GS_OK;
 }
 
+gs_status gs_proposal_mixture(const float *log_s, int64_t n, float floor, float *p, void *stream) {
+    g_last_error.clear();
+    if (!log_s || !p) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (!(floor > 0.0f && floor <= 1.0f)) return fail(GS_ERR_INVALID_ARGUMENT, "floor must be in (0, 1]");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    HIP_TRY(arena_reserve(g_work[dev], mixture_scratch_bytes(n)));
+    proposal_mixture(log_s, n, floor, p, g_work[dev].base, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+gs_status gs_log_targets(const float *sens, int64_t n, float floor, float *out, void *stream) {
+    g_last_error.clear();
+    if (!sens || !out) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (!(floor > 0.0f) || !std::isfinite(floor)) return fail(GS_ERR_INVALID_ARGUMENT, "floor must be > 0");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    log_targets(sens, n, floor, out, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
 gs_status gs_mlp_forward(const float *params, const float *features, const float *norm, int64_t n, float *out,
                          void *stream) {
     g_last_error.clear();

@@ -166,6 +166,9 @@ void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *
 size_t knn_scratch_bytes(int64_t n);
 hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStream_t st);
 void feature_stats(const float *feat, int64_t n, float *norm, hipStream_t st);
+size_t mixture_scratch_bytes(int64_t n);
+void proposal_mixture(const float *y, int64_t n, float floor, float *p, void *scratch, hipStream_t st);
+void log_targets(const float *s, int64_t n, float floor, float *out, hipStream_t st);
 
 // Small utilities
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);

@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace gs {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -393,6 +395,75 @@ void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *
         hipLaunchKernelGGL(k_adam, dim3(blocks_for(kMlpParams)), dim3(256), 0, st, P, adam, m.G, (int64_t)kMlpParams,
                            lr, b1, b2, eps, c1, c2);
     }
+}
+
+}  // namespace gs
+
+namespace gs {
+
+// ---------------------------------------------------------------------------
+// Proposal mixture and training targets.
+//
+// p_i = (1 - f) e_i / sum_j e_j + f / n with e_i = exp(y_i - max_j y_j): the
+// network's predicted ln s normalised into a distribution and mixed with a
+// uniform floor f, so every Gaussian keeps p_i >= f / n (sensitivity sampling
+// stays unbiased for any such proposal, proof of Theorem 2).  The maximum is
+// an order-free integer atomic on ordered float bits and the sum is a
+// fixed-order FP64 reduction, so the result is deterministic.
+
+__device__ __forceinline__ uint32_t ordered_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_ordered(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+__global__ __launch_bounds__(256) void k_max_ordered(const float *__restrict__ y, int64_t n,
+                                                     uint32_t *__restrict__ out) {
+    uint32_t m = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = max(m, ordered_bits(y[i]));
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+__global__ __launch_bounds__(256) void k_exp_shift(const float *__restrict__ y, int64_t n,
+                                                   const uint32_t *__restrict__ ymax, float *__restrict__ e) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) e[i] = (float)exp((double)y[i] - (double)from_ordered(*ymax));
+}
+
+__global__ __launch_bounds__(256) void k_mix(float *__restrict__ p, int64_t n, const double *__restrict__ esum,
+                                             float floor) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = (float)((1.0 - (double)floor) * (double)p[i] / *esum + (double)floor / (double)n);
+}
+
+// ln(max(s, floor)): regression targets from exact sensitivities.
+__global__ __launch_bounds__(256) void k_log_floor(const float *__restrict__ s, int64_t n, float floor,
+                                                   float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (float)log((double)fmaxf(s[i], floor));
+}
+
+size_t mixture_scratch_bytes(int64_t n) { return sizeof(double) * ((size_t)(n + 4095) / 4096 + 2) + 256; }
+
+void proposal_mixture(const float *y, int64_t n, float floor, float *p, void *scratch, hipStream_t st) {
+    uint32_t *ymax = (uint32_t *)scratch;
+    double *esum = (double *)((char *)scratch + 64);
+    double *tmp = esum + 1;
+    launch_fill_u32(ymax, 0u, 1, st);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_max_ordered, dim3(blocks), dim3(256), 0, st, y, n, ymax);
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_exp_shift, dim3(g), dim3(256), 0, st, y, n, ymax, p);
+    launch_sum_f32_to_f64(p, n, esum, tmp, st);
+    hipLaunchKernelGGL(k_mix, dim3(g), dim3(256), 0, st, p, n, esum, floor);
+}
+
+void log_targets(const float *s, int64_t n, float floor, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_log_floor, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, n, floor, out);
 }
 
 }  // namespace gs

@@ -9,9 +9,10 @@ on held-out rays decides whether the draw is good enough, and the exact pass
 takes over when it is not.
 
 Every computation runs in the library's HIP kernels (gs_features,
-gs_feature_stats, gs_mlp_*, gs_sample_coreset, gs_render_objective,
-gs_sensitivity); this module only sequences them and holds the device
-buffers.
+gs_feature_stats, gs_mlp_*, gs_log_targets, gs_proposal_mixture,
+gs_sample_coreset, gs_render_objective, gs_sensitivity); this module only
+sequences them and holds the device buffers (training batches are gathered
+by index with torch: data movement only).
 """
 from __future__ import annotations
 
@@ -53,10 +54,13 @@ def feature_stats(feat, stream=None):
     return norm
 
 
-def log_targets(sens):
-    """ln(max(s, 1e-6)), computed by torch on device (target preparation)."""
+def log_targets(sens, stream=None):
+    """ln(max(s, 1e-6)) as float32 device tensor [n] (gs_log_targets)."""
     torch = _torch()
-    return torch.log(torch.clamp(sens, min=LOG_FLOOR)).float().contiguous()
+    out = torch.empty_like(sens)
+    _lib.check(load().gs_log_targets(C.c_void_p(sens.data_ptr()), sens.numel(), C.c_float(LOG_FLOOR),
+                                     C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
 
 
 class Proposal:
@@ -131,13 +135,14 @@ class Proposal:
         return losses
 
 
-def mixture(log_s_hat, floor=0.1):
-    """Proposal p = (1 - floor) s_hat / sum(s_hat) + floor / n, as float32
-    scores for gs_sample_coreset (which normalises them)."""
+def mixture(log_s_hat, floor=0.1, stream=None):
+    """Proposal p = (1 - floor) s_hat / sum(s_hat) + floor / n (gs_proposal_mixture),
+    as float32 scores for gs_sample_coreset."""
     torch = _torch()
-    s = torch.exp(log_s_hat.double() - log_s_hat.double().max())
-    p = (1.0 - floor) * s / s.sum() + floor / s.numel()
-    return p.float().contiguous()
+    p = torch.empty_like(log_s_hat)
+    _lib.check(load().gs_proposal_mixture(C.c_void_p(log_s_hat.data_ptr()), log_s_hat.numel(), C.c_float(floor),
+                                          C.c_void_p(p.data_ptr()), _stream_handle(stream)))
+    return p
 
 
 def sample_with_fallback(scene: DeviceScene, judge_views, m: int, seed: int, proposal: Proposal,

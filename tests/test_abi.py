@@ -140,3 +140,12 @@ def test_plan_argument_errors(lib):
     assert lib.gs_plan_get_info(None, None) == 1
     assert lib.gs_plan_status(None, None) == 1
     lib.gs_plan_destroy(None)
+
+
+def test_learned_helper_argument_errors(lib):
+    ok = C.c_void_p(0x1000)
+    assert lib.gs_proposal_mixture(ok, 0, C.c_float(0.1), ok, None) == 1
+    assert lib.gs_proposal_mixture(ok, 10, C.c_float(0.0), ok, None) == 1
+    assert lib.gs_proposal_mixture(None, 10, C.c_float(0.1), ok, None) == 1
+    assert lib.gs_log_targets(ok, 10, C.c_float(-1.0), ok, None) == 1
+    assert lib.gs_log_targets(ok, 10, C.c_float(1e-6), None, None) == 1

@@ -171,3 +171,20 @@ def test_fallback_runs_exact_pass(gs, L, trained):
     assert np.array_equal(out["weights"].cpu().numpy(), w_exact.cpu().numpy())
     out2 = L.sample_with_fallback(d, vw, sc.n // 10, 1, prop, mask, err_bound=1e9)
     assert not out2["fallback"]
+
+
+def test_mixture_and_targets_match_numpy(gs, L):
+    import torch
+    g = torch.Generator().manual_seed(7)
+    y = (torch.randn(100_003, generator=g) * 4 - 6)
+    p = L.mixture(y.cuda(), 0.1).double().cpu().numpy()
+    yd = y.double().numpy()
+    e = np.exp(yd - yd.max())
+    want = 0.9 * e / e.sum() + 0.1 / yd.size
+    assert np.allclose(p, want, rtol=1e-6, atol=0)
+    assert abs(p.sum() - 1.0) < 1e-5 and p.min() >= 0.1 / yd.size * (1 - 1e-6)
+    s = torch.rand(50_000, generator=g) ** 4
+    s[::7] = 0.0
+    t = L.log_targets(s.cuda()).cpu().numpy()
+    ref = np.log(np.maximum(s.double().numpy(), np.float32(L.LOG_FLOOR).astype(np.float64))).astype(np.float32)
+    assert np.array_equal(t, ref)
