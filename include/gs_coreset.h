@@ -280,6 +280,18 @@ gs_status gs_proposal_mixture(const float *log_s, int64_t n, float floor, float 
  * device float[n] in and out. */
 gs_status gs_log_targets(const float *sens, int64_t n, float floor, float *out, void *stream);
 
+/* Measured rates of the calling device, the denominators of the rooflines:
+ * a 1 GiB device copy (bytes read + written per second), FP32 FMAs (non-packed,
+ * one per lane-instruction), v_exp_f32 and dense BF16 MFMA (16x16x32,
+ * flops).  Synchronises the stream; uses 2 GiB of the scratch arena. */
+typedef struct {
+    double copy_bytes_per_s;
+    double fma_per_s;
+    double exp_per_s;
+    double mfma_bf16_flop_per_s;
+} gs_peaks;
+gs_status gs_measure_peaks(gs_peaks *out, void *stream);
+
 /* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum). */
 void gs_default_params(gs_params *params);
 

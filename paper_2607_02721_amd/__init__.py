@@ -245,6 +245,13 @@ def render_objective(scene: DeviceScene, views, weights=None, objective=OBJ_FULL
     return out
 
 
+def measure_peaks(stream=None):
+    """Measured copy bandwidth, FP32 FMA, v_exp_f32 and BF16 MFMA rates (gs_measure_peaks)."""
+    p = _lib.Peaks()
+    _lib.check(load().gs_measure_peaks(C.byref(p), _stream_handle(stream)))
+    return {k: getattr(p, k) for k, _ in p._fields_}
+
+
 def release_workspace():
     _lib.check(load().gs_release_workspace())
 

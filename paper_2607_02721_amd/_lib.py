@@ -23,7 +23,7 @@ EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_de
             "gs_mlp_init", "gs_features", "gs_feature_stats", "gs_mlp_forward", "gs_mlp_train_step",
             "gs_plan_create", "gs_plan_set_config", "gs_plan_tune", "gs_plan_get_info",
             "gs_plan_sensitivity", "gs_plan_status", "gs_plan_destroy", "gs_proposal_mixture",
-            "gs_log_targets"]
+            "gs_log_targets", "gs_measure_peaks"]
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 FLAG_COUNT_PAIRS = 1
@@ -76,6 +76,11 @@ class PlanInfo(C.Structure):
                 ("list_capacity", C.c_int64)]
 
 
+class Peaks(C.Structure):
+    _fields_ = [("copy_bytes_per_s", C.c_double), ("fma_per_s", C.c_double), ("exp_per_s", C.c_double),
+                ("mfma_bf16_flop_per_s", C.c_double)]
+
+
 class RenderDiag(C.Structure):
     _fields_ = [("n_invalid_pairs", C.c_int64), ("gamma_max", C.c_double)]
 
@@ -126,12 +131,13 @@ def load(path: str = LIB_PATH):
         lib.gs_plan_status.argtypes = [P, P]
         lib.gs_proposal_mixture.argtypes = [P, C.c_int64, C.c_float, P, P]
         lib.gs_log_targets.argtypes = [P, C.c_int64, C.c_float, P, P]
+        lib.gs_measure_peaks.argtypes = [P, P]
         lib.gs_plan_destroy.argtypes = [P]
         lib.gs_plan_destroy.restype = None
         for f in (lib.gs_mlp_init, lib.gs_features, lib.gs_feature_stats, lib.gs_mlp_forward,
                   lib.gs_mlp_train_step, lib.gs_plan_create, lib.gs_plan_set_config, lib.gs_plan_tune,
                   lib.gs_plan_get_info, lib.gs_plan_sensitivity, lib.gs_plan_status, lib.gs_proposal_mixture,
-                  lib.gs_log_targets):
+                  lib.gs_log_targets, lib.gs_measure_peaks):
             f.restype = C.c_int
         _lib = lib
     return _lib

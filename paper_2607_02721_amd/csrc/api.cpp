@@ -761,6 +761,24 @@ gs_status gs_log_targets(const float *sens, int64_t n, float floor, float *out, 
     return GS_OK;
 }
 
+gs_status gs_measure_peaks(gs_peaks *out, void *stream) {
+    g_last_error.clear();
+    if (!out) return fail(GS_ERR_INVALID_ARGUMENT, "out is NULL");
+    memset(out, 0, sizeof(*out));
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    const size_t bytes = (size_t)2 << 30;   // 1 GiB copied into another 1 GiB
+    HIP_TRY(arena_reserve(g_work[dev], bytes));
+    HIP_TRY(measure_peaks(&out->copy_bytes_per_s, &out->fma_per_s, &out->exp_per_s, &out->mfma_bf16_flop_per_s,
+                          g_work[dev].base, bytes, st));
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
 gs_status gs_mlp_forward(const float *params, const float *features, const float *norm, int64_t n, float *out,
                          void *stream) {
     g_last_error.clear();

@@ -169,6 +169,8 @@ void feature_stats(const float *feat, int64_t n, float *norm, hipStream_t st);
 size_t mixture_scratch_bytes(int64_t n);
 void proposal_mixture(const float *y, int64_t n, float floor, float *p, void *scratch, hipStream_t st);
 void log_targets(const float *s, int64_t n, float floor, float *out, hipStream_t st);
+hipError_t measure_peaks(double *copy_bytes_per_s, double *fma_per_s, double *exp_per_s, double *mfma_flop_per_s,
+                         void *scratch, size_t scratch_bytes, hipStream_t st);
 
 // Small utilities
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
