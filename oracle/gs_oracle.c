@@ -519,6 +519,193 @@ int ora_sensitivity(const ora_scene *g, const ora_views *vw, const ora_params *p
 }
 
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Aggregated sensitivities (Section 3.4, per-tile, per-image and per-scene
+ * queries).  A query Q is a set of rays; a Gaussian's contribution to it is
+ * a_i(Q) = sum over q in Q of a_i(q), the query objective is A(Q) = sum over
+ * q in Q of A(q), and s_i = max over queries with A(Q) > 0 of a_i(Q) / A(Q).
+ * level 1: Q = the rays of one 16x16 pixel tile of one view (ragged at the
+ * right and bottom edges); level 2: Q = the rays of one view; level 3: one
+ * query holding every ray.  Only rays selected by the mask belong to queries.
+ * The 16-row bands the threads take are tile rows, so a band holds whole
+ * tiles: after a Gaussian's visit the band knows its contribution to each
+ * tile of the row.                                                          */
+typedef struct {
+    const ora_scene *g;
+    const ora_views *vw;
+    const ora_params *prm;
+    const uint32_t *ray_mask;
+    int32_t view, level;
+    int64_t ray_base;
+    int32_t n_threads, tid;
+    ora_view_setup *setup;
+    double *s_thread;   /* level 1: this worker's max over its tiles [n] */
+    double *num;        /* levels 2, 3: this worker's sum of a_i over its rays [n] */
+    double den;         /* levels 2, 3: this worker's sum of A over its rays */
+} agg_worker;
+
+static void *agg_worker_main(void *arg)
+{
+    agg_worker *w = (agg_worker *)arg;
+    const double r2 = w->prm->footprint_sigma * w->prm->footprint_sigma;
+    const int32_t v = w->view;
+    const int32_t W = w->vw->size[2 * v], H = w->vw->size[2 * v + 1];
+    const int32_t tiles_x = (W + 15) / 16;
+    ora_view_setup *S = w->setup;
+    double *tile_sum = (double *)calloc((size_t)tiles_x, sizeof(double));
+    double *tile_A = (double *)malloc(sizeof(double) * (size_t)tiles_x);
+    for (int32_t y0 = w->tid * 16; y0 < H; y0 += w->n_threads * 16) {
+        const int32_t y1 = y0 + 16 < H ? y0 + 16 : H;
+        const int64_t npix = (int64_t)(y1 - y0) * W;
+        const int64_t base = w->ray_base + (int64_t)y0 * W;
+        double *T = (double *)malloc(sizeof(double) * (size_t)npix);
+        double *A = (double *)calloc((size_t)npix, sizeof(double));
+        uint8_t *sel = (uint8_t *)malloc((size_t)npix);
+        int any = 0;
+        for (int64_t p = 0; p < npix; ++p) {
+            sel[p] = (uint8_t)ray_selected(w->ray_mask, base + p);
+            any |= sel[p];
+            T[p] = 1.0;
+        }
+        if (any) {
+            /* A(q) for every selected ray of the band, front to back */
+            for (int64_t k = 0; k < S->n_present; ++k) {
+                const ora_proj *o = &S->proj[S->order[k].idx];
+                int32_t ylo, yhi, xlo, xhi;
+                pixel_range(o->my, o->ry, H, &ylo, &yhi);
+                if (yhi < y0 || ylo >= y1) continue;
+                if (ylo < y0) ylo = y0;
+                if (yhi > y1 - 1) yhi = y1 - 1;
+                pixel_range(o->mx, o->rx, W, &xlo, &xhi);
+                for (int32_t py = ylo; py <= yhi; ++py)
+                    for (int32_t px = xlo; px <= xhi; ++px) {
+                        int64_t p = (int64_t)(py - y0) * W + px;
+                        if (!sel[p]) continue;
+                        double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
+                        double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
+                        if (d2 > r2) continue;
+                        double rho = o->alpha * exp(-0.5 * d2);
+                        A[p] += o->cbar * rho * T[p];
+                        T[p] *= (1.0 - rho);
+                    }
+            }
+            /* query objectives: per tile of the row, or summed into den */
+            for (int32_t tx = 0; tx < tiles_x; ++tx) tile_A[tx] = 0.0;
+            for (int64_t p = 0; p < npix; ++p) {
+                T[p] = 1.0;
+                if (!sel[p]) continue;
+                if (w->level == 1) tile_A[(p % W) / 16] += A[p];
+                else w->den += A[p];
+            }
+            /* contributions a_i(q) summed over each query's rays */
+            for (int64_t k = 0; k < S->n_present; ++k) {
+                const int64_t i = S->order[k].idx;
+                const ora_proj *o = &S->proj[i];
+                int32_t ylo, yhi, xlo, xhi;
+                pixel_range(o->my, o->ry, H, &ylo, &yhi);
+                if (yhi < y0 || ylo >= y1) continue;
+                if (ylo < y0) ylo = y0;
+                if (yhi > y1 - 1) yhi = y1 - 1;
+                pixel_range(o->mx, o->rx, W, &xlo, &xhi);
+                for (int32_t py = ylo; py <= yhi; ++py)
+                    for (int32_t px = xlo; px <= xhi; ++px) {
+                        int64_t p = (int64_t)(py - y0) * W + px;
+                        if (!sel[p]) continue;
+                        double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
+                        double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
+                        if (d2 > r2) continue;
+                        double rho = o->alpha * exp(-0.5 * d2);
+                        double a = o->cbar * rho * T[p];
+                        if (w->level == 1) tile_sum[px / 16] += a;
+                        else w->num[i] += a;
+                        T[p] *= (1.0 - rho);
+                    }
+                if (w->level == 1)
+                    for (int32_t tx = xlo / 16; tx <= xhi / 16; ++tx) {
+                        if (tile_A[tx] > 0.0) {
+                            double share = tile_sum[tx] / tile_A[tx];
+                            if (share > w->s_thread[i]) w->s_thread[i] = share;
+                        }
+                        tile_sum[tx] = 0.0;
+                    }
+            }
+        }
+        free(T); free(A); free(sel);
+    }
+    free(tile_sum); free(tile_A);
+    return NULL;
+}
+
+/* s: [n] out, the aggregated sensitivities of `level` (1 tile, 2 image,
+ * 3 scene).  Views one after another; threads split each view's tile rows;
+ * per-image and per-scene sums are merged in thread order.                  */
+int ora_sensitivity_agg(const ora_scene *g, const ora_views *vw, const ora_params *prm,
+                        const uint32_t *ray_mask, int32_t level, double *s)
+{
+    if (level < 1 || level > 3) return 1;
+    const int32_t V = vw->n_views;
+    const int nt = prm->n_threads > 0 ? prm->n_threads : 1;
+    agg_worker *ws = (agg_worker *)calloc((size_t)nt, sizeof(agg_worker));
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nt);
+    double *num = (double *)calloc((size_t)g->n, sizeof(double));   /* scene level */
+    double den = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        ws[t].s_thread = (double *)calloc((size_t)g->n, sizeof(double));
+        ws[t].num = (double *)calloc((size_t)g->n, sizeof(double));
+    }
+    for (int64_t i = 0; i < g->n; ++i) s[i] = 0.0;
+    int64_t ray_base = 0;
+    for (int32_t v = 0; v < V; ++v) {
+        const int32_t W = vw->size[2 * v], H = vw->size[2 * v + 1];
+        const int64_t nrays = (int64_t)W * H;
+        uint8_t *band_used = (uint8_t *)calloc((size_t)(H / 16 + 1), 1);
+        int any = 0;
+        for (int32_t y = 0; y < H; ++y) {
+            int row_any = ray_mask == NULL;
+            for (int32_t x = 0; x < W && !row_any; ++x) row_any = ray_selected(ray_mask, ray_base + (int64_t)y * W + x);
+            if (row_any) { band_used[y / 16] = 1; any = 1; }
+        }
+        if (any) {
+            ora_view_setup S;
+            setup_view_threaded(g, vw, prm, v, nt, band_used, &S);
+            for (int t = 0; t < nt; ++t) {
+                agg_worker *w = &ws[t];
+                w->g = g; w->vw = vw; w->prm = prm; w->ray_mask = ray_mask; w->view = v; w->level = level;
+                w->ray_base = ray_base; w->n_threads = nt; w->tid = t; w->setup = &S; w->den = 0.0;
+                pthread_create(&th[t], NULL, agg_worker_main, w);
+            }
+            for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+            free_view(&S);
+            if (level >= 2) {
+                /* the view's sums, thread by thread */
+                double dv = 0.0;
+                for (int t = 0; t < nt; ++t) dv += ws[t].den;
+                for (int64_t i = 0; i < g->n; ++i) {
+                    double nv = 0.0;
+                    for (int t = 0; t < nt; ++t) { nv += ws[t].num[i]; ws[t].num[i] = 0.0; }
+                    if (level == 2) {
+                        if (dv > 0.0 && nv / dv > s[i]) s[i] = nv / dv;
+                    } else {
+                        num[i] += nv;
+                    }
+                }
+                den += dv;
+            }
+        }
+        free(band_used);
+        ray_base += nrays;
+    }
+    if (level == 1)
+        for (int t = 0; t < nt; ++t)
+            for (int64_t i = 0; i < g->n; ++i)
+                if (ws[t].s_thread[i] > s[i]) s[i] = ws[t].s_thread[i];
+    if (level == 3 && den > 0.0)
+        for (int64_t i = 0; i < g->n; ++i) s[i] = num[i] / den;
+    for (int t = 0; t < nt; ++t) { free(ws[t].s_thread); free(ws[t].num); }
+    free(ws); free(th); free(num);
+    return 0;
+}
+
 /* Objectives (Section 3): full render A, fixed relaxation
  * A^th_w = sum_i w_i a_i (full-scene transmittance), true reduced render
  * A_w = sum_i w_i c_i rho_i T_w,i with T_w,i = prod_{j before i} (1 - w_j rho_j).

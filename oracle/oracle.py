@@ -61,6 +61,7 @@ def _load():
         _lib = C.CDLL(_LIB)
         P = C.c_void_p
         _lib.ora_sensitivity.argtypes = [P, P, P, P, P, P, P, P]
+        _lib.ora_sensitivity_agg.argtypes = [P, P, P, P, C.c_int32, P]
         _lib.ora_objective.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
         _lib.ora_sample.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, P, P, P, P]
         _lib.ora_philox4x32_10.argtypes = [P, P, P]
@@ -68,7 +69,7 @@ def _load():
         _lib.ora_draw_target.argtypes = [P, C.c_uint64]
         _lib.ora_draw_target.restype = C.c_uint64
         _lib.ora_sh_basis.argtypes = [C.c_double, C.c_double, C.c_double, P]
-        for f in (_lib.ora_sensitivity, _lib.ora_objective, _lib.ora_sample):
+        for f in (_lib.ora_sensitivity, _lib.ora_sensitivity_agg, _lib.ora_objective, _lib.ora_sample):
             f.restype = C.c_int
     return _lib
 
@@ -122,6 +123,25 @@ def sensitivity(scene, views, params=None, ray_mask=None):
     assert rc == 0
     return {"s": s, "A": A, "flag": flag.astype(bool), "pairs": int(cnt[0]),
             "live_pairs": int(cnt[1]), "rays_positive": int(cnt[2])}
+
+
+AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE = 0, 1, 2, 3
+
+
+def sensitivity_agg(scene, views, level, params=None, ray_mask=None):
+    """Aggregated sensitivities s[n] (float64) for queries that are 16x16
+    tiles (level 1), whole views (2) or the whole scene (3): the maximum over
+    queries of a_i(Q) / A(Q) with both summed over the query's rays
+    (Section 3.4).  Level 0 is the per-ray sensitivity."""
+    if level == AGG_RAY:
+        return sensitivity(scene, views, params, ray_mask)["s"]
+    lib = _load()
+    k = _Keep(scene, views, params or default_params())
+    s = np.zeros(scene.n, np.float64)
+    mask = None if ray_mask is None else np.ascontiguousarray(ray_mask, np.uint32)
+    rc = lib.ora_sensitivity_agg(C.byref(k.s), C.byref(k.v), C.byref(k.p), _ptr(mask), int(level), _ptr(s))
+    assert rc == 0
+    return s
 
 
 def objective(scene, views, weights, params=None, ray_mask=None):

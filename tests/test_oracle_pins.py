@@ -13,7 +13,8 @@ import numpy as np
 import pytest
 
 import synth
-from synth import make_explicit_scene, make_camera_set, pack_bits
+from synth import (make_camera_set, make_cluster_scene, make_explicit_scene, make_orbit_views, make_tiny_scene,
+                   make_tiny_views, pack_bits)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ID_Q = (1.0, 0.0, 0.0, 0.0)
@@ -345,24 +346,14 @@ def test_adding_views_never_lowers_sensitivity(ora):
     assert np.all(s4 >= s2)
 
 
-def test_bruteforce_mpmath_tiny(ora):
+def _mp_ray_contributions(sc, vw, W, H):
     """All (ray, Gaussian) pairs in 50-digit arithmetic, no bounding boxes, no
-    sorting shortcuts: the oracle's sensitivities agree to ~1e-13."""
+    sorting shortcuts: {(view, px, py): (A, [(i, a_i)])} over every ray."""
     import mpmath as mp
     mp.mp.dps = 50
-    rng = np.random.default_rng(11)
-    n, W, H = 6, 10, 8
-    means = rng.uniform(-0.15, 0.15, (n, 3))
-    ls = rng.normal(-2.6, 0.2, (n, 3))
-    q = rng.standard_normal((n, 4))
-    op = rng.uniform(0.2, 0.9, n)
-    col = rng.uniform(0, 1, (n, 3))
-    sc = make_explicit_scene(means, ls, q, op, col)
-    vw = make_camera_set([(2.0, 0.5, 0.4), (-0.3, -2.0, 0.6)], [(0, 0, 0)] * 2, W, H, 40.0)
-    prm = ora.default_params(dilation=0.3)
-    r = ora.sensitivity(sc, vw, prm)
-    s_ref = [mp.mpf(0)] * n
-    for v in range(2):
+    n = sc.n
+    out = {}
+    for v in range(vw.n_views):
         P = [[mp.mpf(float(x)) for x in vw.world_to_cam[v][4 * k:4 * k + 4]] for k in range(3)]
         fx, fy, cx, cy = [mp.mpf(float(x)) for x in vw.intrinsics[v]]
         camc = [-(P[0][c] * P[0][3] + P[1][c] * P[1][3] + P[2][c] * P[2][3]) for c in range(3)]
@@ -386,7 +377,6 @@ def test_bruteforce_mpmath_tiny(ora):
             inv = C2 ** -1
             m2 = (fx * x / z + cx, fy * y / z + cy)
             d = [mu[k] - camc[k] for k in range(3)]
-            dn = mp.sqrt(sum(t * t for t in d))
             cbar = 0
             for ch in range(3):
                 c = mp.mpf(float(sc.sh[0, ch, i])) * mp.mpf(1) / (2 * mp.sqrt(mp.pi)) + mp.mpf("0.5")
@@ -407,12 +397,88 @@ def test_bruteforce_mpmath_tiny(ora):
                     contrib.append((i, a))
                     A += a
                     T *= 1 - rho
-                if A > 0:
-                    for i, a in contrib:
-                        s_ref[i] = max(s_ref[i], a / A)
+                out[(v, px, py)] = (A, contrib)
+    return out
+
+
+def _bruteforce_scene(n, W, H, seed):
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-0.15, 0.15, (n, 3))
+    ls = rng.normal(-2.6, 0.2, (n, 3))
+    q = rng.standard_normal((n, 4))
+    op = rng.uniform(0.2, 0.9, n)
+    col = rng.uniform(0, 1, (n, 3))
+    sc = make_explicit_scene(means, ls, q, op, col)
+    vw = make_camera_set([(2.0, 0.5, 0.4), (-0.3, -2.0, 0.6)], [(0, 0, 0)] * 2, W, H, 40.0)
+    return sc, vw
+
+
+def test_bruteforce_mpmath_tiny(ora):
+    """The oracle's per-ray sensitivities agree with 50-digit brute force to ~1e-13."""
+    import mpmath as mp
+    n, W, H = 6, 10, 8
+    sc, vw = _bruteforce_scene(n, W, H, 11)
+    r = ora.sensitivity(sc, vw, ora.default_params(dilation=0.3))
+    s_ref = [mp.mpf(0)] * n
+    for (A, contrib) in _mp_ray_contributions(sc, vw, W, H).values():
+        if A > 0:
+            for i, a in contrib:
+                s_ref[i] = max(s_ref[i], a / A)
     ref = np.array([float(x) for x in s_ref])
     assert (ref > 0).sum() >= 4
     assert np.allclose(r["s"], ref, rtol=1e-12, atol=1e-300)
+
+
+def test_bruteforce_mpmath_aggregated(ora):
+    """Per-tile (16x16, ragged at the edges), per-image and per-scene
+    sensitivities (Section 3.4): a_i and A summed over each query's rays in
+    50-digit arithmetic, then the maximum over queries of their ratio."""
+    import mpmath as mp
+    n, W, H = 6, 20, 18              # 2 x 2 tiles per view, the right and bottom ones ragged
+    sc, vw = _bruteforce_scene(n, W, H, 12)
+    rays = _mp_ray_contributions(sc, vw, W, H)
+    keys = {1: lambda v, px, py: (v, px // 16, py // 16), 2: lambda v, px, py: v, 3: lambda v, px, py: 0}
+    for level in (1, 2, 3):
+        num, den = {}, {}
+        for (v, px, py), (A, contrib) in rays.items():
+            k = keys[level](v, px, py)
+            den[k] = den.get(k, mp.mpf(0)) + A
+            for i, a in contrib:
+                num[(k, i)] = num.get((k, i), mp.mpf(0)) + a
+        s_ref = [mp.mpf(0)] * n
+        for (k, i), a in num.items():
+            if den[k] > 0:
+                s_ref[i] = max(s_ref[i], a / den[k])
+        ref = np.array([float(x) for x in s_ref])
+        got = ora.sensitivity_agg(sc, vw, level, ora.default_params(dilation=0.3))
+        assert (ref > 0).sum() >= 4, level
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-300), (level, got, ref)
+
+
+def test_aggregated_invariants(ora):
+    """Per-scene S = 1 (the contributions of all Gaussians to a query sum to
+    its objective); coarser queries average finer ones with weights A, so
+    s_scene <= s_image <= s_tile <= s_ray elementwise; 1 <= S <= number of
+    queries with A > 0."""
+    for sc, vw in ((make_tiny_scene(2000, 0), make_tiny_views()),
+                   (make_cluster_scene(6000, 7, 3), make_orbit_views(3, 17, 200, 136))):
+        r = ora.sensitivity(sc, vw)
+        s = [r["s"]] + [ora.sensitivity_agg(sc, vw, L) for L in (1, 2, 3)]
+        assert abs(s[3].sum() - 1.0) < 1e-12
+        for fine, coarse in zip(s[:-1], s[1:]):
+            assert np.all(coarse <= fine * (1 + 1e-12) + 1e-300)
+        A = r["A"]
+        n_tiles_pos, n_views_pos, base = 0, 0, 0
+        for v in range(vw.n_views):
+            W, H = vw.size[v]
+            img = A[base:base + W * H].reshape(H, W)
+            base += W * H
+            n_views_pos += img.sum() > 0
+            for ty in range(0, H, 16):
+                for tx in range(0, W, 16):
+                    n_tiles_pos += img[ty:ty + 16, tx:tx + 16].sum() > 0
+        assert 1.0 - 1e-12 <= s[2].sum() <= n_views_pos
+        assert 1.0 - 1e-12 <= s[1].sum() <= n_tiles_pos
 
 
 # --------------------------------------------------------------------------
