@@ -56,6 +56,14 @@ typedef enum { GS_OBJ_FULL = 0, GS_OBJ_FIXED = 1, GS_OBJ_TRUE = 2 } gs_objective
 /* GS_FLAG_COUNT_PAIRS: gs_sensitivity fills the pair counters of gs_stats
  * (a pass-2 variant that counts; without it those counters read 0). */
 typedef enum { GS_FLAG_COUNT_PAIRS = 1 } gs_flag;
+/* Query granularity of the sensitivity (Section 3.4, practical extensions):
+ * a query is one ray (GS_AGG_RAY, Eq. sen), the rays of one 16x16 pixel tile
+ * of a view (ragged at the right and bottom edges), the rays of one view, or
+ * every ray (the per-scene variant).  For an aggregated query Q,
+ * a_i(Q) = sum over its rays of a_i(q), A(Q) = sum of A(q), and
+ * s_i = max over queries with A(Q) > 0 of a_i(Q) / A(Q); only rays selected
+ * by the ray mask belong to queries. */
+typedef enum { GS_AGG_RAY = 0, GS_AGG_TILE = 1, GS_AGG_IMAGE = 2, GS_AGG_SCENE = 3 } gs_aggregate;
 
 /* Scene G = {(mu_i, Sigma_i, alpha_i, c_i)} (Section 3, "3DGS scene"), as
  * structure-of-arrays planes in device memory, n Gaussians.
@@ -98,6 +106,7 @@ typedef struct {
     int32_t max_views_per_chunk; /* 0 = as many as the scratch budget allows */
     int32_t flags;            /* GS_FLAG_* bits */
     const uint32_t *ray_mask; /* device bitset over all rays (bit r%32 of word r/32), NULL = all */
+    int32_t aggregate;        /* gs_aggregate: query granularity of gs_sensitivity; default GS_AGG_RAY */
 } gs_params;
 
 /* Filled only when a non-NULL pointer is passed (the call then synchronises
@@ -129,7 +138,10 @@ typedef struct {
  * Rays outside params->ray_mask are not scored.  Rays stop once the largest
  * possible remaining share is below params->share_floor, so every s_i below
  * that floor may read 0.  Synchronises the stream once per view chunk (to
- * size the tile lists).  stats may be NULL. */
+ * size the tile lists).  stats may be NULL.  params->aggregate selects the
+ * query granularity (gs_aggregate); aggregated sums are accumulated in exact
+ * 64-bit fixed point, so every granularity is deterministic.  The pair
+ * counters (GS_FLAG_COUNT_PAIRS) need GS_AGG_RAY. */
 gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_params *params,
                          float *sens, gs_stats *stats, void *stream);
 
@@ -292,7 +304,8 @@ typedef struct {
 } gs_peaks;
 gs_status gs_measure_peaks(gs_peaks *out, void *stream);
 
-/* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum). */
+/* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum,
+ * per-ray queries). */
 void gs_default_params(gs_params *params);
 
 /* Frees the calling device's scratch arena (waits for the device first). */

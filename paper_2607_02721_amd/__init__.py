@@ -18,12 +18,13 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (ATTR_F32, ATTR_MIXED16, GsError, OBJ_FIXED, OBJ_FULL, OBJ_TRUE,
-                   QUERY_NOCOLOR, QUERY_RGBSUM, load)
+from ._lib import (AGG_IMAGE, AGG_RAY, AGG_SCENE, AGG_TILE, ATTR_F32, ATTR_MIXED16, GsError, OBJ_FIXED,
+                   OBJ_FULL, OBJ_TRUE, QUERY_NOCOLOR, QUERY_RGBSUM, load)
 
 __all__ = ["DeviceScene", "sensitivity", "sample_coreset", "render_objective", "GsError",
            "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "ATTR_F32",
-           "ATTR_MIXED16", "load", "release_workspace", "Plan"]
+           "ATTR_MIXED16", "AGG_RAY", "AGG_TILE", "AGG_IMAGE", "AGG_SCENE", "load", "release_workspace",
+           "Plan", "measure_peaks"]
 
 
 def _torch():
@@ -87,9 +88,10 @@ def _views(views):
 
 
 def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
-            max_views_per_chunk, flags=0):
+            max_views_per_chunk, flags=0, aggregate=AGG_RAY):
     p = _lib.default_params()
     p.flags = flags
+    p.aggregate = aggregate
     p.footprint_sigma = footprint_sigma
     p.dilation = dilation
     p.z_near = z_near
@@ -105,15 +107,17 @@ def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask
 
 def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
                 share_floor=1e-12, query_mode=QUERY_RGBSUM, ray_mask=None,
-                max_views_per_chunk=0, stats=False, count_pairs=False, out=None, stream=None):
-    """Per-Gaussian sensitivities (float32 device tensor [n]); with stats=True
-    also a dict of counters and per-stage device milliseconds (pair counters
-    need count_pairs=True)."""
+                max_views_per_chunk=0, stats=False, count_pairs=False, aggregate=AGG_RAY, out=None,
+                stream=None):
+    """Per-Gaussian sensitivities (float32 device tensor [n]) for queries of
+    the given granularity (AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE); with
+    stats=True also a dict of counters and per-stage device milliseconds
+    (pair counters need count_pairs=True)."""
     torch = _torch()
     lib = load()
     hv = _views(views)
     p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
-                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0)
+                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0, aggregate)
     if out is None:
         out = torch.empty(scene.n, dtype=torch.float32, device=scene.opacity.device)
     sc = scene.c_struct()

@@ -27,6 +27,7 @@ EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_de
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 FLAG_COUNT_PAIRS = 1
+AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE = 0, 1, 2, 3
 QUERY_RGBSUM, QUERY_NOCOLOR = 0, 1
 ATTR_F32, ATTR_MIXED16 = 0, 1
 
@@ -51,7 +52,8 @@ class Views(C.Structure):
 class Params(C.Structure):
     _fields_ = [("footprint_sigma", C.c_float), ("dilation", C.c_float), ("z_near", C.c_float),
                 ("share_floor", C.c_float), ("query_mode", C.c_int32),
-                ("max_views_per_chunk", C.c_int32), ("flags", C.c_int32), ("ray_mask", C.c_void_p)]
+                ("max_views_per_chunk", C.c_int32), ("flags", C.c_int32), ("ray_mask", C.c_void_p),
+                ("aggregate", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -47,7 +47,7 @@ struct Arena {
     int device = -1;
 };
 constexpr int kMaxDevices = 16;
-Arena g_work[kMaxDevices], g_lists[kMaxDevices];
+Arena g_work[kMaxDevices], g_lists[kMaxDevices], g_agg[kMaxDevices];
 // Recorded at the end of every call on the call's stream; the next call waits
 // for it on its own stream, so the shared arenas are never used by two
 // streams at once.
@@ -110,6 +110,7 @@ struct ChunkPlan {
 struct Setup {
     int64_t N;
     int nchunks;
+    int agg = GS_AGG_RAY;       // query granularity of the sensitivity pass
     std::vector<int> tiles_x, tiles_y;
     std::vector<int64_t> ray_base;
 };
@@ -138,6 +139,10 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
     add(sizeof(double) * 3 * 4 * (size_t)c.total_tiles);   // objective partials
     add(sizeof(double) * (3 * (size_t)c.vc + 1));
+    add(sizeof(double) * (size_t)c.total_tiles);            // per-tile A(Q)
+    add(sizeof(double) * ((size_t)c.vc + 1));               // per-view A(Q), launch total
+    if (S.agg == GS_AGG_IMAGE) add(sizeof(uint64_t) * (size_t)c.vc * N);   // per (view, Gaussian) shares
+    if (S.agg == GS_AGG_SCENE) add(sizeof(uint64_t) * (size_t)N);          // per Gaussian shares
     return b + (64 << 10);  // slack for the per-buffer alignment
 }
 
@@ -199,6 +204,10 @@ gs_status check_params(const gs_params *p) {
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown query_mode %d", p->query_mode);
     if (p->max_views_per_chunk < 0) return fail(GS_ERR_INVALID_ARGUMENT, "max_views_per_chunk must be >= 0");
     if (p->flags & ~GS_FLAG_COUNT_PAIRS) return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", p->flags);
+    if (p->aggregate < GS_AGG_RAY || p->aggregate > GS_AGG_SCENE)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown aggregate %d", p->aggregate);
+    if (p->aggregate != GS_AGG_RAY && (p->flags & GS_FLAG_COUNT_PAIRS))
+        return fail(GS_ERR_UNSUPPORTED, "pair counting needs per-ray queries");
     return GS_OK;
 }
 
@@ -271,6 +280,9 @@ struct ChunkRun {
     double *sum_tmp = nullptr;
     double *tile_sums = nullptr;
     double *view_sums = nullptr;
+    double *tile_A = nullptr;      // aggregated queries: A(Q) per tile, per view (+ the launch total)
+    double *view_A = nullptr;
+    uint64_t *acc = nullptr;       // aggregated shares (fixed point); per list entry for tiles
     int64_t n_entries = 0;
 };
 
@@ -310,6 +322,11 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     r.sum_tmp = cv.take<double>((N + 4095) / 4096 + 2);
     r.tile_sums = cv.take<double>(3 * 4 * (size_t)c.total_tiles);
     r.view_sums = cv.take<double>(3 * (size_t)c.vc + 1);
+    r.tile_A = cv.take<double>(c.total_tiles);
+    r.view_A = cv.take<double>((size_t)c.vc + 1);
+    r.acc = nullptr;
+    if (S.agg == GS_AGG_IMAGE) r.acc = cv.take<uint64_t>((size_t)c.vc * N);
+    if (S.agg == GS_AGG_SCENE) r.acc = cv.take<uint64_t>((size_t)N);
 
     hv.assign(c.vc, ViewDev{});
     htv.assign(c.total_tiles, 0);
@@ -372,8 +389,11 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(hipStreamSynchronize(st));
     r.n_entries = (int64_t)total;
     const size_t list_bytes = ((std::max<size_t>(total, 1) * sizeof(uint32_t) + 255) & ~(size_t)255);
-    HIP_TRY(arena_reserve(g_lists[dev], list_bytes));
+    // per-tile queries keep one accumulator per list entry, after the lists
+    const size_t acc_bytes = S.agg == GS_AGG_TILE ? std::max<size_t>(total, 1) * sizeof(uint64_t) : 0;
+    HIP_TRY(arena_reserve(g_lists[dev], list_bytes + acc_bytes));
     b.lists = (uint32_t *)g_lists[dev].base;
+    if (S.agg == GS_AGG_TILE) r.acc = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
     tm.mark(6, st);
     launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, st);
     HIP_TRY(hipGetLastError());
@@ -442,6 +462,7 @@ void gs_default_params(gs_params *p) {
     p->max_views_per_chunk = 0;
     p->flags = 0;
     p->ray_mask = nullptr;
+    p->aggregate = GS_AGG_RAY;
 }
 
 const char *gs_last_error(void) { return g_last_error.c_str(); }
@@ -465,7 +486,7 @@ gs_status gs_release_workspace(void) {
     const int dev = current_device(&s);
     if (dev < 0) return s;
     HIP_TRY(hipDeviceSynchronize());
-    for (Arena *a : {&g_work[dev], &g_lists[dev]}) {
+    for (Arena *a : {&g_work[dev], &g_lists[dev], &g_agg[dev]}) {
         if (a->base) hipFree(a->base);
         a->base = nullptr;
         a->cap = 0;
@@ -490,8 +511,19 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     DoneGuard done_guard{dev, st};
     S.N = scene->n;
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
+    S.agg = params->aggregate;
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
     launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
+    // per-scene queries: the absolute contributions and A summed over chunks
+    double *agg_num = nullptr, *agg_den = nullptr;
+    if (S.agg == GS_AGG_SCENE) {
+        const size_t nb = ((size_t)S.N * sizeof(double) + 255) & ~(size_t)255;
+        HIP_TRY(arena_reserve(g_agg[dev], nb + 256));
+        agg_num = (double *)g_agg[dev].base;
+        agg_den = (double *)((char *)g_agg[dev].base + nb);
+        launch_fill_u64((uint64_t *)agg_num, 0ull, S.N, st);
+        launch_fill_u64((uint64_t *)agg_den, 0ull, 1, st);
+    }
     HIP_TRY(hipGetLastError());
     Timer tm(stats != nullptr);
     double ms[6] = {0, 0, 0, 0, 0, 0};
@@ -513,8 +545,23 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         launch_composite_pass1(a, st);
         HIP_TRY(hipGetLastError());
         tm.mark(4, st);
+        if (S.agg != GS_AGG_RAY) {
+            double *total = r.view_A + c.vc;
+            launch_query_sums(a, c.vc, r.tile_A, r.view_A, S.agg == GS_AGG_SCENE ? total : nullptr, st);
+            a.agg = S.agg;
+            a.query_A = S.agg == GS_AGG_TILE ? r.tile_A : (S.agg == GS_AGG_IMAGE ? r.view_A : total);
+            a.acc = r.acc;
+            const int64_t n_acc = S.agg == GS_AGG_TILE ? std::max<int64_t>(r.n_entries, 1)
+                                                       : (S.agg == GS_AGG_IMAGE ? (int64_t)c.vc * S.N : S.N);
+            launch_fill_u64(r.acc, 0ull, n_acc, st);
+        }
         launch_composite_pass2(a, (params->flags & GS_FLAG_COUNT_PAIRS) != 0, r.b.counters, st);
         HIP_TRY(hipGetLastError());
+        if (S.agg != GS_AGG_RAY) {
+            launch_agg_finalize(S.agg, r.acc, r.b.lists, (uint64_t)r.n_entries, S.N, c.vc, (uint32_t *)sens,
+                                agg_num, agg_den, r.view_A + c.vc, st);
+            HIP_TRY(hipGetLastError());
+        }
         tm.mark(5, st);
         if (stats) {
             std::vector<uint32_t> nv(c.vc);
@@ -524,6 +571,10 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
             ms[3] += tm.ms(3, 4);
             ms[4] += tm.ms(4, 5);
         }
+    }
+    if (S.agg == GS_AGG_SCENE) {
+        launch_div_f64_to_f32(agg_num, agg_den, S.N, sens, st);
+        HIP_TRY(hipGetLastError());
     }
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -1083,6 +1134,7 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
     gs_status s;
     if ((s = check_params(params)) != GS_OK) return s;
     if (params->ray_mask) return fail(GS_ERR_UNSUPPORTED, "plans do not take a ray mask");
+    if (params->aggregate != GS_AGG_RAY) return fail(GS_ERR_UNSUPPORTED, "plans compute per-ray sensitivities");
     if (params->flags) return fail(GS_ERR_UNSUPPORTED, "plans do not count pairs");
     gs_plan *P = new gs_plan();
     P->p = *params;

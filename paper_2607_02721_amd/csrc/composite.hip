@@ -161,7 +161,7 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
 // run in unguarded blocks of kPad pairs.
 // geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
 // col = (g', alpha, cbar, extra).
-template <int kExtra, int kPad = 1>  // kExtra 0: none, 1: s_old + index, 2: weight
+template <int kExtra, int kPad = 1>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
 __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
                                            uint32_t *sid, float *sold, const double *__restrict__ weights) {
     const int lane = threadIdx.x;
@@ -202,6 +202,10 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         if (kExtra == 1) {
             sid[slot] = g;
             sold[slot] = __uint_as_float(w.sens_bits[g]);
+        }
+        if (kExtra == 3) {   // aggregated pass 2: index and position in the tile's list
+            sid[slot] = g;
+            sold[slot] = __uint_as_float((uint32_t)(e - w.start));
         }
         if (kExtra == 2) extra = (float)weights[g];
         col[slot] = make_float4(r1.z, r1.w, cb, extra);
@@ -331,8 +335,44 @@ __device__ __forceinline__ float wave_transpose_max16(float (&v)[16]) {
     return dpp_max<0xB1>(dpp_max<0x4E>(v[0]));
 }
 
-template <bool kStats, bool kPersistent>
-__global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
+template <int kCtrl>
+__device__ __forceinline__ float dpp_add(float x) {
+    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, false));
+    return x + y;
+}
+
+// The 16-value network with sums instead of maxima: lane L ends with the sum
+// over all 64 lanes of value (L >> 2) & 15 (each level pairs disjoint lane
+// sets, so every lane's value is counted once).
+__device__ __forceinline__ float wave_transpose_sum16(float (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 8]),
+                                                        false, false);
+        v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 4]),
+                                                        false, false);
+        v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool s3 = (lane & 8) != 0, s2 = (lane & 4) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float m0 = dpp_add<0x140>(v[k]), m1 = dpp_add<0x140>(v[k + 2]);
+        v[k] = s3 ? m1 : m0;
+    }
+    {
+        const float m0 = dpp_add<0x141>(v[0]), m1 = dpp_add<0x141>(v[1]);
+        v[0] = s2 ? m1 : m0;
+    }
+    return dpp_add<0xB1>(dpp_add<0x4E>(v[0]));
+}
+
+template <bool kStats, bool kPersistent, int kAgg>
+__global__ __launch_bounds__(kWave, kPersistent ? 5 : (kAgg != 0 ? 6 : 8)) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     __shared__ float4 geo[kWave], col[kWave];
     __shared__ uint32_t sid[kWave];
     __shared__ float sold[kWave];
@@ -346,6 +386,12 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeA
         const bool scored = w.inside && ray_selected(w.ray_mask, w.ray_global);
         const float Af = scored ? w.ray_A[w.ray_local] : 0.0f;
         const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
+        // the share's denominator: the ray's A, or the A of the lane's query
+        float invQ = invA;
+        if (kAgg != 0) {
+            const double qA = kAgg == 1 ? a.query_A[w.gt] : (kAgg == 2 ? a.query_A[w.v] : a.query_A[0]);
+            invQ = (invA > 0.0f && qA > 0.0) ? (float)(1.0 / qA) : 0.0f;
+        }
         const float cmax = w.cmax;
         uint32_t *sens_bits = w.sens_bits;
         float T = 1.0f;
@@ -354,7 +400,7 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeA
         const float live_bar = a.share_floor * Af;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<1, kBlock>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr);
+            const int n = stage_slice<kAgg == 0 ? 1 : 3, kBlock>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr);
             __syncthreads();
             for (int jb = 0; jb < n; jb += 16) {
                 float sh[16];
@@ -368,7 +414,7 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeA
                             bool in_fp;
                             const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
                             const float cr = Cc.z * rho;
-                            sh[k0 + q] = (cr * T) * invA;
+                            sh[k0 + q] = (cr * T) * invQ;
                             if (kStats) {
                                 const bool real = j < n;
                                 n_in += (real && in_fp) ? 1u : 0u;
@@ -382,9 +428,18 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : 8) void k_pass2(CompositeA
                     }
                 }
                 if (kStats) n_eval += (uint32_t)min(16, n - jb);
-                const float m = wave_transpose_max16(sh);
                 const int j = jb + (lane >> 2);
-                if ((lane & 3) == 0 && j < n && m > sold[j]) atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
+                if (kAgg == 0) {
+                    const float m = wave_transpose_max16(sh);
+                    if ((lane & 3) == 0 && j < n && m > sold[j]) atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
+                } else {
+                    const float m = wave_transpose_sum16(sh);
+                    if ((lane & 3) == 0 && j < n && m > 0.0f) {
+                        const int64_t idx = kAgg == 1 ? (int64_t)(w.start + __float_as_uint(sold[j]))
+                                                      : (kAgg == 2 ? w.vbase + sid[j] : (int64_t)sid[j]);
+                        atomicAdd((unsigned long long *)&a.acc[idx], (unsigned long long)fma((double)m, kAggScale, 0.5));
+                    }
+                }
             }
             done = done || (T * cmax < a.share_floor * Af);
             __syncthreads();
@@ -441,20 +496,148 @@ void launch_composite_pass1(const CompositeArgs &a, hipStream_t st) {
 }
 
 void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
+    if (a.agg != 0) {   // aggregated queries: flat form, no pair counters
+        if (a.agg == 1)
+            hipLaunchKernelGGL((k_pass2<false, false, 1>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        else if (a.agg == 2)
+            hipLaunchKernelGGL((k_pass2<false, false, 2>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        else
+            hipLaunchKernelGGL((k_pass2<false, false, 3>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        return;
+    }
     if (a.work) {
         launch_fill_u32(a.work, 0u, 1, st);
         if (stats) {
-            static const unsigned grid = resident_waves(k_pass2<true, true>);
-            hipLaunchKernelGGL((k_pass2<true, true>), dim3(grid), dim3(kWave), 0, st, a, counters);
+            static const unsigned grid = resident_waves(k_pass2<true, true, 0>);
+            hipLaunchKernelGGL((k_pass2<true, true, 0>), dim3(grid), dim3(kWave), 0, st, a, counters);
         } else {
-            static const unsigned grid = resident_waves(k_pass2<false, true>);
-            hipLaunchKernelGGL((k_pass2<false, true>), dim3(grid), dim3(kWave), 0, st, a, counters);
+            static const unsigned grid = resident_waves(k_pass2<false, true, 0>);
+            hipLaunchKernelGGL((k_pass2<false, true, 0>), dim3(grid), dim3(kWave), 0, st, a, counters);
         }
     } else if (stats) {
-        hipLaunchKernelGGL((k_pass2<true, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<true, false, 0>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
     } else {
-        hipLaunchKernelGGL((k_pass2<false, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<false, false, 0>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Aggregated queries (Section 3.4): the query objectives A(Q) from the per-ray
+// A of pass 1 (zero on rays outside the mask), and the maximum over queries.
+// Every sum has a fixed order (per lane in index order, then a fixed
+// butterfly), so the results do not depend on scheduling.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// One wave per tile: lane l sums column l % 16 of rows l / 16, +4, +8, +12.
+__global__ __launch_bounds__(kWave) void k_tile_A(CompositeArgs a, double *__restrict__ tile_A) {
+    const int t = blockIdx.x;
+    const int v = a.tile_view[t];
+    const SceneSlot &S = a.slots[0];
+    const ViewDev &V = a.views[v];
+    const int tl = t - V.tile_base;
+    const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
+    const int lane = threadIdx.x;
+    const int px = tx * kTile + (lane & 15);
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = ty * kTile + (lane >> 4) + 4 * k;
+        if (px < V.W && py < V.H) sum += (double)S.ray_A[V.ray_local + (int64_t)py * V.W + px];
+    }
+    sum = wave_sum_f64(sum);
+    if (lane == 0) tile_A[t] = sum;
+}
+
+// One wave per view: the sum of its tiles' A(Q).
+__global__ __launch_bounds__(kWave) void k_view_A(const ViewDev *__restrict__ views,
+                                                  const double *__restrict__ tile_A, double *__restrict__ view_A) {
+    const ViewDev &V = views[blockIdx.x];
+    const int nt = V.tiles_x * V.tiles_y;
+    double sum = 0.0;
+    for (int t = threadIdx.x; t < nt; t += kWave) sum += tile_A[V.tile_base + t];
+    sum = wave_sum_f64(sum);
+    if (threadIdx.x == 0) view_A[blockIdx.x] = sum;
+}
+
+// One wave: the sum over the launch's views.
+__global__ __launch_bounds__(kWave) void k_total_A(const double *__restrict__ view_A, int Vc,
+                                                   double *__restrict__ total) {
+    double sum = 0.0;
+    for (int v = threadIdx.x; v < Vc; v += kWave) sum += view_A[v];
+    sum = wave_sum_f64(sum);
+    if (threadIdx.x == 0) total[0] = sum;
+}
+
+void launch_query_sums(const CompositeArgs &a, int Vc, double *tile_A, double *view_A, double *total,
+                       hipStream_t st) {
+    if (a.total_tiles <= 0 || Vc <= 0) return;
+    hipLaunchKernelGGL(k_tile_A, dim3(a.total_tiles), dim3(kWave), 0, st, a, tile_A);
+    hipLaunchKernelGGL(k_view_A, dim3(Vc), dim3(kWave), 0, st, a.views, (const double *)tile_A, view_A);
+    if (total) hipLaunchKernelGGL(k_total_A, dim3(1), dim3(kWave), 0, st, (const double *)view_A, Vc, total);
+}
+
+__device__ __forceinline__ float agg_share(uint64_t x) { return (float)((double)x * (1.0 / kAggScale)); }
+
+__global__ __launch_bounds__(256) void k_agg_tile_max(const uint64_t *__restrict__ acc,
+                                                      const uint32_t *__restrict__ lists, uint64_t n,
+                                                      uint32_t *__restrict__ sens_bits) {
+    const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float s = agg_share(acc[e]);
+    if (s > 0.0f) atomicMax(&sens_bits[lists[e] & kIndexMask], __float_as_uint(s));
+}
+
+__global__ __launch_bounds__(256) void k_agg_view_max(const uint64_t *__restrict__ acc, int64_t N, int Vc,
+                                                      uint32_t *__restrict__ sens_bits) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= N) return;
+    uint64_t m = 0;
+    for (int v = 0; v < Vc; ++v) m = max(m, acc[(int64_t)v * N + g]);
+    const float s = agg_share(m);
+    if (s > __uint_as_float(sens_bits[g])) sens_bits[g] = __float_as_uint(s);
+}
+
+__global__ __launch_bounds__(256) void k_agg_scene_add(const uint64_t *__restrict__ acc, int64_t N,
+                                                       double *__restrict__ num, double *__restrict__ den,
+                                                       const double *__restrict__ launch_A) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double LA = launch_A[0];
+    if (g == 0) den[0] += LA;
+    if (g < N) num[g] += ((double)acc[g] * (1.0 / kAggScale)) * LA;
+}
+
+void launch_agg_finalize(int agg, const uint64_t *acc, const uint32_t *lists, uint64_t n_entries, int64_t N,
+                         int Vc, uint32_t *sens_bits, double *num, double *den, const double *launch_A,
+                         hipStream_t st) {
+    if (agg == 1) {
+        if (n_entries == 0) return;
+        hipLaunchKernelGGL(k_agg_tile_max, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0, st, acc, lists,
+                           n_entries, sens_bits);
+    } else if (agg == 2) {
+        hipLaunchKernelGGL(k_agg_view_max, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, acc, N, Vc,
+                           sens_bits);
+    } else if (agg == 3) {
+        hipLaunchKernelGGL(k_agg_scene_add, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, acc, N, num, den,
+                           launch_A);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_div_f64_to_f32(const double *__restrict__ num,
+                                                        const double *__restrict__ den, int64_t n,
+                                                        float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double d = den[0];
+    out[i] = d > 0.0 ? (float)(num[i] / d) : 0.0f;
+}
+
+void launch_div_f64_to_f32(const double *num, const double *den, int64_t n, float *out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_div_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, num, den, n, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -131,10 +131,31 @@ struct CompositeArgs {
     float share_floor;
     uint32_t *work;              // persistent form: work counter (zeroed before the launch); null = one wave per quadrant
     int32_t xcd_remap;           // 1: give each XCD a contiguous range of quadrants
-    int32_t pad;
+    int32_t agg;                 // query granularity (gs_aggregate) of pass 2
+    const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
+    uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
 };
+// Fixed-point scale of the aggregated shares.  A Gaussian's accumulated share
+// of one query is at most 1 (a_i(q) <= A(q) on every ray), so 2^60 leaves a
+// factor 16 of headroom in 64 bits; one unit is 8.7e-19 of the query's A.
+constexpr double kAggScale = 1152921504606846976.0;   // 2^60
 void launch_composite_pass1(const CompositeArgs &a, hipStream_t st);
 void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st);
+// Query objectives of the aggregated granularities from pass 1's per-ray A:
+// tile_A[t] over each tile's rays and view_A[v] over each view's tiles, FP64
+// sums in a fixed order; total[0] = sum of view_A (total may be null).
+// Launches with a single scene slot at tile 0 (one call's chunk).
+void launch_query_sums(const CompositeArgs &a, int Vc, double *tile_A, double *view_A, double *total,
+                       hipStream_t st);
+// Folds one launch's accumulators into the result.  agg 1: every list entry's
+// share raises its Gaussian's sens_bits (float-bit maximum); agg 2: the maximum
+// over the launch's views raises sens_bits; agg 3: num[g] += acc[g] 2^-60
+// launch_A[0] (the launch's absolute contributions) and den[0] += launch_A[0].
+void launch_agg_finalize(int agg, const uint64_t *acc, const uint32_t *lists, uint64_t n_entries, int64_t N,
+                         int Vc, uint32_t *sens_bits, double *num, double *den, const double *launch_A,
+                         hipStream_t st);
+// out[i] = den[0] > 0 ? num[i] / den[0] : 0, rounded to float.
+void launch_div_f64_to_f32(const double *num, const double *den, int64_t n, float *out, hipStream_t st);
 
 struct ObjectiveArgs {
     const double *weights;

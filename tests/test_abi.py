@@ -69,7 +69,7 @@ def _call_sens(lib, scene, views, params, out=0x1000):
 @pytest.mark.parametrize("case,status", [
     ("n0", 1), ("deg4", 1), ("fmt7", 1), ("nullplane", 1), ("nullviews", 1), ("nullparams", 1),
     ("sigma0", 1), ("mode9", 1), ("nullout", 1), ("huge_n", 2), ("too_many_tiles", 2), ("bad_size", 1),
-    ("neg_floor", 1),
+    ("neg_floor", 1), ("agg7", 1), ("agg_neg", 1), ("agg_pairs", 2),
 ])
 def test_sensitivity_argument_errors(lib, case, status):
     from paper_2607_02721_amd import _lib
@@ -87,6 +87,11 @@ def test_sensitivity_argument_errors(lib, case, status):
     if case == "too_many_tiles": vw = _views(4096, 4096)
     if case == "bad_size": vw = _views(0, 64)
     if case == "neg_floor": p.share_floor = -1.0
+    if case == "agg7": p.aggregate = 7
+    if case == "agg_neg": p.aggregate = -1
+    if case == "agg_pairs":
+        p.aggregate = _lib.AGG_TILE
+        p.flags = _lib.FLAG_COUNT_PAIRS
     assert _call_sens(lib, sc, vw, p, out) == status
     assert lib.gs_last_error()
 
@@ -113,6 +118,7 @@ def test_default_params(lib):
     p = _lib.default_params()
     assert p.footprint_sigma == 3.0 and abs(p.dilation - 0.3) < 1e-7 and abs(p.z_near - 0.2) < 1e-7
     assert abs(p.share_floor - 1e-12) < 1e-18 and p.query_mode == 0 and p.ray_mask is None
+    assert p.aggregate == _lib.AGG_RAY
 
 
 def test_plan_argument_errors(lib):
@@ -130,6 +136,9 @@ def test_plan_argument_errors(lib):
     p = _lib.default_params()
     p.flags = 1
     assert f(scenes, views, 1, C.byref(p), C.byref(h), None) == 2      # no pair counting in plans
+    p = _lib.default_params()
+    p.aggregate = _lib.AGG_IMAGE
+    assert f(scenes, views, 1, C.byref(p), C.byref(h), None) == 2      # per-ray queries only
     p = _lib.default_params()
     bad = (_lib.Scene * 1)(_scene(n=0))
     assert f(bad, views, 1, C.byref(p), C.byref(h), None) == 1

@@ -1,0 +1,118 @@
+"""Aggregated sensitivities (Section 3.4: queries that are 16x16 tiles, whole
+views or the whole scene) of the HIP path against the FP64 oracle, through
+the C ABI.
+
+Both sides score the same rays: the oracle's ambiguous rays (a pair within
+1e-5 r^2 of the footprint cutoff, or an order key near a float32 rounding
+midpoint) are removed from every query through the ray mask.  The bar is the
+per-ray one, |s_gpu - s_oracle| <= 1e-5 s_oracle + 1e-12: the GPU's shares
+are float32 per ray, summed over a wave in float32 (at most 6 roundings of
+positive terms, < 4e-7 relative), then in exact 64-bit fixed point with unit
+2^-60 of the query's A; the share floor drops less than 1e-12 A(Q) per
+query.  Properties at any size: the per-scene sensitivities sum to 1, the
+levels are ordered (scene <= image <= tile <= ray) and every granularity is
+deterministic (bit-identical on a second call)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+REL, ABS = 1e-5, 1e-12
+LEVELS = ("tile", "image", "scene")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_02721_amd as gs
+    gs.load()
+    return gs
+
+
+def _level(gs, name):
+    return {"ray": gs.AGG_RAY, "tile": gs.AGG_TILE, "image": gs.AGG_IMAGE, "scene": gs.AGG_SCENE}[name]
+
+
+def _mask_tensor(bits):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(bits, np.uint32).view(np.int32)).cuda()
+
+
+def _ragged():
+    # 200x136 is 12.5 x 8.5 tiles: ragged right and bottom tiles in every view
+    return synth.make_cluster_scene(20_000, 7, 3), synth.make_orbit_views(3, 17, 200, 136)
+
+
+def _case(ora, sc, vw):
+    flag = ora.sensitivity(sc, vw)["flag"]
+    return synth.pack_bits(~flag), int(flag.sum())
+
+
+def _check(label, s, ref):
+    excess = np.abs(s - ref) - (REL * ref + ABS)
+    worst = int(np.argmax(excess))
+    big = ref > 1e-9
+    rel = np.max(np.abs(s[big] - ref[big]) / ref[big]) if big.any() else 0.0
+    print(f"[{label}] s>0 on {int((ref > 0).sum())}, max rel err (s > 1e-9) {rel:.2e}, "
+          f"worst excess {excess[worst]:.2e}", flush=True)
+    assert excess.max() <= 0, f"{label}: Gaussian {worst}: gpu {s[worst]!r} oracle {ref[worst]!r}"
+
+
+@pytest.mark.parametrize("level", LEVELS)
+@pytest.mark.parametrize("which", ["tiny", "ragged"])
+def test_aggregated_parity(gs, ora, which, level):
+    sc, vw = synth.make_config("tiny")[:2] if which == "tiny" else _ragged()
+    bits, n_flag = _case(ora, sc, vw)
+    ref = ora.sensitivity_agg(sc, vw, getattr(ora, "AGG_" + level.upper()), ray_mask=bits)
+    d = gs.DeviceScene.from_scene(sc)
+    s, _ = gs.sensitivity(d, vw, ray_mask=_mask_tensor(bits), aggregate=_level(gs, level))
+    print(f"[{which}/{level}] flagged rays {n_flag}/{vw.n_rays}", flush=True)
+    _check(f"{which}/{level}", s.double().cpu().numpy(), ref)
+
+
+def test_views_in_several_chunks(gs, ora):
+    """One view per launch: tile and image queries never straddle launches,
+    so they are bit-identical to one launch; the per-scene sums are carried
+    across launches in FP64 and still match the oracle."""
+    import torch
+    sc, vw = _ragged()
+    bits, _ = _case(ora, sc, vw)
+    d = gs.DeviceScene.from_scene(sc)
+    m = _mask_tensor(bits)
+    for level in LEVELS:
+        one, _ = gs.sensitivity(d, vw, ray_mask=m, aggregate=_level(gs, level))
+        per_view, _ = gs.sensitivity(d, vw, ray_mask=m, aggregate=_level(gs, level), max_views_per_chunk=1)
+        torch.cuda.synchronize()
+        if level != "scene":
+            assert torch.equal(one, per_view), level
+        else:
+            ref = ora.sensitivity_agg(sc, vw, ora.AGG_SCENE, ray_mask=bits)
+            _check("chunks/scene", per_view.double().cpu().numpy(), ref)
+
+
+def test_invariants_and_determinism(gs):
+    """Unmasked, on the ragged scene: per-scene shares sum to 1; each level is
+    at most the finer one (up to float32 rounding of both); a second call is
+    bit-identical at every granularity."""
+    import torch
+    sc, vw = _ragged()
+    d = gs.DeviceScene.from_scene(sc)
+    out = {}
+    for level in ("ray",) + LEVELS:
+        a, st = gs.sensitivity(d, vw, aggregate=_level(gs, level), stats=True)
+        b, _ = gs.sensitivity(d, vw, aggregate=_level(gs, level))
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), level
+        assert bool((a >= 0).all()) and bool((a <= 1.0 + 1e-6).all())
+        out[level] = (a.double().cpu().numpy(), st["total_sensitivity"])
+    S_scene = out["scene"][1]
+    print(f"[invariants] S per level: " + ", ".join(f"{k}={v[1]:.6f}" for k, v in out.items()), flush=True)
+    assert abs(S_scene - 1.0) <= 1e-5
+    for fine, coarse in (("ray", "tile"), ("tile", "image"), ("image", "scene")):
+        f, c = out[fine][0], out[coarse][0]
+        assert np.all(c <= f * (1 + 2e-6) + 1e-12), (fine, coarse, float(np.max(c - f)))
+    assert out["ray"][1] >= out["tile"][1] >= out["image"][1] >= S_scene * (1 - 1e-6)
