@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--train-scenes", type=int, default=8)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-agg", action="store_true", help="skip the aggregated-query variants")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate microbenchmarks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (reference dispatch for counter runs)")
@@ -196,8 +197,8 @@ def main():
     dsc = gs.DeviceScene.from_scene(scene)
     torch.cuda.synchronize()
 
-    def step(stats=False, count_pairs=False, scene_dev=dsc):
-        s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs)
+    def step(stats=False, count_pairs=False, scene_dev=dsc, aggregate=gs.AGG_RAY):
+        s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs, aggregate=aggregate)
         counts, w, sup = gs.sample_coreset(s, m, seed)
         return s, st, w
 
@@ -241,6 +242,30 @@ def main():
         ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
         errs[name] = gs.coreset_error(ob["per_view"])
     log(f"E: {errs}")
+
+    # aggregated queries (16x16 tiles, whole views, the whole scene): the same
+    # pass with sums over each query's rays, then the same sampler and judge
+    aggregated = None
+    if not args.no_agg:
+        aggregated = {}
+        for name, level in (("tile", gs.AGG_TILE), ("image", gs.AGG_IMAGE), ("scene", gs.AGG_SCENE)):
+            for _ in range(args.warmup):
+                step(aggregate=level)
+            torch.cuda.synchronize()
+            stage_a = {k: 0.0 for k in stage}
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                s_a, st_a, w_a = step(stats=True, aggregate=level)
+                for key in stage_a:
+                    stage_a[key] += st_a[key] / args.steps
+            torch.cuda.synchronize()
+            ms_a = (time.perf_counter() - t0) * 1e3 / args.steps
+            ob = gs.render_objective(dsc, views, w_a, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
+            aggregated[name] = {"ms": ms_a, "coreset_err": gs.coreset_error(ob["per_view"]),
+                                "total_sensitivity": st_a["total_sensitivity"], "stages_ms": stage_a}
+            log(f"aggregated {name}: {ms_a:.2f} ms/step, S {st_a['total_sensitivity']:.4g}, "
+                f"E {aggregated[name]['coreset_err']:.4f}")
+        gs.release_workspace()
 
     learned = None
     if not args.no_learned:
@@ -357,7 +382,7 @@ def main():
         "variants": {"exact_f32": {"ms": ms, "coreset_err": errs["exact"]},
                      "mixed16": {"ms": ms16, "coreset_err": errs["mixed16"], "stages_ms": stage16,
                                  "attribute_bytes": d16.attribute_bytes()},
-                     "learned": learned},
+                     "learned": learned, "aggregated": aggregated},
         "coreset_err_vs_m": scan,
         "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on 1% of the 8x8 pixel blocks, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],

@@ -116,3 +116,23 @@ def test_invariants_and_determinism(gs):
         f, c = out[fine][0], out[coarse][0]
         assert np.all(c <= f * (1 + 2e-6) + 1e-12), (fine, coarse, float(np.max(c - f)))
     assert out["ray"][1] >= out["tile"][1] >= out["image"][1] >= S_scene * (1 - 1e-6)
+
+
+def test_per_scene_sampling_has_zero_variance(gs):
+    """Per-scene sensitivities sampled on the GPU reproduce the scene's total
+    objective at every seed (sum over views of A^th_w = sum of A) up to the
+    2^-40 quantisation of the probabilities and float32 shares."""
+    import torch
+    sc, vw = _ragged()
+    d = gs.DeviceScene.from_scene(sc)
+    s, _ = gs.sensitivity(d, vw, aggregate=gs.AGG_SCENE)
+    full = gs.render_objective(d, vw, None, gs.OBJ_FULL, per_ray=False, diag=False)["per_view"][:, 0]
+    A = float(full.sum())
+    errs = []
+    for seed in range(3):
+        _, w, _ = gs.sample_coreset(s, 2000, seed)
+        pv = gs.render_objective(d, vw, w, gs.OBJ_FIXED, per_ray=False, diag=False)["per_view"]
+        torch.cuda.synchronize()
+        errs.append(abs(float(pv[:, 1].sum()) - A) / A)
+    print(f"[zero variance] relative errors {errs}", flush=True)
+    assert max(errs) < 1e-5

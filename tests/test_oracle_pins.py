@@ -572,6 +572,25 @@ def test_zero_variance_when_sensitivity_is_proportional_to_contribution(ora):
         assert ob["A_fixed"][ray] == pytest.approx(ob["A"][ray], rel=1e-5)
 
 
+def test_per_scene_sensitivities_give_zero_variance(ora):
+    """With per-scene sensitivities (Section 3.4) the sampling probabilities
+    are a_i(Q) / A(Q) for the single query Q holding every ray, so every draw
+    reproduces the scene's total objective: sum over all rays of A^th_w equals
+    sum of A, up to the 2^-40 quantisation of the probabilities; per-ray
+    sensitivities do not have this property."""
+    sc, vw, _, _ = synth.make_config("tiny")
+    s_scene = ora.sensitivity_agg(sc, vw, ora.AGG_SCENE).astype(np.float32)
+    s_ray = ora.sensitivity(sc, vw)["s"].astype(np.float32)
+    errs = []
+    for seed in range(4):
+        for s in (s_scene, s_ray):
+            w = ora.sample(s, 200, seed)["weights"]
+            pv = ora.objective(sc, vw, w)["view_sums"]
+            errs.append(abs(pv[:, 1].sum() - pv[:, 0].sum()) / pv[:, 0].sum())
+    assert max(errs[0::2]) < 1e-7, errs
+    assert min(errs[1::2]) > 5e-4, errs
+
+
 def test_theorem2_sample_size_failure_rate(ora):
     """At m >= 3S/eps^2 log(2|Q'|/delta), the fixed objective is an eps-coreset
     on every ray in (far) more than a 1 - delta fraction of seeds."""
