@@ -69,7 +69,7 @@ typedef struct {
     double z_near;
     double share_floor;     /* only used to count "live" pairs */
     double ambiguity_beta;  /* relative band around d^2 = r^2 that flags a pair */
-    int32_t query_mode;     /* 0: RGB sum, 1: colour 1 */
+    int32_t query_mode;     /* 0: RGB sum, 1: colour 1 (nocolor), 2: L2 of the RGB sum, 3: per channel */
     int32_t n_threads;
 } ora_params;
 
@@ -83,7 +83,8 @@ typedef struct {
     double cov[3];      /* Sigma_2d: xx, xy, yy (with dilation) */
     double conic[3];    /* inverse of Sigma_2d: xx, xy, yy */
     double rgb[3];      /* clamped colour per channel */
-    double cbar;        /* query colour (sum of channels, or 1) */
+    double cbar;        /* colour factor of the query: sum of channels (mode 0), 1 (mode 1),
+                           sum of squared channels (mode 2), largest channel (mode 3) */
     double alpha;
     double rx, ry;      /* half extents of the r-ellipse */
 } ora_proj;
@@ -208,7 +209,41 @@ void ora_project_one(const ora_scene *g, const ora_views *vw, const ora_params *
         acc += 0.5;
         o->rgb[ch] = acc > 0.0 ? acc : 0.0;
     }
-    o->cbar = prm->query_mode == 1 ? 1.0 : o->rgb[0] + o->rgb[1] + o->rgb[2];
+    if (prm->query_mode == 1) o->cbar = 1.0;
+    else if (prm->query_mode == 2) o->cbar = o->rgb[0] * o->rgb[0] + o->rgb[1] * o->rgb[1] + o->rgb[2] * o->rgb[2];
+    else if (prm->query_mode == 3) o->cbar = fmax(o->rgb[0], fmax(o->rgb[1], o->rgb[2]));
+    else o->cbar = o->rgb[0] + o->rgb[1] + o->rgb[2];
+}
+
+/* Query variants (Section 3.4, additional variants, and Algorithm 1's
+ * per-channel queries).  Each ray holds nq queries: one for the pixel-level
+ * objectives, three (R, G, B) per channel.  A Gaussian's contributions to
+ * them at a pair with attenuation rho and prefix transmittance T:
+ *   mode 0 (L1, RGB sum):  a = (c_R + c_G + c_B) rho T
+ *   mode 1 (nocolor):      a = rho T
+ *   mode 2 (L2):           a = (c_R^2 + c_G^2 + c_B^2) rho^2 T^2, the three
+ *                          channels' squared contributions summed into one
+ *                          pixel objective
+ *   mode 3 (per channel):  a_k = c_k rho T for k = R, G, B.
+ * Each query's objective A is the sum of its contributions over the ray.   */
+static int n_queries(const ora_params *prm) { return prm->query_mode == 3 ? 3 : 1; }
+
+static void pair_contrib(const ora_params *prm, const ora_proj *o, double rho, double T, double *a)
+{
+    if (prm->query_mode == 3) {
+        for (int k = 0; k < 3; ++k) a[k] = o->rgb[k] * rho * T;
+    } else if (prm->query_mode == 2) {
+        a[0] = o->cbar * (rho * T) * (rho * T);
+    } else {
+        a[0] = o->cbar * rho * T;
+    }
+}
+
+/* Largest contribution any later Gaussian of the ray can make to one of its
+ * queries (rho <= 1): c_max T, or c_max T^2 for the L2 objective.          */
+static double later_bound(const ora_params *prm, double cbar_max, double T)
+{
+    return prm->query_mode == 2 ? cbar_max * T * T : cbar_max * T;
 }
 
 /* Batched projection for tests: fills arrays of length V*n (view-major). */
@@ -341,8 +376,9 @@ static void *sens_worker_main(void *arg)
         const int32_t y1 = y0 + w->band_rows < H ? y0 + w->band_rows : H; /* exclusive */
         const int64_t npix = (int64_t)(y1 - y0) * W;
         const int64_t base = w->ray_base + (int64_t)y0 * W;
+        const int nq = n_queries(w->prm);
         double *T = (double *)malloc(sizeof(double) * (size_t)npix);
-        double *A = (double *)calloc((size_t)npix, sizeof(double));
+        double *A = (double *)calloc((size_t)(npix * nq), sizeof(double));   /* [pixel][query] */
         uint8_t *sel = (uint8_t *)malloc((size_t)npix);
         uint8_t *flag = (uint8_t *)calloc((size_t)npix, 1);
         uint8_t row_on[16] = {0};
@@ -373,16 +409,25 @@ static void *sens_worker_main(void *arg)
                         if (fabs(d2 - r2) <= beta * r2 || (o->key_ambiguous && d2 <= r2 * (1.0 + beta)))
                             flag[p] = 1;
                         if (d2 > r2) continue;
-                        double rho = o->alpha * exp(-0.5 * d2);
-                        A[p] += o->cbar * rho * T[p];
+                        double rho = o->alpha * exp(-0.5 * d2), a[3];
+                        pair_contrib(w->prm, o, rho, T[p], a);
+                        for (int q = 0; q < nq; ++q) A[p * nq + q] += a[q];
                         T[p] *= (1.0 - rho);
                     }
                 }
             }
-            /* Pass 2: shares a/A on rays with A > 0; running maxima. */
+            /* Pass 2: shares a/A on the queries with A > 0; running maxima.
+             * A ray counts as positive if one of its queries is.            */
+            uint8_t *pos = (uint8_t *)calloc((size_t)npix, 1);
+            double *Amin = (double *)malloc(sizeof(double) * (size_t)npix);
             for (int64_t p = 0; p < npix; ++p) {
                 T[p] = 1.0;
-                if (sel[p] && A[p] > 0.0) w->rays_positive++;
+                Amin[p] = A[p * nq];
+                for (int q = 0; q < nq; ++q) {
+                    if (A[p * nq + q] > 0.0) pos[p] = 1;
+                    if (A[p * nq + q] < Amin[p]) Amin[p] = A[p * nq + q];
+                }
+                if (sel[p] && pos[p]) w->rays_positive++;
             }
             for (int64_t k = 0; k < S->n_present; ++k) {
                 const int64_t i = S->order[k].idx;
@@ -397,23 +442,30 @@ static void *sens_worker_main(void *arg)
                     if (!row_on[py - y0]) continue;
                     for (int32_t px = xlo; px <= xhi; ++px) {
                         int64_t p = (int64_t)(py - y0) * W + px;
-                        if (!sel[p] || !(A[p] > 0.0)) continue;
+                        if (!sel[p] || !pos[p]) continue;
                         double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
                         double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
                         if (d2 > r2) continue;
-                        double rho = o->alpha * exp(-0.5 * d2);
-                        double a = o->cbar * rho * T[p];
-                        double share = a / A[p];
-                        if (share > w->s_thread[i]) w->s_thread[i] = share;
+                        double rho = o->alpha * exp(-0.5 * d2), a[3];
+                        pair_contrib(w->prm, o, rho, T[p], a);
+                        for (int q = 0; q < nq; ++q) {
+                            if (!(A[p * nq + q] > 0.0)) continue;
+                            double share = a[q] / A[p * nq + q];
+                            if (share > w->s_thread[i]) w->s_thread[i] = share;
+                        }
                         w->pairs++;
-                        if (T[p] * S->cbar_max >= w->prm->share_floor * A[p]) w->live_pairs++;
+                        /* live: some query of the ray could still receive a
+                         * contribution of at least floor times its objective */
+                        if (later_bound(w->prm, S->cbar_max, T[p]) >= w->prm->share_floor * Amin[p]) w->live_pairs++;
                         T[p] *= (1.0 - rho);
                     }
                 }
             }
+            free(pos); free(Amin);
         }
         for (int64_t p = 0; p < npix; ++p) {
-            if (w->A) w->A[base + p] = sel[p] ? A[p] : 0.0;
+            for (int q = 0; q < nq; ++q)
+                if (w->A) w->A[(base + p) * nq + q] = sel[p] ? A[p * nq + q] : 0.0;
             if (w->ray_flag) w->ray_flag[base + p] = flag[p];
         }
         free(T); free(A); free(sel); free(flag);
@@ -456,7 +508,8 @@ static void setup_view_threaded(const ora_scene *g, const ora_views *vw, const o
     qsort(s->order, (size_t)s->n_present, sizeof(ora_order), order_cmp);
 }
 
-/* s: [n] out.  A: [rays] out (nullable), 0 on unselected rays.
+/* s: [n] out.  A: [rays][nq] out (nullable; nq = 3 per channel, else 1),
+ * every query's objective, 0 on unselected rays.
  * ray_flag: [rays] out (nullable), 1 where some candidate pair lies within the
  * ambiguity band of the cutoff or has an ambiguous order key.
  * counters: [3] out = pairs with d^2 <= r^2 on selected rays with A > 0,
@@ -484,7 +537,8 @@ int ora_sensitivity(const ora_scene *g, const ora_views *vw, const ora_params *p
         }
         if (!any) {
             for (int64_t p = 0; p < nrays; ++p) {
-                if (A) A[ray_base + p] = 0.0;
+                for (int q = 0; q < n_queries(prm); ++q)
+                    if (A) A[(ray_base + p) * n_queries(prm) + q] = 0.0;
                 if (ray_flag) ray_flag[ray_base + p] = 0;
             }
             ray_base += nrays;
@@ -584,8 +638,9 @@ static void *agg_worker_main(void *arg)
                         double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
                         double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
                         if (d2 > r2) continue;
-                        double rho = o->alpha * exp(-0.5 * d2);
-                        A[p] += o->cbar * rho * T[p];
+                        double rho = o->alpha * exp(-0.5 * d2), a;
+                        pair_contrib(w->prm, o, rho, T[p], &a);
+                        A[p] += a;
                         T[p] *= (1.0 - rho);
                     }
             }
@@ -614,8 +669,8 @@ static void *agg_worker_main(void *arg)
                         double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
                         double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
                         if (d2 > r2) continue;
-                        double rho = o->alpha * exp(-0.5 * d2);
-                        double a = o->cbar * rho * T[p];
+                        double rho = o->alpha * exp(-0.5 * d2), a;
+                        pair_contrib(w->prm, o, rho, T[p], &a);
                         if (w->level == 1) tile_sum[px / 16] += a;
                         else w->num[i] += a;
                         T[p] *= (1.0 - rho);
@@ -643,6 +698,9 @@ int ora_sensitivity_agg(const ora_scene *g, const ora_views *vw, const ora_param
                         const uint32_t *ray_mask, int32_t level, double *s)
 {
     if (level < 1 || level > 3) return 1;
+    /* an aggregated query sums its rays' channels (Section 3.4), so the
+     * per-channel mode has no aggregated form of its own */
+    if (n_queries(prm) != 1) return 2;
     const int32_t V = vw->n_views;
     const int nt = prm->n_threads > 0 ? prm->n_threads : 1;
     agg_worker *ws = (agg_worker *)calloc((size_t)nt, sizeof(agg_worker));
@@ -709,6 +767,8 @@ int ora_sensitivity_agg(const ora_scene *g, const ora_views *vw, const ora_param
 /* Objectives (Section 3): full render A, fixed relaxation
  * A^th_w = sum_i w_i a_i (full-scene transmittance), true reduced render
  * A_w = sum_i w_i c_i rho_i T_w,i with T_w,i = prod_{j before i} (1 - w_j rho_j).
+ * The nocolor and L2 variants replace a_i by their contribution (with T_w
+ * in place of T for the reduced render); per-channel queries are rejected.
  * Validity (Definition 2): pairs with w_i rho_i >= 1 are counted.
  * Log-transmittance gap (Assumption 1): gamma = max |log T - log T_w| over
  * contributing pairs (rho > 0) of retained Gaussians (w > 0), on rays where
@@ -720,6 +780,8 @@ int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm
                   double *A_full, double *A_fixed, double *A_true, /* [rays] each, nullable */
                   double *view_sums /* [V][3] nullable */, int64_t *n_invalid, double *gamma)
 {
+    /* one objective per ray: the per-channel mode has three */
+    if (n_queries(prm) != 1) return 2;
     const int32_t V = vw->n_views;
     const double r2 = prm->footprint_sigma * prm->footprint_sigma;
     int64_t ray0 = 0, invalid = 0;
@@ -753,12 +815,15 @@ int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm
                     double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
                     double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
                     if (d2 > r2) continue;
-                    double rho = o->alpha * exp(-0.5 * d2);
-                    double a = o->cbar * rho * T[p];
+                    double rho = o->alpha * exp(-0.5 * d2), a, aw;
+                    pair_contrib(prm, o, rho, T[p], &a);
                     Af[p] += a;
                     Ax[p] += wi * a;
                     if (wi > 0.0) {
-                        At[p] += wi * o->cbar * rho * Tw[p];
+                        /* the reduced render: the same contribution with the
+                         * retained scene's transmittance T_w */
+                        pair_contrib(prm, o, rho, Tw[p], &aw);
+                        At[p] += wi * aw;
                         if (!bad[p] && rho > 0.0) {
                             double gap = fabs(LT[p] - LTw[p]);
                             if (gap > gq[p]) gq[p] = gap;

@@ -99,6 +99,10 @@ class _Keep:
                          params.get("n_threads", os.cpu_count() or 1))
 
 
+# query modes (gs_oracle.c: pair_contrib)
+QUERY_RGBSUM, QUERY_NOCOLOR, QUERY_L2, QUERY_CHANNEL = 0, 1, 2, 3
+
+
 def default_params(**kw):
     p = dict(footprint_sigma=3.0, dilation=0.3, z_near=0.2, share_floor=1e-12,
              ambiguity_beta=1e-5, query_mode=0, n_threads=os.cpu_count() or 1)
@@ -107,20 +111,25 @@ def default_params(**kw):
 
 
 def sensitivity(scene, views, params=None, ray_mask=None):
-    """Sensitivities s[n] (float64), per-ray A[rays], per-ray ambiguity flags,
-    and counters (pairs, live pairs, positive rays).  ``ray_mask`` is a uint32
-    bitset over rays (view-major, row-major) or None for every ray."""
+    """Sensitivities s[n] (float64), per-ray A[rays] ([rays, 3] for per-channel
+    queries), per-ray ambiguity flags, and counters (pairs, live pairs, rays
+    with a positive query).  ``ray_mask`` is a uint32 bitset over rays
+    (view-major, row-major) or None for every ray."""
     lib = _load()
-    k = _Keep(scene, views, params or default_params())
+    params = params or default_params()
+    k = _Keep(scene, views, params)
     n_rays = views.n_rays
+    nq = 3 if params.get("query_mode", 0) == QUERY_CHANNEL else 1
     s = np.zeros(scene.n, np.float64)
-    A = np.zeros(n_rays, np.float64)
+    A = np.zeros(n_rays * nq, np.float64)
     flag = np.zeros(n_rays, np.uint8)
     cnt = np.zeros(3, np.int64)
     mask = None if ray_mask is None else np.ascontiguousarray(ray_mask, np.uint32)
     rc = lib.ora_sensitivity(C.byref(k.s), C.byref(k.v), C.byref(k.p), _ptr(mask),
                              _ptr(s), _ptr(A), _ptr(flag), _ptr(cnt))
     assert rc == 0
+    if nq > 1:
+        A = A.reshape(n_rays, nq)
     return {"s": s, "A": A, "flag": flag.astype(bool), "pairs": int(cnt[0]),
             "live_pairs": int(cnt[1]), "rays_positive": int(cnt[2])}
 
@@ -140,6 +149,8 @@ def sensitivity_agg(scene, views, level, params=None, ray_mask=None):
     s = np.zeros(scene.n, np.float64)
     mask = None if ray_mask is None else np.ascontiguousarray(ray_mask, np.uint32)
     rc = lib.ora_sensitivity_agg(C.byref(k.s), C.byref(k.v), C.byref(k.p), _ptr(mask), int(level), _ptr(s))
+    if rc == 2:
+        raise ValueError("per-channel queries have no aggregated form")
     assert rc == 0
     return s
 
@@ -158,6 +169,8 @@ def objective(scene, views, weights, params=None, ray_mask=None):
     mask = None if ray_mask is None else np.ascontiguousarray(ray_mask, np.uint32)
     rc = lib.ora_objective(C.byref(k.s), C.byref(k.v), C.byref(k.p), _ptr(mask), _ptr(w),
                            _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(vs), _ptr(inv), _ptr(gam))
+    if rc == 2:
+        raise ValueError("the objectives hold one query per ray (not per channel)")
     assert rc == 0
     return {"A": out[0], "A_fixed": out[1], "A_true": out[2], "view_sums": vs,
             "n_invalid": int(inv[0]), "gamma": float(gam[0])}

@@ -234,6 +234,58 @@ def test_telescoping_and_two_gaussian_closed_form(ora):
     assert np.allclose(r2["s"], [r1_ / den, r2_ * (1 - r1_) / den], rtol=1e-12)
 
 
+def test_l2_closed_forms(ora):
+    """L2 queries (Section 3.4): on the central ray (rho_j = alpha_j)
+    A = sum_j (c_R^2 + c_G^2 + c_B^2)_j alpha_j^2 T_j^2; for n equal
+    Gaussians of colour c this is the geometric series
+    |c|^2 alpha^2 (1 - (1 - alpha)^(2n)) / (1 - (1 - alpha)^2)."""
+    al = np.array([0.3, 0.55, 0.8, 0.25], np.float32).astype(np.float64)
+    col = np.array([[0.2, 0.3, 0.1], [0.9, 0.1, 0.4], [0.5, 0.5, 0.5], [0.05, 0.6, 0.7]])
+    depths = [3.5, 2.0, 4.2, 3.0]
+    sc, vw = _axis_stack(al, col, depths)
+    mask = _central_ray_mask(vw)
+    rgb = ora.project(sc, vw)["rgb"][0]
+    T, Aref, a = 1.0, 0.0, np.zeros(4)
+    for j in np.argsort(depths):
+        a[j] = (rgb[j] ** 2).sum() * al[j] ** 2 * T ** 2
+        Aref += a[j]
+        T *= 1 - al[j]
+    r = ora.sensitivity(sc, vw, ora.default_params(query_mode=ora.QUERY_L2), mask)
+    assert r["A"][mask_index(vw)] == pytest.approx(Aref, rel=1e-13)
+    assert np.allclose(r["s"], a / Aref, rtol=1e-12)
+    n, alpha = 5, float(np.float32(0.4))
+    sc5, vw5 = _axis_stack([alpha] * n, [[0.3, 0.6, 0.2]] * n, [2.0 + 0.3 * k for k in range(n)])
+    c2 = (ora.project(sc5, vw5)["rgb"][0, 0] ** 2).sum()
+    r5 = ora.sensitivity(sc5, vw5, ora.default_params(query_mode=ora.QUERY_L2), _central_ray_mask(vw5))
+    geo = c2 * alpha ** 2 * (1 - (1 - alpha) ** (2 * n)) / (1 - (1 - alpha) ** 2)
+    assert r5["A"][mask_index(vw5)] == pytest.approx(geo, rel=1e-13)
+
+
+def test_per_channel_queries(ora):
+    """Per-channel queries (Algorithm 1: queries per camera, pixel and RGB
+    channel): a Gaussian that is alone in its channel on a ray has share 1
+    there however deep it sits, while its RGB-sum share is below 1; and since
+    a pixel's RGB-sum share is a weighted mean (mediant) of its channel
+    shares, s_channel >= s_rgbsum for every Gaussian."""
+    sc, vw = _axis_stack([0.6, 0.5], [[1.0, -0.2, -0.2], [-0.2, -0.2, 0.8]], [2.0, 3.0])
+    mask = _central_ray_mask(vw)
+    ch = ora.sensitivity(sc, vw, ora.default_params(query_mode=ora.QUERY_CHANNEL), mask)
+    assert np.allclose(ch["s"], 1.0, rtol=0, atol=1e-15)
+    A = ch["A"][mask_index(vw)]
+    rgb = ora.project(sc, vw)["rgb"][0]
+    assert rgb[0, 1] == rgb[0, 2] == rgb[1, 0] == rgb[1, 1] == 0.0
+    assert A == pytest.approx([rgb[0, 0] * 0.6, 0.0, rgb[1, 2] * 0.5 * 0.4], rel=1e-7)
+    s0 = ora.sensitivity(sc, vw, ora.default_params(query_mode=0), mask)["s"]
+    assert s0[1] < 0.5
+    tsc, tvw, _, _ = synth.make_config("tiny")
+    a = ora.sensitivity(tsc, tvw, ora.default_params(query_mode=0))["s"]
+    b = ora.sensitivity(tsc, tvw, ora.default_params(query_mode=ora.QUERY_CHANNEL))["s"]
+    assert np.all(b >= a * (1 - 1e-12))
+    assert np.mean(b > a * (1 + 1e-6)) > 0.5
+    with pytest.raises(ValueError):
+        ora.sensitivity_agg(tsc, tvw, ora.AGG_TILE, ora.default_params(query_mode=ora.QUERY_CHANNEL))
+
+
 def mask_index(vw):
     W, H = int(vw.size[0, 0]), int(vw.size[0, 1])
     return (H // 2) * W + W // 2
@@ -346,9 +398,12 @@ def test_adding_views_never_lowers_sensitivity(ora):
     assert np.all(s4 >= s2)
 
 
-def _mp_ray_contributions(sc, vw, W, H):
+def _mp_ray_contributions(sc, vw, W, H, mode=0):
     """All (ray, Gaussian) pairs in 50-digit arithmetic, no bounding boxes, no
-    sorting shortcuts: {(view, px, py): (A, [(i, a_i)])} over every ray."""
+    sorting shortcuts: {(view, px, py): ([A_q], [(i, [a_q])])} over every
+    ray, for the queries of `mode` (Section 3.4): one with c_R + c_G + c_B
+    (0), with colour 1 (1), the L2 form sum_k c_k^2 rho^2 T^2 (2), or three
+    with c_R, c_G, c_B (3)."""
     import mpmath as mp
     mp.mp.dps = 50
     n = sc.n
@@ -377,25 +432,31 @@ def _mp_ray_contributions(sc, vw, W, H):
             inv = C2 ** -1
             m2 = (fx * x / z + cx, fy * y / z + cy)
             d = [mu[k] - camc[k] for k in range(3)]
-            cbar = 0
-            for ch in range(3):
-                c = mp.mpf(float(sc.sh[0, ch, i])) * mp.mpf(1) / (2 * mp.sqrt(mp.pi)) + mp.mpf("0.5")
-                cbar += max(c, 0)
-            gs.append((np.float32(float(z)), i, inv, m2, mp.mpf(float(sc.opacity[i])), cbar))
+            rgb = [max(mp.mpf(float(sc.sh[0, ch, i])) * mp.mpf(1) / (2 * mp.sqrt(mp.pi)) + mp.mpf("0.5"), 0)
+                   for ch in range(3)]
+            gs.append((np.float32(float(z)), i, inv, m2, mp.mpf(float(sc.opacity[i])), rgb))
         gs.sort(key=lambda t: (t[0], t[1]))
         for py in range(H):
             for px in range(W):
                 u = (mp.mpf(px) + mp.mpf("0.5"), mp.mpf(py) + mp.mpf("0.5"))
-                T, A, contrib = mp.mpf(1), mp.mpf(0), []
-                for (_, i, inv, m2, al, cb) in gs:
+                nq = 3 if mode == 3 else 1
+                T, A, contrib = mp.mpf(1), [mp.mpf(0)] * nq, []
+                for (_, i, inv, m2, al, rgb) in gs:
                     dx, dy = u[0] - m2[0], u[1] - m2[1]
                     d2 = inv[0, 0] * dx * dx + 2 * inv[0, 1] * dx * dy + inv[1, 1] * dy * dy
                     if d2 > 9:
                         continue
                     rho = al * mp.e ** (-d2 / 2)
-                    a = cb * rho * T
+                    if mode == 0:
+                        a = [(rgb[0] + rgb[1] + rgb[2]) * rho * T]
+                    elif mode == 1:
+                        a = [rho * T]
+                    elif mode == 2:
+                        a = [sum(c * c * rho * rho * T * T for c in rgb)]
+                    else:
+                        a = [c * rho * T for c in rgb]
                     contrib.append((i, a))
-                    A += a
+                    A = [x + y for x, y in zip(A, a)]
                     T *= 1 - rho
                 out[(v, px, py)] = (A, contrib)
     return out
@@ -413,30 +474,41 @@ def _bruteforce_scene(n, W, H, seed):
     return sc, vw
 
 
-def test_bruteforce_mpmath_tiny(ora):
-    """The oracle's per-ray sensitivities agree with 50-digit brute force to ~1e-13."""
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_bruteforce_mpmath_tiny(ora, mode):
+    """The oracle's per-ray sensitivities and query objectives agree with
+    50-digit brute force to ~1e-13 for every query mode: RGB sum, nocolor,
+    L2 and per channel (Section 3.4; Algorithm 1's channel queries)."""
     import mpmath as mp
     n, W, H = 6, 10, 8
     sc, vw = _bruteforce_scene(n, W, H, 11)
-    r = ora.sensitivity(sc, vw, ora.default_params(dilation=0.3))
+    r = ora.sensitivity(sc, vw, ora.default_params(dilation=0.3, query_mode=mode))
+    rays = _mp_ray_contributions(sc, vw, W, H, mode)
     s_ref = [mp.mpf(0)] * n
-    for (A, contrib) in _mp_ray_contributions(sc, vw, W, H).values():
-        if A > 0:
-            for i, a in contrib:
-                s_ref[i] = max(s_ref[i], a / A)
+    for (A, contrib) in rays.values():
+        for q, Aq in enumerate(A):
+            if Aq > 0:
+                for i, a in contrib:
+                    s_ref[i] = max(s_ref[i], a[q] / Aq)
     ref = np.array([float(x) for x in s_ref])
     assert (ref > 0).sum() >= 4
     assert np.allclose(r["s"], ref, rtol=1e-12, atol=1e-300)
+    A_ref = np.array([[float(x) for x in rays[(v, px, py)][0]]
+                      for v in range(vw.n_views) for py in range(H) for px in range(W)])
+    A_got = r["A"].reshape(A_ref.shape)
+    assert np.allclose(A_got, A_ref, rtol=1e-12, atol=1e-300)
 
 
-def test_bruteforce_mpmath_aggregated(ora):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_bruteforce_mpmath_aggregated(ora, mode):
     """Per-tile (16x16, ragged at the edges), per-image and per-scene
     sensitivities (Section 3.4): a_i and A summed over each query's rays in
-    50-digit arithmetic, then the maximum over queries of their ratio."""
+    50-digit arithmetic, then the maximum over queries of their ratio (for
+    the L1 and the L2 contributions)."""
     import mpmath as mp
     n, W, H = 6, 20, 18              # 2 x 2 tiles per view, the right and bottom ones ragged
     sc, vw = _bruteforce_scene(n, W, H, 12)
-    rays = _mp_ray_contributions(sc, vw, W, H)
+    rays = {k: (A[0], [(i, a[0]) for i, a in c]) for k, (A, c) in _mp_ray_contributions(sc, vw, W, H, mode).items()}
     keys = {1: lambda v, px, py: (v, px // 16, py // 16), 2: lambda v, px, py: v, 3: lambda v, px, py: 0}
     for level in (1, 2, 3):
         num, den = {}, {}
@@ -450,7 +522,7 @@ def test_bruteforce_mpmath_aggregated(ora):
             if den[k] > 0:
                 s_ref[i] = max(s_ref[i], a / den[k])
         ref = np.array([float(x) for x in s_ref])
-        got = ora.sensitivity_agg(sc, vw, level, ora.default_params(dilation=0.3))
+        got = ora.sensitivity_agg(sc, vw, level, ora.default_params(dilation=0.3, query_mode=mode))
         assert (ref > 0).sum() >= 4, level
         assert np.allclose(got, ref, rtol=1e-12, atol=1e-300), (level, got, ref)
 
