@@ -26,9 +26,7 @@
  * included); Gaussians with camera depth z <= z_near are absent; the
  * front-to-back order is ascending float32-rounded camera depth with ties
  * broken by index; colour is real SH of degree <= 3 at the direction from the
- * camera centre to the mean, plus 1/2, clamped at 0; the per-ray objective
- * sums the three channels (GS_QUERY_RGBSUM) or uses colour 1
- * (GS_QUERY_NOCOLOR, the paper's "nocolor" score variant).
+ * camera centre to the mean, plus 1/2, clamped at 0.
  */
 #ifndef GS_CORESET_H
 #define GS_CORESET_H
@@ -51,7 +49,25 @@ typedef enum {
 } gs_status;
 
 typedef enum { GS_ATTR_F32 = 0, GS_ATTR_MIXED16 = 1 } gs_attr_format;
-typedef enum { GS_QUERY_RGBSUM = 0, GS_QUERY_NOCOLOR = 1 } gs_query_mode;
+/* What a query measures (Section 3.4, score variants; Algorithm 1's channel
+ * queries).  With rho the attenuation of a pair and T the transmittance in
+ * front of it, a Gaussian's contribution to a query of its ray is
+ *   GS_QUERY_RGBSUM:  (c_R + c_G + c_B) rho T   (one query per ray: the L1
+ *                     score with the channels summed)
+ *   GS_QUERY_NOCOLOR: rho T                     (the "nocolor" variant)
+ *   GS_QUERY_L2:      (c_R^2 + c_G^2 + c_B^2) rho^2 T^2  (the L2 variant,
+ *                     its three channel terms summed into one pixel query)
+ *   GS_QUERY_CHANNEL: c_k rho T for k = R, G, B (three queries per ray)
+ * and a query's objective A is the sum of the contributions over its ray.
+ * GS_QUERY_CHANNEL has no aggregated form (an aggregated query sums its
+ * channels: use GS_QUERY_RGBSUM) and no gs_render_objective form (which
+ * reports one value per ray); plans take every mode but GS_QUERY_CHANNEL. */
+typedef enum {
+    GS_QUERY_RGBSUM = 0,
+    GS_QUERY_NOCOLOR = 1,
+    GS_QUERY_L2 = 2,
+    GS_QUERY_CHANNEL = 3
+} gs_query_mode;
 typedef enum { GS_OBJ_FULL = 0, GS_OBJ_FIXED = 1, GS_OBJ_TRUE = 2 } gs_objective;
 /* GS_FLAG_COUNT_PAIRS: gs_sensitivity fills the pair counters of gs_stats
  * (a pass-2 variant that counts; without it those counters read 0). */

@@ -19,10 +19,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (AGG_IMAGE, AGG_RAY, AGG_SCENE, AGG_TILE, ATTR_F32, ATTR_MIXED16, GsError, OBJ_FIXED,
-                   OBJ_FULL, OBJ_TRUE, QUERY_NOCOLOR, QUERY_RGBSUM, load)
+                   OBJ_FULL, OBJ_TRUE, QUERY_CHANNEL, QUERY_L2, QUERY_NOCOLOR, QUERY_RGBSUM, load)
 
 __all__ = ["DeviceScene", "sensitivity", "sample_coreset", "render_objective", "GsError",
-           "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "ATTR_F32",
+           "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "QUERY_L2", "QUERY_CHANNEL", "ATTR_F32",
            "ATTR_MIXED16", "AGG_RAY", "AGG_TILE", "AGG_IMAGE", "AGG_SCENE", "load", "release_workspace",
            "Plan", "measure_peaks"]
 

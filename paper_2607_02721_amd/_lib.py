@@ -28,7 +28,7 @@ EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_de
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 FLAG_COUNT_PAIRS = 1
 AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE = 0, 1, 2, 3
-QUERY_RGBSUM, QUERY_NOCOLOR = 0, 1
+QUERY_RGBSUM, QUERY_NOCOLOR, QUERY_L2, QUERY_CHANNEL = 0, 1, 2, 3
 ATTR_F32, ATTR_MIXED16 = 0, 1
 
 

@@ -111,6 +111,7 @@ struct Setup {
     int64_t N;
     int nchunks;
     int agg = GS_AGG_RAY;       // query granularity of the sensitivity pass
+    int nq = 1;                 // queries per ray (3 for per-channel queries)
     std::vector<int> tiles_x, tiles_y;
     std::vector<int64_t> ray_base;
 };
@@ -122,6 +123,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
     add(3 * sizeof(float4) * (size_t)c.vc * N);      // records
+    if (S.nq > 1) add(sizeof(float4) * (size_t)c.vc * N);   // channel colours
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)c.vc * N);
     add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
     add(2 * sizeof(uint32_t) * (size_t)c.vc);
@@ -129,7 +131,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint32_t) * c.total_tiles);
     add(sizeof(uint64_t) * (c.total_tiles + 1));
     add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
-    add(sizeof(float) * (size_t)c.rays);
+    add(sizeof(float) * (size_t)c.rays * S.nq);
     add(sizeof(uint64_t) * CNT_WORDS);
     add(sizeof(ViewDev) * c.vc);
     add(sizeof(int32_t) * c.total_tiles);
@@ -200,7 +202,7 @@ gs_status check_params(const gs_params *p) {
         return fail(GS_ERR_INVALID_ARGUMENT, "z_near must be finite and > 0");
     if (!(p->share_floor >= 0.0f) || !std::isfinite(p->share_floor))
         return fail(GS_ERR_INVALID_ARGUMENT, "share_floor must be >= 0");
-    if (p->query_mode != GS_QUERY_RGBSUM && p->query_mode != GS_QUERY_NOCOLOR)
+    if (p->query_mode < GS_QUERY_RGBSUM || p->query_mode > GS_QUERY_CHANNEL)
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown query_mode %d", p->query_mode);
     if (p->max_views_per_chunk < 0) return fail(GS_ERR_INVALID_ARGUMENT, "max_views_per_chunk must be >= 0");
     if (p->flags & ~GS_FLAG_COUNT_PAIRS) return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", p->flags);
@@ -208,6 +210,9 @@ gs_status check_params(const gs_params *p) {
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown aggregate %d", p->aggregate);
     if (p->aggregate != GS_AGG_RAY && (p->flags & GS_FLAG_COUNT_PAIRS))
         return fail(GS_ERR_UNSUPPORTED, "pair counting needs per-ray queries");
+    if (p->aggregate != GS_AGG_RAY && p->query_mode == GS_QUERY_CHANNEL)
+        return fail(GS_ERR_UNSUPPORTED, "per-channel queries have no aggregated form (an aggregated query sums "
+                                        "its channels: use GS_QUERY_RGBSUM)");
     return GS_OK;
 }
 
@@ -299,6 +304,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.R0 = cv.take<float4>((size_t)c.vc * N);
     b.R1 = cv.take<float4>((size_t)c.vc * N);
     b.R2 = cv.take<float4>((size_t)c.vc * N);
+    b.R3 = S.nq > 1 ? cv.take<float4>((size_t)c.vc * N) : nullptr;
     b.key0 = cv.take<uint32_t>((size_t)c.vc * N);
     b.val0 = cv.take<uint32_t>((size_t)c.vc * N);
     b.key1 = cv.take<uint32_t>((size_t)c.vc * N);
@@ -311,7 +317,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.tile_tot = cv.take<uint32_t>(c.total_tiles);
     b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
     r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
-    b.ray_A = cv.take<float>(c.rays);
+    b.ray_A = cv.take<float>((size_t)c.rays * S.nq);
     b.counters = cv.take<uint64_t>(CNT_WORDS);
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
@@ -400,7 +406,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     tm.mark(7, st);
     // the compositing launch sees this chunk as a single scene slot
     r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
-                            N, 0, 0};
+                            N, 0, 0, b.R3, c.rays};
     HIP_TRY(hipMemcpyAsync(r.slot_dev, &r.host_slot, sizeof(SceneSlot), hipMemcpyHostToDevice, st));
     launch_fill_u32((uint32_t *)r.tile_scene, 0u, c.total_tiles, st);
     tm.mark(3, st);
@@ -512,6 +518,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     S.N = scene->n;
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     S.agg = params->aggregate;
+    S.nq = params->query_mode == GS_QUERY_CHANNEL ? 3 : 1;
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
     launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
     // per-scene queries: the absolute contributions and A summed over chunks
@@ -621,6 +628,8 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown objective %d", objective);
     if (objective != GS_OBJ_FULL && !weights)
         return fail(GS_ERR_INVALID_ARGUMENT, "weights are required for the fixed and true objectives");
+    if (params->query_mode == GS_QUERY_CHANNEL)
+        return fail(GS_ERR_UNSUPPORTED, "the objectives hold one query per ray (no per-channel queries)");
     std::lock_guard<std::mutex> lk(g_lock);
     const int dev = current_device(&s);
     if (dev < 0) return s;
@@ -1135,6 +1144,8 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
     if ((s = check_params(params)) != GS_OK) return s;
     if (params->ray_mask) return fail(GS_ERR_UNSUPPORTED, "plans do not take a ray mask");
     if (params->aggregate != GS_AGG_RAY) return fail(GS_ERR_UNSUPPORTED, "plans compute per-ray sensitivities");
+    if (params->query_mode == GS_QUERY_CHANNEL)
+        return fail(GS_ERR_UNSUPPORTED, "plans compute one query per ray (no per-channel queries)");
     if (params->flags) return fail(GS_ERR_UNSUPPORTED, "plans do not count pairs");
     gs_plan *P = new gs_plan();
     P->p = *params;

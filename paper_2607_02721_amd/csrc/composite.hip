@@ -59,6 +59,8 @@ struct WaveSetup {
     const uint32_t *ray_mask;
     float *ray_A;
     float cmax;
+    const float4 *R3;       // per-channel queries: channel colours
+    int64_t ray_stride;     // per-channel queries: ray_A plane stride
 };
 
 __device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles * 4; }
@@ -98,6 +100,8 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.ray_mask = S.ray_mask;
     w.ray_A = S.ray_A;
     w.cmax = __uint_as_float(S.cmax[w.v - S.view0]);
+    w.R3 = S.R3;
+    w.ray_stride = S.ray_stride;
     return true;
 }
 
@@ -160,10 +164,13 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
 // the slots up to the next multiple of kPad hold null entries, so a loop can
 // run in unguarded blocks of kPad pairs.
 // geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
-// col = (g', alpha, cbar, extra).
-template <int kExtra, int kPad = 1>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
+// col = (g', alpha, cbar, extra), or with kChannel (g', alpha, c_R, c_G) and
+// c_B in cblue.
+template <int kExtra, int kPad = 1, bool kChannel = false>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
 __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
-                                           uint32_t *sid, float *sold, const double *__restrict__ weights) {
+                                           uint32_t *sid, float *sold, const double *__restrict__ weights,
+                                           float *cblue = nullptr) {
+    static_assert(!(kChannel && kExtra == 2), "per-channel queries have no weighted objective");
     const int lane = threadIdx.x;
     const uint64_t e = e0 + lane;
     const uint32_t raw = e < w.end ? w.lists[e] : 0u;
@@ -192,11 +199,20 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         if (slot < ((n + kPad - 1) & ~(kPad - 1))) {
             geo[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             col[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (kChannel) cblue[slot] = 0.0f;
         }
     }
     if (touch) {
         const int slot = __popcll(bal & lanemask_lt64());
-        const float cb = R2[o].x;
+        float cb = 0.0f, cg = 0.0f;
+        if (kChannel) {
+            const float4 c3 = w.R3[o];
+            cb = c3.x;
+            cg = c3.y;
+            cblue[slot] = c3.z;
+        } else {
+            cb = R2[o].x;
+        }
         geo[slot] = make_float4(mx, my, r1.x, r1.y);
         float extra = 0.0f;
         if (kExtra == 1) {
@@ -208,6 +224,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
             sold[slot] = __uint_as_float((uint32_t)(e - w.start));
         }
         if (kExtra == 2) extra = (float)weights[g];
+        if (kChannel) extra = cg;
         col[slot] = make_float4(r1.z, r1.w, cb, extra);
     }
     return n;
@@ -227,9 +244,15 @@ __device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, flo
     return in_fp ? Cc.y * E : 0.0f;
 }
 
-template <bool kPersistent>
+// Pass 1 per query mode (kModeL1: a = c rho T; kModeL2: a = c (rho T)^2;
+// kModeChannel: three queries, a_k = c_k rho T).  A ray stops once no later
+// Gaussian can add floor times its objective: c_max T (c_max T^2 for L2)
+// below floor A, with the smallest of the three objectives per channel.
+template <bool kPersistent, int kMode>
 __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
     __shared__ float4 geo[kWave], col[kWave];
+    __shared__ float cblue[kMode == kModeChannel ? kWave : 1];
+    constexpr bool kCh = kMode == kModeChannel;
     const int nq = quad_count(a);
     int iter = 0;
     for (int qi = next_quad<kPersistent>(a, iter); qi < nq; qi = next_quad<kPersistent>(a, iter)) {
@@ -237,24 +260,42 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
         if (!setup_quad(a, qi, w)) continue;
         const bool scored = w.inside && ray_selected(w.ray_mask, w.ray_global);
         const float cmax = w.cmax;
-        float T = 1.0f, A = 0.0f;
+        float T = 1.0f, A = 0.0f, AG = 0.0f, AB = 0.0f;
         bool done = !scored;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<0>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr);
+            const int n = stage_slice<0, 1, kCh>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr, cblue);
             __syncthreads();
             for (int j = 0; j < n; ++j) {
                 const float4 G = geo[j], Cc = col[j];
                 bool in_fp;
                 const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
-                const float cr = Cc.z * rho;
-                A = fmaf(cr, T, A);
+                if (kMode == kModeL1) {
+                    const float cr = Cc.z * rho;
+                    A = fmaf(cr, T, A);
+                } else if (kMode == kModeL2) {
+                    const float rt = rho * T;
+                    A = fmaf(Cc.z * rt, rt, A);
+                } else {
+                    const float rt = rho * T;
+                    A = fmaf(Cc.z, rt, A);
+                    AG = fmaf(Cc.w, rt, AG);
+                    AB = fmaf(cblue[j], rt, AB);
+                }
                 T = fmaf(-rho, T, T);
             }
-            done = done || (T * cmax < a.share_floor * A);
+            if (kMode == kModeL1) done = done || (T * cmax < a.share_floor * A);
+            if (kMode == kModeL2) done = done || ((T * T) * cmax < a.share_floor * A);
+            if (kCh) done = done || (T * cmax < a.share_floor * fminf(A, fminf(AG, AB)));
             __syncthreads();
         }
-        if (w.inside) w.ray_A[w.ray_local] = scored ? A : 0.0f;
+        if (w.inside) {
+            w.ray_A[w.ray_local] = scored ? A : 0.0f;
+            if (kCh) {
+                w.ray_A[w.ray_stride + w.ray_local] = scored ? AG : 0.0f;
+                w.ray_A[2 * w.ray_stride + w.ray_local] = scored ? AB : 0.0f;
+            }
+        }
     }
 }
 
@@ -371,11 +412,15 @@ __device__ __forceinline__ float wave_transpose_sum16(float (&v)[16]) {
     return dpp_add<0xB1>(dpp_add<0x4E>(v[0]));
 }
 
-template <bool kStats, bool kPersistent, int kAgg>
-__global__ __launch_bounds__(kWave, kPersistent ? 5 : (kAgg != 0 ? 6 : 8)) void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
+template <bool kStats, bool kPersistent, int kAgg, int kMode>
+__global__ __launch_bounds__(kWave, kPersistent ? 5 : ((kAgg != 0 || kMode == kModeChannel) ? 6 : 8))
+void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
+    static_assert(!(kAgg != 0 && kMode == kModeChannel), "per-channel queries have no aggregated form");
+    constexpr bool kCh = kMode == kModeChannel;
     __shared__ float4 geo[kWave], col[kWave];
     __shared__ uint32_t sid[kWave];
     __shared__ float sold[kWave];
+    __shared__ float cblue[kCh ? kWave : 1];
     const int lane = threadIdx.x;
     const int nq = quad_count(a);
     int iter = 0;
@@ -386,6 +431,18 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : (kAgg != 0 ? 6 : 8)) void 
         const bool scored = w.inside && ray_selected(w.ray_mask, w.ray_global);
         const float Af = scored ? w.ray_A[w.ray_local] : 0.0f;
         const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
+        // per channel: the G and B objectives, and the smallest of the three
+        // (the stop bar); a ray counts as positive if one of them is
+        float invG = 0.0f, invB = 0.0f, Amin = Af;
+        bool positive = invA > 0.0f;
+        if (kCh) {
+            const float AG = scored ? w.ray_A[w.ray_stride + w.ray_local] : 0.0f;
+            const float AB = scored ? w.ray_A[2 * w.ray_stride + w.ray_local] : 0.0f;
+            invG = AG > 0.0f ? 1.0f / AG : 0.0f;
+            invB = AB > 0.0f ? 1.0f / AB : 0.0f;
+            Amin = fminf(Af, fminf(AG, AB));
+            positive = positive || invG > 0.0f || invB > 0.0f;
+        }
         // the share's denominator: the ray's A, or the A of the lane's query
         float invQ = invA;
         if (kAgg != 0) {
@@ -395,12 +452,13 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : (kAgg != 0 ? 6 : 8)) void 
         const float cmax = w.cmax;
         uint32_t *sens_bits = w.sens_bits;
         float T = 1.0f;
-        bool done = invA == 0.0f;
+        bool done = !positive;
         uint32_t n_in = 0, n_live = 0, n_eval = 0;
-        const float live_bar = a.share_floor * Af;
+        const float live_bar = a.share_floor * Amin;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<kAgg == 0 ? 1 : 3, kBlock>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr);
+            const int n = stage_slice<kAgg == 0 ? 1 : 3, kBlock, kCh>(w, e0, a.r2_log2, geo, col, sid, sold,
+                                                                      nullptr, cblue);
             __syncthreads();
             for (int jb = 0; jb < n; jb += 16) {
                 float sh[16];
@@ -413,12 +471,21 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : (kAgg != 0 ? 6 : 8)) void 
                             const float4 G = geo[j], Cc = col[j];
                             bool in_fp;
                             const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
-                            const float cr = Cc.z * rho;
-                            sh[k0 + q] = (cr * T) * invQ;
+                            if (kMode == kModeL1) {
+                                const float cr = Cc.z * rho;
+                                sh[k0 + q] = (cr * T) * invQ;
+                            } else if (kMode == kModeL2) {
+                                const float rt = rho * T;
+                                sh[k0 + q] = ((Cc.z * rt) * rt) * invQ;
+                            } else {
+                                const float rt = rho * T;
+                                sh[k0 + q] = rt * fmaxf(Cc.z * invA, fmaxf(Cc.w * invG, cblue[j] * invB));
+                            }
                             if (kStats) {
                                 const bool real = j < n;
+                                const float later = kMode == kModeL2 ? (T * T) * cmax : T * cmax;
                                 n_in += (real && in_fp) ? 1u : 0u;
-                                n_live += (real && in_fp && T * cmax >= live_bar) ? 1u : 0u;
+                                n_live += (real && in_fp && later >= live_bar) ? 1u : 0u;
                             }
                             T = fmaf(-rho, T, T);
                         }
@@ -441,13 +508,14 @@ __global__ __launch_bounds__(kWave, kPersistent ? 5 : (kAgg != 0 ? 6 : 8)) void 
                     }
                 }
             }
-            done = done || (T * cmax < a.share_floor * Af);
+            const float later = kMode == kModeL2 ? (T * T) * cmax : T * cmax;
+            done = done || (later < a.share_floor * Amin);
             __syncthreads();
         }
         if (kStats) {
-            pin += invA > 0.0f ? n_in : 0u;
-            plive += invA > 0.0f ? n_live : 0u;
-            pos += invA > 0.0f ? 1u : 0u;
+            pin += positive ? n_in : 0u;
+            plive += positive ? n_live : 0u;
+            pos += positive ? 1u : 0u;
             peval += (uint64_t)n_eval;
         }
     }
@@ -485,40 +553,78 @@ static unsigned resident_waves(K kernel) {
 
 static inline unsigned flat_grid(const CompositeArgs &a) { return (unsigned)(((a.total_tiles * 4) + 7) & ~7); }
 
+template <int kMode>
+static void pass1_mode(const CompositeArgs &a, hipStream_t st) {
+    if constexpr (kMode != kModeChannel) {
+        if (a.work) {
+            static const unsigned grid = resident_waves(k_pass1<true, kMode>);
+            launch_fill_u32(a.work, 0u, 1, st);
+            hipLaunchKernelGGL((k_pass1<true, kMode>), dim3(grid), dim3(kWave), 0, st, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_pass1<false, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a);
+}
+
+// The persistent form exists for the one-query modes (per-channel launches
+// are always flat).
 void launch_composite_pass1(const CompositeArgs &a, hipStream_t st) {
-    if (a.work) {
-        static const unsigned grid = resident_waves(k_pass1<true>);
-        launch_fill_u32(a.work, 0u, 1, st);
-        hipLaunchKernelGGL(k_pass1<true>, dim3(grid), dim3(kWave), 0, st, a);
-    } else {
-        hipLaunchKernelGGL(k_pass1<false>, dim3(flat_grid(a)), dim3(kWave), 0, st, a);
+    switch (composite_mode(a.query_mode)) {
+        case kModeL2: pass1_mode<kModeL2>(a, st); break;
+        case kModeChannel: pass1_mode<kModeChannel>(a, st); break;
+        default: pass1_mode<kModeL1>(a, st); break;
     }
 }
 
+template <int kMode>
+static void pass2_agg(const CompositeArgs &a, uint64_t *counters, hipStream_t st) {
+    if (a.agg == 1)
+        hipLaunchKernelGGL((k_pass2<false, false, 1, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    else if (a.agg == 2)
+        hipLaunchKernelGGL((k_pass2<false, false, 2, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    else
+        hipLaunchKernelGGL((k_pass2<false, false, 3, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+}
+
+template <int kMode, bool kPersistentForm>
+static void pass2_ray(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
+    if constexpr (kPersistentForm) {
+        if (a.work) {
+            launch_fill_u32(a.work, 0u, 1, st);
+            if (stats) {
+                static const unsigned grid = resident_waves(k_pass2<true, true, 0, kMode>);
+                hipLaunchKernelGGL((k_pass2<true, true, 0, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+            } else {
+                static const unsigned grid = resident_waves(k_pass2<false, true, 0, kMode>);
+                hipLaunchKernelGGL((k_pass2<false, true, 0, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+            }
+            return;
+        }
+    }
+    if (stats) {
+        hipLaunchKernelGGL((k_pass2<true, false, 0, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    } else {
+        hipLaunchKernelGGL((k_pass2<false, false, 0, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    }
+}
+
+// Aggregated queries run the flat form without pair counters; per-channel
+// queries have no aggregated or persistent form (the host rejects the first).
 void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
-    if (a.agg != 0) {   // aggregated queries: flat form, no pair counters
-        if (a.agg == 1)
-            hipLaunchKernelGGL((k_pass2<false, false, 1>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
-        else if (a.agg == 2)
-            hipLaunchKernelGGL((k_pass2<false, false, 2>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
-        else
-            hipLaunchKernelGGL((k_pass2<false, false, 3>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+    const int mode = composite_mode(a.query_mode);
+    if (a.agg != 0) {
+        if (mode == kModeL2)
+            pass2_agg<kModeL2>(a, counters, st);
+        else if (mode == kModeL1)
+            pass2_agg<kModeL1>(a, counters, st);
         return;
     }
-    if (a.work) {
-        launch_fill_u32(a.work, 0u, 1, st);
-        if (stats) {
-            static const unsigned grid = resident_waves(k_pass2<true, true, 0>);
-            hipLaunchKernelGGL((k_pass2<true, true, 0>), dim3(grid), dim3(kWave), 0, st, a, counters);
-        } else {
-            static const unsigned grid = resident_waves(k_pass2<false, true, 0>);
-            hipLaunchKernelGGL((k_pass2<false, true, 0>), dim3(grid), dim3(kWave), 0, st, a, counters);
-        }
-    } else if (stats) {
-        hipLaunchKernelGGL((k_pass2<true, false, 0>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
-    } else {
-        hipLaunchKernelGGL((k_pass2<false, false, 0>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
-    }
+    if (mode == kModeL2)
+        pass2_ray<kModeL2, true>(a, stats, counters, st);
+    else if (mode == kModeChannel)
+        pass2_ray<kModeChannel, false>(a, stats, counters, st);
+    else
+        pass2_ray<kModeL1, true>(a, stats, counters, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,8 +753,12 @@ void launch_div_f64_to_f32(const double *num, const double *den, int64_t n, floa
 // pairs with w rho >= 1 (Definition 2) and tracks the log-transmittance gap
 // |log T - log T_w| = |sum log(1 - rho_j) - log(1 - w_j rho_j)| at every
 // contributing retained pair (Assumption 1), on rays that stay valid.
+// kModeL2 replaces each contribution c rho T by c (rho T)^2 (and c rho T_w by
+// c (rho T_w)^2 in the reduced render).
+template <int kMode>
 __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveArgs o,
                                                      uint64_t *__restrict__ counters) {
+    static_assert(kMode != kModeChannel, "the objectives hold one query per ray");
     __shared__ float4 geo[kWave], col[kWave];
     const int nq = quad_count(a);
     int iter = 0;
@@ -667,9 +777,9 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
     bool bad = false;
     uint32_t n_bad = 0;
     // Optional stop for the full and fixed objectives: every later term of
-    // A^th_w is w_i c_i rho_i T_i <= w_max c_max T, so once
-    // T c_max w_max < stop_rel A the rest changes A and A^th_w by less than
-    // stop_rel A.  (A_w has its own transmittance and gets no stop.)
+    // A^th_w is w_i c_i rho_i T_i <= w_max c_max T (w_max c_max T^2 for L2),
+    // so once that bound is below stop_rel A the rest changes A and A^th_w by
+    // less than stop_rel A.  (A_w has its own transmittance and gets no stop.)
     float stop_scale = 0.0f;
     if (o.wmax_bits) {
         const double wm = __longlong_as_double((long long)*o.wmax_bits);
@@ -686,14 +796,20 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
             bool in_fp;
             const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
             const float cr = Cc.z * rho;
-            const float aT = cr * T;
+            const float rt = rho * T;
+            const float aT = kMode == kModeL2 ? (Cc.z * rt) * rt : cr * T;
             A += aT;
             if (has_w) {
                 const float wi = Cc.w;
                 Ax = fmaf(wi, aT, Ax);
                 if (wi > 0.0f) {
                     const float wr = wi * rho;
-                    At = fmaf(wi * cr, Tw, At);
+                    if (kMode == kModeL2) {
+                        const float rtw = rho * Tw;
+                        At = fmaf(wi * (Cc.z * rtw), rtw, At);
+                    } else {
+                        At = fmaf(wi * cr, Tw, At);
+                    }
                     if (rho > 0.0f && !bad) gmax = fmaxf(gmax, fabsf(gap));
                     if (wr >= 1.0f) {
                         bad = true;
@@ -707,7 +823,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
             }
             T = fmaf(-rho, T, T);
         }
-        if (o.wmax_bits) done = done || (T * stop_scale < o.stop_rel * A);
+        if (o.wmax_bits) done = done || ((kMode == kModeL2 ? T * T : T) * stop_scale < o.stop_rel * A);
         __syncthreads();
     }
     const bool on = scored && A > 0.0f;
@@ -738,7 +854,10 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
 
 // Always the flat form (a.work is ignored).
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st) {
-    hipLaunchKernelGGL(k_objective, dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
+    if (composite_mode(a.query_mode) == kModeL2)
+        hipLaunchKernelGGL(k_objective<kModeL2>, dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
+    else
+        hipLaunchKernelGGL(k_objective<kModeL1>, dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
 }
 
 // Largest value of a non-negative double array (as bits: monotone for x >= 0).

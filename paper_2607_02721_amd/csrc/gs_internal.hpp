@@ -51,6 +51,7 @@ struct ChunkBufs {
     float4 *R0;          // [Vc*N] mean2d hi.x, hi.y, lo.x, lo.y
     float4 *R1;          // [Vc*N] beta, a', g', alpha   (d^2 form, see project.hip)
     float4 *R2;          // [Vc*N] cbar, x-range, y-range (int16 pairs as bits), z
+    float4 *R3;          // [Vc*N] per-channel queries only: c_R, c_G, c_B, 0 (else null)
     uint32_t *key0, *val0, *key1, *val1;  // [Vc*N] sort ping-pong
     uint32_t *hist;      // radix histograms [Vc][256][nb]
     uint32_t *nvis;      // [Vc] visible Gaussians per view
@@ -62,7 +63,7 @@ struct ChunkBufs {
     uint32_t *tile_tot;  // [tiles in chunk] entries per tile
     uint64_t *tile_off;  // exclusive scan of tile_tot (+1 trailing total): the tile's list
     uint32_t *lists;     // [D] entries
-    float *ray_A;        // [rays in chunk] pass-1 render
+    float *ray_A;        // [queries per ray][rays in chunk] pass-1 render
     uint8_t *tile_active; // [tiles in chunk] tiles holding a selected ray (null: all)
     uint64_t *counters;  // device statistics
 };
@@ -118,7 +119,16 @@ struct SceneSlot {
     int64_t N;
     int32_t view0;                // first view of the scene in the launch's view table
     int32_t tile0;                // first tile of the scene in the launch's tile table
+    const float4 *R3;             // per-channel queries: channel colours [views][N] (else null)
+    int64_t ray_stride;           // per-channel queries: distance between the R, G and B planes of ray_A
 };
+
+// Compositing arithmetic of a query mode: one L1 query per ray (RGB sum or
+// colour 1), one L2 query, or three per-channel L1 queries.
+enum : int { kModeL1 = 0, kModeL2 = 1, kModeChannel = 2 };
+constexpr int composite_mode(int query_mode) {
+    return query_mode == 2 ? kModeL2 : (query_mode == 3 ? kModeChannel : kModeL1);
+}
 
 struct CompositeArgs {
     const ViewDev *views;        // view table of the launch (tile_base is scene-local)

@@ -18,6 +18,10 @@
 //        cancellation between them.
 //   R2 = (cbar, x-range, y-range, z): the inclusive pixel ranges whose
 //        centres can fall inside the r-ellipse, packed as int16 (lo | hi << 16).
+//        cbar is the query colour factor: c_R + c_G + c_B (RGB sum), 1
+//        (nocolor), c_R^2 + c_G^2 + c_B^2 (L2) or the largest channel (per
+//        channel, where it only bounds later contributions).
+//   R3 = (c_R, c_G, c_B, 0), written for per-channel queries only.
 #include "gs_internal.hpp"
 
 #include <hip/hip_fp16.h>
@@ -73,7 +77,7 @@ template <int kDeg, int kFmt>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
                                                  ProjParams pp, float4 *__restrict__ R0,
                                                  float4 *__restrict__ R1, float4 *__restrict__ R2,
-                                                 uint32_t *__restrict__ keys, uint32_t *__restrict__ nvis,
+                                                 float4 *__restrict__ R3, uint32_t *__restrict__ keys, uint32_t *__restrict__ nvis,
                                                  uint32_t *__restrict__ cmax_bits,
                                                  uint64_t *__restrict__ counters) {
     const int64_t n = sc.n;
@@ -130,6 +134,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
         const double pz = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + V.t[2];
         bool vis = valid && pz > (double)pp.z_near;
         float4 r0 = make_float4(0, 0, 0, 0), r1 = make_float4(0, 0, 0, 0), r2 = make_float4(0, 0, 0, 0);
+        float4 r3 = make_float4(0, 0, 0, 0);
         float cbar = 0.0f;
         if (vis) {
             const double iz = 1.0 / pz;
@@ -173,16 +178,24 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                 const double dn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
                 double Y[16];
                 sh_basis(d0 * dn, d1 * dn, d2 * dn, Y);
-                double csum = 0.0;
+                double c[3];
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     double acc = 0.0;
 #pragma unroll
                     for (int k = 0; k < K; ++k) acc += Y[k] * (double)shc[3 * k + ch];
                     acc += 0.5;
-                    csum += acc > 0.0 ? acc : 0.0;
+                    c[ch] = acc > 0.0 ? acc : 0.0;
                 }
-                cbar = pp.query_mode == 1 ? 1.0f : (float)csum;
+                if (pp.query_mode == 1)
+                    cbar = 1.0f;
+                else if (pp.query_mode == 2)
+                    cbar = (float)(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+                else if (pp.query_mode == 3)
+                    cbar = (float)fmax(c[0], fmax(c[1], c[2]));
+                else
+                    cbar = (float)(c[0] + c[1] + c[2]);
+                r3 = make_float4((float)c[0], (float)c[1], (float)c[2], 0.0f);
                 r2 = make_float4(cbar, __uint_as_float(pack_range((int)xl, (int)xh)),
                                  __uint_as_float(pack_range((int)yl, (int)yh)), (float)pz);
             }
@@ -192,6 +205,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
             R0[o] = r0;
             R1[o] = r1;
             R2[o] = r2;
+            if (R3) R3[o] = r3;
             keys[o] = vis ? __float_as_uint((float)pz) : kInvisibleKey;
         }
         // per-view visible count and colour maximum (wave-reduced first)
@@ -210,7 +224,7 @@ static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const
                      hipStream_t st) {
     const int64_t blocks = (sc.n + 255) / 256;
     hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0,
-                       b.R1, b.R2, b.key0, b.nvis, b.cmax, b.counters);
+                       b.R1, b.R2, b.R3, b.key0, b.nvis, b.cmax, b.counters);
 }
 
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,

@@ -69,7 +69,7 @@ def _call_sens(lib, scene, views, params, out=0x1000):
 @pytest.mark.parametrize("case,status", [
     ("n0", 1), ("deg4", 1), ("fmt7", 1), ("nullplane", 1), ("nullviews", 1), ("nullparams", 1),
     ("sigma0", 1), ("mode9", 1), ("nullout", 1), ("huge_n", 2), ("too_many_tiles", 2), ("bad_size", 1),
-    ("neg_floor", 1), ("agg7", 1), ("agg_neg", 1), ("agg_pairs", 2),
+    ("neg_floor", 1), ("agg7", 1), ("agg_neg", 1), ("agg_pairs", 2), ("mode4", 1), ("channel_agg", 2),
 ])
 def test_sensitivity_argument_errors(lib, case, status):
     from paper_2607_02721_amd import _lib
@@ -89,6 +89,10 @@ def test_sensitivity_argument_errors(lib, case, status):
     if case == "neg_floor": p.share_floor = -1.0
     if case == "agg7": p.aggregate = 7
     if case == "agg_neg": p.aggregate = -1
+    if case == "mode4": p.query_mode = 4
+    if case == "channel_agg":
+        p.query_mode = _lib.QUERY_CHANNEL
+        p.aggregate = _lib.AGG_IMAGE
     if case == "agg_pairs":
         p.aggregate = _lib.AGG_TILE
         p.flags = _lib.FLAG_COUNT_PAIRS
@@ -111,6 +115,8 @@ def test_objective_argument_errors(lib):
     f = lib.gs_render_objective
     assert f(C.byref(sc), C.byref(vw.c), C.byref(p), None, 1, None, None, None, None) == 1  # weights needed
     assert f(C.byref(sc), C.byref(vw.c), C.byref(p), None, 5, None, None, None, None) == 1  # objective
+    p.query_mode = _lib.QUERY_CHANNEL
+    assert f(C.byref(sc), C.byref(vw.c), C.byref(p), None, 0, None, None, None, None) == 2  # one query per ray
 
 
 def test_default_params(lib):
@@ -139,6 +145,9 @@ def test_plan_argument_errors(lib):
     p = _lib.default_params()
     p.aggregate = _lib.AGG_IMAGE
     assert f(scenes, views, 1, C.byref(p), C.byref(h), None) == 2      # per-ray queries only
+    p = _lib.default_params()
+    p.query_mode = _lib.QUERY_CHANNEL
+    assert f(scenes, views, 1, C.byref(p), C.byref(h), None) == 2      # one query per ray
     p = _lib.default_params()
     bad = (_lib.Scene * 1)(_scene(n=0))
     assert f(bad, views, 1, C.byref(p), C.byref(h), None) == 1
