@@ -166,6 +166,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-agg", action="store_true", help="skip the aggregated-query variants")
+    ap.add_argument("--no-modes", action="store_true", help="skip the nocolor, L2 and per-channel score variants")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate microbenchmarks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (reference dispatch for counter runs)")
@@ -197,8 +198,9 @@ def main():
     dsc = gs.DeviceScene.from_scene(scene)
     torch.cuda.synchronize()
 
-    def step(stats=False, count_pairs=False, scene_dev=dsc, aggregate=gs.AGG_RAY):
-        s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs, aggregate=aggregate)
+    def step(stats=False, count_pairs=False, scene_dev=dsc, aggregate=gs.AGG_RAY, query_mode=gs.QUERY_RGBSUM):
+        s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs, aggregate=aggregate,
+                               query_mode=query_mode)
         counts, w, sup = gs.sample_coreset(s, m, seed)
         return s, st, w
 
@@ -265,6 +267,30 @@ def main():
                                 "total_sensitivity": st_a["total_sensitivity"], "stages_ms": stage_a}
             log(f"aggregated {name}: {ms_a:.2f} ms/step, S {st_a['total_sensitivity']:.4g}, "
                 f"E {aggregated[name]['coreset_err']:.4f}")
+        gs.release_workspace()
+
+    # score variants (per-ray queries): nocolor, L2 and per channel; each
+    # coreset is judged on the RGB-sum objective like the others
+    modes = None
+    if not args.no_modes:
+        modes = {}
+        for name, qm in (("nocolor", gs.QUERY_NOCOLOR), ("l2", gs.QUERY_L2), ("channel", gs.QUERY_CHANNEL)):
+            for _ in range(args.warmup):
+                step(query_mode=qm)
+            torch.cuda.synchronize()
+            stage_m = {k: 0.0 for k in stage}
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                s_m, st_m, w_m = step(stats=True, query_mode=qm)
+                for key in stage_m:
+                    stage_m[key] += st_m[key] / args.steps
+            torch.cuda.synchronize()
+            ms_m = (time.perf_counter() - t0) * 1e3 / args.steps
+            ob = gs.render_objective(dsc, views, w_m, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
+            modes[name] = {"ms": ms_m, "coreset_err": gs.coreset_error(ob["per_view"]),
+                           "total_sensitivity": st_m["total_sensitivity"], "stages_ms": stage_m}
+            log(f"mode {name}: {ms_m:.2f} ms/step, S {st_m['total_sensitivity']:.4g}, "
+                f"E {modes[name]['coreset_err']:.4f}")
         gs.release_workspace()
 
     learned = None
@@ -382,7 +408,7 @@ def main():
         "variants": {"exact_f32": {"ms": ms, "coreset_err": errs["exact"]},
                      "mixed16": {"ms": ms16, "coreset_err": errs["mixed16"], "stages_ms": stage16,
                                  "attribute_bytes": d16.attribute_bytes()},
-                     "learned": learned, "aggregated": aggregated},
+                     "learned": learned, "aggregated": aggregated, "score_variants": modes},
         "coreset_err_vs_m": scan,
         "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on 1% of the 8x8 pixel blocks, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],

@@ -4,30 +4,36 @@
 // radix-sorted (depth key, index) sequence; ties by index because the sort is
 // stable and starts from index order).  A list entry is keyed by (tile, p)
 // and the lists are built by a counting sort on that key:
-//   1. count: one block per chunk of 2^11 consecutive positions counts its
+//   1. count: one block per chunk of 2^14 consecutive positions counts its
 //             entries per tile in LDS and stores them, one row per chunk;
 //   2. scan:  per tile, the exclusive prefix over chunks (in place) and the
 //             tile's total; a scan of the totals gives each tile's list start,
 //             so a tile's list is its chunks' segments in order;
 //   3. emit:  one wave per (chunk, group of tile rows) expands the chunk's
-//             positions that meet its rows, in order, into (position, tile)
-//             items packed 64 to a batch; every tile's next slot comes from a
-//             wave-private LDS cursor (atomic add, executed in issue order),
-//             so each (tile, chunk) segment is written already sorted by p,
-//             as g | quadrant mask << 28.
+//             positions that meet its rows, in order and 2^9 at a time, into
+//             (position, tile) items packed 64 to a batch; every tile's next
+//             slot comes from a wave-private LDS cursor (atomic add, executed
+//             in issue order), so each (tile, chunk) segment is written
+//             already sorted by p, as g | quadrant mask << 28.
+// Chunks are long so that a tile's segment in a chunk spans whole cache
+// lines: list entries are 4 bytes, and segments of a few entries each end in
+// partial lines that cost a full write each.
 // Bit q of the mask says whether the Gaussian's pixel range touches 8x8
 // quadrant q of the 16x16 tile.
 #include "gs_internal.hpp"
+
+#include <algorithm>
 
 namespace gs {
 
 constexpr int kBinThreads = 256;
 constexpr int kCountGroup = 32;        // chunks per XCD run (multiples of the 16 counts in a 64-byte line)
-constexpr int kEmitGroupChunks = 16;   // chunks (times the row groups) per XCD run
+constexpr int kEmitGroupChunks = 4;    // chunks (times the row groups) per XCD run
 constexpr int kSegBits = kChunkBits;
 constexpr int kSegSize = 1 << kSegBits;          // positions per chunk
 
 static_assert(kSegSize == kBinPositions, "one binning block per chunk");
+static_assert(kBinPositions <= 65536, "queued positions are 16-bit chunk offsets");
 
 __device__ __forceinline__ void unpack_range(float f, int &lo, int &hi) {
     const uint32_t u = __float_as_uint(f);
@@ -46,15 +52,14 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t group) {
     return ((slot / group) * 8 + xcd) * group + slot % group;
 }
 
+// Quadrants of tile (tx, ty) met by the pixel rectangle [xl, xh] x [yl, yh],
+// which meets the tile: it meets the left (top) half iff it starts before
+// the middle, and the right (bottom) half iff it ends after it.
 __device__ __forceinline__ uint32_t quad_mask(int tx, int ty, int xl, int xh, int yl, int yh) {
-    uint32_t m = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int x0 = tx * kTile + (q & 1) * kQuad, y0 = ty * kTile + (q >> 1) * kQuad;
-        const bool hit = xl <= x0 + kQuad - 1 && xh >= x0 && yl <= y0 + kQuad - 1 && yh >= y0;
-        m |= hit ? (1u << q) : 0u;
-    }
-    return m;
+    const int mx = tx * kTile + kQuad, my = ty * kTile + kQuad;
+    const uint32_t l = xl < mx ? 1u : 0u, r = xh >= mx ? 2u : 0u;
+    const uint32_t top = yl < my ? (l | r) : 0u, bottom = yh >= my ? (l | r) << 2 : 0u;
+    return top | bottom;
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__restrict__ views, int n_views,
@@ -129,23 +134,34 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_prefix(const ViewDev *__r
     tile_tot[V.tile_base + t] = run;
 }
 
-// Ordered emission.  One wave per (group of kEmitRows tile rows, chunk,
-// view).  The wave first compacts, in order, the chunk's positions whose
-// rectangle meets its rows (an LDS queue), then takes them 64 at a time and
-// expands them into (position, tile) items in position order: a wave prefix
-// sum of the per-position item counts numbers the items, and each 64-item
-// batch finds every item's owner with one LDS write of run heads and a
-// max-scan.  A tile's slot comes from an LDS atomic add on its cursor.  Items
-// of one batch that hit distinct tiles are independent; when two of them hit
-// the same tile (an LDS claim byte per tile detects it) the batch takes its
-// owners one at a time in order.  A wave's LDS operations execute in issue
-// order, so later positions always receive later slots and every (tile,
-// chunk) segment is filled in increasing p.  Splitting a chunk by rows keeps
-// the wave's cursors small (high occupancy) and the list lines being written
-// at any moment few, so partial lines merge in the caches before they reach
-// HBM.
+// Ordered emission.  One wave per (group of kEmitRows tile rows and at most
+// kEmitCols tile columns, chunk, view).  For each batch of kEmitBatch
+// positions of its chunk, the wave first compacts, in order, the positions
+// whose rectangle meets its rows (an LDS queue), then takes them 64 at a
+// time and expands them into (position,
+// tile) items in position order: a wave prefix sum of the per-position item
+// counts numbers the items, and each 64-item batch finds every item's owner
+// with one LDS write of run heads and a max-scan.  A tile's slot comes from
+// an LDS atomic add on its cursor.  Items of one batch that hit the same tile
+// must take their slots in position (= lane) order: a per-tile LDS lane mask
+// gives each item the lanes that share its tile, the lowest of them takes the
+// whole run from the cursor and each item adds its rank.  A
+// wave's LDS operations execute in issue order, so later positions always
+// receive later slots and every (tile, chunk) segment is filled in
+// increasing p.
+//
+// Entries are not stored one by one: each tile keeps the 32-byte block of
+// its list that it is filling in LDS (slot = absolute entry index mod 8),
+// and a block goes out as one 8-lane store once its last slot is filled.
+// Only the first and last block of a segment (shared with the neighbouring
+// chunks' segments) are written partially.  Scattered 4-byte stores leave
+// the L2 as several partial-line writes per line (about 24 GB of writes for
+// 4.3 GB of entries at 1M Gaussians x 100 views, against 6.6 GB this way),
+// and 32-byte blocks keep the wave's LDS small enough for 28 waves per CU.
 constexpr int kEmitWave = 64;
-constexpr int kEmitRows = 4;
+constexpr int kEmitRows = 1;
+constexpr int kEmitCols = 128;     // tile columns per wave (2048 pixels)
+constexpr int kLine = 8;           // list entries per staged block (a power of two)
 
 __device__ __forceinline__ uint64_t lanemask_lt64_bin() {
     const unsigned lane = threadIdx.x & 63;
@@ -171,13 +187,14 @@ __device__ __forceinline__ int wave_scan_add(int v) {
     return v;
 }
 
-__device__ __forceinline__ int wave_scan_max(int v) {  // identity -1
-    v = max(v, dpp_src<0x111, 0xF>(-1, v));
-    v = max(v, dpp_src<0x112, 0xF>(-1, v));
-    v = max(v, dpp_src<0x114, 0xF>(-1, v));
-    v = max(v, dpp_src<0x118, 0xF>(-1, v));
-    v = max(v, dpp_src<0x142, 0xA>(-1, v));
-    v = max(v, dpp_src<0x143, 0xC>(-1, v));
+__device__ __forceinline__ int wave_scan_max(int v) {
+    constexpr int lo = -2147483647 - 1;   // identity of max
+    v = max(v, dpp_src<0x111, 0xF>(lo, v));
+    v = max(v, dpp_src<0x112, 0xF>(lo, v));
+    v = max(v, dpp_src<0x114, 0xF>(lo, v));
+    v = max(v, dpp_src<0x118, 0xF>(lo, v));
+    v = max(v, dpp_src<0x142, 0xA>(lo, v));
+    v = max(v, dpp_src<0x143, 0xC>(lo, v));
     return v;
 }
 
@@ -186,9 +203,62 @@ __device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
     return !kMasked || ((act[t >> 5] >> (t & 31)) & 1u);
 }
 
+// LDS layout of one emission wave (32-bit words unless noted).
+struct EmitLds {
+    uint64_t *lanes;    // [tiles] lanes of the current item batch on the tile
+    uint32_t *line;     // [tiles][kLine] the line each tile is filling
+    uint32_t *cur;      // [tiles] next entry, relative to the view's first entry
+    uint32_t *seg0;     // [tiles] first entry of the tile's segment in this chunk
+    int32_t *head;      // [64] lane owning the item that starts a run
+    uint32_t *rx, *ry, *rg;   // [64] the round's pixel ranges and indices
+    uint32_t *ft, *fc;  // [64] lines to store: tile, and the entry in its last slot
+    uint16_t *queue;    // [kEmitBatch] chunk-local positions meeting the rows
+    uint32_t *act;      // [tiles / 32] (masked form only)
+};
+
+__host__ __device__ constexpr size_t emit_lds_bytes(int tiles, bool masked) {
+    return sizeof(uint32_t) * ((size_t)tiles * (kLine + 4) + 6 * kEmitWave) + sizeof(uint16_t) * kEmitBatch +
+           (masked ? sizeof(uint32_t) * (((size_t)tiles + 31) / 32) : 0);
+}
+
+__device__ __forceinline__ EmitLds emit_lds(uint32_t *base, int tiles) {
+    EmitLds L;
+    L.lanes = (uint64_t *)base;
+    L.line = base + 2 * (size_t)tiles;
+    L.cur = L.line + (size_t)tiles * kLine;
+    L.seg0 = L.cur + tiles;
+    L.head = (int32_t *)(L.seg0 + tiles);
+    L.rx = (uint32_t *)L.head + kEmitWave;
+    L.ry = L.rx + kEmitWave;
+    L.rg = L.ry + kEmitWave;
+    L.ft = L.rg + kEmitWave;
+    L.fc = L.ft + kEmitWave;
+    L.queue = (uint16_t *)(L.fc + kEmitWave);
+    L.act = (uint32_t *)(L.queue + kEmitBatch);
+    return L;
+}
+
+// Stores the staged blocks ("lines") listed in L.ft / L.fc (n of them), 64 / kLine per step
+// with kLine lanes each; entries before the tile's segment (another chunk's) and at or
+// past `room` are left alone.
+__device__ __forceinline__ void store_lines(const EmitLds &L, int n, uint32_t align, uint32_t *__restrict__ vl,
+                                            uint64_t room) {
+    const int lane = threadIdx.x;
+    for (int f0 = 0; f0 < n; f0 += kEmitWave / kLine) {
+        const int f = f0 + lane / kLine, k = lane % kLine;
+        if (f < n) {
+            const int t = (int)L.ft[f];
+            const uint32_t last = L.fc[f];                           // entry in the line's last slot
+            const int64_t e = (int64_t)last - (int64_t)((align + last) & (kLine - 1u)) + k;
+            if (e >= (int64_t)L.seg0[t] && (uint64_t)e < room && e <= (int64_t)last)
+                vl[e] = L.line[t * kLine + k];
+        }
+    }
+}
+
 template <bool kMasked>
 __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restrict__ views, int n_views, int64_t N,
-                                                        int nchunks, int row_groups,
+                                                        int nchunks, int row_groups, int col_groups,
                                                         const uint32_t *__restrict__ nvis,
                                                         const uint32_t *__restrict__ xr_in,
                                                         const uint32_t *__restrict__ yr_in,
@@ -199,137 +269,210 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                                                         const uint8_t *__restrict__ active, uint64_t cap,
                                                         int group_tiles) {
     extern __shared__ uint32_t lds[];
-    uint32_t *cur = lds;                                  // [group tiles] next slot, relative to the view's first entry
-    int32_t *head = (int32_t *)(cur + group_tiles);        // [64] lane owning the item that starts a run
-    uint32_t *rx = (uint32_t *)head + kEmitWave;           // [64] the round's pixel ranges and indices
-    uint32_t *ry = rx + kEmitWave;
-    uint32_t *rg = ry + kEmitWave;
-    uint16_t *queue = (uint16_t *)(rg + kEmitWave);       // [2048] chunk-local positions meeting the rows
-    uint8_t *claim = (uint8_t *)(queue + kBinPositions);  // [group tiles] lane that last claimed the tile
-    uint32_t *act = (uint32_t *)(claim + ((group_tiles + 3) & ~3));  // [group tiles / 32] (masked form only)
-    // logical block: row group + row_groups * (chunk + nchunks * view)
-    const int64_t lb = xcd_block(blockIdx.x, (int64_t)kEmitGroupChunks * row_groups);
-    const int64_t per_view = (int64_t)row_groups * nchunks;
+    const EmitLds L = emit_lds(lds, group_tiles);
+    // logical block: group + groups * (chunk + nchunks * view), with group =
+    // row group + row_groups * column group
+    const int groups = row_groups * col_groups;
+    const int64_t lb = xcd_block(blockIdx.x, (int64_t)kEmitGroupChunks * groups);
+    const int64_t per_view = (int64_t)groups * nchunks;
     const int v = (int)(lb / per_view);
     if (v >= n_views) return;
-    const int grp = (int)(lb % row_groups);
-    const int chunk = (int)((lb - (int64_t)v * per_view) / row_groups);
+    const int grp = (int)(lb % groups);
+    const int chunk = (int)((lb - (int64_t)v * per_view) / groups);
     const int lane = threadIdx.x;
     const ViewDev &V = views[v];
     const int64_t nv = nvis[v];
     const int64_t lo = (int64_t)chunk * kBinPositions;
-    const int r0 = grp * kEmitRows;
-    if (lo >= nv || r0 >= V.tiles_y) return;
+    const int r0 = (grp % row_groups) * kEmitRows, c0 = (grp / row_groups) * kEmitCols;
+    if (lo >= nv || r0 >= V.tiles_y || c0 >= V.tiles_x) return;
     const int r1 = min(r0 + kEmitRows, V.tiles_y);    // rows [r0, r1)
+    const int c1 = min(c0 + kEmitCols, V.tiles_x);    // columns [c0, c1)
     const int hi = (int)(min(lo + (int64_t)kBinPositions, nv) - lo);
-    const int tiles_x = V.tiles_x;
-    const int ntiles = (r1 - r0) * tiles_x;           // this wave's tiles: t = tile_base + r0 * tiles_x + local
-    const int64_t t0 = (int64_t)V.tile_base + (int64_t)r0 * tiles_x;
+    const int tiles_x = V.tiles_x, ncols = c1 - c0;
+    const int ntiles = (r1 - r0) * ncols;             // local tile (ty - r0) * ncols + (tx - c0)
     const uint64_t vlist = tile_off[V.tile_base];
+    const uint32_t align = (uint32_t)(vlist & (kLine - 1u));   // slot of the view's first entry in its line
     // segment start of each of the wave's tiles for this chunk, relative to
     // the view's first entry: the tile's list start plus the tile's prefix
-    const uint32_t *pre = bin_count + (int64_t)V.tile_base * nchunks + (int64_t)chunk * (V.tiles_x * V.tiles_y) +
-                          (int64_t)r0 * tiles_x;
-    for (int t = lane; t < ntiles; t += kEmitWave) cur[t] = (uint32_t)(tile_off[t0 + t] - vlist) + pre[t];
+    const uint32_t *pre = bin_count + (int64_t)V.tile_base * nchunks + (int64_t)chunk * (V.tiles_x * V.tiles_y);
+    for (int t = lane; t < ntiles; t += kEmitWave) {
+        const int vt = (r0 + t / ncols) * tiles_x + c0 + t % ncols;   // tile within the view
+        const uint32_t s0 = (uint32_t)(tile_off[V.tile_base + vt] - vlist) + pre[vt];
+        L.cur[t] = s0;
+        L.seg0[t] = s0;
+    }
     if (kMasked) {
         for (int w = lane; w < (ntiles + 31) / 32; w += kEmitWave) {
             uint32_t bits = 0;
             for (int b = 0; b < 32; ++b) {
                 const int t = 32 * w + b;
-                bits |= (t < ntiles && active[t0 + t]) ? (1u << b) : 0u;
+                const int vt = (r0 + t / ncols) * tiles_x + c0 + t % ncols;
+                bits |= (t < ntiles && active[V.tile_base + vt]) ? (1u << b) : 0u;
             }
-            act[w] = bits;
+            L.act[w] = bits;
         }
     }
+    __syncthreads();
     // entries at or past `room` would fall outside the list buffer
     const uint64_t room = cap > vlist ? cap - vlist : 0ull;
     uint32_t *__restrict__ vl = lists + vlist;
     const int64_t o = (int64_t)v * N + lo;
-    // 1. positions whose rows meet [r0, r1), in order
-    int nq = 0;
-    for (int base = 0; base < hi; base += kEmitWave) {
-        const int p = base + lane;
-        bool meets = false;
-        if (p < hi) {
+    for (int b0 = 0; b0 < hi; b0 += kEmitBatch) {
+        const int b1 = min(b0 + kEmitBatch, hi);
+        // 1. positions of the batch whose rows meet [r0, r1), in order (all
+        // of the batch's row ranges are loaded first, so their latencies overlap)
+        constexpr int kGroups = kEmitBatch / kEmitWave;
+        uint32_t yv[kGroups];
+#pragma unroll
+        for (int q = 0; q < kGroups; ++q) {
+            const int p = b0 + q * kEmitWave + lane;
+            yv[q] = p < b1 ? yr_in[o + p] : 0u;
+        }
+        int nq = 0;
+#pragma unroll
+        for (int q = 0; q < kGroups; ++q) {
+            const int p = b0 + q * kEmitWave + lane;
             int yl, yh;
-            unpack_range(__uint_as_float(yr_in[o + p]), yl, yh);
-            meets = (yl >> 4) < r1 && (yh >> 4) >= r0;
+            unpack_range(__uint_as_float(yv[q]), yl, yh);
+            const bool meets = (p < b1) & ((yl >> 4) < r1) & ((yh >> 4) >= r0);
+            const uint64_t bal = __ballot(meets);
+            if (meets) L.queue[nq + __popcll(bal & lanemask_lt64_bin())] = (uint16_t)p;
+            nq += __popcll(bal);
         }
-        const uint64_t bal = __ballot(meets);
-        if (meets) queue[nq + __popcll(bal & lanemask_lt64_bin())] = (uint16_t)p;
-        nq += __popcll(bal);
-    }
-    __syncthreads();
-    // 2. expansion of the queued positions against this wave's tiles
-    for (int base = 0; base < nq; base += kEmitWave) {
-        const int qi = base + lane;
-        uint32_t ux = 0, uy = 0, ug = 0;
-        int k = 0;
-        if (qi < nq) {
-            const int p = queue[qi];
-            ux = xr_in[o + p];
-            uy = yr_in[o + p];
-            ug = sorted_g[o + p];
-            int xl, xh, yl, yh;
-            unpack_range(__uint_as_float(ux), xl, xh);
-            unpack_range(__uint_as_float(uy), yl, yh);
-            k = ((xh >> 4) - (xl >> 4) + 1) * (min(yh >> 4, r1 - 1) - max(yl >> 4, r0) + 1);
-        }
-        const int incl = wave_scan_add(k);
-        const int K = __builtin_amdgcn_readlane(incl, kEmitWave - 1);
-        const int excl = incl - k;   // first item of this lane's position
-        rx[lane] = ux;
-        ry[lane] = uy;
-        rg[lane] = ug;
         __syncthreads();
-        for (int i0 = 0; i0 < K; i0 += kEmitWave) {
-            const int i = i0 + lane;
-            const bool item = i < K;
-            // owner of item i: the last position lane whose first item is <= i.
-            // Item i0's owner is the highest lane with excl <= i0; a lane whose
-            // run starts inside the batch marks its first item, and a max-scan
-            // over the marks carries each owner forward.
-            const uint64_t started = __ballot(excl <= i0);
-            const int carry = 63 - __builtin_clzll(started);
-            head[lane] = -1;
-            if (k > 0 && excl > i0 && excl < i0 + kEmitWave) head[excl - i0] = lane;
-            __syncthreads();
-            const int L = max(carry, wave_scan_max(head[lane]));
-            const int j = i - __shfl(excl, L);
-            int xl, xh, yl, yh;
-            unpack_range(__uint_as_float(rx[L]), xl, xh);
-            unpack_range(__uint_as_float(ry[L]), yl, yh);
-            const uint32_t g = rg[L];
-            const int tx0 = xl >> 4, ty0 = max(yl >> 4, r0);
-            const int nx = (xh >> 4) - tx0 + 1;
-            // j / nx as floor((j + 1/2) r) with r within one ulp of 1/nx:
-            // exact for nx * ny <= 8160 (checked exhaustively on the host)
-            const int dy = (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
-            const int tx = tx0 + (j - dy * nx), ty = ty0 + dy;
-            const int tc = (ty - r0) * tiles_x + tx;
-            const bool in = item && (unsigned)tc < (unsigned)ntiles;
-            const int t = in ? tc : 0;
-            const bool on = in && tile_on<kMasked>(act, t);
-            if (on) claim[t] = (uint8_t)lane;
-            __syncthreads();
-            const bool clash = on && claim[t] != (uint8_t)lane;
-            uint32_t c = 0;
-            if (__ballot(clash) == 0ull) {
-                if (on) c = atomicAdd(&cur[t], 1u);
-            } else {
-                // owners in increasing order; one owner's tiles are distinct
-                uint64_t rem = __ballot(on);
-                while (rem) {
-                    const int first = __ffsll((long long)rem) - 1;
-                    const int owner = __shfl(L, first);
-                    const bool mine = on && L == owner;
-                    if (mine) c = atomicAdd(&cur[t], 1u);
-                    rem &= ~__ballot(mine);
-                }
-            }
-            if (on && (uint64_t)c < room) vl[c] = g | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
-            __syncthreads();
+        // 2. expansion of the queued positions against this wave's tiles; the
+        // next round's ranges and indices are loaded while this one expands
+        uint32_t nx_ = 0, ny_ = 0, ng_ = 0;
+        if (lane < nq) {
+            const int p = L.queue[lane];
+            nx_ = xr_in[o + p];
+            ny_ = yr_in[o + p];
+            ng_ = sorted_g[o + p];
         }
+        for (int base = 0; base < nq; base += kEmitWave) {
+            const int qi = base + lane;
+            const uint32_t ux = nx_, uy = ny_, ug = ng_;
+            if (qi + kEmitWave < nq) {
+                const int p = L.queue[qi + kEmitWave];
+                nx_ = xr_in[o + p];
+                ny_ = yr_in[o + p];
+                ng_ = sorted_g[o + p];
+            }
+            int k = 0;
+            if (qi < nq) {
+                int xl, xh, yl, yh;
+                unpack_range(__uint_as_float(ux), xl, xh);
+                unpack_range(__uint_as_float(uy), yl, yh);
+                // the tiles of its rectangle inside this wave's rows and columns
+                const int kx = min(xh >> 4, c1 - 1) - max(xl >> 4, c0) + 1;
+                k = kx > 0 ? kx * (min(yh >> 4, r1 - 1) - max(yl >> 4, r0) + 1) : 0;
+            }
+            const int incl = wave_scan_add(k);
+            const int K = __builtin_amdgcn_readlane(incl, kEmitWave - 1);
+            const int excl = incl - k;   // first item of this lane's position
+            L.rx[lane] = ux;
+            L.ry[lane] = uy;
+            L.rg[lane] = ug;
+            __syncthreads();
+            for (int i0 = 0; i0 < K; i0 += kEmitWave) {
+                const int i = i0 + lane;
+                const bool item = i < K;
+                // owner of item i: the last position lane whose first item is <= i.
+                // Item i0's owner is the highest lane with excl <= i0; a lane whose
+                // run starts inside the batch marks its first item, and a max-scan
+                // over the marks carries each owner forward.
+                const uint64_t started = __ballot(excl <= i0);
+                const int carry = 63 - __builtin_clzll(started);
+                L.head[lane] = -1;
+                if (k > 0 && excl > i0 && excl < i0 + kEmitWave) L.head[excl - i0] = lane;
+                __syncthreads();
+                const int own = max(carry, wave_scan_max(L.head[lane]));
+                const int j = i - __shfl(excl, own);
+                int xl, xh, yl, yh;
+                unpack_range(__uint_as_float(L.rx[own]), xl, xh);
+                unpack_range(__uint_as_float(L.ry[own]), yl, yh);
+                const uint32_t g = L.rg[own];
+                const int tx0 = max(xl >> 4, c0), ty0 = max(yl >> 4, r0);
+                const int nx = min(xh >> 4, c1 - 1) - tx0 + 1;
+                // j / nx as floor((j + 1/2) r) with r within one ulp of 1/nx:
+                // exact for nx * ny <= 8160 (checked exhaustively on the host)
+                const int dy = kEmitRows == 1 ? 0 : (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
+                const int tx = tx0 + (j - dy * nx), ty = kEmitRows == 1 ? r0 : ty0 + dy;
+                const int tc = kEmitRows == 1 ? tx - c0 : (ty - r0) * ncols + (tx - c0);
+                const bool in = item && (unsigned)tc < (unsigned)ntiles;
+                const int t = in ? tc : 0;
+                const bool on = in && tile_on<kMasked>(L.act, t);
+                const uint32_t val = g | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
+                // Lanes on the same tile: each lane ORs its bit into its tile's
+                // 64-bit LDS mask (cleared just before), then reads it back.
+                // A lane's rank among them (lanes are in position order) is its
+                // offset in the tile's run of entries; the lowest lane takes the
+                // run from the tile's cursor.
+                if (on) L.lanes[t] = 0ull;
+                __syncthreads();
+                if (on) atomicOr((unsigned long long *)&L.lanes[t], 1ull << lane);
+                __syncthreads();
+                const uint64_t same = on ? L.lanes[t] : 0ull;
+                const int rank = __popcll(same & lanemask_lt64_bin());
+                uint32_t base = 0;
+                if (on && rank == 0) base = atomicAdd(&L.cur[t], (uint32_t)__popcll(same));
+                const int lead = on ? __ffsll((long long)same) - 1 : lane;
+                const uint32_t c = (uint32_t)__shfl((int)base, lead) + (uint32_t)rank;
+                // The entries go into their tiles' lines one line at a time: in
+                // step s every tile writes only within the s-th line its run
+                // touches, and the lines whose last slot was filled are stored
+                // before the next step reuses their slots.
+                const uint32_t slot = (align + c) & (kLine - 1u);
+                const int step = on ? (int)(((align + c - (uint32_t)rank) & (kLine - 1u)) + (uint32_t)rank) / kLine : -1;
+                for (int s = 0; __ballot(step >= s) != 0ull; ++s) {
+                    const bool now = step == s;
+                    if (now) L.line[t * kLine + slot] = val;
+                    const bool full = now && slot == kLine - 1u;
+                    const uint64_t need = __ballot(full);
+                    if (need) {
+                        if (full) {
+                            const int r = __popcll(need & lanemask_lt64_bin());
+                            L.ft[r] = (uint32_t)t;
+                            L.fc[r] = c;
+                        }
+                        __syncthreads();
+                        store_lines(L, __popcll(need), align, vl, room);
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();   // the queue is refilled by the next batch
+    }
+    // 3. the last, partly filled line of every tile whose segment ends inside one
+    for (int t4 = 0; t4 < ntiles; t4 += kEmitWave) {
+        const int t = t4 + lane;
+        bool part = false;
+        uint32_t c = 0;
+        if (t < ntiles) {
+            c = L.cur[t];
+            part = c > L.seg0[t] && ((align + c) & (kLine - 1u)) != 0u;
+        }
+        const uint64_t need = __ballot(part);
+        if (part) {
+            const int r = __popcll(need & lanemask_lt64_bin());
+            L.ft[r] = (uint32_t)t;
+            L.fc[r] = c - 1u;       // the last entry; slots after it are not stored
+        }
+        __syncthreads();
+        const int n = __popcll(need);
+        for (int f0 = 0; f0 < n; f0 += kEmitWave / kLine) {
+            const int f = f0 + lane / kLine, k = lane % kLine;
+            if (f < n) {
+                const int tt = (int)L.ft[f];
+                const uint32_t last = L.fc[f];
+                const int64_t e = (int64_t)last - (int64_t)((align + last) & (kLine - 1u)) + k;
+                if (e >= (int64_t)L.seg0[tt] && (uint64_t)e < room && e <= (int64_t)last)
+                    vl[e] = L.line[tt * kLine + k];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -351,20 +494,20 @@ void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, c
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
                      int max_tiles_y, uint64_t cap, hipStream_t st) {
     const int row_groups = (max_tiles_y + kEmitRows - 1) / kEmitRows;
-    const int64_t run = 8 * (int64_t)kEmitGroupChunks * row_groups;
-    const int64_t blocks = ((int64_t)row_groups * nchunks * Vc + run - 1) / run * run;
-    const int group_tiles = kEmitRows * max_tiles_x;
-    // cursors, run heads, three round arrays, queue, claim bytes, tile bitmap
-    const size_t lds = sizeof(uint32_t) * ((size_t)group_tiles + kEmitWave + 3 * kEmitWave) +
-                       sizeof(uint16_t) * kBinPositions + (((size_t)group_tiles + 3) & ~(size_t)3) +
-                       (b.tile_active ? sizeof(uint32_t) * ((size_t)group_tiles + 31) / 32 : 0);
+    const int col_groups = (max_tiles_x + kEmitCols - 1) / kEmitCols;
+    const int64_t run = 8 * (int64_t)kEmitGroupChunks * row_groups * col_groups;
+    const int64_t blocks = ((int64_t)row_groups * col_groups * nchunks * Vc + run - 1) / run * run;
+    const int group_tiles = kEmitRows * std::min(max_tiles_x, kEmitCols);
+    const size_t lds = emit_lds_bytes(group_tiles, b.tile_active != nullptr);
     const dim3 grid((unsigned)blocks);
     if (b.tile_active)
         hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
+                           col_groups,
                            b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
                            group_tiles);
     else
         hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
+                           col_groups,
                            b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
                            group_tiles);
 }

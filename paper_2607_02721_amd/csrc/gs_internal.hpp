@@ -9,10 +9,11 @@ namespace gs {
 
 constexpr int kTile = 16;          // binning tile edge (pixels)
 constexpr int kQuad = 8;           // compositing quadrant edge: one wave per 8x8 quadrant
-constexpr int kChunkBits = 11;     // depth ranks are binned in chunks of 2^11 (one binning block)
+constexpr int kChunkBits = 14;     // depth ranks are binned in chunks of 2^14 (one list segment per tile)
 constexpr int kMaxTilesPerView = 8160;  // two u32 LDS arrays of this size fit 64 KiB
 constexpr int kSortTile = 4096;    // radix sort: keys per block (4 waves x 16 rounds x 64 lanes)
-constexpr int kBinPositions = 2048; // binning: depth-sorted positions per block
+constexpr int kBinPositions = 1 << kChunkBits;  // binning: depth-sorted positions per chunk (count block)
+constexpr int kEmitBatch = 512;    // emission: positions a wave queues at a time
 constexpr uint32_t kInvisibleKey = 0xFFFFFFFFu;
 constexpr uint32_t kIndexMask = 0x0FFFFFFFu; // list entry = gaussian | quadrant mask << 28
 
