@@ -127,6 +127,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)c.vc * N);
     add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
     add(2 * sizeof(uint32_t) * (size_t)c.vc);
+    add(2 * sizeof(uint32_t) * (size_t)c.vc * proj_waves(N));
     add(sizeof(uint32_t) * nbins);
     add(sizeof(uint32_t) * c.total_tiles);
     add(sizeof(uint64_t) * (c.total_tiles + 1));
@@ -313,6 +314,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.hist = cv.take<uint32_t>((size_t)c.vc * 256 * nb);
     b.nvis = cv.take<uint32_t>(2 * (size_t)c.vc);
     b.cmax = b.nvis + c.vc;
+    b.proj_part = cv.take<uint32_t>(2 * (size_t)c.vc * proj_waves(N));
     b.bin_count = cv.take<uint32_t>(nbins);
     b.tile_tot = cv.take<uint32_t>(c.total_tiles);
     b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
@@ -946,6 +948,7 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)ps.c.vc * N);
     add(sizeof(uint32_t) * (size_t)ps.c.vc * 256 * nb);
     add(2 * sizeof(uint32_t) * (size_t)ps.c.vc);
+    add(2 * sizeof(uint32_t) * (size_t)ps.c.vc * proj_waves(N));
     add(sizeof(uint32_t) * ps.nbins);
     add(sizeof(uint32_t) * ps.c.total_tiles);
     add(sizeof(uint64_t) * (ps.c.total_tiles + 1));
@@ -970,6 +973,7 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.hist = cv.take<uint32_t>((size_t)ps.c.vc * 256 * nb);
     b.nvis = cv.take<uint32_t>(2 * (size_t)ps.c.vc);
     b.cmax = b.nvis + ps.c.vc;
+    b.proj_part = cv.take<uint32_t>(2 * (size_t)ps.c.vc * proj_waves(N));
     b.bin_count = cv.take<uint32_t>(ps.nbins);
     b.tile_tot = cv.take<uint32_t>(ps.c.total_tiles);
     b.tile_off = cv.take<uint64_t>(ps.c.total_tiles + 1);

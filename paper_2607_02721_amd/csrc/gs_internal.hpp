@@ -57,6 +57,7 @@ struct ChunkBufs {
     uint32_t *hist;      // radix histograms [Vc][256][nb]
     uint32_t *nvis;      // [Vc] visible Gaussians per view
     uint32_t *cmax;      // [Vc] largest query colour per view (float bits)
+    uint32_t *proj_part; // [2][Vc][projection waves] per-wave visible counts and colour maxima
     // per (tile, chunk) entry counts, chunk-major inside each view (view v at
     // tile_base(v) * nchunks, then [chunk][tile of v]); turned in place into
     // each tile's exclusive prefix over chunks
@@ -80,6 +81,9 @@ enum : int {
 // the per-wave additions do not all meet on one address; the host sums them.
 constexpr int kCntSpread = 64;
 constexpr int CNT_WORDS = CNT_SLOTS + 4 * kCntSpread;
+
+// Waves of the projection launch (256-thread blocks, one Gaussian per thread).
+inline int64_t proj_waves(int64_t n) { return (n + 255) / 256 * 4; }
 
 // ---- launchers (each enqueues on `st`) -------------------------------------
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,

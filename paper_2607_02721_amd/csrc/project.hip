@@ -77,9 +77,8 @@ template <int kDeg, int kFmt>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
                                                  ProjParams pp, float4 *__restrict__ R0,
                                                  float4 *__restrict__ R1, float4 *__restrict__ R2,
-                                                 float4 *__restrict__ R3, uint32_t *__restrict__ keys, uint32_t *__restrict__ nvis,
-                                                 uint32_t *__restrict__ cmax_bits,
-                                                 uint64_t *__restrict__ counters) {
+                                                 float4 *__restrict__ R3, uint32_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ part, uint64_t *__restrict__ counters) {
     const int64_t n = sc.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in_range = g < n;
@@ -208,14 +207,44 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
             if (R3) R3[o] = r3;
             keys[o] = vis ? __float_as_uint((float)pz) : kInvisibleKey;
         }
-        // per-view visible count and colour maximum (wave-reduced first)
+        // per-view visible count and colour maximum of this wave, folded
+        // over the waves by k_proj_reduce (one shared counter per view would
+        // take every wave's atomic in turn)
         const uint64_t bal = __ballot(vis);
         float cm = vis ? cbar : 0.0f;
         for (int off = 32; off > 0; off >>= 1) cm = fmaxf(cm, __shfl_xor(cm, off));
         if ((threadIdx.x & 63) == 0) {
-            if (bal) atomicAdd(&nvis[v], (uint32_t)__popcll(bal));
-            if (cm > 0.0f) atomicMax(&cmax_bits[v], __float_as_uint(cm));
+            const int64_t nw = (int64_t)gridDim.x * 4, w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+            part[(int64_t)v * nw + w] = (uint32_t)__popcll(bal);
+            part[((int64_t)Vc + v) * nw + w] = __float_as_uint(cm);
         }
+    }
+}
+
+// nvis[v] = sum and cmax[v] = maximum of the per-wave values of view v (one
+// block per view; colour maxima are non-negative, so their float bits order
+// like the floats).
+__global__ __launch_bounds__(256) void k_proj_reduce(const uint32_t *__restrict__ part, int Vc, int64_t nw,
+                                                     uint32_t *__restrict__ nvis, uint32_t *__restrict__ cmax_bits) {
+    __shared__ uint32_t sh[2][4];
+    const int v = blockIdx.x;
+    uint32_t cnt = 0, cm = 0;
+    for (int64_t w = threadIdx.x; w < nw; w += 256) {
+        cnt += part[(int64_t)v * nw + w];
+        cm = max(cm, part[((int64_t)Vc + v) * nw + w]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off);
+        cm = max(cm, (uint32_t)__shfl_xor((int)cm, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = cnt;
+        sh[1][threadIdx.x >> 6] = cm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        nvis[v] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+        cmax_bits[v] = max(max(sh[1][0], sh[1][1]), max(sh[1][2], sh[1][3]));
     }
 }
 
@@ -224,7 +253,9 @@ static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const
                      hipStream_t st) {
     const int64_t blocks = (sc.n + 255) / 256;
     hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0,
-                       b.R1, b.R2, b.R3, b.key0, b.nvis, b.cmax, b.counters);
+                       b.R1, b.R2, b.R3, b.key0, b.proj_part, b.counters);
+    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (const uint32_t *)b.proj_part, Vc,
+                       blocks * 4, b.nvis, b.cmax);
 }
 
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
