@@ -497,8 +497,17 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                 if (kStats) n_eval += (uint32_t)min(16, n - jb);
                 const int j = jb + (lane >> 2);
                 if (kAgg == 0) {
-                    const float m = wave_transpose_max16(sh);
-                    if ((lane & 3) == 0 && j < n && m > sold[j]) atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
+                    // the reduction is needed only if some pixel beats the
+                    // staged sensitivity of its entry (padded entries have
+                    // share 0, which beats no sensitivity)
+                    bool beat = false;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) beat |= sh[k] > sold[jb + k];
+                    if (__ballot(beat) != 0ull) {
+                        const float m = wave_transpose_max16(sh);
+                        if ((lane & 3) == 0 && j < n && m > sold[j])
+                            atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
+                    }
                 } else {
                     const float m = wave_transpose_sum16(sh);
                     if ((lane & 3) == 0 && j < n && m > 0.0f) {
