@@ -167,6 +167,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-agg", action="store_true", help="skip the aggregated-query variants")
     ap.add_argument("--no-modes", action="store_true", help="skip the nocolor, L2 and per-channel score variants")
+    ap.add_argument("--no-transfer", action="store_true", help="skip the transfer study on the judge rays")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate microbenchmarks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (reference dispatch for counter runs)")
@@ -355,6 +356,37 @@ def main():
             scan[name][str(mm)] = gs.coreset_error(ob["per_view"])
     log(f"E vs m: {json.dumps(scan)}")
 
+    # transfer study (untimed): for coresets of 1-20% of N drawn from the exact
+    # sensitivities, the validity violations (w rho >= 1, Definition 2), the
+    # largest log-transmittance gap gamma (Assumption 1) and the per-ray
+    # relative errors of the fixed relaxation and of the true reduced render,
+    # on the judge rays
+    transfer = None
+    if not args.no_transfer:
+        transfer = {}
+        full = gs.render_objective(dsc, views, None, gs.OBJ_FULL, ray_mask=sub, per_view=False, diag=False)
+        A = full["per_ray"]
+        on = A > 0
+        for frac in (0.01, 0.02, 0.05, 0.10, 0.20):
+            mm = int(round(frac * scene.n))
+            _, w_t, sup = gs.sample_coreset(s, mm, seed)
+            fx = gs.render_objective(dsc, views, w_t, gs.OBJ_FIXED, ray_mask=sub, diag=False)
+            tr = gs.render_objective(dsc, views, w_t, gs.OBJ_TRUE, ray_mask=sub)
+            e_fix = ((fx["per_ray"][on] - A[on]).abs() / A[on]).double()
+            e_tr = ((tr["per_ray"][on] - A[on]).abs() / A[on]).double()
+            pv = tr["per_view"].cpu().numpy()
+            transfer[f"{frac:.2f}"] = {
+                "m": mm, "support": int(sup.item()),
+                "invalid_pairs": tr["n_invalid_pairs"], "gamma_max": tr["gamma_max"],
+                "ray_err_fixed": {"median": float(e_fix.median()), "p99": float(e_fix.quantile(0.99)),
+                                  "max": float(e_fix.max())},
+                "ray_err_true": {"median": float(e_tr.median()), "p99": float(e_tr.quantile(0.99)),
+                                 "max": float(e_tr.max())},
+                "E_fixed": gs.coreset_error(fx["per_view"]),
+                "E_true": float(np.max(np.abs(pv[:, 2] - pv[:, 0]) / np.maximum(pv[:, 0], 1e-30))),
+            }
+        log(f"transfer: {json.dumps(transfer)}")
+
     batching = None
     if not args.no_batch:
         batching = batch_leg(gs, synth, torch, args)
@@ -410,6 +442,7 @@ def main():
                                  "attribute_bytes": d16.attribute_bytes()},
                      "learned": learned, "aggregated": aggregated, "score_variants": modes},
         "coreset_err_vs_m": scan,
+        "transfer": transfer,
         "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on 1% of the 8x8 pixel blocks, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],
                   "entries": cst["n_entries"], "projected": cst["n_projected"], "bins": cst["n_bins"]},

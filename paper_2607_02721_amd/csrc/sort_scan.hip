@@ -86,7 +86,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                  int nb, int shift, int vals_are_iota,
                                                                  const uint32_t *__restrict__ offs) {
     __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t wbase[4][256];
+    __shared__ uint32_t wbase[4][256];   // block-local start of each wave's run of each digit
+    __shared__ uint32_t dstart[256];     // block-local start of each digit
+    __shared__ uint32_t gdst[256];       // global start of the block's run of each digit
+    __shared__ uint32_t lkey[kSortTile], lval[kSortTile];
     const int seg = blockIdx.y, b = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
@@ -111,25 +114,54 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+    // digit counts of the block, their exclusive scan (block-local run
+    // starts) and each wave's start inside its digit's run
     {
         const int d = threadIdx.x;
-        uint32_t g = offs[((int64_t)seg * 256 + d) * nb + b];
-#pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
-            wbase[ww][d] = g;
-            g += wcnt[ww][d];
+        const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+        dstart[d] = c0 + c1 + c2 + c3;
+        gdst[d] = offs[((int64_t)seg * 256 + d) * nb + b];
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t x = d >= off ? dstart[d - off] : 0u;
+            __syncthreads();
+            dstart[d] += x;
+            __syncthreads();
         }
+        const uint32_t start = dstart[d] - (c0 + c1 + c2 + c3);
+        __syncthreads();
+        dstart[d] = start;
+        wbase[0][d] = start;
+        wbase[1][d] = start + c0;
+        wbase[2][d] = start + c0 + c1;
+        wbase[3][d] = start + c0 + c1 + c2;
     }
     __syncthreads();
+    // the block's keys in LDS in stable digit order, then written out in that
+    // order: consecutive threads store consecutive positions of each digit's
+    // run, so the stores of a wave cover a few runs instead of 64 scattered words
+    int nvalid = 0;
 #pragma unroll
     for (int k = 0; k < kSortRounds; ++k) {
         const int64_t i = wlo + k * 64 + lane;
         if (i < n_per_seg) {
             const uint32_t d = (key[k] >> shift) & 255u;
-            const uint32_t dst = wbase[w][d] + rank[k];
-            kout[base + dst] = key[k];
-            vout[base + dst] = val[k];
+            const uint32_t pos = wbase[w][d] + rank[k];
+            lkey[pos] = key[k];
+            lval[pos] = val[k];
         }
+    }
+    {
+        const int64_t lo = (int64_t)b * kSortTile;
+        nvalid = (int)min((int64_t)kSortTile, n_per_seg - lo);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nvalid; i += kSortThreads) {
+        const uint32_t kk = lkey[i];
+        const uint32_t d = (kk >> shift) & 255u;
+        const uint32_t dst = gdst[d] + ((uint32_t)i - dstart[d]);
+        kout[base + dst] = kk;
+        vout[base + dst] = lval[i];
     }
 }
 
