@@ -126,8 +126,8 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     if (S.nq > 1) add(sizeof(float4) * (size_t)c.vc * N);   // channel colours
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)c.vc * N);
     add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
-    add(2 * sizeof(uint32_t) * (size_t)c.vc);
-    add(2 * sizeof(uint32_t) * (size_t)c.vc * proj_waves(N));
+    add(4 * sizeof(uint32_t) * (size_t)c.vc);
+    add(4 * sizeof(uint32_t) * (size_t)c.vc * proj_blocks(N));
     add(sizeof(uint32_t) * nbins);
     add(sizeof(uint32_t) * c.total_tiles);
     add(sizeof(uint64_t) * (c.total_tiles + 1));
@@ -312,9 +312,10 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.val1 = cv.take<uint32_t>((size_t)c.vc * N);
     const int64_t nb = (N + kSortTile - 1) / kSortTile;
     b.hist = cv.take<uint32_t>((size_t)c.vc * 256 * nb);
-    b.nvis = cv.take<uint32_t>(2 * (size_t)c.vc);
+    b.nvis = cv.take<uint32_t>(4 * (size_t)c.vc);
     b.cmax = b.nvis + c.vc;
-    b.proj_part = cv.take<uint32_t>(2 * (size_t)c.vc * proj_waves(N));
+    b.kmin = b.nvis + 2 * c.vc;
+    b.proj_part = cv.take<uint32_t>(4 * (size_t)c.vc * proj_blocks(N));
     b.bin_count = cv.take<uint32_t>(nbins);
     b.tile_tot = cv.take<uint32_t>(c.total_tiles);
     b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
@@ -375,12 +376,24 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     launch_project(sd, r.views_dev, c.vc, pp, b, st);
     HIP_TRY(hipGetLastError());
     tm.mark(1, st);
+    // Three 8-bit passes suffice when every view's visible depth keys, less
+    // the view's smallest, stay below 2^24 - 1 (depths within about a factor
+    // of four: the float bits of a positive depth grow by 2^23 per octave).
+    std::vector<uint32_t> kr(2 * (size_t)c.vc);
+    HIP_TRY(hipMemcpyAsync(kr.data(), b.kmin, sizeof(uint32_t) * 2 * c.vc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    uint32_t span = 0;
+    for (int k = 0; k < c.vc; ++k)
+        if (kr[c.vc + k] >= kr[k]) span = std::max(span, kr[c.vc + k] - kr[k]);
+    const int passes = span < 0xFFFFFFu ? 3 : 4;
     uint32_t *skeys = nullptr;
-    HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, &skeys, &r.sorted_g, st));
+    HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, passes,
+                                passes == 3 ? b.kmin : nullptr, &skeys, &r.sorted_g, st));
     tm.mark(2, st);
     if (b.tile_active) launch_tile_active(r.views_dev, r.tile_view, c.total_tiles, p->ray_mask, b.tile_active, st);
-    // after 4 radix passes the sorted pairs are back in (key0, val0); key1/val1 are free
-    uint32_t *xr = b.key1, *yr = b.val1;
+    // the pair of sort buffers that does not hold the sorted output is free
+    const bool out_in_0 = r.sorted_g == b.val0;
+    uint32_t *xr = out_in_0 ? b.key1 : b.key0, *yr = out_in_0 ? b.val1 : b.val0;
     launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
     int max_tiles = 1, max_tx = 1, max_ty = 1;
     for (const ViewDev &V : hv) {
@@ -947,8 +960,8 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     add(3 * sizeof(float4) * (size_t)ps.c.vc * N);
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)ps.c.vc * N);
     add(sizeof(uint32_t) * (size_t)ps.c.vc * 256 * nb);
-    add(2 * sizeof(uint32_t) * (size_t)ps.c.vc);
-    add(2 * sizeof(uint32_t) * (size_t)ps.c.vc * proj_waves(N));
+    add(4 * sizeof(uint32_t) * (size_t)ps.c.vc);
+    add(4 * sizeof(uint32_t) * (size_t)ps.c.vc * proj_blocks(N));
     add(sizeof(uint32_t) * ps.nbins);
     add(sizeof(uint32_t) * ps.c.total_tiles);
     add(sizeof(uint64_t) * (ps.c.total_tiles + 1));
@@ -971,9 +984,10 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.key1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
     b.val1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
     b.hist = cv.take<uint32_t>((size_t)ps.c.vc * 256 * nb);
-    b.nvis = cv.take<uint32_t>(2 * (size_t)ps.c.vc);
+    b.nvis = cv.take<uint32_t>(4 * (size_t)ps.c.vc);
     b.cmax = b.nvis + ps.c.vc;
-    b.proj_part = cv.take<uint32_t>(2 * (size_t)ps.c.vc * proj_waves(N));
+    b.kmin = b.nvis + 2 * ps.c.vc;
+    b.proj_part = cv.take<uint32_t>(4 * (size_t)ps.c.vc * proj_blocks(N));
     b.bin_count = cv.take<uint32_t>(ps.nbins);
     b.tile_tot = cv.take<uint32_t>(ps.c.total_tiles);
     b.tile_off = cv.take<uint64_t>(ps.c.total_tiles + 1);
@@ -996,7 +1010,8 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ProjParams pp{P->p.footprint_sigma, P->p.dilation, P->p.z_near, P->p.query_mode};
     launch_project(sd, ps.views_dev, ps.c.vc, pp, b, st);
     uint32_t *skeys = nullptr;
-    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, &skeys, &ps.sorted_g, st);
+    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, 4, nullptr, &skeys, &ps.sorted_g,
+                        st);
     ps.xr = b.key1;
     ps.yr = b.val1;
     launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);

@@ -57,7 +57,8 @@ struct ChunkBufs {
     uint32_t *hist;      // radix histograms [Vc][256][nb]
     uint32_t *nvis;      // [Vc] visible Gaussians per view
     uint32_t *cmax;      // [Vc] largest query colour per view (float bits)
-    uint32_t *proj_part; // [2][Vc][projection waves] per-wave visible counts and colour maxima
+    uint32_t *kmin;      // [Vc] smallest visible depth key per view; kmax = kmin + Vc the largest
+    uint32_t *proj_part; // [Vc][projection blocks][4] per-block visible count, colour maximum, key minimum, maximum
     // per (tile, chunk) entry counts, chunk-major inside each view (view v at
     // tile_base(v) * nchunks, then [chunk][tile of v]); turned in place into
     // each tile's exclusive prefix over chunks
@@ -82,15 +83,20 @@ enum : int {
 constexpr int kCntSpread = 64;
 constexpr int CNT_WORDS = CNT_SLOTS + 4 * kCntSpread;
 
-// Waves of the projection launch (256-thread blocks, one Gaussian per thread).
-inline int64_t proj_waves(int64_t n) { return (n + 255) / 256 * 4; }
+// Blocks of the projection launch (256 threads, one Gaussian per thread).
+inline int64_t proj_blocks(int64_t n) { return (n + 255) / 256; }
 
 // ---- launchers (each enqueues on `st`) -------------------------------------
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
                     const ChunkBufs &b, hipStream_t st);
+// `passes` 8-bit LSD passes (3 or 4).  With kbase non-null the first pass
+// subtracts kbase[seg] from every key but kInvisibleKey (the result must stay
+// below 2^(8 passes) - 1 for the visible keys, so that invisible keys still
+// sort last).
 hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1,
                                uint32_t *hist, int64_t n_per_seg, int n_segs, bool vals_are_iota,
-                               uint32_t **key_out, uint32_t **val_out, hipStream_t st);
+                               int passes, const uint32_t *kbase, uint32_t **key_out, uint32_t **val_out,
+                               hipStream_t st);
 void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
                             uint32_t *yr, hipStream_t st);
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,

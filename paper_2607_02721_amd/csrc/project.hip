@@ -38,6 +38,32 @@ __device__ __forceinline__ float load_attr(const void *base, int64_t idx, int f1
     return __half2float(__ushort_as_half(b));
 }
 
+// Wave-wide maximum / minimum: an inclusive DPP scan (shifts by 1, 2, 4, 8
+// inside rows of 16 lanes, then row_bcast:15 and row_bcast:31; lanes without
+// a source keep their value) leaves the result in lane 63.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t identity, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, kCtrl, kRowMask, 0xF, false);
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp_u32<0x111, 0xF>(0u, v));
+    v = max(v, dpp_u32<0x112, 0xF>(0u, v));
+    v = max(v, dpp_u32<0x114, 0xF>(0u, v));
+    v = max(v, dpp_u32<0x118, 0xF>(0u, v));
+    v = max(v, dpp_u32<0x142, 0xA>(0u, v));
+    v = max(v, dpp_u32<0x143, 0xC>(0u, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    v = min(v, dpp_u32<0x111, 0xF>(0xFFFFFFFFu, v));
+    v = min(v, dpp_u32<0x112, 0xF>(0xFFFFFFFFu, v));
+    v = min(v, dpp_u32<0x114, 0xF>(0xFFFFFFFFu, v));
+    v = min(v, dpp_u32<0x118, 0xF>(0xFFFFFFFFu, v));
+    v = min(v, dpp_u32<0x142, 0xA>(0xFFFFFFFFu, v));
+    v = min(v, dpp_u32<0x143, 0xC>(0xFFFFFFFFu, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Real spherical harmonics (orthonormal, degree <= 3) at unit direction d.
 __device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y) {
     const double k00 = 0.28209479177387814;       // 1/(2 sqrt(pi))
@@ -78,7 +104,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                                                  ProjParams pp, float4 *__restrict__ R0,
                                                  float4 *__restrict__ R1, float4 *__restrict__ R2,
                                                  float4 *__restrict__ R3, uint32_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ part, uint64_t *__restrict__ counters) {
+                                                 uint4 *__restrict__ part, uint64_t *__restrict__ counters) {
+    __shared__ uint4 red[2][4];
     const int64_t n = sc.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in_range = g < n;
@@ -210,41 +237,59 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
         // per-view visible count and colour maximum of this wave, folded
         // over the waves by k_proj_reduce (one shared counter per view would
         // take every wave's atomic in turn)
+        // (colours and depths are positive: their float bits order like them);
+        // the block's four waves meet in LDS (two buffers, one barrier per
+        // view) and thread 0 stores the block's values
         const uint64_t bal = __ballot(vis);
-        float cm = vis ? cbar : 0.0f;
-        for (int off = 32; off > 0; off >>= 1) cm = fmaxf(cm, __shfl_xor(cm, off));
-        if ((threadIdx.x & 63) == 0) {
-            const int64_t nw = (int64_t)gridDim.x * 4, w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-            part[(int64_t)v * nw + w] = (uint32_t)__popcll(bal);
-            part[((int64_t)Vc + v) * nw + w] = __float_as_uint(cm);
+        const uint32_t key = __float_as_uint((float)pz);
+        const uint32_t cm = wave_max_u32(vis ? __float_as_uint(cbar) : 0u);
+        const uint32_t klo = wave_min_u32(vis ? key : 0xFFFFFFFFu);
+        const uint32_t khi = wave_max_u32(vis ? key : 0u);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[v & 1][wv] = make_uint4((uint32_t)__popcll(bal), cm, klo, khi);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint4 a = red[v & 1][0], b = red[v & 1][1], c = red[v & 1][2], d = red[v & 1][3];
+            part[(int64_t)v * gridDim.x + blockIdx.x] =
+                make_uint4(a.x + b.x + c.x + d.x, max(max(a.y, b.y), max(c.y, d.y)),
+                           min(min(a.z, b.z), min(c.z, d.z)), max(max(a.w, b.w), max(c.w, d.w)));
         }
     }
 }
 
-// nvis[v] = sum and cmax[v] = maximum of the per-wave values of view v (one
-// block per view; colour maxima are non-negative, so their float bits order
-// like the floats).
-__global__ __launch_bounds__(256) void k_proj_reduce(const uint32_t *__restrict__ part, int Vc, int64_t nw,
-                                                     uint32_t *__restrict__ nvis, uint32_t *__restrict__ cmax_bits) {
-    __shared__ uint32_t sh[2][4];
+// nvis[v] = sum, cmax[v] = maximum, kmin[v] / kmax[v] = smallest / largest
+// visible depth key of the per-block values of view v (one block per view).
+__global__ __launch_bounds__(256) void k_proj_reduce(const uint4 *__restrict__ part, int Vc, int64_t nblk,
+                                                     uint32_t *__restrict__ nvis, uint32_t *__restrict__ cmax_bits,
+                                                     uint32_t *__restrict__ kmin) {
+    __shared__ uint32_t sh[4][4];
     const int v = blockIdx.x;
-    uint32_t cnt = 0, cm = 0;
-    for (int64_t w = threadIdx.x; w < nw; w += 256) {
-        cnt += part[(int64_t)v * nw + w];
-        cm = max(cm, part[((int64_t)Vc + v) * nw + w]);
+    uint32_t cnt = 0, cm = 0, klo = 0xFFFFFFFFu, khi = 0;
+    for (int64_t w = threadIdx.x; w < nblk; w += 256) {
+        const uint4 q = part[(int64_t)v * nblk + w];
+        cnt += q.x;
+        cm = max(cm, q.y);
+        klo = min(klo, q.z);
+        khi = max(khi, q.w);
     }
     for (int off = 32; off > 0; off >>= 1) {
         cnt += __shfl_xor(cnt, off);
         cm = max(cm, (uint32_t)__shfl_xor((int)cm, off));
+        klo = min(klo, (uint32_t)__shfl_xor((int)klo, off));
+        khi = max(khi, (uint32_t)__shfl_xor((int)khi, off));
     }
     if ((threadIdx.x & 63) == 0) {
         sh[0][threadIdx.x >> 6] = cnt;
         sh[1][threadIdx.x >> 6] = cm;
+        sh[2][threadIdx.x >> 6] = klo;
+        sh[3][threadIdx.x >> 6] = khi;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         nvis[v] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
         cmax_bits[v] = max(max(sh[1][0], sh[1][1]), max(sh[1][2], sh[1][3]));
+        kmin[v] = min(min(sh[2][0], sh[2][1]), min(sh[2][2], sh[2][3]));
+        kmin[Vc + v] = max(max(sh[3][0], sh[3][1]), max(sh[3][2], sh[3][3]));
     }
 }
 
@@ -253,9 +298,9 @@ static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const
                      hipStream_t st) {
     const int64_t blocks = (sc.n + 255) / 256;
     hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0,
-                       b.R1, b.R2, b.R3, b.key0, b.proj_part, b.counters);
-    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (const uint32_t *)b.proj_part, Vc,
-                       blocks * 4, b.nvis, b.cmax);
+                       b.R1, b.R2, b.R3, b.key0, (uint4 *)b.proj_part, b.counters);
+    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (const uint4 *)b.proj_part, Vc,
+                       blocks, b.nvis, b.cmax, b.kmin);
 }
 
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,

@@ -2,8 +2,9 @@
 // prefix sums, fills and a fixed-order float sum.
 //
 // Radix sort: each of n_segs segments of n_per_seg items (one segment per
-// view) is sorted independently and stably by key, 8 bits per pass, 4
-// passes.  Blocks never straddle segments.  Per pass:
+// view) is sorted independently and stably by key, 8 bits per pass, 3 or 4
+// passes (3 when every segment's keys, minus the segment's smallest, fit in
+// 24 bits).  Blocks never straddle segments.  Per pass:
 //   hist:    per block, per digit counts -> hist[seg][digit][block]
 //   offsets: per segment exclusive scan of hist in (digit, block) order
 //   scatter: each wave ranks its 1024 keys in 16 rounds of 64 with ballot
@@ -33,8 +34,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
     return m;
 }
 
+// Key as the pass sees it: with kbase, visible keys relative to their
+// segment's smallest one (first pass only; later passes read rebased keys).
+__device__ __forceinline__ uint32_t rebase(uint32_t k, const uint32_t *kbase, int seg) {
+    return (kbase && k != kInvisibleKey) ? k - kbase[seg] : k;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_per_seg,
-                                                              int nb, int shift, uint32_t *__restrict__ hist) {
+                                                              int nb, int shift, uint32_t *__restrict__ hist,
+                                                              const uint32_t *__restrict__ kbase) {
     __shared__ uint32_t cnt[4][256];
     const int seg = blockIdx.y, b = blockIdx.x;
     const int w = threadIdx.x >> 6;
@@ -44,7 +52,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
     const int64_t lo = (int64_t)b * kSortTile;
     const int64_t hi = min(lo + (int64_t)kSortTile, n_per_seg);
     for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) {
-        const uint32_t d = (keys[base + i] >> shift) & 255u;
+        const uint32_t d = (rebase(keys[base + i], kbase, seg) >> shift) & 255u;
         atomicAdd(&cnt[w][d], 1u);
     }
     __syncthreads();
@@ -84,7 +92,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                  uint32_t *__restrict__ kout,
                                                                  uint32_t *__restrict__ vout, int64_t n_per_seg,
                                                                  int nb, int shift, int vals_are_iota,
-                                                                 const uint32_t *__restrict__ offs) {
+                                                                 const uint32_t *__restrict__ offs,
+                                                                 const uint32_t *__restrict__ kbase) {
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t wbase[4][256];   // block-local start of each wave's run of each digit
     __shared__ uint32_t dstart[256];     // block-local start of each digit
@@ -101,7 +110,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     for (int k = 0; k < kSortRounds; ++k) {
         const int64_t i = wlo + k * 64 + lane;
         const bool ok = i < n_per_seg;
-        key[k] = ok ? kin[base + i] : 0u;
+        key[k] = ok ? rebase(kin[base + i], kbase, seg) : 0u;
         val[k] = ok ? (vals_are_iota ? (uint32_t)i : vin[base + i]) : 0u;
         const uint32_t d = (key[k] >> shift) & 255u;
         const uint64_t active = __ballot(ok);
@@ -166,17 +175,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 }
 
 hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1, uint32_t *hist,
-                               int64_t n_per_seg, int n_segs, bool vals_are_iota, uint32_t **key_out,
-                               uint32_t **val_out, hipStream_t st) {
+                               int64_t n_per_seg, int n_segs, bool vals_are_iota, int passes,
+                               const uint32_t *kbase, uint32_t **key_out, uint32_t **val_out, hipStream_t st) {
     const int nb = (int)((n_per_seg + kSortTile - 1) / kSortTile);
     uint32_t *ki = key0, *vi = val0, *ko = key1, *vo = val1;
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
+        const uint32_t *kb = pass == 0 ? kbase : nullptr;
         hipLaunchKernelGGL(k_radix_hist, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, n_per_seg, nb, shift,
-                           hist);
+                           hist, kb);
         hipLaunchKernelGGL(k_radix_offsets, dim3(n_segs), dim3(1024), 0, st, hist, nb);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_per_seg,
-                           nb, shift, (pass == 0 && vals_are_iota) ? 1 : 0, hist);
+                           nb, shift, (pass == 0 && vals_are_iota) ? 1 : 0, hist, kb);
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
