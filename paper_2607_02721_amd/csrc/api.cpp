@@ -47,7 +47,7 @@ struct Arena {
     int device = -1;
 };
 constexpr int kMaxDevices = 16;
-Arena g_work[kMaxDevices], g_lists[kMaxDevices], g_agg[kMaxDevices];
+Arena g_work[kMaxDevices], g_lists[kMaxDevices], g_agg[kMaxDevices], g_compact[kMaxDevices];
 // Recorded at the end of every call on the call's stream; the next call waits
 // for it on its own stream, so the shared arenas are never used by two
 // streams at once.
@@ -112,6 +112,7 @@ struct Setup {
     int nchunks;
     int agg = GS_AGG_RAY;       // query granularity of the sensitivity pass
     int nq = 1;                 // queries per ray (3 for per-channel queries)
+    bool compact = false;       // pass 1 leaves compacted quadrant lists for pass 2
     std::vector<int> tiles_x, tiles_y;
     std::vector<int64_t> ray_base;
 };
@@ -142,6 +143,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
     add(sizeof(double) * 3 * 4 * (size_t)c.total_tiles);   // objective partials
     add(sizeof(double) * (3 * (size_t)c.vc + 1));
+    add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // compacted entries per quadrant
     add(sizeof(double) * (size_t)c.total_tiles);            // per-tile A(Q)
     add(sizeof(double) * ((size_t)c.vc + 1));               // per-view A(Q), launch total
     if (S.agg == GS_AGG_IMAGE) add(sizeof(uint64_t) * (size_t)c.vc * N);   // per (view, Gaussian) shares
@@ -289,6 +291,7 @@ struct ChunkRun {
     double *tile_A = nullptr;      // aggregated queries: A(Q) per tile, per view (+ the launch total)
     double *view_A = nullptr;
     uint64_t *acc = nullptr;       // aggregated shares (fixed point); per list entry for tiles
+    uint32_t *ccount = nullptr;    // entries pass 1 compacted per quadrant
     int64_t n_entries = 0;
 };
 
@@ -331,6 +334,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     r.sum_tmp = cv.take<double>((N + 4095) / 4096 + 2);
     r.tile_sums = cv.take<double>(3 * 4 * (size_t)c.total_tiles);
     r.view_sums = cv.take<double>(3 * (size_t)c.vc + 1);
+    r.ccount = cv.take<uint32_t>(4 * (size_t)c.total_tiles);
     r.tile_A = cv.take<double>(c.total_tiles);
     r.view_A = cv.take<double>((size_t)c.vc + 1);
     r.acc = nullptr;
@@ -415,13 +419,21 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(arena_reserve(g_lists[dev], list_bytes + acc_bytes));
     b.lists = (uint32_t *)g_lists[dev].base;
     if (S.agg == GS_AGG_TILE) r.acc = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
+    // room for every quadrant's compacted list (4 x the lists); without it
+    // pass 2 filters the tile lists again
+    uint32_t *clist = nullptr;
+    if (S.compact) {
+        const size_t cbytes = 4 * std::max<size_t>(total, 1) * sizeof(uint32_t);
+        if (arena_reserve(g_compact[dev], cbytes) == hipSuccess) clist = (uint32_t *)g_compact[dev].base;
+        else (void)hipGetLastError();
+    }
     tm.mark(6, st);
     launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, st);
     HIP_TRY(hipGetLastError());
     tm.mark(7, st);
     // the compositing launch sees this chunk as a single scene slot
     r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
-                            N, 0, 0, b.R3, c.rays};
+                            N, 0, 0, b.R3, c.rays, clist};
     HIP_TRY(hipMemcpyAsync(r.slot_dev, &r.host_slot, sizeof(SceneSlot), hipMemcpyHostToDevice, st));
     launch_fill_u32((uint32_t *)r.tile_scene, 0u, c.total_tiles, st);
     tm.mark(3, st);
@@ -507,7 +519,7 @@ gs_status gs_release_workspace(void) {
     const int dev = current_device(&s);
     if (dev < 0) return s;
     HIP_TRY(hipDeviceSynchronize());
-    for (Arena *a : {&g_work[dev], &g_lists[dev], &g_agg[dev]}) {
+    for (Arena *a : {&g_work[dev], &g_lists[dev], &g_agg[dev], &g_compact[dev]}) {
         if (a->base) hipFree(a->base);
         a->base = nullptr;
         a->cap = 0;
@@ -534,6 +546,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     S.agg = params->aggregate;
     S.nq = params->query_mode == GS_QUERY_CHANNEL ? 3 : 1;
+    S.compact = S.agg == GS_AGG_RAY;
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
     launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
     // per-scene queries: the absolute contributions and A summed over chunks
@@ -563,6 +576,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         entries += r.n_entries;
         n_bins += (int64_t)c.total_tiles * S.nchunks;
         CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor);
+        a.ccount = r.host_slot.clist ? r.ccount : nullptr;
         tm.mark(3, st);
         launch_composite_pass1(a, st);
         HIP_TRY(hipGetLastError());
@@ -919,16 +933,18 @@ struct PlanScene {
     int64_t nbins = 0;
     int max_tiles = 1, max_tx = 1, max_ty = 1;
     uint64_t cap = 0;
+    uint32_t *clist = nullptr;    // compacted quadrant lists (4 x cap), or null
     int group = 0, view0 = 0, tile0 = 0;
 };
 
 struct PlanGroup {
     std::vector<int> scenes;
-    void *buf = nullptr, *lists = nullptr;
+    void *buf = nullptr, *lists = nullptr, *clists = nullptr;   // clists: compacted quadrant lists + counts
     ViewDev *views = nullptr;
     int32_t *tile_view = nullptr, *tile_scene = nullptr;
     SceneSlot *slots = nullptr;
     uint32_t *work = nullptr;
+    uint32_t *ccount = nullptr;
     int total_tiles = 0, total_views = 0;
     size_t bytes = 0, list_bytes = 0;
 };
@@ -1042,6 +1058,7 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
         a.share_floor = P->p.share_floor;
         a.work = P->cfg.persistent ? G.work : nullptr;
         a.xcd_remap = P->cfg.xcd_remap;
+        a.ccount = G.clists ? G.ccount : nullptr;
         launch_composite_pass1(a, st);
         launch_composite_pass2(a, false, nullptr, st);
     }
@@ -1053,6 +1070,7 @@ void plan_free(gs_plan *P) {
     for (PlanGroup &G : P->groups) {
         if (G.buf) hipFree(G.buf);
         if (G.lists) hipFree(G.lists);
+        if (G.clists) hipFree(G.clists);
     }
     if (P->flag) hipFree(P->flag);
     if (P->cap) hipStreamDestroy(P->cap);
@@ -1144,6 +1162,21 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         for (int si : G.scenes) {
             PlanScene &ps = P->scenes[si];
             ps.b.lists = lc.take<uint32_t>(ps.cap);
+        }
+        // compacted quadrant lists (4 x each scene's capacity) and their
+        // counts; without room pass 2 filters the tile lists again
+        const size_t cb = 4 * lb + sizeof(uint32_t) * 4 * (size_t)G.total_tiles + 8192;
+        if (hipMalloc(&G.clists, cb) == hipSuccess) {
+            Carve cc(G.clists);
+            for (int si : G.scenes) {
+                PlanScene &ps = P->scenes[si];
+                ps.clist = cc.take<uint32_t>(4 * ps.cap);
+            }
+            G.ccount = cc.take<uint32_t>(4 * (size_t)G.total_tiles);
+            G.list_bytes += cb;
+        } else {
+            (void)hipGetLastError();
+            G.clists = nullptr;
         }
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -1279,7 +1312,8 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
             for (int si : G.scenes) {
                 PlanScene &ps = plan->scenes[si];
                 hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
-                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0});
+                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0, nullptr, 0,
+                                       ps.clist});
             }
             HIP_TRY(hipMemcpyAsync(G.slots, hs.data(), sizeof(SceneSlot) * hs.size(), hipMemcpyHostToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));

@@ -61,6 +61,7 @@ struct WaveSetup {
     float cmax;
     const float4 *R3;       // per-channel queries: channel colours
     int64_t ray_stride;     // per-channel queries: ray_A plane stride
+    uint32_t *clist;        // compacted entries of the scene's quadrants (null: none)
 };
 
 __device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles * 4; }
@@ -102,6 +103,7 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.cmax = __uint_as_float(S.cmax[w.v - S.view0]);
     w.R3 = S.R3;
     w.ray_stride = S.ray_stride;
+    w.clist = S.clist;
     return true;
 }
 
@@ -169,7 +171,7 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
 template <int kExtra, int kPad = 1, bool kChannel = false>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
 __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
                                            uint32_t *sid, float *sold, const double *__restrict__ weights,
-                                           float *cblue = nullptr) {
+                                           float *cblue = nullptr, uint32_t *cout = nullptr) {
     static_assert(!(kChannel && kExtra == 2), "per-channel queries have no weighted objective");
     const int lane = threadIdx.x;
     const uint64_t e = e0 + lane;
@@ -204,6 +206,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
     }
     if (touch) {
         const int slot = __popcll(bal & lanemask_lt64());
+        if (cout) cout[slot] = g;    // pass 1 keeps the quadrant's entries in order
         float cb = 0.0f, cg = 0.0f;
         if (kChannel) {
             const float4 c3 = w.R3[o];
@@ -226,6 +229,40 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         if (kExtra == 2) extra = (float)weights[g];
         if (kChannel) extra = cg;
         col[slot] = make_float4(r1.z, r1.w, cb, extra);
+    }
+    return n;
+}
+
+// Stage up to 64 entries of a quadrant's compacted list (every one passed
+// the quadrant's exact test in pass 1): the same slots as stage_slice would
+// fill for them, padded with null entries to a multiple of kPad.
+template <int kPad, bool kChannel>
+__device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t *__restrict__ cl, uint32_t left,
+                                             float4 *geo, float4 *col, uint32_t *sid, float *sold, float *cblue) {
+    const int lane = threadIdx.x;
+    const int n = (int)min(left, (uint32_t)kWave);
+    if (lane < n) {
+        const uint32_t g = cl[lane];
+        const int64_t o = w.vbase + g;
+        const float4 r0 = w.R0[o];
+        const float4 r1 = w.R1[o];
+        float cb = 0.0f, cg = 0.0f;
+        if (kChannel) {
+            const float4 c3 = w.R3[o];
+            cb = c3.x;
+            cg = c3.y;
+            cblue[lane] = c3.z;
+        } else {
+            cb = w.R2[o].x;
+        }
+        geo[lane] = make_float4((r0.x - w.qx0) + r0.z, (r0.y - w.qy0) + r0.w, r1.x, r1.y);
+        col[lane] = make_float4(r1.z, r1.w, cb, kChannel ? cg : 0.0f);
+        sid[lane] = g;
+        sold[lane] = __uint_as_float(w.sens_bits[g]);
+    } else if (lane < ((n + kPad - 1) & ~(kPad - 1))) {
+        geo[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        col[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (kChannel) cblue[lane] = 0.0f;
     }
     return n;
 }
@@ -262,9 +299,14 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
         const float cmax = w.cmax;
         float T = 1.0f, A = 0.0f, AG = 0.0f, AB = 0.0f;
         bool done = !scored;
+        // this quadrant's compacted list (see SceneSlot::clist)
+        uint32_t *cl = w.clist ? w.clist + 4 * w.start + (uint64_t)w.quad * (w.end - w.start) : nullptr;
+        uint32_t ccnt = 0;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<0, 1, kCh>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr, cblue);
+            const int n = stage_slice<0, 1, kCh>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr, cblue,
+                                                 cl ? cl + ccnt : nullptr);
+            ccnt += (uint32_t)n;
             __syncthreads();
             for (int j = 0; j < n; ++j) {
                 const float4 G = geo[j], Cc = col[j];
@@ -296,6 +338,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
                 w.ray_A[2 * w.ray_stride + w.ray_local] = scored ? AB : 0.0f;
             }
         }
+        if (cl && threadIdx.x == 0) a.ccount[qi] = ccnt;
     }
 }
 
@@ -412,10 +455,11 @@ __device__ __forceinline__ float wave_transpose_sum16(float (&v)[16]) {
     return dpp_add<0xB1>(dpp_add<0x4E>(v[0]));
 }
 
-template <bool kStats, bool kPersistent, int kAgg, int kMode>
+template <bool kStats, bool kPersistent, int kAgg, int kMode, bool kCompact>
 __global__ __launch_bounds__(kWave, kPersistent ? 5 : ((kAgg != 0 || kMode == kModeChannel) ? 6 : 8))
 void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     static_assert(!(kAgg != 0 && kMode == kModeChannel), "per-channel queries have no aggregated form");
+    static_assert(!(kAgg != 0 && kCompact), "aggregated queries walk the tile lists");
     constexpr bool kCh = kMode == kModeChannel;
     __shared__ float4 geo[kWave], col[kWave];
     __shared__ uint32_t sid[kWave];
@@ -455,10 +499,18 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
         bool done = !positive;
         uint32_t n_in = 0, n_live = 0, n_eval = 0;
         const float live_bar = a.share_floor * Amin;
-        for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
+        // the quadrant's entries: its compacted list from pass 1, or its
+        // tile's list filtered again
+        const uint32_t *cl = kCompact ? w.clist + 4 * w.start + (uint64_t)w.quad * (w.end - w.start) : nullptr;
+        const uint64_t lo = kCompact ? 0 : w.start, hi = kCompact ? (uint64_t)a.ccount[qi] : w.end;
+        for (uint64_t e0 = lo; e0 < hi; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<kAgg == 0 ? 1 : 3, kBlock, kCh>(w, e0, a.r2_log2, geo, col, sid, sold,
-                                                                      nullptr, cblue);
+            int n;
+            if (kCompact)
+                n = stage_compact<kBlock, kCh>(w, cl + e0, (uint32_t)(hi - e0), geo, col, sid, sold, cblue);
+            else
+                n = stage_slice<kAgg == 0 ? 1 : 3, kBlock, kCh>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr,
+                                                                cblue);
             __syncthreads();
             for (int jb = 0; jb < n; jb += 16) {
                 float sh[16];
@@ -588,33 +640,48 @@ void launch_composite_pass1(const CompositeArgs &a, hipStream_t st) {
 template <int kMode>
 static void pass2_agg(const CompositeArgs &a, uint64_t *counters, hipStream_t st) {
     if (a.agg == 1)
-        hipLaunchKernelGGL((k_pass2<false, false, 1, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<false, false, 1, kMode, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a,
+                           counters);
     else if (a.agg == 2)
-        hipLaunchKernelGGL((k_pass2<false, false, 2, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<false, false, 2, kMode, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a,
+                           counters);
     else
-        hipLaunchKernelGGL((k_pass2<false, false, 3, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<false, false, 3, kMode, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a,
+                           counters);
 }
 
-template <int kMode, bool kPersistentForm>
+template <int kMode, bool kPersistentForm, bool kCompact>
 static void pass2_ray(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
     if constexpr (kPersistentForm) {
         if (a.work) {
             launch_fill_u32(a.work, 0u, 1, st);
             if (stats) {
-                static const unsigned grid = resident_waves(k_pass2<true, true, 0, kMode>);
-                hipLaunchKernelGGL((k_pass2<true, true, 0, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+                static const unsigned grid = resident_waves(k_pass2<true, true, 0, kMode, kCompact>);
+                hipLaunchKernelGGL((k_pass2<true, true, 0, kMode, kCompact>), dim3(grid), dim3(kWave), 0, st, a,
+                                   counters);
             } else {
-                static const unsigned grid = resident_waves(k_pass2<false, true, 0, kMode>);
-                hipLaunchKernelGGL((k_pass2<false, true, 0, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+                static const unsigned grid = resident_waves(k_pass2<false, true, 0, kMode, kCompact>);
+                hipLaunchKernelGGL((k_pass2<false, true, 0, kMode, kCompact>), dim3(grid), dim3(kWave), 0, st, a,
+                                   counters);
             }
             return;
         }
     }
     if (stats) {
-        hipLaunchKernelGGL((k_pass2<true, false, 0, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<true, false, 0, kMode, kCompact>), dim3(flat_grid(a)), dim3(kWave), 0, st, a,
+                           counters);
     } else {
-        hipLaunchKernelGGL((k_pass2<false, false, 0, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, counters);
+        hipLaunchKernelGGL((k_pass2<false, false, 0, kMode, kCompact>), dim3(flat_grid(a)), dim3(kWave), 0, st, a,
+                           counters);
     }
+}
+
+template <int kMode, bool kPersistentForm>
+static void pass2_ray_any(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
+    if (a.ccount)
+        pass2_ray<kMode, kPersistentForm, true>(a, stats, counters, st);
+    else
+        pass2_ray<kMode, kPersistentForm, false>(a, stats, counters, st);
 }
 
 // Aggregated queries run the flat form without pair counters; per-channel
@@ -629,11 +696,11 @@ void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counte
         return;
     }
     if (mode == kModeL2)
-        pass2_ray<kModeL2, true>(a, stats, counters, st);
+        pass2_ray_any<kModeL2, true>(a, stats, counters, st);
     else if (mode == kModeChannel)
-        pass2_ray<kModeChannel, false>(a, stats, counters, st);
+        pass2_ray_any<kModeChannel, false>(a, stats, counters, st);
     else
-        pass2_ray<kModeL1, true>(a, stats, counters, st);
+        pass2_ray_any<kModeL1, true>(a, stats, counters, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -132,6 +132,13 @@ struct SceneSlot {
     int32_t tile0;                // first tile of the scene in the launch's tile table
     const float4 *R3;             // per-channel queries: channel colours [views][N] (else null)
     int64_t ray_stride;           // per-channel queries: distance between the R, G and B planes of ray_A
+    // Pass 1 leaves each quadrant's entries that pass its exact test here
+    // (the Gaussian indices, in list order, up to where the quadrant's rays
+    // stopped): quadrant q of a tile with list [start, end) owns
+    // [4 start + q (end - start), 4 start + (q + 1)(end - start)).  Pass 2
+    // walks these dense lists.  Null: no compaction (pass 2 filters the tile
+    // lists again).
+    uint32_t *clist;
 };
 
 // Compositing arithmetic of a query mode: one L1 query per ray (RGB sum or
@@ -155,6 +162,7 @@ struct CompositeArgs {
     int32_t agg;                 // query granularity (gs_aggregate) of pass 2
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
+    uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant (with SceneSlot::clist)
 };
 // Fixed-point scale of the aggregated shares.  A Gaussian's accumulated share
 // of one query is at most 1 (a_i(q) <= A(q) on every ray), so 2^60 leaves a
