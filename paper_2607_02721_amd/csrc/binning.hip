@@ -10,7 +10,7 @@
 //             tile's total; a scan of the totals gives each tile's list start,
 //             so a tile's list is its chunks' segments in order;
 //   3. emit:  one wave per (chunk, group of tile rows) expands the chunk's
-//             positions that meet its rows, in order and 2^9 at a time, into
+//             positions that meet its rows, in order and 2^10 at a time, into
 //             (position, tile) items packed 64 to a batch; every tile's next
 //             slot comes from a wave-private LDS cursor (atomic add, executed
 //             in issue order), so each (tile, chunk) segment is written

@@ -13,7 +13,7 @@ constexpr int kChunkBits = 14;     // depth ranks are binned in chunks of 2^14 (
 constexpr int kMaxTilesPerView = 8160;  // two u32 LDS arrays of this size fit 64 KiB
 constexpr int kSortTile = 4096;    // radix sort: keys per block (4 waves x 16 rounds x 64 lanes)
 constexpr int kBinPositions = 1 << kChunkBits;  // binning: depth-sorted positions per chunk (count block)
-constexpr int kEmitBatch = 512;    // emission: positions a wave queues at a time
+constexpr int kEmitBatch = 1024;   // emission: positions a wave queues at a time
 constexpr uint32_t kInvisibleKey = 0xFFFFFFFFu;
 constexpr uint32_t kIndexMask = 0x0FFFFFFFu; // list entry = gaussian | quadrant mask << 28
 
