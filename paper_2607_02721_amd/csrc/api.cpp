@@ -399,13 +399,14 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     const bool out_in_0 = r.sorted_g == b.val0;
     uint32_t *xr = out_in_0 ? b.key1 : b.key0, *yr = out_in_0 ? b.val1 : b.val0;
     launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
-    int max_tiles = 1, max_tx = 1, max_ty = 1;
+    int max_tiles = 1, max_tx = 1, max_ty = 1, max_cells = 1;
     for (const ViewDev &V : hv) {
         max_tiles = std::max(max_tiles, V.tiles_x * V.tiles_y);
+        max_cells = std::max(max_cells, (V.tiles_x + 1) * (V.tiles_y + 1));
         max_tx = std::max(max_tx, V.tiles_x);
         max_ty = std::max(max_ty, V.tiles_y);
     }
-    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, max_tiles, st);
+    launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, max_cells, st);
     launch_chunk_prefix(r.views_dev, c.vc, S.nchunks, b, max_tiles, st);
     scan_u32_to_u64_exclusive(b.tile_tot, b.tile_off, c.total_tiles, r.scan_tmp, st);
     HIP_TRY(hipGetLastError());
@@ -931,7 +932,7 @@ struct PlanScene {
     uint64_t *scan_tmp = nullptr;
     uint32_t *over = nullptr;
     int64_t nbins = 0;
-    int max_tiles = 1, max_tx = 1, max_ty = 1;
+    int max_tiles = 1, max_tx = 1, max_ty = 1, max_cells = 1;
     uint64_t cap = 0;
     uint32_t *clist = nullptr;    // compacted quadrant lists (4 x cap), or null
     int group = 0, view0 = 0, tile0 = 0;
@@ -1031,7 +1032,7 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ps.xr = b.key1;
     ps.yr = b.val1;
     launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);
-    launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, ps.max_tiles, st);
+    launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, ps.max_cells, st);
     launch_chunk_prefix(ps.views_dev, ps.c.vc, ps.S.nchunks, b, ps.max_tiles, st);
     scan_u32_to_u64_exclusive(b.tile_tot, b.tile_off, ps.c.total_tiles, ps.scan_tmp, st);
 }
@@ -1242,6 +1243,7 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
             V.ray_local = ps.S.ray_base[k];
             V.tile_base = tb;
             ps.max_tiles = std::max(ps.max_tiles, V.tiles_x * V.tiles_y);
+            ps.max_cells = std::max(ps.max_cells, (V.tiles_x + 1) * (V.tiles_y + 1));
             ps.max_tx = std::max(ps.max_tx, V.tiles_x);
             ps.max_ty = std::max(ps.max_ty, V.tiles_y);
             for (int t = 0; t < V.tiles_x * V.tiles_y; ++t) ps.htv[tb + t] = k;

@@ -69,10 +69,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
                                                            const uint32_t *__restrict__ yr_in,
                                                            uint32_t *__restrict__ bin_count,
                                                            const uint8_t *__restrict__ active) {
-    extern __shared__ uint32_t cnt[];                 // [tiles]
-    // Bit 31 of cnt[t] marks a tile without any selected ray (no entries);
-    // the counts themselves stay below 2^31.
-    constexpr uint32_t kOff = 0x80000000u;
+    // A position adds 1 to every tile of its tile rectangle: +1 / -1 at the
+    // rectangle's corners of a 2D difference array, whose prefix sums along
+    // x and then y are the counts (four LDS atomics per position, whatever
+    // its size).
+    extern __shared__ int32_t dif[];                  // [tiles_y + 1][tiles_x + 1]
     const int64_t lb = xcd_block(blockIdx.x, kCountGroup);   // logical block: chunk + nchunks * view
     const int v = (int)(lb / nchunks);
     if (v >= n_views) return;
@@ -82,25 +83,44 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
     if (lo >= nv) return;
     const int64_t hi = min(lo + (int64_t)kBinPositions, nv);
     const int chunk = (int)(lo >> kSegBits);
-    const int ntiles = V.tiles_x * V.tiles_y;
-    for (int t = threadIdx.x; t < ntiles; t += kBinThreads)
-        cnt[t] = (active && !active[V.tile_base + t]) ? kOff : 0u;
+    const int tx_n = V.tiles_x, ty_n = V.tiles_y, ntiles = tx_n * ty_n;
+    const int stride = tx_n + 1, cells = stride * (ty_n + 1);
+    for (int i = threadIdx.x; i < cells; i += kBinThreads) dif[i] = 0;
     __syncthreads();
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBinThreads) {
         int xl, xh, yl, yh;
         unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
         unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
-        for (int ty = yl >> 4; ty <= (yh >> 4); ++ty)
-            for (int tx = xl >> 4; tx <= (xh >> 4); ++tx) {
-                const int t = ty * V.tiles_x + tx;
-                if (cnt[t] & kOff) continue;
-                atomicAdd(&cnt[t], 1u);
-            }
+        const int x0 = xl >> 4, x1 = (xh >> 4) + 1, y0 = (yl >> 4) * stride, y1 = ((yh >> 4) + 1) * stride;
+        atomicAdd(&dif[y0 + x0], 1);
+        atomicAdd(&dif[y0 + x1], -1);
+        atomicAdd(&dif[y1 + x0], -1);
+        atomicAdd(&dif[y1 + x1], 1);
     }
     __syncthreads();
-    // this block is the only writer of (tile, chunk) for every tile of the view
+    for (int ty = threadIdx.x; ty < ty_n; ty += kBinThreads) {       // along x, one row per thread
+        int run = 0;
+        for (int tx = 0; tx < tx_n; ++tx) {
+            run += dif[ty * stride + tx];
+            dif[ty * stride + tx] = run;
+        }
+    }
+    __syncthreads();
+    for (int tx = threadIdx.x; tx < tx_n; tx += kBinThreads) {       // along y, one column per thread
+        int run = 0;
+        for (int ty = 0; ty < ty_n; ++ty) {
+            run += dif[ty * stride + tx];
+            dif[ty * stride + tx] = run;
+        }
+    }
+    __syncthreads();
+    // this block is the only writer of (tile, chunk) for every tile of the
+    // view; tiles without a selected ray get no entries
     uint32_t *row = bin_count + (int64_t)V.tile_base * nchunks + (int64_t)chunk * ntiles;
-    for (int t = threadIdx.x; t < ntiles; t += kBinThreads) row[t] = cnt[t] & ~kOff;
+    for (int t = threadIdx.x; t < ntiles; t += kBinThreads) {
+        const bool off = active && !active[V.tile_base + t];
+        row[t] = off ? 0u : (uint32_t)dif[(t / tx_n) * stride + t % tx_n];
+    }
 }
 
 // Column pass over one view's [chunk][tile] counts: each thread owns one tile
@@ -477,10 +497,10 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
 }
 
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                      const uint32_t *xr, const uint32_t *yr, int max_tiles, hipStream_t st) {
+                      const uint32_t *xr, const uint32_t *yr, int max_cells, hipStream_t st) {
     const int64_t run = 8 * kCountGroup;
     const int64_t blocks = ((int64_t)nchunks * Vc + run - 1) / run * run;
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)blocks), dim3(kBinThreads), (size_t)max_tiles * sizeof(uint32_t),
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)blocks), dim3(kBinThreads), (size_t)max_cells * sizeof(int32_t),
                        st, views_dev, Vc, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active);
 }
 

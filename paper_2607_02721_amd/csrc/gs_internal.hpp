@@ -101,8 +101,9 @@ void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc
                             uint32_t *yr, hipStream_t st);
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
                         uint8_t *active, hipStream_t st);
+// max_cells: the largest (tiles_x + 1) (tiles_y + 1) of the views.
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
-                      const uint32_t *xr, const uint32_t *yr, int max_tiles, hipStream_t st);
+                      const uint32_t *xr, const uint32_t *yr, int max_cells, hipStream_t st);
 // bin_count -> per-tile prefix over chunks (in place) and tile_tot.
 void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const ChunkBufs &b, int max_tiles,
                          hipStream_t st);
