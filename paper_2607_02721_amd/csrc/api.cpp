@@ -420,18 +420,29 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(arena_reserve(g_lists[dev], list_bytes + acc_bytes));
     b.lists = (uint32_t *)g_lists[dev].base;
     if (S.agg == GS_AGG_TILE) r.acc = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
-    // room for every quadrant's compacted list (4 x the lists); without it
-    // pass 2 filters the tile lists again
+    // room for the quadrants' compacted lists (4 x the lists), if it fits in
+    // half of the free memory; without it pass 2 filters the tile lists again
     uint32_t *clist = nullptr;
     if (S.compact) {
         const size_t cbytes = 4 * std::max<size_t>(total, 1) * sizeof(uint32_t);
-        if (arena_reserve(g_compact[dev], cbytes) == hipSuccess) clist = (uint32_t *)g_compact[dev].base;
-        else (void)hipGetLastError();
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        const size_t held = g_compact[dev].cap;
+        if (cbytes <= held || cbytes <= (free_b + held) / 2) {
+            if (arena_reserve(g_compact[dev], cbytes) == hipSuccess)
+                clist = (uint32_t *)g_compact[dev].base;
+            else
+                (void)hipGetLastError();
+        }
     }
     tm.mark(6, st);
     launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, st);
     HIP_TRY(hipGetLastError());
     tm.mark(7, st);
+
     // the compositing launch sees this chunk as a single scene slot
     r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
                             N, 0, 0, b.R3, c.rays, clist};
@@ -460,6 +471,7 @@ CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params
     a.share_floor = share_floor;
     a.work = nullptr;
     a.xcd_remap = 1;
+    a.report_floor = share_floor > 0.0f ? std::nextafter(share_floor, 0.0f) : 0.0f;
     return a;
 }
 
@@ -934,18 +946,16 @@ struct PlanScene {
     int64_t nbins = 0;
     int max_tiles = 1, max_tx = 1, max_ty = 1, max_cells = 1;
     uint64_t cap = 0;
-    uint32_t *clist = nullptr;    // compacted quadrant lists (4 x cap), or null
     int group = 0, view0 = 0, tile0 = 0;
 };
 
 struct PlanGroup {
     std::vector<int> scenes;
-    void *buf = nullptr, *lists = nullptr, *clists = nullptr;   // clists: compacted quadrant lists + counts
+    void *buf = nullptr, *lists = nullptr;
     ViewDev *views = nullptr;
     int32_t *tile_view = nullptr, *tile_scene = nullptr;
     SceneSlot *slots = nullptr;
     uint32_t *work = nullptr;
-    uint32_t *ccount = nullptr;
     int total_tiles = 0, total_views = 0;
     size_t bytes = 0, list_bytes = 0;
 };
@@ -1059,7 +1069,7 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
         a.share_floor = P->p.share_floor;
         a.work = P->cfg.persistent ? G.work : nullptr;
         a.xcd_remap = P->cfg.xcd_remap;
-        a.ccount = G.clists ? G.ccount : nullptr;
+        a.report_floor = P->p.share_floor > 0.0f ? std::nextafter(P->p.share_floor, 0.0f) : 0.0f;
         launch_composite_pass1(a, st);
         launch_composite_pass2(a, false, nullptr, st);
     }
@@ -1071,7 +1081,6 @@ void plan_free(gs_plan *P) {
     for (PlanGroup &G : P->groups) {
         if (G.buf) hipFree(G.buf);
         if (G.lists) hipFree(G.lists);
-        if (G.clists) hipFree(G.clists);
     }
     if (P->flag) hipFree(P->flag);
     if (P->cap) hipStreamDestroy(P->cap);
@@ -1164,21 +1173,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
             PlanScene &ps = P->scenes[si];
             ps.b.lists = lc.take<uint32_t>(ps.cap);
         }
-        // compacted quadrant lists (4 x each scene's capacity) and their
-        // counts; without room pass 2 filters the tile lists again
-        const size_t cb = 4 * lb + sizeof(uint32_t) * 4 * (size_t)G.total_tiles + 8192;
-        if (hipMalloc(&G.clists, cb) == hipSuccess) {
-            Carve cc(G.clists);
-            for (int si : G.scenes) {
-                PlanScene &ps = P->scenes[si];
-                ps.clist = cc.take<uint32_t>(4 * ps.cap);
-            }
-            G.ccount = cc.take<uint32_t>(4 * (size_t)G.total_tiles);
-            G.list_bytes += cb;
-        } else {
-            (void)hipGetLastError();
-            G.clists = nullptr;
-        }
+
     }
     HIP_TRY(hipStreamSynchronize(st));
     return GS_OK;
@@ -1314,8 +1309,7 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
             for (int si : G.scenes) {
                 PlanScene &ps = plan->scenes[si];
                 hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
-                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0, nullptr, 0,
-                                       ps.clist});
+                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0});
             }
             HIP_TRY(hipMemcpyAsync(G.slots, hs.data(), sizeof(SceneSlot) * hs.size(), hipMemcpyHostToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));

@@ -62,6 +62,8 @@ struct WaveSetup {
     const float4 *R3;       // per-channel queries: channel colours
     int64_t ray_stride;     // per-channel queries: ray_A plane stride
     uint32_t *clist;        // compacted entries of the scene's quadrants (null: none)
+    uint64_t cbase;         // this quadrant's compacted slots start at clist + cbase
+    float sfloor;           // staged sensitivities are raised to this (pass 2)
 };
 
 __device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles * 4; }
@@ -104,6 +106,8 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.R3 = S.R3;
     w.ray_stride = S.ray_stride;
     w.clist = S.clist;
+    w.cbase = 4 * w.start + (uint64_t)w.quad * (w.end - w.start);
+    w.sfloor = a.report_floor;
     return true;
 }
 
@@ -220,7 +224,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         float extra = 0.0f;
         if (kExtra == 1) {
             sid[slot] = g;
-            sold[slot] = __uint_as_float(w.sens_bits[g]);
+            sold[slot] = fmaxf(__uint_as_float(w.sens_bits[g]), w.sfloor);
         }
         if (kExtra == 3) {   // aggregated pass 2: index and position in the tile's list
             sid[slot] = g;
@@ -258,7 +262,7 @@ __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t 
         geo[lane] = make_float4((r0.x - w.qx0) + r0.z, (r0.y - w.qy0) + r0.w, r1.x, r1.y);
         col[lane] = make_float4(r1.z, r1.w, cb, kChannel ? cg : 0.0f);
         sid[lane] = g;
-        sold[lane] = __uint_as_float(w.sens_bits[g]);
+        sold[lane] = fmaxf(__uint_as_float(w.sens_bits[g]), w.sfloor);
     } else if (lane < ((n + kPad - 1) & ~(kPad - 1))) {
         geo[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         col[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
         float T = 1.0f, A = 0.0f, AG = 0.0f, AB = 0.0f;
         bool done = !scored;
         // this quadrant's compacted list (see SceneSlot::clist)
-        uint32_t *cl = w.clist ? w.clist + 4 * w.start + (uint64_t)w.quad * (w.end - w.start) : nullptr;
+        uint32_t *cl = w.clist ? w.clist + w.cbase : nullptr;
         uint32_t ccnt = 0;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
@@ -501,7 +505,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
         const float live_bar = a.share_floor * Amin;
         // the quadrant's entries: its compacted list from pass 1, or its
         // tile's list filtered again
-        const uint32_t *cl = kCompact ? w.clist + 4 * w.start + (uint64_t)w.quad * (w.end - w.start) : nullptr;
+        const uint32_t *cl = kCompact ? w.clist + w.cbase : nullptr;
         const uint64_t lo = kCompact ? 0 : w.start, hi = kCompact ? (uint64_t)a.ccount[qi] : w.end;
         for (uint64_t e0 = lo; e0 < hi; e0 += kWave) {
             if (__all(done)) break;

@@ -138,7 +138,9 @@ struct SceneSlot {
     // stopped): quadrant q of a tile with list [start, end) owns
     // [4 start + q (end - start), 4 start + (q + 1)(end - start)).  Pass 2
     // walks these dense lists.  Null: no compaction (pass 2 filters the tile
-    // lists again).
+    // lists again).  Both give the same sensitivities (pass 2 reports no
+    // share below the share floor, and every pair before a ray's stop is
+    // walked either way).
     uint32_t *clist;
 };
 
@@ -164,6 +166,7 @@ struct CompositeArgs {
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
     uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant (with SceneSlot::clist)
+    float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
 };
 // Fixed-point scale of the aggregated shares.  A Gaussian's accumulated share
 // of one query is at most 1 (a_i(q) <= A(q) on every ray), so 2^60 leaves a
