@@ -152,7 +152,8 @@ def batch_leg(gs, synth, torch, args):
             "gaussian_views_per_s": gv / (ms_plan * 1e-3), "rays": rays,
             "tuner": {"best": best, "ms": dict(zip(["flat_xcd", "flat", "persistent"], tune_ms))},
             "groups": info["n_groups"], "device_bytes": info["device_bytes"],
-            "graph": info["graph_captured"], "create_s": t_create}
+            "composite_launches": info["n_launches"], "compacting_launches": info["n_compact_launches"],
+            "compact_bytes": info["compact_bytes"], "graph": info["graph_captured"], "create_s": t_create}
 
 
 def main():

@@ -202,8 +202,16 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
  * slack per scene), every buffer is owned by the plan, and the sequence is
  * captured into a HIP graph that later calls replay.  Scenes are packed into
  * groups that fit the scratch budget; in each group one compositing launch
- * per pass covers the tiles of all the group's scenes.  Each scene's output
- * equals that of gs_sensitivity with the same params and no ray mask. */
+ * per pass covers the tiles of consecutive scenes whose compacted quadrant
+ * lists (4 x the list capacity) fit a shared pool sized at creation, usually
+ * all of the group's scenes; a scene too large for the pool composites alone
+ * on its plain tile lists.  Each scene's output equals that of
+ * gs_sensitivity with the same params and no ray mask.
+ * Memory: the scratch budget is 45% of the device's free memory (the
+ * environment variable GS_SCRATCH_GB, in GiB, replaces it); groups take
+ * half of it, the compaction pool at most half of what is left after the
+ * plan's other buffers (GS_COMPACT_POOL_GB replaces that bound; 0 turns
+ * compaction off). */
 typedef struct gs_plan gs_plan;
 
 /* Launch shape of the compositing kernels.  persistent = 1: a fixed grid of
@@ -222,6 +230,9 @@ typedef struct {
     int32_t graph_captured;   /* 1 once the sequence runs as a HIP graph */
     int64_t device_bytes;     /* plan-owned device memory */
     int64_t list_capacity;    /* tile-list entries reserved over all scenes */
+    int64_t compact_bytes;    /* pool of compacted quadrant lists (0: none) */
+    int32_t n_launches;       /* pass-1 + pass-2 launch pairs per run */
+    int32_t n_compact_launches; /* of which pass 2 walks compacted lists */
 } gs_plan_info;
 
 /* scenes, views: host arrays of n_scenes (the attribute arrays they point to

@@ -183,7 +183,9 @@ class Plan:
         _lib.check(load().gs_plan_get_info(self._h, C.byref(i)))
         return {"n_scenes": i.n_scenes, "n_groups": i.n_groups, "persistent": i.config.persistent,
                 "xcd_remap": i.config.xcd_remap, "graph_captured": i.graph_captured,
-                "device_bytes": i.device_bytes, "list_capacity": i.list_capacity}
+                "device_bytes": i.device_bytes, "list_capacity": i.list_capacity,
+                "compact_bytes": i.compact_bytes, "n_launches": i.n_launches,
+                "n_compact_launches": i.n_compact_launches}
 
     def status(self, stream=None):
         """Raises GsError if some run overflowed a scene's list capacity."""

@@ -947,6 +947,16 @@ struct PlanScene {
     int max_tiles = 1, max_tx = 1, max_ty = 1, max_cells = 1;
     uint64_t cap = 0;
     int group = 0, view0 = 0, tile0 = 0;
+    uint32_t *clist = nullptr;    // the scene's compacted quadrant lists in the plan's pool (null: none)
+};
+
+// One pass-1 + pass-2 launch over consecutive scenes of a group (tiles
+// [t0, t1) of the group's tile table).  Compacting launches share the plan's
+// pool: each scene owns 4 x its list capacity there, so no run can write past
+// its region (the list guard empties lists that outgrow the capacity).
+struct CompositeBatch {
+    int t0 = 0, t1 = 0;
+    bool compact = false;
 };
 
 struct PlanGroup {
@@ -956,6 +966,8 @@ struct PlanGroup {
     int32_t *tile_view = nullptr, *tile_scene = nullptr;
     SceneSlot *slots = nullptr;
     uint32_t *work = nullptr;
+    uint32_t *ccount = nullptr;   // [4 total_tiles] entries pass 1 compacted per quadrant
+    std::vector<CompositeBatch> batches;
     int total_tiles = 0, total_views = 0;
     size_t bytes = 0, list_bytes = 0;
 };
@@ -968,6 +980,8 @@ struct gs_plan {
     std::vector<PlanScene> scenes;
     std::vector<PlanGroup> groups;
     uint32_t *flag = nullptr;   // device: 1 if some list capacity was exceeded
+    void *pool = nullptr;       // compacted quadrant lists, shared by the compacting launches
+    size_t pool_bytes = 0;
     gs_plan_config cfg{0, 1};
     hipStream_t cap = nullptr;  // stream the sequence is captured on (the null stream cannot capture)
     hipGraph_t graph = nullptr;
@@ -1058,20 +1072,24 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
                             ps.max_tx, ps.max_ty, ps.cap, st);
             launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
         }
-        CompositeArgs a{};
-        a.views = G.views;
-        a.tile_view = G.tile_view;
-        a.tile_scene = G.tile_scene;
-        a.slots = G.slots;
-        a.total_tiles = G.total_tiles;
-        a.query_mode = P->p.query_mode;
-        a.r2_log2 = -0.5f * log2e * P->p.footprint_sigma * P->p.footprint_sigma;
-        a.share_floor = P->p.share_floor;
-        a.work = P->cfg.persistent ? G.work : nullptr;
-        a.xcd_remap = P->cfg.xcd_remap;
-        a.report_floor = P->p.share_floor > 0.0f ? std::nextafter(P->p.share_floor, 0.0f) : 0.0f;
-        launch_composite_pass1(a, st);
-        launch_composite_pass2(a, false, nullptr, st);
+        for (const CompositeBatch &cb : G.batches) {
+            CompositeArgs a{};
+            a.views = G.views;
+            a.tile_view = G.tile_view;
+            a.tile_scene = G.tile_scene;
+            a.slots = G.slots;
+            a.total_tiles = cb.t1 - cb.t0;
+            a.tile_first = cb.t0;
+            a.query_mode = P->p.query_mode;
+            a.r2_log2 = -0.5f * log2e * P->p.footprint_sigma * P->p.footprint_sigma;
+            a.share_floor = P->p.share_floor;
+            a.work = P->cfg.persistent ? G.work : nullptr;
+            a.xcd_remap = P->cfg.xcd_remap;
+            a.ccount = cb.compact ? G.ccount + 4 * (size_t)cb.t0 : nullptr;
+            a.report_floor = P->p.share_floor > 0.0f ? std::nextafter(P->p.share_floor, 0.0f) : 0.0f;
+            launch_composite_pass1(a, st);
+            launch_composite_pass2(a, false, nullptr, st);
+        }
     }
 }
 
@@ -1083,10 +1101,65 @@ void plan_free(gs_plan *P) {
         if (G.lists) hipFree(G.lists);
     }
     if (P->flag) hipFree(P->flag);
+    if (P->pool) hipFree(P->pool);
     if (P->cap) hipStreamDestroy(P->cap);
     delete P;
 }
 
+
+// Compositing launches of each group.  Pass 2 walks compacted lists when
+// they fit: scenes are taken in order into launches whose regions (4 x each
+// scene's list capacity) fit a pool of half the scratch budget left after the
+// plan's other buffers; a scene whose region alone exceeds it gets a launch
+// of its own without compaction, and so does every scene if the pool cannot
+// be allocated.  GS_COMPACT_POOL_GB replaces the pool's budget.  All forms
+// give the same sensitivities.
+void plan_batches(gs_plan *P) {
+    size_t pool_budget = scratch_budget() / 2;
+    if (const char *e = getenv("GS_COMPACT_POOL_GB")) pool_budget = (size_t)(atof(e) * (double)(1ull << 30));
+    auto region = [](const PlanScene &ps) { return (4 * ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255; };
+    std::vector<size_t> off(P->scenes.size(), 0);
+    size_t pool = 0;
+    for (PlanGroup &G : P->groups) {
+        G.batches.clear();
+        size_t used = 0;
+        for (int si : G.scenes) {
+            const PlanScene &ps = P->scenes[si];
+            const int t0 = ps.tile0, t1 = ps.tile0 + ps.c.total_tiles;
+            const size_t need = region(ps);
+            if (need > pool_budget) {
+                G.batches.push_back(CompositeBatch{t0, t1, false});
+                used = 0;
+                continue;
+            }
+            if (G.batches.empty() || !G.batches.back().compact || used + need > pool_budget) {
+                G.batches.push_back(CompositeBatch{t0, t1, true});
+                used = 0;
+            }
+            G.batches.back().t1 = t1;
+            off[si] = used;
+            used += need;
+            pool = std::max(pool, used);
+        }
+    }
+    if (pool > 0 && hipMalloc(&P->pool, pool) != hipSuccess) {
+        (void)hipGetLastError();
+        P->pool = nullptr;
+        for (PlanGroup &G : P->groups) {
+            G.batches.clear();
+            if (G.total_tiles > 0) G.batches.push_back(CompositeBatch{0, G.total_tiles, false});
+        }
+        return;
+    }
+    P->pool_bytes = P->pool ? pool : 0;
+    for (PlanGroup &G : P->groups)
+        for (const CompositeBatch &cb : G.batches)
+            for (int si : G.scenes) {
+                PlanScene &ps = P->scenes[si];
+                if (cb.compact && ps.tile0 >= cb.t0 && ps.tile0 + ps.c.total_tiles <= cb.t1 && ps.c.total_tiles > 0)
+                    ps.clist = (uint32_t *)((char *)P->pool + off[si]);
+            }
+}
 
 // Groups, buffers, tables and list capacities of a new plan.
 gs_status plan_allocate(gs_plan *P, hipStream_t st) {
@@ -1121,7 +1194,8 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
             G.total_tiles += ps.c.total_tiles;
         }
         const size_t table_bytes = sizeof(ViewDev) * G.total_views + 2 * sizeof(int32_t) * G.total_tiles +
-                                   sizeof(SceneSlot) * G.scenes.size() + 4096;
+                                   4 * sizeof(uint32_t) * G.total_tiles + sizeof(SceneSlot) * G.scenes.size() +
+                                   8192;
         if (hipMalloc(&G.buf, G.bytes + table_bytes + 65536) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GS_ERR_OUT_OF_MEMORY, "plan group %zu: %zu bytes", gi, G.bytes + table_bytes);
@@ -1133,6 +1207,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         G.tile_scene = cv.take<int32_t>(G.total_tiles);
         G.slots = cv.take<SceneSlot>(G.scenes.size());
         G.work = cv.take<uint32_t>(64);
+        G.ccount = cv.take<uint32_t>(4 * (size_t)G.total_tiles);
         auto &gv = group_views[gi];
         auto &gtv = group_tv[gi];
         auto &gts = group_ts[gi];
@@ -1175,6 +1250,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         }
 
     }
+    plan_batches(P);
     HIP_TRY(hipStreamSynchronize(st));
     return GS_OK;
 }
@@ -1284,7 +1360,13 @@ gs_status gs_plan_get_info(const gs_plan *plan, gs_plan_info *info) {
     info->n_groups = (int32_t)plan->groups.size();
     info->config = plan->cfg;
     info->graph_captured = plan->graph_ok;
-    for (const PlanGroup &G : plan->groups) info->device_bytes += (int64_t)(G.bytes + G.list_bytes);
+    for (const PlanGroup &G : plan->groups) {
+        info->device_bytes += (int64_t)(G.bytes + G.list_bytes);
+        info->n_launches += (int32_t)G.batches.size();
+        for (const CompositeBatch &cb : G.batches) info->n_compact_launches += cb.compact ? 1 : 0;
+    }
+    info->device_bytes += (int64_t)plan->pool_bytes;
+    info->compact_bytes = (int64_t)plan->pool_bytes;
     for (const PlanScene &ps : plan->scenes) info->list_capacity += (int64_t)ps.cap;
     return GS_OK;
 }
@@ -1309,7 +1391,8 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
             for (int si : G.scenes) {
                 PlanScene &ps = plan->scenes[si];
                 hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
-                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0});
+                                       (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0, nullptr, 0,
+                                       ps.clist});
             }
             HIP_TRY(hipMemcpyAsync(G.slots, hs.data(), sizeof(SceneSlot) * hs.size(), hipMemcpyHostToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));

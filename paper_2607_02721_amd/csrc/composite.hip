@@ -70,7 +70,7 @@ __device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.tot
 
 // Quadrant `logical` of the launch -> this wave's pixels, list range and scene.
 __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, WaveSetup &w) {
-    w.gt = logical >> 2;
+    w.gt = a.tile_first + (logical >> 2);
     w.quad = logical & 3;
     w.v = a.tile_view[w.gt];
     const SceneSlot &S = a.slots[a.tile_scene[w.gt]];

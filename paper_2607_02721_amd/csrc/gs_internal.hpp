@@ -156,7 +156,8 @@ struct CompositeArgs {
     const int32_t *tile_view;    // [total_tiles] view of each tile
     const int32_t *tile_scene;   // [total_tiles] scene slot of each tile
     const SceneSlot *slots;
-    int32_t total_tiles;
+    int32_t total_tiles;         // tiles of this launch
+    int32_t tile_first;          // launch tile t is tile tile_first + t of tile_view / tile_scene
     int32_t query_mode;
     float r2_log2;               // -0.5 log2(e) r^2  (cut on the exp2 argument)
     float share_floor;
@@ -165,7 +166,7 @@ struct CompositeArgs {
     int32_t agg;                 // query granularity (gs_aggregate) of pass 2
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
-    uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant (with SceneSlot::clist)
+    uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist)
     float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
 };
 // Fixed-point scale of the aggregated shares.  A Gaussian's accumulated share

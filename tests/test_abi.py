@@ -37,6 +37,35 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct (a field added on one side only
+    shows up here, without a GPU)."""
+    import shutil
+    import subprocess
+    from paper_2607_02721_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = {"gs_scene": _lib.Scene, "gs_views": _lib.Views, "gs_params": _lib.Params, "gs_stats": _lib.Stats,
+             "gs_plan_config": _lib.PlanConfig, "gs_plan_info": _lib.PlanInfo, "gs_peaks": _lib.Peaks,
+             "gs_render_diag": _lib.RenderDiag}
+    lines, want = [], []
+    for cname, py in pairs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(C.sizeof(py))
+        for f, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+            want.append(getattr(py, f).offset)
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gs_coreset.h"\nint main(void) {\n' +
+                   "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
+
+
 def test_library_has_no_oracle_dependency():
     from paper_2607_02721_amd import _lib
     data = open(_lib.LIB_PATH, "rb").read()

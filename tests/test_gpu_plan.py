@@ -65,6 +65,7 @@ def test_plan_matches_per_scene_calls(gs, batch, ref):
     info = plan.info()
     print("[plan]", info)
     assert info["n_scenes"] == 3 and info["n_groups"] == 1
+    assert info["n_launches"] == 1 and info["n_compact_launches"] == 1 and info["compact_bytes"] > 0
     plan.status()
     for k, (o, r) in enumerate(zip(outs, ref)):
         assert float(r.max()) > 0.0
@@ -181,4 +182,52 @@ def test_scenes_split_into_groups(gs, monkeypatch):
     ref = _reference(gs, batch)
     for o, r in zip(outs, ref):
         assert _same(o, r)
+    plan.close()
+
+
+def _expected_launches(regions, budget):
+    """Scenes in order into launches whose compacted regions fit the budget;
+    a scene larger than the budget alone, uncompacted: (launches, compacting)."""
+    launches, compact, used, last_compact = 0, 0, 0, False
+    for r in regions:
+        if r > budget:
+            launches, used, last_compact = launches + 1, 0, False
+            continue
+        if not last_compact or used + r > budget:
+            launches, compact, used, last_compact = launches + 1, compact + 1, 0, True
+        used += r
+    return launches, compact
+
+
+@pytest.mark.parametrize("pool", ["none", "smallest", "all"])
+def test_compaction_pool_splits_launches(gs, batch, ref, monkeypatch, pool):
+    """The compaction pool bounds which scenes composite together: no pool
+    (one launch per scene on the plain lists), a pool that holds only the
+    smallest scene's compacted lists (mixed launches), and one that holds all
+    three.  Every form gives the per-scene results bit for bit, in both
+    launch shapes."""
+    import torch
+    regions = []
+    for d, vw in batch:
+        n = gs.sensitivity(d, vw, stats=True)[1]["n_entries"]
+        cap = n + n // 64 + 1024
+        regions.append((16 * cap + 255) // 256 * 256)
+    budget = {"none": 0, "smallest": min(regions), "all": sum(regions)}[pool]
+    monkeypatch.setenv("GS_COMPACT_POOL_GB", repr(budget / 2**30))
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    monkeypatch.delenv("GS_COMPACT_POOL_GB")
+    info = plan.info()
+    want = _expected_launches(regions, budget)
+    print("[pool]", pool, regions, info, flush=True)
+    assert (info["n_launches"], info["n_compact_launches"]) == want
+    if pool == "none":
+        assert want == (3, 0) and info["compact_bytes"] == 0
+    if pool == "all":
+        assert want == (1, 1) and info["compact_bytes"] == sum(regions)
+    for persistent, xcd in ((0, 1), (1, 0)):
+        plan.set_config(persistent, xcd)
+        outs = plan.run()
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(outs, ref)):
+            assert _same(o, r), (pool, persistent, k)
     plan.close()
