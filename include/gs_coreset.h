@@ -129,7 +129,8 @@ typedef struct {
  * the stream once at its end and times each stage with HIP events on the
  * call's stream).  The pair counters need GS_FLAG_COUNT_PAIRS. */
 typedef struct {
-    int64_t n_projected;      /* (view, Gaussian) pairs in front of the camera and on screen */
+    int64_t n_projected;      /* (view, Gaussian) pairs in front of the camera and on screen (with a
+                                 ray mask: and meeting a 16x16 tile that holds a selected ray) */
     int64_t n_entries;        /* (tile, Gaussian) list entries */
     int64_t n_pairs;          /* pass-2 ray-Gaussian pairs inside the footprint on scored rays */
     int64_t n_live_pairs;     /* ... of which the ray still needed (T c_max >= floor A before the pair) */
@@ -187,9 +188,10 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
  * diag (nullable, host): validity violations and the log-transmittance gap
  *   (Definition 2, Assumption 1); the call synchronises the stream when set.
  * For GS_OBJ_FULL and GS_OBJ_FIXED a ray stops once T c_max w_max < 1e-9 A
- * (no later term can move A or A^th_w by more than 1e-9 A), so the A_w
- * column of per_view and the diagnostics are complete only for GS_OBJ_TRUE,
- * which walks every ray to its end. */
+ * (no later term can move A or A^th_w by more than 1e-9 A), and the reduced
+ * render is not computed: the A_w column of per_view is 0 and the
+ * diagnostics count nothing.  GS_OBJ_TRUE walks every ray to its end and
+ * fills all three columns and the diagnostics. */
 gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, const gs_params *params,
                               const double *weights, int32_t objective, float *per_ray,
                               double *per_view, gs_render_diag *diag, void *stream);

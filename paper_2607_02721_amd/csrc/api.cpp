@@ -138,6 +138,11 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(ViewDev) * c.vc);
     add(sizeof(int32_t) * c.total_tiles);
     add(c.total_tiles);                                     // tile activity
+    add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // active-tile tables ((tx+1)(ty+1) <= 4 tx ty)
+    add(sizeof(uint32_t) * (size_t)c.total_tiles);          // listed quadrants: per-tile counts,
+    add(sizeof(uint64_t) * ((size_t)c.total_tiles + 1));    // their scan,
+    add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
+    add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // and the list
     add(sizeof(int32_t) * c.total_tiles);                   // tile -> scene slot
     add(sizeof(SceneSlot) + 256);                           // slot + work counter
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
@@ -292,6 +297,8 @@ struct ChunkRun {
     double *view_A = nullptr;
     uint64_t *acc = nullptr;       // aggregated shares (fixed point); per list entry for tiles
     uint32_t *ccount = nullptr;    // entries pass 1 compacted per quadrant
+    uint32_t *quad_list = nullptr; // ray-masked runs: the quadrants holding a selected ray
+    int32_t n_listed = 0;
     int64_t n_entries = 0;
 };
 
@@ -328,6 +335,17 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
     b.tile_active = p->ray_mask ? cv.take<uint8_t>(c.total_tiles) : nullptr;
+    b.tile_sat = p->ray_mask ? cv.take<uint32_t>(4 * (size_t)c.total_tiles) : nullptr;
+    uint32_t *qcnt = nullptr;
+    uint64_t *qoff = nullptr, *qtmp = nullptr;
+    r.quad_list = nullptr;
+    r.n_listed = 0;
+    if (p->ray_mask) {
+        qcnt = cv.take<uint32_t>(c.total_tiles);
+        qoff = cv.take<uint64_t>((size_t)c.total_tiles + 1);
+        qtmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
+        r.quad_list = cv.take<uint32_t>(4 * (size_t)c.total_tiles);
+    }
     r.tile_scene = cv.take<int32_t>(c.total_tiles);
     r.slot_dev = cv.take<SceneSlot>(1);
     r.work = cv.take<uint32_t>(64);
@@ -343,7 +361,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
 
     hv.assign(c.vc, ViewDev{});
     htv.assign(c.total_tiles, 0);
-    int tb = 0;
+    int tb = 0, sb = 0;
     for (int k = 0; k < c.vc; ++k) {
         const int i = c.v0 + k;
         ViewDev &V = hv[k];
@@ -364,8 +382,17 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         V.ray_base = S.ray_base[i];
         V.ray_local = S.ray_base[i] - S.ray_base[c.v0];
         V.tile_base = tb;
+        V.sat_base = sb;
         for (int t = 0; t < V.tiles_x * V.tiles_y; ++t) htv[tb + t] = k;
         tb += V.tiles_x * V.tiles_y;
+        sb += (V.tiles_x + 1) * (V.tiles_y + 1);
+    }
+    int max_tiles = 1, max_tx = 1, max_ty = 1, max_cells = 1;
+    for (const ViewDev &V : hv) {
+        max_tiles = std::max(max_tiles, V.tiles_x * V.tiles_y);
+        max_cells = std::max(max_cells, (V.tiles_x + 1) * (V.tiles_y + 1));
+        max_tx = std::max(max_tx, V.tiles_x);
+        max_ty = std::max(max_ty, V.tiles_y);
     }
     HIP_TRY(hipMemcpyAsync(r.views_dev, hv.data(), sizeof(ViewDev) * c.vc, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(r.tile_view, htv.data(), sizeof(int32_t) * c.total_tiles, hipMemcpyHostToDevice, st));
@@ -376,6 +403,13 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
                 scene->quat, scene->opacity, scene->sh};
     ProjParams pp{p->footprint_sigma, p->dilation, p->z_near, p->query_mode};
+    // ray-masked runs: which tiles hold a selected ray, as per-view tables
+    // that projection uses to drop Gaussians meeting none of them
+    if (b.tile_active) {
+        launch_tile_active(r.views_dev, r.tile_view, c.total_tiles, p->ray_mask, b.tile_active, st);
+        launch_tile_sat(r.views_dev, c.vc, max_tx, max_ty, b.tile_active, b.tile_sat, st);
+        launch_quad_list(b.tile_active, c.total_tiles, qcnt, qoff, qtmp, r.quad_list, st);
+    }
     tm.mark(0, st);
     launch_project(sd, r.views_dev, c.vc, pp, b, st);
     HIP_TRY(hipGetLastError());
@@ -383,29 +417,37 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     // Three 8-bit passes suffice when every view's visible depth keys, less
     // the view's smallest, stay below 2^24 - 1 (depths within about a factor
     // of four: the float bits of a positive depth grow by 2^23 per octave).
-    std::vector<uint32_t> kr(2 * (size_t)c.vc);
+    std::vector<uint32_t> kr(2 * (size_t)c.vc), nv(c.vc);
     HIP_TRY(hipMemcpyAsync(kr.data(), b.kmin, sizeof(uint32_t) * 2 * c.vc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(nv.data(), b.nvis, sizeof(uint32_t) * c.vc, hipMemcpyDeviceToHost, st));
+    uint64_t n_listed = 0;
+    if (qoff)
+        HIP_TRY(hipMemcpyAsync(&n_listed, qoff + c.total_tiles, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    r.n_listed = (int32_t)n_listed;
     uint32_t span = 0;
     for (int k = 0; k < c.vc; ++k)
         if (kr[c.vc + k] >= kr[k]) span = std::max(span, kr[c.vc + k] - kr[k]);
     const int passes = span < 0xFFFFFFu ? 3 : 4;
     uint32_t *skeys = nullptr;
-    HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, passes,
-                                passes == 3 ? b.kmin : nullptr, &skeys, &r.sorted_g, st));
+    // When a quarter or more of the (view, Gaussian) pairs are dropped (ray
+    // masks, views that see little of the scene) the kept keys are moved to
+    // the front of each view's segment first and only they are sorted.
+    uint64_t kept = 0;
+    for (uint32_t x : nv) kept += x;
+    if (4 * kept <= 3 * (uint64_t)N * (uint64_t)c.vc) {
+        launch_key_compact(b, c.vc, N, b.key1, b.val1, st);
+        HIP_TRY(radix_sort_segments(b.key1, b.val1, b.key0, b.val0, b.hist, N, c.vc, false, passes,
+                                    passes == 3 ? b.kmin : nullptr, b.nvis, &skeys, &r.sorted_g, st));
+    } else {
+        HIP_TRY(radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, c.vc, true, passes,
+                                    passes == 3 ? b.kmin : nullptr, nullptr, &skeys, &r.sorted_g, st));
+    }
     tm.mark(2, st);
-    if (b.tile_active) launch_tile_active(r.views_dev, r.tile_view, c.total_tiles, p->ray_mask, b.tile_active, st);
     // the pair of sort buffers that does not hold the sorted output is free
     const bool out_in_0 = r.sorted_g == b.val0;
     uint32_t *xr = out_in_0 ? b.key1 : b.key0, *yr = out_in_0 ? b.val1 : b.val0;
     launch_ranges_in_order(r.sorted_g, b, c.vc, N, xr, yr, st);
-    int max_tiles = 1, max_tx = 1, max_ty = 1, max_cells = 1;
-    for (const ViewDev &V : hv) {
-        max_tiles = std::max(max_tiles, V.tiles_x * V.tiles_y);
-        max_cells = std::max(max_cells, (V.tiles_x + 1) * (V.tiles_y + 1));
-        max_tx = std::max(max_tx, V.tiles_x);
-        max_ty = std::max(max_ty, V.tiles_y);
-    }
     launch_bin_count(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, max_cells, st);
     launch_chunk_prefix(r.views_dev, c.vc, S.nchunks, b, max_tiles, st);
     scan_u32_to_u64_exclusive(b.tile_tot, b.tile_off, c.total_tiles, r.scan_tmp, st);
@@ -590,6 +632,12 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         n_bins += (int64_t)c.total_tiles * S.nchunks;
         CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor);
         a.ccount = r.host_slot.clist ? r.ccount : nullptr;
+        if (r.quad_list) {
+            // only the listed quadrants are composited: the other rays read A = 0
+            launch_fill_u32((uint32_t *)r.b.ray_A, 0u, (int64_t)c.rays * S.nq, st);
+            a.quad_list = r.quad_list;
+            a.n_listed = r.n_listed;
+        }
         tm.mark(3, st);
         launch_composite_pass1(a, st);
         HIP_TRY(hipGetLastError());
@@ -695,6 +743,12 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
             return s;
         CompositeArgs a = composite_args(r, c.total_tiles, params, 0.0f);
         ObjectiveArgs o{weights, objective, per_ray, r.tile_sums, nullptr, 1e-9f};
+        if (r.quad_list) {
+            // only the listed quadrants are rendered: the chunk's other rays read 0
+            if (per_ray) launch_fill_u32((uint32_t *)(per_ray + S.ray_base[c.v0]), 0u, (int64_t)c.rays, st);
+            a.quad_list = r.quad_list;
+            a.n_listed = r.n_listed;
+        }
         if (objective != GS_OBJ_TRUE) {
             // w_max (1 without weights) bounds every later fixed-objective term
             uint64_t *wmax = (uint64_t *)(r.view_sums + 3 * (size_t)c.vc);
@@ -1037,6 +1091,7 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.counters = cv.take<uint64_t>(CNT_WORDS);
     ps.over = cv.take<uint32_t>(64);
     b.tile_active = nullptr;
+    b.tile_sat = nullptr;
 }
 
 // Projection, depth sort and the count of the lists of one plan scene.
@@ -1051,8 +1106,8 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ProjParams pp{P->p.footprint_sigma, P->p.dilation, P->p.z_near, P->p.query_mode};
     launch_project(sd, ps.views_dev, ps.c.vc, pp, b, st);
     uint32_t *skeys = nullptr;
-    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, 4, nullptr, &skeys, &ps.sorted_g,
-                        st);
+    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, 4, nullptr, nullptr, &skeys,
+                        &ps.sorted_g, st);
     ps.xr = b.key1;
     ps.yr = b.val1;
     launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);

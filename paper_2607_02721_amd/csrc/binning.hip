@@ -218,6 +218,18 @@ __device__ __forceinline__ int wave_scan_max(int v) {
     return v;
 }
 
+// Bits >= s of a 64-bit word (s may be negative or past 63).
+__device__ __forceinline__ uint64_t bits_from(int s) {
+    return s >= 64 ? 0ull : (s <= 0 ? ~0ull : (~0ull << s));
+}
+
+// Whether the 128-bit set (lo, hi) holds any of the bits a..b (0 <= a <= b < 128).
+__device__ __forceinline__ bool range_hits(uint64_t lo, uint64_t hi, int a, int b) {
+    const uint64_t mlo = bits_from(a) & ~bits_from(b + 1);
+    const uint64_t mhi = bits_from(a - 64) & ~bits_from(b + 1 - 64);
+    return ((lo & mlo) | (hi & mhi)) != 0ull;
+}
+
 template <bool kMasked>
 __device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
     return !kMasked || ((act[t >> 5] >> (t & 31)) & 1u);
@@ -333,6 +345,16 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
         }
     }
     __syncthreads();
+    // masked form: the wave's active tiles as a 128-bit set (one tile row);
+    // a wave with none has nothing to emit
+    static_assert(!kMasked || (kEmitRows == 1 && kEmitCols <= 128), "one row of at most 128 tiles");
+    uint64_t act_lo = 0ull, act_hi = 0ull;
+    if (kMasked) {
+        const int nw = (ntiles + 31) / 32;
+        act_lo = (uint64_t)L.act[0] | (nw > 1 ? (uint64_t)L.act[1] << 32 : 0ull);
+        act_hi = (nw > 2 ? (uint64_t)L.act[2] : 0ull) | (nw > 3 ? (uint64_t)L.act[3] << 32 : 0ull);
+        if ((act_lo | act_hi) == 0ull) return;
+    }
     // entries at or past `room` would fall outside the list buffer
     const uint64_t room = cap > vlist ? cap - vlist : 0ull;
     uint32_t *__restrict__ vl = lists + vlist;
@@ -384,8 +406,12 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                 unpack_range(__uint_as_float(ux), xl, xh);
                 unpack_range(__uint_as_float(uy), yl, yh);
                 // the tiles of its rectangle inside this wave's rows and columns
+                // (masked form: none unless one of them is active)
                 const int kx = min(xh >> 4, c1 - 1) - max(xl >> 4, c0) + 1;
                 k = kx > 0 ? kx * (min(yh >> 4, r1 - 1) - max(yl >> 4, r0) + 1) : 0;
+                if (kMasked && k > 0 &&
+                    !range_hits(act_lo, act_hi, max(xl >> 4, c0) - c0, min(xh >> 4, c1 - 1) - c0))
+                    k = 0;
             }
             const int incl = wave_scan_add(k);
             const int K = __builtin_amdgcn_readlane(incl, kEmitWave - 1);
@@ -553,7 +579,9 @@ void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_
 }
 
 // A tile is active when at least one of its rays is selected by the ray mask;
-// inactive tiles get empty lists.  One wave per tile, 4 rays per lane.
+// inactive tiles get empty lists.  active[t] holds one bit per 8x8 quadrant
+// (bit q: quadrant q = (x >= 8) + 2 (y >= 8) holds a selected ray).  One wave
+// per tile, 4 rays per lane.
 __global__ __launch_bounds__(64) void k_tile_active(const ViewDev *__restrict__ views,
                                                     const int32_t *__restrict__ tile_view,
                                                     const uint32_t *__restrict__ mask, uint8_t *__restrict__ active) {
@@ -561,22 +589,93 @@ __global__ __launch_bounds__(64) void k_tile_active(const ViewDev *__restrict__ 
     const ViewDev &V = views[tile_view[gt]];
     const int tl = gt - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
+    // lane L covers row L / 4 of the tile, columns 4 (L % 4) .. 4 (L % 4) + 3,
+    // all inside one quadrant
+    const int rx = (threadIdx.x & 3) * 4, ry = threadIdx.x >> 2;
     bool any = false;
     for (int k = 0; k < 4; ++k) {
-        const int r = threadIdx.x * 4 + k;             // 0..255 inside the tile
-        const int px = tx * kTile + (r & 15), py = ty * kTile + (r >> 4);
+        const int px = tx * kTile + rx + k, py = ty * kTile + ry;
         if (px < V.W && py < V.H) {
             const int64_t ray = V.ray_base + (int64_t)py * V.W + px;
             any = any || ((mask[ray >> 5] >> (ray & 31)) & 1u);
         }
     }
-    const bool a = __any(any);
-    if (threadIdx.x == 0) active[gt] = a ? 1 : 0;
+    const int q = (rx >= kQuad ? 1 : 0) + (ry >= kQuad ? 2 : 0);
+    const uint8_t bits = (uint8_t)((__any(any && q == 0) ? 1 : 0) | (__any(any && q == 1) ? 2 : 0) |
+                                   (__any(any && q == 2) ? 4 : 0) | (__any(any && q == 3) ? 8 : 0));
+    if (threadIdx.x == 0) active[gt] = bits;
 }
 
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
                         uint8_t *active, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_active, dim3(total_tiles), dim3(64), 0, st, views_dev, tile_view, mask, active);
+}
+
+// Row y + 1 of view v's table: running counts of active tiles along tile row
+// y; row 0 is all zeros (written by the thread of row 0).
+__global__ __launch_bounds__(64) void k_tile_sat_rows(const ViewDev *__restrict__ views,
+                                                      const uint8_t *__restrict__ active, uint32_t *__restrict__ sat) {
+    const ViewDev &V = views[blockIdx.y];
+    const int ty = blockIdx.x * 64 + threadIdx.x;
+    if (ty >= V.tiles_y) return;
+    const int stride = V.tiles_x + 1;
+    uint32_t *S = sat + V.sat_base;
+    if (ty == 0)
+        for (int x = 0; x < stride; ++x) S[x] = 0u;
+    uint32_t *row = S + (int64_t)(ty + 1) * stride;
+    const uint8_t *a = active + V.tile_base + (int64_t)ty * V.tiles_x;
+    uint32_t run = 0;
+    row[0] = 0u;
+    for (int x = 0; x < V.tiles_x; ++x) {
+        run += a[x] ? 1u : 0u;
+        row[x + 1] = run;
+    }
+}
+
+// Column x of view v's table: running sums down the rows.
+__global__ __launch_bounds__(64) void k_tile_sat_cols(const ViewDev *__restrict__ views, uint32_t *__restrict__ sat) {
+    const ViewDev &V = views[blockIdx.y];
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int stride = V.tiles_x + 1;
+    if (x >= stride) return;
+    uint32_t *S = sat + V.sat_base;
+    uint32_t run = 0;
+    for (int y = 1; y <= V.tiles_y; ++y) {
+        run += S[(int64_t)y * stride + x];
+        S[(int64_t)y * stride + x] = run;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_quad_count(const uint8_t *__restrict__ active, int n,
+                                                    uint32_t *__restrict__ qcnt) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n) qcnt[t] = (uint32_t)__popc((unsigned)active[t]);
+}
+
+__global__ __launch_bounds__(256) void k_quad_write(const uint8_t *__restrict__ active, int n,
+                                                    const uint64_t *__restrict__ qoff, uint32_t *__restrict__ qlist) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const unsigned bits = active[t];
+    uint64_t o = qoff[t];
+    for (int q = 0; q < 4; ++q)
+        if ((bits >> q) & 1u) qlist[o++] = (uint32_t)(4 * t + q);
+}
+
+void launch_quad_list(const uint8_t *active, int total_tiles, uint32_t *qcnt, uint64_t *qoff, uint64_t *scan_tmp,
+                      uint32_t *qlist, hipStream_t st) {
+    const unsigned blocks = (unsigned)((total_tiles + 255) / 256);
+    hipLaunchKernelGGL(k_quad_count, dim3(blocks), dim3(256), 0, st, active, total_tiles, qcnt);
+    scan_u32_to_u64_exclusive(qcnt, qoff, total_tiles, scan_tmp, st);
+    hipLaunchKernelGGL(k_quad_write, dim3(blocks), dim3(256), 0, st, active, total_tiles, qoff, qlist);
+}
+
+void launch_tile_sat(const ViewDev *views_dev, int Vc, int max_tx, int max_ty, const uint8_t *active, uint32_t *sat,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_sat_rows, dim3((unsigned)((max_ty + 63) / 64), (unsigned)Vc), dim3(64), 0, st,
+                       views_dev, active, sat);
+    hipLaunchKernelGGL(k_tile_sat_cols, dim3((unsigned)((max_tx + 1 + 63) / 64), (unsigned)Vc), dim3(64), 0, st,
+                       views_dev, sat);
 }
 
 }  // namespace gs

@@ -120,6 +120,7 @@ __device__ __forceinline__ int next_quad(const CompositeArgs &a, int &iter) {
     const int nq = quad_count(a);
     if (!kPersistent) {
         if (iter++) return nq;
+        if (a.quad_list) return (int)blockIdx.x < a.n_listed ? (int)a.quad_list[blockIdx.x] : nq;
         if (!a.xcd_remap) return blockIdx.x;
         const int padded = (nq + 7) & ~7;
         return xcd_remap(blockIdx.x, padded);
@@ -127,7 +128,9 @@ __device__ __forceinline__ int next_quad(const CompositeArgs &a, int &iter) {
     int q = 0;
     if (threadIdx.x == 0) q = (int)atomicAdd(a.work, 1u);
     // lane 0's value, as a wave-uniform (scalar) quantity
-    return __builtin_amdgcn_readfirstlane(q);
+    q = __builtin_amdgcn_readfirstlane(q);
+    if (a.quad_list) return q < a.n_listed ? (int)a.quad_list[q] : nq;
+    return q;
 }
 
 __device__ __forceinline__ bool ray_selected(const uint32_t *mask, int64_t ray) {
@@ -616,7 +619,10 @@ static unsigned resident_waves(K kernel) {
     return (unsigned)std::max(1, cus) * (unsigned)std::max(1, per_cu);
 }
 
-static inline unsigned flat_grid(const CompositeArgs &a) { return (unsigned)(((a.total_tiles * 4) + 7) & ~7); }
+static inline unsigned flat_grid(const CompositeArgs &a) {
+    if (a.quad_list) return (unsigned)std::max(a.n_listed, 1);
+    return (unsigned)(((a.total_tiles * 4) + 7) & ~7);
+}
 
 template <int kMode>
 static void pass1_mode(const CompositeArgs &a, hipStream_t st) {
@@ -834,8 +840,9 @@ void launch_div_f64_to_f32(const double *num, const double *den, int64_t n, floa
 // |log T - log T_w| = |sum log(1 - rho_j) - log(1 - w_j rho_j)| at every
 // contributing retained pair (Assumption 1), on rays that stay valid.
 // kModeL2 replaces each contribution c rho T by c (rho T)^2 (and c rho T_w by
-// c (rho T_w)^2 in the reduced render).
-template <int kMode>
+// c (rho T_w)^2 in the reduced render).  kTrue: the reduced render and its
+// diagnostics are computed (the true objective); otherwise A_w reads 0.
+template <int kMode, bool kTrue>
 __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveArgs o,
                                                      uint64_t *__restrict__ counters) {
     static_assert(kMode != kModeChannel, "the objectives hold one query per ray");
@@ -882,7 +889,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
             if (has_w) {
                 const float wi = Cc.w;
                 Ax = fmaf(wi, aT, Ax);
-                if (wi > 0.0f) {
+                if (kTrue && wi > 0.0f) {
                     const float wr = wi * rho;
                     if (kMode == kModeL2) {
                         const float rtw = rho * Tw;
@@ -897,7 +904,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
                     }
                     if (!bad) gap += log1pf(-rho) - log1pf(-wr);
                     Tw = fmaf(-wr, Tw, Tw);
-                } else if (!bad) {
+                } else if (kTrue && !bad) {
                     gap += log1pf(-rho);
                 }
             }
@@ -934,10 +941,15 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
 
 // Always the flat form (a.work is ignored).
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st) {
-    if (composite_mode(a.query_mode) == kModeL2)
-        hipLaunchKernelGGL(k_objective<kModeL2>, dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
+    const bool l2 = composite_mode(a.query_mode) == kModeL2, tr = o.objective == 2;
+    if (l2 && tr)
+        hipLaunchKernelGGL((k_objective<kModeL2, true>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
+    else if (l2)
+        hipLaunchKernelGGL((k_objective<kModeL2, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
+    else if (tr)
+        hipLaunchKernelGGL((k_objective<kModeL1, true>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
     else
-        hipLaunchKernelGGL(k_objective<kModeL1>, dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
+        hipLaunchKernelGGL((k_objective<kModeL1, false>), dim3(flat_grid(a)), dim3(kWave), 0, st, a, o, counters);
 }
 
 // Largest value of a non-negative double array (as bits: monotone for x >= 0).

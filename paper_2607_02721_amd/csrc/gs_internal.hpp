@@ -32,7 +32,7 @@ struct ViewDev {
     int64_t ray_base;   // global index of the view's first ray
     int64_t ray_local;  // index of the view's first ray inside this chunk's ray buffers
     int32_t tile_base;  // first tile of this view inside the chunk
-    int32_t pad;
+    int32_t sat_base;   // first entry of this view's active-tile table (ray-masked runs)
 };
 
 struct SceneDev {
@@ -58,7 +58,7 @@ struct ChunkBufs {
     uint32_t *nvis;      // [Vc] visible Gaussians per view
     uint32_t *cmax;      // [Vc] largest query colour per view (float bits)
     uint32_t *kmin;      // [Vc] smallest visible depth key per view; kmax = kmin + Vc the largest
-    uint32_t *proj_part; // [Vc][projection blocks][4] per-block visible count, colour maximum, key minimum, maximum
+    uint32_t *proj_part; // [Vc][projection blocks][4] per-block kept count (then its exclusive offset), colour maximum, key minimum, maximum
     // per (tile, chunk) entry counts, chunk-major inside each view (view v at
     // tile_base(v) * nchunks, then [chunk][tile of v]); turned in place into
     // each tile's exclusive prefix over chunks
@@ -67,7 +67,12 @@ struct ChunkBufs {
     uint64_t *tile_off;  // exclusive scan of tile_tot (+1 trailing total): the tile's list
     uint32_t *lists;     // [D] entries
     float *ray_A;        // [queries per ray][rays in chunk] pass-1 render
-    uint8_t *tile_active; // [tiles in chunk] tiles holding a selected ray (null: all)
+    uint8_t *tile_active; // [tiles in chunk] bit q set: quadrant q of the tile holds a selected ray (null: all)
+    // Ray-masked runs: per view, (tiles_y + 1) x (tiles_x + 1) counts, entry
+    // (y, x) = active tiles with row < y and column < x, from sat_base on
+    // (null: no ray mask).  Projection drops (view, Gaussian) pairs whose tile
+    // rectangle holds no active tile: they can meet no selected ray.
+    uint32_t *tile_sat;
     uint64_t *counters;  // device statistics
 };
 
@@ -92,15 +97,28 @@ void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const 
 // `passes` 8-bit LSD passes (3 or 4).  With kbase non-null the first pass
 // subtracts kbase[seg] from every key but kInvisibleKey (the result must stay
 // below 2^(8 passes) - 1 for the visible keys, so that invisible keys still
-// sort last).
+// sort last).  seg_len (device, nullable): only the first seg_len[seg] items
+// of each segment are sorted (the rest are left alone).
 hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1,
                                uint32_t *hist, int64_t n_per_seg, int n_segs, bool vals_are_iota,
-                               int passes, const uint32_t *kbase, uint32_t **key_out, uint32_t **val_out,
-                               hipStream_t st);
+                               int passes, const uint32_t *kbase, const uint32_t *seg_len, uint32_t **key_out,
+                               uint32_t **val_out, hipStream_t st);
+// The kept depth keys of each view, moved to the front of the view's segment
+// of kout in index order with their Gaussian indices in vout (after
+// launch_project, whose per-block counts it turns into offsets).
+void launch_key_compact(const ChunkBufs &b, int Vc, int64_t N, uint32_t *kout, uint32_t *vout, hipStream_t st);
 void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
                             uint32_t *yr, hipStream_t st);
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
                         uint8_t *active, hipStream_t st);
+// The quadrants with a selected ray, in order: per-tile counts, their
+// exclusive scan (qoff[total_tiles] = the number listed) and the list.
+void launch_quad_list(const uint8_t *active, int total_tiles, uint32_t *qcnt, uint64_t *qoff, uint64_t *scan_tmp,
+                      uint32_t *qlist, hipStream_t st);
+// tile_sat from tile_active (two passes: along each tile row, then down each
+// column).  max_tx / max_ty: the largest tile grid of the chunk's views.
+void launch_tile_sat(const ViewDev *views_dev, int Vc, int max_tx, int max_ty, const uint8_t *active, uint32_t *sat,
+                     hipStream_t st);
 // max_cells: the largest (tiles_x + 1) (tiles_y + 1) of the views.
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                       const uint32_t *xr, const uint32_t *yr, int max_cells, hipStream_t st);
@@ -167,6 +185,8 @@ struct CompositeArgs {
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
     uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist)
+    const uint32_t *quad_list;   // ray-masked runs: the quadrants (4 tile + quadrant) holding a selected ray,
+    int32_t n_listed;            // in order; only these are composited (null: every quadrant)
     float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
 };
 // Fixed-point scale of the aggregated shares.  A Gaussian's accumulated share

@@ -104,7 +104,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                                                  ProjParams pp, float4 *__restrict__ R0,
                                                  float4 *__restrict__ R1, float4 *__restrict__ R2,
                                                  float4 *__restrict__ R3, uint32_t *__restrict__ keys,
-                                                 uint4 *__restrict__ part, uint64_t *__restrict__ counters) {
+                                                 uint4 *__restrict__ part, uint64_t *__restrict__ counters,
+                                                 const uint32_t *__restrict__ tile_sat) {
     __shared__ uint4 red[2][4];
     const int64_t n = sc.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
         const double py = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + V.t[1];
         const double pz = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + V.t[2];
         bool vis = valid && pz > (double)pp.z_near;
+        bool keep = false;   // visible and, in ray-masked runs, meeting a tile that holds a selected ray
         float4 r0 = make_float4(0, 0, 0, 0), r1 = make_float4(0, 0, 0, 0), r2 = make_float4(0, 0, 0, 0);
         float4 r3 = make_float4(0, 0, 0, 0);
         float cbar = 0.0f;
@@ -224,6 +226,15 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                 r3 = make_float4((float)c[0], (float)c[1], (float)c[2], 0.0f);
                 r2 = make_float4(cbar, __uint_as_float(pack_range((int)xl, (int)xh)),
                                  __uint_as_float(pack_range((int)yl, (int)yh)), (float)pz);
+                keep = true;
+                if (tile_sat) {
+                    // active tiles inside the tile rectangle [x0, x1) x [y0, y1)
+                    const uint32_t *S = tile_sat + V.sat_base;
+                    const int stride = V.tiles_x + 1;
+                    const int x0 = (int)xl >> 4, x1 = ((int)xh >> 4) + 1;
+                    const int y0 = ((int)yl >> 4) * stride, y1 = (((int)yh >> 4) + 1) * stride;
+                    keep = S[y1 + x1] - S[y0 + x1] - S[y1 + x0] + S[y0 + x0] != 0u;
+                }
             }
         }
         const int64_t o = (int64_t)v * n + gi;
@@ -232,7 +243,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
             R1[o] = r1;
             R2[o] = r2;
             if (R3) R3[o] = r3;
-            keys[o] = vis ? __float_as_uint((float)pz) : kInvisibleKey;
+            keys[o] = keep ? __float_as_uint((float)pz) : kInvisibleKey;
         }
         // per-view visible count and colour maximum of this wave, folded
         // over the waves by k_proj_reduce (one shared counter per view would
@@ -240,11 +251,14 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
         // (colours and depths are positive: their float bits order like them);
         // the block's four waves meet in LDS (two buffers, one barrier per
         // view) and thread 0 stores the block's values
-        const uint64_t bal = __ballot(vis);
+        // (the colour maximum bounds later contributions on a ray, so it
+        // covers every visible Gaussian, kept or not: a ray-masked run then
+        // stops its rays exactly where the unmasked run does)
+        const uint64_t bal = __ballot(keep);
         const uint32_t key = __float_as_uint((float)pz);
         const uint32_t cm = wave_max_u32(vis ? __float_as_uint(cbar) : 0u);
-        const uint32_t klo = wave_min_u32(vis ? key : 0xFFFFFFFFu);
-        const uint32_t khi = wave_max_u32(vis ? key : 0u);
+        const uint32_t klo = wave_min_u32(keep ? key : 0xFFFFFFFFu);
+        const uint32_t khi = wave_max_u32(keep ? key : 0u);
         const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) red[v & 1][wv] = make_uint4((uint32_t)__popcll(bal), cm, klo, khi);
         __syncthreads();
@@ -258,19 +272,40 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
 }
 
 // nvis[v] = sum, cmax[v] = maximum, kmin[v] / kmax[v] = smallest / largest
-// visible depth key of the per-block values of view v (one block per view).
-__global__ __launch_bounds__(256) void k_proj_reduce(const uint4 *__restrict__ part, int Vc, int64_t nblk,
+// kept depth key of the per-block values of view v (one block per view); each
+// block's count is replaced by the kept keys of the blocks before it (the
+// offsets launch_key_compact writes at).  Thread t takes a contiguous run of
+// blocks so that a block scan of the runs' sums gives those offsets.
+__global__ __launch_bounds__(256) void k_proj_reduce(uint4 *__restrict__ part, int Vc, int64_t nblk,
                                                      uint32_t *__restrict__ nvis, uint32_t *__restrict__ cmax_bits,
                                                      uint32_t *__restrict__ kmin) {
     __shared__ uint32_t sh[4][4];
+    __shared__ uint32_t pre[256];
     const int v = blockIdx.x;
+    const int64_t per = (nblk + 255) / 256;
+    const int64_t lo = (int64_t)threadIdx.x * per, hi = min(lo + per, nblk);
+    uint4 *pv = part + (int64_t)v * nblk;
     uint32_t cnt = 0, cm = 0, klo = 0xFFFFFFFFu, khi = 0;
-    for (int64_t w = threadIdx.x; w < nblk; w += 256) {
-        const uint4 q = part[(int64_t)v * nblk + w];
+    for (int64_t w = lo; w < hi; ++w) {
+        const uint4 q = pv[w];
         cnt += q.x;
         cm = max(cm, q.y);
         klo = min(klo, q.z);
         khi = max(khi, q.w);
+    }
+    pre[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t x = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
+        __syncthreads();
+        pre[threadIdx.x] += x;
+        __syncthreads();
+    }
+    uint32_t run = pre[threadIdx.x] - cnt;
+    for (int64_t w = lo; w < hi; ++w) {
+        const uint32_t c = pv[w].x;
+        pv[w].x = run;
+        run += c;
     }
     for (int off = 32; off > 0; off >>= 1) {
         cnt += __shfl_xor(cnt, off);
@@ -298,9 +333,40 @@ static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const
                      hipStream_t st) {
     const int64_t blocks = (sc.n + 255) / 256;
     hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0,
-                       b.R1, b.R2, b.R3, b.key0, (uint4 *)b.proj_part, b.counters);
-    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (const uint4 *)b.proj_part, Vc,
-                       blocks, b.nvis, b.cmax, b.kmin);
+                       b.R1, b.R2, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
+    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (uint4 *)b.proj_part, Vc, blocks,
+                       b.nvis, b.cmax, b.kmin);
+}
+
+// Block (g, v) moves the kept keys of Gaussians [256 g, 256 g + 256) of view
+// v to their place after the kept keys of the blocks before it (the offsets
+// k_proj_reduce left), in index order.
+__global__ __launch_bounds__(256) void k_key_compact(const uint32_t *__restrict__ keys, const uint4 *__restrict__ part,
+                                                     int64_t N, int64_t nblk, uint32_t *__restrict__ kout,
+                                                     uint32_t *__restrict__ vout) {
+    __shared__ uint32_t wsum[4];
+    const int v = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t key = i < N ? keys[(int64_t)v * N + i] : kInvisibleKey;
+    const bool keep = key != kInvisibleKey;
+    const uint64_t bal = __ballot(keep);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t below = (uint32_t)__popcll(bal & (lane ? (~0ull >> (64 - lane)) : 0ull));
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = part[(int64_t)v * nblk + blockIdx.x].x;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    if (keep) {
+        const int64_t dst = (int64_t)v * N + before + below;
+        kout[dst] = key;
+        vout[dst] = (uint32_t)i;
+    }
+}
+
+void launch_key_compact(const ChunkBufs &b, int Vc, int64_t N, uint32_t *kout, uint32_t *vout, hipStream_t st) {
+    const int64_t blocks = proj_blocks(N);
+    hipLaunchKernelGGL(k_key_compact, dim3((unsigned)blocks, (unsigned)Vc), dim3(256), 0, st, b.key0,
+                       (const uint4 *)b.proj_part, N, blocks, kout, vout);
 }
 
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,

@@ -42,15 +42,17 @@ __device__ __forceinline__ uint32_t rebase(uint32_t k, const uint32_t *kbase, in
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_per_seg,
                                                               int nb, int shift, uint32_t *__restrict__ hist,
-                                                              const uint32_t *__restrict__ kbase) {
+                                                              const uint32_t *__restrict__ kbase,
+                                                              const uint32_t *__restrict__ seg_len) {
     __shared__ uint32_t cnt[4][256];
     const int seg = blockIdx.y, b = blockIdx.x;
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)seg * n_per_seg;
+    const int64_t len = seg_len ? (int64_t)seg_len[seg] : n_per_seg;
     const int64_t lo = (int64_t)b * kSortTile;
-    const int64_t hi = min(lo + (int64_t)kSortTile, n_per_seg);
+    const int64_t hi = min(lo + (int64_t)kSortTile, len);
     for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) {
         const uint32_t d = (rebase(keys[base + i], kbase, seg) >> shift) & 255u;
         atomicAdd(&cnt[w][d], 1u);
@@ -93,7 +95,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                  uint32_t *__restrict__ vout, int64_t n_per_seg,
                                                                  int nb, int shift, int vals_are_iota,
                                                                  const uint32_t *__restrict__ offs,
-                                                                 const uint32_t *__restrict__ kbase) {
+                                                                 const uint32_t *__restrict__ kbase,
+                                                                 const uint32_t *__restrict__ seg_len) {
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t wbase[4][256];   // block-local start of each wave's run of each digit
     __shared__ uint32_t dstart[256];     // block-local start of each digit
@@ -101,6 +104,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     __shared__ uint32_t lkey[kSortTile], lval[kSortTile];
     const int seg = blockIdx.y, b = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // items of the segment to sort (the whole block leaves if it holds none)
+    const int64_t len = seg_len ? (int64_t)seg_len[seg] : n_per_seg;
+    if ((int64_t)b * kSortTile >= len) return;
     for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)seg * n_per_seg;
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 #pragma unroll
     for (int k = 0; k < kSortRounds; ++k) {
         const int64_t i = wlo + k * 64 + lane;
-        const bool ok = i < n_per_seg;
+        const bool ok = i < len;
         key[k] = ok ? rebase(kin[base + i], kbase, seg) : 0u;
         val[k] = ok ? (vals_are_iota ? (uint32_t)i : vin[base + i]) : 0u;
         const uint32_t d = (key[k] >> shift) & 255u;
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 #pragma unroll
     for (int k = 0; k < kSortRounds; ++k) {
         const int64_t i = wlo + k * 64 + lane;
-        if (i < n_per_seg) {
+        if (i < len) {
             const uint32_t d = (key[k] >> shift) & 255u;
             const uint32_t pos = wbase[w][d] + rank[k];
             lkey[pos] = key[k];
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     }
     {
         const int64_t lo = (int64_t)b * kSortTile;
-        nvalid = (int)min((int64_t)kSortTile, n_per_seg - lo);
+        nvalid = (int)min((int64_t)kSortTile, len - lo);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nvalid; i += kSortThreads) {
@@ -176,17 +182,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 
 hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1, uint32_t *hist,
                                int64_t n_per_seg, int n_segs, bool vals_are_iota, int passes,
-                               const uint32_t *kbase, uint32_t **key_out, uint32_t **val_out, hipStream_t st) {
+                               const uint32_t *kbase, const uint32_t *seg_len, uint32_t **key_out,
+                               uint32_t **val_out, hipStream_t st) {
     const int nb = (int)((n_per_seg + kSortTile - 1) / kSortTile);
     uint32_t *ki = key0, *vi = val0, *ko = key1, *vo = val1;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         const uint32_t *kb = pass == 0 ? kbase : nullptr;
         hipLaunchKernelGGL(k_radix_hist, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, n_per_seg, nb, shift,
-                           hist, kb);
+                           hist, kb, seg_len);
         hipLaunchKernelGGL(k_radix_offsets, dim3(n_segs), dim3(1024), 0, st, hist, nb);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_per_seg,
-                           nb, shift, (pass == 0 && vals_are_iota) ? 1 : 0, hist, kb);
+                           nb, shift, (pass == 0 && vals_are_iota) ? 1 : 0, hist, kb, seg_len);
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
