@@ -48,6 +48,9 @@ struct Arena {
 };
 constexpr int kMaxDevices = 16;
 Arena g_work[kMaxDevices], g_lists[kMaxDevices], g_agg[kMaxDevices], g_compact[kMaxDevices];
+// Device statistics of a call, at one address for all of its view chunks
+// (the work arena is carved differently per chunk and may be reallocated).
+Arena g_cnt[kMaxDevices];
 // Recorded at the end of every call on the call's stream; the next call waits
 // for it on its own stream, so the shared arenas are never used by two
 // streams at once.
@@ -331,7 +334,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
     r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
     b.ray_A = cv.take<float>((size_t)c.rays * S.nq);
-    b.counters = cv.take<uint64_t>(CNT_WORDS);
+    HIP_TRY(arena_reserve(g_cnt[dev], sizeof(uint64_t) * CNT_WORDS));
+    b.counters = (uint64_t *)g_cnt[dev].base;
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
     b.tile_active = p->ray_mask ? cv.take<uint8_t>(c.total_tiles) : nullptr;
@@ -398,7 +402,11 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(hipMemcpyAsync(r.tile_view, htv.data(), sizeof(int32_t) * c.total_tiles, hipMemcpyHostToDevice, st));
     launch_fill_u32(b.nvis, 0u, 2 * (int64_t)c.vc, st);
     launch_fill_u32(b.bin_count, 0u, nbins, st);
-    if (zero_counters) launch_fill_u64(b.counters, 0ull, CNT_WORDS, st);
+    // every chunk projects every Gaussian, so the invalid count restarts per chunk
+    if (zero_counters)
+        launch_fill_u64(b.counters, 0ull, CNT_WORDS, st);
+    else
+        launch_fill_u64(b.counters + CNT_INVALID, 0ull, 1, st);
 
     SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
                 scene->quat, scene->opacity, scene->sh};
@@ -574,7 +582,7 @@ gs_status gs_release_workspace(void) {
     const int dev = current_device(&s);
     if (dev < 0) return s;
     HIP_TRY(hipDeviceSynchronize());
-    for (Arena *a : {&g_work[dev], &g_lists[dev], &g_agg[dev], &g_compact[dev]}) {
+    for (Arena *a : {&g_work[dev], &g_lists[dev], &g_agg[dev], &g_compact[dev], &g_cnt[dev]}) {
         if (a->base) hipFree(a->base);
         a->base = nullptr;
         a->cap = 0;

@@ -104,6 +104,31 @@ def test_determinism_and_chunking(gs):
     assert np.array_equal(a, c)
 
 
+def test_stats_over_view_chunks(gs):
+    """Counters are summed over view chunks of different sizes (3 views in
+    chunks of 2 and 1), equal those of one chunk, and stay right on repeated
+    calls; a non-finite Gaussian is counted once however many chunks there are."""
+    import re
+    import torch
+    sc, vw = _ragged()
+    dsc = gs.DeviceScene.from_scene(sc)
+    _, one = gs.sensitivity(dsc, vw, stats=True, count_pairs=True)
+    keys = ("n_projected", "n_entries", "n_pairs", "n_live_pairs", "n_rays_positive", "n_lane_pairs",
+            "n_invalid_gaussians")
+    for _ in range(3):
+        # leave unrelated values in the work arena between the calls
+        gs.sensitivity(dsc, vw, max_views_per_chunk=1)
+        _, two = gs.sensitivity(dsc, vw, stats=True, count_pairs=True, max_views_per_chunk=2)
+        torch.cuda.synchronize()
+        assert {k: two[k] for k in keys} == {k: one[k] for k in keys}
+    bad = synth.Scene(sc.mean.copy(), sc.log_scale, sc.quat, sc.opacity, sc.sh, sc.sh_degree)
+    bad.mean[0, 17] = np.nan
+    with pytest.raises(gs.GsError) as e:
+        gs.sensitivity(gs.DeviceScene.from_scene(bad), vw, stats=True, max_views_per_chunk=1)
+    assert e.value.status == 5
+    assert re.search(r"\b1 Gaussians have non-finite", str(e.value)), str(e.value)
+
+
 def test_render_full_matches_oracle(gs, ora):
     sc, vw = _ragged()
     ref = ora.sensitivity(sc, vw)
