@@ -188,3 +188,84 @@ def test_mixture_and_targets_match_numpy(gs, L):
     t = L.log_targets(s.cuda()).cpu().numpy()
     ref = np.log(np.maximum(s.double().numpy(), np.float32(L.LOG_FLOOR).astype(np.float64))).astype(np.float32)
     assert np.array_equal(t, ref)
+
+
+def test_learned_workload_full_size(gs, L, ora, trained):
+    """The learned-proposal workload at full size: a held-out scene of
+    5 000 000 Gaussians seen from 300 views at 1280x720.  Checked on samples
+    the CPU references can afford: kNN features of 2 000 Gaussians against a
+    k-d tree over all 5M means, the MLP on 4 096 rows against the FP64
+    reference, the mixture's normalisation and floor, the exact pass (the
+    fallback) and the fixed objective the judge evaluates on three 64x64
+    blocks against the FP64 oracle (with w = 1 the fixed objective is A).
+    The judge runs on 1% of the 8x8 blocks of all 300 views; when it sends
+    the draw to the fallback, the weights must equal the exact pass's draw."""
+    import time
+    import torch
+    from scipy.spatial import cKDTree
+    from oracle import mlp_ref
+    prop, _ = trained
+    sc = synth.make_cluster_scene(5_000_000, 4200, 3)
+    vw = synth.make_orbit_views(300, 4201)
+    d = gs.DeviceScene.from_scene(sc)
+    feat = L.features(d)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+
+    # kNN features on a sample, against a k-d tree over every mean
+    pts = sc.mean.T.astype(np.float64)
+    qi = rng.choice(sc.n, 2000, replace=False)
+    dist, idx = cKDTree(pts).query(pts[qi], k=17)
+    dist, idx = dist[:, 1:], idx[:, 1:]
+    f = feat[torch.as_tensor(qi).cuda()].double().cpu().numpy()
+    assert np.allclose(f[:, 59], np.log(dist.mean(1)), atol=1e-4)
+    assert np.allclose(f[:, 60], np.log(dist[:, -1]), atol=1e-4)
+    ok = np.abs(f[:, 61] - sc.opacity.astype(np.float64)[idx].mean(1)) < 1e-5
+    assert ok.mean() > 0.995
+    print(f"[learned5m] kNN features agree on {ok.mean():.4f} of 2000 sampled Gaussians", flush=True)
+
+    # MLP forward on sampled rows
+    rows = torch.as_tensor(rng.choice(sc.n, 4096, replace=False)).cuda()
+    got = prop.predict(feat[rows].contiguous()).double().cpu().numpy()
+    P, X = _ref_inputs(prop, feat[rows].contiguous())
+    want = mlp_ref.forward(P, X)[0]
+    assert np.abs(got - want).max() <= 2e-2 * max(want.std(), 1e-3) + 1e-3
+
+    # proposal: a distribution with the uniform floor
+    scores = L.mixture(prop.predict(feat))
+    ps = scores.double()
+    assert abs(float(ps.sum()) - 1.0) < 1e-4 and float(ps.min()) >= 0.1 / sc.n * (1 - 1e-5)
+
+    # draw, judge on 1% of the 8x8 blocks, fall back to the exact pass when E > 1%
+    judge = torch.as_tensor(synth.block_subsample_mask(vw, 4202).view(np.int32)).cuda()
+    m = sc.n // 10
+    out = L.sample_with_fallback(d, vw, m, 0, prop, judge, feat=feat)
+    print(f"[learned5m] E learned {out['E_learned']:.4f}, propose {out['ms_propose']:.1f} ms, judge "
+          f"{out['ms_judge']:.1f} ms, fallback {out['fallback']}", flush=True)
+    if out["fallback"]:
+        s, _ = gs.sensitivity(d, vw)
+        _, w_exact, _ = gs.sample_coreset(s, m, 0)
+        assert torch.equal(out["weights"], w_exact)
+        print(f"[learned5m] exact fallback E {out['E_exact']:.4f} in {out['ms_fallback']:.1f} ms", flush=True)
+
+    # the exact pass and the fixed objective against the oracle on three blocks
+    W, H = 1280, 720
+    keep = np.zeros(vw.n_rays, bool)
+    for v, (x0, y0) in ((0, (608, 328)), (150, (0, 0)), (299, (1216, 656))):
+        for y in range(y0, y0 + 64):
+            keep[v * W * H + y * W + x0: v * W * H + y * W + x0 + 64] = True
+    params = ora.default_params()
+    t0 = time.perf_counter()
+    keep &= ~ora.sensitivity(sc, vw, params, synth.pack_bits(keep))["flag"]
+    ref = ora.sensitivity(sc, vw, params, synth.pack_bits(keep))
+    print(f"[learned5m] oracle on {int(keep.sum())} rays in {time.perf_counter() - t0:.1f} s", flush=True)
+    mask = torch.as_tensor(synth.pack_bits(keep).view(np.int32)).cuda()
+    s_m, _ = gs.sensitivity(d, vw, ray_mask=mask)
+    s_m = s_m.double().cpu().numpy()
+    excess = np.abs(s_m - ref["s"]) - (1e-5 * ref["s"] + 1e-12)
+    assert excess.max() <= 0, int(np.argmax(excess))
+    ones = torch.ones(sc.n, dtype=torch.float64, device="cuda")
+    ob = gs.render_objective(d, vw, ones, gs.OBJ_FIXED, ray_mask=mask, per_view=False, diag=False)
+    A_gpu = ob["per_ray"][torch.as_tensor(np.flatnonzero(keep)).cuda()].double().cpu().numpy()
+    A_ref = ref["A"][keep]
+    assert np.all(np.abs(A_gpu - A_ref) <= 1e-5 * A_ref + 1e-30)
