@@ -140,7 +140,7 @@ typedef struct {
     double total_sensitivity; /* S = sum_i s_i, fixed-order reduction */
     double ms_project, ms_sort, ms_bin, ms_pass1, ms_pass2; /* device time per stage, summed over chunks */
     double ms_emit;           /* the tile-list emission kernel alone (part of ms_bin) */
-    int64_t n_bins;           /* (tile, chunk) segments: tiles x chunks of 2048 depth positions */
+    int64_t n_bins;           /* (tile, chunk) segments: tiles x chunks of 16384 depth positions */
 } gs_stats;
 
 typedef struct {
@@ -158,7 +158,12 @@ typedef struct {
  * size the tile lists).  stats may be NULL.  params->aggregate selects the
  * query granularity (gs_aggregate); aggregated sums are accumulated in exact
  * 64-bit fixed point, so every granularity is deterministic.  The pair
- * counters (GS_FLAG_COUNT_PAIRS) need GS_AGG_RAY. */
+ * counters (GS_FLAG_COUNT_PAIRS) need GS_AGG_RAY.  Per-ray queries: pass 1
+ * leaves each 8x8 quadrant's culled list for pass 2 in a device room of up
+ * to 4 x the list bytes, at most half of the free memory (the environment
+ * variable GS_COMPACT_POOL_GB, in GiB, replaces that bound; 0 turns the room
+ * off); when the room holds only part of the lists, the tiles are
+ * composited in ranges that fit.  The results do not depend on the room. */
 gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_params *params,
                          float *sens, gs_stats *stats, void *stream);
 

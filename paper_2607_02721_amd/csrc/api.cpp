@@ -120,6 +120,9 @@ struct Setup {
     std::vector<int64_t> ray_base;
 };
 
+// Compaction ranges are cut at every ceil(tiles / kRangeSamples)-th tile.
+constexpr int64_t kRangeSamples = 4096;
+
 size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     const int64_t N = S.N;
     const int64_t nb = (N + kSortTile - 1) / kSortTile;
@@ -146,6 +149,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint64_t) * ((size_t)c.total_tiles + 1));    // their scan,
     add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
     add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // and the list
+    add(sizeof(uint64_t) * (kRangeSamples + 2));            // sampled tile offsets (compaction ranges)
     add(sizeof(int32_t) * c.total_tiles);                   // tile -> scene slot
     add(sizeof(SceneSlot) + 256);                           // slot + work counter
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
@@ -303,6 +307,14 @@ struct ChunkRun {
     uint32_t *quad_list = nullptr; // ray-masked runs: the quadrants holding a selected ray
     int32_t n_listed = 0;
     int64_t n_entries = 0;
+    // Compositing launches: tiles [t0, t1) whose compacted lists start at
+    // list entry `first` (their pool offsets are 4 (entry - first)).  One
+    // range over every tile unless the compacted lists only fit in pieces.
+    struct Range {
+        int t0, t1;
+        uint64_t first;
+    };
+    std::vector<Range> ranges;
 };
 
 gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_params *p, const Setup &S,
@@ -350,6 +362,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         qtmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
         r.quad_list = cv.take<uint32_t>(4 * (size_t)c.total_tiles);
     }
+    uint64_t *off_samples = cv.take<uint64_t>(kRangeSamples + 2);
     r.tile_scene = cv.take<int32_t>(c.total_tiles);
     r.slot_dev = cv.take<SceneSlot>(1);
     r.work = cv.take<uint32_t>(64);
@@ -472,7 +485,10 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     if (S.agg == GS_AGG_TILE) r.acc = (uint64_t *)((char *)g_lists[dev].base + list_bytes);
     // room for the quadrants' compacted lists (4 x the lists), if it fits in
     // half of the free memory; without it pass 2 filters the tile lists again
+    // (when only part fits, the tiles are cut into ranges whose compacted
+    // lists fit, composited one range after another through the same room)
     uint32_t *clist = nullptr;
+    r.ranges.assign(1, ChunkRun::Range{0, c.total_tiles, 0});
     if (S.compact) {
         const size_t cbytes = 4 * std::max<size_t>(total, 1) * sizeof(uint32_t);
         size_t free_b = 0, total_b = 0;
@@ -481,11 +497,41 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
             free_b = 0;
         }
         const size_t held = g_compact[dev].cap;
-        if (cbytes <= held || cbytes <= (free_b + held) / 2) {
+        size_t avail = std::max(held, (free_b + held) / 2);
+        if (const char *e = getenv("GS_COMPACT_POOL_GB")) avail = (size_t)(atof(e) * (double)(1ull << 30));
+        if (avail == 0) {
+            // no room: pass 2 filters the tile lists itself
+        } else if (cbytes <= avail) {
             if (arena_reserve(g_compact[dev], cbytes) == hipSuccess)
                 clist = (uint32_t *)g_compact[dev].base;
             else
                 (void)hipGetLastError();
+        } else if (!r.quad_list) {
+            // list offsets at every G-th tile: ranges are cut there
+            const int64_t T = c.total_tiles;
+            const int64_t G = (T + kRangeSamples - 1) / kRangeSamples;
+            const int64_t K = (T + G - 1) / G;                      // blocks of G tiles
+            std::vector<uint64_t> off((size_t)K + 1);
+            launch_gather_u64(off_samples, b.tile_off, T, G, st);
+            HIP_TRY(hipMemcpyAsync(off.data(), off_samples, sizeof(uint64_t) * off.size(), hipMemcpyDeviceToHost,
+                                   st));
+            HIP_TRY(hipStreamSynchronize(st));
+            const uint64_t room = avail / (4 * sizeof(uint32_t));   // list entries whose compacted lists fit
+            uint64_t longest = 0;
+            for (int64_t k = 0; k < K; ++k) longest = std::max(longest, off[k + 1] - off[k]);
+            if (longest <= room && arena_reserve(g_compact[dev], avail) == hipSuccess) {
+                clist = (uint32_t *)g_compact[dev].base;
+                r.ranges.clear();
+                int64_t k0 = 0;
+                for (int64_t k = 0; k < K; ++k)
+                    if (off[k + 1] - off[k0] > room) {
+                        r.ranges.push_back(ChunkRun::Range{(int)(k0 * G), (int)(k * G), off[k0]});
+                        k0 = k;
+                    }
+                r.ranges.push_back(ChunkRun::Range{(int)(k0 * G), (int)T, off[k0]});
+            } else {
+                (void)hipGetLastError();
+            }
         }
     }
     tm.mark(6, st);
@@ -645,6 +691,45 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
             launch_fill_u32((uint32_t *)r.b.ray_A, 0u, (int64_t)c.rays * S.nq, st);
             a.quad_list = r.quad_list;
             a.n_listed = r.n_listed;
+        }
+        if (r.ranges.size() > 1) {
+            // per-ray queries through a compaction room that holds part of
+            // the chunk's lists: pass 1 and pass 2 of one tile range after
+            // another (each pass 2 reads what its pass 1 left in the room)
+            std::vector<hipEvent_t> ev(tm.on ? 3 * r.ranges.size() : 0);
+            for (hipEvent_t &e : ev) HIP_TRY(hipEventCreate(&e));
+            for (size_t k = 0; k < r.ranges.size(); ++k) {
+                const ChunkRun::Range &g = r.ranges[k];
+                CompositeArgs ar = a;
+                ar.tile_first = g.t0;
+                ar.total_tiles = g.t1 - g.t0;
+                ar.ccount = r.ccount + 4 * (size_t)g.t0;
+                ar.clist_shift = 4 * g.first;
+                if (tm.on) HIP_TRY(hipEventRecord(ev[3 * k], st));
+                launch_composite_pass1(ar, st);
+                if (tm.on) HIP_TRY(hipEventRecord(ev[3 * k + 1], st));
+                launch_composite_pass2(ar, (params->flags & GS_FLAG_COUNT_PAIRS) != 0, r.b.counters, st);
+                if (tm.on) HIP_TRY(hipEventRecord(ev[3 * k + 2], st));
+                HIP_TRY(hipGetLastError());
+            }
+            if (tm.on) {
+                HIP_TRY(hipEventSynchronize(ev.back()));
+                for (size_t k = 0; k < r.ranges.size(); ++k) {
+                    float t1 = 0.0f, t2 = 0.0f;
+                    hipEventElapsedTime(&t1, ev[3 * k], ev[3 * k + 1]);
+                    hipEventElapsedTime(&t2, ev[3 * k + 1], ev[3 * k + 2]);
+                    ms[3] += t1;
+                    ms[4] += t2;
+                }
+            }
+            for (hipEvent_t &e : ev) hipEventDestroy(e);
+            if (stats) {
+                std::vector<uint32_t> nv(c.vc);
+                HIP_TRY(hipMemcpyAsync(nv.data(), r.b.nvis, sizeof(uint32_t) * c.vc, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                for (uint32_t x : nv) projected += x;
+            }
+            continue;
         }
         tm.mark(3, st);
         launch_composite_pass1(a, st);

@@ -106,7 +106,7 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.R3 = S.R3;
     w.ray_stride = S.ray_stride;
     w.clist = S.clist;
-    w.cbase = 4 * w.start + (uint64_t)w.quad * (w.end - w.start);
+    w.cbase = 4 * w.start + (uint64_t)w.quad * (w.end - w.start) - a.clist_shift;
     w.sfloor = a.report_floor;
     return true;
 }

@@ -185,6 +185,8 @@ struct CompositeArgs {
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
     uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist)
+    uint64_t clist_shift;        // subtracted from every compacted-list offset (launches over a tile range
+                                 // whose compacted lists fill a pool from its start)
     const uint32_t *quad_list;   // ray-masked runs: the quadrants (4 tile + quadrant) holding a selected ray,
     int32_t n_listed;            // in order; only these are composited (null: every quadrant)
     float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
@@ -250,6 +252,8 @@ hipError_t measure_peaks(double *copy_bytes_per_s, double *fma_per_s, double *ex
 // Small utilities
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+// dst[k] = src[min(k stride, n)] for k = 0 .. ceil(n / stride) (dst holds that many + 1).
+void launch_gather_u64(uint64_t *dst, const uint64_t *src, int64_t n, int64_t stride, hipStream_t st);
 void launch_copy_u64(uint64_t *dst, const uint64_t *src, int64_t n, hipStream_t st);
 void launch_sum_f32_to_f64(const float *x, int64_t n, double *out, double *block_tmp, hipStream_t st);
 

@@ -331,6 +331,16 @@ void launch_copy_u64(uint64_t *dst, const uint64_t *src, int64_t n, hipStream_t 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_copy_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
 }
+// dst[k] = src[min(k stride, n)] for k = 0 .. ceil(n / stride).
+__global__ void k_gather_u64(uint64_t *dst, const uint64_t *src, int64_t n, int64_t stride, int64_t count) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) dst[k] = src[min(k * stride, n)];
+}
+void launch_gather_u64(uint64_t *dst, const uint64_t *src, int64_t n, int64_t stride, hipStream_t st) {
+    const int64_t count = (n + stride - 1) / stride + 1;
+    hipLaunchKernelGGL(k_gather_u64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, dst, src, n, stride,
+                       count);
+}
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return;
     const int64_t blocks = min((n + 255) / 256, (int64_t)65536);

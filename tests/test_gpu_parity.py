@@ -129,6 +129,28 @@ def test_stats_over_view_chunks(gs):
     assert re.search(r"\b1 Gaussians have non-finite", str(e.value)), str(e.value)
 
 
+@pytest.mark.parametrize("room", ["none", "quarter", "tenth"])
+def test_compaction_room_in_ranges(gs, monkeypatch, room):
+    """Pass 2 reads the quadrant lists pass 1 left in a room; a room that
+    holds a quarter or a tenth of them makes the call composite tile ranges
+    one after another, and no room makes pass 2 filter the tile lists
+    itself.  Sensitivities and the live-pair counts are identical in every case."""
+    import torch
+    sc, vw = _ragged()
+    dsc = gs.DeviceScene.from_scene(sc)
+    ref, st = gs.sensitivity(dsc, vw, stats=True, count_pairs=True)
+    frac = {"none": 0.0, "quarter": 0.25, "tenth": 0.1}[room]
+    monkeypatch.setenv("GS_COMPACT_POOL_GB", repr(16 * st["n_entries"] * frac / 2**30))
+    s, st2 = gs.sensitivity(dsc, vw, stats=True, count_pairs=True)
+    monkeypatch.delenv("GS_COMPACT_POOL_GB")
+    torch.cuda.synchronize()
+    assert torch.equal(s, ref)
+    # (pairs evaluated past a ray's stop depend on where slices end, so only
+    # the counters that do not are compared)
+    keys = ("n_live_pairs", "n_rays_positive", "n_entries")
+    assert {k: st2[k] for k in keys} == {k: st[k] for k in keys}
+
+
 def test_render_full_matches_oracle(gs, ora):
     sc, vw = _ragged()
     ref = ora.sensitivity(sc, vw)
