@@ -30,10 +30,12 @@ sys.path.insert(0, ROOT)
 # 157.3 TFLOP/s counting an FMA as 2 flops; this path uses no packed math).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Algorithmic VALU slots per live ray-Gaussian pair in pass 2: offset (2),
-# quadratic form (5), cutoff select (1), rho (1), c rho (1), share (2),
-# transmittance update (1), running max (1), plus v_exp_f32 counted as 2
-# slots (measured on gfx950 at 1.86 FMA slots: a half-rate transcendental).
-OPS_PASS2 = 14 + 2
+# quadratic form with log2(alpha) folded in (5), footprint cutoff (compare and
+# select, 2), c rho (1), share = c rho times the transmittance scaled by
+# 1/A (1), transmittance update (1), compare with the entry's sensitivity (1),
+# plus v_exp_f32 counted as 2 slots (measured on gfx950 at 1.86 FMA slots: a
+# half-rate transcendental).  Pass 1: the same up to c rho, then A and T.
+OPS_PASS2 = 13 + 2
 OPS_PASS1 = 12 + 2
 # HBM peak of an MI355X (bytes/s).
 PEAK_HBM = 8.0e12
@@ -407,7 +409,7 @@ def main():
     p2["frac_of_packed_fp32_peak"] = p2["achieved"] / (2 * p2["peak"])
     if peaks:
         # the same work priced with the measured issue rate and exp cost
-        slots = 14 + peaks["exp_cost_in_fma_slots"]
+        slots = OPS_PASS2 - 2 + peaks["exp_cost_in_fma_slots"]
         p2["frac_of_measured_issue_rate"] = live * slots / (stage["ms_pass2"] * 1e-3) / (peaks["fma_Tlane_per_s"] * 1e12)
     emit_bytes = (EMIT_BYTES_POSITION * cst["n_projected"] + EMIT_BYTES_BIN * cst["n_bins"]
                   + EMIT_BYTES_ENTRY * cst["n_entries"])

@@ -174,12 +174,15 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
 // run in unguarded blocks of kPad pairs.
 // geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
 // col = (g', alpha, cbar, extra), or with kChannel (g', alpha, c_R, c_G) and
-// c_B in cblue.
-template <int kExtra, int kPad = 1, bool kChannel = false>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
+// c_B in cblue.  With kLog (no extra value, one query per ray) col = (g',
+// log2 alpha, cbar, cut + log2 alpha) for pair_rho_log2; null entries then
+// carry an infinite bar.
+template <int kExtra, int kPad = 1, bool kChannel = false, bool kLog = false>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
 __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
                                            uint32_t *sid, float *sold, const double *__restrict__ weights,
                                            float *cblue = nullptr, uint32_t *cout = nullptr) {
     static_assert(!(kChannel && kExtra == 2), "per-channel queries have no weighted objective");
+    static_assert(!(kLog && (kChannel || kExtra == 2)), "the log form has no room for an extra value");
     const int lane = threadIdx.x;
     const uint64_t e = e0 + lane;
     const uint32_t raw = e < w.end ? w.lists[e] : 0u;
@@ -207,7 +210,7 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         const int slot = n + __popcll(~bal & lanemask_lt64());
         if (slot < ((n + kPad - 1) & ~(kPad - 1))) {
             geo[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            col[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            col[slot] = make_float4(0.0f, 0.0f, 0.0f, kLog ? __builtin_inff() : 0.0f);
             if (kChannel) cblue[slot] = 0.0f;
         }
     }
@@ -235,7 +238,12 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         }
         if (kExtra == 2) extra = (float)weights[g];
         if (kChannel) extra = cg;
-        col[slot] = make_float4(r1.z, r1.w, cb, extra);
+        if (kLog) {
+            const float la = __builtin_amdgcn_logf(r1.w);
+            col[slot] = make_float4(r1.z, la, cb, cut + la);
+        } else {
+            col[slot] = make_float4(r1.z, r1.w, cb, extra);
+        }
     }
     return n;
 }
@@ -243,9 +251,11 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
 // Stage up to 64 entries of a quadrant's compacted list (every one passed
 // the quadrant's exact test in pass 1): the same slots as stage_slice would
 // fill for them, padded with null entries to a multiple of kPad.
-template <int kPad, bool kChannel>
+template <int kPad, bool kChannel, bool kLog = false>
 __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t *__restrict__ cl, uint32_t left,
-                                             float4 *geo, float4 *col, uint32_t *sid, float *sold, float *cblue) {
+                                             float cut, float4 *geo, float4 *col, uint32_t *sid, float *sold,
+                                             float *cblue) {
+    static_assert(!(kLog && kChannel), "the log form holds one query per ray");
     const int lane = threadIdx.x;
     const int n = (int)min(left, (uint32_t)kWave);
     if (lane < n) {
@@ -263,12 +273,17 @@ __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t 
             cb = w.R2[o].x;
         }
         geo[lane] = make_float4((r0.x - w.qx0) + r0.z, (r0.y - w.qy0) + r0.w, r1.x, r1.y);
-        col[lane] = make_float4(r1.z, r1.w, cb, kChannel ? cg : 0.0f);
+        if (kLog) {
+            const float la = __builtin_amdgcn_logf(r1.w);
+            col[lane] = make_float4(r1.z, la, cb, cut + la);
+        } else {
+            col[lane] = make_float4(r1.z, r1.w, cb, kChannel ? cg : 0.0f);
+        }
         sid[lane] = g;
         sold[lane] = fmaxf(__uint_as_float(w.sens_bits[g]), w.sfloor);
     } else if (lane < ((n + kPad - 1) & ~(kPad - 1))) {
         geo[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        col[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        col[lane] = make_float4(0.0f, 0.0f, 0.0f, kLog ? __builtin_inff() : 0.0f);
         if (kChannel) cblue[lane] = 0.0f;
     }
     return n;
@@ -286,6 +301,20 @@ __device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, flo
     const float E = __builtin_amdgcn_exp2f(P);
     in_fp = P >= cut;
     return in_fp ? Cc.y * E : 0.0f;
+}
+
+// The same with alpha folded into the exponent: col = (g', log2 alpha, ., bar)
+// with bar = cut + log2 alpha (stage_slice / stage_compact with kLog), so
+// rho = exp2(P + log2 alpha) inside the footprint (P + log2 alpha >= bar).
+__device__ __forceinline__ float pair_rho_log2(const float4 &G, const float4 &Cc, float xl, float yl, bool &in_fp) {
+    const float dx = xl - G.x;
+    const float dy = yl - G.y;
+    const float u = fmaf(G.z, dy, dx);
+    const float t = fmaf(Cc.x, dy * dy, Cc.y);
+    const float P = fmaf(G.w * u, u, t);
+    const float E = __builtin_amdgcn_exp2f(P);
+    in_fp = P >= Cc.w;
+    return in_fp ? E : 0.0f;
 }
 
 // Pass 1 per query mode (kModeL1: a = c rho T; kModeL2: a = c (rho T)^2;
@@ -311,14 +340,15 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
         uint32_t ccnt = 0;
         for (uint64_t e0 = w.start; e0 < w.end; e0 += kWave) {
             if (__all(done)) break;
-            const int n = stage_slice<0, 1, kCh>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr, cblue,
+            const int n = stage_slice<0, 1, kCh, !kCh>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr, cblue,
                                                  cl ? cl + ccnt : nullptr);
             ccnt += (uint32_t)n;
             __syncthreads();
             for (int j = 0; j < n; ++j) {
                 const float4 G = geo[j], Cc = col[j];
                 bool in_fp;
-                const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+                const float rho = kCh ? pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp)
+                                      : pair_rho_log2(G, Cc, w.xl, w.yl, in_fp);
                 if (kMode == kModeL1) {
                     const float cr = Cc.z * rho;
                     A = fmaf(cr, T, A);
@@ -463,7 +493,7 @@ __device__ __forceinline__ float wave_transpose_sum16(float (&v)[16]) {
 }
 
 template <bool kStats, bool kPersistent, int kAgg, int kMode, bool kCompact>
-__global__ __launch_bounds__(kWave, kPersistent ? 5 : ((kAgg != 0 || kMode == kModeChannel) ? 6 : 8))
+__global__ __launch_bounds__(kWave, kPersistent ? 5 : ((kAgg != 0 || kMode == kModeChannel) ? 6 : 7))
 void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     static_assert(!(kAgg != 0 && kMode == kModeChannel), "per-channel queries have no aggregated form");
     static_assert(!(kAgg != 0 && kCompact), "aggregated queries walk the tile lists");
@@ -502,10 +532,15 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
         }
         const float cmax = w.cmax;
         uint32_t *sens_bits = w.sens_bits;
-        float T = 1.0f;
+        // One query per ray: the running transmittance is kept scaled, by
+        // 1/A(Q) for L1 shares (share = c rho T / A(Q) = c rho T') and by
+        // 1/sqrt(A(Q)) for L2 shares (c (rho T')^2), and the stop bar with it.
+        // Per channel: T itself.
+        const float tscale = kCh ? 1.0f : (kMode == kModeL2 ? sqrtf(invQ) : invQ);
+        float T = tscale;
         bool done = !positive;
         uint32_t n_in = 0, n_live = 0, n_eval = 0;
-        const float live_bar = a.share_floor * Amin;
+        const float live_bar = kCh ? a.share_floor * Amin : a.share_floor * (Amin * invQ);
         // the quadrant's entries: its compacted list from pass 1, or its
         // tile's list filtered again
         const uint32_t *cl = kCompact ? w.clist + w.cbase : nullptr;
@@ -514,10 +549,11 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
             if (__all(done)) break;
             int n;
             if (kCompact)
-                n = stage_compact<kBlock, kCh>(w, cl + e0, (uint32_t)(hi - e0), geo, col, sid, sold, cblue);
+                n = stage_compact<kBlock, kCh, !kCh>(w, cl + e0, (uint32_t)(hi - e0), a.r2_log2, geo, col, sid,
+                                                     sold, cblue);
             else
-                n = stage_slice<kAgg == 0 ? 1 : 3, kBlock, kCh>(w, e0, a.r2_log2, geo, col, sid, sold, nullptr,
-                                                                cblue);
+                n = stage_slice<kAgg == 0 ? 1 : 3, kBlock, kCh, !kCh>(w, e0, a.r2_log2, geo, col, sid, sold,
+                                                                      nullptr, cblue);
             __syncthreads();
             for (int jb = 0; jb < n; jb += 16) {
                 float sh[16];
@@ -529,13 +565,13 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                             const int j = jb + k0 + q;
                             const float4 G = geo[j], Cc = col[j];
                             bool in_fp;
-                            const float rho = pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp);
+                            const float rho = kCh ? pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp)
+                                                  : pair_rho_log2(G, Cc, w.xl, w.yl, in_fp);
                             if (kMode == kModeL1) {
-                                const float cr = Cc.z * rho;
-                                sh[k0 + q] = (cr * T) * invQ;
+                                sh[k0 + q] = (Cc.z * rho) * T;
                             } else if (kMode == kModeL2) {
                                 const float rt = rho * T;
-                                sh[k0 + q] = ((Cc.z * rt) * rt) * invQ;
+                                sh[k0 + q] = (Cc.z * rt) * rt;
                             } else {
                                 const float rt = rho * T;
                                 sh[k0 + q] = rt * fmaxf(Cc.z * invA, fmaxf(Cc.w * invG, cblue[j] * invB));
@@ -559,10 +595,11 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                     // the reduction is needed only if some pixel beats the
                     // staged sensitivity of its entry (padded entries have
                     // share 0, which beats no sensitivity)
-                    bool beat = false;
+                    // (one compare per value, its lane mask OR-ed in scalar registers)
+                    uint64_t beat = 0ull;
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) beat |= sh[k] > sold[jb + k];
-                    if (__ballot(beat) != 0ull) {
+                    for (int k = 0; k < 16; ++k) beat |= __ballot(sh[k] > sold[jb + k]);
+                    if (beat != 0ull) {
                         const float m = wave_transpose_max16(sh);
                         if ((lane & 3) == 0 && j < n && m > sold[j])
                             atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
@@ -577,7 +614,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                 }
             }
             const float later = kMode == kModeL2 ? (T * T) * cmax : T * cmax;
-            done = done || (later < a.share_floor * Amin);
+            done = done || (later < live_bar);
             __syncthreads();
         }
         if (kStats) {
