@@ -1039,7 +1039,7 @@ gs_status gs_mlp_forward(const float *params, const float *features, const float
     gs_status s = begin_call(&dev, st);
     if (s != GS_OK) return s;
     DoneGuard done_guard{dev, st};
-    const int64_t rows = std::min<int64_t>(kMlpRows, (n + 63) / 64 * 64);
+    const int64_t rows = 64;   // the fused forward needs only the bf16 weights from the scratch
     HIP_TRY(arena_reserve(g_work[dev], mlp_scratch_bytes(rows)));
     mlp_forward(params, features, norm, n, out, g_work[dev].base, rows, st);
     HIP_TRY(hipGetLastError());

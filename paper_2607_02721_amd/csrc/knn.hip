@@ -40,20 +40,36 @@ __device__ __forceinline__ uint32_t ord_bits(float f) {
 }
 
 // box[0..2] = min (ordered bits), box[3..5] = max
-__global__ void k_bbox(SceneDev sc, uint32_t *box) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = i < sc.n;
-    for (int c = 0; c < 3; ++c) {
-        const float x = ok ? kload(sc.mean, c * sc.n + i, sc.format, false) : 0.0f;
-        uint32_t lo = ok ? ord_bits(x) : 0xFFFFFFFFu, hi = ok ? ord_bits(x) : 0u;
+// Bounding box of the means (order-preserving bits, so min / max are integer
+// operations): a fixed grid strides over the points, each block folds its
+// waves in LDS and adds one atomic per bound (atomics on one address
+// serialise, so one per wave would cost about a millisecond at 10^6 points).
+constexpr int kBoxBlocks = 256;
+__global__ __launch_bounds__(256) void k_bbox(SceneDev sc, uint32_t *box) {
+    __shared__ uint32_t red[4][6];
+    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sc.n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t b = ord_bits(kload(sc.mean, c * sc.n + i, sc.format, false));
+            lo[c] = min(lo[c], b);
+            hi[c] = max(hi[c], b);
+        }
+    for (int c = 0; c < 3; ++c)
         for (int off = 32; off > 0; off >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
+            lo[c] = min(lo[c], (uint32_t)__shfl_xor((int)lo[c], off));
+            hi[c] = max(hi[c], (uint32_t)__shfl_xor((int)hi[c], off));
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(&box[c], lo);
-            atomicMax(&box[3 + c], hi);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < 3; ++c) {
+            red[w][c] = lo[c];
+            red[w][3 + c] = hi[c];
         }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        atomicMin(&box[c], min(min(red[0][c], red[1][c]), min(red[2][c], red[3][c])));
+        atomicMax(&box[3 + c], max(max(red[0][3 + c], red[1][3 + c]), max(red[2][3 + c], red[3][3 + c])));
     }
 }
 
@@ -253,7 +269,7 @@ hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStrea
     uint32_t init[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
     hipError_t e = hipMemcpyAsync(box, init, sizeof init, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bbox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sc, box);
+    hipLaunchKernelGGL(k_bbox, dim3(kBoxBlocks), dim3(256), 0, st, sc, box);
     uint32_t hb[6];
     e = hipMemcpyAsync(hb, box, sizeof hb, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;

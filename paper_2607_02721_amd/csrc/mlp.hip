@@ -335,24 +335,115 @@ static void mlp_forward_rows(const float *P, const MlpBufs &m, int64_t rows, boo
     }
 }
 
+// Fused inference: one block of 4 waves per 64 rows runs the whole network
+// with the activations in LDS (two row-major bf16 buffers with a padded row
+// stride, so the 16 rows a fragment load reads fall on different banks) and
+// the bf16 weights read straight from global memory (L2): wave w computes
+// output columns [64 w, 64 w + 64) of every layer for the block's 64 rows,
+// with the fragment layout and k order of k_gemm_nt, so every activation is
+// the bf16 value the unfused path stores.  The head sums bf16(SiLU(z3)) w4
+// over each wave's columns (DPP over the 16 lanes of a fragment row), then
+// over the waves.
+constexpr int kFuseRows = 64;
+constexpr int kFusePitch = kMlpH + 8;   // bf16 per LDS row
+
+template <int kK>
+__device__ __forceinline__ void fused_layer(const __bf16 (*In)[kFusePitch], const __bf16 *__restrict__ W,
+                                            const float *__restrict__ bias, int w, int lane, f32x4 (&acc)[4][4]) {
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < kK; k0 += 32) {
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            b[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(64 * w + 16 * j + fr) * kK + k0 + fk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&In[16 * i + fr][k0 + fk]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float bj = bias[64 * w + 16 * j + fr];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = silu(acc[i][j][r] + bj);
+        }
+}
+
+__device__ __forceinline__ void fused_store(__bf16 (*Out)[kFusePitch], int w, int lane, const f32x4 (&acc)[4][4]) {
+    const int fr = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Out[16 * i + 4 * g + r][64 * w + 16 * j + fr] = (__bf16)acc[i][j][r];
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fused(const float *__restrict__ feat, const float *__restrict__ norm,
+                                                   int64_t n, const __bf16 *__restrict__ W1,
+                                                   const __bf16 *__restrict__ W2, const __bf16 *__restrict__ W3,
+                                                   const float *__restrict__ P, float *__restrict__ y) {
+    __shared__ __attribute__((aligned(16))) __bf16 HA[kFuseRows][kFusePitch], HB[kFuseRows][kFusePitch];
+    __shared__ float ypart[4][kFuseRows];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kFuseRows;
+    // standardised inputs, rows past n are zero (as k_standardize)
+    for (int i = threadIdx.x; i < kFuseRows * kMlpIn; i += 256) {
+        const int r = i / kMlpIn, c = i % kMlpIn;
+        const int64_t row = r0 + r;
+        const float x = row < n ? (feat[row * kMlpIn + c] - norm[c]) * norm[kMlpIn + c] : 0.0f;
+        HA[r][c] = (__bf16)x;
+    }
+    __syncthreads();
+    f32x4 acc[4][4];
+    fused_layer<kMlpIn>(HA, W1, P + kOffB1, w, lane, acc);
+    fused_store(HB, w, lane, acc);
+    __syncthreads();
+    fused_layer<kMlpH>(HB, W2, P + kOffB2, w, lane, acc);
+    fused_store(HA, w, lane, acc);
+    __syncthreads();
+    fused_layer<kMlpH>(HA, W3, P + kOffB3, w, lane, acc);
+    // head: this wave's columns, summed over the 16 lanes of each fragment row
+    const int fr = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float s = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                s += (float)(__bf16)acc[i][j][r] * (float)(__bf16)P[kOffW4 + 64 * w + 16 * j + fr];
+            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (fr == 0) ypart[w][16 * i + 4 * g + r] = s;
+        }
+    __syncthreads();
+    if (threadIdx.x < kFuseRows && r0 + threadIdx.x < n) {
+        const int t = threadIdx.x;
+        y[r0 + t] = ((ypart[0][t] + ypart[1][t]) + (ypart[2][t] + ypart[3][t])) + P[kOffB4];
+    }
+}
+
 void mlp_init(float *params, uint64_t seed, hipStream_t st) {
     hipLaunchKernelGGL(k_mlp_init, dim3(blocks_for(kMlpParams)), dim3(256), 0, st, params, seed);
 }
 
-// Predictions for n rows of raw features, in batches of `rows` (multiple of 64).
+// Predictions for n rows of raw features: the bf16 weights, then one fused
+// launch over every row (`rows` only sizes the scratch the weights come from).
 void mlp_forward(const float *P, const float *feat, const float *norm, int64_t n, float *y, void *scratch,
                  int64_t rows, hipStream_t st) {
     const MlpBufs m = carve_mlp(scratch, rows);
     hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3, m.W2t,
                        m.W3t, m.W1t);
-    for (int64_t r0 = 0; r0 < n; r0 += rows) {
-        const int64_t nb = n - r0 < rows ? n - r0 : rows;
-        const int64_t padded = (nb + 63) / 64 * 64;
-        hipLaunchKernelGGL(k_standardize, dim3(blocks_for(padded * kMlpIn)), dim3(256), 0, st,
-                           feat + r0 * kMlpIn, norm, nb, padded, m.X0);
-        mlp_forward_rows(P, m, padded, false, st);
-        hipLaunchKernelGGL(k_head, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, m.H3, P, nb, y + r0);
-    }
+    hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)((n + kFuseRows - 1) / kFuseRows)), dim3(256), 0, st, feat, norm, n,
+                       m.W1, m.W2, m.W3, P, y);
 }
 
 // Loss and gradient on one batch of n <= rows rows; if adam != nullptr also
