@@ -148,53 +148,81 @@ __global__ __launch_bounds__(256) void k_knn_features(SceneDev sc, Grid G, const
                     if (x < 0 || x >= G.dim[0]) continue;
                     const uint32_t id = (uint32_t)((z * G.dim[1] + y) * G.dim[0] + x);
                     const uint64_t lo = off[id], hi = off[id + 1];
-                    for (uint64_t p = lo; p < hi; ++p) {
-                        const uint32_t j = order[p];
-                        if (j == q) continue;
-                        const float4 o = pts[p];
-                        const float ex = o.x - me.x, ey = o.y - me.y, ez = o.z - me.z;
-                        const float d2 = ex * ex + ey * ey + ez * ez;
-                        if (!knn_less(d2, j, bd[kK - 1], bi[kK - 1])) continue;
-                        bool placed = false;
+                    // candidates four at a time, their loads issued together
+                    // (slots past the cell's end repeat the query and are skipped)
+                    for (uint64_t p0 = lo; p0 < hi; p0 += 4) {
+                        uint32_t jj[4];
+                        float4 oo[4];
 #pragma unroll
-                        for (int k = kK - 1; k >= 0; --k) {
-                            if (placed) continue;
-                            const bool move = k > 0 && knn_less(d2, j, bd[k - 1], bi[k - 1]);
-                            if (move) {
-                                bd[k] = bd[k - 1];
-                                bi[k] = bi[k - 1];
-                                ba[k] = ba[k - 1];
-                            } else {
-                                bd[k] = d2;
-                                bi[k] = j;
-                                ba[k] = o.w;
-                                placed = true;
+                        for (int u = 0; u < 4; ++u) {
+                            const bool ok = p0 + u < hi;
+                            jj[u] = ok ? order[p0 + u] : q;
+                            oo[u] = ok ? pts[p0 + u] : me;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t j = jj[u];
+                            if (j == q) continue;
+                            const float4 o = oo[u];
+                            const float ex = o.x - me.x, ey = o.y - me.y, ez = o.z - me.z;
+                            const float d2 = ex * ex + ey * ey + ez * ez;
+                            if (!knn_less(d2, j, bd[kK - 1], bi[kK - 1])) continue;
+                            bool placed = false;
+#pragma unroll
+                            for (int k = kK - 1; k >= 0; --k) {
+                                if (placed) continue;
+                                const bool move = k > 0 && knn_less(d2, j, bd[k - 1], bi[k - 1]);
+                                if (move) {
+                                    bd[k] = bd[k - 1];
+                                    bi[k] = bi[k - 1];
+                                    ba[k] = ba[k - 1];
+                                } else {
+                                    bd[k] = d2;
+                                    bi[k] = j;
+                                    ba[k] = o.w;
+                                    placed = true;
+                                }
                             }
                         }
                     }
                 }
             }
         }
-        const float reach = (float)r * G.cell;
-        if (bi[kK - 1] != 0xFFFFFFFFu && bd[kK - 1] < reach * reach) break;
+        // every point outside the searched cube of cells is at least `reach`
+        // away: the distance to the cube's nearest face that has cells beyond
+        // it (less a margin for the rounding of the cell assignment)
+        float reach = INFINITY;
+        const float pc[3] = {me.x, me.y, me.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (c3[a] - r > 0) reach = fminf(reach, pc[a] - (G.lo[a] + (float)(c3[a] - r) * G.cell));
+            if (c3[a] + r < G.dim[a] - 1) reach = fminf(reach, (G.lo[a] + (float)(c3[a] + r + 1) * G.cell) - pc[a]);
+        }
+        reach -= 1e-4f * G.cell;
+        if (bi[kK - 1] != 0xFFFFFFFFu && (reach == INFINITY || (reach > 0.0f && bd[kK - 1] < reach * reach))) break;
     }
-    // features
+    // features, assembled in registers and stored as 16 float4 (one row of
+    // 256 bytes per point)
     const int64_t n = sc.n;
-    float *f = feat + (int64_t)q * kMlpIn;
+    float f[kMlpIn];
+    f[0] = kload(sc.mean, q, sc.format, false);
     f[1] = kload(sc.mean, n + q, sc.format, false);
     f[2] = kload(sc.mean, 2 * n + q, sc.format, false);
-    f[0] = kload(sc.mean, q, sc.format, false);
+#pragma unroll
     for (int c = 0; c < 3; ++c) f[3 + c] = kload(sc.log_scale, c * n + q, sc.format, false);
     float qq[4], qn = 0.0f;
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
         qq[c] = kload(sc.quat, c * n + q, sc.format, true);
         qn += qq[c] * qq[c];
     }
     const float qs = (qq[0] < 0.0f ? -1.0f : 1.0f) * rsqrtf(fmaxf(qn, 1e-30f));
+#pragma unroll
     for (int c = 0; c < 4; ++c) f[6 + c] = qq[c] * qs;
     const float al = fminf(fmaxf(me.w, 1e-6f), 1.0f - 1e-6f);
     f[10] = logf(al / (1.0f - al));
     const int K = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+#pragma unroll
     for (int k = 0; k < 48; ++k) f[11 + k] = k < 3 * K ? kload(sc.sh, (int64_t)k * n + q, sc.format, false) : 0.0f;
     int cnt = 0;
     float sd = 0.0f, sa = 0.0f, ma = 0.0f;
@@ -213,6 +241,9 @@ __global__ __launch_bounds__(256) void k_knn_features(SceneDev sc, Grid G, const
     f[61] = cnt ? sa / cnt : 0.0f;
     f[62] = ma;
     f[63] = logf(fmaxf(sa, tiny) / fmaxf(4.18879020f * d16 * d16 * d16, tiny));
+    float4 *row = reinterpret_cast<float4 *>(feat + (int64_t)q * kMlpIn);
+#pragma unroll
+    for (int k = 0; k < kMlpIn / 4; ++k) row[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
 }
 
 // Column means and 1/std (population) of an n x 64 float32 matrix, in FP64.
@@ -290,7 +321,9 @@ hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStrea
         ext[c] = std::max(h - G.lo[c], 1e-6f);
         vol *= ext[c];
     }
-    double cell = cbrt(vol / (double)n);
+    // about four points per cell of the bounding box (measured on clustered
+    // scenes: one per cell scans more cells, sixteen more candidates)
+    double cell = cbrt(4.0 * vol / (double)n);
     int64_t cells = 0;
     for (;;) {
         cells = 1;
