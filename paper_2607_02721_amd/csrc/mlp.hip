@@ -355,17 +355,25 @@ __device__ __forceinline__ void fused_layer(const __bf16 (*In)[kFusePitch], cons
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < kK; k0 += 32) {
-        bf16x8 a[4], b[4];
+    // the next k step's weight fragments are loaded while this one multiplies
+    bf16x8 b[4], bn[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            b[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(64 * w + 16 * j + fr) * kK + k0 + fk);
+    for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(64 * w + 16 * j + fr) * kK + fk);
+    for (int k0 = 0; k0 < kK; k0 += 32) {
+        bf16x8 a[4];
+        if (k0 + 32 < kK) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bn[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(64 * w + 16 * j + fr) * kK + k0 + 32 + fk);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&In[16 * i + fr][k0 + fk]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = bn[j];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
