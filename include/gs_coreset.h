@@ -240,6 +240,11 @@ typedef struct {
     int64_t compact_bytes;    /* pool of compacted quadrant lists (0: none) */
     int32_t n_launches;       /* pass-1 + pass-2 launch pairs per run */
     int32_t n_compact_launches; /* of which pass 2 walks compacted lists */
+    int32_t n_sort3_scenes;   /* scenes whose depth sort takes three 8-bit passes (every view's keys
+                                 spanned under 2^24 - 1 at creation; a run where a view's keys span
+                                 more empties that scene's lists and reports GS_ERR_INVALID_DATA
+                                 through gs_plan_status) */
+    int32_t pad;
 } gs_plan_info;
 
 /* scenes, views: host arrays of n_scenes (the attribute arrays they point to

@@ -185,7 +185,7 @@ class Plan:
                 "xcd_remap": i.config.xcd_remap, "graph_captured": i.graph_captured,
                 "device_bytes": i.device_bytes, "list_capacity": i.list_capacity,
                 "compact_bytes": i.compact_bytes, "n_launches": i.n_launches,
-                "n_compact_launches": i.n_compact_launches}
+                "n_compact_launches": i.n_compact_launches, "n_sort3_scenes": i.n_sort3_scenes}
 
     def status(self, stream=None):
         """Raises GsError if some run overflowed a scene's list capacity."""

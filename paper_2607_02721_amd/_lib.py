@@ -76,7 +76,7 @@ class PlanInfo(C.Structure):
     _fields_ = [("n_scenes", C.c_int32), ("n_groups", C.c_int32), ("config", PlanConfig),
                 ("graph_captured", C.c_int32), ("device_bytes", C.c_int64),
                 ("list_capacity", C.c_int64), ("compact_bytes", C.c_int64), ("n_launches", C.c_int32),
-                ("n_compact_launches", C.c_int32)]
+                ("n_compact_launches", C.c_int32), ("n_sort3_scenes", C.c_int32), ("pad", C.c_int32)]
 
 
 class Peaks(C.Structure):

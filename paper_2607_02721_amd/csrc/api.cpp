@@ -1095,6 +1095,7 @@ struct PlanScene {
     uint64_t cap = 0;
     int group = 0, view0 = 0, tile0 = 0;
     uint32_t *clist = nullptr;    // the scene's compacted quadrant lists in the plan's pool (null: none)
+    int passes = 4;               // depth sort passes (3 when the keys span well under 2^24 at creation)
 };
 
 // One pass-1 + pass-2 launch over consecutive scenes of a group (tiles
@@ -1199,10 +1200,12 @@ void enqueue_front(const gs_plan *P, PlanScene &ps, hipStream_t st) {
     ProjParams pp{P->p.footprint_sigma, P->p.dilation, P->p.z_near, P->p.query_mode};
     launch_project(sd, ps.views_dev, ps.c.vc, pp, b, st);
     uint32_t *skeys = nullptr;
-    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, 4, nullptr, nullptr, &skeys,
-                        &ps.sorted_g, st);
-    ps.xr = b.key1;
-    ps.yr = b.val1;
+    radix_sort_segments(b.key0, b.val0, b.key1, b.val1, b.hist, N, ps.c.vc, true, ps.passes,
+                        ps.passes == 3 ? b.kmin : nullptr, nullptr, &skeys, &ps.sorted_g, st);
+    // the pair of sort buffers that does not hold the sorted output
+    const bool out_in_0 = ps.sorted_g == b.val0;
+    ps.xr = out_in_0 ? b.key1 : b.key0;
+    ps.yr = out_in_0 ? b.val1 : b.val0;
     launch_ranges_in_order(ps.sorted_g, b, ps.c.vc, N, ps.xr, ps.yr, st);
     launch_bin_count(ps.views_dev, ps.c.vc, N, ps.S.nchunks, b, ps.xr, ps.yr, ps.max_cells, st);
     launch_chunk_prefix(ps.views_dev, ps.c.vc, ps.S.nchunks, b, ps.max_tiles, st);
@@ -1215,7 +1218,8 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
         for (int si : G.scenes) {
             PlanScene &ps = P->scenes[si];
             enqueue_front(P, ps, st);
-            launch_list_guard(ps.b.tile_off, ps.c.total_tiles, ps.cap, ps.over, P->flag, st);
+            if (ps.passes == 3) launch_span_check(ps.b.kmin, ps.c.vc, ps.over, P->flag, st);
+            launch_list_guard(ps.b.tile_off, ps.c.total_tiles, ps.cap, ps.over, P->flag, ps.passes == 3, st);
             launch_bin_emit(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.sorted_g,
                             ps.max_tx, ps.max_ty, ps.cap, st);
             launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
@@ -1373,16 +1377,27 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         HIP_TRY(hipMemcpyAsync(G.tile_scene, gts.data(), sizeof(int32_t) * gts.size(), hipMemcpyHostToDevice, st));
         // count pre-pass: list sizes of every scene of the group
         std::vector<uint64_t> totals(G.scenes.size());
+        std::vector<std::vector<uint32_t>> kr(G.scenes.size());
         for (size_t k = 0; k < G.scenes.size(); ++k) {
             PlanScene &ps = P->scenes[G.scenes[k]];
             enqueue_front(P, ps, st);
             HIP_TRY(hipMemcpyAsync(&totals[k], ps.b.tile_off + ps.c.total_tiles, sizeof(uint64_t),
                                    hipMemcpyDeviceToHost, st));
+            kr[k].resize(2 * (size_t)ps.c.vc);
+            HIP_TRY(hipMemcpyAsync(kr[k].data(), ps.b.kmin, sizeof(uint32_t) * kr[k].size(), hipMemcpyDeviceToHost,
+                                   st));
         }
         HIP_TRY(hipStreamSynchronize(st));
         size_t lb = 0;
         for (size_t k = 0; k < G.scenes.size(); ++k) {
             PlanScene &ps = P->scenes[G.scenes[k]];
+            // three sort passes when every view's depth keys span under 2^24
+            // - 1 at creation, as in gs_sensitivity (attributes that change in
+            // place can cross it: the span check guards every run)
+            uint32_t span = 0;
+            for (int v = 0; v < ps.c.vc; ++v)
+                if (kr[k][ps.c.vc + v] >= kr[k][v]) span = std::max(span, kr[k][ps.c.vc + v] - kr[k][v]);
+            ps.passes = span < 0xFFFFFFu ? 3 : 4;
             ps.cap = totals[k] + totals[k] / 64 + 1024;
             lb += ((ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255);
         }
@@ -1515,7 +1530,10 @@ gs_status gs_plan_get_info(const gs_plan *plan, gs_plan_info *info) {
     }
     info->device_bytes += (int64_t)plan->pool_bytes;
     info->compact_bytes = (int64_t)plan->pool_bytes;
-    for (const PlanScene &ps : plan->scenes) info->list_capacity += (int64_t)ps.cap;
+    for (const PlanScene &ps : plan->scenes) {
+        info->list_capacity += (int64_t)ps.cap;
+        info->n_sort3_scenes += ps.passes == 3 ? 1 : 0;
+    }
     return GS_OK;
 }
 

@@ -561,19 +561,36 @@ void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, c
 // Capacity guard for lists sized in advance (plans): if the counted entries
 // exceed the capacity, flag it and empty every list of the scene so that no
 // later kernel reads past the buffer.
+// Plan guards.  A scene whose lists outgrow their capacity, or (with the
+// three-pass depth sort) whose view's depth keys span 2^24 or more, gets
+// empty lists this run (its output is zero) and raises the sticky flag.
+__global__ void k_span_check(const uint32_t *__restrict__ kmin, int Vc, uint32_t *__restrict__ over,
+                             uint32_t *__restrict__ flag) {
+    bool bad = false;
+    for (int v = threadIdx.x; v < Vc; v += blockDim.x)
+        bad = bad || (kmin[Vc + v] >= kmin[v] && kmin[Vc + v] - kmin[v] >= 0xFFFFFFu);
+    bad = __any(bad);
+    if (threadIdx.x == 0) {
+        *over = bad ? 1u : 0u;
+        if (bad) atomicOr(flag, 1u);
+    }
+}
 __global__ void k_guard_check(const uint64_t *__restrict__ tile_off, int64_t ntiles, uint64_t cap,
-                              uint32_t *__restrict__ over, uint32_t *__restrict__ flag) {
+                              uint32_t *__restrict__ over, uint32_t *__restrict__ flag, int keep) {
     const bool o = tile_off[ntiles] > cap;
-    *over = o ? 1u : 0u;
+    *over = (o || (keep && *over)) ? 1u : 0u;
     if (o) atomicOr(flag, 1u);
 }
 __global__ void k_guard_apply(uint64_t *__restrict__ tile_off, int64_t ntiles, const uint32_t *__restrict__ over) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (*over && i <= ntiles) tile_off[i] = 0;
 }
-void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag,
+void launch_span_check(const uint32_t *kmin, int Vc, uint32_t *over, uint32_t *flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_span_check, dim3(1), dim3(64), 0, st, kmin, Vc, over, flag);
+}
+void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag, bool keep,
                        hipStream_t st) {
-    hipLaunchKernelGGL(k_guard_check, dim3(1), dim3(1), 0, st, tile_off, ntiles, cap, over, flag);
+    hipLaunchKernelGGL(k_guard_check, dim3(1), dim3(1), 0, st, tile_off, ntiles, cap, over, flag, keep ? 1 : 0);
     hipLaunchKernelGGL(k_guard_apply, dim3((unsigned)((ntiles + 256) / 256)), dim3(256), 0, st, tile_off, ntiles,
                        over);
 }

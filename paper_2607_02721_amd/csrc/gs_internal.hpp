@@ -130,7 +130,12 @@ void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const Ch
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
                      int max_tiles_y, uint64_t cap, hipStream_t st);
-void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag,
+// Plan guards: *over = 1 (and *flag |= 1) when some view's kept depth keys
+// span 2^24 or more (a three-pass sort would misorder them); the list guard
+// sets it when the lists outgrow `cap` (keep: also when it is already set)
+// and then empties the lists.
+void launch_span_check(const uint32_t *kmin, int Vc, uint32_t *over, uint32_t *flag, hipStream_t st);
+void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag, bool keep,
                        hipStream_t st);
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
                                hipStream_t st);

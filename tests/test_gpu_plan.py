@@ -165,6 +165,35 @@ def test_capacity_guard(gs):
     plan.close()
 
 
+def test_depth_span_guard(gs):
+    """Scenes whose depth keys span little enough take a three-pass sort; a
+    Gaussian moved in place to half a unit in front of a camera stretches
+    that view's keys past what three passes order: that scene's output is
+    zero, the other scene is unaffected, and the status reports it."""
+    import torch
+    batch = _batch(gs, SPECS[:2])
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    info = plan.info()
+    print("[span]", info, flush=True)
+    assert info["n_sort3_scenes"] == 2
+    ref0 = plan.run()[0].clone()
+    torch.cuda.synchronize()
+    plan.status()
+    assert _same(ref0, gs.sensitivity(*batch[0])[0])
+    d0, v0 = batch[0]
+    M = v0.world_to_cam[0].reshape(3, 4)
+    eye = -M[:, :3].T @ M[:, 3]
+    d0.mean[:, 0] = torch.as_tensor(eye + 0.5 * M[2, :3], dtype=torch.float32, device="cuda")
+    outs = plan.run()
+    torch.cuda.synchronize()
+    with pytest.raises(gs.GsError) as e:
+        plan.status()
+    assert e.value.status == 5
+    assert float(outs[0].abs().max()) == 0.0
+    assert _same(outs[1], gs.sensitivity(*batch[1])[0])
+    plan.close()
+
+
 def test_scenes_split_into_groups(gs, monkeypatch):
     """With a small scratch budget the plan packs the scenes into several
     groups (one compositing launch each); results are unchanged."""
