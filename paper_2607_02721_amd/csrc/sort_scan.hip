@@ -63,29 +63,46 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
     hist[((int64_t)seg * 256 + d) * nb + b] = tot;
 }
 
-// One block per segment: exclusive scan over 256*nb counts (digit-major).
+// One block per segment: exclusive scan over 256*nb counts (digit-major), in
+// tiles of 1024 consecutive counts (coalesced loads, the next tile's loaded
+// while this one is scanned): a DPP scan inside each wave, the 16 wave sums
+// through LDS, and a carry from tile to tile.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void k_radix_offsets(uint32_t *__restrict__ hist, int nb) {
-    __shared__ uint32_t part[1024];
+    __shared__ uint32_t wsum[2][16];
     const int seg = blockIdx.x;
     uint32_t *h = hist + (int64_t)seg * 256 * nb;
     const int64_t total = (int64_t)256 * nb;
-    const int64_t per = (total + 1023) / 1024;
-    const int64_t lo = threadIdx.x * per, hi = min(lo + per, total);
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += h[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    uint32_t v = threadIdx.x < total ? h[threadIdx.x] : 0u;
+    int buf = 0;
+    for (int64_t base = 0; base < total; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t nxt = i + 1024 < total ? h[i + 1024] : 0u;
+        const uint32_t incl = wave_incl_scan_u32(v);
+        if (lane == 63) wsum[buf][w] = incl;
         __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t c = h[i];
-        h[i] = run;
-        run += c;
+        uint32_t before = 0, tile = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t s = wsum[buf][k];
+            before += k < w ? s : 0u;
+            tile += s;
+        }
+        if (i < total) h[i] = carry + before + incl - v;
+        carry += tile;
+        v = nxt;
+        buf ^= 1;   // the next tile's wave sums go to the other buffer, so no second barrier
     }
 }
 
