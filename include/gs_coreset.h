@@ -162,8 +162,9 @@ typedef struct {
  * leaves each 8x8 quadrant's culled list for pass 2 in a device room of up
  * to 4 x the list bytes, at most half of the free memory (the environment
  * variable GS_COMPACT_POOL_GB, in GiB, replaces that bound; 0 turns the room
- * off); when the room holds only part of the lists, the tiles are
- * composited in ranges that fit.  The results do not depend on the room. */
+ * off; a value that is not a number of GiB >= 0 is ignored); when the room
+ * holds only part of the lists, the tiles are composited in ranges that fit.
+ * The results do not depend on the room. */
 gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_params *params,
                          float *sens, gs_stats *stats, void *stream);
 
@@ -215,7 +216,8 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
  * on its plain tile lists.  Each scene's output equals that of
  * gs_sensitivity with the same params and no ray mask.
  * Memory: the scratch budget is 45% of the device's free memory (the
- * environment variable GS_SCRATCH_GB, in GiB, replaces it); groups take
+ * environment variable GS_SCRATCH_GB, in GiB >= 0, replaces it; other
+ * values are ignored, and the budget is never below 256 MiB); groups take
  * half of it, the compaction pool at most half of what is left after the
  * plan's other buffers (GS_COMPACT_POOL_GB replaces that bound; 0 turns
  * compaction off). */

@@ -231,6 +231,18 @@ gs_status check_params(const gs_params *p) {
     return GS_OK;
 }
 
+// A size in GiB from the environment: false (and *bytes untouched) when the
+// variable is unset, not a number, negative or not finite.
+bool env_gib(const char *name, size_t *bytes) {
+    const char *e = getenv(name);
+    if (!e) return false;
+    char *end = nullptr;
+    const double g = strtod(e, &end);
+    if (end == e || !std::isfinite(g) || g < 0.0 || g > 1.0e6) return false;
+    *bytes = (size_t)(g * (double)(1ull << 30));
+    return true;
+}
+
 size_t scratch_budget() {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
@@ -238,7 +250,7 @@ size_t scratch_budget() {
         free_b = (size_t)16 << 30;
     }
     size_t budget = (size_t)(0.45 * (double)free_b);
-    if (const char *e = getenv("GS_SCRATCH_GB")) budget = (size_t)(atof(e) * (double)(1ull << 30));
+    env_gib("GS_SCRATCH_GB", &budget);
     return std::max(budget, (size_t)256 << 20);
 }
 
@@ -498,7 +510,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         }
         const size_t held = g_compact[dev].cap;
         size_t avail = std::max(held, (free_b + held) / 2);
-        if (const char *e = getenv("GS_COMPACT_POOL_GB")) avail = (size_t)(atof(e) * (double)(1ull << 30));
+        env_gib("GS_COMPACT_POOL_GB", &avail);
         if (avail == 0) {
             // no room: pass 2 filters the tile lists itself
         } else if (cbytes <= avail) {
@@ -1268,7 +1280,7 @@ void plan_free(gs_plan *P) {
 // give the same sensitivities.
 void plan_batches(gs_plan *P) {
     size_t pool_budget = scratch_budget() / 2;
-    if (const char *e = getenv("GS_COMPACT_POOL_GB")) pool_budget = (size_t)(atof(e) * (double)(1ull << 30));
+    env_gib("GS_COMPACT_POOL_GB", &pool_budget);
     auto region = [](const PlanScene &ps) { return (4 * ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255; };
     std::vector<size_t> off(P->scenes.size(), 0);
     size_t pool = 0;
