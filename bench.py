@@ -39,6 +39,11 @@ OPS_PASS2 = 13 + 2
 OPS_PASS1 = 12 + 2
 # HBM peak of an MI355X (bytes/s).
 PEAK_HBM = 8.0e12
+# Dense BF16 MFMA peak of an MI355X (FLOP/s, without sparsity).
+PEAK_MFMA_BF16 = 2.5e15
+# FLOP per row of the proposal MLP (64 -> 256 -> 256 -> 256 -> 1): two per
+# multiply-add of its four layers.
+MLP_FLOP_PER_ROW = 2 * (64 * 256 + 256 * 256 + 256 * 256 + 256 * 1)
 # Algorithmic bytes of the tile-list emission kernel: per visible (view,
 # Gaussian) position its two packed pixel ranges and its index are read once
 # (12 B); per (tile, chunk) segment its start offset is read once (8 B); per
@@ -333,6 +338,19 @@ def main():
             scores, wl = learned_step()
         torch.cuda.synchronize()
         ms_l = (time.perf_counter() - t0) * 1e3 / args.steps
+        # the MLP inference alone (one gs_mlp_forward: BF16 weight copy +
+        # the fused three-layer kernel), on torch's stream, which it uses
+        feat = L.features(dsc)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        prop.predict(feat)
+        e0.record()
+        for _ in range(10):
+            prop.predict(feat)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_mlp = e0.elapsed_time(e1) / 10
+        mlp_rows = int(feat.shape[0])
+        del feat
         t0 = time.perf_counter()
         ob = gs.render_objective(dsc, views, wl, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
         errs["learned"] = gs.coreset_error(ob["per_view"])
@@ -341,6 +359,7 @@ def main():
         learned = {"ms": ms_l, "coreset_err": errs["learned"], "ms_judge": ms_judge,
                    "fallback": errs["learned"] > 0.01,
                    "ms_with_fallback": ms_l + ms_judge + (ms if errs["learned"] > 0.01 else 0.0),
+                   "ms_mlp": ms_mlp,
                    "train": {"scenes": args.train_scenes, "gaussians": args.train_scenes * 1_000_000,
                              "epochs": len(losses), "final_loss": losses[-1], "seconds": t_tr}}
         log(f"learned: {ms_l:.2f} ms/step, judge {ms_judge:.1f} ms, E {errs['learned']:.4f}")
@@ -426,6 +445,16 @@ def main():
     roofline = dict(ranked[0])
     roofline["pass1_frac"] = live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / PEAK_LANE_OPS
     others = ranked[1:]
+    if learned is not None:
+        flop = mlp_rows * MLP_FLOP_PER_ROW
+        ml = {"kernel": "k_mlp_fused (proposal MLP inference, BF16 MFMA; with the BF16 weight copy)",
+              "bound": "mfma", "achieved": flop / (ms_mlp * 1e-3) / 1e12, "peak": PEAK_MFMA_BF16 / 1e12,
+              "unit": "TFLOP/s", "ms": ms_mlp, "work": f"{mlp_rows} rows x {MLP_FLOP_PER_ROW} FLOP",
+              "traffic": None}
+        ml["frac"] = ml["achieved"] / ml["peak"]
+        if peaks is not None:
+            ml["frac_of_measured_mfma"] = ml["achieved"] / peaks["mfma_bf16_TFLOPs"]
+        others.append(ml)
 
     cpu = None
     if not args.no_cpu_baseline:
