@@ -215,7 +215,7 @@ void ora_project_one(const ora_scene *g, const ora_views *vw, const ora_params *
     else o->cbar = o->rgb[0] + o->rgb[1] + o->rgb[2];
 }
 
-/* Query variants (Section 3.4, additional variants, and Algorithm 1's
+/* Query variants (Section 3.5, additional variants, and Algorithm 1's
  * per-channel queries).  Each ray holds nq queries: one for the pixel-level
  * objectives, three (R, G, B) per channel.  A Gaussian's contributions to
  * them at a pair with attenuation rho and prefix transmittance T:
@@ -574,7 +574,7 @@ int ora_sensitivity(const ora_scene *g, const ora_views *vw, const ora_params *p
 
 /* ------------------------------------------------------------------------ */
 /* ------------------------------------------------------------------------ */
-/* Aggregated sensitivities (Section 3.4, per-tile, per-image and per-scene
+/* Aggregated sensitivities (Section 3.5, per-tile, per-image and per-scene
  * queries).  A query Q is a set of rays; a Gaussian's contribution to it is
  * a_i(Q) = sum over q in Q of a_i(q), the query objective is A(Q) = sum over
  * q in Q of A(q), and s_i = max over queries with A(Q) > 0 of a_i(Q) / A(Q).
@@ -698,7 +698,7 @@ int ora_sensitivity_agg(const ora_scene *g, const ora_views *vw, const ora_param
                         const uint32_t *ray_mask, int32_t level, double *s)
 {
     if (level < 1 || level > 3) return 1;
-    /* an aggregated query sums its rays' channels (Section 3.4), so the
+    /* an aggregated query sums its rays' channels (Section 3.5), so the
      * per-channel mode has no aggregated form of its own */
     if (n_queries(prm) != 1) return 2;
     const int32_t V = vw->n_views;
@@ -903,6 +903,16 @@ int ora_sample(const float *s, int64_t n, int64_t m, uint64_t seed,
                uint32_t *counts, double *weights, int64_t *support, uint64_t *Q_out)
 {
     if (n < 1 || m < 1) return 1;
+    /* A sensitivity is a largest share (Eq. sen), so it lies in [0, 1]; with
+     * n < 2^24 such values keep Q = sum ceil(s 2^40) below 2^64.  Anything
+     * else (NaN included) is rejected with every output zeroed. */
+    for (int64_t i = 0; i < n; ++i)
+        if (!(s[i] >= 0.0f && s[i] <= 1.0f) || n >= ((int64_t)1 << 24)) {
+            for (int64_t j = 0; j < n; ++j) { counts[j] = 0; weights[j] = 0.0; }
+            *support = 0;
+            if (Q_out) *Q_out = 0;
+            return 5;
+        }
     uint64_t *q = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     uint64_t *C = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     uint64_t acc = 0;
@@ -944,5 +954,81 @@ int ora_sample(const float *s, int64_t n, int64_t m, uint64_t seed,
         }
     *support = sup;
     free(q); free(C);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Neighbourhood of each mean for the learned sampling proposal (features of
+ * the proposal network; the paper has no learned part, so this follows the
+ * feature definition the library documents, not a passage of the paper).
+ *
+ * For every Gaussian i, its k nearest other means by brute force over every
+ * j != i.  The squared distance is a float32 value computed in this order,
+ * each operation rounded to float32:  (dx*dx + dy*dy) + dz*dz  with
+ * dx = float(x_j - x_i) etc.  Neighbours are ordered by (squared distance,
+ * index), so ties go to the smaller index.  The decision which points are
+ * neighbours is therefore taken in float32 on both sides; the features built
+ * from the neighbours are then evaluated in FP64 by the Python layer.
+ * idx [n][k]: neighbour indices (0xFFFFFFFF when fewer than k others exist);
+ * d2 [n][k]: their float32 squared distances (+inf for missing ones).
+ */
+typedef struct {
+    const float *mean;
+    int64_t n;
+    int k;
+    int64_t i0, i1;
+    uint32_t *idx;
+    float *d2;
+} knn_job;
+
+static void *knn_worker(void *arg)
+{
+    knn_job *J = (knn_job *)arg;
+    const int64_t n = J->n;
+    const float *X = J->mean, *Y = J->mean + n, *Z = J->mean + 2 * n;
+    for (int64_t i = J->i0; i < J->i1; ++i) {
+        uint32_t *bi = J->idx + i * J->k;
+        float *bd = J->d2 + i * J->k;
+        for (int t = 0; t < J->k; ++t) { bi[t] = 0xFFFFFFFFu; bd[t] = INFINITY; }
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            volatile float dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            volatile float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            volatile float s = xx + yy;
+            const float d = s + zz;
+            /* insert (d, j) into the sorted list if it precedes the last */
+            const int last = J->k - 1;
+            if (!(d < bd[last] || (d == bd[last] && (uint32_t)j < bi[last]))) continue;
+            int t = last;
+            while (t > 0 && (d < bd[t - 1] || (d == bd[t - 1] && (uint32_t)j < bi[t - 1]))) {
+                bd[t] = bd[t - 1];
+                bi[t] = bi[t - 1];
+                --t;
+            }
+            bd[t] = d;
+            bi[t] = (uint32_t)j;
+        }
+    }
+    return NULL;
+}
+
+int ora_knn(const float *mean, int64_t n, int k, int n_threads, uint32_t *idx, float *d2)
+{
+    if (n < 1 || k < 1) return 1;
+    int nt = n_threads < 1 ? 1 : n_threads;
+    if (nt > 64) nt = 64;
+    pthread_t th[64];
+    knn_job jobs[64];
+    for (int t = 0; t < nt; ++t) {
+        jobs[t].mean = mean;
+        jobs[t].n = n;
+        jobs[t].k = k;
+        jobs[t].i0 = n * t / nt;
+        jobs[t].i1 = n * (t + 1) / nt;
+        jobs[t].idx = idx;
+        jobs[t].d2 = d2;
+        pthread_create(&th[t], NULL, knn_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
     return 0;
 }

@@ -1,4 +1,4 @@
-"""FP64 NumPy reference of the proposal MLP (forward, loss, gradient).
+"""FP64 NumPy reference of the proposal MLP (forward, loss, gradient, Adam step).
 
 TEST INFRASTRUCTURE ONLY (used by the tests to check the HIP kernels).
 Network: x -> SiLU(W1 x + b1) -> SiLU(W2 . + b2) -> SiLU(W3 . + b3) -> w4 . + b4,
@@ -74,3 +74,17 @@ def loss_and_grad(P, X, y):
         dh = dz @ layers[i][0]
     grads.reverse()
     return loss, pack(grads, g_w4, g_b4)
+
+
+def adam_step(P, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, Algorithm 1) in FP64:
+    m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2;
+    P <- P - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+    with t = step >= 1.  Returns the new (P, m, v)."""
+    P = np.asarray(P, np.float64)
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return P - lr * mhat / (np.sqrt(vhat) + eps), m, v

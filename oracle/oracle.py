@@ -69,6 +69,8 @@ def _load():
         _lib.ora_draw_target.argtypes = [P, C.c_uint64]
         _lib.ora_draw_target.restype = C.c_uint64
         _lib.ora_sh_basis.argtypes = [C.c_double, C.c_double, C.c_double, P]
+        _lib.ora_knn.argtypes = [P, C.c_int64, C.c_int, C.c_int, P, P]
+        _lib.ora_knn.restype = C.c_int
         for f in (_lib.ora_sensitivity, _lib.ora_sensitivity_agg, _lib.ora_objective, _lib.ora_sample):
             f.restype = C.c_int
     return _lib
@@ -141,7 +143,7 @@ def sensitivity_agg(scene, views, level, params=None, ray_mask=None):
     """Aggregated sensitivities s[n] (float64) for queries that are 16x16
     tiles (level 1), whole views (2) or the whole scene (3): the maximum over
     queries of a_i(Q) / A(Q) with both summed over the query's rays
-    (Section 3.4).  Level 0 is the per-ray sensitivity."""
+    (Section 3.5).  Level 0 is the per-ray sensitivity."""
     if level == AGG_RAY:
         return sensitivity(scene, views, params, ray_mask)["s"]
     lib = _load()
@@ -200,7 +202,8 @@ def project(scene, views, params=None):
 
 
 def sample(s_f32, m, seed):
-    """Counts u32[n], weights f64[n], support, Q and status (0 ok, 4 if all s = 0)."""
+    """Counts u32[n], weights f64[n], support, Q and status (0 ok, 4 if all s = 0,
+    5 if some s is outside [0, 1] or NaN: outputs zeroed)."""
     lib = _load()
     s = np.ascontiguousarray(s_f32, np.float32)
     n = s.shape[0]
@@ -233,3 +236,83 @@ def sh_basis(d):
     Y = np.zeros(16, np.float64)
     lib.ora_sh_basis(float(d[0]), float(d[1]), float(d[2]), _ptr(Y))
     return Y
+
+
+# --------------------------------------------------------------------------
+# Features of the learned sampling proposal.  The paper has no learned part:
+# these follow the feature definition the library documents (64 values per
+# Gaussian), evaluated in FP64 from neighbour sets chosen in float32.
+N_FEATURES = 64
+KNN_K = 16
+
+
+def knn(mean, k=KNN_K, n_threads=None):
+    """k nearest other means of every Gaussian by brute force over all pairs:
+    float32 squared distances ((dx dx + dy dy) + dz dz, each step rounded to
+    float32), ordered by (distance, index).  mean: float32 [3][n].
+    Returns (idx uint32 [n][k], 0xFFFFFFFF where fewer than k others exist;
+    d2 float32 [n][k], +inf there)."""
+    lib = _load()
+    m = np.ascontiguousarray(mean, np.float32).reshape(3, -1)
+    n = m.shape[1]
+    idx = np.zeros((n, k), np.uint32)
+    d2 = np.zeros((n, k), np.float32)
+    rc = lib.ora_knn(_ptr(m), n, int(k), int(n_threads or os.cpu_count() or 1), _ptr(idx), _ptr(d2))
+    assert rc == 0
+    return idx, d2
+
+
+def features(scene, k=KNN_K):
+    """FP64 features [n][64] of the learned proposal, from the float32 scene:
+      0-2 mean, 3-5 log-scale, 6-9 quaternion / |quaternion| with the sign
+      that makes w >= 0 (w = 0 keeps the sign), 10 logit(alpha) with alpha
+      first clamped in float32 to [1e-6, 1 - 1e-6], 11-58 the SH
+      coefficients in plane order (zero past the scene's degree), and over
+      the k nearest other means (``knn``): 59 log of their mean distance,
+      60 log of the k-th distance d_k, 61 mean and 62 largest neighbour
+      opacity, 63 log(sum of neighbour opacities / (4/3 pi d_k^3)); each
+      logarithm's argument is first raised to at least 1e-12.  With no
+      neighbour at all: 59 = 60 = 0, 61 = 62 = 0 and d_k = 1 in 63."""
+    n = scene.n
+    f = np.zeros((n, N_FEATURES), np.float64)
+    mean = np.asarray(scene.mean, np.float32).reshape(3, n)
+    f[:, 0:3] = mean.T
+    f[:, 3:6] = np.asarray(scene.log_scale, np.float32).reshape(3, n).T
+    q = np.asarray(scene.quat, np.float32).reshape(4, n).T.astype(np.float64)
+    qn = q / np.linalg.norm(q, axis=1, keepdims=True)
+    qn[q[:, 0] < 0] *= -1.0
+    f[:, 6:10] = qn
+    op = np.asarray(scene.opacity, np.float32).reshape(n)
+    lo, hi = np.float32(1e-6), np.float32(1.0) - np.float32(1e-6)
+    a = np.minimum(np.maximum(op, lo), hi).astype(np.float64)
+    f[:, 10] = np.log(a / (1.0 - a))
+    sh = np.asarray(scene.sh, np.float32).reshape(-1, n)
+    nsh = min(sh.shape[0], 48)
+    f[:, 11:11 + nsh] = sh[:nsh].T
+    idx, d2 = knn(mean, k)
+    valid = idx != np.uint32(0xFFFFFFFF)
+    cnt = valid.sum(axis=1)
+    dist = np.where(valid, np.sqrt(np.where(valid, d2, 0).astype(np.float64)), 0.0)
+    nb_a = np.where(valid, op[np.where(valid, idx, 0)].astype(np.float64), 0.0)
+    has = cnt > 0
+    dk = np.ones(n)
+    dk[has] = dist[has, cnt[has] - 1]
+    tiny = 1e-12
+    mean_d = np.where(has, dist.sum(axis=1) / np.maximum(cnt, 1), 1.0)
+    f[:, 59] = np.log(np.maximum(mean_d, tiny))
+    f[:, 60] = np.log(np.maximum(dk, tiny))
+    f[:, 61] = np.where(has, nb_a.sum(axis=1) / np.maximum(cnt, 1), 0.0)
+    f[:, 62] = nb_a.max(axis=1)
+    vol = 4.0 / 3.0 * np.pi * dk ** 3
+    f[:, 63] = np.log(np.maximum(nb_a.sum(axis=1), tiny) / np.maximum(vol, tiny))
+    return f, idx, d2
+
+
+# --------------------------------------------------------------------------
+# Theorem 3 (finite-query rendered coreset): a fixed-objective guarantee eps_c
+# and log-transmittance stability gamma give the rendered guarantee eps_r.
+def eps_rendered(gamma, eps_c):
+    """eps_r = max{1 - e^-gamma (1 - eps_c), e^gamma (1 + eps_c) - 1}."""
+    g = np.asarray(gamma, np.float64)
+    e = np.asarray(eps_c, np.float64)
+    return np.maximum(1.0 - np.exp(-g) * (1.0 - e), np.exp(g) * (1.0 + e) - 1.0)

@@ -1,4 +1,4 @@
-"""Aggregated sensitivities (Section 3.4: queries that are 16x16 tiles, whole
+"""Aggregated sensitivities (Section 3.5: queries that are 16x16 tiles, whole
 views or the whole scene) of the HIP path against the FP64 oracle, through
 the C ABI.
 

@@ -1,5 +1,5 @@
 """Score variants of the HIP path against the FP64 oracle, through the C ABI
-(Section 3.4: the L2 contribution c^2 rho^2 T^2 with the three channel terms
+(Section 3.5: the L2 contribution c^2 rho^2 T^2 with the three channel terms
 summed per pixel, and Algorithm 1's per-channel queries c_k rho T; the
 nocolor variant is covered with the per-ray parity tests).
 

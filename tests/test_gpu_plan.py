@@ -159,6 +159,7 @@ def test_capacity_guard(gs):
     with pytest.raises(gs.GsError) as e:
         plan.status()
     assert e.value.status == 5
+    assert "more tile-list entries" in str(e.value) and "depth keys" not in str(e.value)
     assert float(outs[0].abs().max()) == 0.0
     ref1 = gs.sensitivity(*batch[1])[0]
     assert _same(outs[1], ref1)
@@ -189,6 +190,7 @@ def test_depth_span_guard(gs):
     with pytest.raises(gs.GsError) as e:
         plan.status()
     assert e.value.status == 5
+    assert "depth keys spanned" in str(e.value) and "tile-list entries" not in str(e.value)
     assert float(outs[0].abs().max()) == 0.0
     assert _same(outs[1], gs.sensitivity(*batch[1])[0])
     plan.close()

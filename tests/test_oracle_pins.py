@@ -235,7 +235,7 @@ def test_telescoping_and_two_gaussian_closed_form(ora):
 
 
 def test_l2_closed_forms(ora):
-    """L2 queries (Section 3.4): on the central ray (rho_j = alpha_j)
+    """L2 queries (Section 3.5): on the central ray (rho_j = alpha_j)
     A = sum_j (c_R^2 + c_G^2 + c_B^2)_j alpha_j^2 T_j^2; for n equal
     Gaussians of colour c this is the geometric series
     |c|^2 alpha^2 (1 - (1 - alpha)^(2n)) / (1 - (1 - alpha)^2)."""
@@ -401,7 +401,7 @@ def test_adding_views_never_lowers_sensitivity(ora):
 def _mp_ray_contributions(sc, vw, W, H, mode=0):
     """All (ray, Gaussian) pairs in 50-digit arithmetic, no bounding boxes, no
     sorting shortcuts: {(view, px, py): ([A_q], [(i, [a_q])])} over every
-    ray, for the queries of `mode` (Section 3.4): one with c_R + c_G + c_B
+    ray, for the queries of `mode` (Section 3.5): one with c_R + c_G + c_B
     (0), with colour 1 (1), the L2 form sum_k c_k^2 rho^2 T^2 (2), or three
     with c_R, c_G, c_B (3)."""
     import mpmath as mp
@@ -478,7 +478,7 @@ def _bruteforce_scene(n, W, H, seed):
 def test_bruteforce_mpmath_tiny(ora, mode):
     """The oracle's per-ray sensitivities and query objectives agree with
     50-digit brute force to ~1e-13 for every query mode: RGB sum, nocolor,
-    L2 and per channel (Section 3.4; Algorithm 1's channel queries)."""
+    L2 and per channel (Section 3.5; Algorithm 1's channel queries)."""
     import mpmath as mp
     n, W, H = 6, 10, 8
     sc, vw = _bruteforce_scene(n, W, H, 11)
@@ -502,7 +502,7 @@ def test_bruteforce_mpmath_tiny(ora, mode):
 @pytest.mark.parametrize("mode", [0, 2])
 def test_bruteforce_mpmath_aggregated(ora, mode):
     """Per-tile (16x16, ragged at the edges), per-image and per-scene
-    sensitivities (Section 3.4): a_i and A summed over each query's rays in
+    sensitivities (Section 3.5): a_i and A summed over each query's rays in
     50-digit arithmetic, then the maximum over queries of their ratio (for
     the L1 and the L2 contributions)."""
     import mpmath as mp
@@ -569,6 +569,17 @@ def test_sampler_bookkeeping_and_zero_support(ora):
     assert r["Q"] == int(q.sum())
     bad = ora.sample(np.zeros(10, np.float32), 5, 0)
     assert bad["status"] == 4 and bad["support"] == 0
+    # a sensitivity is a largest share, so it lies in [0, 1]; anything else
+    # would let ceil(s 2^40) or Q overflow 64 bits and is rejected
+    for v in (np.nextafter(np.float32(1), np.float32(2)), np.float32(2.0 ** 30), np.nan, np.inf,
+              np.float32(-1e-30)):
+        x = s.copy()
+        x[5] = v
+        r = ora.sample(x, 10, 0)
+        assert r["status"] == 5 and r["support"] == 0 and not r["counts"].any() and not r["weights"].any()
+    ones = np.ones(4096, np.float32)
+    r = ora.sample(ones, 100, 0)
+    assert r["status"] == 0 and r["Q"] == 4096 * 2 ** 40
 
 
 def test_sampler_draws_match_bigint_definition(ora):
@@ -645,7 +656,7 @@ def test_zero_variance_when_sensitivity_is_proportional_to_contribution(ora):
 
 
 def test_per_scene_sensitivities_give_zero_variance(ora):
-    """With per-scene sensitivities (Section 3.4) the sampling probabilities
+    """With per-scene sensitivities (Section 3.5) the sampling probabilities
     are a_i(Q) / A(Q) for the single query Q holding every ray, so every draw
     reproduces the scene's total objective: sum over all rays of A^th_w equals
     sum of A, up to the 2^-40 quantisation of the probabilities; per-ray
@@ -726,6 +737,43 @@ def test_transfer_sandwich(ora):
     if ob["n_invalid"] == 0:
         assert np.all(At >= lo - 1e-300) and np.all(At <= hi + 1e-300)
     assert g > 0
+
+
+def test_eps_rendered_closed_forms(ora):
+    """Theorem 3's eps_r: gamma = 0 gives eps_c back; eps_c = 0 gives
+    e^gamma - 1 (the upper branch wins for gamma > 0); it grows with both."""
+    e = np.linspace(0, 0.9, 10)
+    assert np.allclose(ora.eps_rendered(0.0, e), e, atol=1e-15)
+    g = np.linspace(0, 3, 13)
+    assert np.allclose(ora.eps_rendered(g, 0.0), np.expm1(g), rtol=1e-14, atol=1e-15)
+    assert abs(ora.eps_rendered(np.log(2.0), 0.5) - max(1 - 0.5 * 0.5, 2 * 1.5 - 1)) < 1e-15
+    G, E = np.meshgrid(np.linspace(0, 2, 9), np.linspace(0, 0.9, 9))
+    r = ora.eps_rendered(G, E)
+    assert np.all(np.diff(r, axis=0) > 0) and np.all(np.diff(r, axis=1) >= 0)
+    assert np.all(r >= E - 1e-15)
+
+
+def test_rendered_bound_holds_for_valid_weights(ora):
+    """Theorem 3's deterministic step: for any valid w (every w rho < 1) with
+    measured gamma and eps_c = max_q |A^th_w - A| / A, every ray satisfies
+    |A_w - A| <= eps_r A.  Weights of 0.6-1.4 on a scene with alpha <= 0.6
+    keep w rho < 1."""
+    sc, vw, _, _ = synth.make_config("tiny")
+    sc.opacity = np.ascontiguousarray(np.minimum(sc.opacity, 0.6).astype(np.float32))
+    rng = np.random.default_rng(9)
+    w = rng.uniform(0.6, 1.4, sc.n)
+    ob = ora.objective(sc, vw, w)
+    assert ob["n_invalid"] == 0
+    on = ob["A"] > 0
+    A, Af, At = ob["A"][on], ob["A_fixed"][on], ob["A_true"][on]
+    eps_c = float(np.max(np.abs(Af - A) / A))
+    g = ob["gamma"]
+    assert g > 0 and 0 < eps_c < 1
+    eps_r = float(ora.eps_rendered(g, eps_c))
+    err = np.abs(At - A) / A
+    assert np.all(err <= eps_r * (1 + 1e-9)), (err.max(), eps_r)
+    # the reduced render really differs from the fixed relaxation here
+    assert np.max(np.abs(At - Af) / Af) > 1e-2
 
 
 # --------------------------------------------------------------------------
