@@ -326,3 +326,31 @@ def make_camera_set(eyes, targets, width, height, fov_deg=60.0, up=(0.0, 0.0, 1.
     intr = np.stack([_intrinsics(width, height, fov_deg)] * len(w2c))
     size = np.array([[width, height]] * len(w2c), dtype=np.int32)
     return Views(w2c, intr, size)
+
+
+def _ball(rng, radius):
+    """A point uniform in the 3D ball of the given radius."""
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v) * radius * rng.uniform() ** (1.0 / 3.0)
+
+
+def make_pose_region(w2c0, n_poses: int, pos_radius: float, ang_radius: float, seed: int = 0):
+    """Camera poses around the world-to-camera pose `w2c0` ([12], [R | t]):
+    the first is w2c0 itself; each other has its centre moved uniformly within
+    `pos_radius` and its orientation turned by a rotation vector drawn
+    uniformly within `ang_radius` radians (world frame).  Returns a list of
+    [12] arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M0 = np.asarray(w2c0, np.float64).reshape(3, 4)
+    R0, t0 = M0[:, :3], M0[:, 3]
+    c0 = -R0.T @ t0
+    out = [M0.ravel().copy()]
+    for _ in range(n_poses - 1):
+        w = _ball(rng, ang_radius)
+        th = np.linalg.norm(w)
+        K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]]) / max(th, 1e-300)
+        Rw = np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * (K @ K)
+        R = R0 @ Rw.T          # camera turned by Rw in the world frame
+        c = c0 + _ball(rng, pos_radius)
+        out.append(np.concatenate([R, (-R @ c)[:, None]], 1).ravel())
+    return out
