@@ -903,11 +903,13 @@ int ora_sample(const float *s, int64_t n, int64_t m, uint64_t seed,
                uint32_t *counts, double *weights, int64_t *support, uint64_t *Q_out)
 {
     if (n < 1 || m < 1) return 1;
-    /* A sensitivity is a largest share (Eq. sen), so it lies in [0, 1]; with
-     * n < 2^24 such values keep Q = sum ceil(s 2^40) below 2^64.  Anything
-     * else (NaN included) is rejected with every output zeroed. */
+    /* A sensitivity is a largest share (Eq. sen), so it lies in [0, 1]; the
+     * float32 value of a share can exceed 1 by a few ulps, so values up to
+     * 1 + 2^-10 are accepted.  With n <= 2^24 - 2^16 such values keep
+     * Q = sum ceil(s 2^40) below 2^64.  Anything else (NaN included) is
+     * rejected with every output zeroed. */
     for (int64_t i = 0; i < n; ++i)
-        if (!(s[i] >= 0.0f && s[i] <= 1.0f) || n >= ((int64_t)1 << 24)) {
+        if (!(s[i] >= 0.0f && s[i] <= 1.0009765625f) || n > ((int64_t)1 << 24) - ((int64_t)1 << 16)) {
             for (int64_t j = 0; j < n; ++j) { counts[j] = 0; weights[j] = 0.0; }
             *support = 0;
             if (Q_out) *Q_out = 0;

@@ -203,7 +203,7 @@ def project(scene, views, params=None):
 
 def sample(s_f32, m, seed):
     """Counts u32[n], weights f64[n], support, Q and status (0 ok, 4 if all s = 0,
-    5 if some s is outside [0, 1] or NaN: outputs zeroed)."""
+    5 if some s is outside [0, 1 + 2^-10] or NaN: outputs zeroed)."""
     lib = _load()
     s = np.ascontiguousarray(s_f32, np.float32)
     n = s.shape[0]

@@ -569,14 +569,19 @@ def test_sampler_bookkeeping_and_zero_support(ora):
     assert r["Q"] == int(q.sum())
     bad = ora.sample(np.zeros(10, np.float32), 5, 0)
     assert bad["status"] == 4 and bad["support"] == 0
-    # a sensitivity is a largest share, so it lies in [0, 1]; anything else
-    # would let ceil(s 2^40) or Q overflow 64 bits and is rejected
-    for v in (np.nextafter(np.float32(1), np.float32(2)), np.float32(2.0 ** 30), np.nan, np.inf,
-              np.float32(-1e-30)):
+    # a sensitivity is a largest share, so it lies in [0, 1] up to the float32
+    # rounding of the share; anything past 1 + 2^-10 could let Q overflow 64
+    # bits and is rejected
+    for v in (np.float32(1.001), np.float32(2.0 ** 30), np.nan, np.inf, np.float32(-1e-30)):
         x = s.copy()
         x[5] = v
         r = ora.sample(x, 10, 0)
         assert r["status"] == 5 and r["support"] == 0 and not r["counts"].any() and not r["weights"].any()
+    for v in (np.nextafter(np.float32(1), np.float32(2)), np.float32(1 + 2.0 ** -10)):
+        x = s.copy()
+        x[5] = v
+        r = ora.sample(x, 10, 0)
+        assert r["status"] == 0 and r["Q"] == int(np.ceil(np.asarray(x, np.float64) * 2.0 ** 40).sum())
     ones = np.ones(4096, np.float32)
     r = ora.sample(ones, 100, 0)
     assert r["status"] == 0 and r["Q"] == 4096 * 2 ** 40
