@@ -95,20 +95,40 @@ def copy_calibration(torch):
     del src, dst
 
 
-def cpu_baseline(scene, views, n_views_total, n_sample=5):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, views, n_views_total, gpu_live_sample, m, seed, s_gpu, n_sample=5):
     """FP64 oracle on the first `n_sample` views (all of their rays), scaled to
-    the full view count.  Runs on all host cores."""
+    the full view count, on all host cores; its live-pair count on those views
+    beside the GPU's on the same views (the roofline's unit); and the
+    single-threaded oracle sampler on the whole workload's sensitivities."""
     from oracle import oracle as ora
     ora.build(force=False)
     v1 = views.subset(list(range(n_sample)))
     t0 = time.perf_counter()
     r = ora.sensitivity(scene, v1)
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    smp = ora.sample(s_gpu, m, seed)
+    dt_s = time.perf_counter() - t0
     return {"value": dt * n_views_total / n_sample * 1e3, "unit": "ms", "cores": ora.default_params()["n_threads"],
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n_sample} of {n_views_total} views ({int(v1.size[0,0])}x{int(v1.size[0,1])}, all rays), "
                       f"{dt:.2f} s measured, scaled x{n_views_total / n_sample:g}",
-            "sample_pairs": r["pairs"]}
+            "sample_pairs": r["pairs"], "sample_live_pairs_oracle": r["live_pairs"],
+            "sample_live_pairs_gpu": gpu_live_sample,
+            "sample_live_ratio_gpu_to_oracle": gpu_live_sample / max(r["live_pairs"], 1),
+            "sampler_ms_1core": dt_s * 1e3,
+            "sampler_sample": f"oracle sampler on all {scene.n} sensitivities, m={m}, one thread",
+            "sampler_status": smp["status"]}
 
 
 def batch_leg(gs, synth, torch, args):
@@ -177,6 +197,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true", help="skip the nocolor, L2 and per-channel score variants")
     ap.add_argument("--no-transfer", action="store_true", help="skip the transfer study on the judge rays")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate microbenchmarks")
+    ap.add_argument("--no-region", action="store_true", help="skip the compact-region bound")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (reference dispatch for counter runs)")
     args = ap.parse_args()
@@ -365,18 +386,25 @@ def main():
         log(f"learned: {ms_l:.2f} ms/step, judge {ms_judge:.1f} ms, E {errs['learned']:.4f}")
         scores_learned = scores
 
-    # E against m for each proposal (same judge rays)
-    scan = {}
+    # E against m for each proposal: on the judge rays (1% of the 8x8 blocks)
+    # and on every ray of every view (the per-image objective over all rays)
+    scan, scan_all = {}, {}
     props = {"exact": s, "mixed16": s16, "uniform": torch.ones_like(s)}
     if learned is not None:
         props["learned"] = scores_learned
+    m_grid = (100_000, 200_000, 400_000, 800_000, 1_600_000, 3_200_000)
     for name, sc_ in props.items():
-        scan[name] = {}
-        for mm in (100_000, 200_000, 400_000, 800_000):
+        scan[name], scan_all[name] = {}, {}
+        for mm in m_grid:
             _, w_, _ = gs.sample_coreset(sc_, mm, seed)
             ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, ray_mask=sub, per_ray=False, diag=False)
             scan[name][str(mm)] = gs.coreset_error(ob["per_view"])
-    log(f"E vs m: {json.dumps(scan)}")
+            if name != "mixed16":
+                ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, per_ray=False, diag=False)
+                scan_all[name][str(mm)] = gs.coreset_error(ob["per_view"])
+    passes_at = {name: next((int(k) for k, v in tab.items() if v <= 0.01), None) for name, tab in scan_all.items()}
+    log(f"E vs m (judge rays): {json.dumps(scan)}")
+    log(f"E vs m (all rays): {json.dumps(scan_all)}; smallest m with E <= 1%: {passes_at}")
 
     # transfer study (untimed): for coresets of 1-20% of N drawn from the exact
     # sensitivities, the validity violations (w rho >= 1, Definition 2), the
@@ -405,9 +433,43 @@ def main():
                 "ray_err_true": {"median": float(e_tr.median()), "p99": float(e_tr.quantile(0.99)),
                                  "max": float(e_tr.max())},
                 "E_fixed": gs.coreset_error(fx["per_view"]),
-                "E_true": float(np.max(np.abs(pv[:, 2] - pv[:, 0]) / np.maximum(pv[:, 0], 1e-30))),
+                "E_true": gs.coreset_error(tr["per_view"], reduced=True),
             }
+            # Theorem 3's rendered bound from the measured gamma and eps_c (the
+            # largest per-ray error of the fixed relaxation); it applies only
+            # when every w rho < 1 (Definition 2)
+            g_, ec = tr["gamma_max"], float(e_fix.max())
+            with np.errstate(over="ignore"):
+                er = max(1.0 - np.exp(-g_) * (1.0 - ec), np.expm1(g_) + np.exp(g_) * ec)
+            transfer[f"{frac:.2f}"]["eps_c"] = ec
+            transfer[f"{frac:.2f}"]["eps_r_bound"] = float(er) if np.isfinite(er) else None
+            transfer[f"{frac:.2f}"]["valid"] = tr["n_invalid_pairs"] == 0
         log(f"transfer: {json.dumps(transfer)}")
+
+    # compact-region extension (untimed): 32 poses around the first camera
+    # (centres within 0.06, orientations within 0.03 rad), the exact draw at
+    # m = 10^5 judged by the true reduced render, representatives every 0.04
+    region_rep = None
+    if not args.no_region:
+        K = 32
+        w2c = synth.make_pose_region(views.world_to_cam[0], K, 0.06, 0.03, seed=7)
+        rv = synth.Views(np.stack(w2c), np.repeat(views.intrinsics[:1], K, 0), np.repeat(views.size[:1], K, 0))
+        P = int(views.size[0, 0]) * int(views.size[0, 1])
+        t0 = time.perf_counter()
+        fullr = gs.render_objective(dsc, rv, None, gs.OBJ_FULL, per_view=False, diag=False)["per_ray"]
+        region_rep = {}
+        for name, obj in (("true", gs.OBJ_TRUE), ("fixed", gs.OBJ_FIXED)):
+            red = gs.render_objective(dsc, rv, w, obj, per_view=False, diag=False)["per_ray"]
+            rep, net = gs.region_bound(rv.world_to_cam, fullr.reshape(K, P).contiguous(),
+                                       red.reshape(K, P).contiguous(), lam=1.0, rho_target=0.04, a_floor=1e-2)
+            rep["rho_for_10pct"] = ((0.10 - rep["eps_0"]) * rep["A_min"] /
+                                    ((1 + rep["eps_0"]) * rep["L_full"] + rep["L_w"])) if rep["eps_0"] < 0.1 else None
+            region_rep[name] = rep
+            del red
+        del fullr
+        region_rep["poses"] = K
+        region_rep["seconds"] = time.perf_counter() - t0
+        log(f"region: {json.dumps(region_rep)}")
 
     batching = None
     if not args.no_batch:
@@ -441,6 +503,19 @@ def main():
     em["frac"] = em["achieved"] / em["peak"]
     if peaks:
         em["frac_of_measured_copy"] = em["achieved"] / peaks["copy_GBps"]
+    # whole pass against its two bounds (the algorithmic work of every stage):
+    # compositing VALU slots of both passes, and the minimum HBM bytes
+    # (records written and read, 96 B per visible (view, Gaussian); one sort
+    # read + write, 16 B; list entries written, read and their two index
+    # gathers, 32 B; the attributes once; the sampler's arrays)
+    t_valu = live * (OPS_PASS1 + OPS_PASS2) / PEAK_LANE_OPS * 1e3
+    hbm_bytes = (96 + 16) * cst["n_projected"] + 32 * cst["n_entries"] + dsc.attribute_bytes() + \
+        scene.n * (4 + 8 + 16 + 12) + m * int(np.ceil(np.log2(scene.n))) * 8
+    t_hbm = hbm_bytes / PEAK_HBM * 1e3
+    whole = {"T_valu_ms": t_valu, "T_hbm_ms": t_hbm, "hbm_bytes": hbm_bytes,
+             "roof_overlapped_ms": max(t_valu, t_hbm), "roof_summed_ms": t_valu + t_hbm,
+             "frac_overlapped": max(t_valu, t_hbm) / ms, "frac_summed": (t_valu + t_hbm) / ms}
+    log(f"whole pass: {json.dumps(whole)}")
     ranked = sorted([p2, em], key=lambda r: -r["ms"])
     roofline = dict(ranked[0])
     roofline["pass1_frac"] = live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / PEAK_LANE_OPS
@@ -459,7 +534,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on five views) ...")
-        cpu = cpu_baseline(scene, views, args.views)
+        _, st5 = gs.sensitivity(dsc, views.subset(list(range(5))), stats=True, count_pairs=True)
+        cpu = cpu_baseline(scene, views, args.views, st5["n_live_pairs"], m, seed, s.cpu().numpy())
 
     out = {
         "metric": "sensitivity pass ms (1M G x 100 views): exact vs learned/BF16 at <=1% err",
@@ -474,6 +550,9 @@ def main():
                                  "attribute_bytes": d16.attribute_bytes()},
                      "learned": learned, "aggregated": aggregated, "score_variants": modes},
         "coreset_err_vs_m": scan,
+        "coreset_err_vs_m_all_rays": scan_all, "smallest_m_with_err_le_1pct_all_rays": passes_at,
+        "whole_pass_roofline": whole,
+        "region": region_rep,
         "transfer": transfer,
         "coreset_err_def": "max over views of |sum A^th_w - sum A| / sum A on 1% of the 8x8 pixel blocks, m=100000",
         "pairs": {"live": live, "in_footprint": cst["n_pairs"], "lane_evaluations": cst["n_lane_pairs"],

@@ -49,7 +49,7 @@ typedef enum {
 } gs_status;
 
 typedef enum { GS_ATTR_F32 = 0, GS_ATTR_MIXED16 = 1 } gs_attr_format;
-/* What a query measures (Section 3.4, score variants; Algorithm 1's channel
+/* What a query measures (Section 3.5, score variants; Algorithm 1's channel
  * queries).  With rho the attenuation of a pair and T the transmittance in
  * front of it, a Gaussian's contribution to a query of its ray is
  *   GS_QUERY_RGBSUM:  (c_R + c_G + c_B) rho T   (one query per ray: the L1
@@ -72,7 +72,7 @@ typedef enum { GS_OBJ_FULL = 0, GS_OBJ_FIXED = 1, GS_OBJ_TRUE = 2 } gs_objective
 /* GS_FLAG_COUNT_PAIRS: gs_sensitivity fills the pair counters of gs_stats
  * (a pass-2 variant that counts; without it those counters read 0). */
 typedef enum { GS_FLAG_COUNT_PAIRS = 1 } gs_flag;
-/* Query granularity of the sensitivity (Section 3.4, practical extensions):
+/* Query granularity of the sensitivity (Section 3.5, practical extensions):
  * a query is one ray (GS_AGG_RAY, Eq. sen), the rays of one 16x16 pixel tile
  * of a view (ragged at the right and bottom edges), the rays of one view, or
  * every ray (the per-scene variant).  For an aggregated query Q,
@@ -123,6 +123,12 @@ typedef struct {
     int32_t flags;            /* GS_FLAG_* bits */
     const uint32_t *ray_mask; /* device bitset over all rays (bit r%32 of word r/32), NULL = all */
     int32_t aggregate;        /* gs_aggregate: query granularity of gs_sensitivity; default GS_AGG_RAY */
+    /* gs_sensitivity with GS_FLAG_COUNT_PAIRS (per-ray queries): device bitset
+     * over all rays (as ray_mask) into which the bit of every scored ray that
+     * holds an ambiguous pair (|d^2 - r^2| <= 1e-5 r^2: float32 and float64
+     * may put it on different sides of the cutoff) is OR-ed; the caller
+     * clears it.  NULL = not reported.  Must be NULL for other calls. */
+    uint32_t *ambiguous_rays;
 } gs_params;
 
 /* Filled only when a non-NULL pointer is passed (the call then synchronises
@@ -141,6 +147,13 @@ typedef struct {
     double ms_project, ms_sort, ms_bin, ms_pass1, ms_pass2; /* device time per stage, summed over chunks */
     double ms_emit;           /* the tile-list emission kernel alone (part of ms_bin) */
     int64_t n_bins;           /* (tile, chunk) segments: tiles x chunks of 16384 depth positions */
+    int32_t sort_passes;      /* most 8-bit passes a view chunk's depth sort took: 3 when every view's
+                                 depth keys span under 2^24 - 1, else 4 */
+    int32_t pad0;
+    int64_t n_ambiguous_keys; /* (view, Gaussian) pairs in front of the camera whose FP64 depth lies within
+                                 2^-40 of a midpoint between float32 values (its key could round either way) */
+    int64_t n_ambiguous_pairs; /* pass-2 pairs on scored rays with |d^2 - r^2| <= 1e-5 r^2 (needs
+                                  GS_FLAG_COUNT_PAIRS) */
 } gs_stats;
 
 typedef struct {
@@ -176,10 +189,15 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
  * sum exceeds floor(u Q / 2^128).  counts[i] = number of draws of i;
  * weights[i] = counts[i] Q / (m q_i) in IEEE double (0 if not drawn);
  * support[0] = number of distinct drawn i.
- * sens: device float[n], all >= 0 and finite, n < 2^24.  counts: device
- * uint32[n]; weights: device double[n]; support: device int64[1]; 1 <= m < 2^31.
- * Returns GS_ERR_NO_POSITIVE_SENSITIVITY (outputs zeroed) if Q = 0.
- * Synchronises the stream once (to read Q). */
+ * sens: device float[n], every value in [0, 1 + 2^-10] (a sensitivity is a
+ * largest share, Eq. sen, at most 1 up to the float32 rounding of the share;
+ * a normalised proposal also qualifies), n <= 2^24 - 2^16, which keeps Q
+ * below 2^64.  counts: device uint32[n]; weights: device double[n];
+ * support: device int64[1]; 1 <= m < 2^31.
+ * Returns GS_ERR_INVALID_DATA if some sens[i] is outside [0, 1 + 2^-10] or
+ * NaN (detected on the device) and GS_ERR_NO_POSITIVE_SENSITIVITY if Q = 0;
+ * in both cases the outputs are zeroed and nothing is drawn.
+ * Synchronises the stream once (to read Q and the range check). */
 gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t seed,
                             uint32_t *counts, double *weights, int64_t *support, void *stream);
 
@@ -201,6 +219,52 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
 gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, const gs_params *params,
                               const double *weights, int32_t objective, float *per_ray,
                               double *per_view, gs_render_diag *diag, void *stream);
+
+/* Coreset-objective error of a weighted draw at per-image resolution
+ * (Definition 1 applied to objectives aggregated over each view's scored
+ * rays, Section 3.5): from the per-view sums of gs_render_objective,
+ *   out[0] = max over views with sum A > 0 of |sum A^th_w - sum A| / sum A,
+ *   out[1] = the same with the reduced render sum A_w (column 2; 0 when
+ *            that column was not computed),
+ * in FP64 (the maximum is order-free, so the result is deterministic).
+ * per_view: device double[n_views][3]; out: device double[2].  Queued on
+ * the stream; no synchronisation. */
+gs_status gs_coreset_error(const double *per_view, int32_t n_views, double *out, void *stream);
+
+/* ---- Compact-region extension (Section 3.4: Assumption 2, the rho-net
+ * definition, Theorem 4) -------------------------------------------------
+ * A query region: sampled camera poses around a representative one (same
+ * intrinsics and pixels), with the pose distance
+ *   d(q, q') = |c - c'| + lambda * angle(R R'^T)
+ * (camera centres c = -R^T t; lambda in length units per radian).  From the
+ * per-ray full and reduced renders at every sampled pose (gs_render_objective
+ * per_ray with GS_OBJ_FULL and GS_OBJ_TRUE, or GS_OBJ_FIXED for the fixed
+ * relaxation), the call
+ *   - picks representatives greedily (the first pose, then repeatedly the
+ *     pose farthest from those chosen) until every sampled pose is within
+ *     rho_target of one: is_net (host int32[n_poses]) = 1 for them, and
+ *     rho = the covering radius reached;
+ *   - keeps the pixels with A > a_floor at every pose (Assumption 2 (iv));
+ *   - estimates L_full and L_w as the largest |A(q) - A(q')| / d(q, q') and
+ *     |A_w(q) - A_w(q')| / d(q, q') over pairs of poses and kept pixels;
+ *   - A_min = smallest A there; eps_0 = largest |A - A_w| / A over the
+ *     representatives; max_err = the same over every pose;
+ *   - eps_reg = eps_0 + ((1 + eps_0) L_full + L_w) rho / A_min (Theorem 4).
+ * The constants are estimates from the samples (lower bounds of the true
+ * ones), so the bound holds at every sampled query by construction of the
+ * estimates; max_err shows how tight it is.
+ * world_to_cam: host double[n_poses][12]; A, A_w: device float
+ * [n_poses][n_pixels] (pose-major); 2 <= n_poses <= 4096.  Synchronises the
+ * stream.  GS_ERR_NO_POSITIVE_SENSITIVITY if no pixel is kept. */
+typedef struct {
+    double L_full, L_w, A_min, eps_0, rho, eps_reg, max_err;
+    int64_t n_pixels;     /* pixels kept */
+    int32_t n_net;        /* representatives */
+    int32_t pad;
+} gs_region_report;
+gs_status gs_region_bound(const double *world_to_cam, int32_t n_poses, double lambda, double rho_target,
+                          const float *A, const float *A_w, int64_t n_pixels, float a_floor, int32_t *is_net,
+                          gs_region_report *report, void *stream);
 
 /* ---- Batched plans -------------------------------------------------------
  * A plan runs the sensitivity pass (Algorithm 1, steps 1-3) of several
@@ -273,8 +337,10 @@ gs_status gs_plan_get_info(const gs_plan *plan, gs_plan_info *info);
 gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream);
 
 /* Synchronises the stream and returns GS_ERR_INVALID_DATA if, in any run
- * since creation, a scene needed more tile-list entries than its capacity
- * (that scene's output of that run is then all zeros). */
+ * since creation, a scene needed more tile-list entries than its capacity,
+ * or a view of a scene planned for the three-pass depth sort had depth keys
+ * spanning 2^24 or more (that scene's output of that run is then all zeros);
+ * gs_last_error() names which guard fired. */
 gs_status gs_plan_status(gs_plan *plan, void *stream);
 
 /* Waits for the device and frees the plan (NULL is ignored). */
@@ -305,6 +371,13 @@ gs_status gs_mlp_init(float *params, uint64_t seed, void *stream);
  * Synchronises the stream once (grid sizing). */
 gs_status gs_features(const gs_scene *scene, float *features, void *stream);
 
+/* The 16 nearest other means of every Gaussian, the neighbourhood the
+ * features above are built from: neighbours device uint32[n][16] (indices;
+ * 0xFFFFFFFF where fewer than 16 others exist), sq_dist device float[n][16]
+ * (squared distances as float32 (dx dx + dy dy) + dz dz, +inf where missing),
+ * ordered by (squared distance, index).  Synchronises the stream once. */
+gs_status gs_knn(const gs_scene *scene, uint32_t *neighbours, float *sq_dist, void *stream);
+
 /* Column means and 1/std of device float[n][64] into device float[2][64]. */
 gs_status gs_feature_stats(const float *features, int64_t n, float *norm, void *stream);
 
@@ -317,10 +390,23 @@ gs_status gs_mlp_forward(const float *params, const float *features, const float
  * device float[1]; gradient of the loss into `grad` (device float[P],
  * nullable); if `adam` (device float[2][P]: first then second moments) is
  * non-NULL, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
- * with `step` >= 1) updates `params` in place. */
+ * with `step` >= 1) updates `params` in place.  Weight gradients sum the
+ * batch in up to 32 row ranges whose partial products are added in order,
+ * and no sum uses float atomics, so the result is deterministic. */
 gs_status gs_mlp_train_step(float *params, float *adam, int64_t step, float lr, const float *features,
                             const float *norm, const float *targets, int64_t n, float *loss, float *grad,
                             void *stream);
+
+/* Precision of gs_mlp_gradient: BF16 operands (the training path of
+ * gs_mlp_train_step), or FP32 operands and activations through the same
+ * kernels (v_mfma_f32_16x16x4_f32), to check the gradient's arithmetic. */
+typedef enum { GS_MLP_BF16 = 0, GS_MLP_FP32 = 1 } gs_mlp_precision;
+
+/* Loss and gradient of one batch (as gs_mlp_train_step without the update)
+ * in the given precision: loss device float[1], grad device float[P]; the
+ * parameters are not changed.  Every sum has a fixed order (deterministic). */
+gs_status gs_mlp_gradient(const float *params, const float *features, const float *norm, const float *targets,
+                          int64_t n, int32_t precision, float *loss, float *grad, void *stream);
 
 /* Learned proposal for sensitivity sampling: p_i = (1 - floor) e_i / sum e +
  * floor / n with e_i = exp(log_s[i] - max log_s), from predicted ln s
@@ -351,6 +437,22 @@ void gs_default_params(gs_params *params);
 
 /* Frees the calling device's scratch arena (waits for the device first). */
 gs_status gs_release_workspace(void);
+
+/* Where the library's device memory comes from (its scratch arenas and
+ * the buffers of plans created afterwards): hipMalloc / hipFree by default,
+ * or a caller's allocator, e.g. a framework's caching allocator (the Python
+ * binding can register torch's).  alloc(ctx, bytes, stream) returns device
+ * memory on the current device, or NULL when it cannot (the call that asked
+ * then fails with GS_ERR_DEVICE); release(ctx, ptr, stream) takes back a
+ * block alloc returned.  The library passes the null stream and releases a
+ * block only after the device has finished with it.  Both functions, or
+ * neither (NULL, NULL: back to hipMalloc / hipFree).  Process-wide; the
+ * call waits for every device that holds arenas and returns each arena to
+ * the allocator it came from (plans keep their allocator until destroyed).
+ * The functions must not call into this library. */
+typedef void *(*gs_alloc_fn)(void *ctx, size_t bytes, void *stream);
+typedef void (*gs_free_fn)(void *ctx, void *ptr, void *stream);
+gs_status gs_set_allocator(gs_alloc_fn alloc, gs_free_fn release, void *ctx);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *gs_last_error(void);

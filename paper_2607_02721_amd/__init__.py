@@ -24,7 +24,7 @@ from ._lib import (AGG_IMAGE, AGG_RAY, AGG_SCENE, AGG_TILE, ATTR_F32, ATTR_MIXED
 __all__ = ["DeviceScene", "sensitivity", "sample_coreset", "render_objective", "GsError",
            "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "QUERY_L2", "QUERY_CHANNEL", "ATTR_F32",
            "ATTR_MIXED16", "AGG_RAY", "AGG_TILE", "AGG_IMAGE", "AGG_SCENE", "load", "release_workspace",
-           "Plan", "measure_peaks"]
+           "Plan", "measure_peaks", "coreset_error", "use_torch_allocator", "region_bound"]
 
 
 def _torch():
@@ -88,7 +88,7 @@ def _views(views):
 
 
 def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
-            max_views_per_chunk, flags=0, aggregate=AGG_RAY):
+            max_views_per_chunk, flags=0, aggregate=AGG_RAY, ambiguous_rays=None):
     p = _lib.default_params()
     p.flags = flags
     p.aggregate = aggregate
@@ -102,22 +102,28 @@ def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask
         if not ray_mask.is_cuda or ray_mask.dtype.itemsize != 4:
             raise ValueError("ray_mask must be a device tensor of 32-bit words")
         p.ray_mask = ray_mask.data_ptr()
+    if ambiguous_rays is not None:
+        if not ambiguous_rays.is_cuda or ambiguous_rays.dtype.itemsize != 4:
+            raise ValueError("ambiguous_rays must be a device tensor of 32-bit words")
+        p.ambiguous_rays = ambiguous_rays.data_ptr()
     return p
 
 
 def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
                 share_floor=1e-12, query_mode=QUERY_RGBSUM, ray_mask=None,
                 max_views_per_chunk=0, stats=False, count_pairs=False, aggregate=AGG_RAY, out=None,
-                stream=None):
+                ambiguous_rays=None, stream=None):
     """Per-Gaussian sensitivities (float32 device tensor [n]) for queries of
     the given granularity (AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE); with
     stats=True also a dict of counters and per-stage device milliseconds
-    (pair counters need count_pairs=True)."""
+    (pair counters need count_pairs=True, which can also OR the rays holding
+    a pair within 1e-5 r^2 of the cutoff into the device bitset
+    `ambiguous_rays`)."""
     torch = _torch()
     lib = load()
     hv = _views(views)
     p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
-                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0, aggregate)
+                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0, aggregate, ambiguous_rays)
     if out is None:
         out = torch.empty(scene.n, dtype=torch.float32, device=scene.opacity.device)
     sc = scene.c_struct()
@@ -203,19 +209,23 @@ class Plan:
             pass
 
 
-def sample_coreset(sens, m: int, seed: int, stream=None):
-    """Counts (int32 view of uint32), float64 weights and support (int64 [1])."""
+def sample_coreset(sens, m: int, seed: int, stream=None, out=None):
+    """Counts (int32 view of uint32), float64 weights and support (int64 [1]).
+    out: optional (counts, weights, support) tensors to write into."""
     torch = _torch()
     lib = load()
     if sens.dtype != torch.float32 or not sens.is_cuda or not sens.is_contiguous():
         raise ValueError("sens must be a contiguous float32 device tensor")
     n = sens.numel()
-    counts = torch.empty(n, dtype=torch.int32, device=sens.device)
-    weights = torch.empty(n, dtype=torch.float64, device=sens.device)
-    support = torch.empty(1, dtype=torch.int64, device=sens.device)
+    if out is None:
+        counts = torch.empty(n, dtype=torch.int32, device=sens.device)
+        weights = torch.empty(n, dtype=torch.float64, device=sens.device)
+        support = torch.empty(1, dtype=torch.int64, device=sens.device)
+    else:
+        counts, weights, support = out
     status = lib.gs_sample_coreset(C.c_void_p(sens.data_ptr()), n, int(m), C.c_uint64(seed & (2**64 - 1)),
-                                   C.c_void_p(counts.data_ptr()), C.c_void_p(weights.data_ptr()),
-                                   C.c_void_p(support.data_ptr()), _stream_handle(stream))
+                C.c_void_p(counts.data_ptr()), C.c_void_p(weights.data_ptr()),
+                C.c_void_p(support.data_ptr()), _stream_handle(stream))
     _lib.check(status)
     return counts, weights, support
 
@@ -251,6 +261,25 @@ def render_objective(scene: DeviceScene, views, weights=None, objective=OBJ_FULL
     return out
 
 
+def region_bound(world_to_cam, A, A_w, lam=1.0, rho_target=0.0, a_floor=1e-3, stream=None):
+    """Theorem 4's bound over a region of sampled camera poses
+    (gs_region_bound): world_to_cam [K][12] host array, A and A_w float32
+    device tensors [K][pixels] of per-ray full and reduced renders.  Returns
+    (report dict, representative flags as a bool array)."""
+    torch = _torch()
+    w = np.ascontiguousarray(np.asarray(world_to_cam, np.float64).reshape(-1, 12))
+    K = w.shape[0]
+    for t in (A, A_w):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() % K:
+            raise ValueError("A and A_w must be contiguous float32 device tensors of K rows")
+    net = np.zeros(K, np.int32)
+    rep = _lib.RegionReport()
+    _lib.check(load().gs_region_bound(w.ctypes.data, K, float(lam), float(rho_target), C.c_void_p(A.data_ptr()),
+                                      C.c_void_p(A_w.data_ptr()), A.numel() // K, float(a_floor), net.ctypes.data,
+                                      C.byref(rep), _stream_handle(stream)))
+    return {k: getattr(rep, k) for k, _ in rep._fields_ if k != "pad"}, net.astype(bool)
+
+
 def measure_peaks(stream=None):
     """Measured copy bandwidth, FP32 FMA, v_exp_f32 and BF16 MFMA rates (gs_measure_peaks)."""
     p = _lib.Peaks()
@@ -262,8 +291,51 @@ def release_workspace():
     _lib.check(load().gs_release_workspace())
 
 
-def coreset_error(per_view):
-    """E = max over views of |sum A^th_w - sum A| / sum A (per-image fixed objective)."""
-    pv = per_view.detach().cpu().numpy() if hasattr(per_view, "detach") else np.asarray(per_view)
-    on = pv[:, 0] > 0
-    return float(np.max(np.abs(pv[on, 1] - pv[on, 0]) / pv[on, 0])) if on.any() else 0.0
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_allocator_refs = None   # keeps the registered callbacks alive
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device memory (scratch arenas, plan buffers)
+    through torch's caching allocator (gs_set_allocator), or back to
+    hipMalloc / hipFree with enable=False.  Memory the library holds then
+    shows in torch.cuda.memory_allocated() and returns to torch's cache."""
+    global _allocator_refs
+    torch = _torch()
+    lib = load()
+    if not enable:
+        _lib.check(lib.gs_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+
+    def alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+        except Exception:   # noqa: BLE001 - a failed allocation is reported as NULL
+            return None
+
+    def release(ctx, ptr, stream):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:   # noqa: BLE001
+            pass
+
+    refs = (_ALLOC_FN(alloc), _FREE_FN(release))
+    _lib.check(lib.gs_set_allocator(C.cast(refs[0], C.c_void_p), C.cast(refs[1], C.c_void_p), None))
+    _allocator_refs = refs
+
+
+def coreset_error(per_view, reduced=False, stream=None):
+    """E = max over views of |sum A^th_w - sum A| / sum A (per-image fixed
+    objective), or with reduced=True the same with the reduced render A_w
+    (gs_coreset_error on the per-view sums of render_objective)."""
+    torch = _torch()
+    pv = per_view
+    if not (hasattr(pv, "is_cuda") and pv.is_cuda and pv.dtype == torch.float64 and pv.is_contiguous()):
+        pv = torch.as_tensor(np.ascontiguousarray(np.asarray(pv if not hasattr(pv, "detach") else pv.cpu()),
+                                                  np.float64)).cuda()
+    out = torch.empty(2, dtype=torch.float64, device=pv.device)
+    _lib.check(load().gs_coreset_error(C.c_void_p(pv.data_ptr()), int(pv.shape[0]), C.c_void_p(out.data_ptr()),
+                                       _stream_handle(stream)))
+    return float(out[1 if reduced else 0].item())

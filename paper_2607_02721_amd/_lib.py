@@ -23,9 +23,11 @@ EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_de
             "gs_mlp_init", "gs_features", "gs_feature_stats", "gs_mlp_forward", "gs_mlp_train_step",
             "gs_plan_create", "gs_plan_set_config", "gs_plan_tune", "gs_plan_get_info",
             "gs_plan_sensitivity", "gs_plan_status", "gs_plan_destroy", "gs_proposal_mixture",
-            "gs_log_targets", "gs_measure_peaks"]
+            "gs_log_targets", "gs_measure_peaks", "gs_knn", "gs_coreset_error", "gs_mlp_gradient",
+            "gs_set_allocator", "gs_region_bound"]
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
+MLP_BF16, MLP_FP32 = 0, 1
 FLAG_COUNT_PAIRS = 1
 AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE = 0, 1, 2, 3
 QUERY_RGBSUM, QUERY_NOCOLOR, QUERY_L2, QUERY_CHANNEL = 0, 1, 2, 3
@@ -53,7 +55,7 @@ class Params(C.Structure):
     _fields_ = [("footprint_sigma", C.c_float), ("dilation", C.c_float), ("z_near", C.c_float),
                 ("share_floor", C.c_float), ("query_mode", C.c_int32),
                 ("max_views_per_chunk", C.c_int32), ("flags", C.c_int32), ("ray_mask", C.c_void_p),
-                ("aggregate", C.c_int32)]
+                ("aggregate", C.c_int32), ("ambiguous_rays", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -62,7 +64,8 @@ class Stats(C.Structure):
                 ("n_invalid_gaussians", C.c_int64), ("total_sensitivity", C.c_double),
                 ("ms_project", C.c_double), ("ms_sort", C.c_double), ("ms_bin", C.c_double),
                 ("ms_pass1", C.c_double), ("ms_pass2", C.c_double), ("ms_emit", C.c_double),
-                ("n_bins", C.c_int64)]
+                ("n_bins", C.c_int64), ("sort_passes", C.c_int32), ("pad0", C.c_int32),
+                ("n_ambiguous_keys", C.c_int64), ("n_ambiguous_pairs", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +85,12 @@ class PlanInfo(C.Structure):
 class Peaks(C.Structure):
     _fields_ = [("copy_bytes_per_s", C.c_double), ("fma_per_s", C.c_double), ("exp_per_s", C.c_double),
                 ("mfma_bf16_flop_per_s", C.c_double)]
+
+
+class RegionReport(C.Structure):
+    _fields_ = [("L_full", C.c_double), ("L_w", C.c_double), ("A_min", C.c_double), ("eps_0", C.c_double),
+                ("rho", C.c_double), ("eps_reg", C.c_double), ("max_err", C.c_double), ("n_pixels", C.c_int64),
+                ("n_net", C.c_int32), ("pad", C.c_int32)]
 
 
 class RenderDiag(C.Structure):
@@ -123,6 +132,13 @@ def load(path: str = LIB_PATH):
         lib.gs_mlp_param_count.restype = C.c_int64
         lib.gs_mlp_init.argtypes = [P, C.c_uint64, P]
         lib.gs_features.argtypes = [P, P, P]
+        lib.gs_knn.argtypes = [P, P, P, P]
+        lib.gs_region_bound.argtypes = [P, C.c_int32, C.c_double, C.c_double, P, P, C.c_int64, C.c_float, P, P, P]
+        lib.gs_region_bound.restype = C.c_int
+        lib.gs_set_allocator.argtypes = [P, P, P]
+        lib.gs_set_allocator.restype = C.c_int
+        lib.gs_mlp_gradient.argtypes = [P, P, P, P, C.c_int64, C.c_int32, P, P, P]
+        lib.gs_coreset_error.argtypes = [P, C.c_int32, P, P]
         lib.gs_feature_stats.argtypes = [P, C.c_int64, P, P]
         lib.gs_mlp_forward.argtypes = [P, P, P, C.c_int64, P, P]
         lib.gs_mlp_train_step.argtypes = [P, P, C.c_int64, C.c_float, P, P, P, C.c_int64, P, P, P]
@@ -137,7 +153,7 @@ def load(path: str = LIB_PATH):
         lib.gs_measure_peaks.argtypes = [P, P]
         lib.gs_plan_destroy.argtypes = [P]
         lib.gs_plan_destroy.restype = None
-        for f in (lib.gs_mlp_init, lib.gs_features, lib.gs_feature_stats, lib.gs_mlp_forward,
+        for f in (lib.gs_mlp_init, lib.gs_features, lib.gs_knn, lib.gs_coreset_error, lib.gs_mlp_gradient, lib.gs_feature_stats, lib.gs_mlp_forward,
                   lib.gs_mlp_train_step, lib.gs_plan_create, lib.gs_plan_set_config, lib.gs_plan_tune,
                   lib.gs_plan_get_info, lib.gs_plan_sensitivity, lib.gs_plan_status, lib.gs_proposal_mixture,
                   lib.gs_log_targets, lib.gs_measure_peaks):
@@ -155,8 +171,8 @@ def default_params(**kw) -> Params:
     p = Params()
     load().gs_default_params(C.byref(p))
     for k, v in kw.items():
-        if k == "ray_mask":
-            p.ray_mask = v
+        if k in ("ray_mask", "ambiguous_rays"):
+            setattr(p, k, v)
         else:
             setattr(p, k, v)
     return p

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgscoreset.so")
 SOURCES = ["project.hip", "sort_scan.hip", "binning.hip", "composite.hip", "sample.hip", "mlp.hip", "knn.hip",
-           "peaks.hip", "api.cpp"]
+           "peaks.hip", "region.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -40,11 +40,36 @@ gs_status fail(gs_status s, const char *fmt, ...) {
                                           __FILE__, __LINE__);                                          \
     } while (0)
 
+// Device memory of the library: hipMalloc / hipFree unless the caller
+// registered an allocator (gs_set_allocator).  Each block remembers the
+// allocator that produced it, so a change of allocator never frees a block
+// with the wrong one.
+struct Allocator {
+    gs_alloc_fn alloc = nullptr;   // null: hipMalloc / hipFree
+    gs_free_fn release = nullptr;
+    void *ctx = nullptr;
+};
+Allocator g_allocator;
+
+hipError_t dev_alloc(const Allocator &A, void **p, size_t bytes, hipStream_t st) {
+    if (!A.alloc) return hipMalloc(p, bytes);
+    *p = A.alloc(A.ctx, bytes, (void *)st);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+void dev_free(const Allocator &A, void *p, hipStream_t st) {
+    if (!p) return;
+    if (A.alloc)
+        A.release(A.ctx, p, (void *)st);
+    else
+        (void)hipFree(p);
+}
+
 // Grow-only device arena, one per device and purpose.
 struct Arena {
     void *base = nullptr;
     size_t cap = 0;
     int device = -1;
+    Allocator from;                // allocator of base
 };
 constexpr int kMaxDevices = 16;
 Arena g_work[kMaxDevices], g_lists[kMaxDevices], g_agg[kMaxDevices], g_compact[kMaxDevices];
@@ -66,20 +91,23 @@ hipError_t order_after_previous(int dev, hipStream_t st) {
 }
 hipError_t mark_done(int dev, hipStream_t st) { return hipEventRecord(g_done[dev], st); }
 
+// Blocks are taken on the null stream: the arenas serve every stream, and a
+// block is only released after the device has finished with it.
 hipError_t arena_reserve(Arena &a, size_t bytes) {
     if (a.base && a.cap >= bytes) return hipSuccess;
     if (a.base) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return e;
-        hipFree(a.base);
+        dev_free(a.from, a.base, nullptr);
         a.base = nullptr;
         a.cap = 0;
     }
+    a.from = g_allocator;
     size_t want = std::max(bytes + bytes / 8, (size_t)1 << 20);
-    hipError_t e = hipMalloc(&a.base, want);
+    hipError_t e = dev_alloc(a.from, &a.base, want, nullptr);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        e = hipMalloc(&a.base, bytes);
+        e = dev_alloc(a.from, &a.base, bytes, nullptr);
         if (e != hipSuccess) {
             a.base = nullptr;
             return e;
@@ -225,6 +253,8 @@ gs_status check_params(const gs_params *p) {
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown aggregate %d", p->aggregate);
     if (p->aggregate != GS_AGG_RAY && (p->flags & GS_FLAG_COUNT_PAIRS))
         return fail(GS_ERR_UNSUPPORTED, "pair counting needs per-ray queries");
+    if (p->ambiguous_rays && !(p->flags & GS_FLAG_COUNT_PAIRS))
+        return fail(GS_ERR_INVALID_ARGUMENT, "ambiguous_rays needs GS_FLAG_COUNT_PAIRS");
     if (p->aggregate != GS_AGG_RAY && p->query_mode == GS_QUERY_CHANNEL)
         return fail(GS_ERR_UNSUPPORTED, "per-channel queries have no aggregated form (an aggregated query sums "
                                         "its channels: use GS_QUERY_RGBSUM)");
@@ -319,6 +349,7 @@ struct ChunkRun {
     uint32_t *quad_list = nullptr; // ray-masked runs: the quadrants holding a selected ray
     int32_t n_listed = 0;
     int64_t n_entries = 0;
+    int32_t passes = 4;            // 8-bit passes of the depth sort
     // Compositing launches: tiles [t0, t1) whose compacted lists start at
     // list entry `first` (their pool offsets are 4 (entry - first)).  One
     // range over every tile unless the compacted lists only fit in pieces.
@@ -462,6 +493,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     for (int k = 0; k < c.vc; ++k)
         if (kr[c.vc + k] >= kr[k]) span = std::max(span, kr[c.vc + k] - kr[k]);
     const int passes = span < 0xFFFFFFu ? 3 : 4;
+    r.passes = passes;
     uint32_t *skeys = nullptr;
     // When a quarter or more of the (view, Gaussian) pairs are dropped (ray
     // masks, views that see little of the scene) the kept keys are moved to
@@ -580,6 +612,7 @@ CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params
     a.work = nullptr;
     a.xcd_remap = 1;
     a.report_floor = share_floor > 0.0f ? std::nextafter(share_floor, 0.0f) : 0.0f;
+    a.amb_rays = p->ambiguous_rays;
     return a;
 }
 
@@ -641,10 +674,36 @@ gs_status gs_release_workspace(void) {
     if (dev < 0) return s;
     HIP_TRY(hipDeviceSynchronize());
     for (Arena *a : {&g_work[dev], &g_lists[dev], &g_agg[dev], &g_compact[dev], &g_cnt[dev]}) {
-        if (a->base) hipFree(a->base);
+        dev_free(a->from, a->base, nullptr);
         a->base = nullptr;
         a->cap = 0;
     }
+    return GS_OK;
+}
+
+gs_status gs_set_allocator(gs_alloc_fn alloc, gs_free_fn release, void *ctx) {
+    g_last_error.clear();
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(GS_ERR_INVALID_ARGUMENT, "give both an allocation and a release function, or neither");
+    std::lock_guard<std::mutex> lk(g_lock);
+    // every arena goes back to the allocator it came from (on its device)
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    for (int dev = 0; dev < kMaxDevices; ++dev) {
+        Arena *arenas[] = {&g_work[dev], &g_lists[dev], &g_agg[dev], &g_compact[dev], &g_cnt[dev]};
+        bool any = false;
+        for (Arena *a : arenas) any = any || a->base;
+        if (!any) continue;
+        HIP_TRY(hipSetDevice(dev));
+        HIP_TRY(hipDeviceSynchronize());
+        for (Arena *a : arenas) {
+            dev_free(a->from, a->base, nullptr);
+            a->base = nullptr;
+            a->cap = 0;
+        }
+    }
+    HIP_TRY(hipSetDevice(cur));
+    g_allocator = Allocator{alloc, release, ctx};
     return GS_OK;
 }
 
@@ -687,6 +746,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     std::vector<ViewDev> hv;
     std::vector<int32_t> htv;
     int64_t entries = 0, projected = 0;
+    int32_t sort_passes = 0;
     ChunkRun r;
     const float log2e = 1.4426950408889634f;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
@@ -696,6 +756,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
             return s;
         entries += r.n_entries;
         n_bins += (int64_t)c.total_tiles * S.nchunks;
+        sort_passes = std::max(sort_passes, r.passes);
         CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor);
         a.ccount = r.host_slot.clist ? r.ccount : nullptr;
         if (r.quad_list) {
@@ -788,8 +849,8 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         HIP_TRY(hipStreamSynchronize(st));
         stats->n_projected = projected;
         stats->n_entries = entries;
-        uint64_t spread[4] = {0, 0, 0, 0};
-        for (int k = 0; k < 4; ++k)
+        uint64_t spread[kCntSpreadKinds] = {};
+        for (int k = 0; k < kCntSpreadKinds; ++k)
             for (int i = 0; i < kCntSpread; ++i) spread[k] += cnt[CNT_SLOTS + k * kCntSpread + i];
         stats->n_pairs = (int64_t)spread[0];
         stats->n_live_pairs = (int64_t)spread[1];
@@ -804,6 +865,9 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         stats->ms_pass2 = ms[4];
         stats->ms_emit = ms[5];
         stats->n_bins = n_bins;
+        stats->sort_passes = sort_passes;
+        stats->n_ambiguous_keys = (int64_t)cnt[CNT_AMB_KEYS];
+        stats->n_ambiguous_pairs = (int64_t)spread[4];
         if (cnt[CNT_INVALID]) return fail(GS_ERR_INVALID_DATA, "%llu Gaussians have non-finite attributes",
                                           (unsigned long long)cnt[CNT_INVALID]);
     }
@@ -825,6 +889,7 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
         return fail(GS_ERR_INVALID_ARGUMENT, "weights are required for the fixed and true objectives");
     if (params->query_mode == GS_QUERY_CHANNEL)
         return fail(GS_ERR_UNSUPPORTED, "the objectives hold one query per ray (no per-channel queries)");
+    if (params->ambiguous_rays) return fail(GS_ERR_INVALID_ARGUMENT, "ambiguous_rays is for gs_sensitivity");
     std::lock_guard<std::mutex> lk(g_lock);
     const int dev = current_device(&s);
     if (dev < 0) return s;
@@ -896,7 +961,7 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
     g_last_error.clear();
     if (!sens || !counts || !weights || !support) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
     if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
-    if (n >= ((int64_t)1 << 24)) return fail(GS_ERR_UNSUPPORTED, "n must be < 2^24 so that Q fits 64 bits");
+    if (n > kSampleMaxN) return fail(GS_ERR_UNSUPPORTED, "n must be <= 2^24 - 2^16 so that Q fits 64 bits");
     if (m < 1) return fail(GS_ERR_INVALID_ARGUMENT, "m must be >= 1");
     if (m >= ((int64_t)1 << 31)) return fail(GS_ERR_UNSUPPORTED, "m must be < 2^31");
     std::lock_guard<std::mutex> lk(g_lock);
@@ -906,24 +971,29 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(order_after_previous(dev, st));
     DoneGuard done_guard{dev, st};
-    const size_t need = 2 * sizeof(uint64_t) * (size_t)n + sizeof(uint64_t) * (scan_tmp_elems(n) + 2) + 1024;
+    const size_t need = 2 * sizeof(uint64_t) * (size_t)n + sizeof(uint64_t) * (scan_tmp_elems(n) + 2) + 2048;
     HIP_TRY(arena_reserve(g_work[dev], need));
     Carve cv(g_work[dev].base);
     uint64_t *q = cv.take<uint64_t>(n);
     uint64_t *C = cv.take<uint64_t>(n);
     uint64_t *tmp = cv.take<uint64_t>(scan_tmp_elems(n) + 2);
-    launch_quantize(sens, n, q, st);
+    uint32_t *bad = cv.take<uint32_t>(64);
+    launch_fill_u32(bad, 0u, 1, st);
+    launch_quantize(sens, n, q, bad, st);
     scan_u64_inclusive(q, C, n, tmp, st);
     launch_fill_u32(counts, 0u, n, st);
     launch_fill_u64((uint64_t *)weights, 0ull, n, st);
     launch_fill_u64((uint64_t *)support, 0ull, 1, st);
     HIP_TRY(hipGetLastError());
     uint64_t Q = 0;
+    uint32_t hbad = 0;
     HIP_TRY(hipMemcpyAsync(&Q, C + n - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (hbad) return fail(GS_ERR_INVALID_DATA, "a sensitivity is outside [0, 1 + 2^-10] or NaN");
     if (Q == 0) return fail(GS_ERR_NO_POSITIVE_SENSITIVITY, "every sensitivity is 0");
     launch_draws(C, n, m, seed, counts, st);
-    launch_weights(counts, q, C, n, m, weights, support, st);
+    launch_weights(counts, q, sens, C, n, m, weights, support, st);
     HIP_TRY(hipGetLastError());
     return GS_OK;
 }
@@ -971,6 +1041,148 @@ gs_status gs_features(const gs_scene *scene, float *features, void *stream) {
     SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
                 scene->quat, scene->opacity, scene->sh};
     HIP_TRY(knn_features(sd, features, g_work[dev].base, st));
+    return GS_OK;
+}
+
+gs_status gs_coreset_error(const double *per_view, int32_t n_views, double *out, void *stream) {
+    g_last_error.clear();
+    if (!per_view || !out) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n_views < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n_views must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    launch_coreset_error(per_view, n_views, out, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
+// Compact-region extension: host-side pose metric and greedy rho-net.
+static void pose_centre(const double *M, double c[3]) {
+    for (int a = 0; a < 3; ++a) c[a] = -(M[a] * M[3] + M[4 + a] * M[7] + M[8 + a] * M[11]);
+}
+// Angle of Ra Rb^T from its skew part (sine) and trace (cosine).
+static double pose_angle(const double *Ma, const double *Mb) {
+    double R[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) R[r][c] = Ma[4 * r] * Mb[4 * c] + Ma[4 * r + 1] * Mb[4 * c + 1] + Ma[4 * r + 2] * Mb[4 * c + 2];
+    const double sx = R[2][1] - R[1][2], sy = R[0][2] - R[2][0], sz = R[1][0] - R[0][1];
+    const double sn = 0.5 * std::sqrt(sx * sx + sy * sy + sz * sz);
+    const double cs = 0.5 * (R[0][0] + R[1][1] + R[2][2] - 1.0);
+    return std::atan2(sn, cs);
+}
+
+gs_status gs_region_bound(const double *world_to_cam, int32_t n_poses, double lambda, double rho_target,
+                          const float *A, const float *A_w, int64_t n_pixels, float a_floor, int32_t *is_net,
+                          gs_region_report *report, void *stream) {
+    g_last_error.clear();
+    if (!world_to_cam || !A || !A_w || !is_net || !report) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (n_poses < 2 || n_poses > 4096) return fail(GS_ERR_INVALID_ARGUMENT, "n_poses must be in 2..4096");
+    if (n_pixels < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n_pixels must be >= 1");
+    if (!(lambda >= 0.0) || !(rho_target >= 0.0) || !std::isfinite(lambda) || !std::isfinite(rho_target))
+        return fail(GS_ERR_INVALID_ARGUMENT, "lambda and rho_target must be finite and >= 0");
+    if (!(a_floor >= 0.0f)) return fail(GS_ERR_INVALID_ARGUMENT, "a_floor must be >= 0");
+    for (int64_t i = 0; i < 12 * (int64_t)n_poses; ++i)
+        if (!std::isfinite(world_to_cam[i])) return fail(GS_ERR_INVALID_ARGUMENT, "non-finite pose");
+    const int K = n_poses;
+    // pose distances and the greedy net (first pose, then the farthest one)
+    std::vector<double> D((size_t)K * K, 0.0), cen((size_t)3 * K);
+    for (int i = 0; i < K; ++i) pose_centre(world_to_cam + 12 * i, &cen[3 * i]);
+    for (int i = 0; i < K; ++i)
+        for (int j = i + 1; j < K; ++j) {
+            const double dx = cen[3 * i] - cen[3 * j], dy = cen[3 * i + 1] - cen[3 * j + 1];
+            const double dz = cen[3 * i + 2] - cen[3 * j + 2];
+            const double d = std::sqrt(dx * dx + dy * dy + dz * dz) +
+                             lambda * pose_angle(world_to_cam + 12 * i, world_to_cam + 12 * j);
+            D[(size_t)i * K + j] = D[(size_t)j * K + i] = d;
+        }
+    std::vector<double> near(D.begin(), D.begin() + K);
+    std::fill(is_net, is_net + K, 0);
+    is_net[0] = 1;
+    int n_net = 1;
+    for (;;) {
+        int far = 0;
+        for (int k = 1; k < K; ++k)
+            if (near[k] > near[far]) far = k;
+        if (near[far] <= rho_target) break;
+        is_net[far] = 1;
+        ++n_net;
+        for (int k = 0; k < K; ++k) near[k] = std::min(near[k], D[(size_t)far * K + k]);
+    }
+    double rho = 0.0;
+    for (int k = 0; k < K; ++k) rho = std::max(rho, near[k]);
+    std::vector<int32_t> pi, pj;
+    for (int i = 0; i < K; ++i)
+        for (int j = i + 1; j < K; ++j) {
+            pi.push_back(i);
+            pj.push_back(j);
+        }
+    const int npairs = (int)pi.size();
+    std::lock_guard<std::mutex> lk(g_lock);
+    gs_status s;
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(order_after_previous(dev, st));
+    DoneGuard done_guard{dev, st};
+    const size_t need = (size_t)n_pixels + 4 * sizeof(int32_t) * (size_t)(K + 2 * npairs) +
+                        2 * sizeof(float) * (size_t)npairs + 8192;
+    HIP_TRY(arena_reserve(g_work[dev], need));
+    Carve cv(g_work[dev].base);
+    uint8_t *keep = cv.take<uint8_t>((size_t)n_pixels);
+    int32_t *net_d = cv.take<int32_t>(K);
+    int32_t *pi_d = cv.take<int32_t>(npairs);
+    int32_t *pj_d = cv.take<int32_t>(npairs);
+    float *diff = cv.take<float>(2 * (size_t)npairs);
+    uint32_t *bits = cv.take<uint32_t>(64);
+    HIP_TRY(hipMemcpyAsync(net_d, is_net, sizeof(int32_t) * K, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pi_d, pi.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pj_d, pj.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, st));
+    launch_fill_u32(bits, 0x7F800000u, 1, st);     // +inf
+    launch_fill_u32(bits + 1, 0u, 3, st);
+    launch_region_pixels(A, A_w, K, n_pixels, a_floor, net_d, keep, bits, st);
+    launch_region_pairs(A, A_w, K, n_pixels, keep, pi_d, pj_d, npairs, diff, st);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> hd(2 * (size_t)npairs);
+    uint32_t hb[4];
+    HIP_TRY(hipMemcpyAsync(hd.data(), diff, sizeof(float) * hd.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hb, bits, sizeof hb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    gs_region_report R{};
+    R.n_pixels = hb[3];
+    R.n_net = n_net;
+    R.rho = rho;
+    for (int q = 0; q < npairs; ++q) {
+        const double d = D[(size_t)pi[q] * K + pj[q]];
+        if (d > 0.0) {
+            R.L_full = std::max(R.L_full, (double)hd[2 * q] / d);
+            R.L_w = std::max(R.L_w, (double)hd[2 * q + 1] / d);
+        }
+    }
+    float f;
+    memcpy(&f, &hb[0], 4);
+    R.A_min = hb[3] ? (double)f : 0.0;
+    memcpy(&f, &hb[1], 4);
+    R.eps_0 = f;
+    memcpy(&f, &hb[2], 4);
+    R.max_err = f;
+    R.eps_reg = R.A_min > 0.0 ? R.eps_0 + ((1.0 + R.eps_0) * R.L_full + R.L_w) * R.rho / R.A_min : INFINITY;
+    *report = R;
+    if (!hb[3]) return fail(GS_ERR_NO_POSITIVE_SENSITIVITY, "no pixel has A above the floor at every pose");
+    return GS_OK;
+}
+
+gs_status gs_knn(const gs_scene *scene, uint32_t *neighbours, float *sq_dist, void *stream) {
+    g_last_error.clear();
+    gs_status s;
+    if ((s = check_scene(scene)) != GS_OK) return s;
+    if (!neighbours || !sq_dist) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    if ((s = begin_call(&dev, st)) != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    HIP_TRY(arena_reserve(g_work[dev], knn_scratch_bytes(scene->n)));
+    SceneDev sd{scene->n, scene->sh_degree, scene->format, scene->mean, scene->log_scale,
+                scene->quat, scene->opacity, scene->sh};
+    HIP_TRY(knn_features(sd, nullptr, g_work[dev].base, st, neighbours, sq_dist));
     return GS_OK;
 }
 
@@ -1080,6 +1292,28 @@ gs_status gs_mlp_train_step(float *params, float *adam, int64_t step, float lr, 
     return GS_OK;
 }
 
+gs_status gs_mlp_gradient(const float *params, const float *features, const float *norm, const float *targets,
+                          int64_t n, int32_t precision, float *loss, float *grad, void *stream) {
+    g_last_error.clear();
+    if (!params || !features || !norm || !targets || !loss || !grad)
+        return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1 || n > kMlpRows) return fail(GS_ERR_INVALID_ARGUMENT, "batch rows must be in 1..65536");
+    if (precision != GS_MLP_BF16 && precision != GS_MLP_FP32)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown precision %d", precision);
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    gs_status s = begin_call(&dev, st);
+    if (s != GS_OK) return s;
+    DoneGuard done_guard{dev, st};
+    const int64_t rows = (n + 63) / 64 * 64;
+    HIP_TRY(arena_reserve(g_work[dev], mlp_scratch_bytes(rows)));
+    mlp_train_step(const_cast<float *>(params), nullptr, 0, 0.0f, features, norm, targets, n, loss, grad,
+                   g_work[dev].base, rows, st, precision == GS_MLP_FP32);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -1136,6 +1370,7 @@ struct PlanGroup {
 
 struct gs_plan {
     int dev = -1;
+    Allocator from;              // allocator of every block the plan owns
     gs_params p{};
     std::vector<PlanScene> scenes;
     std::vector<PlanGroup> groups;
@@ -1261,11 +1496,11 @@ void plan_free(gs_plan *P) {
     if (P->exec) hipGraphExecDestroy(P->exec);
     if (P->graph) hipGraphDestroy(P->graph);
     for (PlanGroup &G : P->groups) {
-        if (G.buf) hipFree(G.buf);
-        if (G.lists) hipFree(G.lists);
+        dev_free(P->from, G.buf, nullptr);
+        dev_free(P->from, G.lists, nullptr);
     }
-    if (P->flag) hipFree(P->flag);
-    if (P->pool) hipFree(P->pool);
+    dev_free(P->from, P->flag, nullptr);
+    dev_free(P->from, P->pool, nullptr);
     if (P->cap) hipStreamDestroy(P->cap);
     delete P;
 }
@@ -1306,7 +1541,7 @@ void plan_batches(gs_plan *P) {
             pool = std::max(pool, used);
         }
     }
-    if (pool > 0 && hipMalloc(&P->pool, pool) != hipSuccess) {
+    if (pool > 0 && dev_alloc(P->from, &P->pool, pool, nullptr) != hipSuccess) {
         (void)hipGetLastError();
         P->pool = nullptr;
         for (PlanGroup &G : P->groups) {
@@ -1342,7 +1577,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         G.bytes += need;
         P->scenes[i].group = (int)P->groups.size() - 1;
     }
-    if (hipMalloc((void **)&P->flag, 256) != hipSuccess) {
+    if (dev_alloc(P->from, (void **)&P->flag, 256, nullptr) != hipSuccess) {
         return fail(GS_ERR_OUT_OF_MEMORY, "plan flag");
     }
     launch_fill_u32(P->flag, 0u, 1, st);
@@ -1360,7 +1595,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         const size_t table_bytes = sizeof(ViewDev) * G.total_views + 2 * sizeof(int32_t) * G.total_tiles +
                                    4 * sizeof(uint32_t) * G.total_tiles + sizeof(SceneSlot) * G.scenes.size() +
                                    8192;
-        if (hipMalloc(&G.buf, G.bytes + table_bytes + 65536) != hipSuccess) {
+        if (dev_alloc(P->from, &G.buf, G.bytes + table_bytes + 65536, nullptr) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GS_ERR_OUT_OF_MEMORY, "plan group %zu: %zu bytes", gi, G.bytes + table_bytes);
         }
@@ -1413,7 +1648,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
             ps.cap = totals[k] + totals[k] / 64 + 1024;
             lb += ((ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255);
         }
-        if (hipMalloc(&G.lists, lb + 4096) != hipSuccess) {
+        if (dev_alloc(P->from, &G.lists, lb + 4096, nullptr) != hipSuccess) {
             (void)hipGetLastError();
             return fail(GS_ERR_OUT_OF_MEMORY, "plan group %zu lists: %zu bytes", gi, lb);
         }
@@ -1447,6 +1682,10 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
         return fail(GS_ERR_UNSUPPORTED, "plans compute one query per ray (no per-channel queries)");
     if (params->flags) return fail(GS_ERR_UNSUPPORTED, "plans do not count pairs");
     gs_plan *P = new gs_plan();
+    {
+        std::lock_guard<std::mutex> lk(g_lock);
+        P->from = g_allocator;
+    }
     P->p = *params;
     P->scenes.resize(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
@@ -1654,8 +1893,17 @@ gs_status gs_plan_status(gs_plan *plan, void *stream) {
     uint32_t f = 0;
     HIP_TRY(hipMemcpyAsync(&f, plan->flag, sizeof f, hipMemcpyDeviceToHost, (hipStream_t)stream));
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    if (f) return fail(GS_ERR_INVALID_DATA, "a scene produced more tile-list entries than at plan creation; "
-                                           "its lists were emptied (recreate the plan)");
+    if (f & kGuardSpan && f & kGuardList)
+        return fail(GS_ERR_INVALID_DATA, "a scene's depth keys spanned 2^24 or more in a view (its plan sorts with "
+                                         "three passes) and a scene produced more tile-list entries than at plan "
+                                         "creation; their lists were emptied (recreate the plan)");
+    if (f & kGuardSpan)
+        return fail(GS_ERR_INVALID_DATA, "a scene's depth keys spanned 2^24 or more in a view, which the plan's "
+                                         "three-pass depth sort cannot order; its lists were emptied (recreate "
+                                         "the plan)");
+    if (f)
+        return fail(GS_ERR_INVALID_DATA, "a scene produced more tile-list entries than at plan creation; "
+                                         "its lists were emptied (recreate the plan)");
     return GS_OK;
 }
 

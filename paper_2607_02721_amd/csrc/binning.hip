@@ -572,14 +572,14 @@ __global__ void k_span_check(const uint32_t *__restrict__ kmin, int Vc, uint32_t
     bad = __any(bad);
     if (threadIdx.x == 0) {
         *over = bad ? 1u : 0u;
-        if (bad) atomicOr(flag, 1u);
+        if (bad) atomicOr(flag, kGuardSpan);
     }
 }
 __global__ void k_guard_check(const uint64_t *__restrict__ tile_off, int64_t ntiles, uint64_t cap,
                               uint32_t *__restrict__ over, uint32_t *__restrict__ flag, int keep) {
     const bool o = tile_off[ntiles] > cap;
     *over = (o || (keep && *over)) ? 1u : 0u;
-    if (o) atomicOr(flag, 1u);
+    if (o) atomicOr(flag, kGuardList);
 }
 __global__ void k_guard_apply(uint64_t *__restrict__ tile_off, int64_t ntiles, const uint32_t *__restrict__ over) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -505,7 +505,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     const int lane = threadIdx.x;
     const int nq = quad_count(a);
     int iter = 0;
-    uint64_t pin = 0, plive = 0, pos = 0, peval = 0;
+    uint64_t pin = 0, plive = 0, pos = 0, peval = 0, pamb = 0;
     for (int qi = next_quad<kPersistent>(a, iter); qi < nq; qi = next_quad<kPersistent>(a, iter)) {
         WaveSetup w;
         if (!setup_quad(a, qi, w)) continue;
@@ -539,7 +539,8 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
         const float tscale = kCh ? 1.0f : (kMode == kModeL2 ? sqrtf(invQ) : invQ);
         float T = tscale;
         bool done = !positive;
-        uint32_t n_in = 0, n_live = 0, n_eval = 0;
+        uint32_t n_in = 0, n_live = 0, n_eval = 0, n_amb = 0;
+        const float amb_band = kAmbiguityBeta * fabsf(a.r2_log2);
         const float live_bar = kCh ? a.share_floor * Amin : a.share_floor * (Amin * invQ);
         // the quadrant's entries: its compacted list from pass 1, or its
         // tile's list filtered again
@@ -581,6 +582,14 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                                 const float later = kMode == kModeL2 ? (T * T) * cmax : T * cmax;
                                 n_in += (real && in_fp) ? 1u : 0u;
                                 n_live += (real && in_fp && later >= live_bar) ? 1u : 0u;
+                                // the exponent against the cutoff, as pair_rho(_log2) forms
+                                // them: P - bar = -(log2 e / 2)(d^2 - r^2)
+                                const float ddx = w.xl - G.x, ddy = w.yl - G.y;
+                                const float uu = fmaf(G.z, ddy, ddx);
+                                const float tt = kCh ? Cc.x * (ddy * ddy) : fmaf(Cc.x, ddy * ddy, Cc.y);
+                                const float PP = fmaf(G.w * uu, uu, tt);
+                                const float bar = kCh ? a.r2_log2 : Cc.w;
+                                n_amb += (real && positive && fabsf(PP - bar) <= amb_band) ? 1u : 0u;
                             }
                             T = fmaf(-rho, T, T);
                         }
@@ -622,6 +631,9 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
             plive += positive ? n_live : 0u;
             pos += positive ? 1u : 0u;
             peval += (uint64_t)n_eval;
+            pamb += n_amb;
+            if (n_amb && a.amb_rays)
+                atomicOr(&a.amb_rays[w.ray_global >> 5], 1u << (uint32_t)(w.ray_global & 31));
         }
     }
     if (kStats) {
@@ -629,6 +641,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
             pin += __shfl_xor(pin, off);
             plive += __shfl_xor(plive, off);
             pos += __shfl_xor(pos, off);
+            pamb += __shfl_xor(pamb, off);
         }
         if (lane == 0) {
             unsigned long long *c = (unsigned long long *)counters + CNT_SLOTS + (blockIdx.x % kCntSpread);
@@ -636,6 +649,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
             atomicAdd(c + 1 * kCntSpread, (unsigned long long)plive);
             atomicAdd(c + 2 * kCntSpread, (unsigned long long)pos);
             atomicAdd(c + 3 * kCntSpread, (unsigned long long)peval * 64ull);
+            if (pamb) atomicAdd(c + 4 * kCntSpread, (unsigned long long)pamb);
         }
     }
 }
@@ -751,7 +765,7 @@ void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counte
 }
 
 // ---------------------------------------------------------------------------
-// Aggregated queries (Section 3.4): the query objectives A(Q) from the per-ray
+// Aggregated queries (Section 3.5): the query objectives A(Q) from the per-ray
 // A of pass 1 (zero on rays outside the mask), and the maximum over queries.
 // Every sum has a fixed order (per lane in index order, then a fixed
 // butterfly), so the results do not depend on scheduling.
@@ -1037,6 +1051,38 @@ __global__ __launch_bounds__(256) void k_view_sums(const double *__restrict__ ti
 void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
                       hipStream_t st) {
     hipLaunchKernelGGL(k_view_sums, dim3(Vc), dim3(256), 0, st, tile_sums, views_dev, Vc, per_view_out);
+}
+
+// Coreset-objective error of per-image objectives: out[0] = max over views
+// with sum A > 0 of |sum A^th_w - sum A| / sum A, out[1] the same with the
+// reduced render.  Each thread takes a fixed strided set of views, then a
+// tree of maxima (order-free); one block.
+__global__ __launch_bounds__(256) void k_coreset_error(const double *__restrict__ pv, int n_views,
+                                                       double *__restrict__ out) {
+    __shared__ double sh[2][256];
+    double e0 = 0.0, e1 = 0.0;
+    for (int v = threadIdx.x; v < n_views; v += 256) {
+        const double A = pv[3 * v];
+        if (A > 0.0) {
+            e0 = fmax(e0, fabs(pv[3 * v + 1] - A) / A);
+            e1 = fmax(e1, fabs(pv[3 * v + 2] - A) / A);
+        }
+    }
+    sh[0][threadIdx.x] = e0;
+    sh[1][threadIdx.x] = e1;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + off]);
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+void launch_coreset_error(const double *per_view, int n_views, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_coreset_error, dim3(1), dim3(256), 0, st, per_view, n_views, out);
 }
 
 }  // namespace gs

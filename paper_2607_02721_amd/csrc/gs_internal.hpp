@@ -79,14 +79,19 @@ struct ChunkBufs {
 // counters[] slots
 enum : int {
     CNT_PAIRS = 0, CNT_LANE_PAIRS = 1, CNT_RAYS_POS = 2, CNT_INVALID = 3, CNT_INVALID_PAIRS = 4,
-    CNT_GAMMA_BITS = 5, CNT_LIVE = 6, CNT_SLOTS = 8
+    CNT_GAMMA_BITS = 5, CNT_LIVE = 6, CNT_AMB_KEYS = 7, CNT_SLOTS = 8
 };
 // The pass-2 pair counters (pairs, live pairs, positive rays, lane
-// evaluations) are each spread over kCntSpread words after the CNT_SLOTS
-// words (word CNT_SLOTS + k * kCntSpread + (block mod kCntSpread)), so that
-// the per-wave additions do not all meet on one address; the host sums them.
+// evaluations, pairs within the cutoff's ambiguity band) are each spread over
+// kCntSpread words after the CNT_SLOTS words (word CNT_SLOTS + k * kCntSpread
+// + (block mod kCntSpread)), so that the per-wave additions do not all meet on
+// one address; the host sums them.
 constexpr int kCntSpread = 64;
-constexpr int CNT_WORDS = CNT_SLOTS + 4 * kCntSpread;
+constexpr int kCntSpreadKinds = 5;
+constexpr int CNT_WORDS = CNT_SLOTS + kCntSpreadKinds * kCntSpread;
+// A pair is ambiguous when |d^2 - r^2| <= kAmbiguityBeta r^2: float32 and
+// float64 arithmetic may put it on different sides of the cutoff.
+constexpr float kAmbiguityBeta = 1e-5f;
 
 // Blocks of the projection launch (256 threads, one Gaussian per thread).
 inline int64_t proj_blocks(int64_t n) { return (n + 255) / 256; }
@@ -130,16 +135,19 @@ void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const Ch
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
                      int max_tiles_y, uint64_t cap, hipStream_t st);
-// Plan guards: *over = 1 (and *flag |= 1) when some view's kept depth keys
-// span 2^24 or more (a three-pass sort would misorder them); the list guard
-// sets it when the lists outgrow `cap` (keep: also when it is already set)
-// and then empties the lists.
+// Plan guards: *over = 1 (and *flag |= kGuardSpan) when some view's kept
+// depth keys span 2^24 or more (a three-pass sort would misorder them); the
+// list guard sets *over (and *flag |= kGuardList) when the lists outgrow
+// `cap` (keep: *over also stays set when the span guard set it) and then
+// empties the lists.
+constexpr uint32_t kGuardList = 1u, kGuardSpan = 2u;
 void launch_span_check(const uint32_t *kmin, int Vc, uint32_t *over, uint32_t *flag, hipStream_t st);
 void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_t *over, uint32_t *flag, bool keep,
                        hipStream_t st);
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp,
                                hipStream_t st);
 void scan_u64_inclusive(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *block_tmp, hipStream_t st);
+void scan_u64_inclusive_inplace(uint64_t *data, int64_t n, uint64_t *block_tmp, hipStream_t st);
 int64_t scan_tmp_elems(int64_t n);
 
 // One scene of a compositing launch (a launch may cover several scenes).
@@ -195,6 +203,8 @@ struct CompositeArgs {
     const uint32_t *quad_list;   // ray-masked runs: the quadrants (4 tile + quadrant) holding a selected ray,
     int32_t n_listed;            // in order; only these are composited (null: every quadrant)
     float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
+    uint32_t *amb_rays;          // pass 2 with counters: bit of every ray (ViewDev::ray_base numbering) with an
+                                 // ambiguous pair is OR-ed in (null: none)
 };
 // Fixed-point scale of the aggregated shares.  A Gaussian's accumulated share
 // of one query is at most 1 (a_i(q) <= A(q) on every ray), so 2^60 leaves a
@@ -230,29 +240,49 @@ void launch_max_f64(const double *x, int64_t n, uint64_t *out_bits, hipStream_t 
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st);
 void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
                       hipStream_t st);
+// out[0] = max over views with A > 0 of |A^th_w - A| / A, out[1] with A_w.
+void launch_coreset_error(const double *per_view, int n_views, double *out, hipStream_t st);
 
 // Sampler
-void launch_quantize(const float *sens, int64_t n, uint64_t *q, hipStream_t st);
+// q_i = ceil(s_i 2^40); *bad |= 1 if some s_i is outside [0, 1 + 2^-10] or
+// NaN (*bad must be zeroed first).
+constexpr int64_t kSampleMaxN = ((int64_t)1 << 24) - ((int64_t)1 << 16);
+void launch_quantize(const float *sens, int64_t n, uint64_t *q, uint32_t *bad, hipStream_t st);
 void launch_draws(const uint64_t *C, int64_t n, int64_t m, uint64_t seed, uint32_t *counts, hipStream_t st);
-void launch_weights(const uint32_t *counts, const uint64_t *q, const uint64_t *C, int64_t n, int64_t m,
-                    double *weights, int64_t *support, hipStream_t st);
+// q: the quanta of k_quantize, or null to recompute them from sens.
+void launch_weights(const uint32_t *counts, const uint64_t *q, const float *sens, const uint64_t *C, int64_t n,
+                    int64_t m, double *weights, int64_t *support, hipStream_t st);
 
 // MLP proposal and features
 size_t mlp_scratch_bytes(int64_t rows);
 void mlp_init(float *params, uint64_t seed, hipStream_t st);
 void mlp_forward(const float *P, const float *feat, const float *norm, int64_t n, float *y, void *scratch,
                  int64_t rows, hipStream_t st);
+// fp32: products in FP32 (v_mfma_f32_16x16x4_f32) with FP32 activations
+// instead of BF16 (a precision mode of the same kernels).
 void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *feat, const float *norm,
                     const float *y, int64_t n, float *loss, float *grad_out, void *scratch, int64_t rows,
-                    hipStream_t st);
+                    hipStream_t st, bool fp32 = false);
 size_t knn_scratch_bytes(int64_t n);
-hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStream_t st);
+// Features [n][64], or with nidx non-null the 16 neighbours of every point
+// instead (nidx [n][16] indices, nd2 [n][16] float32 squared distances).
+hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStream_t st, uint32_t *nidx = nullptr,
+                        float *nd2 = nullptr);
 void feature_stats(const float *feat, int64_t n, float *norm, hipStream_t st);
 size_t mixture_scratch_bytes(int64_t n);
 void proposal_mixture(const float *y, int64_t n, float floor, float *p, void *scratch, hipStream_t st);
 void log_targets(const float *s, int64_t n, float floor, float *out, hipStream_t st);
 hipError_t measure_peaks(double *copy_bytes_per_s, double *fma_per_s, double *exp_per_s, double *mfma_flop_per_s,
                          void *scratch, size_t scratch_bytes, hipStream_t st);
+
+// Compact-region bound: kept pixels and min A / max errors (out_bits: min A,
+// max error over the representatives, over all poses, kept count; the first
+// must start at +inf bits, the others at 0), and per pose pair the largest
+// differences of A and A_w over the kept pixels.
+void launch_region_pixels(const float *A, const float *Aw, int K, int64_t P, float floor_, const int32_t *is_net,
+                          uint8_t *keep, uint32_t *out_bits, hipStream_t st);
+void launch_region_pairs(const float *A, const float *Aw, int K, int64_t P, const uint8_t *keep, const int32_t *pi,
+                         const int32_t *pj, int n_pairs, float *diff, hipStream_t st);
 
 // Small utilities
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);

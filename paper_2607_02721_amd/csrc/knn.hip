@@ -113,9 +113,13 @@ __device__ __forceinline__ bool knn_less(float da, uint32_t ia, float db, uint32
     return da < db || (da == db && ia < ib);
 }
 
+// kNeighbours: write the neighbour lists (indices and float32 squared
+// distances, ordered by (distance, index)) instead of the features.
+template <bool kNeighbours>
 __global__ __launch_bounds__(256) void k_knn_features(SceneDev sc, Grid G, const uint64_t *__restrict__ off,
                                                       const uint32_t *__restrict__ order,
-                                                      const float4 *__restrict__ pts, float *__restrict__ feat) {
+                                                      const float4 *__restrict__ pts, float *__restrict__ feat,
+                                                      uint32_t *__restrict__ nidx, float *__restrict__ nd2) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= sc.n) return;
     const uint32_t q = order[t];     // queries in cell order: neighbouring lanes share cells
@@ -200,6 +204,14 @@ __global__ __launch_bounds__(256) void k_knn_features(SceneDev sc, Grid G, const
         }
         reach -= 1e-4f * G.cell;
         if (bi[kK - 1] != 0xFFFFFFFFu && (reach == INFINITY || (reach > 0.0f && bd[kK - 1] < reach * reach))) break;
+    }
+    if (kNeighbours) {
+#pragma unroll
+        for (int k = 0; k < kK; ++k) {
+            nidx[(int64_t)q * kK + k] = bi[k];
+            nd2[(int64_t)q * kK + k] = bd[k];
+        }
+        return;
     }
     // features, assembled in registers and stored as 16 float4 (one row of
     // 256 bytes per point)
@@ -286,7 +298,8 @@ size_t knn_scratch_bytes(int64_t n) {
            64 * 256;
 }
 
-hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStream_t st) {
+hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStream_t st, uint32_t *nidx,
+                        float *nd2) {
     const int64_t n = sc.n;
     char *p = (char *)scratch;
     size_t o = 0;
@@ -349,8 +362,12 @@ hipError_t knn_features(const SceneDev &sc, float *feat, void *scratch, hipStrea
     scan_u32_to_u64_exclusive(count, offs, cells, tmp, st);
     hipLaunchKernelGGL(k_cell_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, cell_of, offs, fill,
                        order, pts, sc);
-    hipLaunchKernelGGL(k_knn_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sc, G, offs, order, pts,
-                       feat);
+    if (nidx)
+        hipLaunchKernelGGL(k_knn_features<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sc, G, offs,
+                           order, pts, nullptr, nidx, nd2);
+    else
+        hipLaunchKernelGGL(k_knn_features<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sc, G, offs,
+                           order, pts, feat, nullptr, nullptr);
     return hipGetLastError();
 }
 

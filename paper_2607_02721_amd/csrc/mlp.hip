@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <cmath>
+
 #include <algorithm>
 
 namespace gs {
@@ -33,32 +35,87 @@ __device__ __forceinline__ float silu_grad(float z) {
 // Epilogues: 0 = store FP32 C; 1 = Z = C + bias -> store Z (FP32) and
 // SiLU(Z) (BF16); 2 = store only SiLU(C + bias) (BF16).
 // Requires M, N multiples of 64 and K a multiple of 32 (checked by the host).
-template <int kEpi>
-__global__ __launch_bounds__(256) void k_gemm_nt(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
-                                                 int ldb, int K, float *__restrict__ C, int ldc,
-                                                 const float *__restrict__ bias, __bf16 *__restrict__ H, int ldh) {
+// Element type of the training path: BF16 on the matrix cores (training),
+// or FP32 through the same kernels (v_mfma_f32_16x16x4_f32; a precision mode
+// for gradient checks).  Fragment loads are 8 consecutive k per lane either
+// way.
+template <typename T>
+struct Frag8;
+template <>
+struct Frag8<__bf16> {
+    bf16x8 v;
+    __device__ __forceinline__ void load(const __bf16 *p) { v = *reinterpret_cast<const bf16x8 *>(p); }
+};
+template <>
+struct Frag8<float> {
+    float4 lo, hi;
+    __device__ __forceinline__ void load(const float *p) {
+        lo = *reinterpret_cast<const float4 *>(p);
+        hi = *reinterpret_cast<const float4 *>(p + 4);
+    }
+};
+
+// acc += A-fragment x B-fragment over one k step of 32.  BF16: one
+// v_mfma_f32_16x16x32_bf16.  FP32: v_mfma_f32_16x16x4_f32 sums over the four
+// 16-lane groups, so call e of 8 multiplies the k = 8 g + e of every group g:
+// together the eight cover the same 32 k.
+__device__ __forceinline__ void mma32(const Frag8<__bf16> &a, const Frag8<__bf16> &b, f32x4 &acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma32(const Frag8<float> &a, const Frag8<float> &b, f32x4 &acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.x, b.lo.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.y, b.lo.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.z, b.lo.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo.w, b.lo.w, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.x, b.hi.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.y, b.hi.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.z, b.hi.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi.w, b.hi.w, acc, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T to_elem(float x) { return static_cast<T>(x); }
+
+// C[M][N] = A[M][K] * B[N][K]^T (row-major, K contiguous), FP32 accumulate.
+// Block = 4 waves computing a 64x64 tile (each wave 32x32 = 2x2 MFMA tiles of
+// 16x16, K in steps of 32).  Fragment layout of the 16x16 MFMAs: lane l
+// holds row (l % 16) of A and column (l % 16) of B^T for the 8 consecutive k
+// at 8 (l / 16); the 16x16 result gives lane l the 4 rows 4 (l / 16) + r of
+// column l % 16.
+// Split K: block z multiplies k in [z kchunk, min(K, (z + 1) kchunk)) and
+// stores its partial product at C + z czstride (epilogue 0 only).
+// Epilogues: 0 = store FP32 C; 1 = Z = C + bias -> store Z (FP32) and
+// SiLU(Z) (T); 2 = store only SiLU(C + bias) (T).
+// Requires M, N multiples of 64 and K, kchunk multiples of 32 (checked by the host).
+template <int kEpi, typename T>
+__global__ __launch_bounds__(256) void k_gemm_nt(const T *__restrict__ A, int lda, const T *__restrict__ B, int ldb,
+                                                 int K, int kchunk, float *__restrict__ C, int ldc, int64_t czstride,
+                                                 const float *__restrict__ bias, T *__restrict__ H, int ldh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row0 = blockIdx.x * 64 + (w & 1) * 32;
     const int col0 = blockIdx.y * 64 + (w >> 1) * 32;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    C += (int64_t)blockIdx.z * czstride;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const __bf16 *a0 = A + (int64_t)(row0 + fr) * lda + fk;
-    const __bf16 *a1 = A + (int64_t)(row0 + 16 + fr) * lda + fk;
-    const __bf16 *b0 = B + (int64_t)(col0 + fr) * ldb + fk;
-    const __bf16 *b1 = B + (int64_t)(col0 + 16 + fr) * ldb + fk;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const bf16x8 fa0 = *reinterpret_cast<const bf16x8 *>(a0 + k0);
-        const bf16x8 fa1 = *reinterpret_cast<const bf16x8 *>(a1 + k0);
-        const bf16x8 fb0 = *reinterpret_cast<const bf16x8 *>(b0 + k0);
-        const bf16x8 fb1 = *reinterpret_cast<const bf16x8 *>(b1 + k0);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+    const T *a0 = A + (int64_t)(row0 + fr) * lda + fk;
+    const T *a1 = A + (int64_t)(row0 + 16 + fr) * lda + fk;
+    const T *b0 = B + (int64_t)(col0 + fr) * ldb + fk;
+    const T *b1 = B + (int64_t)(col0 + 16 + fr) * ldb + fk;
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        Frag8<T> fa0, fa1, fb0, fb1;
+        fa0.load(a0 + k0);
+        fa1.load(a1 + k0);
+        fb0.load(b0 + k0);
+        fb1.load(b1 + k0);
+        mma32(fa0, fb0, acc[0][0]);
+        mma32(fa0, fb1, acc[0][1]);
+        mma32(fa1, fb0, acc[1][0]);
+        mma32(fa1, fb1, acc[1][1]);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -74,50 +131,84 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const __bf16 *__restrict__ A, i
                 } else {
                     v += bias[col];
                     if (kEpi == 1) C[(int64_t)row * ldc + col] = v;
-                    H[(int64_t)row * ldh + col] = (__bf16)silu(v);
+                    H[(int64_t)row * ldh + col] = to_elem<T>(silu(v));
                 }
             }
 }
 
-static void gemm_nt(int epi, const __bf16 *A, int lda, const __bf16 *B, int ldb, int M, int N, int K, float *C,
-                    int ldc, const float *bias, __bf16 *H, int ldh, hipStream_t st) {
+template <typename T>
+static void gemm_nt(int epi, const T *A, int lda, const T *B, int ldb, int M, int N, int K, float *C, int ldc,
+                    const float *bias, T *H, int ldh, hipStream_t st) {
     dim3 grid(M / 64, N / 64);
     if (epi == 0)
-        hipLaunchKernelGGL(k_gemm_nt<0>, grid, dim3(256), 0, st, A, lda, B, ldb, K, C, ldc, bias, H, ldh);
+        hipLaunchKernelGGL((k_gemm_nt<0, T>), grid, dim3(256), 0, st, A, lda, B, ldb, K, K, C, ldc, (int64_t)0, bias,
+                           H, ldh);
     else if (epi == 1)
-        hipLaunchKernelGGL(k_gemm_nt<1>, grid, dim3(256), 0, st, A, lda, B, ldb, K, C, ldc, bias, H, ldh);
+        hipLaunchKernelGGL((k_gemm_nt<1, T>), grid, dim3(256), 0, st, A, lda, B, ldb, K, K, C, ldc, (int64_t)0, bias,
+                           H, ldh);
     else
-        hipLaunchKernelGGL(k_gemm_nt<2>, grid, dim3(256), 0, st, A, lda, B, ldb, K, C, ldc, bias, H, ldh);
+        hipLaunchKernelGGL((k_gemm_nt<2, T>), grid, dim3(256), 0, st, A, lda, B, ldb, K, K, C, ldc, (int64_t)0, bias,
+                           H, ldh);
+}
+
+// Weight gradients are M x N = 256 x {256, 64} products over K = the batch
+// rows: a 4 x 4 (or 4 x 1) grid of tiles would leave most of the 256 CUs
+// idle, so K is split into up to kMaxSplits ranges of at least 512 rows, each
+// tile of each range is one block, and a second kernel sums the partial
+// products in range order (fixed, so the result is deterministic).
+constexpr int kMaxSplits = 32;
+static int split_count(int64_t K) { return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplits, K / 512)); }
+
+__global__ void k_sum_splits(const float *__restrict__ part, int splits, int64_t count, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = part[i];
+    for (int z = 1; z < splits; ++z) s += part[(int64_t)z * count + i];
+    out[i] = s;
+}
+
+template <typename T>
+static void gemm_nt_splitk(const T *A, int lda, const T *B, int ldb, int M, int N, int K, float *part, float *C,
+                           hipStream_t st) {
+    const int S = split_count(K);
+    const int kchunk = (int)(((int64_t)K + S - 1) / S + 31) / 32 * 32;
+    const int used = (K + kchunk - 1) / kchunk;
+    dim3 grid(M / 64, N / 64, used);
+    hipLaunchKernelGGL((k_gemm_nt<0, T>), grid, dim3(256), 0, st, A, lda, B, ldb, K, kchunk, part, N,
+                       (int64_t)M * N, (const float *)nullptr, (T *)nullptr, 0);
+    const int64_t count = (int64_t)M * N;
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, part, used, count, C);
 }
 
 // ---------------------------------------------------------------------------
 // Elementwise and small kernels.
 
-// X0[r][c] = bf16((feat[r][c] - mean[c]) * inv_std[c]); rows >= n are zero.
+// X0[r][c] = T((feat[r][c] - mean[c]) * inv_std[c]); rows >= n are zero.
+template <typename T>
 __global__ void k_standardize(const float *__restrict__ feat, const float *__restrict__ norm, int64_t n,
-                              int64_t rows, __bf16 *__restrict__ X0) {
+                              int64_t rows, T *__restrict__ X0) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * kMlpIn) return;
     const int64_t r = i / kMlpIn;
     const int c = (int)(i % kMlpIn);
     const float v = r < n ? (feat[i] - norm[c]) * norm[kMlpIn + c] : 0.0f;
-    X0[i] = (__bf16)v;
+    X0[i] = to_elem<T>(v);
 }
 
-// bf16 copies of the weights: Wk[out][in] and their transposes Wk^T[in][out].
-__global__ void k_weights_bf16(const float *__restrict__ P, __bf16 *__restrict__ W1, __bf16 *__restrict__ W2,
-                               __bf16 *__restrict__ W3, __bf16 *__restrict__ W2t, __bf16 *__restrict__ W3t,
-                               __bf16 *__restrict__ W1t) {
+// T copies of the weights: Wk[out][in] and their transposes Wk^T[in][out].
+template <typename T>
+__global__ void k_weights_cast(const float *__restrict__ P, T *__restrict__ W1, T *__restrict__ W2,
+                               T *__restrict__ W3, T *__restrict__ W2t, T *__restrict__ W3t, T *__restrict__ W1t) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kMlpH * kMlpIn) {
         const int o = i / kMlpIn, c = i % kMlpIn;
-        const __bf16 v = (__bf16)P[kOffW1 + i];
+        const T v = to_elem<T>(P[kOffW1 + i]);
         W1[i] = v;
         W1t[c * kMlpH + o] = v;
     }
     if (i < kMlpH * kMlpH) {
         const int o = i / kMlpH, c = i % kMlpH;
-        const __bf16 v2 = (__bf16)P[kOffW2 + i], v3 = (__bf16)P[kOffW3 + i];
+        const T v2 = to_elem<T>(P[kOffW2 + i]), v3 = to_elem<T>(P[kOffW3 + i]);
         W2[i] = v2;
         W3[i] = v3;
         W2t[c * kMlpH + o] = v2;
@@ -125,8 +216,9 @@ __global__ void k_weights_bf16(const float *__restrict__ P, __bf16 *__restrict__
     }
 }
 
-// y[r] = H3[r] . w4 + b4 (w4 rounded to bf16 like the other weights), one wave per row.
-__global__ __launch_bounds__(256) void k_head(const __bf16 *__restrict__ H3, const float *__restrict__ P, int64_t n,
+// y[r] = H3[r] . w4 + b4 (w4 rounded to T like the other weights), one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_head(const T *__restrict__ H3, const float *__restrict__ P, int64_t n,
                                               float *__restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -135,24 +227,28 @@ __global__ __launch_bounds__(256) void k_head(const __bf16 *__restrict__ H3, con
 #pragma unroll
     for (int k = 0; k < kMlpH / 64; ++k) {
         const int c = k * 64 + lane;
-        acc += (float)H3[r * kMlpH + c] * (float)(__bf16)P[kOffW4 + c];
+        acc += (float)H3[r * kMlpH + c] * (float)to_elem<T>(P[kOffW4 + c]);
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) y[r] = acc + P[kOffB4];
 }
 
 // Loss and head backward.  dy = 2 (yhat - y) / n; per row r < n:
-//   dZ3[r][c] = dy w4[c] silu'(Z3[r][c])  (bf16, also transposed into dZ3t)
-// grad(w4)[c] += sum_r dy H3[r][c], grad(b4) += sum_r dy, loss += (yhat - y)^2 / n.
+//   dZ3[r][c] = dy w4[c] silu'(Z3[r][c])  (T, also transposed into dZ3t).
+// Block b (64 rows) writes its sums over those rows to part[b][0..257]:
+// grad(w4)[c] (c < 256), grad(b4) (256) and the loss (257); k_head_sums adds
+// the blocks in order (no float atomics: the result is deterministic).
+constexpr int kHeadCols = kMlpH + 2;
+template <typename T>
 __global__ __launch_bounds__(256) void k_head_backward(const float *__restrict__ yhat, const float *__restrict__ y,
                                                        int64_t n, int64_t rows, const float *__restrict__ Z3,
-                                                       const __bf16 *__restrict__ H3, const float *__restrict__ P,
-                                                       __bf16 *__restrict__ dZ3, __bf16 *__restrict__ dZ3t,
-                                                       float *__restrict__ G, float *__restrict__ loss) {
+                                                       const T *__restrict__ H3, const float *__restrict__ P,
+                                                       T *__restrict__ dZ3, T *__restrict__ dZ3t,
+                                                       float *__restrict__ part) {
     // one block per 64 rows; thread c handles column c of those rows
     const int c = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * 64;
-    const float w4 = (float)(__bf16)P[kOffW4 + c];
+    const float w4 = (float)to_elem<T>(P[kOffW4 + c]);
     float gw = 0.0f, gb = 0.0f, ls = 0.0f;
     for (int k = 0; k < 64; ++k) {
         const int64_t r = r0 + k;
@@ -167,32 +263,49 @@ __global__ __launch_bounds__(256) void k_head_backward(const float *__restrict__
                 ls += e * e / (float)n;
             }
         }
-        const __bf16 b = (__bf16)dz;
+        const T b = to_elem<T>(dz);
         dZ3[r * kMlpH + c] = b;
         dZ3t[(int64_t)c * rows + r] = b;
     }
-    atomicAdd(&G[kOffW4 + c], gw);
+    float *out = part + (int64_t)blockIdx.x * kHeadCols;
+    out[c] = gw;
     if (c == 0) {
-        atomicAdd(&G[kOffB4], gb);
-        atomicAdd(loss, ls);
+        out[kMlpH] = gb;
+        out[kMlpH + 1] = ls;
     }
 }
 
-// dZ = dH * silu'(Z) for a hidden layer; writes bf16 dZ and its transpose.
+// G[kOffW4 + c] (c <= 256: w4 then b4) and the loss from the per-block
+// partials, summed over blocks in order.
+__global__ __launch_bounds__(256) void k_head_sums(const float *__restrict__ part, int nblocks,
+                                                   float *__restrict__ G, float *__restrict__ loss) {
+    for (int c = threadIdx.x; c < kHeadCols; c += 256) {
+        float s = 0.0f;
+        for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kHeadCols + c];
+        if (c < kMlpH + 1)
+            G[kOffW4 + c] = s;
+        else
+            *loss = s;
+    }
+}
+
+// dZ = dH * silu'(Z) for a hidden layer; writes T dZ and its transpose.
+template <typename T>
 __global__ void k_act_backward(const float *__restrict__ dH, const float *__restrict__ Z, int64_t n, int64_t rows,
-                               __bf16 *__restrict__ dZ, __bf16 *__restrict__ dZt) {
+                               T *__restrict__ dZ, T *__restrict__ dZt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * kMlpH) return;
     const int64_t r = i / kMlpH;
     const int c = (int)(i % kMlpH);
     const float v = r < n ? dH[i] * silu_grad(Z[i]) : 0.0f;
-    const __bf16 b = (__bf16)v;
+    const T b = to_elem<T>(v);
     dZ[i] = b;
     dZt[(int64_t)c * rows + r] = b;
 }
 
-// out[c][r] = in[r][c] for a rows x cols bf16 matrix.
-__global__ void k_transpose_bf16(const __bf16 *__restrict__ in, int64_t rows, int cols, __bf16 *__restrict__ out) {
+// out[c][r] = in[r][c] for a rows x cols matrix.
+template <typename T>
+__global__ void k_transpose(const T *__restrict__ in, int64_t rows, int cols, T *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * cols) return;
     const int64_t r = i / cols;
@@ -200,8 +313,9 @@ __global__ void k_transpose_bf16(const __bf16 *__restrict__ in, int64_t rows, in
     out[(int64_t)c * rows + r] = in[i];
 }
 
-// grad(b)[c] += sum_r dZt[c][r]: one block per output c.
-__global__ __launch_bounds__(256) void k_bias_grad(const __bf16 *__restrict__ dZt, int64_t rows, float *__restrict__ g) {
+// grad(b)[c] = sum_r dZt[c][r]: one block per output c, fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bias_grad(const T *__restrict__ dZt, int64_t rows, float *__restrict__ g) {
     __shared__ float sh[256];
     const int c = blockIdx.x;
     float s = 0.0f;
@@ -212,29 +326,27 @@ __global__ __launch_bounds__(256) void k_bias_grad(const __bf16 *__restrict__ dZ
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) g[c] += sh[0];
-}
-
-__global__ void k_add_f32(float *__restrict__ dst, const float *__restrict__ src, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] += src[i];
+    if (threadIdx.x == 0) g[c] = sh[0];
 }
 
 // Adam (Kingma & Ba) with bias correction; m and v follow P in `adam`.
+// omb1 = 1 - beta1 and omb2 = 1 - beta2 come from the host rounded once from
+// double (1.0f - 0.999f in float32 would be 5e-5 off 0.001).
 __global__ void k_adam(float *__restrict__ P, float *__restrict__ adam, const float *__restrict__ G, int64_t n,
-                       float lr, float b1, float b2, float eps, float c1, float c2) {
+                       float lr, float b1, float b2, float omb1, float omb2, float eps, float c1, float c2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float g = G[i];
-    const float m = b1 * adam[i] + (1.0f - b1) * g;
-    const float v = b2 * adam[n + i] + (1.0f - b2) * g * g;
+    const float m = b1 * adam[i] + omb1 * g;
+    const float v = b2 * adam[n + i] + omb2 * (g * g);
     adam[i] = m;
     adam[n + i] = v;
     P[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
 // Deterministic initialisation: uniform(-a, a) with a = sqrt(6 / (fan_in + fan_out))
-// for weights (Philox of (index, layer) with the given seed), zero biases.
+// for weights (24 bits of a 64-bit finaliser of seed and parameter index:
+// MurmurHash3's fmix64), zero biases.
 __device__ __forceinline__ uint32_t mix32(uint64_t x) {
     x ^= x >> 33;
     x *= 0xff51afd7ed558ccdull;
@@ -266,26 +378,32 @@ __global__ void k_mlp_init(float *__restrict__ P, uint64_t seed) {
 }
 
 // ---------------------------------------------------------------------------
-size_t mlp_scratch_bytes(int64_t rows) {
+// Training scratch for `rows` rows with elements of `esz` bytes (2: BF16,
+// 4: FP32); the largest of the two is what the host reserves.
+static size_t mlp_scratch_bytes_e(int64_t rows, size_t esz) {
     const size_t h = (size_t)rows * kMlpH;
     size_t b = 0;
-    b += 2 * (size_t)kMlpH * kMlpIn * 2 + 4 * (size_t)kMlpH * kMlpH * 2;  // bf16 weights and transposes
-    b += (size_t)rows * kMlpIn * 2 * 2;                                   // X0, X0t
-    b += 3 * h * 4;                                                       // Z1..Z3
-    b += 4 * h * 2;                                                       // H1..H3, transposed H
-    b += (size_t)rows * 4;                                                // yhat
-    b += 2 * h * 2 + h * 4;                                               // dZ, dZt, dH
-    b += (size_t)kMlpParams * 4;                                          // gradient buffer
-    b += (size_t)kMlpH * kMlpH * 4;                                       // weight-gradient temp
+    b += (2 * (size_t)kMlpH * kMlpIn + 4 * (size_t)kMlpH * kMlpH) * esz;   // weights and transposes
+    b += (size_t)rows * kMlpIn * 2 * esz;                                  // X0, X0t
+    b += 3 * h * 4;                                                        // Z1..Z3
+    b += 4 * h * esz;                                                      // H1..H3, transposed H
+    b += (size_t)rows * 4;                                                 // yhat
+    b += 2 * h * esz + h * 4;                                              // dZ, dZt, dH
+    b += (size_t)kMlpParams * 4;                                           // gradient buffer
+    b += (size_t)kMaxSplits * kMlpH * kMlpH * 4;                           // split-K partial products
+    b += (size_t)(rows / 64 + 1) * kHeadCols * 4;                          // head partials per block
     return b + 64 * 256;
 }
+size_t mlp_scratch_bytes(int64_t rows) { return mlp_scratch_bytes_e(rows, 4); }
 
+template <typename T>
 struct MlpBufs {
-    __bf16 *W1, *W1t, *W2, *W3, *W2t, *W3t, *X0, *X0t, *H1, *H2, *H3, *Ht, *dZ, *dZt;
-    float *Z1, *Z2, *Z3, *yhat, *dH, *G, *Gtmp;
+    T *W1, *W1t, *W2, *W3, *W2t, *W3t, *X0, *X0t, *H1, *H2, *H3, *Ht, *dZ, *dZt;
+    float *Z1, *Z2, *Z3, *yhat, *dH, *G, *Gpart, *Hpart;
 };
 
-static MlpBufs carve_mlp(void *base, int64_t rows) {
+template <typename T>
+static MlpBufs<T> carve_mlp(void *base, int64_t rows) {
     char *p = (char *)base;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -295,44 +413,41 @@ static MlpBufs carve_mlp(void *base, int64_t rows) {
         return r;
     };
     const size_t h = (size_t)rows * kMlpH;
-    MlpBufs m;
-    m.W1 = (__bf16 *)take((size_t)kMlpH * kMlpIn * 2);
-    m.W1t = (__bf16 *)take((size_t)kMlpH * kMlpIn * 2);
-    m.W2 = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
-    m.W3 = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
-    m.W2t = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
-    m.W3t = (__bf16 *)take((size_t)kMlpH * kMlpH * 2);
-    m.X0 = (__bf16 *)take((size_t)rows * kMlpIn * 2);
-    m.X0t = (__bf16 *)take((size_t)rows * kMlpIn * 2);
+    const size_t e = sizeof(T);
+    MlpBufs<T> m;
+    m.W1 = (T *)take((size_t)kMlpH * kMlpIn * e);
+    m.W1t = (T *)take((size_t)kMlpH * kMlpIn * e);
+    m.W2 = (T *)take((size_t)kMlpH * kMlpH * e);
+    m.W3 = (T *)take((size_t)kMlpH * kMlpH * e);
+    m.W2t = (T *)take((size_t)kMlpH * kMlpH * e);
+    m.W3t = (T *)take((size_t)kMlpH * kMlpH * e);
+    m.X0 = (T *)take((size_t)rows * kMlpIn * e);
+    m.X0t = (T *)take((size_t)rows * kMlpIn * e);
     m.Z1 = (float *)take(h * 4);
     m.Z2 = (float *)take(h * 4);
     m.Z3 = (float *)take(h * 4);
-    m.H1 = (__bf16 *)take(h * 2);
-    m.H2 = (__bf16 *)take(h * 2);
-    m.H3 = (__bf16 *)take(h * 2);
-    m.Ht = (__bf16 *)take(h * 2);
+    m.H1 = (T *)take(h * e);
+    m.H2 = (T *)take(h * e);
+    m.H3 = (T *)take(h * e);
+    m.Ht = (T *)take(h * e);
     m.yhat = (float *)take((size_t)rows * 4);
-    m.dZ = (__bf16 *)take(h * 2);
-    m.dZt = (__bf16 *)take(h * 2);
+    m.dZ = (T *)take(h * e);
+    m.dZt = (T *)take(h * e);
     m.dH = (float *)take(h * 4);
     m.G = (float *)take((size_t)kMlpParams * 4);
-    m.Gtmp = (float *)take((size_t)kMlpH * kMlpH * 4);
+    m.Gpart = (float *)take((size_t)kMaxSplits * kMlpH * kMlpH * 4);
+    m.Hpart = (float *)take((size_t)(rows / 64 + 1) * kHeadCols * 4);
     return m;
 }
 
 static inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-static void mlp_forward_rows(const float *P, const MlpBufs &m, int64_t rows, bool keep_z, hipStream_t st) {
+template <typename T>
+static void mlp_forward_rows(const float *P, const MlpBufs<T> &m, int64_t rows, hipStream_t st) {
     const int H = kMlpH;
-    if (keep_z) {
-        gemm_nt(1, m.X0, kMlpIn, m.W1, kMlpIn, rows, H, kMlpIn, m.Z1, H, P + kOffB1, m.H1, H, st);
-        gemm_nt(1, m.H1, H, m.W2, H, rows, H, H, m.Z2, H, P + kOffB2, m.H2, H, st);
-        gemm_nt(1, m.H2, H, m.W3, H, rows, H, H, m.Z3, H, P + kOffB3, m.H3, H, st);
-    } else {
-        gemm_nt(2, m.X0, kMlpIn, m.W1, kMlpIn, rows, H, kMlpIn, nullptr, H, P + kOffB1, m.H1, H, st);
-        gemm_nt(2, m.H1, H, m.W2, H, rows, H, H, nullptr, H, P + kOffB2, m.H2, H, st);
-        gemm_nt(2, m.H2, H, m.W3, H, rows, H, H, nullptr, H, P + kOffB3, m.H3, H, st);
-    }
+    gemm_nt<T>(1, m.X0, kMlpIn, m.W1, kMlpIn, rows, H, kMlpIn, m.Z1, H, P + kOffB1, m.H1, H, st);
+    gemm_nt<T>(1, m.H1, H, m.W2, H, rows, H, H, m.Z2, H, P + kOffB2, m.H2, H, st);
+    gemm_nt<T>(1, m.H2, H, m.W3, H, rows, H, H, m.Z3, H, P + kOffB3, m.H3, H, st);
 }
 
 // Fused inference: one block of 4 waves per 64 rows runs the whole network
@@ -444,56 +559,67 @@ void mlp_init(float *params, uint64_t seed, hipStream_t st) {
 }
 
 // Predictions for n rows of raw features: the bf16 weights, then one fused
-// launch over every row (`rows` only sizes the scratch the weights come from).
+// launch over every row (the scratch holds only the weights).
 void mlp_forward(const float *P, const float *feat, const float *norm, int64_t n, float *y, void *scratch,
                  int64_t rows, hipStream_t st) {
-    const MlpBufs m = carve_mlp(scratch, rows);
-    hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3, m.W2t,
-                       m.W3t, m.W1t);
+    const MlpBufs<__bf16> m = carve_mlp<__bf16>(scratch, rows);
+    hipLaunchKernelGGL(k_weights_cast<__bf16>, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3,
+                       m.W2t, m.W3t, m.W1t);
     hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)((n + kFuseRows - 1) / kFuseRows)), dim3(256), 0, st, feat, norm, n,
                        m.W1, m.W2, m.W3, P, y);
 }
 
-// Loss and gradient on one batch of n <= rows rows; if adam != nullptr also
-// applies one Adam step (step >= 1).  grad_out (optional) receives the gradient.
-void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *feat, const float *norm,
-                    const float *y, int64_t n, float *loss, float *grad_out, void *scratch, int64_t rows,
-                    hipStream_t st) {
-    const MlpBufs m = carve_mlp(scratch, rows);
+// Loss and gradient on one batch of n <= rows rows with elements T; if
+// adam != nullptr also applies one Adam step (step >= 1).  grad_out
+// (optional) receives the gradient.  Every sum has a fixed order, so two
+// calls on the same inputs give the same bits.
+template <typename T>
+static void train_step_t(float *P, float *adam, int64_t step, float lr, const float *feat, const float *norm,
+                         const float *y, int64_t n, float *loss, float *grad_out, void *scratch, int64_t rows,
+                         hipStream_t st) {
+    const MlpBufs<T> m = carve_mlp<T>(scratch, rows);
     const int H = kMlpH;
     const int64_t R = (n + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_weights_bf16, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3, m.W2t,
-                       m.W3t, m.W1t);
-    hipLaunchKernelGGL(k_standardize, dim3(blocks_for(R * kMlpIn)), dim3(256), 0, st, feat, norm, n, R, m.X0);
-    mlp_forward_rows(P, m, R, true, st);
-    hipLaunchKernelGGL(k_head, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, m.H3, P, R, m.yhat);
-    launch_fill_u32((uint32_t *)m.G, 0u, kMlpParams, st);
-    launch_fill_u32((uint32_t *)loss, 0u, 1, st);
-    hipLaunchKernelGGL(k_head_backward, dim3((unsigned)(R / 64)), dim3(256), 0, st, m.yhat, y, n, R, m.Z3, m.H3, P,
-                       m.dZ, m.dZt, m.G, loss);
+    hipLaunchKernelGGL(k_weights_cast<T>, dim3(blocks_for(kMlpH * kMlpH)), dim3(256), 0, st, P, m.W1, m.W2, m.W3,
+                       m.W2t, m.W3t, m.W1t);
+    hipLaunchKernelGGL(k_standardize<T>, dim3(blocks_for(R * kMlpIn)), dim3(256), 0, st, feat, norm, n, R, m.X0);
+    mlp_forward_rows<T>(P, m, R, st);
+    hipLaunchKernelGGL(k_head<T>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, m.H3, P, R, m.yhat);
+    hipLaunchKernelGGL(k_head_backward<T>, dim3((unsigned)(R / 64)), dim3(256), 0, st, m.yhat, y, n, R, m.Z3, m.H3, P,
+                       m.dZ, m.dZt, m.Hpart);
+    hipLaunchKernelGGL(k_head_sums, dim3(1), dim3(256), 0, st, m.Hpart, (int)(R / 64), m.G, loss);
     // layer 3: grad W3 = dZ3^T H2, grad b3, dH2 = dZ3 W3
-    hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H2, R, H, m.Ht);
-    gemm_nt(0, m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.G + kOffW3, H, nullptr, nullptr, 0, st);
-    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB3);
-    gemm_nt(0, m.dZ, H, m.W3t, H, R, H, H, m.dH, H, nullptr, nullptr, 0, st);
-    hipLaunchKernelGGL(k_act_backward, dim3(blocks_for(R * H)), dim3(256), 0, st, m.dH, m.Z2, n, R, m.dZ, m.dZt);
+    hipLaunchKernelGGL(k_transpose<T>, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H2, R, H, m.Ht);
+    gemm_nt_splitk<T>(m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.Gpart, m.G + kOffW3, st);
+    hipLaunchKernelGGL(k_bias_grad<T>, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB3);
+    gemm_nt<T>(0, m.dZ, H, m.W3t, H, R, H, H, m.dH, H, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_act_backward<T>, dim3(blocks_for(R * H)), dim3(256), 0, st, m.dH, m.Z2, n, R, m.dZ, m.dZt);
     // layer 2
-    hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H1, R, H, m.Ht);
-    gemm_nt(0, m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.G + kOffW2, H, nullptr, nullptr, 0, st);
-    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB2);
-    gemm_nt(0, m.dZ, H, m.W2t, H, R, H, H, m.dH, H, nullptr, nullptr, 0, st);
-    hipLaunchKernelGGL(k_act_backward, dim3(blocks_for(R * H)), dim3(256), 0, st, m.dH, m.Z1, n, R, m.dZ, m.dZt);
+    hipLaunchKernelGGL(k_transpose<T>, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H1, R, H, m.Ht);
+    gemm_nt_splitk<T>(m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.Gpart, m.G + kOffW2, st);
+    hipLaunchKernelGGL(k_bias_grad<T>, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB2);
+    gemm_nt<T>(0, m.dZ, H, m.W2t, H, R, H, H, m.dH, H, nullptr, nullptr, 0, st);
+    hipLaunchKernelGGL(k_act_backward<T>, dim3(blocks_for(R * H)), dim3(256), 0, st, m.dH, m.Z1, n, R, m.dZ, m.dZt);
     // layer 1: grad W1 = dZ1^T X0
-    hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(R * kMlpIn)), dim3(256), 0, st, m.X0, R, kMlpIn, m.X0t);
-    gemm_nt(0, m.dZt, (int)R, m.X0t, (int)R, H, kMlpIn, (int)R, m.G + kOffW1, kMlpIn, nullptr, nullptr, 0, st);
-    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB1);
+    hipLaunchKernelGGL(k_transpose<T>, dim3(blocks_for(R * kMlpIn)), dim3(256), 0, st, m.X0, R, kMlpIn, m.X0t);
+    gemm_nt_splitk<T>(m.dZt, (int)R, m.X0t, (int)R, H, kMlpIn, (int)R, m.Gpart, m.G + kOffW1, st);
+    hipLaunchKernelGGL(k_bias_grad<T>, dim3(H), dim3(256), 0, st, m.dZt, R, m.G + kOffB1);
     if (grad_out) hipMemcpyAsync(grad_out, m.G, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, st);
     if (adam) {
-        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-        const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+        const double b1 = 0.9, b2 = 0.999;
+        const float c1 = (float)(1.0 - std::pow(b1, (double)step)), c2 = (float)(1.0 - std::pow(b2, (double)step));
         hipLaunchKernelGGL(k_adam, dim3(blocks_for(kMlpParams)), dim3(256), 0, st, P, adam, m.G, (int64_t)kMlpParams,
-                           lr, b1, b2, eps, c1, c2);
+                           lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
     }
+}
+
+void mlp_train_step(float *P, float *adam, int64_t step, float lr, const float *feat, const float *norm,
+                    const float *y, int64_t n, float *loss, float *grad_out, void *scratch, int64_t rows,
+                    hipStream_t st, bool fp32) {
+    if (fp32)
+        train_step_t<float>(P, adam, step, lr, feat, norm, y, n, loss, grad_out, scratch, rows, st);
+    else
+        train_step_t<__bf16>(P, adam, step, lr, feat, norm, y, n, loss, grad_out, scratch, rows, st);
 }
 
 }  // namespace gs

@@ -256,6 +256,20 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
         // stops its rays exactly where the unmasked run does)
         const uint64_t bal = __ballot(keep);
         const uint32_t key = __float_as_uint((float)pz);
+        // Depth keys that FP32 rounding could order either way: pz within
+        // 2^-40 pz of the midpoint between its float32 rounding and a float32
+        // neighbour (pz > z_near > 0, so the neighbours are the next and
+        // previous bit patterns).  Counted only; such keys are rare.
+        if (vis) {
+            const double f = (double)__uint_as_float(key);
+            const double up = 0.5 * (f + (double)__uint_as_float(key + 1u));
+            const double dn = 0.5 * (f + (double)__uint_as_float(key - 1u));
+            const double band = ldexp(pz, -40);
+            const bool amb = fabs(pz - up) <= band || fabs(pz - dn) <= band;
+            const uint64_t ab = __ballot(amb);
+            if (ab && (threadIdx.x & 63) == 0)
+                atomicAdd((unsigned long long *)&counters[CNT_AMB_KEYS], (unsigned long long)__popcll(ab));
+        }
         const uint32_t cm = wave_max_u32(vis ? __float_as_uint(cbar) : 0u);
         const uint32_t klo = wave_min_u32(keep ? key : 0xFFFFFFFFu);
         const uint32_t khi = wave_max_u32(keep ? key : 0u);

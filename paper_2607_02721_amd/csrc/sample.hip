@@ -11,15 +11,31 @@
 
 namespace gs {
 
-__global__ void k_quantize(const float *__restrict__ s, int64_t n, uint64_t *__restrict__ q) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float x = s[i];
-    q[i] = x > 0.0f ? (uint64_t)ceil(ldexp((double)x, 40)) : 0ull;
+// Accepted sensitivities: [0, 1 + 2^-10].  A share is at most 1, but its
+// float32 value can exceed 1 by a few ulps (a Gaussian alone on a ray scores
+// (c rho) (1/A) with 1/A rounded); with n <= 2^24 - 2^16 values of at most
+// 2^40 + 2^30 each, Q stays below 2^64.
+constexpr float kSensMax = 1.0009765625f;   // 1 + 2^-10
+
+// q_i = ceil(s_i 2^40) (0 for s_i = 0 and for values outside the accepted
+// range, which k_quantize reports).
+__device__ __forceinline__ uint64_t quantum(float x) {
+    return (x > 0.0f && x <= kSensMax) ? (uint64_t)ceil(ldexp((double)x, 40)) : 0ull;
 }
 
-void launch_quantize(const float *sens, int64_t n, uint64_t *q, hipStream_t st) {
-    hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sens, n, q);
+// A sensitivity outside [0, 1 + 2^-10] (or NaN) could overflow Q: such a
+// value gets q_i = 0 and raises *bad, which the host reads with Q and turns
+// into an error.
+__global__ void k_quantize(const float *__restrict__ s, int64_t n, uint64_t *__restrict__ q, uint32_t *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float x = i < n ? s[i] : 0.0f;
+    const bool ok = x >= 0.0f && x <= kSensMax;
+    if (i < n) q[i] = quantum(x);
+    if (__ballot(!ok) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+void launch_quantize(const float *sens, int64_t n, uint64_t *q, uint32_t *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sens, n, q, bad);
 }
 
 // Philox4x32-10 (Salmon et al., SC 2011): ten rounds of two 32x32->64
@@ -68,16 +84,17 @@ void launch_draws(const uint64_t *C, int64_t n, int64_t m, uint64_t seed, uint32
     hipLaunchKernelGGL(k_draws, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, C, n, m, seed, counts);
 }
 
+// With q null, q_i is recomputed from the sensitivities (same value).
 __global__ void k_weights(const uint32_t *__restrict__ counts, const uint64_t *__restrict__ q,
-                          const uint64_t *__restrict__ C, int64_t n, int64_t m, double *__restrict__ w,
-                          int64_t *__restrict__ support) {
+                          const float *__restrict__ sens, const uint64_t *__restrict__ C, int64_t n, int64_t m,
+                          double *__restrict__ w, int64_t *__restrict__ support) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = i < n;
     const uint32_t c = ok ? counts[i] : 0u;
     if (ok) {
         const double Q = (double)C[n - 1];
         const double num = (double)c * Q;
-        const double den = (double)m * (double)q[i];
+        const double den = (double)m * (double)(q ? q[i] : quantum(sens[i]));
         w[i] = c ? num / den : 0.0;
     }
     const uint64_t bal = __ballot(c > 0u);
@@ -85,10 +102,10 @@ __global__ void k_weights(const uint32_t *__restrict__ counts, const uint64_t *_
         atomicAdd((unsigned long long *)support, (unsigned long long)__popcll(bal));
 }
 
-void launch_weights(const uint32_t *counts, const uint64_t *q, const uint64_t *C, int64_t n, int64_t m,
-                    double *weights, int64_t *support, hipStream_t st) {
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, counts, q, C, n, m, weights,
-                       support);
+void launch_weights(const uint32_t *counts, const uint64_t *q, const float *sens, const uint64_t *C, int64_t n,
+                    int64_t m, double *weights, int64_t *support, hipStream_t st) {
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, counts, q, sens, C, n, m,
+                       weights, support);
 }
 
 }  // namespace gs

@@ -311,6 +311,37 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T *__restrict
     }
 }
 
+// The inclusive apply phase over one array in place: each thread reads its
+// own items before the block scan and writes the same items after it, so no
+// item is read after another thread has written it (no __restrict__ here:
+// input and output are the same memory).
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply_inplace(uint64_t *data, int64_t n,
+                                                                      const uint64_t *__restrict__ partial) {
+    __shared__ uint64_t sh[kScanThreads];
+    const int64_t lo = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = lo + k;
+        v[k] = i < n ? data[i] : 0ull;
+        s += v[k];
+    }
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<uint64_t>(s, sh, &total) + partial[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = lo + k;
+        run += v[k];
+        if (i < n) data[i] = run;
+    }
+}
+
+void scan_u64_inclusive_inplace(uint64_t *data, int64_t n, uint64_t *tmp, hipStream_t st) {
+    const int64_t nblk = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_reduce<uint64_t>, dim3((unsigned)nblk), dim3(kScanThreads), 0, st, data, n, tmp);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, tmp, nblk);
+    hipLaunchKernelGGL(k_scan_apply_inplace, dim3((unsigned)nblk), dim3(kScanThreads), 0, st, data, n, tmp);
+}
+
 // out[i] = sum_{j<i} in[j] for i in [0, n]; out has n+1 entries.
 void scan_u32_to_u64_exclusive(const uint32_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t st) {
     const int64_t nblk = (n + kScanBlock - 1) / kScanBlock;

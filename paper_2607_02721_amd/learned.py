@@ -46,6 +46,18 @@ def features(scene: DeviceScene, stream=None):
     return out
 
 
+def knn(scene: DeviceScene, stream=None):
+    """The 16 nearest other means of every Gaussian (gs_knn): (indices as an
+    int32 view of uint32 [n, 16], float32 squared distances [n, 16])."""
+    torch = _torch()
+    idx = torch.empty((scene.n, 16), dtype=torch.int32, device=scene.opacity.device)
+    d2 = torch.empty((scene.n, 16), dtype=torch.float32, device=scene.opacity.device)
+    sc = scene.c_struct()
+    _lib.check(load().gs_knn(C.byref(sc), C.c_void_p(idx.data_ptr()), C.c_void_p(d2.data_ptr()),
+                             _stream_handle(stream)))
+    return idx, d2
+
+
 def feature_stats(feat, stream=None):
     torch = _torch()
     norm = torch.empty((2, N_FEATURES), dtype=torch.float32, device=feat.device)
@@ -93,14 +105,15 @@ class Proposal:
             C.c_void_p(grad.data_ptr()) if grad is not None else None, _stream_handle()))
         return loss
 
-    def gradient(self, feat, target):
-        """Loss and gradient on a batch without updating (for checks)."""
+    def gradient(self, feat, target, fp32=False):
+        """Loss and gradient on a batch without updating (gs_mlp_gradient), in
+        BF16 (the training arithmetic) or with fp32=True in FP32."""
         torch = _torch()
         loss = torch.empty(1, dtype=torch.float32, device=feat.device)
         grad = torch.empty(self.P, dtype=torch.float32, device=feat.device)
-        _lib.check(load().gs_mlp_train_step(
-            C.c_void_p(self.params.data_ptr()), None, 0, C.c_float(0.0), C.c_void_p(feat.data_ptr()),
-            C.c_void_p(self.norm.data_ptr()), C.c_void_p(target.data_ptr()), feat.shape[0],
+        _lib.check(load().gs_mlp_gradient(
+            C.c_void_p(self.params.data_ptr()), C.c_void_p(feat.data_ptr()), C.c_void_p(self.norm.data_ptr()),
+            C.c_void_p(target.data_ptr()), feat.shape[0], _lib.MLP_FP32 if fp32 else _lib.MLP_BF16,
             C.c_void_p(loss.data_ptr()), C.c_void_p(grad.data_ptr()), _stream_handle()))
         return loss, grad
 
@@ -150,7 +163,9 @@ def sample_with_fallback(scene: DeviceScene, judge_views, m: int, seed: int, pro
     """Draw a weighted coreset from the learned mixture proposal; judge it by
     E (per-view fixed objective on the masked judge rays); if E exceeds the
     bound, run the exact sensitivity pass (on `exact_views`, default the judge
-    views) and draw from it instead."""
+    views) and draw from it instead.  The result says which draw it returns
+    ("fallback") and whether that draw meets the bound ("bound_met": False
+    when the exact draw misses it too, since no draw of this m did)."""
     torch = _torch()
     t0 = time.perf_counter()
     if feat is None:
@@ -162,14 +177,15 @@ def sample_with_fallback(scene: DeviceScene, judge_views, m: int, seed: int, pro
     ob = render_objective(scene, judge_views, w, OBJ_FIXED, ray_mask=judge_mask, per_ray=False, diag=False)
     err = coreset_error(ob["per_view"])
     t2 = time.perf_counter()
-    out = {"weights": w, "E_learned": err, "fallback": False, "ms_propose": (t1 - t0) * 1e3,
-           "ms_judge": (t2 - t1) * 1e3}
+    out = {"weights": w, "E_learned": err, "fallback": False, "bound_met": err <= err_bound,
+           "ms_propose": (t1 - t0) * 1e3, "ms_judge": (t2 - t1) * 1e3}
     if err > err_bound:
         s, _ = sensitivity(scene, exact_views if exact_views is not None else judge_views)
         _, w2, _ = sample_coreset(s, m, seed)
         ob2 = render_objective(scene, judge_views, w2, OBJ_FIXED, ray_mask=judge_mask, per_ray=False,
                                diag=False)
         torch.cuda.synchronize()
-        out.update(weights=w2, fallback=True, E_exact=coreset_error(ob2["per_view"]),
+        e2 = coreset_error(ob2["per_view"])
+        out.update(weights=w2, fallback=True, E_exact=e2, bound_met=e2 <= err_bound,
                    ms_fallback=(time.perf_counter() - t2) * 1e3)
     return out

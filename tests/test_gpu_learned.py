@@ -1,6 +1,8 @@
 """Learned proposal on the GPU: MFMA MLP forward/gradient against the FP64
-reference (same bf16-rounded weights and inputs), kNN features against a
-k-d tree, training, the gain over uniform sampling, and the fallback."""
+reference (same bf16-rounded weights and inputs; the FP32 mode of the same
+kernels at 1e-5), the Adam step against the FP64 reference, deterministic
+training, neighbour sets bit-exact and all 64 features against the oracle,
+training, the gain over uniform sampling, and the fallback."""
 import numpy as np
 import pytest
 
@@ -82,26 +84,134 @@ def test_gradient_matches_reference(gs, L):
         assert r <= 2e-2, (a, b, r)
 
 
-def test_knn_features_match_kdtree(gs, L):
-    from scipy.spatial import cKDTree
+def test_gradient_fp32_mode_matches_reference(gs, L):
+    """The FP32 mode of the same kernels (FP32 operands on
+    v_mfma_f32_16x16x4_f32, FP32 activations) against the FP64 reference on
+    the same FP32 parameters and standardised inputs: loss and every layer's
+    gradient within 1e-5 relative (L2)."""
+    from oracle import mlp_ref
+    feat, y = _random_batch(4096, seed=2)
+    prop = L.Proposal(seed=6)
+    prop.set_norm(L.feature_stats(feat))
+    loss, grad = prop.gradient(feat, y, fp32=True)
+    P = prop.params.double().cpu().numpy()
+    X = ((feat - prop.norm[0]) * prop.norm[1]).double().cpu().numpy()
+    l_ref, g_ref = mlp_ref.loss_and_grad(P, X, y.double().cpu().numpy())
+    g = grad.double().cpu().numpy()
+    rels = []
+    for a, b in ((0, 16384), (16384, 16640), (16640, 82176), (82176, 82432), (82432, 147968),
+                 (147968, 148224), (148224, 148481)):
+        rels.append(float(np.linalg.norm(g[a:b] - g_ref[a:b]) / np.linalg.norm(g_ref[a:b])))
+    print(f"[mlp grad fp32] loss {float(loss.item()):.8f} vs {l_ref:.8f}; rel-L2 per block "
+          + " ".join(f"{r:.2e}" for r in rels), flush=True)
+    assert abs(float(loss.item()) - l_ref) <= 1e-5 * l_ref
+    assert max(rels) <= 1e-5
+
+
+def test_adam_step_matches_reference(gs, L):
+    """Two training steps: the parameters and both moments after each equal
+    the FP64 Adam step applied to the gradient the kernels computed (the
+    update itself is checked, the gradient is checked above)."""
+    import torch
+    from oracle import mlp_ref
+    feat, y = _random_batch(2048, seed=4)
+    prop = L.Proposal(seed=8)
+    prop.set_norm(L.feature_stats(feat))
+    P = prop.params.double().cpu().numpy()
+    m = np.zeros_like(P)
+    v = np.zeros_like(P)
+    for step, lr in ((1, 1e-3), (2, 3e-3)):
+        g = torch.empty_like(prop.params)
+        prop.train_step(feat, y, lr=lr, grad=g)
+        torch.cuda.synchronize()
+        P, m, v = mlp_ref.adam_step(P, m, v, g.double().cpu().numpy(), step, lr)
+        got_P = prop.params.double().cpu().numpy()
+        got_m = prop.adam[:prop.P].double().cpu().numpy()
+        got_v = prop.adam[prop.P:].double().cpu().numpy()
+        scale = np.abs(m).max()
+        assert np.all(np.abs(got_m - m) <= 1e-6 * np.abs(m) + 1e-7 * scale), step
+        assert np.all(np.abs(got_v - v) <= 1e-6 * np.abs(v) + 1e-30), step
+        # the step is at most lr per parameter: compare it to lr, and the
+        # parameters to their float32 rounding
+        assert np.all(np.abs(got_P - P) <= 2e-6 * lr + 2e-7 * np.abs(P)), step
+        P = got_P.copy()    # continue from the float32 parameters the kernels hold
+
+
+def test_training_is_deterministic(gs, L):
+    """Two runs of the same training steps give bit-identical parameters."""
+    import torch
+    feat, y = _random_batch(20_000, seed=9)
+    outs = []
+    for _ in range(2):
+        prop = L.Proposal(seed=2)
+        prop.set_norm(L.feature_stats(feat))
+        for k in range(3):
+            prop.train_step(feat[k * 5000:(k + 2) * 5000].contiguous(), y[k * 5000:(k + 2) * 5000].contiguous(),
+                            lr=1e-3)
+        torch.cuda.synchronize()
+        outs.append(prop.params.clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+def _dequantized(sc):
+    """The float32 values of a mixed16 scene (bf16 mean, log-scale, SH; f16
+    quaternion and opacity), exactly as the kernels widen them."""
+    import torch
+    q = lambda a, dt: np.ascontiguousarray(torch.as_tensor(np.asarray(a, np.float32)).to(dt).float().numpy())
+    return synth.Scene(q(sc.mean, torch.bfloat16), q(sc.log_scale, torch.bfloat16),
+                       q(sc.quat, torch.float16), q(sc.opacity, torch.float16),
+                       q(sc.sh, torch.bfloat16), sc.sh_degree)
+
+
+def _knn_check(gs, L, ora, sc, label, fmt=None):
+    """Neighbour indices and float32 squared distances bit-exact against the
+    oracle's brute force; every feature column against the FP64 features."""
+    import torch
+    d = gs.DeviceScene.from_scene(sc) if fmt is None else gs.DeviceScene.from_scene(sc, fmt=fmt)
+    if fmt is not None:     # the oracle sees the dequantized scene the kernels read
+        sc = _dequantized(sc)
+    idx, d2 = L.knn(d)
+    f = L.features(d)
+    torch.cuda.synchronize()
+    ref_f, ref_idx, ref_d2 = ora.features(sc)
+    gi = idx.cpu().numpy().view(np.uint32)
+    gd = d2.cpu().numpy()
+    bad = np.nonzero(np.any(gi != ref_idx, axis=1))[0]
+    print(f"[knn {label}] n={sc.n} rows with other neighbours: {bad.size}", flush=True)
+    assert bad.size == 0, (bad[:5], gi[bad[:1]], ref_idx[bad[:1]])
+    assert np.array_equal(gd.view(np.uint32), ref_d2.view(np.uint32))
+    g = f.cpu().numpy().astype(np.float64)
+    exact = list(range(0, 6)) + list(range(11, 59)) + [62]
+    assert np.array_equal(g[:, exact], ref_f[:, exact])
+    tol = {6: 1e-6, 7: 1e-6, 8: 1e-6, 9: 1e-6, 10: 1e-5, 59: 1e-5, 60: 1e-5, 61: 1e-6, 63: 1e-5}
+    for c, t in tol.items():
+        err = np.abs(g[:, c] - ref_f[:, c]) / np.maximum(1.0, np.abs(ref_f[:, c]))
+        assert err.max() <= t, (label, c, float(err.max()))
+
+
+def test_knn_features_match_oracle(gs, L, ora):
     sc = synth.make_cluster_scene(20_000, 11, 3)
-    f = L.features(gs.DeviceScene.from_scene(sc)).cpu().numpy().astype(np.float64)
-    pts = sc.mean.T.astype(np.float64)
-    d, idx = cKDTree(pts).query(pts, k=17)
-    d, idx = d[:, 1:], idx[:, 1:]
-    al = sc.opacity.astype(np.float64)
-    mean_d = d.mean(1)
-    d16 = d[:, -1]
-    na = al[idx]
-    dens = na.sum(1) / (4.0 / 3.0 * np.pi * d16 ** 3)
-    assert np.allclose(f[:, 0:3], pts, atol=0)
-    assert np.allclose(f[:, 59], np.log(mean_d), atol=1e-4)
-    assert np.allclose(f[:, 60], np.log(d16), atol=1e-4)
-    ok = np.abs(f[:, 61] - na.mean(1)) < 1e-5
-    assert ok.mean() > 0.999            # neighbour sets agree except for float32 near-ties
-    assert np.allclose(f[:, 63], np.log(dens), atol=1e-3)
-    sh = sc.sh.reshape(-1, sc.n).T
-    assert np.array_equal(f[:, 11:59], sh.astype(np.float64))
+    _knn_check(gs, L, ora, sc, "cluster20k")
+
+
+def test_knn_features_edge_cases(gs, L, ora):
+    """Fewer points than neighbours, a lattice full of distance ties (ties go
+    by index), coincident means, and mixed16 storage."""
+    rng = np.random.default_rng(12)
+    for n in (1, 2, 9, 17):
+        sc = synth.make_explicit_scene(rng.uniform(-1, 1, (n, 3)), np.full((n, 3), -3.0),
+                                       np.tile([1.0, 0, 0, 0], (n, 1)), rng.uniform(0.1, 0.9, n),
+                                       colours=np.full((n, 3), 0.5))
+        _knn_check(gs, L, ora, sc, f"n={n}")
+    g = np.arange(9, dtype=np.float64) * 0.125
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    pts = np.concatenate([pts, pts[:50]])           # 50 coincident pairs
+    n = pts.shape[0]
+    sc = synth.make_explicit_scene(pts, np.full((n, 3), -3.0), rng.standard_normal((n, 4)),
+                                   rng.uniform(0.1, 0.9, n), colours=rng.uniform(0, 1, (n, 3)))
+    _knn_check(gs, L, ora, sc, "lattice")
+    _knn_check(gs, L, ora, synth.make_cluster_scene(5_000, 13, 2), "mixed16", fmt=gs.ATTR_MIXED16)
 
 
 def _train_scenes(n_scenes=3, n=60_000, views=20):

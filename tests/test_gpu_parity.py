@@ -1,10 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Floating point: |s_gpu - s_oracle| <= 1e-5 s_oracle + 1e-12 for every
-Gaussian, and per-ray A within 1e-5 relative, on the rays the oracle does not
-flag as ambiguous (a pair within 1e-5 r^2 of the footprint cutoff, or an
-order key within 2^-40 of a float32 rounding midpoint); both sides score
-exactly the same unflagged rays through the ray mask.  Sampling: bit-exact
+Gaussian, and per-ray A within 1e-5 relative, on the rays neither side flags
+as ambiguous (the oracle: a pair within 1e-5 r^2 of the footprint cutoff, or
+an order key within 2^-40 of a float32 rounding midpoint; the GPU: a pair
+within 1e-5 r^2 of the cutoff in its own float32 arithmetic); both sides
+score exactly the same unflagged rays through the ray mask.  Sampling: bit-exact
 counts, weights and support given the same float32 sensitivities.
 """
 import math
@@ -12,6 +13,7 @@ import math
 import numpy as np
 import pytest
 
+import parity_util
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -29,24 +31,22 @@ def gs():
     return gs
 
 
-def _mask_tensor(bits):
-    import torch
-    return torch.as_tensor(np.ascontiguousarray(bits, np.uint32).view(np.int32)).cuda()
+_mask_tensor = parity_util.mask_tensor
 
 
 def _parity(gs, ora, sc, vw, label, **kw):
-    ref_all = ora.sensitivity(sc, vw, ora.default_params(**{k: v for k, v in kw.items()
-                                                            if k in ("query_mode", "dilation")}))
-    keep = ~ref_all["flag"]
-    bits = synth.pack_bits(keep)
-    ref = ora.sensitivity(sc, vw, ora.default_params(**{k: v for k, v in kw.items()
-                                                        if k in ("query_mode", "dilation")}), bits)
+    """Both sides score the rays outside the union of the oracle's and the
+    GPU's ambiguity flags."""
+    oprm = ora.default_params(**{k: v for k, v in kw.items() if k in ("query_mode", "dilation")})
     dsc = gs.DeviceScene.from_scene(sc)
+    bits, oflag, gflag = parity_util.union_mask(gs, ora, sc, vw, dsc, oprm, **kw)
+    ref = ora.sensitivity(sc, vw, oprm, bits)
     s, st = gs.sensitivity(dsc, vw, ray_mask=_mask_tensor(bits), stats=True, count_pairs=True, **kw)
     s = s.cpu().numpy().astype(np.float64)
     excess = np.abs(s - ref["s"]) - (REL * ref["s"] + ABS)
     worst = int(np.argmax(excess))
-    print(f"[{label}] n={sc.n} flagged rays={int(ref_all['flag'].sum())}/{vw.n_rays} "
+    print(f"[{label}] n={sc.n} flagged rays: oracle {int(oflag.sum())}, gpu {int(gflag.sum())}, "
+          f"gpu only {int((gflag & ~oflag).sum())} of {vw.n_rays}; sort passes {st['sort_passes']} "
           f"max rel err={np.max(np.abs(s - ref['s']) / np.maximum(ref['s'], 1e-30)):.2e} "
           f"worst excess={excess[worst]:.2e} (s_ref={ref['s'][worst]:.3e})", flush=True)
     assert excess.max() <= 0, f"{label}: Gaussian {worst}: gpu {s[worst]!r} oracle {ref['s'][worst]!r}"
@@ -64,6 +64,29 @@ def _ragged():
     sc = synth.make_cluster_scene(20_000, 7, 3)
     vw = synth.make_orbit_views(3, 17, 200, 136)
     return sc, vw
+
+
+def test_tiny_scene_sorts_in_three_passes(gs, ora):
+    """Orbit views of the tiny scene see depths within a factor of four, so
+    every view's keys span under 2^24 and the depth sort takes 3 passes."""
+    sc, vw, _, _ = synth.make_config("tiny")
+    _, st = gs.sensitivity(gs.DeviceScene.from_scene(sc), vw, stats=True)
+    assert st["sort_passes"] == 3
+
+
+@pytest.mark.parametrize("eye", [(1.3, 0.35, 0.25), (0.2, -0.1, 0.05)])
+def test_four_pass_depth_sort_parity(gs, ora, eye):
+    """A camera close to the cloud, or inside it, sees depths from z_near to
+    several units: the keys span more than 2^24, the depth sort takes four
+    8-bit passes, and the sensitivities still meet the bar."""
+    sc, _, _, _ = synth.make_config("tiny")
+    vw = synth.make_camera_set([eye, (3.0, 0.2, 0.4)], [(0.0, 0.0, 0.0), (0.0, 0.0, 0.0)], 96, 72, 70.0)
+    pr = ora.project(sc, vw)
+    z = pr["z"][0][pr["present"][0]]
+    print(f"[4-pass {eye}] depths {z.min():.3f}..{z.max():.3f}, visible {z.size}", flush=True)
+    s, ref, st, _ = _parity(gs, ora, sc, vw, f"4-pass {eye}")
+    assert st["sort_passes"] == 4
+    assert float(np.max(ref["s"])) > 0.5
 
 
 def test_ragged_cluster_scene_parity(gs, ora):
@@ -163,7 +186,7 @@ def test_render_full_matches_oracle(gs, ora):
 
 
 @pytest.mark.parametrize("n,m,seed", [(2000, 200, 0), (100_000, 10_000, 123456789012345),
-                                      (257, 5000, 2 ** 63 + 11)])
+                                      (257, 5000, 2 ** 63 + 11), (1_000_000, 100_000, 0)])
 def test_sampler_bit_exact(gs, ora, n, m, seed):
     import torch
     rng = np.random.default_rng(n)
@@ -192,6 +215,49 @@ def test_sampler_rejects_all_zero(gs):
     with pytest.raises(gs.GsError) as e:
         gs.sample_coreset(torch.zeros(100, device="cuda"), 10, 0)
     assert e.value.status == 4
+
+
+def test_sampler_rejects_values_outside_unit_interval(gs, ora):
+    """A sensitivity is a largest share, so it lies in [0, 1] up to float32
+    rounding; a value above 1 + 2^-10 (which could overflow the 64-bit CDF),
+    NaN or a negative value is rejected with the outputs zeroed, as the
+    oracle does; 1 and values an ulp above it are drawn as usual."""
+    import torch
+    rng = np.random.default_rng(77)
+    base = rng.uniform(0, 1, 5000).astype(np.float32)
+    for v in (np.float32(1.001), np.float32(2.0 ** 30), np.float32(np.nan),
+              np.float32(-1e-30), np.float32(np.inf)):
+        x = base.copy()
+        x[1234] = v
+        assert ora.sample(x, 100, 1)["status"] == 5
+        with pytest.raises(gs.GsError) as e:
+            counts, w, sup = gs.sample_coreset(torch.as_tensor(x).cuda(), 100, 1)
+        assert e.value.status == 5
+    x = base.copy()
+    x[:100] = 1.0
+    x[100] = np.nextafter(np.float32(1), np.float32(2))
+    x[101] = np.float32(1 + 2.0 ** -10)
+    ref = ora.sample(x, 300, 2)
+    counts, w, sup = gs.sample_coreset(torch.as_tensor(x).cuda(), 300, 2)
+    assert ref["status"] == 0
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), ref["counts"])
+    assert np.array_equal(w.cpu().numpy().view(np.uint64), ref["weights"].view(np.uint64))
+
+
+def test_coreset_error_kernel(gs):
+    """gs_coreset_error against its definition on per-view sums, views with
+    A = 0 left out."""
+    import torch
+    rng = np.random.default_rng(5)
+    pv = rng.uniform(0.5, 2.0, (333, 3))
+    pv[7, 0] = 0.0
+    pv[7, 1] = 50.0
+    on = pv[:, 0] > 0
+    want0 = np.max(np.abs(pv[on, 1] - pv[on, 0]) / pv[on, 0])
+    want1 = np.max(np.abs(pv[on, 2] - pv[on, 0]) / pv[on, 0])
+    t = torch.as_tensor(pv).cuda()
+    assert gs.coreset_error(t) == want0
+    assert gs.coreset_error(t, reduced=True) == want1
 
 
 def test_objective_parity(gs, ora):

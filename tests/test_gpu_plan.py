@@ -1,12 +1,12 @@
-"""Batched plans (several scenes in one captured sequence) against the
-per-scene entry point: every scene's sensitivities must be bit-identical to
-gs_sensitivity with the same parameters, for every launch shape, on graph
-replays, after in-place attribute updates, and across scene groups.  (The
-per-scene entry point is itself held to the FP64 oracle by the parity tests,
-so bit-identity carries that parity over.)  The list-capacity guard is
-exercised by growing the footprints in place."""
+"""Batched plans (several scenes in one captured sequence) against the FP64
+oracle (element by element, per scene) and against the per-scene entry
+point: every scene's sensitivities must be bit-identical to gs_sensitivity
+with the same parameters, for every launch shape, on graph replays, after
+in-place attribute updates, and across scene groups.  The list-capacity and
+depth-span guards are exercised by changing attributes in place."""
 import pytest
 
+import parity_util
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -70,6 +70,39 @@ def test_plan_matches_per_scene_calls(gs, batch, ref):
     for k, (o, r) in enumerate(zip(outs, ref)):
         assert float(r.max()) > 0.0
         assert _same(o, r), (k, float((o - r).abs().max()))
+    plan.close()
+
+
+def test_plan_matches_oracle(gs, ora):
+    """Each scene of a plan against the FP64 oracle, element by element:
+    three orbit scenes of mixed sizes and SH degrees, and one whose first
+    camera sits close to the cloud (its keys span more than 2^24, so the plan
+    sorts that scene with four passes).  Plans take no ray mask, so the
+    Gaussians a flagged ray touches are left out (see parity_util)."""
+    import torch
+    specs = SPECS[:2] + [(4_000, 14, 2, 2, 96, 80)]
+    batch = _batch(gs, specs)
+    close_sc = synth.make_tiny_scene(3_000, 15)
+    close_vw = synth.make_camera_set([(1.3, 0.35, 0.25), (0.0, 3.0, 0.5)], [(0.0, 0.0, 0.0)] * 2, 112, 80, 70.0)
+    batch.append((gs.DeviceScene.from_scene(close_sc), close_vw))
+    scenes = [synth.make_cluster_scene(n, seed, deg) for n, seed, deg, _, _, _ in specs] + [close_sc]
+    plan = gs.Plan([d for d, _ in batch], [v for _, v in batch])
+    info = plan.info()
+    print("[plan vs oracle]", info, flush=True)
+    assert info["n_sort3_scenes"] == len(batch) - 1
+    outs = plan.run()
+    torch.cuda.synchronize()
+    plan.status()
+    for k, ((d, vw), sc, o) in enumerate(zip(batch, scenes, outs)):
+        ref = ora.sensitivity(sc, vw)
+        gflag = parity_util.gpu_flags(gs, d, vw)[0]
+        flag = ref["flag"] | gflag
+        touched = parity_util.touched_by_flagged(ora, sc, vw, flag)
+        worst, compared = parity_util.compare_unmasked(o.cpu().numpy(), ref["s"], touched)
+        print(f"[plan vs oracle] scene {k}: n={sc.n} flagged rays {int(flag.sum())}, Gaussians compared "
+              f"{compared}, worst excess {worst:.3e}", flush=True)
+        assert worst <= 0.0, k
+        assert compared >= 0.6 * sc.n
     plan.close()
 
 
