@@ -201,6 +201,20 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
 gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t seed,
                             uint32_t *counts, double *weights, int64_t *support, void *stream);
 
+/* gs_sample_coreset for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, checks and results, bit for bit, but the
+ * library allocates nothing.  Its scratch (the u64 CDF and the scan's block
+ * partials) is a file-scope device array sized for n <= 2^23 = 8,388,608
+ * Gaussians (64 MiB plus 32 KiB per GPU, held until the process ends); larger
+ * n returns GS_ERR_UNSUPPORTED.  Every call on a GPU uses that GPU's one
+ * array, so calls that overlap on one GPU (different streams, or threads
+ * that do not wait for each other's streams) race; the array keeps the last
+ * call's contents, and each call rewrites what it reads.  Synchronises the
+ * stream once (to read Q and the range check), like gs_sample_coreset. */
+gs_status gs_sample_coreset_noalloc(const float *sens, int64_t n, int64_t m, uint64_t seed,
+                                    uint32_t *counts, double *weights, int64_t *support, void *stream);
+
 /* Objectives of a weighted pruned scene (Section 3: A, the fixed relaxation
  * A^th_w = sum_i w_i a(G, g_i, q), and the true reduced render
  * A_w = sum_i w_i c_i rho_i T_w with T_w = prod_{j before i} (1 - w_j rho_j)).

@@ -209,9 +209,11 @@ class Plan:
             pass
 
 
-def sample_coreset(sens, m: int, seed: int, stream=None, out=None):
+def sample_coreset(sens, m: int, seed: int, stream=None, out=None, noalloc=False):
     """Counts (int32 view of uint32), float64 weights and support (int64 [1]).
-    out: optional (counts, weights, support) tensors to write into."""
+    out: optional (counts, weights, support) tensors to write into.
+    noalloc=True calls gs_sample_coreset_noalloc (same results, no device
+    allocation by the library; n <= 2^23)."""
     torch = _torch()
     lib = load()
     if sens.dtype != torch.float32 or not sens.is_cuda or not sens.is_contiguous():
@@ -223,7 +225,8 @@ def sample_coreset(sens, m: int, seed: int, stream=None, out=None):
         support = torch.empty(1, dtype=torch.int64, device=sens.device)
     else:
         counts, weights, support = out
-    status = lib.gs_sample_coreset(C.c_void_p(sens.data_ptr()), n, int(m), C.c_uint64(seed & (2**64 - 1)),
+    fn = lib.gs_sample_coreset_noalloc if noalloc else lib.gs_sample_coreset
+    status = fn(C.c_void_p(sens.data_ptr()), n, int(m), C.c_uint64(seed & (2**64 - 1)),
                 C.c_void_p(counts.data_ptr()), C.c_void_p(weights.data_ptr()),
                 C.c_void_p(support.data_ptr()), _stream_handle(stream))
     _lib.check(status)

@@ -24,7 +24,7 @@ EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_de
             "gs_plan_create", "gs_plan_set_config", "gs_plan_tune", "gs_plan_get_info",
             "gs_plan_sensitivity", "gs_plan_status", "gs_plan_destroy", "gs_proposal_mixture",
             "gs_log_targets", "gs_measure_peaks", "gs_knn", "gs_coreset_error", "gs_mlp_gradient",
-            "gs_set_allocator", "gs_region_bound"]
+            "gs_sample_coreset_noalloc", "gs_set_allocator", "gs_region_bound"]
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 MLP_BF16, MLP_FP32 = 0, 1
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
         lib.gs_sensitivity.restype = C.c_int
         lib.gs_sample_coreset.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, P, P, P, P]
         lib.gs_sample_coreset.restype = C.c_int
+        lib.gs_sample_coreset_noalloc.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, P, P, P, P]
+        lib.gs_sample_coreset_noalloc.restype = C.c_int
         lib.gs_render_objective.argtypes = [P, P, P, P, C.c_int32, P, P, P, P]
         lib.gs_render_objective.restype = C.c_int
         lib.gs_default_params.argtypes = [P]

@@ -634,6 +634,31 @@ int current_device(gs_status *st) {
     return dev;
 }
 
+// Sampling without allocation: the inclusive CDF of the quanta lives in a
+// file-scope device array instead of the scratch arena (the weights kernel
+// recomputes each q_i from s_i).  Every GPU the library runs on holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 23;
+constexpr int64_t kNoAllocTmp = (kNoAllocMaxN + 2047) / 2048 + 1;       // scan block partials
+constexpr size_t kNoAllocBytes = sizeof(uint64_t) * (size_t)(kNoAllocMaxN + kNoAllocTmp) + 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+void *g_noalloc_ptr[kMaxDevices];
+
+// The calling device's copy of `scratch`, looked up once per device (with
+// that device current).
+gs_status noalloc_scratch(int dev, void **out) {
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GS_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return GS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1001,6 +1026,50 @@ gs_status gs_sample_coreset(const float *sens, int64_t n, int64_t m, uint64_t se
 // ---------------------------------------------------------------------------
 // Learned proposal.
 constexpr int64_t kMlpRows = 65536;
+
+gs_status gs_sample_coreset_noalloc(const float *sens, int64_t n, int64_t m, uint64_t seed, uint32_t *counts,
+                                    double *weights, int64_t *support, void *stream) {
+    g_last_error.clear();
+    if (!sens || !counts || !weights || !support) return fail(GS_ERR_INVALID_ARGUMENT, "NULL array argument");
+    if (n < 1) return fail(GS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (n > kNoAllocMaxN)
+        return fail(GS_ERR_UNSUPPORTED, "n = %lld exceeds the %lld Gaussians the allocation-free sampler's fixed "
+                                        "scratch holds (use gs_sample_coreset)",
+                    (long long)n, (long long)kNoAllocMaxN);
+    if (m < 1) return fail(GS_ERR_INVALID_ARGUMENT, "m must be >= 1");
+    if (m >= ((int64_t)1 << 31)) return fail(GS_ERR_UNSUPPORTED, "m must be < 2^31");
+    std::lock_guard<std::mutex> lk(g_lock);
+    gs_status s;
+    const int dev = current_device(&s);
+    if (dev < 0) return s;
+    void *base = nullptr;
+    if ((s = noalloc_scratch(dev, &base)) != GS_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t *C = (uint64_t *)base;
+    uint64_t *tmp = C + kNoAllocMaxN;
+    uint32_t *bad = (uint32_t *)(tmp + kNoAllocTmp);
+    // the array keeps the previous call's contents: the flag starts at zero,
+    // and every C entry used is written (quanta, then their prefix sums)
+    // before it is read
+    launch_fill_u32(bad, 0u, 1, st);
+    launch_quantize(sens, n, C, bad, st);
+    scan_u64_inclusive_inplace(C, n, tmp, st);
+    launch_fill_u32(counts, 0u, n, st);
+    launch_fill_u64((uint64_t *)weights, 0ull, n, st);
+    launch_fill_u64((uint64_t *)support, 0ull, 1, st);
+    HIP_TRY(hipGetLastError());
+    uint64_t Q = 0;
+    uint32_t hbad = 0;
+    HIP_TRY(hipMemcpyAsync(&Q, C + n - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hbad) return fail(GS_ERR_INVALID_DATA, "a sensitivity is outside [0, 1 + 2^-10] or NaN");
+    if (Q == 0) return fail(GS_ERR_NO_POSITIVE_SENSITIVITY, "every sensitivity is 0");
+    launch_draws(C, n, m, seed, counts, st);
+    launch_weights(counts, nullptr, sens, C, n, m, weights, support, st);
+    HIP_TRY(hipGetLastError());
+    return GS_OK;
+}
 
 int64_t gs_mlp_param_count(void) { return kMlpParams; }
 
