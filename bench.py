@@ -131,7 +131,7 @@ def cpu_baseline(scene, views, n_views_total, gpu_live_sample, m, seed, s_gpu, n
             "sampler_status": smp["status"]}
 
 
-def batch_leg(gs, synth, torch, args):
+def batch_leg(gs, synth, torch, args, tile):
     """16 scenes of uneven sizes (50k-2M Gaussians, log-uniform; 24-200 views
     each at 640x360 / 1280x720 / 1920x1080) as one plan: capacities fixed at
     creation, the launch shape picked by the plan's tuner, each step one HIP
@@ -145,7 +145,7 @@ def batch_leg(gs, synth, torch, args):
     del batch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = gs.Plan(dev, views)
+    plan = gs.Plan(dev, views, tile=tile)
     t_create = time.perf_counter() - t0
     best, tune_ms = plan.tune(reps=1)
     info = plan.info()
@@ -165,7 +165,7 @@ def batch_leg(gs, synth, torch, args):
     t0 = time.perf_counter()
     same = True
     for d, vw, o in zip(dev, views, plan_out):
-        s_, _ = gs.sensitivity(d, vw)
+        s_, _ = gs.sensitivity(d, vw, tile=tile)
         same = same and bool(torch.equal(s_, o))
     torch.cuda.synchronize()
     ms_seq = (time.perf_counter() - t0) * 1e3
@@ -178,6 +178,7 @@ def batch_leg(gs, synth, torch, args):
             "ms_per_step": ms_plan, "ms_per_scene_calls": ms_seq, "identical_to_per_scene": same,
             "gaussian_views_per_s": gv / (ms_plan * 1e-3), "rays": rays,
             "tuner": {"best": best, "ms": dict(zip(["flat_xcd", "flat", "persistent"], tune_ms))},
+            "tile": list(tile),
             "groups": info["n_groups"], "device_bytes": info["device_bytes"],
             "composite_launches": info["n_launches"], "compacting_launches": info["n_compact_launches"],
             "compact_bytes": info["compact_bytes"], "graph": info["graph_captured"], "create_s": t_create}
@@ -190,7 +191,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--views", type=int, default=100)
-    ap.add_argument("--train-scenes", type=int, default=8)
+    ap.add_argument("--train-scenes", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-agg", action="store_true", help="skip the aggregated-query variants")
@@ -198,6 +199,9 @@ def main():
     ap.add_argument("--no-transfer", action="store_true", help="skip the transfer study on the judge rays")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak-rate microbenchmarks")
     ap.add_argument("--no-region", action="store_true", help="skip the compact-region bound")
+    ap.add_argument("--no-scan", action="store_true", help="skip the coreset-error scan over m and judges")
+    ap.add_argument("--tile", default="auto",
+                    help="binning tile WxH (8, 16 or 32 each), or 'auto' for the library's tuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 1 GiB device copies (reference dispatch for counter runs)")
     args = ap.parse_args()
@@ -227,10 +231,21 @@ def main():
     m, seed = 100_000, 0
     dsc = gs.DeviceScene.from_scene(scene)
     torch.cuda.synchronize()
+    # binning tile: the tuner times one call per shape (untimed, once); the
+    # shape changes the speed only, never the sensitivities
+    tile_ms = None
+    if args.tile == "auto":
+        tile, tile_ms = gs.tune_tile(dsc, views, reps=2)
+        log(f"tile tuner: {tile[0]}x{tile[1]}; ms by shape "
+            f"{json.dumps({f'{w}x{h}': round(v, 3) for (w, h), v in tile_ms.items()})}")
+    else:
+        tile = tuple(int(x) for x in args.tile.lower().split("x"))
 
     def step(stats=False, count_pairs=False, scene_dev=dsc, aggregate=gs.AGG_RAY, query_mode=gs.QUERY_RGBSUM):
+        # tile queries are 16x16 pixel tiles, binned as such
+        t_ = (16, 16) if aggregate == gs.AGG_TILE else tile
         s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs, aggregate=aggregate,
-                               query_mode=query_mode)
+                               query_mode=query_mode, tile=t_)
         counts, w, sup = gs.sample_coreset(s, m, seed)
         return s, st, w
 
@@ -392,7 +407,7 @@ def main():
     props = {"exact": s, "mixed16": s16, "uniform": torch.ones_like(s)}
     if learned is not None:
         props["learned"] = scores_learned
-    m_grid = (100_000, 200_000, 400_000, 800_000, 1_600_000, 3_200_000)
+    m_grid = () if args.no_scan else (100_000, 200_000, 400_000, 800_000, 1_600_000, 3_200_000)
     for name, sc_ in props.items():
         scan[name], scan_all[name] = {}, {}
         for mm in m_grid:
@@ -403,6 +418,15 @@ def main():
                 ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, per_ray=False, diag=False)
                 scan_all[name][str(mm)] = gs.coreset_error(ob["per_view"])
     passes_at = {name: next((int(k) for k, v in tab.items() if v <= 0.01), None) for name, tab in scan_all.items()}
+    # the same draws at m = 10^5 judged on 1% of the rays drawn one by one
+    # (splitmix64 rule), the judge set of the learned-proposal configuration
+    rays1 = torch.as_tensor(synth.ray_subsample_mask(views, 4202).view(np.int32)).cuda()
+    judge_rays = {}
+    for name, sc_ in (() if args.no_scan else props.items()):
+        _, w_, _ = gs.sample_coreset(sc_, m, seed)
+        ob = gs.render_objective(dsc, views, w_, gs.OBJ_FIXED, ray_mask=rays1, per_ray=False, diag=False)
+        judge_rays[name] = gs.coreset_error(ob["per_view"])
+    log(f"E at m={m} on 1% of the rays: {json.dumps(judge_rays)}")
     log(f"E vs m (judge rays): {json.dumps(scan)}")
     log(f"E vs m (all rays): {json.dumps(scan_all)}; smallest m with E <= 1%: {passes_at}")
 
@@ -473,7 +497,7 @@ def main():
 
     batching = None
     if not args.no_batch:
-        batching = batch_leg(gs, synth, torch, args)
+        batching = batch_leg(gs, synth, torch, args, tile)
 
     log("counting pairs (untimed) ...")
     _, cst, _ = step(stats=True, count_pairs=True)
@@ -534,7 +558,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on five views) ...")
-        _, st5 = gs.sensitivity(dsc, views.subset(list(range(5))), stats=True, count_pairs=True)
+        _, st5 = gs.sensitivity(dsc, views.subset(list(range(5))), stats=True, count_pairs=True, tile=tile)
         cpu = cpu_baseline(scene, views, args.views, st5["n_live_pairs"], m, seed, s.cpu().numpy())
 
     out = {
@@ -545,12 +569,15 @@ def main():
         "config": {"workload": "scene1m: 1M Gaussians (64 clusters + 10% uniform, SH deg 3), "
                                f"{args.views} orbit views 1280x720, m=100000, Philox seed 0"},
         "stages_ms": stage,
+        "tile": {"shape": f"{tile[0]}x{tile[1]}",
+                 "tuner_ms": None if tile_ms is None else {f"{w}x{h}": v for (w, h), v in tile_ms.items()}},
         "variants": {"exact_f32": {"ms": ms, "coreset_err": errs["exact"]},
                      "mixed16": {"ms": ms16, "coreset_err": errs["mixed16"], "stages_ms": stage16,
                                  "attribute_bytes": d16.attribute_bytes()},
                      "learned": learned, "aggregated": aggregated, "score_variants": modes},
         "coreset_err_vs_m": scan,
         "coreset_err_vs_m_all_rays": scan_all, "smallest_m_with_err_le_1pct_all_rays": passes_at,
+        "coreset_err_1pct_random_rays": judge_rays,
         "whole_pass_roofline": whole,
         "region": region_rep,
         "transfer": transfer,

@@ -129,6 +129,12 @@ typedef struct {
      * may put it on different sides of the cutoff) is OR-ed; the caller
      * clears it.  NULL = not reported.  Must be NULL for other calls. */
     uint32_t *ambiguous_rays;
+    /* Binning tile of the pipeline, pixels: 8, 16 or 32 each (0 = 16).  Any
+     * shape gives the same sensitivities (the tile only decides which lists
+     * a Gaussian enters, never which pairs count); wider tiles mean fewer
+     * list entries per Gaussian and more rays per list.  GS_AGG_TILE
+     * queries need 16 x 16. */
+    int32_t tile_w, tile_h;
 } gs_params;
 
 /* Filled only when a non-NULL pointer is passed (the call then synchronises
@@ -145,7 +151,7 @@ typedef struct {
     int64_t n_invalid_gaussians; /* non-finite attributes or zero quaternion (treated as absent) */
     double total_sensitivity; /* S = sum_i s_i, fixed-order reduction */
     double ms_project, ms_sort, ms_bin, ms_pass1, ms_pass2; /* device time per stage, summed over chunks */
-    double ms_emit;           /* the tile-list emission kernel alone (part of ms_bin) */
+    double ms_emit;           /* the tile-list emission kernel (not part of ms_bin) */
     int64_t n_bins;           /* (tile, chunk) segments: tiles x chunks of 16384 depth positions */
     int32_t sort_passes;      /* most 8-bit passes a view chunk's depth sort took: 3 when every view's
                                  depth keys span under 2^24 - 1, else 4 */
@@ -337,6 +343,18 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
 /* Changes the compositing launch shape (the next run re-captures). */
 gs_status gs_plan_set_config(gs_plan *plan, const gs_plan_config *config);
 
+/* Binning-tile tuner for gs_sensitivity: times one call per shape (after an
+ * untimed one) for each of the nine shapes {8, 16, 32} x {8, 16, 32}, in the
+ * order w = 8, 16, 32 outer, h = 8, 16, 32 inner, with `params` otherwise as
+ * given, writing into sens (device float[n], the caller's).  ms (host
+ * float[9], nullable) receives the mean time per call of each shape, or -1
+ * for a shape the views cannot take (too many tiles per view) or the
+ * parameters exclude (GS_AGG_TILE: 16 x 16 only); *best_w, *best_h the
+ * fastest.  The shape changes the speed only: every shape gives the same
+ * sensitivities.  Synchronises the stream. */
+gs_status gs_tune_tile(const gs_scene *scene, const gs_views *views, const gs_params *params, int32_t reps,
+                       float *sens, int32_t *best_w, int32_t *best_h, float *ms, void *stream);
+
 /* Times each launch shape ({0,1}, {0,0}, {1,0}) over `reps` >= 1 runs into
  * sens and keeps the fastest; ms (host float[3], nullable) receives the mean
  * time per run of each.  Synchronises the stream. */
@@ -446,7 +464,7 @@ typedef struct {
 gs_status gs_measure_peaks(gs_peaks *out, void *stream);
 
 /* Defaults for gs_params (r = 3, delta = 0.3, z_near = 0.2, floor 1e-12, RGB sum,
- * per-ray queries). */
+ * per-ray queries, 16 x 16 tiles). */
 void gs_default_params(gs_params *params);
 
 /* Frees the calling device's scratch arena (waits for the device first). */

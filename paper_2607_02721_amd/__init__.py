@@ -24,7 +24,7 @@ from ._lib import (AGG_IMAGE, AGG_RAY, AGG_SCENE, AGG_TILE, ATTR_F32, ATTR_MIXED
 __all__ = ["DeviceScene", "sensitivity", "sample_coreset", "render_objective", "GsError",
            "OBJ_FULL", "OBJ_FIXED", "OBJ_TRUE", "QUERY_RGBSUM", "QUERY_NOCOLOR", "QUERY_L2", "QUERY_CHANNEL", "ATTR_F32",
            "ATTR_MIXED16", "AGG_RAY", "AGG_TILE", "AGG_IMAGE", "AGG_SCENE", "load", "release_workspace",
-           "Plan", "measure_peaks", "coreset_error", "use_torch_allocator", "region_bound"]
+           "Plan", "measure_peaks", "coreset_error", "use_torch_allocator", "region_bound", "tune_tile"]
 
 
 def _torch():
@@ -88,8 +88,9 @@ def _views(views):
 
 
 def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
-            max_views_per_chunk, flags=0, aggregate=AGG_RAY, ambiguous_rays=None):
+            max_views_per_chunk, flags=0, aggregate=AGG_RAY, ambiguous_rays=None, tile=(16, 16)):
     p = _lib.default_params()
+    p.tile_w, p.tile_h = int(tile[0]), int(tile[1])
     p.flags = flags
     p.aggregate = aggregate
     p.footprint_sigma = footprint_sigma
@@ -112,18 +113,20 @@ def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask
 def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
                 share_floor=1e-12, query_mode=QUERY_RGBSUM, ray_mask=None,
                 max_views_per_chunk=0, stats=False, count_pairs=False, aggregate=AGG_RAY, out=None,
-                ambiguous_rays=None, stream=None):
+                ambiguous_rays=None, tile=(16, 16), stream=None):
     """Per-Gaussian sensitivities (float32 device tensor [n]) for queries of
     the given granularity (AGG_RAY, AGG_TILE, AGG_IMAGE, AGG_SCENE); with
     stats=True also a dict of counters and per-stage device milliseconds
     (pair counters need count_pairs=True, which can also OR the rays holding
     a pair within 1e-5 r^2 of the cutoff into the device bitset
-    `ambiguous_rays`)."""
+    `ambiguous_rays`).  `tile` is the binning tile (width, height), each 8,
+    16 or 32 pixels: it changes the speed, not the result."""
     torch = _torch()
     lib = load()
     hv = _views(views)
     p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
-                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0, aggregate, ambiguous_rays)
+                max_views_per_chunk, _lib.FLAG_COUNT_PAIRS if count_pairs else 0, aggregate, ambiguous_rays,
+                tile)
     if out is None:
         out = torch.empty(scene.n, dtype=torch.float32, device=scene.opacity.device)
     sc = scene.c_struct()
@@ -134,6 +137,28 @@ def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3,
     return out, (st.as_dict() if st is not None else None)
 
 
+def tune_tile(scene: DeviceScene, views, *, reps=2, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
+              share_floor=1e-12, query_mode=QUERY_RGBSUM, aggregate=AGG_RAY, max_views_per_chunk=0,
+              stream=None):
+    """Fastest binning tile (w, h) for gs_sensitivity on this scene and these
+    views (gs_tune_tile), and the mean ms per call of each shape as a dict
+    {(w, h): ms} (shapes the views cannot take are left out)."""
+    torch = _torch()
+    hv = _views(views)
+    p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, None, max_views_per_chunk,
+                aggregate=aggregate)
+    out = torch.empty(scene.n, dtype=torch.float32, device=scene.opacity.device)
+    bw, bh = C.c_int32(), C.c_int32()
+    ms = (C.c_float * 9)()
+    sc = scene.c_struct()
+    _lib.check(load().gs_tune_tile(C.byref(sc), C.byref(hv.c), C.byref(p), int(reps),
+                                   C.c_void_p(out.data_ptr()), C.byref(bw), C.byref(bh), ms,
+                                   _stream_handle(stream)))
+    sides = (8, 16, 32)
+    table = {(sides[k // 3], sides[k % 3]): float(ms[k]) for k in range(9) if ms[k] >= 0}
+    return (bw.value, bh.value), table
+
+
 class Plan:
     """Batched sensitivity pass over several scenes (gs_plan_* in the C ABI):
     capacities fixed at creation, the whole pass queued without host
@@ -141,7 +166,7 @@ class Plan:
     tensors must stay alive, at the same addresses, while the plan exists."""
 
     def __init__(self, scenes, views, *, footprint_sigma=3.0, dilation=0.3, z_near=0.2,
-                 share_floor=1e-12, query_mode=QUERY_RGBSUM, stream=None):
+                 share_floor=1e-12, query_mode=QUERY_RGBSUM, tile=(16, 16), stream=None):
         if len(scenes) != len(views) or not scenes:
             raise ValueError("need one views set per scene")
         lib = load()
@@ -149,7 +174,7 @@ class Plan:
         self._hv = [_views(v) for v in views]
         sc = (_lib.Scene * len(scenes))(*[s.c_struct() for s in scenes])
         vw = (_lib.Views * len(scenes))(*[h.c for h in self._hv])
-        p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, None, 0)
+        p = _params(footprint_sigma, dilation, z_near, share_floor, query_mode, None, 0, tile=tile)
         h = C.c_void_p()
         _lib.check(lib.gs_plan_create(sc, vw, len(scenes), C.byref(p), C.byref(h), _stream_handle(stream)))
         self._h = h
@@ -236,13 +261,13 @@ def sample_coreset(sens, m: int, seed: int, stream=None, out=None, noalloc=False
 def render_objective(scene: DeviceScene, views, weights=None, objective=OBJ_FULL, *,
                      footprint_sigma=3.0, dilation=0.3, z_near=0.2, query_mode=QUERY_RGBSUM,
                      ray_mask=None, max_views_per_chunk=0, per_ray=True, per_view=True,
-                     diag=True, stream=None):
+                     diag=True, tile=(16, 16), stream=None):
     """Objective of a weighted pruned scene: per-ray values (float32 [rays]),
     per-view sums of (A, A^th_w, A_w) (float64 [V, 3]) and diagnostics."""
     torch = _torch()
     lib = load()
     hv = _views(views)
-    p = _params(footprint_sigma, dilation, z_near, 0.0, query_mode, ray_mask, max_views_per_chunk)
+    p = _params(footprint_sigma, dilation, z_near, 0.0, query_mode, ray_mask, max_views_per_chunk, tile=tile)
     dev = scene.opacity.device
     pr = torch.zeros(hv.n_rays, dtype=torch.float32, device=dev) if per_ray else None
     pv = torch.zeros((hv.size.shape[0], 3), dtype=torch.float64, device=dev) if per_view else None

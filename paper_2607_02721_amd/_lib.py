@@ -24,7 +24,7 @@ EXPORTED = ["gs_sensitivity", "gs_sample_coreset", "gs_render_objective", "gs_de
             "gs_plan_create", "gs_plan_set_config", "gs_plan_tune", "gs_plan_get_info",
             "gs_plan_sensitivity", "gs_plan_status", "gs_plan_destroy", "gs_proposal_mixture",
             "gs_log_targets", "gs_measure_peaks", "gs_knn", "gs_coreset_error", "gs_mlp_gradient",
-            "gs_sample_coreset_noalloc", "gs_set_allocator", "gs_region_bound"]
+            "gs_sample_coreset_noalloc", "gs_set_allocator", "gs_region_bound", "gs_tune_tile"]
 
 OBJ_FULL, OBJ_FIXED, OBJ_TRUE = 0, 1, 2
 MLP_BF16, MLP_FP32 = 0, 1
@@ -55,7 +55,8 @@ class Params(C.Structure):
     _fields_ = [("footprint_sigma", C.c_float), ("dilation", C.c_float), ("z_near", C.c_float),
                 ("share_floor", C.c_float), ("query_mode", C.c_int32),
                 ("max_views_per_chunk", C.c_int32), ("flags", C.c_int32), ("ray_mask", C.c_void_p),
-                ("aggregate", C.c_int32), ("ambiguous_rays", C.c_void_p)]
+                ("aggregate", C.c_int32), ("ambiguous_rays", C.c_void_p),
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -147,6 +148,8 @@ def load(path: str = LIB_PATH):
         lib.gs_plan_create.argtypes = [P, P, C.c_int32, P, P, P]
         lib.gs_plan_set_config.argtypes = [P, P]
         lib.gs_plan_tune.argtypes = [P, P, C.c_int32, P, P, P]
+        lib.gs_tune_tile.argtypes = [P, P, P, C.c_int32, P, P, P, P, P]
+        lib.gs_tune_tile.restype = C.c_int
         lib.gs_plan_get_info.argtypes = [P, P]
         lib.gs_plan_sensitivity.argtypes = [P, P, P]
         lib.gs_plan_status.argtypes = [P, P]

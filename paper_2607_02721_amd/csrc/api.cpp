@@ -144,12 +144,20 @@ struct Setup {
     int agg = GS_AGG_RAY;       // query granularity of the sensitivity pass
     int nq = 1;                 // queries per ray (3 for per-channel queries)
     bool compact = false;       // pass 1 leaves compacted quadrant lists for pass 2
+    int tsx = kTileShiftDefault, tsy = kTileShiftDefault;   // binning tile 2^tsx x 2^tsy pixels
+    int quad_log = 2 * kTileShiftDefault - 6;               // log2 of the 8x8 quadrants per tile
     std::vector<int> tiles_x, tiles_y;
     std::vector<int64_t> ray_base;
 };
 
 // Compaction ranges are cut at every ceil(tiles / kRangeSamples)-th tile.
 constexpr int64_t kRangeSamples = 4096;
+
+int chunk_max_rows(const Setup &S, const ChunkPlan &c) {
+    int m = 1;
+    for (int k = 0; k < c.vc; ++k) m = std::max(m, S.tiles_y[c.v0 + k]);
+    return m;
+}
 
 size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     const int64_t N = S.N;
@@ -164,6 +172,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(4 * sizeof(uint32_t) * (size_t)c.vc);
     add(4 * sizeof(uint32_t) * (size_t)c.vc * proj_blocks(N));
     add(sizeof(uint32_t) * nbins);
+    add(sizeof(uint64_t) * (size_t)rowbits_words(c.vc, chunk_max_rows(S, c), S.nchunks));
     add(sizeof(uint32_t) * c.total_tiles);
     add(sizeof(uint64_t) * (c.total_tiles + 1));
     add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
@@ -171,19 +180,20 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(uint64_t) * CNT_WORDS);
     add(sizeof(ViewDev) * c.vc);
     add(sizeof(int32_t) * c.total_tiles);
-    add(c.total_tiles);                                     // tile activity
+    const size_t quads = (size_t)c.total_tiles << S.quad_log;
+    add(sizeof(uint16_t) * c.total_tiles);                  // tile activity
     add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // active-tile tables ((tx+1)(ty+1) <= 4 tx ty)
     add(sizeof(uint32_t) * (size_t)c.total_tiles);          // listed quadrants: per-tile counts,
     add(sizeof(uint64_t) * ((size_t)c.total_tiles + 1));    // their scan,
     add(sizeof(uint64_t) * scan_tmp_elems(c.total_tiles + 1));
-    add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // and the list
+    add(sizeof(uint32_t) * quads);                          // and the list
     add(sizeof(uint64_t) * (kRangeSamples + 2));            // sampled tile offsets (compaction ranges)
     add(sizeof(int32_t) * c.total_tiles);                   // tile -> scene slot
     add(sizeof(SceneSlot) + 256);                           // slot + work counter
     add(sizeof(double) * ((N + 4095) / 4096 + 2));
-    add(sizeof(double) * 3 * 4 * (size_t)c.total_tiles);   // objective partials
+    add(sizeof(double) * 3 * quads);                        // objective partials
     add(sizeof(double) * (3 * (size_t)c.vc + 1));
-    add(sizeof(uint32_t) * 4 * (size_t)c.total_tiles);      // compacted entries per quadrant
+    add(sizeof(uint32_t) * quads);                          // compacted entries per quadrant
     add(sizeof(double) * (size_t)c.total_tiles);            // per-tile A(Q)
     add(sizeof(double) * ((size_t)c.vc + 1));               // per-view A(Q), launch total
     if (S.agg == GS_AGG_IMAGE) add(sizeof(uint64_t) * (size_t)c.vc * N);   // per (view, Gaussian) shares
@@ -225,14 +235,35 @@ gs_status check_views(const gs_views *v, Setup &S) {
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(v->world_to_cam[12 * i + k]))
                 return fail(GS_ERR_INVALID_ARGUMENT, "view %d: non-finite extrinsics", i);
-        S.tiles_x[i] = (W + kTile - 1) / kTile;
-        S.tiles_y[i] = (H + kTile - 1) / kTile;
+        S.tiles_x[i] = (W + (1 << S.tsx) - 1) >> S.tsx;
+        S.tiles_y[i] = (H + (1 << S.tsy) - 1) >> S.tsy;
         if (S.tiles_x[i] * S.tiles_y[i] > kMaxTilesPerView)
-            return fail(GS_ERR_UNSUPPORTED, "view %d: %dx%d needs more than %d tiles of 16x16", i, W, H,
-                        kMaxTilesPerView);
+            return fail(GS_ERR_UNSUPPORTED, "view %d: %dx%d needs more than %d tiles of %dx%d", i, W, H,
+                        kMaxTilesPerView, 1 << S.tsx, 1 << S.tsy);
         S.ray_base[i + 1] = S.ray_base[i] + (int64_t)W * H;
     }
     return GS_OK;
+}
+
+// Whether every view (already checked) takes at most kMaxTilesPerView tiles
+// of 2^tsx x 2^tsy.
+bool tiles_fit(const gs_views *v, int tsx, int tsy) {
+    for (int i = 0; i < v->n_views; ++i) {
+        const int64_t tx = (v->size[2 * i] + (1 << tsx) - 1) >> tsx, ty = (v->size[2 * i + 1] + (1 << tsy) - 1) >> tsy;
+        if (tx * ty > kMaxTilesPerView) return false;
+    }
+    return true;
+}
+
+// log2 of a tile side (0 stands for 16), -1 for a side the kernels do not take.
+int tile_shift(int side) {
+    switch (side) {
+        case 0: return kTileShiftDefault;
+        case 8: return 3;
+        case 16: return 4;
+        case 32: return 5;
+        default: return -1;
+    }
 }
 
 gs_status check_params(const gs_params *p) {
@@ -258,7 +289,20 @@ gs_status check_params(const gs_params *p) {
     if (p->aggregate != GS_AGG_RAY && p->query_mode == GS_QUERY_CHANNEL)
         return fail(GS_ERR_UNSUPPORTED, "per-channel queries have no aggregated form (an aggregated query sums "
                                         "its channels: use GS_QUERY_RGBSUM)");
+    const int tw = tile_shift(p->tile_w), th = tile_shift(p->tile_h);
+    if (tw < 0 || th < 0)
+        return fail(GS_ERR_INVALID_ARGUMENT, "tile %dx%d: each side must be 8, 16 or 32 (or 0 for 16)", p->tile_w,
+                    p->tile_h);
+    if (p->aggregate == GS_AGG_TILE && (tw != 4 || th != 4))
+        return fail(GS_ERR_UNSUPPORTED, "tile queries are 16x16 pixel tiles: they need 16x16 binning tiles");
     return GS_OK;
+}
+
+// The binning tile of a call, from checked parameters.
+void setup_tiles(const gs_params *p, Setup &S) {
+    S.tsx = tile_shift(p->tile_w);
+    S.tsy = tile_shift(p->tile_h);
+    S.quad_log = S.tsx + S.tsy - 6;
 }
 
 // A size in GiB from the environment: false (and *bytes untouched) when the
@@ -385,6 +429,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.kmin = b.nvis + 2 * c.vc;
     b.proj_part = cv.take<uint32_t>(4 * (size_t)c.vc * proj_blocks(N));
     b.bin_count = cv.take<uint32_t>(nbins);
+    b.rows_stride = chunk_max_rows(S, c);
+    b.rowbits = cv.take<uint64_t>((size_t)rowbits_words(c.vc, b.rows_stride, S.nchunks));
     b.tile_tot = cv.take<uint32_t>(c.total_tiles);
     b.tile_off = cv.take<uint64_t>(c.total_tiles + 1);
     r.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
@@ -393,7 +439,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.counters = (uint64_t *)g_cnt[dev].base;
     r.views_dev = cv.take<ViewDev>(c.vc);
     r.tile_view = cv.take<int32_t>(c.total_tiles);
-    b.tile_active = p->ray_mask ? cv.take<uint8_t>(c.total_tiles) : nullptr;
+    b.tile_active = p->ray_mask ? cv.take<uint16_t>(c.total_tiles) : nullptr;
     b.tile_sat = p->ray_mask ? cv.take<uint32_t>(4 * (size_t)c.total_tiles) : nullptr;
     uint32_t *qcnt = nullptr;
     uint64_t *qoff = nullptr, *qtmp = nullptr;
@@ -403,16 +449,16 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         qcnt = cv.take<uint32_t>(c.total_tiles);
         qoff = cv.take<uint64_t>((size_t)c.total_tiles + 1);
         qtmp = cv.take<uint64_t>(scan_tmp_elems(c.total_tiles + 1));
-        r.quad_list = cv.take<uint32_t>(4 * (size_t)c.total_tiles);
+        r.quad_list = cv.take<uint32_t>((size_t)c.total_tiles << S.quad_log);
     }
     uint64_t *off_samples = cv.take<uint64_t>(kRangeSamples + 2);
     r.tile_scene = cv.take<int32_t>(c.total_tiles);
     r.slot_dev = cv.take<SceneSlot>(1);
     r.work = cv.take<uint32_t>(64);
     r.sum_tmp = cv.take<double>((N + 4095) / 4096 + 2);
-    r.tile_sums = cv.take<double>(3 * 4 * (size_t)c.total_tiles);
+    r.tile_sums = cv.take<double>(3 * ((size_t)c.total_tiles << S.quad_log));
     r.view_sums = cv.take<double>(3 * (size_t)c.vc + 1);
-    r.ccount = cv.take<uint32_t>(4 * (size_t)c.total_tiles);
+    r.ccount = cv.take<uint32_t>((size_t)c.total_tiles << S.quad_log);
     r.tile_A = cv.take<double>(c.total_tiles);
     r.view_A = cv.take<double>((size_t)c.vc + 1);
     r.acc = nullptr;
@@ -439,6 +485,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         V.H = views->size[2 * i + 1];
         V.tiles_x = S.tiles_x[i];
         V.tiles_y = S.tiles_y[i];
+        V.tsx = S.tsx;
+        V.tsy = S.tsy;
         V.ray_base = S.ray_base[i];
         V.ray_local = S.ray_base[i] - S.ray_base[c.v0];
         V.tile_base = tb;
@@ -472,7 +520,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     if (b.tile_active) {
         launch_tile_active(r.views_dev, r.tile_view, c.total_tiles, p->ray_mask, b.tile_active, st);
         launch_tile_sat(r.views_dev, c.vc, max_tx, max_ty, b.tile_active, b.tile_sat, st);
-        launch_quad_list(b.tile_active, c.total_tiles, qcnt, qoff, qtmp, r.quad_list, st);
+        launch_quad_list(b.tile_active, c.total_tiles, S.quad_log, qcnt, qoff, qtmp, r.quad_list, st);
     }
     tm.mark(0, st);
     launch_project(sd, r.views_dev, c.vc, pp, b, st);
@@ -534,7 +582,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     uint32_t *clist = nullptr;
     r.ranges.assign(1, ChunkRun::Range{0, c.total_tiles, 0});
     if (S.compact) {
-        const size_t cbytes = 4 * std::max<size_t>(total, 1) * sizeof(uint32_t);
+        // each quadrant of a tile gets a region of the tile's list length
+        const size_t cbytes = ((size_t)std::max<uint64_t>(total, 1) << S.quad_log) * sizeof(uint32_t);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
             (void)hipGetLastError();
@@ -560,7 +609,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
             HIP_TRY(hipMemcpyAsync(off.data(), off_samples, sizeof(uint64_t) * off.size(), hipMemcpyDeviceToHost,
                                    st));
             HIP_TRY(hipStreamSynchronize(st));
-            const uint64_t room = avail / (4 * sizeof(uint32_t));   // list entries whose compacted lists fit
+            const uint64_t room = avail / (sizeof(uint32_t) << S.quad_log);   // list entries whose compacted lists fit
             uint64_t longest = 0;
             for (int64_t k = 0; k < K; ++k) longest = std::max(longest, off[k + 1] - off[k]);
             if (longest <= room && arena_reserve(g_compact[dev], avail) == hipSuccess) {
@@ -593,14 +642,15 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         HIP_TRY(hipEventSynchronize(tm.ev[3]));
         ms_acc[0] += tm.ms(0, 1);
         ms_acc[1] += tm.ms(1, 2);
-        ms_acc[2] += tm.ms(2, 3);
+        ms_acc[2] += tm.ms(2, 6) + tm.ms(7, 3);   // binning around the emission, which has its own slot
         ms_acc[5] += tm.ms(6, 7);
     }
     return GS_OK;
 }
 
-CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params *p, float share_floor) {
+CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params *p, float share_floor, int quad_log) {
     CompositeArgs a{};
+    a.quad_log = quad_log;
     a.views = r.views_dev;
     a.tile_view = r.tile_view;
     a.tile_scene = r.tile_scene;
@@ -675,6 +725,8 @@ void gs_default_params(gs_params *p) {
     p->flags = 0;
     p->ray_mask = nullptr;
     p->aggregate = GS_AGG_RAY;
+    p->tile_w = 16;
+    p->tile_h = 16;
 }
 
 const char *gs_last_error(void) { return g_last_error.c_str(); }
@@ -738,8 +790,9 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     gs_status s;
     if ((s = check_scene(scene)) != GS_OK) return s;
     Setup S;
-    if ((s = check_views(views, S)) != GS_OK) return s;
     if ((s = check_params(params)) != GS_OK) return s;
+    setup_tiles(params, S);
+    if ((s = check_views(views, S)) != GS_OK) return s;
     if (!sens) return fail(GS_ERR_INVALID_ARGUMENT, "sens is NULL");
     std::lock_guard<std::mutex> lk(g_lock);
     const int dev = current_device(&s);
@@ -782,7 +835,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         entries += r.n_entries;
         n_bins += (int64_t)c.total_tiles * S.nchunks;
         sort_passes = std::max(sort_passes, r.passes);
-        CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor);
+        CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor, S.quad_log);
         a.ccount = r.host_slot.clist ? r.ccount : nullptr;
         if (r.quad_list) {
             // only the listed quadrants are composited: the other rays read A = 0
@@ -801,8 +854,8 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
                 CompositeArgs ar = a;
                 ar.tile_first = g.t0;
                 ar.total_tiles = g.t1 - g.t0;
-                ar.ccount = r.ccount + 4 * (size_t)g.t0;
-                ar.clist_shift = 4 * g.first;
+                ar.ccount = r.ccount + ((size_t)g.t0 << S.quad_log);
+                ar.clist_shift = g.first << S.quad_log;
                 if (tm.on) HIP_TRY(hipEventRecord(ev[3 * k], st));
                 launch_composite_pass1(ar, st);
                 if (tm.on) HIP_TRY(hipEventRecord(ev[3 * k + 1], st));
@@ -906,8 +959,9 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
     gs_status s;
     if ((s = check_scene(scene)) != GS_OK) return s;
     Setup S;
-    if ((s = check_views(views, S)) != GS_OK) return s;
     if ((s = check_params(params)) != GS_OK) return s;
+    setup_tiles(params, S);
+    if ((s = check_views(views, S)) != GS_OK) return s;
     if (objective != GS_OBJ_FULL && objective != GS_OBJ_FIXED && objective != GS_OBJ_TRUE)
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown objective %d", objective);
     if (objective != GS_OBJ_FULL && !weights)
@@ -936,7 +990,7 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
         const ChunkPlan &c = chunks[ci];
         if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, true, nullptr)) != GS_OK)
             return s;
-        CompositeArgs a = composite_args(r, c.total_tiles, params, 0.0f);
+        CompositeArgs a = composite_args(r, c.total_tiles, params, 0.0f, S.quad_log);
         ObjectiveArgs o{weights, objective, per_ray, r.tile_sums, nullptr, 1e-9f};
         if (r.quad_list) {
             // only the listed quadrants are rendered: the chunk's other rays read 0
@@ -957,11 +1011,11 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
             }
             o.wmax_bits = wmax;
         }
-        launch_fill_u64((uint64_t *)r.tile_sums, 0ull, 3 * 4 * (int64_t)c.total_tiles, st);
+        launch_fill_u64((uint64_t *)r.tile_sums, 0ull, 3 * ((int64_t)c.total_tiles << S.quad_log), st);
         launch_objective(a, o, r.b.counters, st);
         HIP_TRY(hipGetLastError());
         if (per_view) {
-            launch_view_sums(r.tile_sums, r.views_dev, c.vc, per_view + 3 * (int64_t)c.v0, st);
+            launch_view_sums(r.tile_sums, r.views_dev, c.vc, S.quad_log, per_view + 3 * (int64_t)c.v0, st);
             HIP_TRY(hipGetLastError());
         }
         if (diag) {
@@ -1429,7 +1483,7 @@ struct PlanGroup {
     int32_t *tile_view = nullptr, *tile_scene = nullptr;
     SceneSlot *slots = nullptr;
     uint32_t *work = nullptr;
-    uint32_t *ccount = nullptr;   // [4 total_tiles] entries pass 1 compacted per quadrant
+    uint32_t *ccount = nullptr;   // [total_tiles << quad_log] entries pass 1 compacted per quadrant
     std::vector<CompositeBatch> batches;
     int total_tiles = 0, total_views = 0;
     size_t bytes = 0, list_bytes = 0;
@@ -1447,6 +1501,7 @@ struct gs_plan {
     void *pool = nullptr;       // compacted quadrant lists, shared by the compacting launches
     size_t pool_bytes = 0;
     gs_plan_config cfg{0, 1};
+    int quad_log = 2 * kTileShiftDefault - 6;   // 8x8 quadrants per tile, log2
     hipStream_t cap = nullptr;  // stream the sequence is captured on (the null stream cannot capture)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1468,6 +1523,7 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     add(4 * sizeof(uint32_t) * (size_t)ps.c.vc);
     add(4 * sizeof(uint32_t) * (size_t)ps.c.vc * proj_blocks(N));
     add(sizeof(uint32_t) * ps.nbins);
+    add(sizeof(uint64_t) * (size_t)rowbits_words(ps.c.vc, chunk_max_rows(ps.S, ps.c), ps.S.nchunks));
     add(sizeof(uint32_t) * ps.c.total_tiles);
     add(sizeof(uint64_t) * (ps.c.total_tiles + 1));
     add(sizeof(uint64_t) * scan_tmp_elems(ps.c.total_tiles + 1));
@@ -1494,6 +1550,8 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.kmin = b.nvis + 2 * ps.c.vc;
     b.proj_part = cv.take<uint32_t>(4 * (size_t)ps.c.vc * proj_blocks(N));
     b.bin_count = cv.take<uint32_t>(ps.nbins);
+    b.rows_stride = chunk_max_rows(ps.S, ps.c);
+    b.rowbits = cv.take<uint64_t>((size_t)rowbits_words(ps.c.vc, b.rows_stride, ps.S.nchunks));
     b.tile_tot = cv.take<uint32_t>(ps.c.total_tiles);
     b.tile_off = cv.take<uint64_t>(ps.c.total_tiles + 1);
     ps.scan_tmp = cv.take<uint64_t>(scan_tmp_elems(ps.c.total_tiles + 1));
@@ -1553,7 +1611,8 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
             a.share_floor = P->p.share_floor;
             a.work = P->cfg.persistent ? G.work : nullptr;
             a.xcd_remap = P->cfg.xcd_remap;
-            a.ccount = cb.compact ? G.ccount + 4 * (size_t)cb.t0 : nullptr;
+            a.quad_log = P->quad_log;
+            a.ccount = cb.compact ? G.ccount + ((size_t)cb.t0 << P->quad_log) : nullptr;
             a.report_floor = P->p.share_floor > 0.0f ? std::nextafter(P->p.share_floor, 0.0f) : 0.0f;
             launch_composite_pass1(a, st);
             launch_composite_pass2(a, false, nullptr, st);
@@ -1585,7 +1644,8 @@ void plan_free(gs_plan *P) {
 void plan_batches(gs_plan *P) {
     size_t pool_budget = scratch_budget() / 2;
     env_gib("GS_COMPACT_POOL_GB", &pool_budget);
-    auto region = [](const PlanScene &ps) { return (4 * ps.cap * sizeof(uint32_t) + 255) & ~(size_t)255; };
+    const int ql = P->quad_log;
+    auto region = [ql](const PlanScene &ps) { return ((ps.cap << ql) * sizeof(uint32_t) + 255) & ~(size_t)255; };
     std::vector<size_t> off(P->scenes.size(), 0);
     size_t pool = 0;
     for (PlanGroup &G : P->groups) {
@@ -1662,7 +1722,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
             G.total_tiles += ps.c.total_tiles;
         }
         const size_t table_bytes = sizeof(ViewDev) * G.total_views + 2 * sizeof(int32_t) * G.total_tiles +
-                                   4 * sizeof(uint32_t) * G.total_tiles + sizeof(SceneSlot) * G.scenes.size() +
+                                   (sizeof(uint32_t) << P->quad_log) * G.total_tiles + sizeof(SceneSlot) * G.scenes.size() +
                                    8192;
         if (dev_alloc(P->from, &G.buf, G.bytes + table_bytes + 65536, nullptr) != hipSuccess) {
             (void)hipGetLastError();
@@ -1675,7 +1735,7 @@ gs_status plan_allocate(gs_plan *P, hipStream_t st) {
         G.tile_scene = cv.take<int32_t>(G.total_tiles);
         G.slots = cv.take<SceneSlot>(G.scenes.size());
         G.work = cv.take<uint32_t>(64);
-        G.ccount = cv.take<uint32_t>(4 * (size_t)G.total_tiles);
+        G.ccount = cv.take<uint32_t>((size_t)G.total_tiles << P->quad_log);
         auto &gv = group_views[gi];
         auto &gtv = group_tv[gi];
         auto &gts = group_ts[gi];
@@ -1756,9 +1816,11 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
         P->from = g_allocator;
     }
     P->p = *params;
+    P->quad_log = tile_shift(params->tile_w) + tile_shift(params->tile_h) - 6;
     P->scenes.resize(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
         PlanScene &ps = P->scenes[i];
+        setup_tiles(params, ps.S);
         if ((s = check_scene(&scenes[i])) != GS_OK || (s = check_views(&views[i], ps.S)) != GS_OK) {
             delete P;
             return s;
@@ -1793,6 +1855,8 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
             V.H = views[i].size[2 * k + 1];
             V.tiles_x = ps.S.tiles_x[k];
             V.tiles_y = ps.S.tiles_y[k];
+            V.tsx = ps.S.tsx;
+            V.tsy = ps.S.tsy;
             V.ray_base = ps.S.ray_base[k];
             V.ray_local = ps.S.ray_base[k];
             V.tile_base = tb;
@@ -1915,6 +1979,57 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
         enqueue_plan(plan, st, sens);
         HIP_TRY(hipGetLastError());
     }
+    return GS_OK;
+}
+
+gs_status gs_tune_tile(const gs_scene *scene, const gs_views *views, const gs_params *params, int32_t reps,
+                       float *sens, int32_t *best_w, int32_t *best_h, float *ms, void *stream) {
+    g_last_error.clear();
+    if (!params || !sens || !best_w || !best_h) return fail(GS_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (reps < 1) return fail(GS_ERR_INVALID_ARGUMENT, "reps must be >= 1");
+    gs_status s;
+    if ((s = check_params(params)) != GS_OK) return s;
+    if (params->ambiguous_rays) return fail(GS_ERR_INVALID_ARGUMENT, "the tuner takes no ambiguous_rays");
+    {
+        Setup S;   // the views' own checks, at the widest shape
+        S.tsx = S.tsy = 5;
+        if ((s = check_views(views, S)) != GS_OK) return s;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(GS_ERR_DEVICE, "hipEventCreate failed");
+    }
+    const int sides[3] = {8, 16, 32};
+    float t[9];
+    int best = -1;
+    s = GS_OK;
+    for (int k = 0; k < 9 && s == GS_OK; ++k) {
+        t[k] = -1.0f;
+        gs_params p = *params;
+        p.tile_w = sides[k / 3];
+        p.tile_h = sides[k % 3];
+        if (p.aggregate == GS_AGG_TILE && (p.tile_w != 16 || p.tile_h != 16)) continue;
+        if (!tiles_fit(views, tile_shift(p.tile_w), tile_shift(p.tile_h))) continue;
+        if ((s = gs_sensitivity(scene, views, &p, sens, nullptr, stream)) != GS_OK) break;   // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) s = fail(GS_ERR_DEVICE, "hipEventRecord failed");
+        for (int r = 0; r < reps && s == GS_OK; ++r) s = gs_sensitivity(scene, views, &p, sens, nullptr, stream);
+        if (s == GS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t[k], e0, e1) != hipSuccess))
+            s = fail(GS_ERR_DEVICE, "timing the sensitivity pass failed");
+        t[k] /= (float)reps;
+        if (s == GS_OK && (best < 0 || t[k] < t[best])) best = k;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != GS_OK) return s;
+    if (best < 0) return fail(GS_ERR_UNSUPPORTED, "no tile shape fits these views");
+    *best_w = sides[best / 3];
+    *best_h = sides[best % 3];
+    if (ms)
+        for (int k = 0; k < 9; ++k) ms[k] = t[k];
     return GS_OK;
 }
 

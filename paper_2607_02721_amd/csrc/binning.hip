@@ -52,11 +52,12 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t group) {
     return ((slot / group) * 8 + xcd) * group + slot % group;
 }
 
-// Quadrants of tile (tx, ty) met by the pixel rectangle [xl, xh] x [yl, yh],
-// which meets the tile: it meets the left (top) half iff it starts before
-// the middle, and the right (bottom) half iff it ends after it.
-__device__ __forceinline__ uint32_t quad_mask(int tx, int ty, int xl, int xh, int yl, int yh) {
-    const int mx = tx * kTile + kQuad, my = ty * kTile + kQuad;
+// Sub-rectangles (halves in x and y) of tile (tx, ty) met by the pixel
+// rectangle [xl, xh] x [yl, yh], which meets the tile: it meets the left
+// (top) half iff it starts before the middle, and the right (bottom) half
+// iff it ends after it.
+__device__ __forceinline__ uint32_t quad_mask(int tx, int ty, int xl, int xh, int yl, int yh, int tsx, int tsy) {
+    const int mx = (tx << tsx) + (1 << (tsx - 1)), my = (ty << tsy) + (1 << (tsy - 1));
     const uint32_t l = xl < mx ? 1u : 0u, r = xh >= mx ? 2u : 0u;
     const uint32_t top = yl < my ? (l | r) : 0u, bottom = yh >= my ? (l | r) << 2 : 0u;
     return top | bottom;
@@ -68,7 +69,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
                                                            const uint32_t *__restrict__ xr_in,
                                                            const uint32_t *__restrict__ yr_in,
                                                            uint32_t *__restrict__ bin_count,
-                                                           const uint8_t *__restrict__ active) {
+                                                           const uint16_t *__restrict__ active,
+                                                           uint64_t *__restrict__ rowbits, int rows_stride) {
     // A position adds 1 to every tile of its tile rectangle: +1 / -1 at the
     // rectangle's corners of a 2D difference array, whose prefix sums along
     // x and then y are the counts (four LDS atomics per position, whatever
@@ -87,15 +89,53 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
     const int stride = tx_n + 1, cells = stride * (ty_n + 1);
     for (int i = threadIdx.x; i < cells; i += kBinThreads) dif[i] = 0;
     __syncthreads();
-    for (int64_t p = lo + threadIdx.x; p < hi; p += kBinThreads) {
-        int xl, xh, yl, yh;
-        unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
-        unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
-        const int x0 = xl >> 4, x1 = (xh >> 4) + 1, y0 = (yl >> 4) * stride, y1 = ((yh >> 4) + 1) * stride;
-        atomicAdd(&dif[y0 + x0], 1);
-        atomicAdd(&dif[y0 + x1], -1);
-        atomicAdd(&dif[y1 + x0], -1);
-        atomicAdd(&dif[y1 + x1], 1);
+    // the view's row bitmaps for this chunk: word w of row r at
+    // rb + r * row_pitch + w
+    constexpr int kWords = kBinPositions / 64;
+    const int64_t row_pitch = (int64_t)nchunks * kWords;
+    uint64_t *rb = rowbits + (int64_t)v * rows_stride * row_pitch + (int64_t)chunk * kWords;
+    // every lane of a wave runs each step (positions past the chunk's end
+    // are invalid), so the row words gathered into the lanes can be stored
+    // by the whole wave
+    const int lane = threadIdx.x & 63;
+    for (int64_t p0 = lo + (threadIdx.x & ~63); p0 < hi; p0 += kBinThreads) {
+        const int64_t p = p0 + lane;
+        const bool valid = p < hi;
+        int ty0 = 1, ty1 = 0;   // an empty row range for invalid positions
+        if (valid) {
+            int xl, xh, yl, yh;
+            unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
+            unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
+            const int x0 = xl >> V.tsx, x1 = (xh >> V.tsx) + 1;
+            ty0 = yl >> V.tsy;
+            ty1 = yh >> V.tsy;
+            const int y0 = ty0 * stride, y1 = (ty1 + 1) * stride;
+            atomicAdd(&dif[y0 + x0], 1);
+            atomicAdd(&dif[y0 + x1], -1);
+            atomicAdd(&dif[y1 + x0], -1);
+            atomicAdd(&dif[y1 + x1], 1);
+        }
+        // the wave's 64 positions form one bitmap word per tile row: one
+        // ballot per row, its two halves kept by lane r (rows 64..127 in a
+        // second pair), then one store per pair by the lanes that own a row
+        const int w = (int)((p0 - lo) >> 6);
+        uint32_t lo0 = 0u, hi0 = 0u, lo1 = 0u, hi1 = 0u;
+        for (int r = 0; r < ty_n; ++r) {
+            const uint64_t bits = __ballot(valid && (unsigned)(r - ty0) <= (unsigned)(ty1 - ty0));
+            if (r < 64) {
+                const bool mine = lane == r;
+                lo0 = mine ? (uint32_t)bits : lo0;
+                hi0 = mine ? (uint32_t)(bits >> 32) : hi0;
+            } else if (r < 128) {
+                const bool mine = lane == r - 64;
+                lo1 = mine ? (uint32_t)bits : lo1;
+                hi1 = mine ? (uint32_t)(bits >> 32) : hi1;
+            } else if (lane == 0) {
+                rb[(int64_t)r * row_pitch + w] = bits;   // views taller than 128 tile rows
+            }
+        }
+        if (lane < ty_n) rb[(int64_t)lane * row_pitch + w] = (uint64_t)lo0 | ((uint64_t)hi0 << 32);
+        if (lane + 64 < ty_n) rb[(int64_t)(lane + 64) * row_pitch + w] = (uint64_t)lo1 | ((uint64_t)hi1 << 32);
     }
     __syncthreads();
     for (int ty = threadIdx.x; ty < ty_n; ty += kBinThreads) {       // along x, one row per thread
@@ -298,8 +338,9 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                                                         const uint32_t *__restrict__ bin_count,
                                                         const uint64_t *__restrict__ tile_off,
                                                         uint32_t *__restrict__ lists,
-                                                        const uint8_t *__restrict__ active, uint64_t cap,
-                                                        int group_tiles) {
+                                                        const uint16_t *__restrict__ active, uint64_t cap,
+                                                        int group_tiles, const uint64_t *__restrict__ rowbits,
+                                                        int rows_stride) {
     extern __shared__ uint32_t lds[];
     const EmitLds L = emit_lds(lds, group_tiles);
     // logical block: group + groups * (chunk + nchunks * view), with group =
@@ -313,6 +354,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
     const int chunk = (int)((lb - (int64_t)v * per_view) / groups);
     const int lane = threadIdx.x;
     const ViewDev &V = views[v];
+    const int sx = V.tsx, sy = V.tsy;
     const int64_t nv = nvis[v];
     const int64_t lo = (int64_t)chunk * kBinPositions;
     const int r0 = (grp % row_groups) * kEmitRows, c0 = (grp / row_groups) * kEmitCols;
@@ -344,7 +386,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             L.act[w] = bits;
         }
     }
-    __syncthreads();
+    wave_sync();
     // masked form: the wave's active tiles as a 128-bit set (one tile row);
     // a wave with none has nothing to emit
     static_assert(!kMasked || (kEmitRows == 1 && kEmitCols <= 128), "one row of at most 128 tiles");
@@ -359,29 +401,29 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
     const uint64_t room = cap > vlist ? cap - vlist : 0ull;
     uint32_t *__restrict__ vl = lists + vlist;
     const int64_t o = (int64_t)v * N + lo;
+    // this wave's row bitmap in the chunk (one word per 64 positions)
+    static_assert(kEmitRows == 1, "the row bitmaps select one tile row");
+    constexpr int kWords = kBinPositions / 64;
+    const uint64_t *rbits =
+        rowbits + ((int64_t)v * rows_stride + r0) * ((int64_t)nchunks * kWords) + (int64_t)chunk * kWords;
     for (int b0 = 0; b0 < hi; b0 += kEmitBatch) {
         const int b1 = min(b0 + kEmitBatch, hi);
-        // 1. positions of the batch whose rows meet [r0, r1), in order (all
-        // of the batch's row ranges are loaded first, so their latencies overlap)
-        constexpr int kGroups = kEmitBatch / kEmitWave;
-        uint32_t yv[kGroups];
-#pragma unroll
-        for (int q = 0; q < kGroups; ++q) {
-            const int p = b0 + q * kEmitWave + lane;
-            yv[q] = p < b1 ? yr_in[o + p] : 0u;
+        // 1. positions of the batch that meet row r0, in order: lane l < 16
+        // takes the bitmap word of positions b0 + 64 l ... + 63 (bits past the
+        // chunk's visible positions are clear), a wave prefix sum of the
+        // popcounts places each lane's positions in the queue
+        const int nw = (b1 - b0 + 63) >> 6;
+        uint64_t word = lane < nw ? rbits[(b0 >> 6) + lane] : 0ull;
+        const int cnt = __popcll(word);
+        const int incl = wave_scan_add(cnt);
+        const int nq = __builtin_amdgcn_readlane(incl, kEmitWave - 1);
+        int slot = incl - cnt;
+        while (word) {
+            const int bit = __ffsll((long long)word) - 1;
+            L.queue[slot++] = (uint16_t)(b0 + 64 * lane + bit);
+            word &= word - 1ull;
         }
-        int nq = 0;
-#pragma unroll
-        for (int q = 0; q < kGroups; ++q) {
-            const int p = b0 + q * kEmitWave + lane;
-            int yl, yh;
-            unpack_range(__uint_as_float(yv[q]), yl, yh);
-            const bool meets = (p < b1) & ((yl >> 4) < r1) & ((yh >> 4) >= r0);
-            const uint64_t bal = __ballot(meets);
-            if (meets) L.queue[nq + __popcll(bal & lanemask_lt64_bin())] = (uint16_t)p;
-            nq += __popcll(bal);
-        }
-        __syncthreads();
+        wave_sync();
         // 2. expansion of the queued positions against this wave's tiles; the
         // next round's ranges and indices are loaded while this one expands
         uint32_t nx_ = 0, ny_ = 0, ng_ = 0;
@@ -407,10 +449,10 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                 unpack_range(__uint_as_float(uy), yl, yh);
                 // the tiles of its rectangle inside this wave's rows and columns
                 // (masked form: none unless one of them is active)
-                const int kx = min(xh >> 4, c1 - 1) - max(xl >> 4, c0) + 1;
-                k = kx > 0 ? kx * (min(yh >> 4, r1 - 1) - max(yl >> 4, r0) + 1) : 0;
+                const int kx = min(xh >> sx, c1 - 1) - max(xl >> sx, c0) + 1;
+                k = kx > 0 ? kx * (min(yh >> sy, r1 - 1) - max(yl >> sy, r0) + 1) : 0;
                 if (kMasked && k > 0 &&
-                    !range_hits(act_lo, act_hi, max(xl >> 4, c0) - c0, min(xh >> 4, c1 - 1) - c0))
+                    !range_hits(act_lo, act_hi, max(xl >> sx, c0) - c0, min(xh >> sx, c1 - 1) - c0))
                     k = 0;
             }
             const int incl = wave_scan_add(k);
@@ -419,7 +461,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             L.rx[lane] = ux;
             L.ry[lane] = uy;
             L.rg[lane] = ug;
-            __syncthreads();
+            wave_sync();
             for (int i0 = 0; i0 < K; i0 += kEmitWave) {
                 const int i = i0 + lane;
                 const bool item = i < K;
@@ -431,15 +473,15 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                 const int carry = 63 - __builtin_clzll(started);
                 L.head[lane] = -1;
                 if (k > 0 && excl > i0 && excl < i0 + kEmitWave) L.head[excl - i0] = lane;
-                __syncthreads();
+                wave_sync();
                 const int own = max(carry, wave_scan_max(L.head[lane]));
                 const int j = i - __shfl(excl, own);
                 int xl, xh, yl, yh;
                 unpack_range(__uint_as_float(L.rx[own]), xl, xh);
                 unpack_range(__uint_as_float(L.ry[own]), yl, yh);
                 const uint32_t g = L.rg[own];
-                const int tx0 = max(xl >> 4, c0), ty0 = max(yl >> 4, r0);
-                const int nx = min(xh >> 4, c1 - 1) - tx0 + 1;
+                const int tx0 = max(xl >> sx, c0), ty0 = max(yl >> sy, r0);
+                const int nx = min(xh >> sx, c1 - 1) - tx0 + 1;
                 // j / nx as floor((j + 1/2) r) with r within one ulp of 1/nx:
                 // exact for nx * ny <= 8160 (checked exhaustively on the host)
                 const int dy = kEmitRows == 1 ? 0 : (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
@@ -448,16 +490,16 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                 const bool in = item && (unsigned)tc < (unsigned)ntiles;
                 const int t = in ? tc : 0;
                 const bool on = in && tile_on<kMasked>(L.act, t);
-                const uint32_t val = g | (quad_mask(tx, ty, xl, xh, yl, yh) << 28);
+                const uint32_t val = g | (quad_mask(tx, ty, xl, xh, yl, yh, sx, sy) << 28);
                 // Lanes on the same tile: each lane ORs its bit into its tile's
                 // 64-bit LDS mask (cleared just before), then reads it back.
                 // A lane's rank among them (lanes are in position order) is its
                 // offset in the tile's run of entries; the lowest lane takes the
                 // run from the tile's cursor.
                 if (on) L.lanes[t] = 0ull;
-                __syncthreads();
+                wave_sync();
                 if (on) atomicOr((unsigned long long *)&L.lanes[t], 1ull << lane);
-                __syncthreads();
+                wave_sync();
                 const uint64_t same = on ? L.lanes[t] : 0ull;
                 const int rank = __popcll(same & lanemask_lt64_bin());
                 uint32_t base = 0;
@@ -481,15 +523,15 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                             L.ft[r] = (uint32_t)t;
                             L.fc[r] = c;
                         }
-                        __syncthreads();
+                        wave_sync();
                         store_lines(L, __popcll(need), align, vl, room);
-                        __syncthreads();
+                        wave_sync();
                     }
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
-        __syncthreads();   // the queue is refilled by the next batch
+        wave_sync();   // the queue is refilled by the next batch
     }
     // 3. the last, partly filled line of every tile whose segment ends inside one
     for (int t4 = 0; t4 < ntiles; t4 += kEmitWave) {
@@ -506,7 +548,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
             L.ft[r] = (uint32_t)t;
             L.fc[r] = c - 1u;       // the last entry; slots after it are not stored
         }
-        __syncthreads();
+        wave_sync();
         const int n = __popcll(need);
         for (int f0 = 0; f0 < n; f0 += kEmitWave / kLine) {
             const int f = f0 + lane / kLine, k = lane % kLine;
@@ -518,7 +560,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                     vl[e] = L.line[tt * kLine + k];
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -527,7 +569,8 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
     const int64_t run = 8 * kCountGroup;
     const int64_t blocks = ((int64_t)nchunks * Vc + run - 1) / run * run;
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)blocks), dim3(kBinThreads), (size_t)max_cells * sizeof(int32_t),
-                       st, views_dev, Vc, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active);
+                       st, views_dev, Vc, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active, b.rowbits,
+                       b.rows_stride);
 }
 
 void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const ChunkBufs &b, int max_tiles,
@@ -550,12 +593,12 @@ void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, c
         hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
                            col_groups,
                            b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
-                           group_tiles);
+                           group_tiles, b.rowbits, b.rows_stride);
     else
         hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
                            col_groups,
                            b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
-                           group_tiles);
+                           group_tiles, b.rowbits, b.rows_stride);
 }
 
 // Capacity guard for lists sized in advance (plans): if the counted entries
@@ -597,41 +640,41 @@ void launch_list_guard(uint64_t *tile_off, int64_t ntiles, uint64_t cap, uint32_
 
 // A tile is active when at least one of its rays is selected by the ray mask;
 // inactive tiles get empty lists.  active[t] holds one bit per 8x8 quadrant
-// (bit q: quadrant q = (x >= 8) + 2 (y >= 8) holds a selected ray).  One wave
-// per tile, 4 rays per lane.
+// (bit q: quadrant q, row-major inside the tile, holds a selected ray).  One
+// wave per tile: lane L takes the pixels L, L + 64, ... of the tile (row-major),
+// and the bits are OR-ed over the wave with a ballot per quadrant.
 __global__ __launch_bounds__(64) void k_tile_active(const ViewDev *__restrict__ views,
                                                     const int32_t *__restrict__ tile_view,
-                                                    const uint32_t *__restrict__ mask, uint8_t *__restrict__ active) {
+                                                    const uint32_t *__restrict__ mask, uint16_t *__restrict__ active) {
     const int gt = blockIdx.x;
     const ViewDev &V = views[tile_view[gt]];
     const int tl = gt - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
-    // lane L covers row L / 4 of the tile, columns 4 (L % 4) .. 4 (L % 4) + 3,
-    // all inside one quadrant
-    const int rx = (threadIdx.x & 3) * 4, ry = threadIdx.x >> 2;
-    bool any = false;
-    for (int k = 0; k < 4; ++k) {
-        const int px = tx * kTile + rx + k, py = ty * kTile + ry;
+    const int tw = 1 << V.tsx, area = tw << V.tsy, qlx = V.tsx - 3;
+    uint32_t mine = 0u;    // quadrants of this lane's pixels that hold a selected ray
+    for (int k = threadIdx.x; k < area; k += 64) {
+        const int lx = k & (tw - 1), ly = k >> V.tsx;
+        const int px = (tx << V.tsx) + lx, py = (ty << V.tsy) + ly;
         if (px < V.W && py < V.H) {
             const int64_t ray = V.ray_base + (int64_t)py * V.W + px;
-            any = any || ((mask[ray >> 5] >> (ray & 31)) & 1u);
+            if ((mask[ray >> 5] >> (ray & 31)) & 1u) mine |= 1u << ((lx >> 3) + ((ly >> 3) << qlx));
         }
     }
-    const int q = (rx >= kQuad ? 1 : 0) + (ry >= kQuad ? 2 : 0);
-    const uint8_t bits = (uint8_t)((__any(any && q == 0) ? 1 : 0) | (__any(any && q == 1) ? 2 : 0) |
-                                   (__any(any && q == 2) ? 4 : 0) | (__any(any && q == 3) ? 8 : 0));
-    if (threadIdx.x == 0) active[gt] = bits;
+    const int nq = 1 << (V.tsx + V.tsy - 6);
+    uint32_t bits = 0u;
+    for (int q = 0; q < nq; ++q) bits |= __any((mine >> q) & 1u) ? (1u << q) : 0u;
+    if (threadIdx.x == 0) active[gt] = (uint16_t)bits;
 }
 
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
-                        uint8_t *active, hipStream_t st) {
+                        uint16_t *active, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_active, dim3(total_tiles), dim3(64), 0, st, views_dev, tile_view, mask, active);
 }
 
 // Row y + 1 of view v's table: running counts of active tiles along tile row
 // y; row 0 is all zeros (written by the thread of row 0).
 __global__ __launch_bounds__(64) void k_tile_sat_rows(const ViewDev *__restrict__ views,
-                                                      const uint8_t *__restrict__ active, uint32_t *__restrict__ sat) {
+                                                      const uint16_t *__restrict__ active, uint32_t *__restrict__ sat) {
     const ViewDev &V = views[blockIdx.y];
     const int ty = blockIdx.x * 64 + threadIdx.x;
     if (ty >= V.tiles_y) return;
@@ -640,7 +683,7 @@ __global__ __launch_bounds__(64) void k_tile_sat_rows(const ViewDev *__restrict_
     if (ty == 0)
         for (int x = 0; x < stride; ++x) S[x] = 0u;
     uint32_t *row = S + (int64_t)(ty + 1) * stride;
-    const uint8_t *a = active + V.tile_base + (int64_t)ty * V.tiles_x;
+    const uint16_t *a = active + V.tile_base + (int64_t)ty * V.tiles_x;
     uint32_t run = 0;
     row[0] = 0u;
     for (int x = 0; x < V.tiles_x; ++x) {
@@ -663,31 +706,31 @@ __global__ __launch_bounds__(64) void k_tile_sat_cols(const ViewDev *__restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void k_quad_count(const uint8_t *__restrict__ active, int n,
+__global__ __launch_bounds__(256) void k_quad_count(const uint16_t *__restrict__ active, int n,
                                                     uint32_t *__restrict__ qcnt) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t < n) qcnt[t] = (uint32_t)__popc((unsigned)active[t]);
 }
 
-__global__ __launch_bounds__(256) void k_quad_write(const uint8_t *__restrict__ active, int n,
+__global__ __launch_bounds__(256) void k_quad_write(const uint16_t *__restrict__ active, int n, int quad_log,
                                                     const uint64_t *__restrict__ qoff, uint32_t *__restrict__ qlist) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= n) return;
     const unsigned bits = active[t];
     uint64_t o = qoff[t];
-    for (int q = 0; q < 4; ++q)
-        if ((bits >> q) & 1u) qlist[o++] = (uint32_t)(4 * t + q);
+    for (int q = 0; q < (1 << quad_log); ++q)
+        if ((bits >> q) & 1u) qlist[o++] = (uint32_t)(((uint32_t)t << quad_log) + q);
 }
 
-void launch_quad_list(const uint8_t *active, int total_tiles, uint32_t *qcnt, uint64_t *qoff, uint64_t *scan_tmp,
-                      uint32_t *qlist, hipStream_t st) {
+void launch_quad_list(const uint16_t *active, int total_tiles, int quad_log, uint32_t *qcnt, uint64_t *qoff,
+                      uint64_t *scan_tmp, uint32_t *qlist, hipStream_t st) {
     const unsigned blocks = (unsigned)((total_tiles + 255) / 256);
     hipLaunchKernelGGL(k_quad_count, dim3(blocks), dim3(256), 0, st, active, total_tiles, qcnt);
     scan_u32_to_u64_exclusive(qcnt, qoff, total_tiles, scan_tmp, st);
-    hipLaunchKernelGGL(k_quad_write, dim3(blocks), dim3(256), 0, st, active, total_tiles, qoff, qlist);
+    hipLaunchKernelGGL(k_quad_write, dim3(blocks), dim3(256), 0, st, active, total_tiles, quad_log, qoff, qlist);
 }
 
-void launch_tile_sat(const ViewDev *views_dev, int Vc, int max_tx, int max_ty, const uint8_t *active, uint32_t *sat,
+void launch_tile_sat(const ViewDev *views_dev, int Vc, int max_tx, int max_ty, const uint16_t *active, uint32_t *sat,
                      hipStream_t st) {
     hipLaunchKernelGGL(k_tile_sat_rows, dim3((unsigned)((max_ty + 63) / 64), (unsigned)Vc), dim3(64), 0, st,
                        views_dev, active, sat);

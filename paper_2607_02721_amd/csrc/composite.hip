@@ -66,19 +66,20 @@ struct WaveSetup {
     float sfloor;           // staged sensitivities are raised to this (pass 2)
 };
 
-__device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles * 4; }
+__device__ __forceinline__ int quad_count(const CompositeArgs &a) { return a.total_tiles << a.quad_log; }
 
 // Quadrant `logical` of the launch -> this wave's pixels, list range and scene.
 __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, WaveSetup &w) {
-    w.gt = a.tile_first + (logical >> 2);
-    w.quad = logical & 3;
+    w.gt = a.tile_first + (logical >> a.quad_log);
+    w.quad = logical & ((1 << a.quad_log) - 1);
     w.v = a.tile_view[w.gt];
     const SceneSlot &S = a.slots[a.tile_scene[w.gt]];
     const ViewDev &V = a.views[w.v];
     const int tl = w.gt - S.tile0 - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
-    const int qx0 = tx * kTile + (w.quad & 1) * kQuad;
-    const int qy0 = ty * kTile + (w.quad >> 1) * kQuad;
+    const int qlx = V.tsx - 3;
+    const int qx0 = (tx << V.tsx) + (w.quad & ((1 << qlx) - 1)) * kQuad;
+    const int qy0 = (ty << V.tsy) + (w.quad >> qlx) * kQuad;
     if (qx0 >= V.W || qy0 >= V.H) return false;
     const int lane = threadIdx.x;
     w.px = qx0 + (lane & 7);
@@ -93,7 +94,7 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.ray_global = V.ray_base + (int64_t)w.py * V.W + w.px;
     w.start = S.tile_off[w.gt - S.tile0];
     w.end = S.tile_off[w.gt - S.tile0 + 1];
-    w.qbit = 1u << (28 + w.quad);
+    w.qbit = quad_subrect_bits(w.quad, V.tsx, V.tsy) << 28;
     w.vbase = (int64_t)(w.v - S.view0) * S.N;
     w.R0 = S.R0;
     w.R1 = S.R1;
@@ -106,7 +107,7 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.R3 = S.R3;
     w.ray_stride = S.ray_stride;
     w.clist = S.clist;
-    w.cbase = 4 * w.start + (uint64_t)w.quad * (w.end - w.start) - a.clist_shift;
+    w.cbase = (w.start << a.quad_log) + (uint64_t)w.quad * (w.end - w.start) - a.clist_shift;
     w.sfloor = a.report_floor;
     return true;
 }
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
             const int n = stage_slice<0, 1, kCh, !kCh>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr, cblue,
                                                  cl ? cl + ccnt : nullptr);
             ccnt += (uint32_t)n;
-            __syncthreads();
+            wave_sync();
             for (int j = 0; j < n; ++j) {
                 const float4 G = geo[j], Cc = col[j];
                 bool in_fp;
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
             if (kMode == kModeL1) done = done || (T * cmax < a.share_floor * A);
             if (kMode == kModeL2) done = done || ((T * T) * cmax < a.share_floor * A);
             if (kCh) done = done || (T * cmax < a.share_floor * fminf(A, fminf(AG, AB)));
-            __syncthreads();
+            wave_sync();
         }
         if (w.inside) {
             w.ray_A[w.ray_local] = scored ? A : 0.0f;
@@ -555,7 +556,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
             else
                 n = stage_slice<kAgg == 0 ? 1 : 3, kBlock, kCh, !kCh>(w, e0, a.r2_log2, geo, col, sid, sold,
                                                                       nullptr, cblue);
-            __syncthreads();
+            wave_sync();
             for (int jb = 0; jb < n; jb += 16) {
                 float sh[16];
 #pragma unroll
@@ -624,7 +625,7 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
             }
             const float later = kMode == kModeL2 ? (T * T) * cmax : T * cmax;
             done = done || (later < live_bar);
-            __syncthreads();
+            wave_sync();
         }
         if (kStats) {
             pin += positive ? n_in : 0u;
@@ -672,7 +673,7 @@ static unsigned resident_waves(K kernel) {
 
 static inline unsigned flat_grid(const CompositeArgs &a) {
     if (a.quad_list) return (unsigned)std::max(a.n_listed, 1);
-    return (unsigned)(((a.total_tiles * 4) + 7) & ~7);
+    return (unsigned)(((a.total_tiles << a.quad_log) + 7) & ~7);
 }
 
 template <int kMode>
@@ -775,7 +776,7 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
     return x;
 }
 
-// One wave per tile: lane l sums column l % 16 of rows l / 16, +4, +8, +12.
+// One wave per tile: lane l sums the tile's pixels l, l + 64, ... (row-major).
 __global__ __launch_bounds__(kWave) void k_tile_A(CompositeArgs a, double *__restrict__ tile_A) {
     const int t = blockIdx.x;
     const int v = a.tile_view[t];
@@ -784,11 +785,10 @@ __global__ __launch_bounds__(kWave) void k_tile_A(CompositeArgs a, double *__res
     const int tl = t - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
     const int lane = threadIdx.x;
-    const int px = tx * kTile + (lane & 15);
+    const int tw = 1 << V.tsx, area = tw << V.tsy;
     double sum = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int py = ty * kTile + (lane >> 4) + 4 * k;
+    for (int k = lane; k < area; k += kWave) {
+        const int px = (tx << V.tsx) + (k & (tw - 1)), py = (ty << V.tsy) + (k >> V.tsx);
         if (px < V.W && py < V.H) sum += (double)S.ray_A[V.ray_local + (int64_t)py * V.W + px];
     }
     sum = wave_sum_f64(sum);
@@ -928,7 +928,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
         if (__all(done)) break;
         const int n = has_w ? stage_slice<2>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, o.weights)
                             : stage_slice<0>(w, e0, a.r2_log2, geo, col, nullptr, nullptr, nullptr);
-        __syncthreads();
+        wave_sync();
         for (int j = 0; j < n; ++j) {
             const float4 G = geo[j], Cc = col[j];
             bool in_fp;
@@ -962,7 +962,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
             T = fmaf(-rho, T, T);
         }
         if (o.wmax_bits) done = done || ((kMode == kModeL2 ? T * T : T) * stop_scale < o.stop_rel * A);
-        __syncthreads();
+        wave_sync();
     }
     const bool on = scored && A > 0.0f;
     if (w.inside && o.per_ray) {
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(kWave) void k_objective(CompositeArgs a, ObjectiveA
         nb += __shfl_xor(nb, off);
     }
     if (threadIdx.x == 0) {
-        const int64_t slot = ((int64_t)w.gt * 4 + w.quad) * 3;
+        const int64_t slot = (((int64_t)w.gt << a.quad_log) + w.quad) * 3;
         o.tile_sums[slot + 0] = s0;
         o.tile_sums[slot + 1] = s1;
         o.tile_sums[slot + 2] = s2;
@@ -1024,12 +1024,12 @@ void launch_max_f64(const double *x, int64_t n, uint64_t *out_bits, hipStream_t 
 // sums a fixed strided subset, then a fixed tree; the order never depends on
 // scheduling.
 __global__ __launch_bounds__(256) void k_view_sums(const double *__restrict__ tile_sums,
-                                                   const ViewDev *__restrict__ views, int Vc,
+                                                   const ViewDev *__restrict__ views, int Vc, int quad_log,
                                                    double *__restrict__ out) {
     __shared__ double sh[3][256];
     const int v = blockIdx.x;
     const ViewDev &V = views[v];
-    const int64_t lo = (int64_t)V.tile_base * 4, hi = lo + (int64_t)V.tiles_x * V.tiles_y * 4;
+    const int64_t lo = (int64_t)V.tile_base << quad_log, hi = lo + ((int64_t)V.tiles_x * V.tiles_y << quad_log);
     double s0 = 0, s1 = 0, s2 = 0;
     for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
         s0 += tile_sums[3 * k];
@@ -1048,9 +1048,9 @@ __global__ __launch_bounds__(256) void k_view_sums(const double *__restrict__ ti
     if (threadIdx.x < 3) out[3 * v + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
+void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, int quad_log, double *per_view_out,
                       hipStream_t st) {
-    hipLaunchKernelGGL(k_view_sums, dim3(Vc), dim3(256), 0, st, tile_sums, views_dev, Vc, per_view_out);
+    hipLaunchKernelGGL(k_view_sums, dim3(Vc), dim3(256), 0, st, tile_sums, views_dev, Vc, quad_log, per_view_out);
 }
 
 // Coreset-objective error of per-image objectives: out[0] = max over views

@@ -7,7 +7,9 @@
 
 namespace gs {
 
-constexpr int kTile = 16;          // binning tile edge (pixels)
+// Binning tiles are 2^tsx x 2^tsy pixels with tsx, tsy in {3, 4, 5} (8, 16
+// or 32); 16 x 16 unless the caller or the tuner picks another shape.
+constexpr int kTileShiftDefault = 4;
 constexpr int kQuad = 8;           // compositing quadrant edge: one wave per 8x8 quadrant
 constexpr int kChunkBits = 14;     // depth ranks are binned in chunks of 2^14 (one list segment per tile)
 constexpr int kMaxTilesPerView = 8160;  // two u32 LDS arrays of this size fit 64 KiB
@@ -33,7 +35,22 @@ struct ViewDev {
     int64_t ray_local;  // index of the view's first ray inside this chunk's ray buffers
     int32_t tile_base;  // first tile of this view inside the chunk
     int32_t sat_base;   // first entry of this view's active-tile table (ray-masked runs)
+    int32_t tsx, tsy;   // tile width 2^tsx, height 2^tsy pixels
 };
+
+// A tile of 2^tsx x 2^tsy pixels holds 2^(tsx-3) x 2^(tsy-3) quadrants of
+// 8 x 8.  A list entry carries 4 bits (<< 28): the 2 x 2 sub-rectangles of
+// the tile (halves in x and y) that the Gaussian's pixel range meets.  The
+// bits of quadrant q (row-major inside the tile) are the sub-rectangles it
+// overlaps: one for tiles of 16 or 32 pixels per side, both halves along a
+// side of 8 pixels.
+__host__ __device__ inline uint32_t quad_subrect_bits(int q, int tsx, int tsy) {
+    const int qlx = tsx - 3, qly = tsy - 3;
+    const int qx = q & ((1 << qlx) - 1), qy = q >> qlx;
+    const uint32_t xm = qlx == 0 ? 3u : (qx >= (1 << (qlx - 1)) ? 2u : 1u);
+    const uint32_t ym = qly == 0 ? 3u : (qy >= (1 << (qly - 1)) ? 2u : 1u);
+    return ((ym & 1u) ? xm : 0u) | ((ym & 2u) ? xm << 2 : 0u);
+}
 
 struct SceneDev {
     int64_t n;
@@ -63,11 +80,16 @@ struct ChunkBufs {
     // tile_base(v) * nchunks, then [chunk][tile of v]); turned in place into
     // each tile's exclusive prefix over chunks
     uint32_t *bin_count;
+    // Per (view, tile row, chunk): bit i of word w is set when depth position
+    // chunk * 2^14 + 64 w + i meets the tile row ([Vc][rows_stride][nchunks][256]
+    // u64, written by the counting kernel, read by the emission).
+    uint64_t *rowbits;
+    int32_t rows_stride; // largest tile-row count of the chunk's views
     uint32_t *tile_tot;  // [tiles in chunk] entries per tile
     uint64_t *tile_off;  // exclusive scan of tile_tot (+1 trailing total): the tile's list
     uint32_t *lists;     // [D] entries
     float *ray_A;        // [queries per ray][rays in chunk] pass-1 render
-    uint8_t *tile_active; // [tiles in chunk] bit q set: quadrant q of the tile holds a selected ray (null: all)
+    uint16_t *tile_active; // [tiles in chunk] bit q set: quadrant q of the tile holds a selected ray (null: all)
     // Ray-masked runs: per view, (tiles_y + 1) x (tiles_x + 1) counts, entry
     // (y, x) = active tiles with row < y and column < x, from sat_base on
     // (null: no ray mask).  Projection drops (view, Gaussian) pairs whose tile
@@ -96,6 +118,19 @@ constexpr float kAmbiguityBeta = 1e-5f;
 // Blocks of the projection launch (256 threads, one Gaussian per thread).
 inline int64_t proj_blocks(int64_t n) { return (n + 255) / 256; }
 
+// Ordering of LDS accesses inside a one-wave workgroup.  A wave's LDS
+// instructions execute and return in issue order, so a write by one lane is
+// seen by a later read of any lane of the same wave; what must not happen is
+// the compiler moving an access across the point.  This is a code-motion
+// barrier only: unlike __syncthreads() it does not wait for the wave's
+// outstanding LDS operations to drain.  Only for kernels launched with one
+// wave per workgroup.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- launchers (each enqueues on `st`) -------------------------------------
 void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp,
                     const ChunkBufs &b, hipStream_t st);
@@ -115,15 +150,20 @@ void launch_key_compact(const ChunkBufs &b, int Vc, int64_t N, uint32_t *kout, u
 void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
                             uint32_t *yr, hipStream_t st);
 void launch_tile_active(const ViewDev *views_dev, const int32_t *tile_view, int total_tiles, const uint32_t *mask,
-                        uint8_t *active, hipStream_t st);
+                        uint16_t *active, hipStream_t st);
 // The quadrants with a selected ray, in order: per-tile counts, their
-// exclusive scan (qoff[total_tiles] = the number listed) and the list.
-void launch_quad_list(const uint8_t *active, int total_tiles, uint32_t *qcnt, uint64_t *qoff, uint64_t *scan_tmp,
-                      uint32_t *qlist, hipStream_t st);
+// exclusive scan (qoff[total_tiles] = the number listed) and the list of
+// (tile << quad_log) + quadrant.
+void launch_quad_list(const uint16_t *active, int total_tiles, int quad_log, uint32_t *qcnt, uint64_t *qoff,
+                      uint64_t *scan_tmp, uint32_t *qlist, hipStream_t st);
 // tile_sat from tile_active (two passes: along each tile row, then down each
 // column).  max_tx / max_ty: the largest tile grid of the chunk's views.
-void launch_tile_sat(const ViewDev *views_dev, int Vc, int max_tx, int max_ty, const uint8_t *active, uint32_t *sat,
+void launch_tile_sat(const ViewDev *views_dev, int Vc, int max_tx, int max_ty, const uint16_t *active, uint32_t *sat,
                      hipStream_t st);
+// u64 words of the row bitmaps of Vc views with at most max_ty tile rows.
+inline int64_t rowbits_words(int Vc, int max_ty, int nchunks) {
+    return (int64_t)Vc * max_ty * nchunks * (kBinPositions / 64);
+}
 // max_cells: the largest (tiles_x + 1) (tiles_y + 1) of the views.
 void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                       const uint32_t *xr, const uint32_t *yr, int max_cells, hipStream_t st);
@@ -166,8 +206,8 @@ struct SceneSlot {
     int64_t ray_stride;           // per-channel queries: distance between the R, G and B planes of ray_A
     // Pass 1 leaves each quadrant's entries that pass its exact test here
     // (the Gaussian indices, in list order, up to where the quadrant's rays
-    // stopped): quadrant q of a tile with list [start, end) owns
-    // [4 start + q (end - start), 4 start + (q + 1)(end - start)).  Pass 2
+    // stopped): quadrant q of a tile with list [start, end) and Q = 2^quad_log
+    // quadrants owns [Q start + q (end - start), Q start + (q + 1)(end - start)).  Pass 2
     // walks these dense lists.  Null: no compaction (pass 2 filters the tile
     // lists again).  Both give the same sensitivities (pass 2 reports no
     // share below the share floor, and every pair before a ray's stop is
@@ -189,6 +229,7 @@ struct CompositeArgs {
     const SceneSlot *slots;
     int32_t total_tiles;         // tiles of this launch
     int32_t tile_first;          // launch tile t is tile tile_first + t of tile_view / tile_scene
+    int32_t quad_log;            // log2 of the 8x8 quadrants per tile (every view of the launch has the same shape)
     int32_t query_mode;
     float r2_log2;               // -0.5 log2(e) r^2  (cut on the exp2 argument)
     float share_floor;
@@ -197,10 +238,10 @@ struct CompositeArgs {
     int32_t agg;                 // query granularity (gs_aggregate) of pass 2
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
-    uint32_t *ccount;            // [4 total_tiles] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist)
+    uint32_t *ccount;            // [quadrants] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist)
     uint64_t clist_shift;        // subtracted from every compacted-list offset (launches over a tile range
                                  // whose compacted lists fill a pool from its start)
-    const uint32_t *quad_list;   // ray-masked runs: the quadrants (4 tile + quadrant) holding a selected ray,
+    const uint32_t *quad_list;   // ray-masked runs: the quadrants ((tile << quad_log) + q) holding a selected ray,
     int32_t n_listed;            // in order; only these are composited (null: every quadrant)
     float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
     uint32_t *amb_rays;          // pass 2 with counters: bit of every ray (ViewDev::ray_base numbering) with an
@@ -232,13 +273,13 @@ struct ObjectiveArgs {
     const double *weights;
     int objective;
     float *per_ray;             // global, nullable
-    double *tile_sums;          // [total_tiles*4][3] per-wave partial sums
+    double *tile_sums;          // [quadrants][3] per-wave partial sums
     const uint64_t *wmax_bits;  // largest weight (double bits); null = no early stop
     float stop_rel;             // stop a ray once T c_max w_max < stop_rel A
 };
 void launch_max_f64(const double *x, int64_t n, uint64_t *out_bits, hipStream_t st);
 void launch_objective(const CompositeArgs &a, const ObjectiveArgs &o, uint64_t *counters, hipStream_t st);
-void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, double *per_view_out,
+void launch_view_sums(const double *tile_sums, const ViewDev *views_dev, int Vc, int quad_log, double *per_view_out,
                       hipStream_t st);
 // out[0] = max over views with A > 0 of |A^th_w - A| / A, out[1] with A_w.
 void launch_coreset_error(const double *per_view, int n_views, double *out, hipStream_t st);

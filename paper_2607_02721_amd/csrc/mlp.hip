@@ -20,9 +20,12 @@ namespace gs {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (v_rcp_f32, 1 ulp)
+// instead of an IEEE division: the same form in training and inference.
+__device__ __forceinline__ float sigmoid_fast(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigmoid_fast(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid_fast(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -451,14 +454,17 @@ static void mlp_forward_rows(const float *P, const MlpBufs<T> &m, int64_t rows, 
 }
 
 // Fused inference: one block of 4 waves per 64 rows runs the whole network
-// with the activations in LDS (two row-major bf16 buffers with a padded row
-// stride, so the 16 rows a fragment load reads fall on different banks) and
-// the bf16 weights read straight from global memory (L2): wave w computes
-// output columns [64 w, 64 w + 64) of every layer for the block's 64 rows,
-// with the fragment layout and k order of k_gemm_nt, so every activation is
-// the bf16 value the unfused path stores.  The head sums bf16(SiLU(z3)) w4
-// over each wave's columns (DPP over the 16 lanes of a fragment row), then
-// over the waves.
+// with the activations in LDS and the bf16 weights read straight from global
+// memory (L2): wave w computes output columns [64 w, 64 w + 64) of every
+// layer for the block's 64 rows, with the fragment layout and k order of
+// k_gemm_nt, so every activation is the bf16 value the unfused path stores.
+// One row-major bf16 buffer (padded row stride, so the 16 rows a fragment
+// load reads fall on different banks) holds the input, then each layer's
+// output in place: a layer's products are finished in registers, the block
+// meets at a barrier, and only then are they written over its input.  The
+// 34 KiB of LDS per block leaves room for four blocks per CU.  The head sums
+// bf16(SiLU(z3)) w4 over each wave's columns (DPP over the 16 lanes of a
+// fragment row), then over the waves.
 constexpr int kFuseRows = 64;
 constexpr int kFusePitch = kMlpH + 8;   // bf16 per LDS row
 
@@ -510,11 +516,11 @@ __device__ __forceinline__ void fused_store(__bf16 (*Out)[kFusePitch], int w, in
             for (int r = 0; r < 4; ++r) Out[16 * i + 4 * g + r][64 * w + 16 * j + fr] = (__bf16)acc[i][j][r];
 }
 
-__global__ __launch_bounds__(256) void k_mlp_fused(const float *__restrict__ feat, const float *__restrict__ norm,
+__global__ __launch_bounds__(256, 3) void k_mlp_fused(const float *__restrict__ feat, const float *__restrict__ norm,
                                                    int64_t n, const __bf16 *__restrict__ W1,
                                                    const __bf16 *__restrict__ W2, const __bf16 *__restrict__ W3,
                                                    const float *__restrict__ P, float *__restrict__ y) {
-    __shared__ __attribute__((aligned(16))) __bf16 HA[kFuseRows][kFusePitch], HB[kFuseRows][kFusePitch];
+    __shared__ __attribute__((aligned(16))) __bf16 H[kFuseRows][kFusePitch];
     __shared__ float ypart[4][kFuseRows];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * kFuseRows;
@@ -523,17 +529,19 @@ __global__ __launch_bounds__(256) void k_mlp_fused(const float *__restrict__ fea
         const int r = i / kMlpIn, c = i % kMlpIn;
         const int64_t row = r0 + r;
         const float x = row < n ? (feat[row * kMlpIn + c] - norm[c]) * norm[kMlpIn + c] : 0.0f;
-        HA[r][c] = (__bf16)x;
+        H[r][c] = (__bf16)x;
     }
     __syncthreads();
     f32x4 acc[4][4];
-    fused_layer<kMlpIn>(HA, W1, P + kOffB1, w, lane, acc);
-    fused_store(HB, w, lane, acc);
+    fused_layer<kMlpIn>(H, W1, P + kOffB1, w, lane, acc);
+    __syncthreads();            // every wave has read the inputs
+    fused_store(H, w, lane, acc);
     __syncthreads();
-    fused_layer<kMlpH>(HB, W2, P + kOffB2, w, lane, acc);
-    fused_store(HA, w, lane, acc);
+    fused_layer<kMlpH>(H, W2, P + kOffB2, w, lane, acc);
     __syncthreads();
-    fused_layer<kMlpH>(HA, W3, P + kOffB3, w, lane, acc);
+    fused_store(H, w, lane, acc);
+    __syncthreads();
+    fused_layer<kMlpH>(H, W3, P + kOffB3, w, lane, acc);
     // head: this wave's columns, summed over the 16 lanes of each fragment row
     const int fr = lane & 15, g = lane >> 4;
 #pragma unroll

@@ -231,8 +231,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                     // active tiles inside the tile rectangle [x0, x1) x [y0, y1)
                     const uint32_t *S = tile_sat + V.sat_base;
                     const int stride = V.tiles_x + 1;
-                    const int x0 = (int)xl >> 4, x1 = ((int)xh >> 4) + 1;
-                    const int y0 = ((int)yl >> 4) * stride, y1 = (((int)yh >> 4) + 1) * stride;
+                    const int x0 = (int)xl >> V.tsx, x1 = ((int)xh >> V.tsx) + 1;
+                    const int y0 = ((int)yl >> V.tsy) * stride, y1 = (((int)yh >> V.tsy) + 1) * stride;
                     keep = S[y1 + x1] - S[y0 + x1] - S[y1 + x0] + S[y0 + x0] != 0u;
                 }
             }

@@ -137,12 +137,12 @@ class Proposal:
         n = X.shape[0]
         for ep in range(epochs):
             perm = torch.randperm(n, generator=g).to(X.device)
-            tot = 0.0
+            tot = torch.zeros(1, dtype=torch.float64, device=X.device)
             for b0 in range(0, n, batch):
                 idx = perm[b0:b0 + batch]
                 loss = self.train_step(X[idx].contiguous(), Y[idx].contiguous(), lr)
-                tot += float(loss.item()) * idx.numel()
-            losses.append(tot / n)
+                tot += loss.double() * idx.numel()
+            losses.append(float(tot.item()) / n)
             if log:
                 log(f"epoch {ep}: loss {losses[-1]:.4f}")
         return losses

@@ -277,6 +277,8 @@ def test_objective_parity(gs, ora):
         scale = np.maximum(np.abs(want), ob["A"])
         err = np.abs(got - want) / np.maximum(scale, 1e-30)
         tol = 1e-5 if obj != gs.OBJ_TRUE else 1e-4
+        print(f"[objective {key}] max rel err {err.max():.3e}, p99.9 {np.quantile(err, 0.999):.3e}; "
+              f"pairs with w rho >= 1: {ob['n_invalid']}", flush=True)
         assert err.max() <= tol, f"{key}: max rel err {err.max():.3e}"
         pv = out["per_view"].cpu().numpy()
         if obj != gs.OBJ_TRUE:
