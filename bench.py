@@ -53,7 +53,8 @@ EMIT_BYTES_POSITION, EMIT_BYTES_BIN, EMIT_BYTES_ENTRY = 12, 8, 4
 # WRITE_SIZE, scaled by a plain copy of known size), with the hash of the
 # kernel source the counters were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scene1m_100views.md")
-KERNEL_SOURCES = {"k_pass2": "paper_2607_02721_amd/csrc/composite.hip",
+KERNEL_SOURCES = {"k_pass1": "paper_2607_02721_amd/csrc/composite.hip",
+                  "k_pass2": "paper_2607_02721_amd/csrc/composite.hip",
                   "k_bin_emit": "paper_2607_02721_amd/csrc/binning.hip"}
 
 
@@ -162,20 +163,30 @@ def batch_leg(gs, synth, torch, args, tile):
     plan_out = [o.clone() for o in outs]
     plan.close()
     del plan
-    t0 = time.perf_counter()
+    # one untimed pass over the scenes (it grows the library's scratch arenas
+    # and checks the plan's results), then the timed passes
     same = True
+    t0 = time.perf_counter()
     for d, vw, o in zip(dev, views, plan_out):
         s_, _ = gs.sensitivity(d, vw, tile=tile)
         same = same and bool(torch.equal(s_, o))
     torch.cuda.synchronize()
-    ms_seq = (time.perf_counter() - t0) * 1e3
+    ms_seq_first = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for d, vw in zip(dev, views):
+            gs.sensitivity(d, vw, tile=tile)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / args.steps
     gv = sum(n * nv for n, nv, _, _ in specs)
     rays = sum(int(np.sum(vw.size[:, 0].astype(np.int64) * vw.size[:, 1])) for vw in views)
-    log(f"batch: plan {ms_plan:.1f} ms/step, per-scene calls {ms_seq:.1f} ms, identical={same}")
+    log(f"batch: plan {ms_plan:.1f} ms/step, per-scene calls {ms_seq:.1f} ms (first pass {ms_seq_first:.1f} ms), "
+        f"identical={same}")
     return {"workload": "16 scenes, 50k-2M Gaussians (log-uniform), 24-200 views each at "
                         "640x360/1280x720/1920x1080 mixed",
             "scenes": [{"gaussians": n, "views": nv} for n, nv, _, _ in specs],
-            "ms_per_step": ms_plan, "ms_per_scene_calls": ms_seq, "identical_to_per_scene": same,
+            "ms_per_step": ms_plan, "ms_per_scene_calls": ms_seq, "ms_per_scene_calls_first_pass": ms_seq_first,
+            "identical_to_per_scene": same,
             "gaussian_views_per_s": gv / (ms_plan * 1e-3), "rays": rays,
             "tuner": {"best": best, "ms": dict(zip(["flat_xcd", "flat", "persistent"], tune_ms))},
             "tile": list(tile),
@@ -516,6 +527,15 @@ def main():
         # the same work priced with the measured issue rate and exp cost
         slots = OPS_PASS2 - 2 + peaks["exp_cost_in_fma_slots"]
         p2["frac_of_measured_issue_rate"] = live * slots / (stage["ms_pass2"] * 1e-3) / (peaks["fma_Tlane_per_s"] * 1e12)
+    p1 = {"kernel": "k_pass1 (compositing pass 1: per-ray A, quadrant culling and list compaction)",
+          "bound": "alu", "achieved": live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / 1e12,
+          "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s", "ms": stage["ms_pass1"],
+          "work": f"{live} live pairs x {OPS_PASS1} VALU slots",
+          "traffic": measured_traffic("k_pass1")}
+    p1["frac"] = p1["achieved"] / p1["peak"]
+    if peaks:
+        slots = OPS_PASS1 - 2 + peaks["exp_cost_in_fma_slots"]
+        p1["frac_of_measured_issue_rate"] = live * slots / (stage["ms_pass1"] * 1e-3) / (peaks["fma_Tlane_per_s"] * 1e12)
     emit_bytes = (EMIT_BYTES_POSITION * cst["n_projected"] + EMIT_BYTES_BIN * cst["n_bins"]
                   + EMIT_BYTES_ENTRY * cst["n_entries"])
     em = {"kernel": "k_bin_emit (ordered tile-list emission)", "bound": "hbm",
@@ -540,9 +560,9 @@ def main():
              "roof_overlapped_ms": max(t_valu, t_hbm), "roof_summed_ms": t_valu + t_hbm,
              "frac_overlapped": max(t_valu, t_hbm) / ms, "frac_summed": (t_valu + t_hbm) / ms}
     log(f"whole pass: {json.dumps(whole)}")
-    ranked = sorted([p2, em], key=lambda r: -r["ms"])
+    # the dominant kernel (longest HIP-event time) carries the headline roofline
+    ranked = sorted([p1, p2, em], key=lambda r: -r["ms"])
     roofline = dict(ranked[0])
-    roofline["pass1_frac"] = live * OPS_PASS1 / (stage["ms_pass1"] * 1e-3) / PEAK_LANE_OPS
     others = ranked[1:]
     if learned is not None:
         flop = mlp_rows * MLP_FLOP_PER_ROW

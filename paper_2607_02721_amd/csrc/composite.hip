@@ -156,15 +156,18 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
         const float u = fmaf(beta, dy, dx);
         return (A * u) * u + (G * dy) * dy;
     };
-    // edges dy = y0, y1: best dx = -beta dy
-    float best = fminf(q(fminf(fmaxf(-beta * y0, x0), x1), y0), q(fminf(fmaxf(-beta * y1, x0), x1), y1));
+    // edges dy = y0, y1: best dx = -beta dy, clamped to [x0, x1] (x0 < x1: a
+    // median of three is the clamp)
+    float best = fminf(q(__builtin_amdgcn_fmed3f(-beta * y0, x0, x1), y0),
+                       q(__builtin_amdgcn_fmed3f(-beta * y1, x0, x1), y1));
     // edges dx = x0, x1: best dy = -A beta dx / (A beta^2 + G)
     const float k = -(A * beta) * __builtin_amdgcn_rcpf(fmaf(A * beta, beta, G));
-    best = fminf(best, q(x0, fminf(fmaxf(k * x0, y0), y1)));
-    best = fminf(best, q(x1, fminf(fmaxf(k * x1, y0), y1)));
+    best = fminf(best, q(x0, __builtin_amdgcn_fmed3f(k * x0, y0, y1)));
+    best = fminf(best, q(x1, __builtin_amdgcn_fmed3f(k * x1, y0, y1)));
     const float S = fabsf(mx) + fabsf(my) + 16.0f;
+    // (v_sqrt_f32, within about an ulp, is ample for a bound this loose)
     const float err = 3.814697265625e-6f /* 2^-18 */ * S *
-                          ((1.0f + fabsf(beta)) * sqrtf(A * C) + sqrtf(G * C)) +
+                          ((1.0f + fabsf(beta)) * __builtin_amdgcn_sqrtf(A * C) + __builtin_amdgcn_sqrtf(G * C)) +
                       1e-4f * C;
     return best <= C + err;
 }
@@ -380,81 +383,46 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
     }
 }
 
-// Transposed butterfly over 64 lanes for 32 values: afterwards lane L holds
-// the maximum over all 64 lanes of value (L >> 1) & 31.  Each level pairs
-// every lane with a partner on the other side of one lane-index bit and
-// keeps half of the values:
+// Transposed butterfly over 64 lanes for 16 values: afterwards lane L holds
+// the maximum over all 64 lanes of value (L >> 2) & 15.  Each level pairs
+// every lane with a partner on the other side of one lane-index bit; the
+// lane keeps one half of its values and sends the other half, which is the
+// half its partner keeps:
 //   bit 5: v_permlane32_swap (upper 32 lanes of one register <-> lower 32 of another)
 //   bit 4: v_permlane16_swap (odd 16-lane rows <-> even rows)
 //   bit 3: DPP row_mirror (i <-> 15-i in a row), bit 2: row_half_mirror (i <-> 7-i),
-//   bit 1: quad_perm [2,3,0,1], bit 0: quad_perm [1,0,3,2]
+// then two plain reductions over bits 1 and 0 (quad_perm [2,3,0,1], [1,0,3,2]).
 // Every index is a compile-time constant, so the values stay in registers.
+// The shares are non-negative floats, whose order is that of their bit
+// patterns as unsigned integers: the maxima are taken as such (v_max_u32,
+// with the DPP move folded in and no NaN canonicalisation).
+__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
 template <int kCtrl>
-__device__ __forceinline__ float dpp_max(float x) {
-    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, false));
-    return fmaxf(x, y);
+__device__ __forceinline__ uint32_t dpp_umax(uint32_t keep, uint32_t send) {
+    return umax32(keep, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send, kCtrl, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ float wave_transpose_max32(float (&v)[32]) {
+__device__ __forceinline__ float wave_transpose_max16(const float (&sh)[16]) {
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 16]),
-                                                        false, false);
-        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
-    }
+    uint32_t v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 8]),
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(sh[k]), __float_as_uint(sh[k + 8]),
                                                         false, false);
-        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
-    }
-    const bool s3 = (lane & 8) != 0, s2 = (lane & 4) != 0, s1 = (lane & 2) != 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float m0 = dpp_max<0x140>(v[k]), m1 = dpp_max<0x140>(v[k + 4]);
-        v[k] = s3 ? m1 : m0;
-    }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float m0 = dpp_max<0x141>(v[k]), m1 = dpp_max<0x141>(v[k + 2]);
-        v[k] = s2 ? m1 : m0;
-    }
-    {
-        const float m0 = dpp_max<0x4E>(v[0]), m1 = dpp_max<0x4E>(v[1]);
-        v[0] = s1 ? m1 : m0;
-    }
-    return dpp_max<0xB1>(v[0]);
-}
-
-// The same network for 16 values: four halving levels (lane bits 5..2)
-// and two plain reductions (bits 1, 0); afterwards lane L holds the maximum
-// over all 64 lanes of value (L >> 2) & 15.
-__device__ __forceinline__ float wave_transpose_max16(float (&v)[16]) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 8]),
-                                                        false, false);
-        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+        v[k] = umax32(r[0], r[1]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]), __float_as_uint(v[k + 4]),
-                                                        false, false);
-        v[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+        const auto r = __builtin_amdgcn_permlane16_swap(v[k], v[k + 4], false, false);
+        v[k] = umax32(r[0], r[1]);
     }
     const bool s3 = (lane & 8) != 0, s2 = (lane & 4) != 0;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float m0 = dpp_max<0x140>(v[k]), m1 = dpp_max<0x140>(v[k + 2]);
-        v[k] = s3 ? m1 : m0;
-    }
-    {
-        const float m0 = dpp_max<0x141>(v[0]), m1 = dpp_max<0x141>(v[1]);
-        v[0] = s2 ? m1 : m0;
-    }
-    return dpp_max<0xB1>(dpp_max<0x4E>(v[0]));
+    for (int k = 0; k < 2; ++k) v[k] = dpp_umax<0x140>(s3 ? v[k + 2] : v[k], s3 ? v[k] : v[k + 2]);
+    v[0] = dpp_umax<0x141>(s2 ? v[1] : v[0], s2 ? v[0] : v[1]);
+    v[0] = dpp_umax<0x4E>(v[0], v[0]);
+    return __uint_as_float(dpp_umax<0xB1>(v[0], v[0]));
 }
 
 template <int kCtrl>
