@@ -628,7 +628,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
         }
     }
     tm.mark(6, st);
-    launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, st);
+    launch_bin_emit(r.views_dev, c.vc, N, S.nchunks, b, xr, yr, r.sorted_g, max_tx, max_ty, (uint64_t)total, S.tsx,
+                    st);
     HIP_TRY(hipGetLastError());
     tm.mark(7, st);
 
@@ -1595,7 +1596,7 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
             if (ps.passes == 3) launch_span_check(ps.b.kmin, ps.c.vc, ps.over, P->flag, st);
             launch_list_guard(ps.b.tile_off, ps.c.total_tiles, ps.cap, ps.over, P->flag, ps.passes == 3, st);
             launch_bin_emit(ps.views_dev, ps.c.vc, ps.S.N, ps.S.nchunks, ps.b, ps.xr, ps.yr, ps.sorted_g,
-                            ps.max_tx, ps.max_ty, ps.cap, st);
+                            ps.max_tx, ps.max_ty, ps.cap, ps.S.tsx, st);
             launch_fill_u32((uint32_t *)sens[si], 0u, ps.S.N, st);
         }
         for (const CompositeBatch &cb : G.batches) {

@@ -210,18 +210,20 @@ __global__ __launch_bounds__(kBinThreads) void k_chunk_prefix(const ViewDev *__r
 // receive later slots and every (tile, chunk) segment is filled in
 // increasing p.
 //
-// Entries are not stored one by one: each tile keeps the 32-byte block of
-// its list that it is filling in LDS (slot = absolute entry index mod 8),
-// and a block goes out as one 8-lane store once its last slot is filled.
-// Only the first and last block of a segment (shared with the neighbouring
-// chunks' segments) are written partially.  Scattered 4-byte stores leave
-// the L2 as several partial-line writes per line (about 24 GB of writes for
-// 4.3 GB of entries at 1M Gaussians x 100 views, against 6.6 GB this way),
-// and 32-byte blocks keep the wave's LDS small enough for 28 waves per CU.
+// Entries are not stored one by one: each tile keeps the block ("line") of
+// its list that it is filling in LDS (slot = absolute entry index mod the
+// line length), and a line goes out as one store of consecutive lanes once
+// its last slot is filled.  Only the first and last line of a segment
+// (shared with the neighbouring chunks' segments) are written partially.
+// Scattered 4-byte stores leave the L2 as several partial-line writes per
+// line (about 24 GB of writes for 4.3 GB of entries at 1M Gaussians x 100
+// views with 16x16 tiles, against 6.6 GB with 32-byte lines).  Lines are 8
+// entries (32 bytes) for tiles 8 or 16 pixels wide, which keeps the wave's
+// LDS small, and 16 entries (64 bytes, streamed past the L2) for tiles 32
+// pixels wide, whose segments per chunk are long enough to fill them.
 constexpr int kEmitWave = 64;
 constexpr int kEmitRows = 1;
 constexpr int kEmitCols = 128;     // tile columns per wave (2048 pixels)
-constexpr int kLine = 8;           // list entries per staged block (a power of two)
 
 __device__ __forceinline__ uint64_t lanemask_lt64_bin() {
     const unsigned lane = threadIdx.x & 63;
@@ -275,10 +277,22 @@ __device__ __forceinline__ bool tile_on(const uint32_t *act, int t) {
     return !kMasked || ((act[t >> 5] >> (t & 31)) & 1u);
 }
 
+// A list entry's store: 64-byte lines bypass the L2 (they are whole write
+// requests, and the lists are read only by a later launch); 32-byte lines
+// go through it, where the halves of a request that two chunks' segments
+// share are merged.
+template <int kLine>
+__device__ __forceinline__ void store_entry(uint32_t v, uint32_t *dst) {
+    if (kLine >= 16)
+        __builtin_nontemporal_store(v, dst);
+    else
+        *dst = v;
+}
+
 // LDS layout of one emission wave (32-bit words unless noted).
 struct EmitLds {
     uint64_t *lanes;    // [tiles] lanes of the current item batch on the tile
-    uint32_t *line;     // [tiles][kLine] the line each tile is filling
+    uint32_t *line;     // [tiles][2^kLineLog] the line each tile is filling
     uint32_t *cur;      // [tiles] next entry, relative to the view's first entry
     uint32_t *seg0;     // [tiles] first entry of the tile's segment in this chunk
     int32_t *head;      // [64] lane owning the item that starts a run
@@ -288,11 +302,12 @@ struct EmitLds {
     uint32_t *act;      // [tiles / 32] (masked form only)
 };
 
-__host__ __device__ constexpr size_t emit_lds_bytes(int tiles, bool masked) {
-    return sizeof(uint32_t) * ((size_t)tiles * (kLine + 4) + 6 * kEmitWave) + sizeof(uint16_t) * kEmitBatch +
+__host__ __device__ constexpr size_t emit_lds_bytes(int tiles, bool masked, int line_log) {
+    return sizeof(uint32_t) * ((size_t)tiles * ((1 << line_log) + 4) + 6 * kEmitWave) + sizeof(uint16_t) * kEmitBatch +
            (masked ? sizeof(uint32_t) * (((size_t)tiles + 31) / 32) : 0);
 }
 
+template <int kLine>
 __device__ __forceinline__ EmitLds emit_lds(uint32_t *base, int tiles) {
     EmitLds L;
     L.lanes = (uint64_t *)base;
@@ -313,6 +328,7 @@ __device__ __forceinline__ EmitLds emit_lds(uint32_t *base, int tiles) {
 // Stores the staged blocks ("lines") listed in L.ft / L.fc (n of them), 64 / kLine per step
 // with kLine lanes each; entries before the tile's segment (another chunk's) and at or
 // past `room` are left alone.
+template <int kLine>
 __device__ __forceinline__ void store_lines(const EmitLds &L, int n, uint32_t align, uint32_t *__restrict__ vl,
                                             uint64_t room) {
     const int lane = threadIdx.x;
@@ -323,12 +339,12 @@ __device__ __forceinline__ void store_lines(const EmitLds &L, int n, uint32_t al
             const uint32_t last = L.fc[f];                           // entry in the line's last slot
             const int64_t e = (int64_t)last - (int64_t)((align + last) & (kLine - 1u)) + k;
             if (e >= (int64_t)L.seg0[t] && (uint64_t)e < room && e <= (int64_t)last)
-                vl[e] = L.line[t * kLine + k];
+                store_entry<kLine>(L.line[t * kLine + k], &vl[e]);
         }
     }
 }
 
-template <bool kMasked>
+template <bool kMasked, int kLineLog>
 __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restrict__ views, int n_views, int64_t N,
                                                         int nchunks, int row_groups, int col_groups,
                                                         const uint32_t *__restrict__ nvis,
@@ -342,7 +358,8 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                                                         int group_tiles, const uint64_t *__restrict__ rowbits,
                                                         int rows_stride) {
     extern __shared__ uint32_t lds[];
-    const EmitLds L = emit_lds(lds, group_tiles);
+    constexpr int kLine = 1 << kLineLog;
+    const EmitLds L = emit_lds<kLine>(lds, group_tiles);
     // logical block: group + groups * (chunk + nchunks * view), with group =
     // row group + row_groups * column group
     const int groups = row_groups * col_groups;
@@ -413,7 +430,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
         // chunk's visible positions are clear), a wave prefix sum of the
         // popcounts places each lane's positions in the queue
         const int nw = (b1 - b0 + 63) >> 6;
-        uint64_t word = lane < nw ? rbits[(b0 >> 6) + lane] : 0ull;
+        uint64_t word = lane < nw ? __builtin_nontemporal_load(&rbits[(b0 >> 6) + lane]) : 0ull;
         const int cnt = __popcll(word);
         const int incl = wave_scan_add(cnt);
         const int nq = __builtin_amdgcn_readlane(incl, kEmitWave - 1);
@@ -524,7 +541,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                             L.fc[r] = c;
                         }
                         wave_sync();
-                        store_lines(L, __popcll(need), align, vl, room);
+                        store_lines<kLine>(L, __popcll(need), align, vl, room);
                         wave_sync();
                     }
                 }
@@ -557,7 +574,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                 const uint32_t last = L.fc[f];
                 const int64_t e = (int64_t)last - (int64_t)((align + last) & (kLine - 1u)) + k;
                 if (e >= (int64_t)L.seg0[tt] && (uint64_t)e < room && e <= (int64_t)last)
-                    vl[e] = L.line[tt * kLine + k];
+                    store_entry<kLine>(L.line[tt * kLine + k], &vl[e]);
             }
         }
         wave_sync();
@@ -581,24 +598,24 @@ void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const Ch
 
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
-                     int max_tiles_y, uint64_t cap, hipStream_t st) {
+                     int max_tiles_y, uint64_t cap, int tile_shift_x, hipStream_t st) {
     const int row_groups = (max_tiles_y + kEmitRows - 1) / kEmitRows;
     const int col_groups = (max_tiles_x + kEmitCols - 1) / kEmitCols;
     const int64_t run = 8 * (int64_t)kEmitGroupChunks * row_groups * col_groups;
     const int64_t blocks = ((int64_t)row_groups * col_groups * nchunks * Vc + run - 1) / run * run;
     const int group_tiles = kEmitRows * std::min(max_tiles_x, kEmitCols);
-    const size_t lds = emit_lds_bytes(group_tiles, b.tile_active != nullptr);
+    const int line_log = tile_shift_x >= 5 ? 4 : 3;
+    const size_t lds = emit_lds_bytes(group_tiles, b.tile_active != nullptr, line_log);
     const dim3 grid((unsigned)blocks);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups, col_groups,
+                           b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
+                           group_tiles, b.rowbits, b.rows_stride);
+    };
     if (b.tile_active)
-        hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
-                           col_groups,
-                           b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
-                           group_tiles, b.rowbits, b.rows_stride);
+        line_log == 4 ? go(k_bin_emit<true, 4>) : go(k_bin_emit<true, 3>);
     else
-        hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(kEmitWave), lds, st, views_dev, Vc, N, nchunks, row_groups,
-                           col_groups,
-                           b.nvis, xr, yr, sorted_g, b.bin_count, b.tile_off, b.lists, b.tile_active, cap,
-                           group_tiles, b.rowbits, b.rows_stride);
+        line_log == 4 ? go(k_bin_emit<false, 4>) : go(k_bin_emit<false, 3>);
 }
 
 // Capacity guard for lists sized in advance (plans): if the counted entries

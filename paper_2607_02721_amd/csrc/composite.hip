@@ -220,7 +220,9 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
     }
     if (touch) {
         const int slot = __popcll(bal & lanemask_lt64());
-        if (cout) cout[slot] = g;    // pass 1 keeps the quadrant's entries in order
+        // pass 1 keeps the quadrant's entries in order (streamed past L2: pass 2
+        // reads them in a later launch)
+        if (cout) __builtin_nontemporal_store(g, &cout[slot]);
         float cb = 0.0f, cg = 0.0f;
         if (kChannel) {
             const float4 c3 = w.R3[o];

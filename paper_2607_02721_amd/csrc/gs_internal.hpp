@@ -174,7 +174,7 @@ void launch_chunk_prefix(const ViewDev *views_dev, int Vc, int nchunks, const Ch
 // place; entries at list index >= cap are dropped.
 void launch_bin_emit(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, const ChunkBufs &b,
                      const uint32_t *xr, const uint32_t *yr, const uint32_t *sorted_g, int max_tiles_x,
-                     int max_tiles_y, uint64_t cap, hipStream_t st);
+                     int max_tiles_y, uint64_t cap, int tile_shift_x, hipStream_t st);
 // Plan guards: *over = 1 (and *flag |= kGuardSpan) when some view's kept
 // depth keys span 2^24 or more (a three-pass sort would misorder them); the
 // list guard sets *over (and *flag |= kGuardList) when the lists outgrow
