@@ -76,6 +76,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
     // x and then y are the counts (four LDS atomics per position, whatever
     // its size).
     extern __shared__ int32_t dif[];                  // [tiles_y + 1][tiles_x + 1]
+    __shared__ uint64_t rowword[kBinThreads / 64][128];   // per wave: row words on their way to the lanes
     const int64_t lb = xcd_block(blockIdx.x, kCountGroup);   // logical block: chunk + nchunks * view
     const int v = (int)(lb / nchunks);
     if (v >= n_views) return;
@@ -98,17 +99,22 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
     // are invalid), so the row words gathered into the lanes can be stored
     // by the whole wave
     const int lane = threadIdx.x & 63;
+    uint64_t *sw = rowword[threadIdx.x >> 6];
     for (int64_t p0 = lo + (threadIdx.x & ~63); p0 < hi; p0 += kBinThreads) {
         const int64_t p = p0 + lane;
         const bool valid = p < hi;
-        int ty0 = 1, ty1 = 0;   // an empty row range for invalid positions
+        // rows [ty0, ty0 + span]; invalid positions meet none (r - ty0 wraps
+        // to a large unsigned value for every row r)
+        int ty0 = 0x40000000;
+        uint32_t span = 0u;
         if (valid) {
             int xl, xh, yl, yh;
             unpack_range(__uint_as_float(xr_in[(int64_t)v * N + p]), xl, xh);
             unpack_range(__uint_as_float(yr_in[(int64_t)v * N + p]), yl, yh);
             const int x0 = xl >> V.tsx, x1 = (xh >> V.tsx) + 1;
             ty0 = yl >> V.tsy;
-            ty1 = yh >> V.tsy;
+            const int ty1 = yh >> V.tsy;
+            span = (uint32_t)(ty1 - ty0);
             const int y0 = ty0 * stride, y1 = (ty1 + 1) * stride;
             atomicAdd(&dif[y0 + x0], 1);
             atomicAdd(&dif[y0 + x1], -1);
@@ -116,26 +122,22 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const ViewDev *__rest
             atomicAdd(&dif[y1 + x1], 1);
         }
         // the wave's 64 positions form one bitmap word per tile row: one
-        // ballot per row, its two halves kept by lane r (rows 64..127 in a
-        // second pair), then one store per pair by the lanes that own a row
+        // ballot per row, written to LDS by lane 0 (128 rows at a time) and
+        // read back by the lane that stores the row's word
         const int w = (int)((p0 - lo) >> 6);
-        uint32_t lo0 = 0u, hi0 = 0u, lo1 = 0u, hi1 = 0u;
-        for (int r = 0; r < ty_n; ++r) {
-            const uint64_t bits = __ballot(valid && (unsigned)(r - ty0) <= (unsigned)(ty1 - ty0));
-            if (r < 64) {
-                const bool mine = lane == r;
-                lo0 = mine ? (uint32_t)bits : lo0;
-                hi0 = mine ? (uint32_t)(bits >> 32) : hi0;
-            } else if (r < 128) {
-                const bool mine = lane == r - 64;
-                lo1 = mine ? (uint32_t)bits : lo1;
-                hi1 = mine ? (uint32_t)(bits >> 32) : hi1;
-            } else if (lane == 0) {
-                rb[(int64_t)r * row_pitch + w] = bits;   // views taller than 128 tile rows
+        for (int rb0 = 0; rb0 < ty_n; rb0 += 128) {
+            const int rn = __builtin_amdgcn_readfirstlane(min(128, ty_n - rb0));
+            const uint32_t rel = (uint32_t)(rb0 - ty0);
+#pragma unroll 8
+            for (int k = 0; k < rn; ++k) {
+                const uint64_t bits = __ballot(rel + (uint32_t)k <= span);
+                if (lane == 0) sw[k] = bits;
             }
+            wave_sync();
+            if (lane < rn) rb[(int64_t)(rb0 + lane) * row_pitch + w] = sw[lane];
+            if (lane + 64 < rn) rb[(int64_t)(rb0 + lane + 64) * row_pitch + w] = sw[lane + 64];
+            wave_sync();   // the words are read before the next rows overwrite them
         }
-        if (lane < ty_n) rb[(int64_t)lane * row_pitch + w] = (uint64_t)lo0 | ((uint64_t)hi0 << 32);
-        if (lane + 64 < ty_n) rb[(int64_t)(lane + 64) * row_pitch + w] = (uint64_t)lo1 | ((uint64_t)hi1 << 32);
     }
     __syncthreads();
     for (int ty = threadIdx.x; ty < ty_n; ty += kBinThreads) {       // along x, one row per thread
