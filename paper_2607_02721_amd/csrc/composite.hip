@@ -181,15 +181,15 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
 // c_B in cblue.  With kLog (no extra value, one query per ray) col = (g',
 // log2 alpha, cbar, cut + log2 alpha) for pair_rho_log2; null entries then
 // carry an infinite bar.
+// stage_raw: the same for one list entry per lane (raw = 0: none), at list
+// position e (read only for kExtra 3).
 template <int kExtra, int kPad = 1, bool kChannel = false, bool kLog = false>  // kExtra 0: none, 1: s_old + index, 2: weight, 3: index + list position
-__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
-                                           uint32_t *sid, float *sold, const double *__restrict__ weights,
-                                           float *cblue = nullptr, uint32_t *cout = nullptr) {
+__device__ __forceinline__ int stage_raw(const WaveSetup &w, uint32_t raw, uint64_t e, float cut, float4 *geo,
+                                         float4 *col, uint32_t *sid, float *sold, const double *__restrict__ weights,
+                                         float *cblue = nullptr, uint32_t *cout = nullptr) {
     static_assert(!(kChannel && kExtra == 2), "per-channel queries have no weighted objective");
     static_assert(!(kLog && (kChannel || kExtra == 2)), "the log form has no room for an extra value");
     const int lane = threadIdx.x;
-    const uint64_t e = e0 + lane;
-    const uint32_t raw = e < w.end ? w.lists[e] : 0u;
     const float4 *__restrict__ R0 = w.R0;
     const float4 *__restrict__ R1 = w.R1;
     const float4 *__restrict__ R2 = w.R2;
@@ -252,6 +252,15 @@ __device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, floa
         }
     }
     return n;
+}
+
+template <int kExtra, int kPad = 1, bool kChannel = false, bool kLog = false>
+__device__ __forceinline__ int stage_slice(const WaveSetup &w, uint64_t e0, float cut, float4 *geo, float4 *col,
+                                           uint32_t *sid, float *sold, const double *__restrict__ weights,
+                                           float *cblue = nullptr, uint32_t *cout = nullptr) {
+    const uint64_t e = e0 + threadIdx.x;
+    const uint32_t raw = e < w.end ? w.lists[e] : 0u;
+    return stage_raw<kExtra, kPad, kChannel, kLog>(w, raw, e, cut, geo, col, sid, sold, weights, cblue, cout);
 }
 
 // Stage up to 64 entries of a quadrant's compacted list (every one passed
