@@ -857,6 +857,72 @@ int ora_objective(const ora_scene *g, const ora_views *vw, const ora_params *prm
     return 0;
 }
 
+/* Rounding scale of the true reduced render (test infrastructure: it sets
+ * the FP32 tolerance of A_w, it is not part of the method).  A relative error
+ * d in rho_j moves the factor 1 - w_j rho_j by a relative
+ * w_j rho_j d / |1 - w_j rho_j|, and with it T_w of every later pair of the
+ * ray; per ray, to first order in d,
+ *   |dA_w| <= d E,  E = sum_i |w_i a_i^w| k (1 + sum_{j before i} (1 + w_j rho_j) / |1 - w_j rho_j|),
+ * with a_i^w the pair's contribution under T_w and k its degree in (rho_i,
+ * T_w): 2 for the L2 objective, else 1.  A factor that is exactly 0 makes
+ * E infinite.  Rays outside the mask or with A = 0 get 0.                 */
+int ora_objective_true_scale(const ora_scene *g, const ora_views *vw, const ora_params *prm,
+                             const uint32_t *ray_mask, const double *w, double *E /* [rays] */)
+{
+    if (n_queries(prm) != 1) return 2;
+    const int32_t V = vw->n_views;
+    const double r2 = prm->footprint_sigma * prm->footprint_sigma;
+    const double kT = prm->query_mode == 2 ? 2.0 : 1.0;
+    int64_t ray0 = 0;
+    for (int32_t v = 0; v < V; ++v) {
+        const int32_t W = vw->size[2 * v], H = vw->size[2 * v + 1];
+        const int64_t npix = (int64_t)W * H;
+        ora_view_setup S;
+        setup_view(g, vw, prm, v, &S);
+        double *T = (double *)malloc(sizeof(double) * (size_t)npix);
+        double *Tw = (double *)malloc(sizeof(double) * (size_t)npix);
+        double *Af = (double *)calloc((size_t)npix, sizeof(double));
+        double *K = (double *)calloc((size_t)npix, sizeof(double));
+        double *Es = (double *)calloc((size_t)npix, sizeof(double));
+        for (int64_t p = 0; p < npix; ++p) { T[p] = 1.0; Tw[p] = 1.0; }
+        for (int64_t k = 0; k < S.n_present; ++k) {
+            const int64_t i = S.order[k].idx;
+            const ora_proj *o = &S.proj[i];
+            int32_t ylo, yhi, xlo, xhi;
+            pixel_range(o->my, o->ry, H, &ylo, &yhi);
+            pixel_range(o->mx, o->rx, W, &xlo, &xhi);
+            const double wi = w ? w[i] : 1.0;
+            for (int32_t py = ylo; py <= yhi; ++py)
+                for (int32_t px = xlo; px <= xhi; ++px) {
+                    int64_t p = (int64_t)py * W + px;
+                    if (!ray_selected(ray_mask, ray0 + p)) continue;
+                    double dx = (px + 0.5) - o->mx, dy = (py + 0.5) - o->my;
+                    double d2 = o->conic[0] * dx * dx + 2.0 * o->conic[1] * dx * dy + o->conic[2] * dy * dy;
+                    if (d2 > r2) continue;
+                    double rho = o->alpha * exp(-0.5 * d2), a, aw;
+                    pair_contrib(prm, o, rho, T[p], &a);
+                    Af[p] += a;
+                    T[p] *= (1.0 - rho);
+                    if (wi > 0.0) {
+                        pair_contrib(prm, o, rho, Tw[p], &aw);
+                        Es[p] += fabs(wi * aw) * kT * (1.0 + K[p]);
+                        const double f = 1.0 - wi * rho;
+                        K[p] += (1.0 + fabs(wi * rho)) / fabs(f);
+                        Tw[p] *= f;
+                    }
+                }
+        }
+        for (int64_t p = 0; p < npix; ++p) {
+            const int on = ray_selected(ray_mask, ray0 + p) && Af[p] > 0.0;
+            E[ray0 + p] = on ? Es[p] : 0.0;
+        }
+        free(T); free(Tw); free(Af); free(K); free(Es);
+        free_view(&S);
+        ray0 += npix;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC 2011): 10 rounds of the Philox S-P network on a

@@ -63,6 +63,8 @@ def _load():
         _lib.ora_sensitivity.argtypes = [P, P, P, P, P, P, P, P]
         _lib.ora_sensitivity_agg.argtypes = [P, P, P, P, C.c_int32, P]
         _lib.ora_objective.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        _lib.ora_objective_true_scale.argtypes = [P, P, P, P, P, P]
+        _lib.ora_objective_true_scale.restype = C.c_int
         _lib.ora_sample.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, P, P, P, P]
         _lib.ora_philox4x32_10.argtypes = [P, P, P]
         _lib.ora_project.argtypes = [P] * 13
@@ -176,6 +178,22 @@ def objective(scene, views, weights, params=None, ray_mask=None):
     assert rc == 0
     return {"A": out[0], "A_fixed": out[1], "A_true": out[2], "view_sums": vs,
             "n_invalid": int(inv[0]), "gamma": float(gam[0])}
+
+
+def objective_true_scale(scene, views, weights, params=None, ray_mask=None):
+    """Per-ray rounding scale E of the true reduced render (test
+    infrastructure): a relative error d in every rho moves A_w by at most
+    d E to first order (see ora_objective_true_scale)."""
+    lib = _load()
+    k = _Keep(scene, views, params or default_params())
+    E = np.zeros(views.n_rays, np.float64)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    mask = None if ray_mask is None else np.ascontiguousarray(ray_mask, np.uint32)
+    rc = lib.ora_objective_true_scale(C.byref(k.s), C.byref(k.v), C.byref(k.p), _ptr(mask), _ptr(w), _ptr(E))
+    if rc == 2:
+        raise ValueError("the objectives hold one query per ray (not per channel)")
+    assert rc == 0
+    return E
 
 
 def project(scene, views, params=None):

@@ -270,23 +270,37 @@ def test_objective_parity(gs, ora):
     w_ref = ora.sample(s.cpu().numpy(), sc.n // 10, 3)["weights"]
     w = torch.as_tensor(w_ref).cuda()
     ob = ora.objective(sc, vw, w_ref, None, bits)
+    # the true reduced render's FP32 error grows with 1 / |1 - w rho| of the
+    # earlier pairs (factors near 0 when w rho is near 1): the oracle's
+    # rounding scale E bounds the change of A_w per unit relative error of
+    # every rho, and float32 rho carries at most ~3e-6 (the exponent's
+    # rounding times ln 2), so 1e-5 E is its share of the tolerance
+    E = ora.objective_true_scale(sc, vw, w_ref, ray_mask=bits)
     for obj, key in ((gs.OBJ_FULL, "A"), (gs.OBJ_FIXED, "A_fixed"), (gs.OBJ_TRUE, "A_true")):
         out = gs.render_objective(dsc, vw, w, obj, ray_mask=_mask_tensor(bits))
         got = out["per_ray"].cpu().numpy().astype(np.float64)
         want = ob[key]
         scale = np.maximum(np.abs(want), ob["A"])
+        tol = 1e-5 * scale + (1e-5 * E if obj == gs.OBJ_TRUE else 0.0)
         err = np.abs(got - want) / np.maximum(scale, 1e-30)
-        tol = 1e-5 if obj != gs.OBJ_TRUE else 1e-4
-        print(f"[objective {key}] max rel err {err.max():.3e}, p99.9 {np.quantile(err, 0.999):.3e}; "
-              f"pairs with w rho >= 1: {ob['n_invalid']}", flush=True)
-        assert err.max() <= tol, f"{key}: max rel err {err.max():.3e}"
+        excess = np.abs(got - want) - tol
+        print(f"[objective {key}] max rel err {err.max():.3e}, p99.9 {np.quantile(err, 0.999):.3e}, "
+              f"worst excess over the bound {excess.max():.3e}; pairs with w rho >= 1: {ob['n_invalid']}",
+              flush=True)
+        assert excess.max() <= 0.0, f"{key}: max rel err {err.max():.3e}"
         pv = out["per_view"].cpu().numpy()
         if obj != gs.OBJ_TRUE:
             # the full and fixed objectives stop a ray once later terms are
             # below 1e-9 A, so only their own columns are complete
             assert np.allclose(pv[:, :2], ob["view_sums"][:, :2], rtol=1e-5)
             continue
-        assert np.allclose(pv, ob["view_sums"], rtol=1e-4)
+        assert np.allclose(pv[:, :2], ob["view_sums"][:, :2], rtol=1e-5)
+        base = 0
+        for v in range(vw.n_views):
+            n = int(vw.size[v, 0]) * int(vw.size[v, 1])
+            bound = 1e-5 * abs(ob["view_sums"][v, 2]) + tol[base:base + n].sum()
+            assert abs(pv[v, 2] - ob["view_sums"][v, 2]) <= bound, v
+            base += n
         assert out["n_invalid_pairs"] == ob["n_invalid"]
         if ob["gamma"] > 0:
             assert abs(out["gamma_max"] - ob["gamma"]) <= 1e-4 * ob["gamma"] + 1e-5
