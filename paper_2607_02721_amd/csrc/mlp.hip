@@ -280,15 +280,33 @@ __global__ __launch_bounds__(256) void k_head_backward(const float *__restrict__
 
 // G[kOffW4 + c] (c <= 256: w4 then b4) and the loss from the per-block
 // partials, summed over blocks in order.
+// 64 columns per block; the four waves sum the blocks b = q, q + 4, ... in
+// order (eight loads in flight), and their sums are added in wave order.
 __global__ __launch_bounds__(256) void k_head_sums(const float *__restrict__ part, int nblocks,
                                                    float *__restrict__ G, float *__restrict__ loss) {
-    for (int c = threadIdx.x; c < kHeadCols; c += 256) {
-        float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kHeadCols + c];
+    __shared__ float sh[4][64];
+    const int l = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + l;
+    float s = 0.0f;
+    if (c < kHeadCols) {
+        int b = q;
+        for (; b + 28 < nblocks; b += 32) {
+            float x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = part[(int64_t)(b + 4 * k) * kHeadCols + c];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += x[k];
+        }
+        for (; b < nblocks; b += 4) s += part[(int64_t)b * kHeadCols + c];
+    }
+    sh[q][l] = s;
+    __syncthreads();
+    if (q == 0 && c < kHeadCols) {
+        const float t = ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
         if (c < kMlpH + 1)
-            G[kOffW4 + c] = s;
+            G[kOffW4 + c] = t;
         else
-            *loss = s;
+            *loss = t;
     }
 }
 
@@ -453,27 +471,33 @@ static void mlp_forward_rows(const float *P, const MlpBufs<T> &m, int64_t rows, 
     gemm_nt<T>(1, m.H2, H, m.W3, H, rows, H, H, m.Z3, H, P + kOffB3, m.H3, H, st);
 }
 
-// Fused inference: one block of 4 waves per 64 rows runs the whole network
+// Fused inference: one block of 4 waves per 128 rows runs the whole network
 // with the activations in LDS and the bf16 weights read straight from global
 // memory (L2): wave w computes output columns [64 w, 64 w + 64) of every
-// layer for the block's 64 rows, with the fragment layout and k order of
-// k_gemm_nt, so every activation is the bf16 value the unfused path stores.
+// layer for the block's 128 rows, with the k order of k_gemm_nt.
 // One row-major bf16 buffer (padded row stride, so the 16 rows a fragment
 // load reads fall on different banks) holds the input, then each layer's
 // output in place: a layer's products are finished in registers, the block
-// meets at a barrier, and only then are they written over its input.  The
-// 34 KiB of LDS per block leaves room for four blocks per CU.  The head sums
-// bf16(SiLU(z3)) w4 over each wave's columns (DPP over the 16 lanes of a
-// fragment row), then over the waves.
-constexpr int kFuseRows = 64;
+// meets at a barrier, and only then are they written over its input.  128
+// rows per block halve the weight reads from L2 against 64 (each block reads
+// all 295 KB of bf16 weights once); the 68 KiB of LDS per block leaves room
+// for two blocks per CU.  The head sums bf16(SiLU(z3)) w4 over each wave's
+// columns (DPP over the 16 lanes of a fragment row), then over the waves.
+constexpr int kFuseTiles = 8;                 // 16-row fragment tiles per block
+constexpr int kFuseRows = 16 * kFuseTiles;
 constexpr int kFusePitch = kMlpH + 8;   // bf16 per LDS row
 
+// The products are taken transposed (the weights as the first MFMA operand,
+// the activations as the second): lane l of a 16x16 output tile then holds
+// four consecutive output columns 4 (l / 16) .. + 3 of row l % 16, which go to
+// LDS as one 8-byte store and are the layout the next layer reads.
 template <int kK>
 __device__ __forceinline__ void fused_layer(const __bf16 (*In)[kFusePitch], const __bf16 *__restrict__ W,
-                                            const float *__restrict__ bias, int w, int lane, f32x4 (&acc)[4][4]) {
+                                            const float *__restrict__ bias, int w, int lane,
+                                            f32x4 (&acc)[kFuseTiles][4]) {
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kFuseTiles; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     // the next k step's weight fragments are loaded while this one multiplies
@@ -481,42 +505,48 @@ __device__ __forceinline__ void fused_layer(const __bf16 (*In)[kFusePitch], cons
 #pragma unroll
     for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(64 * w + 16 * j + fr) * kK + fk);
     for (int k0 = 0; k0 < kK; k0 += 32) {
-        bf16x8 a[4];
         if (k0 + 32 < kK) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 bn[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(64 * w + 16 * j + fr) * kK + k0 + 32 + fk);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&In[16 * i + fr][k0 + fk]);
+        for (int i = 0; i < kFuseTiles; ++i) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&In[16 * i + fr][k0 + fk]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a, acc[i][j], 0, 0, 0);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[j] = bn[j];
     }
+    const int g4 = (lane >> 4) * 4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+        float bj[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bj[r] = bias[64 * w + 16 * j + g4 + r];
+#pragma unroll
+        for (int i = 0; i < kFuseTiles; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = silu(acc[i][j][r] + bj[r]);
+    }
+}
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void fused_store(__bf16 (*Out)[kFusePitch], int w, int lane,
+                                            const f32x4 (&acc)[kFuseTiles][4]) {
+    const int fr = lane & 15, g4 = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < kFuseTiles; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const float bj = bias[64 * w + 16 * j + fr];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][j][r] = silu(acc[i][j][r] + bj);
+            const bf16x4 v = {(__bf16)acc[i][j][0], (__bf16)acc[i][j][1], (__bf16)acc[i][j][2], (__bf16)acc[i][j][3]};
+            *reinterpret_cast<bf16x4 *>(&Out[16 * i + fr][64 * w + 16 * j + g4]) = v;
         }
 }
 
-__device__ __forceinline__ void fused_store(__bf16 (*Out)[kFusePitch], int w, int lane, const f32x4 (&acc)[4][4]) {
-    const int fr = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Out[16 * i + 4 * g + r][64 * w + 16 * j + fr] = (__bf16)acc[i][j][r];
-}
-
-__global__ __launch_bounds__(256, 3) void k_mlp_fused(const float *__restrict__ feat, const float *__restrict__ norm,
+__global__ __launch_bounds__(256, 2) void k_mlp_fused(const float *__restrict__ feat, const float *__restrict__ norm,
                                                    int64_t n, const __bf16 *__restrict__ W1,
                                                    const __bf16 *__restrict__ W2, const __bf16 *__restrict__ W3,
                                                    const float *__restrict__ P, float *__restrict__ y) {
@@ -532,7 +562,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_fused(const float *__restrict__ 
         H[r][c] = (__bf16)x;
     }
     __syncthreads();
-    f32x4 acc[4][4];
+    f32x4 acc[kFuseTiles][4];
     fused_layer<kMlpIn>(H, W1, P + kOffB1, w, lane, acc);
     __syncthreads();            // every wave has read the inputs
     fused_store(H, w, lane, acc);
@@ -542,19 +572,25 @@ __global__ __launch_bounds__(256, 3) void k_mlp_fused(const float *__restrict__ 
     fused_store(H, w, lane, acc);
     __syncthreads();
     fused_layer<kMlpH>(H, W3, P + kOffB3, w, lane, acc);
-    // head: this wave's columns, summed over the 16 lanes of each fragment row
-    const int fr = lane & 15, g = lane >> 4;
+    // head: this wave's columns of each row (lane l holds columns
+    // 16 j + 4 (l / 16) .. + 3 of row l % 16), then over the four lanes of the row
+    const int fr = lane & 15, g4 = (lane >> 4) * 4;
+    float w4[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float s = 0.0f;
+        for (int r = 0; r < 4; ++r) w4[j][r] = (float)(__bf16)P[kOffW4 + 64 * w + 16 * j + g4 + r];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                s += (float)(__bf16)acc[i][j][r] * (float)(__bf16)P[kOffW4 + 64 * w + 16 * j + fr];
-            for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (fr == 0) ypart[w][16 * i + 4 * g + r] = s;
-        }
+    for (int i = 0; i < kFuseTiles; ++i) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s += (float)(__bf16)acc[i][j][r] * w4[j][r];
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (lane < 16) ypart[w][16 * i + fr] = s;
+    }
     __syncthreads();
     if (threadIdx.x < kFuseRows && r0 + threadIdx.x < n) {
         const int t = threadIdx.x;
@@ -595,7 +631,7 @@ static void train_step_t(float *P, float *adam, int64_t step, float lr, const fl
     hipLaunchKernelGGL(k_head<T>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, m.H3, P, R, m.yhat);
     hipLaunchKernelGGL(k_head_backward<T>, dim3((unsigned)(R / 64)), dim3(256), 0, st, m.yhat, y, n, R, m.Z3, m.H3, P,
                        m.dZ, m.dZt, m.Hpart);
-    hipLaunchKernelGGL(k_head_sums, dim3(1), dim3(256), 0, st, m.Hpart, (int)(R / 64), m.G, loss);
+    hipLaunchKernelGGL(k_head_sums, dim3((kHeadCols + 63) / 64), dim3(256), 0, st, m.Hpart, (int)(R / 64), m.G, loss);
     // layer 3: grad W3 = dZ3^T H2, grad b3, dH2 = dZ3 W3
     hipLaunchKernelGGL(k_transpose<T>, dim3(blocks_for(R * H)), dim3(256), 0, st, m.H2, R, H, m.Ht);
     gemm_nt_splitk<T>(m.dZt, (int)R, m.Ht, (int)R, H, H, (int)R, m.Gpart, m.G + kOffW3, st);
