@@ -649,9 +649,11 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     return GS_OK;
 }
 
-CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params *p, float share_floor, int quad_log) {
+CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params *p, float share_floor,
+                             const Setup &S) {
     CompositeArgs a{};
-    a.quad_log = quad_log;
+    a.quad_log = S.quad_log;
+    a.region_log = region_log_of(S.tsx, S.tsy);
     a.views = r.views_dev;
     a.tile_view = r.tile_view;
     a.tile_scene = r.tile_scene;
@@ -836,7 +838,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         entries += r.n_entries;
         n_bins += (int64_t)c.total_tiles * S.nchunks;
         sort_passes = std::max(sort_passes, r.passes);
-        CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor, S.quad_log);
+        CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor, S);
         a.ccount = r.host_slot.clist ? r.ccount : nullptr;
         if (r.quad_list) {
             // only the listed quadrants are composited: the other rays read A = 0
@@ -991,7 +993,7 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
         const ChunkPlan &c = chunks[ci];
         if ((s = run_front(scene, views, params, S, c, st, dev, hv, htv, r, tm, ms, true, nullptr)) != GS_OK)
             return s;
-        CompositeArgs a = composite_args(r, c.total_tiles, params, 0.0f, S.quad_log);
+        CompositeArgs a = composite_args(r, c.total_tiles, params, 0.0f, S);
         ObjectiveArgs o{weights, objective, per_ray, r.tile_sums, nullptr, 1e-9f};
         if (r.quad_list) {
             // only the listed quadrants are rendered: the chunk's other rays read 0
@@ -1503,6 +1505,7 @@ struct gs_plan {
     size_t pool_bytes = 0;
     gs_plan_config cfg{0, 1};
     int quad_log = 2 * kTileShiftDefault - 6;   // 8x8 quadrants per tile, log2
+    int region_log = 0;                          // pass-1 regions per tile, log2
     hipStream_t cap = nullptr;  // stream the sequence is captured on (the null stream cannot capture)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1613,6 +1616,7 @@ void enqueue_plan(gs_plan *P, hipStream_t st, float *const *sens) {
             a.work = P->cfg.persistent ? G.work : nullptr;
             a.xcd_remap = P->cfg.xcd_remap;
             a.quad_log = P->quad_log;
+            a.region_log = P->region_log;
             a.ccount = cb.compact ? G.ccount + ((size_t)cb.t0 << P->quad_log) : nullptr;
             a.report_floor = P->p.share_floor > 0.0f ? std::nextafter(P->p.share_floor, 0.0f) : 0.0f;
             launch_composite_pass1(a, st);
@@ -1818,6 +1822,7 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
     }
     P->p = *params;
     P->quad_log = tile_shift(params->tile_w) + tile_shift(params->tile_h) - 6;
+    P->region_log = region_log_of(tile_shift(params->tile_w), tile_shift(params->tile_h));
     P->scenes.resize(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
         PlanScene &ps = P->scenes[i];

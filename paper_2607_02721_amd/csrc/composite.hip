@@ -394,6 +394,163 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
     }
 }
 
+// Pass 1 over regions of up to 2 x 2 quadrants (one wave per region, region
+// r of a tile covering quadrant columns 2 rx + kx and rows 2 ry + ky, k =
+// kx + 2 ky): the wave reads the tile list once for its quadrants, gathers
+// each candidate's records once, tests it against each of its quadrants with
+// quad_hit and composites the four pixels of each lane (one per quadrant, at
+// the lane's position inside the quadrant).  Per quadrant everything is
+// k_pass1's: the sub-rectangle bit and the exact test on the mean taken
+// relative to the quadrant's origin in the same float operations, the
+// staged entries in list order, the pixel arithmetic, the stop at the same
+// 64-entry slice boundaries (a quadrant whose rays have all stopped takes
+// no further entries) and the compacted list, so the results are
+// bit-identical; what is shared is the list walk and the record loads.
+// One query per ray (kModeL1, kModeL2), one wave per region, no quadrant list.
+template <int kMode>
+__global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
+    static_assert(kMode != kModeChannel, "per-channel queries take k_pass1");
+    __shared__ float4 geo[kWave], col[kWave];
+    __shared__ float2 gxy1[kWave];    // means relative to the second quadrant column / row
+    __shared__ uint32_t hm[kWave];    // quadrants each staged entry reaches
+    const int lane = threadIdx.x;
+    const int nreg = a.total_tiles << a.region_log;
+    const int logical = a.xcd_remap ? xcd_remap(blockIdx.x, (nreg + 7) & ~7) : (int)blockIdx.x;
+    if (logical >= nreg) return;
+    const int gt = a.tile_first + (logical >> a.region_log);
+    const int rg = logical & ((1 << a.region_log) - 1);
+    const int v = a.tile_view[gt];
+    const SceneSlot &S = a.slots[a.tile_scene[gt]];
+    const ViewDev &V = a.views[v];
+    const int tl = gt - S.tile0 - V.tile_base;
+    const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
+    const int qlx = V.tsx - 3, qly = V.tsy - 3;            // log2 quadrant columns, rows per tile
+    const int rlx = qlx > 1 ? qlx - 1 : 0;                 // log2 region columns per tile
+    const int kxn = qlx > 0 ? 2 : 1, kyn = qly > 0 ? 2 : 1;
+    const int qxb = (rg & ((1 << rlx) - 1)) * kxn, qyb = (rg >> rlx) * kyn;
+    const int ox = (tx << V.tsx) + kQuad * qxb, oy = (ty << V.tsy) + kQuad * qyb;   // region origin
+    // per quadrant k: existence, sub-rectangle bit and index in the tile
+    uint32_t qbit[4];
+    int quad[4];
+    uint32_t valid = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int kx = k & 1, ky = k >> 1;
+        quad[k] = (qxb + kx) + ((qyb + ky) << qlx);
+        const bool ok = kx < kxn && ky < kyn && ox + kQuad * kx < V.W && oy + kQuad * ky < V.H;
+        qbit[k] = ok ? quad_subrect_bits(quad[k], V.tsx, V.tsy) << 28 : 0u;
+        valid |= ok ? (1u << k) : 0u;
+    }
+    if (!valid) return;
+    const int lx = lane & 7, ly = lane >> 3;
+    const float xl = (float)lx + 0.5f, yl = (float)ly + 0.5f;
+    const float fx0 = (float)ox, fx1 = (float)(ox + kQuad), fy0 = (float)oy, fy1 = (float)(oy + kQuad);
+    bool inside[4], scored[4], done[4];
+    int64_t ray_local[4];
+    float T[4], A[4];
+    uint32_t alive = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int px = ox + kQuad * (k & 1) + lx, py = oy + kQuad * (k >> 1) + ly;
+        inside[k] = ((valid >> k) & 1u) && px < V.W && py < V.H;
+        ray_local[k] = V.ray_local + (int64_t)py * V.W + px;
+        scored[k] = inside[k] && ray_selected(S.ray_mask, V.ray_base + (int64_t)py * V.W + px);
+        T[k] = 1.0f;
+        A[k] = 0.0f;
+        done[k] = !scored[k];
+        alive |= (((valid >> k) & 1u) && !__all(done[k])) ? (1u << k) : 0u;
+    }
+    const uint64_t start = S.tile_off[gt - S.tile0], end = S.tile_off[gt - S.tile0 + 1];
+    const int64_t vbase = (int64_t)(v - S.view0) * S.N;
+    const float cmax = __uint_as_float(S.cmax[v - S.view0]);
+    const float cut = a.r2_log2;
+    uint32_t *cl[4];
+    uint32_t ccnt[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        cl[k] = S.clist ? S.clist + ((start << a.quad_log) + (uint64_t)quad[k] * (end - start) - a.clist_shift)
+                        : nullptr;
+    const uint64_t lt = lanemask_lt64();
+    for (uint64_t e0 = start; e0 < end && alive; e0 += kWave) {
+        const uint64_t e = e0 + lane;
+        const uint32_t raw = e < end ? S.lists[e] : 0u;
+        uint32_t want = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) want |= ((alive >> k) & 1u) ? qbit[k] : 0u;
+        uint32_t h = 0u;
+        const uint32_t g = raw & kIndexMask;
+        const int64_t o = vbase + g;
+        float4 r1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float mx0 = 0.0f, my0 = 0.0f, mx1 = 0.0f, my1 = 0.0f;
+        if (raw & want) {
+            const float4 r0 = S.R0[o];
+            r1 = S.R1[o];
+            mx0 = (r0.x - fx0) + r0.z;
+            my0 = (r0.y - fy0) + r0.w;
+            mx1 = (r0.x - fx1) + r0.z;
+            my1 = (r0.y - fy1) + r0.w;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (((alive >> k) & 1u) && (raw & qbit[k]) &&
+                    quad_hit((k & 1) ? mx1 : mx0, (k >> 1) ? my1 : my0, r1.x, r1.y, r1.z, cut))
+                    h |= 1u << k;
+        }
+        const uint64_t bal = __ballot(h != 0u);
+        const int n = __popcll(bal);
+        if (h) {
+            const int slot = __popcll(bal & lt);
+            const float cb = S.R2[o].x;
+            const float la = __builtin_amdgcn_logf(r1.w);
+            geo[slot] = make_float4(mx0, my0, r1.x, r1.y);
+            gxy1[slot] = make_float2(mx1, my1);
+            col[slot] = make_float4(r1.z, la, cb, cut + la);
+            hm[slot] = h;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool mine = (h >> k) & 1u;
+            const uint64_t bk = __ballot(mine);
+            if (cl[k] && mine) __builtin_nontemporal_store(g, &cl[k][ccnt[k] + (uint32_t)__popcll(bk & lt)]);
+            ccnt[k] += (uint32_t)__popcll(bk);
+        }
+        wave_sync();
+        for (int j = 0; j < n; ++j) {
+            const float4 Gc = geo[j], Cc = col[j];
+            const float2 G1 = gxy1[j];
+            const uint32_t hj = __builtin_amdgcn_readfirstlane(hm[j]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((hj >> k) & 1u) {
+                    const float4 G = make_float4((k & 1) ? G1.x : Gc.x, (k >> 1) ? G1.y : Gc.y, Gc.z, Gc.w);
+                    bool in_fp;
+                    const float rho = pair_rho_log2(G, Cc, xl, yl, in_fp);
+                    if (kMode == kModeL1) {
+                        const float cr = Cc.z * rho;
+                        A[k] = fmaf(cr, T[k], A[k]);
+                    } else {
+                        const float rt = rho * T[k];
+                        A[k] = fmaf(Cc.z * rt, rt, A[k]);
+                    }
+                    T[k] = fmaf(-rho, T[k], T[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (kMode == kModeL1) done[k] = done[k] || (T[k] * cmax < a.share_floor * A[k]);
+            if (kMode == kModeL2) done[k] = done[k] || ((T[k] * T[k]) * cmax < a.share_floor * A[k]);
+            if (((alive >> k) & 1u) && __all(done[k])) alive &= ~(1u << k);
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (inside[k]) S.ray_A[ray_local[k]] = scored[k] ? A[k] : 0.0f;
+        if (((valid >> k) & 1u) && cl[k] && lane == 0)
+            a.ccount[((gt - a.tile_first) << a.quad_log) + quad[k]] = ccnt[k];
+    }
+}
+
 // Transposed butterfly over 64 lanes for 16 values: afterwards lane L holds
 // the maximum over all 64 lanes of value (L >> 2) & 15.  Each level pairs
 // every lane with a partner on the other side of one lane-index bit; the
@@ -655,6 +812,9 @@ static inline unsigned flat_grid(const CompositeArgs &a) {
     return (unsigned)(((a.total_tiles << a.quad_log) + 7) & ~7);
 }
 
+// The flat form of the one-query modes over every quadrant runs by regions
+// (k_pass1_region, bit-identical); ray-masked runs over a quadrant list, the
+// persistent form and per-channel queries run by quadrants.
 template <int kMode>
 static void pass1_mode(const CompositeArgs &a, hipStream_t st) {
     if constexpr (kMode != kModeChannel) {
@@ -662,6 +822,11 @@ static void pass1_mode(const CompositeArgs &a, hipStream_t st) {
             static const unsigned grid = resident_waves(k_pass1<true, kMode>);
             launch_fill_u32(a.work, 0u, 1, st);
             hipLaunchKernelGGL((k_pass1<true, kMode>), dim3(grid), dim3(kWave), 0, st, a);
+            return;
+        }
+        if (!a.quad_list) {
+            const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
+            hipLaunchKernelGGL((k_pass1_region<kMode>), dim3(grid), dim3(kWave), 0, st, a);
             return;
         }
     }

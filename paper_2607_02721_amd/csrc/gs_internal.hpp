@@ -44,6 +44,13 @@ struct ViewDev {
 // bits of quadrant q (row-major inside the tile) are the sub-rectangles it
 // overlaps: one for tiles of 16 or 32 pixels per side, both halves along a
 // side of 8 pixels.
+// Pass 1 walks each tile list once per region of up to 2 x 2 quadrants (16 x
+// 16 pixels; one quadrant column or row for tiles 8 pixels wide or tall):
+// log2 of the regions per tile.
+__host__ __device__ inline int region_log_of(int tsx, int tsy) {
+    return (tsx > 4 ? tsx - 4 : 0) + (tsy > 4 ? tsy - 4 : 0);
+}
+
 __host__ __device__ inline uint32_t quad_subrect_bits(int q, int tsx, int tsy) {
     const int qlx = tsx - 3, qly = tsy - 3;
     const int qx = q & ((1 << qlx) - 1), qy = q >> qlx;
@@ -230,6 +237,7 @@ struct CompositeArgs {
     int32_t total_tiles;         // tiles of this launch
     int32_t tile_first;          // launch tile t is tile tile_first + t of tile_view / tile_scene
     int32_t quad_log;            // log2 of the 8x8 quadrants per tile (every view of the launch has the same shape)
+    int32_t region_log;          // log2 of the pass-1 regions (up to 2x2 quadrants) per tile
     int32_t query_mode;
     float r2_log2;               // -0.5 log2(e) r^2  (cut on the exp2 argument)
     float share_floor;
