@@ -129,11 +129,14 @@ typedef struct {
      * may put it on different sides of the cutoff) is OR-ed; the caller
      * clears it.  NULL = not reported.  Must be NULL for other calls. */
     uint32_t *ambiguous_rays;
-    /* Binning tile of the pipeline, pixels: 8, 16 or 32 each (0 = 16).  Any
-     * shape gives the same sensitivities (the tile only decides which lists
-     * a Gaussian enters, never which pairs count); wider tiles mean fewer
-     * list entries per Gaussian and more rays per list.  GS_AGG_TILE
-     * queries need 16 x 16. */
+    /* Binning tile of the pipeline, pixels: 8, 16 or 32 each.  Any shape
+     * gives the same sensitivities (the tile only decides which lists a
+     * Gaussian enters, never which pairs count); wider tiles mean fewer list
+     * entries per Gaussian and more rays per list.  tile_w = tile_h = 0: the
+     * shape gs_tune_tile last chose in this process for the same size class
+     * (the largest view's pixel count and n, each rounded down to a power of
+     * two; for a plan, its largest view and scene), else 16 x 16; a single 0
+     * side stands for 16.  GS_AGG_TILE queries need 16 x 16 (0 gives it). */
     int32_t tile_w, tile_h;
 } gs_params;
 
@@ -350,8 +353,10 @@ gs_status gs_plan_set_config(gs_plan *plan, const gs_plan_config *config);
  * float[9], nullable) receives the mean time per call of each shape, or -1
  * for a shape the views cannot take (too many tiles per view) or the
  * parameters exclude (GS_AGG_TILE: 16 x 16 only); *best_w, *best_h the
- * fastest.  The shape changes the speed only: every shape gives the same
- * sensitivities.  Synchronises the stream. */
+ * fastest, which is also kept for the size class of these views and this
+ * scene (see gs_params.tile_w).  A calibration subset of the views may be
+ * passed: the class is that of the views given.  The shape changes the speed
+ * only: every shape gives the same sensitivities.  Synchronises the stream. */
 gs_status gs_tune_tile(const gs_scene *scene, const gs_views *views, const gs_params *params, int32_t reps,
                        float *sens, int32_t *best_w, int32_t *best_h, float *ms, void *stream);
 

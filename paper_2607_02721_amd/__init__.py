@@ -90,6 +90,10 @@ def _views(views):
 def _params(footprint_sigma, dilation, z_near, share_floor, query_mode, ray_mask,
             max_views_per_chunk, flags=0, aggregate=AGG_RAY, ambiguous_rays=None, tile=(16, 16)):
     p = _lib.default_params()
+    if isinstance(tile, str):
+        if tile != "auto":
+            raise ValueError("tile is (width, height) or 'auto'")
+        tile = (0, 0)
     p.tile_w, p.tile_h = int(tile[0]), int(tile[1])
     p.flags = flags
     p.aggregate = aggregate
@@ -120,7 +124,9 @@ def sensitivity(scene: DeviceScene, views, *, footprint_sigma=3.0, dilation=0.3,
     (pair counters need count_pairs=True, which can also OR the rays holding
     a pair within 1e-5 r^2 of the cutoff into the device bitset
     `ambiguous_rays`).  `tile` is the binning tile (width, height), each 8,
-    16 or 32 pixels: it changes the speed, not the result."""
+    16 or 32 pixels, or "auto" for the shape `tune_tile` last chose for
+    views and scenes of this size class: it changes the speed, not the
+    result."""
     torch = _torch()
     lib = load()
     hv = _views(views)

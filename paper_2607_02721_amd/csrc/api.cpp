@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -298,10 +299,42 @@ gs_status check_params(const gs_params *p) {
     return GS_OK;
 }
 
-// The binning tile of a call, from checked parameters.
-void setup_tiles(const gs_params *p, Setup &S) {
+// Tile shapes gs_tune_tile chose, by size class: (log2 of the largest
+// view's pixel count, log2 of N) -> (tsx, tsy).  Guarded by g_tile_lock.
+std::mutex g_tile_lock;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tile_cache;
+
+int log2_floor(int64_t x) {
+    int k = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+std::pair<int, int> size_class(const gs_views *v, int64_t n) {
+    int64_t px = 1;
+    if (v && v->size)
+        for (int i = 0; i < v->n_views; ++i)
+            px = std::max(px, (int64_t)std::max(v->size[2 * i], 1) * std::max(v->size[2 * i + 1], 1));
+    return {log2_floor(px), log2_floor(std::max<int64_t>(n, 1))};
+}
+
+// The binning tile of a call, from checked parameters: tile_w = tile_h = 0
+// takes the shape the tuner chose for this size class (16 x 16 if it has
+// not run for it, and for tile queries); a single 0 side stands for 16.
+void setup_tiles(const gs_params *p, Setup &S, const gs_views *v = nullptr, int64_t n = 0) {
     S.tsx = tile_shift(p->tile_w);
     S.tsy = tile_shift(p->tile_h);
+    if (p->tile_w == 0 && p->tile_h == 0 && p->aggregate != GS_AGG_TILE) {
+        std::lock_guard<std::mutex> lk(g_tile_lock);
+        const auto it = g_tile_cache.find(size_class(v, n));
+        if (it != g_tile_cache.end()) {
+            S.tsx = it->second.first;
+            S.tsy = it->second.second;
+        }
+    }
     S.quad_log = S.tsx + S.tsy - 6;
 }
 
@@ -794,7 +827,7 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     if ((s = check_scene(scene)) != GS_OK) return s;
     Setup S;
     if ((s = check_params(params)) != GS_OK) return s;
-    setup_tiles(params, S);
+    setup_tiles(params, S, views, scene->n);
     if ((s = check_views(views, S)) != GS_OK) return s;
     if (!sens) return fail(GS_ERR_INVALID_ARGUMENT, "sens is NULL");
     std::lock_guard<std::mutex> lk(g_lock);
@@ -963,7 +996,7 @@ gs_status gs_render_objective(const gs_scene *scene, const gs_views *views, cons
     if ((s = check_scene(scene)) != GS_OK) return s;
     Setup S;
     if ((s = check_params(params)) != GS_OK) return s;
-    setup_tiles(params, S);
+    setup_tiles(params, S, views, scene->n);
     if ((s = check_views(views, S)) != GS_OK) return s;
     if (objective != GS_OBJ_FULL && objective != GS_OBJ_FIXED && objective != GS_OBJ_TRUE)
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown objective %d", objective);
@@ -1821,12 +1854,31 @@ gs_status gs_plan_create(const gs_scene *scenes, const gs_views *views, int32_t 
         P->from = g_allocator;
     }
     P->p = *params;
-    P->quad_log = tile_shift(params->tile_w) + tile_shift(params->tile_h) - 6;
-    P->region_log = region_log_of(tile_shift(params->tile_w), tile_shift(params->tile_h));
+    // one binning tile for the whole plan (with tile_w = tile_h = 0, the
+    // tuner's choice for the plan's largest view and scene)
+    Setup T;
+    {
+        int64_t nmax = 1;
+        int big = 0;
+        int64_t pmax = 0;
+        for (int i = 0; i < n_scenes; ++i) {
+            nmax = std::max(nmax, scenes[i].n);
+            const auto c = size_class(&views[i], 1);
+            if (c.first >= pmax) {
+                pmax = c.first;
+                big = i;
+            }
+        }
+        setup_tiles(params, T, &views[big], nmax);
+    }
+    P->p.tile_w = 1 << T.tsx;
+    P->p.tile_h = 1 << T.tsy;
+    P->quad_log = T.quad_log;
+    P->region_log = region_log_of(T.tsx, T.tsy);
     P->scenes.resize(n_scenes);
     for (int i = 0; i < n_scenes; ++i) {
         PlanScene &ps = P->scenes[i];
-        setup_tiles(params, ps.S);
+        setup_tiles(&P->p, ps.S);
         if ((s = check_scene(&scenes[i])) != GS_OK || (s = check_views(&views[i], ps.S)) != GS_OK) {
             delete P;
             return s;
@@ -2034,6 +2086,10 @@ gs_status gs_tune_tile(const gs_scene *scene, const gs_views *views, const gs_pa
     if (best < 0) return fail(GS_ERR_UNSUPPORTED, "no tile shape fits these views");
     *best_w = sides[best / 3];
     *best_h = sides[best % 3];
+    if (params->aggregate != GS_AGG_TILE) {
+        std::lock_guard<std::mutex> lk(g_tile_lock);
+        g_tile_cache[size_class(views, scene->n)] = {tile_shift(*best_w), tile_shift(*best_h)};
+    }
     if (ms)
         for (int k = 0; k < 9; ++k) ms[k] = t[k];
     return GS_OK;

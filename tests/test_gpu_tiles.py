@@ -162,3 +162,30 @@ def test_shape_errors(gs, ragged, base16):
     big = synth.make_orbit_views(1, 3, 1920, 1080)
     with pytest.raises(gs.GsError, match="tiles of 8x8"):
         gs.sensitivity(d, big, tile=(8, 8))
+
+
+def test_auto_tile_takes_the_tuned_shape(gs):
+    """tile="auto" takes the shape the tuner chose for the same size class
+    (seen in the entry count, which depends on the shape), and 16x16 for a
+    size class it has not tuned; the sensitivities are the same."""
+    import torch
+    sc = synth.make_cluster_scene(30_000, 41, 1)
+    vw = synth.make_orbit_views(2, 42, 320, 240)
+    d = gs.DeviceScene.from_scene(sc)
+    best, _ = gs.tune_tile(d, vw, reps=1)
+    s_b, st_b = gs.sensitivity(d, vw, stats=True, tile=best)
+    s_a, st_a = gs.sensitivity(d, vw, stats=True, tile="auto")
+    assert st_a["n_entries"] == st_b["n_entries"]
+    assert torch.equal(s_a, s_b)
+    # another size class (4x the pixels): no tuned shape, so 16x16
+    vw2 = synth.make_orbit_views(2, 43, 640, 480)
+    _, st16 = gs.sensitivity(d, vw2, stats=True, tile=(16, 16))
+    _, st2 = gs.sensitivity(d, vw2, stats=True, tile="auto")
+    assert st2["n_entries"] == st16["n_entries"]
+    # a plan with tile "auto" takes the same shape
+    plan = gs.Plan([d], [vw], tile="auto")
+    out = plan.run()
+    torch.cuda.synchronize()
+    plan.status()
+    assert torch.equal(out[0], s_b)
+    plan.close()
