@@ -394,6 +394,14 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
     }
 }
 
+// An entry staged for a region: g = (mean x, y relative to the region's
+// first quadrant, beta, a'), c = (g', log2 alpha, colour sum, cut + log2
+// alpha), m1 = mean relative to the second quadrant column / row.
+struct __align__(16) RegionRec {
+    float4 g, c;
+    float2 m1, pad;
+};
+
 // Pass 1 over regions of up to 2 x 2 quadrants (one wave per region, region
 // r of a tile covering quadrant columns 2 rx + kx and rows 2 ry + ky, k =
 // kx + 2 ky): the wave reads the tile list once for its quadrants, gathers
@@ -410,9 +418,7 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
 template <int kMode>
 __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
     static_assert(kMode != kModeChannel, "per-channel queries take k_pass1");
-    __shared__ float4 geo[kWave], col[kWave];
-    __shared__ float2 gxy1[kWave];    // means relative to the second quadrant column / row
-    __shared__ uint32_t hm[kWave];    // quadrants each staged entry reaches
+    __shared__ RegionRec rec[kWave];
     const int lane = threadIdx.x;
     const int nreg = a.total_tiles << a.region_log;
     const int logical = a.xcd_remap ? xcd_remap(blockIdx.x, (nreg + 7) & ~7) : (int)blockIdx.x;
@@ -501,37 +507,55 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
             const int slot = __popcll(bal & lt);
             const float cb = S.R2[o].x;
             const float la = __builtin_amdgcn_logf(r1.w);
-            geo[slot] = make_float4(mx0, my0, r1.x, r1.y);
-            gxy1[slot] = make_float2(mx1, my1);
-            col[slot] = make_float4(r1.z, la, cb, cut + la);
-            hm[slot] = h;
+            RegionRec &q = rec[slot];
+            q.g = make_float4(mx0, my0, r1.x, r1.y);
+            q.c = make_float4(r1.z, la, cb, cut + la);
+            q.m1 = make_float2(mx1, my1);
         }
+        uint64_t bq[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const bool mine = (h >> k) & 1u;
-            const uint64_t bk = __ballot(mine);
-            if (cl[k] && mine) __builtin_nontemporal_store(g, &cl[k][ccnt[k] + (uint32_t)__popcll(bk & lt)]);
-            ccnt[k] += (uint32_t)__popcll(bk);
+            bq[k] = __ballot(mine);
+            if (cl[k] && mine) __builtin_nontemporal_store(g, &cl[k][ccnt[k] + (uint32_t)__popcll(bq[k] & lt)]);
+            ccnt[k] += (uint32_t)__popcll(bq[k]);
         }
         wave_sync();
-        for (int j = 0; j < n; ++j) {
-            const float4 Gc = geo[j], Cc = col[j];
-            const float2 G1 = gxy1[j];
-            const uint32_t hj = __builtin_amdgcn_readfirstlane(hm[j]);
+        // Slot j holds the entry of the j-th lane of bal in lane order; its
+        // quadrant bits are that lane's bits of bq[k] (scalar work only).  Two
+        // slots per iteration share one LDS address; a slot past n has no bits.
+        uint64_t rem = bal;
+        for (int j = 0; j < n; j += 2) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if ((hj >> k) & 1u) {
-                    const float4 G = make_float4((k & 1) ? G1.x : Gc.x, (k >> 1) ? G1.y : Gc.y, Gc.z, Gc.w);
-                    bool in_fp;
-                    const float rho = pair_rho_log2(G, Cc, xl, yl, in_fp);
-                    if (kMode == kModeL1) {
-                        const float cr = Cc.z * rho;
-                        A[k] = fmaf(cr, T[k], A[k]);
-                    } else {
-                        const float rt = rho * T[k];
-                        A[k] = fmaf(Cc.z * rt, rt, A[k]);
+            for (int u = 0; u < 2; ++u) {
+                const uint64_t lowbit = rem & (~rem + 1ull);
+                rem ^= lowbit;
+                const RegionRec &q = rec[j + u];
+                const float4 G = q.g, C = q.c;
+                const float2 M1 = q.m1;
+                // offsets from the mean per quadrant column and row and the
+                // row's part of the exponent, formed once for the quadrants
+                // that share them (the operations of pair_rho_log2)
+                const float dxq[2] = {xl - G.x, xl - M1.x};
+                const float dy0 = yl - G.y, dy1 = yl - M1.y;
+                const float dyq[2] = {dy0, dy1};
+                const float tq[2] = {fmaf(C.x, dy0 * dy0, C.y), fmaf(C.x, dy1 * dy1, C.y)};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (bq[k] & lowbit) {
+                        const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
+                        const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
+                        const float E = __builtin_amdgcn_exp2f(P);
+                        const float rho = P >= C.w ? E : 0.0f;
+                        if (kMode == kModeL1) {
+                            const float cr = C.z * rho;
+                            A[k] = fmaf(cr, T[k], A[k]);
+                        } else {
+                            const float rt = rho * T[k];
+                            A[k] = fmaf(C.z * rt, rt, A[k]);
+                        }
+                        T[k] = fmaf(-rho, T[k], T[k]);
                     }
-                    T[k] = fmaf(-rho, T[k], T[k]);
                 }
             }
         }

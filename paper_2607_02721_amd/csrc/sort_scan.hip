@@ -118,6 +118,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     __shared__ uint32_t wbase[4][256];   // block-local start of each wave's run of each digit
     __shared__ uint32_t dstart[256];     // block-local start of each digit
     __shared__ uint32_t gdst[256];       // global start of the block's run of each digit
+    __shared__ uint32_t wsum4[4];        // digit counts of each wave's 64 digits
     __shared__ uint32_t lkey[kSortTile], lval[kSortTile];
     const int seg = blockIdx.y, b = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -151,17 +152,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     {
         const int d = threadIdx.x;
         const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
-        dstart[d] = c0 + c1 + c2 + c3;
+        const uint32_t tot = c0 + c1 + c2 + c3;
         gdst[d] = offs[((int64_t)seg * 256 + d) * nb + b];
+        // digits 64w .. 64w+63 are wave w's lanes: a DPP scan per wave, then
+        // the sums of the waves before
+        const uint32_t incl = wave_incl_scan_u32(tot);
+        if (lane == 63) wsum4[w] = incl;
         __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const uint32_t x = d >= off ? dstart[d - off] : 0u;
-            __syncthreads();
-            dstart[d] += x;
-            __syncthreads();
-        }
-        const uint32_t start = dstart[d] - (c0 + c1 + c2 + c3);
-        __syncthreads();
+        uint32_t start = incl - tot;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) start += k < w ? wsum4[k] : 0u;
         dstart[d] = start;
         wbase[0][d] = start;
         wbase[1][d] = start + c0;
