@@ -397,10 +397,55 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
 // An entry staged for a region: g = (mean x, y relative to the region's
 // first quadrant, beta, a'), c = (g', log2 alpha, colour sum, cut + log2
 // alpha), m1 = mean relative to the second quadrant column / row.
+// Pass 2 adds the entry's staged sensitivity (raised to the report floor)
+// and its Gaussian index.
 struct __align__(16) RegionRec {
     float4 g, c;
-    float2 m1, pad;
+    float2 m1;
+    float sold;
+    uint32_t sid;
 };
+
+// Region `logical` of the launch: its tile, view, scene slot, origin and, per
+// quadrant k (column k & 1, row k >> 1), the quadrant's index in the tile,
+// its sub-rectangle bit and whether it exists (inside the view and the tile).
+struct RegionSetup {
+    int gt, v;
+    const SceneSlot *S;
+    const ViewDev *V;
+    int ox, oy;
+    int quad[4];
+    uint32_t qbit[4];
+    uint32_t valid;
+};
+
+__device__ __forceinline__ bool setup_region(const CompositeArgs &a, int logical, RegionSetup &r) {
+    r.gt = a.tile_first + (logical >> a.region_log);
+    const int rg = logical & ((1 << a.region_log) - 1);
+    r.v = a.tile_view[r.gt];
+    r.S = &a.slots[a.tile_scene[r.gt]];
+    r.V = &a.views[r.v];
+    const ViewDev &V = *r.V;
+    const int tl = r.gt - r.S->tile0 - V.tile_base;
+    const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
+    const int qlx = V.tsx - 3, qly = V.tsy - 3;            // log2 quadrant columns, rows per tile
+    const int rlx = qlx > 1 ? qlx - 1 : 0;                 // log2 region columns per tile
+    const int kxn = qlx > 0 ? 2 : 1, kyn = qly > 0 ? 2 : 1;
+    const int qxb = (rg & ((1 << rlx) - 1)) * kxn, qyb = (rg >> rlx) * kyn;
+    r.ox = (tx << V.tsx) + kQuad * qxb;
+    r.oy = (ty << V.tsy) + kQuad * qyb;
+    r.valid = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int kx = k & 1, ky = k >> 1;
+        r.quad[k] = (qxb + kx) + ((qyb + ky) << qlx);
+        const bool ok = kx < kxn && ky < kyn && r.ox + kQuad * kx < V.W && r.oy + kQuad * ky < V.H;
+        r.qbit[k] = ok ? quad_subrect_bits(r.quad[k], V.tsx, V.tsy) << 28 : 0u;
+        r.valid |= ok ? (1u << k) : 0u;
+    }
+    // quadrant 0 exists whenever any does (it holds the region's origin)
+    return r.valid != 0u;
+}
 
 // Pass 1 over regions of up to 2 x 2 quadrants (one wave per region, region
 // r of a tile covering quadrant columns 2 rx + kx and rows 2 ry + ky, k =
@@ -410,10 +455,14 @@ struct __align__(16) RegionRec {
 // the lane's position inside the quadrant).  Per quadrant everything is
 // k_pass1's: the sub-rectangle bit and the exact test on the mean taken
 // relative to the quadrant's origin in the same float operations, the
-// staged entries in list order, the pixel arithmetic, the stop at the same
-// 64-entry slice boundaries (a quadrant whose rays have all stopped takes
-// no further entries) and the compacted list, so the results are
-// bit-identical; what is shared is the list walk and the record loads.
+// staged entries in list order, the pixel arithmetic and the stop at the
+// same 64-entry slice boundaries (a quadrant whose rays have all stopped
+// takes no further entries), so the results are bit-identical; what is
+// shared is the list walk and the record loads.  Instead of one compacted
+// list per quadrant the wave leaves one per region: the Gaussian index of
+// every entry that reaches one of its quadrants, with the quadrant bits in
+// the top four bits (per quadrant, exactly the entries of its compacted
+// list), for k_pass2_region.
 // One query per ray (kModeL1, kModeL2), one wave per region, no quadrant list.
 template <int kMode>
 __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
@@ -423,31 +472,12 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
     const int nreg = a.total_tiles << a.region_log;
     const int logical = a.xcd_remap ? xcd_remap(blockIdx.x, (nreg + 7) & ~7) : (int)blockIdx.x;
     if (logical >= nreg) return;
-    const int gt = a.tile_first + (logical >> a.region_log);
-    const int rg = logical & ((1 << a.region_log) - 1);
-    const int v = a.tile_view[gt];
-    const SceneSlot &S = a.slots[a.tile_scene[gt]];
-    const ViewDev &V = a.views[v];
-    const int tl = gt - S.tile0 - V.tile_base;
-    const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
-    const int qlx = V.tsx - 3, qly = V.tsy - 3;            // log2 quadrant columns, rows per tile
-    const int rlx = qlx > 1 ? qlx - 1 : 0;                 // log2 region columns per tile
-    const int kxn = qlx > 0 ? 2 : 1, kyn = qly > 0 ? 2 : 1;
-    const int qxb = (rg & ((1 << rlx) - 1)) * kxn, qyb = (rg >> rlx) * kyn;
-    const int ox = (tx << V.tsx) + kQuad * qxb, oy = (ty << V.tsy) + kQuad * qyb;   // region origin
-    // per quadrant k: existence, sub-rectangle bit and index in the tile
-    uint32_t qbit[4];
-    int quad[4];
-    uint32_t valid = 0u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int kx = k & 1, ky = k >> 1;
-        quad[k] = (qxb + kx) + ((qyb + ky) << qlx);
-        const bool ok = kx < kxn && ky < kyn && ox + kQuad * kx < V.W && oy + kQuad * ky < V.H;
-        qbit[k] = ok ? quad_subrect_bits(quad[k], V.tsx, V.tsy) << 28 : 0u;
-        valid |= ok ? (1u << k) : 0u;
-    }
-    if (!valid) return;
+    RegionSetup R;
+    if (!setup_region(a, logical, R)) return;
+    const int gt = R.gt, v = R.v, ox = R.ox, oy = R.oy;
+    const uint32_t valid = R.valid;
+    const SceneSlot &S = *R.S;
+    const ViewDev &V = *R.V;
     const int lx = lane & 7, ly = lane >> 3;
     const float xl = (float)lx + 0.5f, yl = (float)ly + 0.5f;
     const float fx0 = (float)ox, fx1 = (float)(ox + kQuad), fy0 = (float)oy, fy1 = (float)(oy + kQuad);
@@ -470,19 +500,18 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
     const int64_t vbase = (int64_t)(v - S.view0) * S.N;
     const float cmax = __uint_as_float(S.cmax[v - S.view0]);
     const float cut = a.r2_log2;
-    uint32_t *cl[4];
-    uint32_t ccnt[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        cl[k] = S.clist ? S.clist + ((start << a.quad_log) + (uint64_t)quad[k] * (end - start) - a.clist_shift)
-                        : nullptr;
+    // the region's list: entries that reach one of its quadrants, each with
+    // its quadrant bits (in the slots of quadrant 0's compacted list)
+    uint32_t *cl = S.clist ? S.clist + ((start << a.quad_log) + (uint64_t)R.quad[0] * (end - start) - a.clist_shift)
+                           : nullptr;
+    uint32_t ccnt = 0u;
     const uint64_t lt = lanemask_lt64();
     for (uint64_t e0 = start; e0 < end && alive; e0 += kWave) {
         const uint64_t e = e0 + lane;
         const uint32_t raw = e < end ? S.lists[e] : 0u;
         uint32_t want = 0u;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) want |= ((alive >> k) & 1u) ? qbit[k] : 0u;
+        for (int k = 0; k < 4; ++k) want |= ((alive >> k) & 1u) ? R.qbit[k] : 0u;
         uint32_t h = 0u;
         const uint32_t g = raw & kIndexMask;
         const int64_t o = vbase + g;
@@ -497,7 +526,7 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
             my1 = (r0.y - fy1) + r0.w;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (((alive >> k) & 1u) && (raw & qbit[k]) &&
+                if (((alive >> k) & 1u) && (raw & R.qbit[k]) &&
                     quad_hit((k & 1) ? mx1 : mx0, (k >> 1) ? my1 : my0, r1.x, r1.y, r1.z, cut))
                     h |= 1u << k;
         }
@@ -512,14 +541,11 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
             q.c = make_float4(r1.z, la, cb, cut + la);
             q.m1 = make_float2(mx1, my1);
         }
+        if (cl && h) __builtin_nontemporal_store(g | (h << 28), &cl[ccnt + (uint32_t)__popcll(bal & lt)]);
+        ccnt += (uint32_t)n;
         uint64_t bq[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool mine = (h >> k) & 1u;
-            bq[k] = __ballot(mine);
-            if (cl[k] && mine) __builtin_nontemporal_store(g, &cl[k][ccnt[k] + (uint32_t)__popcll(bq[k] & lt)]);
-            ccnt[k] += (uint32_t)__popcll(bq[k]);
-        }
+        for (int k = 0; k < 4; ++k) bq[k] = __ballot((h >> k) & 1u);
         wave_sync();
         // Slot j holds the entry of the j-th lane of bal in lane order; its
         // quadrant bits are that lane's bits of bq[k] (scalar work only).  Two
@@ -570,9 +596,8 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (inside[k]) S.ray_A[ray_local[k]] = scored[k] ? A[k] : 0.0f;
-        if (((valid >> k) & 1u) && cl[k] && lane == 0)
-            a.ccount[((gt - a.tile_first) << a.quad_log) + quad[k]] = ccnt[k];
     }
+    if (cl && lane == 0) a.ccount[((gt - a.tile_first) << a.quad_log) + R.quad[0]] = ccnt;
 }
 
 // Transposed butterfly over 64 lanes for 16 values: afterwards lane L holds
@@ -815,6 +840,182 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
     }
 }
 
+// Pass 2 over regions of up to 2 x 2 quadrants, on the region lists that
+// k_pass1_region leaves.  Per quadrant the wave takes the entries of its
+// compacted list in the same order, with the same pixel arithmetic and the
+// same shares as k_pass2; a quadrant whose rays have all stopped (tested at
+// 64-entry slices of the region list) takes no further entries, which
+// changes nothing that is reported (no share after a ray's stop reaches the
+// share floor).  What is shared: each entry's record loads and staging, the
+// offsets and row terms of the quadrants' pixels, and the reduction: a
+// lane's shares of its four pixels are maximised first (integer maxima of
+// the bit patterns of non-negative floats), then one transposed butterfly
+// and at most one atomic per entry instead of one per (quadrant, entry).
+template <bool kStats, int kMode>
+__global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(CompositeArgs a,
+                                                                         uint64_t *__restrict__ counters) {
+    static_assert(kMode != kModeChannel, "per-channel queries take k_pass2");
+    __shared__ RegionRec rec[kWave];
+    const int lane = threadIdx.x;
+    const int nreg = a.total_tiles << a.region_log;
+    const int logical = a.xcd_remap ? xcd_remap(blockIdx.x, (nreg + 7) & ~7) : (int)blockIdx.x;
+    if (logical >= nreg) return;
+    RegionSetup R;
+    if (!setup_region(a, logical, R)) return;
+    const int gt = R.gt, v = R.v, ox = R.ox, oy = R.oy;
+    const SceneSlot &S = *R.S;
+    const ViewDev &V = *R.V;
+    const int lx = lane & 7, ly = lane >> 3;
+    const float xl = (float)lx + 0.5f, yl = (float)ly + 0.5f;
+    const float fx0 = (float)ox, fx1 = (float)(ox + kQuad), fy0 = (float)oy, fy1 = (float)(oy + kQuad);
+    // per quadrant: the running transmittance scaled as in k_pass2 (by 1/A
+    // for L1, 1/sqrt(A) for L2), the stop bar and whether the ray counts
+    float T[4], live_bar[4];
+    bool done[4], positive[4];
+    int64_t ray_global[4];
+    uint32_t alive = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int px = ox + kQuad * (k & 1) + lx, py = oy + kQuad * (k >> 1) + ly;
+        const bool inside = ((R.valid >> k) & 1u) && px < V.W && py < V.H;
+        ray_global[k] = V.ray_base + (int64_t)py * V.W + px;
+        const bool scored = inside && ray_selected(S.ray_mask, ray_global[k]);
+        const float Af = scored ? S.ray_A[V.ray_local + (int64_t)py * V.W + px] : 0.0f;
+        const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
+        positive[k] = invA > 0.0f;
+        T[k] = kMode == kModeL2 ? sqrtf(invA) : invA;
+        live_bar[k] = a.share_floor * (Af * invA);
+        done[k] = !positive[k];
+        alive |= (((R.valid >> k) & 1u) && !__all(done[k])) ? (1u << k) : 0u;
+    }
+    const uint64_t start = S.tile_off[gt - S.tile0], end = S.tile_off[gt - S.tile0 + 1];
+    const uint32_t *__restrict__ cl =
+        S.clist + ((start << a.quad_log) + (uint64_t)R.quad[0] * (end - start) - a.clist_shift);
+    const uint32_t count = a.ccount[((gt - a.tile_first) << a.quad_log) + R.quad[0]];
+    const int64_t vbase = (int64_t)(v - S.view0) * S.N;
+    const float cmax = __uint_as_float(S.cmax[v - S.view0]);
+    const float cut = a.r2_log2;
+    const float amb_band = kAmbiguityBeta * fabsf(a.r2_log2);
+    uint32_t *sens_bits = S.sens_bits;
+    uint32_t n_in = 0, n_live = 0, n_amb = 0, amb = 0u;   // amb: quadrants whose ray saw an ambiguous pair
+    uint64_t n_eval = 0;
+    const uint64_t lt = lanemask_lt64();
+    for (uint32_t e0 = 0; e0 < count && alive; e0 += kWave) {
+        const uint32_t e = e0 + lane;
+        const uint32_t raw = e < count ? cl[e] : 0u;
+        const uint32_t h = (raw >> 28) & alive;
+        const uint64_t bal = __ballot(h != 0u);
+        const int n = __popcll(bal);
+        if (h) {
+            const uint32_t g = raw & kIndexMask;
+            const int64_t o = vbase + g;
+            const float4 r0 = S.R0[o];
+            const float4 r1 = S.R1[o];
+            const float cb = S.R2[o].x;
+            const float la = __builtin_amdgcn_logf(r1.w);
+            RegionRec &q = rec[__popcll(bal & lt)];
+            q.g = make_float4((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);
+            q.c = make_float4(r1.z, la, cb, cut + la);
+            q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
+            q.sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
+            q.sid = g;
+        }
+        uint64_t bq[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bq[k] = __ballot((h >> k) & 1u);
+        if (kStats) n_eval += (uint64_t)(__popcll(bq[0]) + __popcll(bq[1]) + __popcll(bq[2]) + __popcll(bq[3]));
+        wave_sync();
+        // slot j: the j-th lane of bal, its quadrant bits in bq[k]
+        uint64_t rem = bal;
+        for (int jb = 0; jb < n; jb += 16) {
+            float sh[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint64_t lowbit = rem & (~rem + 1ull);
+                rem ^= lowbit;
+                uint32_t m = 0u;
+                if (lowbit) {
+                    const RegionRec &q = rec[jb + i];
+                    const float4 G = q.g, C = q.c;
+                    const float2 M1 = q.m1;
+                    const float dxq[2] = {xl - G.x, xl - M1.x};
+                    const float dy0 = yl - G.y, dy1 = yl - M1.y;
+                    const float dyq[2] = {dy0, dy1};
+                    const float tq[2] = {fmaf(C.x, dy0 * dy0, C.y), fmaf(C.x, dy1 * dy1, C.y)};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (bq[k] & lowbit) {
+                            const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
+                            const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
+                            const float E = __builtin_amdgcn_exp2f(P);
+                            const bool in_fp = P >= C.w;
+                            const float rho = in_fp ? E : 0.0f;
+                            float share;
+                            if (kMode == kModeL1) {
+                                share = (C.z * rho) * T[k];
+                            } else {
+                                const float rt = rho * T[k];
+                                share = (C.z * rt) * rt;
+                            }
+                            m = umax32(m, __float_as_uint(share));
+                            if (kStats) {
+                                const float later = kMode == kModeL2 ? (T[k] * T[k]) * cmax : T[k] * cmax;
+                                n_in += (positive[k] && in_fp) ? 1u : 0u;
+                                n_live += (positive[k] && in_fp && later >= live_bar[k]) ? 1u : 0u;
+                                const bool am = positive[k] && fabsf(P - C.w) <= amb_band;
+                                n_amb += am ? 1u : 0u;
+                                amb |= am ? (1u << k) : 0u;
+                            }
+                            T[k] = fmaf(-rho, T[k], T[k]);
+                        }
+                    }
+                }
+                sh[i] = __uint_as_float(m);
+            }
+            // the reduction only if some pixel beats its entry's staged
+            // sensitivity (slots past n hold share 0, which beats none)
+            uint64_t beat = 0ull;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > rec[jb + i].sold);
+            if (beat != 0ull) {
+                const float mx = wave_transpose_max16(sh);
+                const int j = jb + (lane >> 2);
+                if ((lane & 3) == 0 && j < n && mx > rec[j].sold) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(mx));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float later = kMode == kModeL2 ? (T[k] * T[k]) * cmax : T[k] * cmax;
+            done[k] = done[k] || (later < live_bar[k]);
+            if (((alive >> k) & 1u) && __all(done[k])) alive &= ~(1u << k);
+        }
+        wave_sync();
+    }
+    if (kStats) {
+        uint64_t pin = n_in, plive = n_live, pos = 0, pamb = n_amb;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pos += positive[k] ? 1u : 0u;
+            if (((amb >> k) & 1u) && a.amb_rays)
+                atomicOr(&a.amb_rays[ray_global[k] >> 5], 1u << (uint32_t)(ray_global[k] & 31));
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            pin += __shfl_xor(pin, off);
+            plive += __shfl_xor(plive, off);
+            pos += __shfl_xor(pos, off);
+            pamb += __shfl_xor(pamb, off);
+        }
+        if (lane == 0) {
+            unsigned long long *c = (unsigned long long *)counters + CNT_SLOTS + (blockIdx.x % kCntSpread);
+            atomicAdd(c + 0 * kCntSpread, (unsigned long long)pin);
+            atomicAdd(c + 1 * kCntSpread, (unsigned long long)plive);
+            atomicAdd(c + 2 * kCntSpread, (unsigned long long)pos);
+            atomicAdd(c + 3 * kCntSpread, (unsigned long long)n_eval * 64ull);
+            if (pamb) atomicAdd(c + 4 * kCntSpread, (unsigned long long)pamb);
+        }
+    }
+}
+
 // Flat form: one wave per quadrant (rounded up to a multiple of 8 for the XCD
 // remap).  Persistent form: as many waves as the chip holds at once for the
 // kernel (its occupancy times the CU count), taking quadrants from a counter.
@@ -906,8 +1107,21 @@ static void pass2_ray(const CompositeArgs &a, bool stats, uint64_t *counters, hi
     }
 }
 
+// With compaction, pass 2 takes the form pass 1 took: the region form
+// (flat one-query launches with no quadrant list) reads the region lists,
+// the others the quadrant lists.
 template <int kMode, bool kPersistentForm>
 static void pass2_ray_any(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
+    if constexpr (kMode != kModeChannel) {
+        if (a.ccount && !a.work && !a.quad_list) {
+            const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
+            if (stats)
+                hipLaunchKernelGGL((k_pass2_region<true, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+            else
+                hipLaunchKernelGGL((k_pass2_region<false, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+            return;
+        }
+    }
     if (a.ccount)
         pass2_ray<kMode, kPersistentForm, true>(a, stats, counters, st);
     else

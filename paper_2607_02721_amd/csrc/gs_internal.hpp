@@ -215,8 +215,12 @@ struct SceneSlot {
     // (the Gaussian indices, in list order, up to where the quadrant's rays
     // stopped): quadrant q of a tile with list [start, end) and Q = 2^quad_log
     // quadrants owns [Q start + q (end - start), Q start + (q + 1)(end - start)).  Pass 2
-    // walks these dense lists.  Null: no compaction (pass 2 filters the tile
-    // lists again).  Both give the same sensitivities (pass 2 reports no
+    // walks these dense lists.  The region form of pass 1 (2 x 2 quadrants
+    // per wave) leaves one list per region instead, in the slots of the
+    // region's first quadrant: each entry that reaches one of the region's
+    // quadrants, as its Gaussian index with those quadrants' bits in the top
+    // four bits; the region form of pass 2 walks it.  Null: no compaction
+    // (pass 2 filters the tile lists again).  Both give the same sensitivities (pass 2 reports no
     // share below the share floor, and every pair before a ray's stop is
     // walked either way).
     uint32_t *clist;
@@ -246,7 +250,8 @@ struct CompositeArgs {
     int32_t agg;                 // query granularity (gs_aggregate) of pass 2
     const double *query_A;       // agg 1: A per tile of the launch; 2: per view; 3: [0] the launch's total
     uint64_t *acc;               // agg 1: per list entry; 2: per (view, Gaussian); 3: per Gaussian (fixed point)
-    uint32_t *ccount;            // [quadrants] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist)
+    uint32_t *ccount;            // [quadrants] entries pass 1 compacted per quadrant of the launch (with SceneSlot::clist;
+                                 // the region form: per region, at the region's first quadrant)
     uint64_t clist_shift;        // subtracted from every compacted-list offset (launches over a tile range
                                  // whose compacted lists fill a pool from its start)
     const uint32_t *quad_list;   // ray-masked runs: the quadrants ((tile << quad_log) + q) holding a selected ray,
