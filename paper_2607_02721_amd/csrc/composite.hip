@@ -397,13 +397,15 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
 // An entry staged for a region: g = (mean x, y relative to the region's
 // first quadrant, beta, a'), c = (g', log2 alpha, colour sum, cut + log2
 // alpha), m1 = mean relative to the second quadrant column / row.
-// Pass 2 adds the entry's staged sensitivity (raised to the report floor)
-// and its Gaussian index.
+// Pass 2 adds the entry's staged sensitivity (raised to the report floor),
+// its Gaussian index and the bar below which a pixel's rho T (L1) or
+// (rho T)^2 (L2) cannot give a share above the staged sensitivity.
 struct __align__(16) RegionRec {
     float4 g, c;
     float2 m1;
     float sold;
     uint32_t sid;
+    float bar, pad[3];
 };
 
 // Region `logical` of the launch: its tile, view, scene slot, origin and, per
@@ -755,10 +757,10 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                             const float rho = kCh ? pair_rho(G, Cc, w.xl, w.yl, a.r2_log2, in_fp)
                                                   : pair_rho_log2(G, Cc, w.xl, w.yl, in_fp);
                             if (kMode == kModeL1) {
-                                sh[k0 + q] = (Cc.z * rho) * T;
+                                sh[k0 + q] = Cc.z * (rho * T);
                             } else if (kMode == kModeL2) {
                                 const float rt = rho * T;
-                                sh[k0 + q] = (Cc.z * rt) * rt;
+                                sh[k0 + q] = Cc.z * (rt * rt);
                             } else {
                                 const float rt = rho * T;
                                 sh[k0 + q] = rt * fmaxf(Cc.z * invA, fmaxf(Cc.w * invG, cblue[j] * invB));
@@ -795,7 +797,8 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
 #pragma unroll
                     for (int k = 0; k < 16; ++k) beat |= __ballot(sh[k] > sold[jb + k]);
                     if (beat != 0ull) {
-                        const float m = wave_transpose_max16(sh);
+                        // (a share cannot exceed 1; its rounding can, by an ulp or two)
+                        const float m = fminf(wave_transpose_max16(sh), 1.0f);
                         if ((lane & 3) == 0 && j < n && m > sold[j])
                             atomicMax(&sens_bits[sid[j]], __float_as_uint(m));
                     }
@@ -848,9 +851,11 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
 // changes nothing that is reported (no share after a ray's stop reaches the
 // share floor).  What is shared: each entry's record loads and staging, the
 // offsets and row terms of the quadrants' pixels, and the reduction: a
-// lane's shares of its four pixels are maximised first (integer maxima of
+// lane's values of its four pixels are maximised first (integer maxima of
 // the bit patterns of non-negative floats), then one transposed butterfly
 // and at most one atomic per entry instead of one per (quadrant, entry).
+// The value reduced is x = rho T (L1) or (rho T)^2 (L2), of which the share
+// is c x: one product per entry instead of one per pair.
 template <bool kStats, int kMode>
 __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(CompositeArgs a,
                                                                          uint64_t *__restrict__ counters) {
@@ -917,8 +922,13 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             q.g = make_float4((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);
             q.c = make_float4(r1.z, la, cb, cut + la);
             q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
-            q.sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
+            const float sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
+            q.sold = sold;
             q.sid = g;
+            // c x > sold implies x > sold / (c (1 + 2^-24)); the bar sits below
+            // that by more than the rounding of v_rcp_f32 and the products
+            // (and is 0, which lets every positive x through, for tiny c)
+            q.bar = (sold > 0.0f && cb >= 0x1p-100f) ? (sold * __builtin_amdgcn_rcpf(cb)) * 0.99999905f : 0.0f;
         }
         uint64_t bq[4];
 #pragma unroll
@@ -950,14 +960,12 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                             const float E = __builtin_amdgcn_exp2f(P);
                             const bool in_fp = P >= C.w;
                             const float rho = in_fp ? E : 0.0f;
-                            float share;
-                            if (kMode == kModeL1) {
-                                share = (C.z * rho) * T[k];
-                            } else {
-                                const float rt = rho * T[k];
-                                share = (C.z * rt) * rt;
-                            }
-                            m = umax32(m, __float_as_uint(share));
+                            // the share is c x, and c x is monotone in x:
+                            // the entry's largest share is c times its
+                            // largest x (rounding is monotone too)
+                            const float rt = rho * T[k];
+                            const float x = kMode == kModeL1 ? rt : rt * rt;
+                            m = umax32(m, __float_as_uint(x));
                             if (kStats) {
                                 const float later = kMode == kModeL2 ? (T[k] * T[k]) * cmax : T[k] * cmax;
                                 n_in += (positive[k] && in_fp) ? 1u : 0u;
@@ -976,11 +984,15 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             // sensitivity (slots past n hold share 0, which beats none)
             uint64_t beat = 0ull;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > rec[jb + i].sold);
+            for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > rec[jb + i].bar);
             if (beat != 0ull) {
                 const float mx = wave_transpose_max16(sh);
                 const int j = jb + (lane >> 2);
-                if ((lane & 3) == 0 && j < n && mx > rec[j].sold) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(mx));
+                if ((lane & 3) == 0 && j < n) {
+                    // (a share cannot exceed 1; its rounding can, by an ulp or two)
+                    const float share = fminf(rec[j].c.z * mx, 1.0f);
+                    if (share > rec[j].sold) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(share));
+                }
             }
         }
 #pragma unroll
