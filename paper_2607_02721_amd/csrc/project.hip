@@ -206,6 +206,12 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
                 const double dn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
                 double Y[16];
                 sh_basis(d0 * dn, d1 * dn, d2 * dn, Y);
+                // the coefficients stay float32 in registers and are widened
+                // here, per view (widened once outside the loop, their FP64
+                // copies take 96 registers instead of 48 and the kernel holds
+                // two waves per SIMD instead of three)
+#pragma unroll
+                for (int k = 0; k < 3 * K; ++k) asm volatile("" : "+v"(shc[k]));
                 double c[3];
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
