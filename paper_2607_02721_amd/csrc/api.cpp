@@ -162,14 +162,13 @@ int chunk_max_rows(const Setup &S, const ChunkPlan &c) {
 
 size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     const int64_t N = S.N;
-    const int64_t nb = (N + kSortTile - 1) / kSortTile;
     const int64_t nbins = (int64_t)c.total_tiles * S.nchunks;
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
     add(3 * sizeof(float4) * (size_t)c.vc * N);      // records
     if (S.nq > 1) add(sizeof(float4) * (size_t)c.vc * N);   // channel colours
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)c.vc * N);
-    add(sizeof(uint32_t) * (size_t)c.vc * 256 * nb);
+    add(sizeof(uint32_t) * (size_t)radix_sort_scratch_words(N, c.vc));
     add(4 * sizeof(uint32_t) * (size_t)c.vc);
     add(4 * sizeof(uint32_t) * (size_t)c.vc * proj_blocks(N));
     add(sizeof(uint32_t) * nbins);
@@ -455,8 +454,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     b.val0 = cv.take<uint32_t>((size_t)c.vc * N);
     b.key1 = cv.take<uint32_t>((size_t)c.vc * N);
     b.val1 = cv.take<uint32_t>((size_t)c.vc * N);
-    const int64_t nb = (N + kSortTile - 1) / kSortTile;
-    b.hist = cv.take<uint32_t>((size_t)c.vc * 256 * nb);
+    b.hist = cv.take<uint32_t>((size_t)radix_sort_scratch_words(N, c.vc));
     b.nvis = cv.take<uint32_t>(4 * (size_t)c.vc);
     b.cmax = b.nvis + c.vc;
     b.kmin = b.nvis + 2 * c.vc;
@@ -1551,12 +1549,11 @@ namespace {
 
 size_t scene_buffer_bytes(const PlanScene &ps) {
     const int64_t N = ps.S.N;
-    const int64_t nb = (N + kSortTile - 1) / kSortTile;
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
     add(3 * sizeof(float4) * (size_t)ps.c.vc * N);
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)ps.c.vc * N);
-    add(sizeof(uint32_t) * (size_t)ps.c.vc * 256 * nb);
+    add(sizeof(uint32_t) * (size_t)radix_sort_scratch_words(N, ps.c.vc));
     add(4 * sizeof(uint32_t) * (size_t)ps.c.vc);
     add(4 * sizeof(uint32_t) * (size_t)ps.c.vc * proj_blocks(N));
     add(sizeof(uint32_t) * ps.nbins);
@@ -1572,7 +1569,6 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
 
 void carve_scene(PlanScene &ps, Carve &cv) {
     const int64_t N = ps.S.N;
-    const int64_t nb = (N + kSortTile - 1) / kSortTile;
     ChunkBufs &b = ps.b;
     b.R0 = cv.take<float4>((size_t)ps.c.vc * N);
     b.R1 = cv.take<float4>((size_t)ps.c.vc * N);
@@ -1581,7 +1577,7 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     b.val0 = cv.take<uint32_t>((size_t)ps.c.vc * N);
     b.key1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
     b.val1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
-    b.hist = cv.take<uint32_t>((size_t)ps.c.vc * 256 * nb);
+    b.hist = cv.take<uint32_t>((size_t)radix_sort_scratch_words(N, ps.c.vc));
     b.nvis = cv.take<uint32_t>(4 * (size_t)ps.c.vc);
     b.cmax = b.nvis + ps.c.vc;
     b.kmin = b.nvis + 2 * ps.c.vc;

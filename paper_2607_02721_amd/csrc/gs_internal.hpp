@@ -145,11 +145,14 @@ void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const 
 // subtracts kbase[seg] from every key but kInvisibleKey (the result must stay
 // below 2^(8 passes) - 1 for the visible keys, so that invisible keys still
 // sort last).  seg_len (device, nullable): only the first seg_len[seg] items
-// of each segment are sorted (the rest are left alone).
+// of each segment are sorted (the rest are left alone).  Only the values
+// leave the last pass: *key_out is null and *val_out holds them.  hist is
+// scratch of radix_sort_scratch_words(n_per_seg, n_segs) words.
 hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, uint32_t *val1,
                                uint32_t *hist, int64_t n_per_seg, int n_segs, bool vals_are_iota,
                                int passes, const uint32_t *kbase, const uint32_t *seg_len, uint32_t **key_out,
                                uint32_t **val_out, hipStream_t st);
+int64_t radix_sort_scratch_words(int64_t n_per_seg, int n_segs);
 // The kept depth keys of each view, moved to the front of the view's segment
 // of kout in index order with their Gaussian indices in vout (after
 // launch_project, whose per-block counts it turns into offsets).

@@ -4,13 +4,16 @@
 // Radix sort: each of n_segs segments of n_per_seg items (one segment per
 // view) is sorted independently and stably by key, 8 bits per pass, 3 or 4
 // passes (3 when every segment's keys, minus the segment's smallest, fit in
-// 24 bits).  Blocks never straddle segments.  Per pass:
-//   hist:    per block, per digit counts -> hist[seg][digit][block]
-//   offsets: per segment exclusive scan of hist in (digit, block) order
+// 24 bits).  Blocks never straddle segments.  Once, before the passes:
+//   hist_all:   every pass's digit counts per segment (one read of the keys)
+//   digit_base: per segment and pass, exclusive scan of the digit counts
+// Per pass:
 //   scatter: each wave ranks its 1024 keys in 16 rounds of 64 with ballot
 //            matching (wave-private LDS digit counters, so no block barrier
 //            inside the rounds); waves then add the counts of the waves
-//            before them, which keeps the sort stable.
+//            before them, which keeps the sort stable; the block's start in
+//            each digit's run is the digit base plus the counts of the
+//            segment's earlier blocks, found by decoupled look-back.
 #include "gs_internal.hpp"
 
 namespace gs {
@@ -40,33 +43,7 @@ __device__ __forceinline__ uint32_t rebase(uint32_t k, const uint32_t *kbase, in
     return (kbase && k != kInvisibleKey) ? k - kbase[seg] : k;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_per_seg,
-                                                              int nb, int shift, uint32_t *__restrict__ hist,
-                                                              const uint32_t *__restrict__ kbase,
-                                                              const uint32_t *__restrict__ seg_len) {
-    __shared__ uint32_t cnt[4][256];
-    const int seg = blockIdx.y, b = blockIdx.x;
-    const int w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&cnt[0][0])[i] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)seg * n_per_seg;
-    const int64_t len = seg_len ? (int64_t)seg_len[seg] : n_per_seg;
-    const int64_t lo = (int64_t)b * kSortTile;
-    const int64_t hi = min(lo + (int64_t)kSortTile, len);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) {
-        const uint32_t d = (rebase(keys[base + i], kbase, seg) >> shift) & 255u;
-        atomicAdd(&cnt[w][d], 1u);
-    }
-    __syncthreads();
-    const int d = threadIdx.x;
-    const uint32_t tot = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
-    hist[((int64_t)seg * 256 + d) * nb + b] = tot;
-}
-
-// One block per segment: exclusive scan over 256*nb counts (digit-major), in
-// tiles of 1024 consecutive counts (coalesced loads, the next tile's loaded
-// while this one is scanned): a DPP scan inside each wave, the 16 wave sums
-// through LDS, and a carry from tile to tile.
+// Inclusive DPP scan of a wave (lanes without a source add 0).
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
@@ -77,33 +54,58 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
     return v;
 }
 
-__global__ __launch_bounds__(1024) void k_radix_offsets(uint32_t *__restrict__ hist, int nb) {
-    __shared__ uint32_t wsum[2][16];
-    const int seg = blockIdx.x;
-    uint32_t *h = hist + (int64_t)seg * 256 * nb;
-    const int64_t total = (int64_t)256 * nb;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t carry = 0;
-    uint32_t v = threadIdx.x < total ? h[threadIdx.x] : 0u;
-    int buf = 0;
-    for (int64_t base = 0; base < total; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const uint32_t nxt = i + 1024 < total ? h[i + 1024] : 0u;
-        const uint32_t incl = wave_incl_scan_u32(v);
-        if (lane == 63) wsum[buf][w] = incl;
-        __syncthreads();
-        uint32_t before = 0, tile = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t s = wsum[buf][k];
-            before += k < w ? s : 0u;
-            tile += s;
-        }
-        if (i < total) h[i] = carry + before + incl - v;
-        carry += tile;
-        v = nxt;
-        buf ^= 1;   // the next tile's wave sums go to the other buffer, so no second barrier
+// Single-sweep form (look-back): one histogram kernel counts every pass's
+// digits of the segment up front; each pass's scatter then takes its block
+// number from a per-segment ticket, publishes its digit counts and sums
+// those of the blocks before it (decoupled look-back), so no per-block
+// histogram or offsets scan runs between the passes.
+// Scratch after the status words, per segment: [4 passes][256] counts,
+// [4][256] exclusive digit bases, [4] tickets (kSweepExtra words).
+constexpr int kSweepExtra = 4 * 256 * 2 + 4;
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagPrefix = 2u << 30, kCountMask = (1u << 30) - 1u;
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist_all(const uint32_t *__restrict__ keys,
+                                                                  int64_t n_per_seg, int passes,
+                                                                  uint32_t *__restrict__ extra,
+                                                                  const uint32_t *__restrict__ kbase,
+                                                                  const uint32_t *__restrict__ seg_len) {
+    __shared__ uint32_t cnt[4][256];
+    const int seg = blockIdx.y, b = blockIdx.x;
+    for (int i = threadIdx.x; i < 4 * 256; i += kSortThreads) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)seg * n_per_seg;
+    const int64_t len = seg_len ? (int64_t)seg_len[seg] : n_per_seg;
+    const int64_t lo = (int64_t)b * kSortTile;
+    const int64_t hi = min(lo + (int64_t)kSortTile, len);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) {
+        const uint32_t k = rebase(keys[base + i], kbase, seg);
+        for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(k >> (8 * p)) & 255u], 1u);
     }
+    __syncthreads();
+    uint32_t *gc = extra + (int64_t)seg * kSweepExtra;
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t c = cnt[p][threadIdx.x];
+        if (c) atomicAdd(&gc[p * 256 + threadIdx.x], c);
+    }
+}
+
+// One block of 256 threads per segment: exclusive scan of each pass's digit
+// counts into the digit bases; the tickets are cleared here too.
+__global__ __launch_bounds__(256) void k_radix_digit_base(uint32_t *__restrict__ extra, int passes) {
+    __shared__ uint32_t wsum[4];
+    uint32_t *e = extra + (int64_t)blockIdx.x * kSweepExtra;
+    const int d = threadIdx.x, w = d >> 6, lane = d & 63;
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t c = e[p * 256 + d];
+        const uint32_t incl = wave_incl_scan_u32(c);
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t before = incl - c;
+        for (int k = 0; k < 3; ++k) before += k < w ? wsum[k] : 0u;
+        e[4 * 256 + p * 256 + d] = before;
+        __syncthreads();
+    }
+    if (d < 4) e[8 * 256 + d] = 0u;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
@@ -111,17 +113,27 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                  uint32_t *__restrict__ kout,
                                                                  uint32_t *__restrict__ vout, int64_t n_per_seg,
                                                                  int nb, int shift, int vals_are_iota,
-                                                                 const uint32_t *__restrict__ offs,
                                                                  const uint32_t *__restrict__ kbase,
-                                                                 const uint32_t *__restrict__ seg_len) {
+                                                                 const uint32_t *__restrict__ seg_len,
+                                                                 uint32_t *__restrict__ status,
+                                                                 uint32_t *__restrict__ extra, int pass) {
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t wbase[4][256];   // block-local start of each wave's run of each digit
     __shared__ uint32_t dstart[256];     // block-local start of each digit
     __shared__ uint32_t gdst[256];       // global start of the block's run of each digit
     __shared__ uint32_t wsum4[4];        // digit counts of each wave's 64 digits
     __shared__ uint32_t lkey[kSortTile], lval[kSortTile];
-    const int seg = blockIdx.y, b = blockIdx.x;
+    __shared__ int tick;
+    const int seg = blockIdx.y;
+    int b = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t *ex = extra + (int64_t)seg * kSweepExtra;
+    // block number in the order the segment's blocks started: every block
+    // this one waits for below has started and publishes its counts before
+    // it waits for anything
+    if (threadIdx.x == 0) tick = (int)atomicAdd(&ex[8 * 256 + pass], 1u);
+    __syncthreads();
+    b = tick;
     // items of the segment to sort (the whole block leaves if it holds none)
     const int64_t len = seg_len ? (int64_t)seg_len[seg] : n_per_seg;
     if ((int64_t)b * kSortTile >= len) return;
@@ -153,7 +165,33 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         const int d = threadIdx.x;
         const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
         const uint32_t tot = c0 + c1 + c2 + c3;
-        gdst[d] = offs[((int64_t)seg * 256 + d) * nb + b];
+        {
+            // publish this block's count of digit d, then add up the counts
+            // of the blocks before it back to one that published its prefix
+            uint32_t *st = status + (int64_t)seg * nb * 256;
+            uint32_t excl = 0;
+            if (b == 0) {
+                __hip_atomic_store(&st[d], kFlagPrefix | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(&st[(int64_t)b * 256 + d], kFlagAgg | tot, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                for (int j = b - 1;; --j) {
+                    uint32_t v = 0;
+                    // (bounded: the block waited for has started; the bound only
+                    // keeps a broken invariant from hanging the device)
+                    for (int spin = 0; spin < (1 << 24); ++spin) {
+                        v = __hip_atomic_load(&st[(int64_t)j * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (v & ~kCountMask) break;
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    excl += v & kCountMask;
+                    if ((v & kFlagPrefix) || j == 0) break;
+                }
+                __hip_atomic_store(&st[(int64_t)b * 256 + d], kFlagPrefix | (excl + tot), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            gdst[d] = ex[4 * 256 + pass * 256 + d] + excl;
+        }
         // digits 64w .. 64w+63 are wave w's lanes: a DPP scan per wave, then
         // the sums of the waves before
         const uint32_t incl = wave_incl_scan_u32(tot);
@@ -192,7 +230,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         const uint32_t kk = lkey[i];
         const uint32_t d = (kk >> shift) & 255u;
         const uint32_t dst = gdst[d] + ((uint32_t)i - dstart[d]);
-        kout[base + dst] = kk;
+        if (kout) kout[base + dst] = kk;
         vout[base + dst] = lval[i];
     }
 }
@@ -203,20 +241,32 @@ hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, u
                                uint32_t **val_out, hipStream_t st) {
     const int nb = (int)((n_per_seg + kSortTile - 1) / kSortTile);
     uint32_t *ki = key0, *vi = val0, *ko = key1, *vo = val1;
+    // hist: [n_segs][256][nb] status words, then kSweepExtra words per segment
+    const int64_t nstatus = (int64_t)n_segs * 256 * nb;
+    uint32_t *extra = hist + nstatus;
+    launch_fill_u32(extra, 0u, (int64_t)n_segs * kSweepExtra, st);
+    hipLaunchKernelGGL(k_radix_hist_all, dim3(nb, n_segs), dim3(kSortThreads), 0, st, key0, n_per_seg, passes,
+                       extra, kbase, seg_len);
+    hipLaunchKernelGGL(k_radix_digit_base, dim3(n_segs), dim3(256), 0, st, extra, passes);
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         const uint32_t *kb = pass == 0 ? kbase : nullptr;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, n_per_seg, nb, shift,
-                           hist, kb, seg_len);
-        hipLaunchKernelGGL(k_radix_offsets, dim3(n_segs), dim3(1024), 0, st, hist, nb);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n_per_seg,
-                           nb, shift, (pass == 0 && vals_are_iota) ? 1 : 0, hist, kb, seg_len);
+        launch_fill_u32(hist, 0u, nstatus, st);
+        // the last pass writes the values only (nothing reads the sorted keys)
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, vi,
+                           pass + 1 < passes ? ko : nullptr, vo, n_per_seg, nb, shift,
+                           (pass == 0 && vals_are_iota) ? 1 : 0, kb, seg_len, hist, extra, pass);
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
-    *key_out = ki;
+    *key_out = nullptr;
     *val_out = vi;
     return hipGetLastError();
+}
+
+int64_t radix_sort_scratch_words(int64_t n_per_seg, int n_segs) {
+    const int64_t nb = (n_per_seg + kSortTile - 1) / kSortTile;
+    return (int64_t)n_segs * (256 * nb + kSweepExtra);
 }
 
 // ---------------------------------------------------------------------------
