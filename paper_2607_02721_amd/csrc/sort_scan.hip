@@ -117,8 +117,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                  const uint32_t *__restrict__ seg_len,
                                                                  uint32_t *__restrict__ status,
                                                                  uint32_t *__restrict__ extra, int pass) {
+    // per wave and digit: the wave's count while ranking, then (thread d
+    // rewrites its own column once it has read it) the block-local start of
+    // the wave's run of digit d; one array instead of two keeps the block
+    // under 40 KB of LDS, four blocks per CU
     __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t wbase[4][256];   // block-local start of each wave's run of each digit
+    uint32_t (*wbase)[256] = wcnt;
     __shared__ uint32_t dstart[256];     // block-local start of each digit
     __shared__ uint32_t gdst[256];       // global start of the block's run of each digit
     __shared__ uint32_t wsum4[4];        // digit counts of each wave's 64 digits
