@@ -123,7 +123,10 @@ constexpr int CNT_WORDS = CNT_SLOTS + kCntSpreadKinds * kCntSpread;
 constexpr float kAmbiguityBeta = 1e-5f;
 
 // Blocks of the projection launch (256 threads, one Gaussian per thread).
-inline int64_t proj_blocks(int64_t n) { return (n + 255) / 256; }
+// The projection runs one wave per block (its per-view folds need no block
+// barrier); proj_part holds one entry per wave.
+constexpr int kProjThreads = 64;
+inline int64_t proj_blocks(int64_t n) { return (n + kProjThreads - 1) / kProjThreads; }
 
 // Ordering of LDS accesses inside a one-wave workgroup.  A wave's LDS
 // instructions execute and return in issue order, so a write by one lane is

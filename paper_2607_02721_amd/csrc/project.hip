@@ -100,13 +100,12 @@ __device__ __forceinline__ uint32_t pack_range(int lo, int hi) {
 }
 
 template <int kDeg, int kFmt>
-__global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
+__global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
                                                  ProjParams pp, float4 *__restrict__ R0,
                                                  float4 *__restrict__ R1, float4 *__restrict__ R2,
                                                  float4 *__restrict__ R3, uint32_t *__restrict__ keys,
                                                  uint4 *__restrict__ part, uint64_t *__restrict__ counters,
                                                  const uint32_t *__restrict__ tile_sat) {
-    __shared__ uint4 red[2][4];
     const int64_t n = sc.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in_range = g < n;
@@ -251,13 +250,11 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
             if (R3) R3[o] = r3;
             keys[o] = keep ? __float_as_uint((float)pz) : kInvisibleKey;
         }
-        // per-view visible count and colour maximum of this wave, folded
-        // over the waves by k_proj_reduce (one shared counter per view would
-        // take every wave's atomic in turn)
-        // (colours and depths are positive: their float bits order like them);
-        // the block's four waves meet in LDS (two buffers, one barrier per
-        // view) and thread 0 stores the block's values
-        // (the colour maximum bounds later contributions on a ray, so it
+        // per-view visible count, colour maximum and key range of this wave
+        // (one wave per block), folded over the waves by k_proj_reduce (one
+        // shared counter per view would take every wave's atomic in turn)
+        // (colours and depths are positive: their float bits order like them;
+        // the colour maximum bounds later contributions on a ray, so it
         // covers every visible Gaussian, kept or not: a ray-masked run then
         // stops its rays exactly where the unmasked run does)
         const uint64_t bal = __ballot(keep);
@@ -279,15 +276,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewDev *__r
         const uint32_t cm = wave_max_u32(vis ? __float_as_uint(cbar) : 0u);
         const uint32_t klo = wave_min_u32(keep ? key : 0xFFFFFFFFu);
         const uint32_t khi = wave_max_u32(keep ? key : 0u);
-        const int wv = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) red[v & 1][wv] = make_uint4((uint32_t)__popcll(bal), cm, klo, khi);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint4 a = red[v & 1][0], b = red[v & 1][1], c = red[v & 1][2], d = red[v & 1][3];
-            part[(int64_t)v * gridDim.x + blockIdx.x] =
-                make_uint4(a.x + b.x + c.x + d.x, max(max(a.y, b.y), max(c.y, d.y)),
-                           min(min(a.z, b.z), min(c.z, d.z)), max(max(a.w, b.w), max(c.w, d.w)));
-        }
+        if (threadIdx.x == 0)
+            part[(int64_t)v * gridDim.x + blockIdx.x] = make_uint4((uint32_t)__popcll(bal), cm, klo, khi);
     }
 }
 
@@ -351,31 +341,27 @@ __global__ __launch_bounds__(256) void k_proj_reduce(uint4 *__restrict__ part, i
 template <int kDeg, int kFmt>
 static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp, const ChunkBufs &b,
                      hipStream_t st) {
-    const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(256), 0, st, sc, views_dev, Vc, pp, b.R0,
+    const int64_t blocks = proj_blocks(sc.n);
+    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R0,
                        b.R1, b.R2, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
     hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (uint4 *)b.proj_part, Vc, blocks,
                        b.nvis, b.cmax, b.kmin);
 }
 
-// Block (g, v) moves the kept keys of Gaussians [256 g, 256 g + 256) of view
-// v to their place after the kept keys of the blocks before it (the offsets
-// k_proj_reduce left), in index order.
-__global__ __launch_bounds__(256) void k_key_compact(const uint32_t *__restrict__ keys, const uint4 *__restrict__ part,
-                                                     int64_t N, int64_t nblk, uint32_t *__restrict__ kout,
-                                                     uint32_t *__restrict__ vout) {
-    __shared__ uint32_t wsum[4];
+// Block (g, v) moves the kept keys of Gaussians [64 g, 64 g + 64) of view v
+// (one wave) to their place after the kept keys of the blocks before it (the
+// offsets k_proj_reduce left), in index order.
+__global__ __launch_bounds__(kProjThreads) void k_key_compact(const uint32_t *__restrict__ keys,
+                                                              const uint4 *__restrict__ part, int64_t N, int64_t nblk,
+                                                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
     const int v = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
     const uint32_t key = i < N ? keys[(int64_t)v * N + i] : kInvisibleKey;
     const bool keep = key != kInvisibleKey;
     const uint64_t bal = __ballot(keep);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     const uint32_t below = (uint32_t)__popcll(bal & (lane ? (~0ull >> (64 - lane)) : 0ull));
-    if (lane == 0) wsum[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t before = part[(int64_t)v * nblk + blockIdx.x].x;
-    for (int k = 0; k < w; ++k) before += wsum[k];
+    const uint32_t before = part[(int64_t)v * nblk + blockIdx.x].x;
     if (keep) {
         const int64_t dst = (int64_t)v * N + before + below;
         kout[dst] = key;
@@ -385,7 +371,7 @@ __global__ __launch_bounds__(256) void k_key_compact(const uint32_t *__restrict_
 
 void launch_key_compact(const ChunkBufs &b, int Vc, int64_t N, uint32_t *kout, uint32_t *vout, hipStream_t st) {
     const int64_t blocks = proj_blocks(N);
-    hipLaunchKernelGGL(k_key_compact, dim3((unsigned)blocks, (unsigned)Vc), dim3(256), 0, st, b.key0,
+    hipLaunchKernelGGL(k_key_compact, dim3((unsigned)blocks, (unsigned)Vc), dim3(kProjThreads), 0, st, b.key0,
                        (const uint4 *)b.proj_part, N, blocks, kout, vout);
 }
 
