@@ -165,7 +165,10 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     const int64_t nbins = (int64_t)c.total_tiles * S.nchunks;
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
-    add(3 * sizeof(float4) * (size_t)c.vc * N);      // records
+    add(sizeof(float4) * (size_t)c.vc * N);          // records
+    add(sizeof(float4) * (size_t)c.vc * N);
+    add(sizeof(float) * (size_t)c.vc * N);
+    add(sizeof(uint2) * (size_t)c.vc * N);
     if (S.nq > 1) add(sizeof(float4) * (size_t)c.vc * N);   // channel colours
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)c.vc * N);
     add(sizeof(uint32_t) * (size_t)radix_sort_scratch_words(N, c.vc));
@@ -448,7 +451,8 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     ChunkBufs &b = r.b;
     b.R0 = cv.take<float4>((size_t)c.vc * N);
     b.R1 = cv.take<float4>((size_t)c.vc * N);
-    b.R2 = cv.take<float4>((size_t)c.vc * N);
+    b.CB = cv.take<float>((size_t)c.vc * N);
+    b.XY = cv.take<uint2>((size_t)c.vc * N);
     b.R3 = S.nq > 1 ? cv.take<float4>((size_t)c.vc * N) : nullptr;
     b.key0 = cv.take<uint32_t>((size_t)c.vc * N);
     b.val0 = cv.take<uint32_t>((size_t)c.vc * N);
@@ -665,7 +669,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     tm.mark(7, st);
 
     // the compositing launch sees this chunk as a single scene slot
-    r.host_slot = SceneSlot{b.R0, b.R1, b.R2, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
+    r.host_slot = SceneSlot{b.R0, b.R1, b.CB, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
                             N, 0, 0, b.R3, c.rays, clist};
     HIP_TRY(hipMemcpyAsync(r.slot_dev, &r.host_slot, sizeof(SceneSlot), hipMemcpyHostToDevice, st));
     launch_fill_u32((uint32_t *)r.tile_scene, 0u, c.total_tiles, st);
@@ -1551,7 +1555,10 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     const int64_t N = ps.S.N;
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
-    add(3 * sizeof(float4) * (size_t)ps.c.vc * N);
+    add(sizeof(float4) * (size_t)ps.c.vc * N);
+    add(sizeof(float4) * (size_t)ps.c.vc * N);
+    add(sizeof(float) * (size_t)ps.c.vc * N);
+    add(sizeof(uint2) * (size_t)ps.c.vc * N);
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)ps.c.vc * N);
     add(sizeof(uint32_t) * (size_t)radix_sort_scratch_words(N, ps.c.vc));
     add(4 * sizeof(uint32_t) * (size_t)ps.c.vc);
@@ -1572,7 +1579,8 @@ void carve_scene(PlanScene &ps, Carve &cv) {
     ChunkBufs &b = ps.b;
     b.R0 = cv.take<float4>((size_t)ps.c.vc * N);
     b.R1 = cv.take<float4>((size_t)ps.c.vc * N);
-    b.R2 = cv.take<float4>((size_t)ps.c.vc * N);
+    b.CB = cv.take<float>((size_t)ps.c.vc * N);
+    b.XY = cv.take<uint2>((size_t)ps.c.vc * N);
     b.key0 = cv.take<uint32_t>((size_t)ps.c.vc * N);
     b.val0 = cv.take<uint32_t>((size_t)ps.c.vc * N);
     b.key1 = cv.take<uint32_t>((size_t)ps.c.vc * N);
@@ -1994,7 +2002,7 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
             std::vector<SceneSlot> hs;
             for (int si : G.scenes) {
                 PlanScene &ps = plan->scenes[si];
-                hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.R2, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
+                hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.CB, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
                                        (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0, nullptr, 0,
                                        ps.clist});
             }

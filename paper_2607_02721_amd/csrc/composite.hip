@@ -53,7 +53,8 @@ struct WaveSetup {
     int W;
     int64_t vbase;
     // the scene slot's fields, read once per quadrant
-    const float4 *R0, *R1, *R2;
+    const float4 *R0, *R1;
+    const float *CB;
     const uint32_t *lists;
     uint32_t *sens_bits;
     const uint32_t *ray_mask;
@@ -98,7 +99,7 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.vbase = (int64_t)(w.v - S.view0) * S.N;
     w.R0 = S.R0;
     w.R1 = S.R1;
-    w.R2 = S.R2;
+    w.CB = S.CB;
     w.lists = S.lists;
     w.sens_bits = S.sens_bits;
     w.ray_mask = S.ray_mask;
@@ -192,7 +193,7 @@ __device__ __forceinline__ int stage_raw(const WaveSetup &w, uint32_t raw, uint6
     const int lane = threadIdx.x;
     const float4 *__restrict__ R0 = w.R0;
     const float4 *__restrict__ R1 = w.R1;
-    const float4 *__restrict__ R2 = w.R2;
+    const float *__restrict__ CB = w.CB;
     const int64_t vbase = w.vbase;
     bool touch = (raw & w.qbit) != 0u;
     const uint32_t g = raw & kIndexMask;
@@ -230,7 +231,7 @@ __device__ __forceinline__ int stage_raw(const WaveSetup &w, uint32_t raw, uint6
             cg = c3.y;
             cblue[slot] = c3.z;
         } else {
-            cb = R2[o].x;
+            cb = CB[o];
         }
         geo[slot] = make_float4(mx, my, r1.x, r1.y);
         float extra = 0.0f;
@@ -285,7 +286,7 @@ __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t 
             cg = c3.y;
             cblue[lane] = c3.z;
         } else {
-            cb = w.R2[o].x;
+            cb = w.CB[o];
         }
         geo[lane] = make_float4((r0.x - w.qx0) + r0.z, (r0.y - w.qy0) + r0.w, r1.x, r1.y);
         if (kLog) {
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
         const int n = __popcll(bal);
         if (h) {
             const int slot = __popcll(bal & lt);
-            const float cb = S.R2[o].x;
+            const float cb = S.CB[o];
             const float la = __builtin_amdgcn_logf(r1.w);
             RegionRec &q = rec[slot];
             q.g = make_float4(mx0, my0, r1.x, r1.y);
@@ -916,7 +917,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             const int64_t o = vbase + g;
             const float4 r0 = S.R0[o];
             const float4 r1 = S.R1[o];
-            const float cb = S.R2[o].x;
+            const float cb = S.CB[o];
             const float la = __builtin_amdgcn_logf(r1.w);
             RegionRec &q = rec[__popcll(bal & lt)];
             q.g = make_float4((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);

@@ -75,7 +75,8 @@ struct ProjParams {
 struct ChunkBufs {
     float4 *R0;          // [Vc*N] mean2d hi.x, hi.y, lo.x, lo.y
     float4 *R1;          // [Vc*N] beta, a', g', alpha   (d^2 form, see project.hip)
-    float4 *R2;          // [Vc*N] cbar, x-range, y-range (int16 pairs as bits), z
+    float *CB;           // [Vc*N] cbar, the query colour factor
+    uint2 *XY;           // [Vc*N] x-range, y-range (int16 pairs as bits)
     float4 *R3;          // [Vc*N] per-channel queries only: c_R, c_G, c_B, 0 (else null)
     uint32_t *key0, *val0, *key1, *val1;  // [Vc*N] sort ping-pong
     uint32_t *hist;      // radix histograms [Vc][256][nb]
@@ -205,7 +206,8 @@ int64_t scan_tmp_elems(int64_t n);
 
 // One scene of a compositing launch (a launch may cover several scenes).
 struct SceneSlot {
-    const float4 *R0, *R1, *R2;   // records [views of the scene][N]
+    const float4 *R0, *R1;        // records [views of the scene][N]
+    const float *CB;              // query colour factor [views of the scene][N]
     const uint32_t *lists;        // tile lists; tile_off values index this array
     const uint64_t *tile_off;     // [scene tiles + 1] start of each tile's list
     const uint32_t *cmax;         // [views of the scene] largest query colour (float bits)

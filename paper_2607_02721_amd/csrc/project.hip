@@ -16,11 +16,13 @@
 //        k = exp(-d^2/2) = exp2(P).  This is the Cholesky form of the
 //        conic: both terms are non-negative multiples of -1, so P has no
 //        cancellation between them.
-//   R2 = (cbar, x-range, y-range, z): the inclusive pixel ranges whose
-//        centres can fall inside the r-ellipse, packed as int16 (lo | hi << 16).
-//        cbar is the query colour factor: c_R + c_G + c_B (RGB sum), 1
+//   CB = cbar, the query colour factor: c_R + c_G + c_B (RGB sum), 1
 //        (nocolor), c_R^2 + c_G^2 + c_B^2 (L2) or the largest channel (per
-//        channel, where it only bounds later contributions).
+//        channel, where it only bounds later contributions); a float array of
+//        its own, so that the compositing passes gather 4-byte values
+//   XY = (x-range, y-range): the inclusive pixel ranges whose centres can
+//        fall inside the r-ellipse, packed as int16 (lo | hi << 16); an
+//        8-byte array of its own, gathered in depth order by k_ranges_in_order
 //   R3 = (c_R, c_G, c_B, 0), written for per-channel queries only.
 #include "gs_internal.hpp"
 
@@ -102,7 +104,8 @@ __device__ __forceinline__ uint32_t pack_range(int lo, int hi) {
 template <int kDeg, int kFmt>
 __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
                                                  ProjParams pp, float4 *__restrict__ R0,
-                                                 float4 *__restrict__ R1, float4 *__restrict__ R2,
+                                                 float4 *__restrict__ R1, float *__restrict__ CB,
+                                                 uint2 *__restrict__ XY,
                                                  float4 *__restrict__ R3, uint32_t *__restrict__ keys,
                                                  uint4 *__restrict__ part, uint64_t *__restrict__ counters,
                                                  const uint32_t *__restrict__ tile_sat) {
@@ -160,7 +163,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const Vie
         const double pz = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + V.t[2];
         bool vis = valid && pz > (double)pp.z_near;
         bool keep = false;   // visible and, in ray-masked runs, meeting a tile that holds a selected ray
-        float4 r0 = make_float4(0, 0, 0, 0), r1 = make_float4(0, 0, 0, 0), r2 = make_float4(0, 0, 0, 0);
+        float4 r0 = make_float4(0, 0, 0, 0), r1 = make_float4(0, 0, 0, 0);
+        uint2 xy = make_uint2(0u, 0u);
         float4 r3 = make_float4(0, 0, 0, 0);
         float cbar = 0.0f;
         if (vis) {
@@ -229,8 +233,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const Vie
                 else
                     cbar = (float)(c[0] + c[1] + c[2]);
                 r3 = make_float4((float)c[0], (float)c[1], (float)c[2], 0.0f);
-                r2 = make_float4(cbar, __uint_as_float(pack_range((int)xl, (int)xh)),
-                                 __uint_as_float(pack_range((int)yl, (int)yh)), (float)pz);
+                xy = make_uint2(pack_range((int)xl, (int)xh), pack_range((int)yl, (int)yh));
                 keep = true;
                 if (tile_sat) {
                     // active tiles inside the tile rectangle [x0, x1) x [y0, y1)
@@ -246,7 +249,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const Vie
         if (in_range) {
             R0[o] = r0;
             R1[o] = r1;
-            R2[o] = r2;
+            CB[o] = cbar;
+            XY[o] = xy;
             if (R3) R3[o] = r3;
             keys[o] = keep ? __float_as_uint((float)pz) : kInvisibleKey;
         }
@@ -343,7 +347,7 @@ static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const
                      hipStream_t st) {
     const int64_t blocks = proj_blocks(sc.n);
     hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R0,
-                       b.R1, b.R2, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
+                       b.R1, b.CB, b.XY, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
     hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (uint4 *)b.proj_part, Vc, blocks,
                        b.nvis, b.cmax, b.kmin);
 }
@@ -387,21 +391,21 @@ void launch_project(const SceneDev &sc, const ViewDev *views_dev, int Vc, const 
 // binning kernels read them with unit stride: xr/yr[v*N + p] for position p
 // of view v's front-to-back order.
 __global__ __launch_bounds__(256) void k_ranges_in_order(const uint32_t *__restrict__ sorted_g,
-                                                         const float4 *__restrict__ R2,
+                                                         const uint2 *__restrict__ XY,
                                                          const uint32_t *__restrict__ nvis, int64_t N,
                                                          uint32_t *__restrict__ xr, uint32_t *__restrict__ yr) {
     const int v = blockIdx.y;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)nvis[v]) return;
     const int64_t o = (int64_t)v * N;
-    const float4 r = R2[o + sorted_g[o + p]];
-    xr[o + p] = __float_as_uint(r.y);
-    yr[o + p] = __float_as_uint(r.z);
+    const uint2 r = XY[o + sorted_g[o + p]];
+    xr[o + p] = r.x;
+    yr[o + p] = r.y;
 }
 
 void launch_ranges_in_order(const uint32_t *sorted_g, const ChunkBufs &b, int Vc, int64_t N, uint32_t *xr,
                             uint32_t *yr, hipStream_t st) {
-    hipLaunchKernelGGL(k_ranges_in_order, dim3((unsigned)((N + 255) / 256), Vc), dim3(256), 0, st, sorted_g, b.R2,
+    hipLaunchKernelGGL(k_ranges_in_order, dim3((unsigned)((N + 255) / 256), Vc), dim3(256), 0, st, sorted_g, b.XY,
                        b.nvis, N, xr, yr);
 }
 
