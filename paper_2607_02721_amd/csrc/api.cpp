@@ -165,8 +165,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     const int64_t nbins = (int64_t)c.total_tiles * S.nchunks;
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
-    add(sizeof(float4) * (size_t)c.vc * N);          // records
-    add(sizeof(float4) * (size_t)c.vc * N);
+    add(sizeof(GeoRec) * (size_t)c.vc * N);          // records
     add(sizeof(float) * (size_t)c.vc * N);
     add(sizeof(uint2) * (size_t)c.vc * N);
     if (S.nq > 1) add(sizeof(float4) * (size_t)c.vc * N);   // channel colours
@@ -449,8 +448,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     HIP_TRY(arena_reserve(g_work[dev], need));
     Carve cv(g_work[dev].base);
     ChunkBufs &b = r.b;
-    b.R0 = cv.take<float4>((size_t)c.vc * N);
-    b.R1 = cv.take<float4>((size_t)c.vc * N);
+    b.R = cv.take<GeoRec>((size_t)c.vc * N);
     b.CB = cv.take<float>((size_t)c.vc * N);
     b.XY = cv.take<uint2>((size_t)c.vc * N);
     b.R3 = S.nq > 1 ? cv.take<float4>((size_t)c.vc * N) : nullptr;
@@ -669,7 +667,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     tm.mark(7, st);
 
     // the compositing launch sees this chunk as a single scene slot
-    r.host_slot = SceneSlot{b.R0, b.R1, b.CB, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
+    r.host_slot = SceneSlot{b.R, b.CB, b.lists, b.tile_off, b.cmax, b.ray_A, sens_bits, p->ray_mask,
                             N, 0, 0, b.R3, c.rays, clist};
     HIP_TRY(hipMemcpyAsync(r.slot_dev, &r.host_slot, sizeof(SceneSlot), hipMemcpyHostToDevice, st));
     launch_fill_u32((uint32_t *)r.tile_scene, 0u, c.total_tiles, st);
@@ -1555,8 +1553,7 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
     const int64_t N = ps.S.N;
     size_t b = 0;
     auto add = [&](size_t x) { b += ((x + 255) & ~(size_t)255); };
-    add(sizeof(float4) * (size_t)ps.c.vc * N);
-    add(sizeof(float4) * (size_t)ps.c.vc * N);
+    add(sizeof(GeoRec) * (size_t)ps.c.vc * N);
     add(sizeof(float) * (size_t)ps.c.vc * N);
     add(sizeof(uint2) * (size_t)ps.c.vc * N);
     for (int k = 0; k < 4; ++k) add(sizeof(uint32_t) * (size_t)ps.c.vc * N);
@@ -1577,8 +1574,7 @@ size_t scene_buffer_bytes(const PlanScene &ps) {
 void carve_scene(PlanScene &ps, Carve &cv) {
     const int64_t N = ps.S.N;
     ChunkBufs &b = ps.b;
-    b.R0 = cv.take<float4>((size_t)ps.c.vc * N);
-    b.R1 = cv.take<float4>((size_t)ps.c.vc * N);
+    b.R = cv.take<GeoRec>((size_t)ps.c.vc * N);
     b.CB = cv.take<float>((size_t)ps.c.vc * N);
     b.XY = cv.take<uint2>((size_t)ps.c.vc * N);
     b.key0 = cv.take<uint32_t>((size_t)ps.c.vc * N);
@@ -2002,7 +1998,7 @@ gs_status gs_plan_sensitivity(gs_plan *plan, float *const *sens, void *stream) {
             std::vector<SceneSlot> hs;
             for (int si : G.scenes) {
                 PlanScene &ps = plan->scenes[si];
-                hs.push_back(SceneSlot{ps.b.R0, ps.b.R1, ps.b.CB, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
+                hs.push_back(SceneSlot{ps.b.R, ps.b.CB, ps.b.lists, ps.b.tile_off, ps.b.cmax, ps.b.ray_A,
                                        (uint32_t *)sens[si], nullptr, ps.S.N, ps.view0, ps.tile0, nullptr, 0,
                                        ps.clist});
             }

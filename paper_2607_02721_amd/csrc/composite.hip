@@ -53,7 +53,7 @@ struct WaveSetup {
     int W;
     int64_t vbase;
     // the scene slot's fields, read once per quadrant
-    const float4 *R0, *R1;
+    const GeoRec *R;
     const float *CB;
     const uint32_t *lists;
     uint32_t *sens_bits;
@@ -97,8 +97,7 @@ __device__ __forceinline__ bool setup_quad(const CompositeArgs &a, int logical, 
     w.end = S.tile_off[w.gt - S.tile0 + 1];
     w.qbit = quad_subrect_bits(w.quad, V.tsx, V.tsy) << 28;
     w.vbase = (int64_t)(w.v - S.view0) * S.N;
-    w.R0 = S.R0;
-    w.R1 = S.R1;
+    w.R = S.R;
     w.CB = S.CB;
     w.lists = S.lists;
     w.sens_bits = S.sens_bits;
@@ -191,8 +190,7 @@ __device__ __forceinline__ int stage_raw(const WaveSetup &w, uint32_t raw, uint6
     static_assert(!(kChannel && kExtra == 2), "per-channel queries have no weighted objective");
     static_assert(!(kLog && (kChannel || kExtra == 2)), "the log form has no room for an extra value");
     const int lane = threadIdx.x;
-    const float4 *__restrict__ R0 = w.R0;
-    const float4 *__restrict__ R1 = w.R1;
+    const GeoRec *__restrict__ R = w.R;
     const float *__restrict__ CB = w.CB;
     const int64_t vbase = w.vbase;
     bool touch = (raw & w.qbit) != 0u;
@@ -201,8 +199,8 @@ __device__ __forceinline__ int stage_raw(const WaveSetup &w, uint32_t raw, uint6
     float4 r1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float mx = 0.0f, my = 0.0f;
     if (touch) {
-        const float4 r0 = R0[o];
-        r1 = R1[o];
+        const float4 r0 = R[o].m;
+        r1 = R[o].q;
         mx = (r0.x - w.qx0) + r0.z;
         my = (r0.y - w.qy0) + r0.w;
         touch = quad_hit(mx, my, r1.x, r1.y, r1.z, cut);
@@ -277,8 +275,8 @@ __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t 
     if (lane < n) {
         const uint32_t g = cl[lane];
         const int64_t o = w.vbase + g;
-        const float4 r0 = w.R0[o];
-        const float4 r1 = w.R1[o];
+        const float4 r0 = w.R[o].m;
+        const float4 r1 = w.R[o].q;
         float cb = 0.0f, cg = 0.0f;
         if (kChannel) {
             const float4 c3 = w.R3[o];
@@ -521,8 +519,8 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
         float4 r1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float mx0 = 0.0f, my0 = 0.0f, mx1 = 0.0f, my1 = 0.0f;
         if (raw & want) {
-            const float4 r0 = S.R0[o];
-            r1 = S.R1[o];
+            const float4 r0 = S.R[o].m;
+            r1 = S.R[o].q;
             mx0 = (r0.x - fx0) + r0.z;
             my0 = (r0.y - fy0) + r0.w;
             mx1 = (r0.x - fx1) + r0.z;
@@ -915,8 +913,8 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         if (h) {
             const uint32_t g = raw & kIndexMask;
             const int64_t o = vbase + g;
-            const float4 r0 = S.R0[o];
-            const float4 r1 = S.R1[o];
+            const float4 r0 = S.R[o].m;
+            const float4 r1 = S.R[o].q;
             const float cb = S.CB[o];
             const float la = __builtin_amdgcn_logf(r1.w);
             RegionRec &q = rec[__popcll(bal & lt)];

@@ -72,9 +72,16 @@ struct ProjParams {
 };
 
 // Per-chunk device pointers produced by projection and binning.
+// The geometry record of a (view, Gaussian) pair: both halves in one
+// 32-byte-aligned record, so that a gather by Gaussian index touches one
+// cache line.
+struct __align__(32) GeoRec {
+    float4 m;            // mean2d hi.x, hi.y, lo.x, lo.y
+    float4 q;            // beta, a', g', alpha   (d^2 form, see project.hip)
+};
+
 struct ChunkBufs {
-    float4 *R0;          // [Vc*N] mean2d hi.x, hi.y, lo.x, lo.y
-    float4 *R1;          // [Vc*N] beta, a', g', alpha   (d^2 form, see project.hip)
+    GeoRec *R;           // [Vc*N] geometry records
     float *CB;           // [Vc*N] cbar, the query colour factor
     uint2 *XY;           // [Vc*N] x-range, y-range (int16 pairs as bits)
     float4 *R3;          // [Vc*N] per-channel queries only: c_R, c_G, c_B, 0 (else null)
@@ -206,7 +213,7 @@ int64_t scan_tmp_elems(int64_t n);
 
 // One scene of a compositing launch (a launch may cover several scenes).
 struct SceneSlot {
-    const float4 *R0, *R1;        // records [views of the scene][N]
+    const GeoRec *R;              // geometry records [views of the scene][N]
     const float *CB;              // query colour factor [views of the scene][N]
     const uint32_t *lists;        // tile lists; tile_off values index this array
     const uint64_t *tile_off;     // [scene tiles + 1] start of each tile's list

@@ -3,14 +3,14 @@
 // front-to-back order by view depth).
 //
 // One thread per Gaussian loads its attributes once (coalesced SoA planes)
-// and loops over the chunk's views; per view it writes a 48-byte record and
-// a depth key.  Set-up runs in FP64 (the vector FP64 rate equals the
-// non-packed FP32 rate on CDNA4), so the float32 record fields carry only
-// their own rounding.
+// and loops over the chunk's views; per view it writes a 32-byte geometry
+// record, the colour factor, the packed pixel ranges and a depth key.
+// Set-up runs in FP64 (the vector FP64 rate equals the non-packed FP32 rate
+// on CDNA4), so the float32 record fields carry only their own rounding.
 //
-// Record (all float32 unless noted):
-//   R0 = mean2d as float hi + float lo (x_hi, y_hi, x_lo, y_lo)
-//   R1 = (beta, a', g', alpha) with, for Delta = pixel centre - mean,
+// Records (all float32 unless noted):
+//   geo.m = mean2d as float hi + float lo (x_hi, y_hi, x_lo, y_lo)
+//   geo.q = (beta, a', g', alpha) with, for Delta = pixel centre - mean,
 //        u = Delta_x + beta Delta_y and P = a' u^2 + g' Delta_y^2,
 //        P = -(log2 e / 2) d^2 exactly in real arithmetic, so that
 //        k = exp(-d^2/2) = exp2(P).  This is the Cholesky form of the
@@ -103,8 +103,7 @@ __device__ __forceinline__ uint32_t pack_range(int lo, int hi) {
 
 template <int kDeg, int kFmt>
 __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const ViewDev *__restrict__ views, int Vc,
-                                                 ProjParams pp, float4 *__restrict__ R0,
-                                                 float4 *__restrict__ R1, float *__restrict__ CB,
+                                                 ProjParams pp, GeoRec *__restrict__ geo, float *__restrict__ CB,
                                                  uint2 *__restrict__ XY,
                                                  float4 *__restrict__ R3, uint32_t *__restrict__ keys,
                                                  uint4 *__restrict__ part, uint64_t *__restrict__ counters,
@@ -247,8 +246,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const Vie
         }
         const int64_t o = (int64_t)v * n + gi;
         if (in_range) {
-            R0[o] = r0;
-            R1[o] = r1;
+            geo[o].m = r0;
+            geo[o].q = r1;
             CB[o] = cbar;
             XY[o] = xy;
             if (R3) R3[o] = r3;
@@ -346,8 +345,8 @@ template <int kDeg, int kFmt>
 static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp, const ChunkBufs &b,
                      hipStream_t st) {
     const int64_t blocks = proj_blocks(sc.n);
-    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R0,
-                       b.R1, b.CB, b.XY, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
+    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R,
+                       b.CB, b.XY, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
     hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (uint4 *)b.proj_part, Vc, blocks,
                        b.nvis, b.cmax, b.kmin);
 }
