@@ -632,7 +632,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
                 clist = (uint32_t *)g_compact[dev].base;
             else
                 (void)hipGetLastError();
-        } else if (!r.quad_list) {
+        } else if (!r.quad_list && S.agg == GS_AGG_RAY) {
             // list offsets at every G-th tile: ranges are cut there
             const int64_t T = c.total_tiles;
             const int64_t G = (T + kRangeSamples - 1) / kRangeSamples;
@@ -840,7 +840,10 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     S.agg = params->aggregate;
     S.nq = params->query_mode == GS_QUERY_CHANNEL ? 3 : 1;
-    S.compact = S.agg == GS_AGG_RAY;
+    // per-ray, per-image and per-scene queries composite on compacted lists
+    // (per-tile accumulators are indexed by list position: those walk the
+    // tile lists)
+    S.compact = S.agg != GS_AGG_TILE;
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
     launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
     // per-scene queries: the absolute contributions and A summed over chunks
@@ -873,8 +876,11 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         sort_passes = std::max(sort_passes, r.passes);
         CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor, S);
         a.ccount = r.host_slot.clist ? r.ccount : nullptr;
-        if (r.quad_list) {
-            // only the listed quadrants are composited: the other rays read A = 0
+        if (r.quad_list && 4 * (int64_t)r.n_listed <= ((int64_t)c.total_tiles << S.quad_log)) {
+            // a sparse mask (a quarter of the quadrants or fewer hold a
+            // selected ray): only the listed quadrants are composited, one wave
+            // each, and the other rays read A = 0; denser masks take the flat
+            // launches, whose waves leave at once where no ray is selected
             launch_fill_u32((uint32_t *)r.b.ray_A, 0u, (int64_t)c.rays * S.nq, st);
             a.quad_list = r.quad_list;
             a.n_listed = r.n_listed;

@@ -855,10 +855,17 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
 // and at most one atomic per entry instead of one per (quadrant, entry).
 // The value reduced is x = rho T (L1) or (rho T)^2 (L2), of which the share
 // is c x: one product per entry instead of one per pair.
-template <bool kStats, int kMode>
+// With kAgg (2: per-image, 3: per-scene queries) the shares are against the
+// query's A and summed instead: per quadrant, the 16 entries' shares go
+// through the transposed sum of k_pass2 (the same per-pixel shares and the
+// same sums over each quadrant's 64 pixels), each sum becomes u64 fixed point
+// as there, and the quadrants' integers are added before one atomic per entry.
+template <bool kStats, int kMode, int kAgg = 0>
 __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(CompositeArgs a,
                                                                          uint64_t *__restrict__ counters) {
     static_assert(kMode != kModeChannel, "per-channel queries take k_pass2");
+    static_assert(kAgg == 0 || kAgg == 2 || kAgg == 3, "per-tile queries walk the tile lists");
+    static_assert(!(kAgg != 0 && kStats), "aggregated queries count no pairs");
     __shared__ RegionRec rec[kWave];
     const int lane = threadIdx.x;
     const int nreg = a.total_tiles << a.region_log;
@@ -887,8 +894,14 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         const float Af = scored ? S.ray_A[V.ray_local + (int64_t)py * V.W + px] : 0.0f;
         const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
         positive[k] = invA > 0.0f;
-        T[k] = kMode == kModeL2 ? sqrtf(invA) : invA;
-        live_bar[k] = a.share_floor * (Af * invA);
+        // the share's denominator: the ray's A, or the A of the ray's query
+        float invQ = invA;
+        if (kAgg != 0) {
+            const double qA = kAgg == 2 ? a.query_A[v] : a.query_A[0];
+            invQ = (invA > 0.0f && qA > 0.0) ? (float)(1.0 / qA) : 0.0f;
+        }
+        T[k] = kMode == kModeL2 ? sqrtf(invQ) : invQ;
+        live_bar[k] = a.share_floor * (Af * invQ);
         done[k] = !positive[k];
         alive |= (((R.valid >> k) & 1u) && !__all(done[k])) ? (1u << k) : 0u;
     }
@@ -921,76 +934,117 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             q.g = make_float4((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);
             q.c = make_float4(r1.z, la, cb, cut + la);
             q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
-            const float sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
-            q.sold = sold;
             q.sid = g;
-            // c x > sold implies x > sold / (c (1 + 2^-24)); the bar sits below
-            // that by more than the rounding of v_rcp_f32 and the products
-            // (and is 0, which lets every positive x through, for tiny c)
-            q.bar = (sold > 0.0f && cb >= 0x1p-100f) ? (sold * __builtin_amdgcn_rcpf(cb)) * 0.99999905f : 0.0f;
+            if (kAgg == 0) {
+                const float sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
+                q.sold = sold;
+                // c x > sold implies x > sold / (c (1 + 2^-24)); the bar sits
+                // below that by more than the rounding of v_rcp_f32 and the
+                // products (and is 0, which lets every positive x through, for
+                // tiny c)
+                q.bar = (sold > 0.0f && cb >= 0x1p-100f) ? (sold * __builtin_amdgcn_rcpf(cb)) * 0.99999905f : 0.0f;
+            }
         }
         uint64_t bq[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) bq[k] = __ballot((h >> k) & 1u);
         if (kStats) n_eval += (uint64_t)(__popcll(bq[0]) + __popcll(bq[1]) + __popcll(bq[2]) + __popcll(bq[3]));
         wave_sync();
-        // slot j: the j-th lane of bal, its quadrant bits in bq[k]
-        uint64_t rem = bal;
-        for (int jb = 0; jb < n; jb += 16) {
-            float sh[16];
+        if constexpr (kAgg != 0) {
+            for (int jb = 0; jb < n; jb += 16) {
+                uint64_t acc = 0ull;   // lane 4 i: entry jb + i's fixed-point sum over the quadrants
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint64_t lowbit = rem & (~rem + 1ull);
-                rem ^= lowbit;
-                uint32_t m = 0u;
-                if (lowbit) {
-                    const RegionRec &q = rec[jb + i];
-                    const float4 G = q.g, C = q.c;
-                    const float2 M1 = q.m1;
-                    const float dxq[2] = {xl - G.x, xl - M1.x};
-                    const float dy0 = yl - G.y, dy1 = yl - M1.y;
-                    const float dyq[2] = {dy0, dy1};
-                    const float tq[2] = {fmaf(C.x, dy0 * dy0, C.y), fmaf(C.x, dy1 * dy1, C.y)};
+                for (int k = 0; k < 4; ++k) {
+                    if (!(((alive >> k) & 1u) && bq[k])) continue;
+                    // the block's entries in slot order; lowbit walks bal again
+                    uint64_t rk = bal;
+                    for (int x = 0; x < jb; ++x) rk &= rk - 1ull;
+                    float sh[16];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
+                    for (int i = 0; i < 16; ++i) {
+                        const uint64_t lowbit = rk & (~rk + 1ull);
+                        rk ^= lowbit;
+                        float share = 0.0f;
                         if (bq[k] & lowbit) {
-                            const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
-                            const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
-                            const float E = __builtin_amdgcn_exp2f(P);
-                            const bool in_fp = P >= C.w;
-                            const float rho = in_fp ? E : 0.0f;
-                            // the share is c x, and c x is monotone in x:
-                            // the entry's largest share is c times its
-                            // largest x (rounding is monotone too)
+                            const RegionRec &q = rec[jb + i];
+                            const float4 G = q.g, C = q.c;
+                            const float mx = (k & 1) ? q.m1.x : G.x, my = (k >> 1) ? q.m1.y : G.y;
+                            bool in_fp;
+                            const float rho = pair_rho_log2(make_float4(mx, my, G.z, G.w), C, xl, yl, in_fp);
                             const float rt = rho * T[k];
-                            const float x = kMode == kModeL1 ? rt : rt * rt;
-                            m = umax32(m, __float_as_uint(x));
-                            if (kStats) {
-                                const float later = kMode == kModeL2 ? (T[k] * T[k]) * cmax : T[k] * cmax;
-                                n_in += (positive[k] && in_fp) ? 1u : 0u;
-                                n_live += (positive[k] && in_fp && later >= live_bar[k]) ? 1u : 0u;
-                                const bool am = positive[k] && fabsf(P - C.w) <= amb_band;
-                                n_amb += am ? 1u : 0u;
-                                amb |= am ? (1u << k) : 0u;
-                            }
+                            share = kMode == kModeL1 ? C.z * rt : C.z * (rt * rt);
                             T[k] = fmaf(-rho, T[k], T[k]);
                         }
+                        sh[i] = share;
                     }
+                    const float m = wave_transpose_sum16(sh);
+                    acc += m > 0.0f ? (uint64_t)fma((double)m, kAggScale, 0.5) : 0ull;
                 }
-                sh[i] = __uint_as_float(m);
-            }
-            // the reduction only if some pixel beats its entry's staged
-            // sensitivity (slots past n hold share 0, which beats none)
-            uint64_t beat = 0ull;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > rec[jb + i].bar);
-            if (beat != 0ull) {
-                const float mx = wave_transpose_max16(sh);
                 const int j = jb + (lane >> 2);
-                if ((lane & 3) == 0 && j < n) {
-                    // (a share cannot exceed 1; its rounding can, by an ulp or two)
-                    const float share = fminf(rec[j].c.z * mx, 1.0f);
-                    if (share > rec[j].sold) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(share));
+                if ((lane & 3) == 0 && j < n && acc) {
+                    const int64_t idx = kAgg == 2 ? vbase + rec[j].sid : (int64_t)rec[j].sid;
+                    atomicAdd((unsigned long long *)&a.acc[idx], (unsigned long long)acc);
+                }
+            }
+        } else {
+            // slot j: the j-th lane of bal, its quadrant bits in bq[k]
+            uint64_t rem = bal;
+            for (int jb = 0; jb < n; jb += 16) {
+                float sh[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const uint64_t lowbit = rem & (~rem + 1ull);
+                    rem ^= lowbit;
+                    uint32_t m = 0u;
+                    if (lowbit) {
+                        const RegionRec &q = rec[jb + i];
+                        const float4 G = q.g, C = q.c;
+                        const float2 M1 = q.m1;
+                        const float dxq[2] = {xl - G.x, xl - M1.x};
+                        const float dy0 = yl - G.y, dy1 = yl - M1.y;
+                        const float dyq[2] = {dy0, dy1};
+                        const float tq[2] = {fmaf(C.x, dy0 * dy0, C.y), fmaf(C.x, dy1 * dy1, C.y)};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (bq[k] & lowbit) {
+                                const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
+                                const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
+                                const float E = __builtin_amdgcn_exp2f(P);
+                                const bool in_fp = P >= C.w;
+                                const float rho = in_fp ? E : 0.0f;
+                                // the share is c x, and c x is monotone in x:
+                                // the entry's largest share is c times its
+                                // largest x (rounding is monotone too)
+                                const float rt = rho * T[k];
+                                const float x = kMode == kModeL1 ? rt : rt * rt;
+                                m = umax32(m, __float_as_uint(x));
+                                if (kStats) {
+                                    const float later = kMode == kModeL2 ? (T[k] * T[k]) * cmax : T[k] * cmax;
+                                    n_in += (positive[k] && in_fp) ? 1u : 0u;
+                                    n_live += (positive[k] && in_fp && later >= live_bar[k]) ? 1u : 0u;
+                                    const bool am = positive[k] && fabsf(P - C.w) <= amb_band;
+                                    n_amb += am ? 1u : 0u;
+                                    amb |= am ? (1u << k) : 0u;
+                                }
+                                T[k] = fmaf(-rho, T[k], T[k]);
+                            }
+                        }
+                    }
+                    sh[i] = __uint_as_float(m);
+                }
+                // the reduction only if some pixel beats its entry's staged
+                // sensitivity (slots past n hold share 0, which beats none)
+                uint64_t beat = 0ull;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > rec[jb + i].bar);
+                if (beat != 0ull) {
+                    const float mx = wave_transpose_max16(sh);
+                    const int j = jb + (lane >> 2);
+                    if ((lane & 3) == 0 && j < n) {
+                        // (a share cannot exceed 1; its rounding can, by an ulp or two)
+                        const float share = fminf(rec[j].c.z * mx, 1.0f);
+                        if (share > rec[j].sold) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(share));
+                    }
                 }
             }
         }
@@ -1139,11 +1193,26 @@ static void pass2_ray_any(const CompositeArgs &a, bool stats, uint64_t *counters
         pass2_ray<kMode, kPersistentForm, false>(a, stats, counters, st);
 }
 
-// Aggregated queries run the flat form without pair counters; per-channel
-// queries have no aggregated or persistent form (the host rejects the first).
+// Aggregated queries run the flat form without pair counters (image and
+// scene queries by regions on the region lists when pass 1 left them);
+// per-channel queries have no aggregated or persistent form (the host
+// rejects the first).
+template <int kMode>
+static bool pass2_agg_region(const CompositeArgs &a, hipStream_t st) {
+    if (!(a.ccount && !a.work && !a.quad_list && (a.agg == 2 || a.agg == 3))) return false;
+    const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
+    if (a.agg == 2)
+        hipLaunchKernelGGL((k_pass2_region<false, kMode, 2>), dim3(grid), dim3(kWave), 0, st, a, nullptr);
+    else
+        hipLaunchKernelGGL((k_pass2_region<false, kMode, 3>), dim3(grid), dim3(kWave), 0, st, a, nullptr);
+    return true;
+}
+
 void launch_composite_pass2(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
     const int mode = composite_mode(a.query_mode);
     if (a.agg != 0) {
+        if (mode == kModeL2 && pass2_agg_region<kModeL2>(a, st)) return;
+        if (mode == kModeL1 && pass2_agg_region<kModeL1>(a, st)) return;
         if (mode == kModeL2)
             pass2_agg<kModeL2>(a, counters, st);
         else if (mode == kModeL1)
