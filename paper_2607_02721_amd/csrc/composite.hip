@@ -399,12 +399,13 @@ __global__ __launch_bounds__(kWave) void k_pass1(CompositeArgs a) {
 // Pass 2 adds the entry's staged sensitivity (raised to the report floor),
 // its Gaussian index and the bar below which a pixel's rho T (L1) or
 // (rho T)^2 (L2) cannot give a share above the staged sensitivity.
+// Per-channel queries stage c = (g', alpha, c_R, c_G) and c_B in cblue.
 struct __align__(16) RegionRec {
     float4 g, c;
     float2 m1;
     float sold;
     uint32_t sid;
-    float bar, pad[3];
+    float bar, cblue, pad[2];
 };
 
 // Region `logical` of the launch: its tile, view, scene slot, origin and, per
@@ -464,10 +465,11 @@ __device__ __forceinline__ bool setup_region(const CompositeArgs &a, int logical
 // every entry that reaches one of its quadrants, with the quadrant bits in
 // the top four bits (per quadrant, exactly the entries of its compacted
 // list), for k_pass2_region.
-// One query per ray (kModeL1, kModeL2), one wave per region, no quadrant list.
+// Every query mode (per-channel queries: the three objectives of
+// k_pass1 per pixel), one wave per region, no quadrant list.
 template <int kMode>
 __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
-    static_assert(kMode != kModeChannel, "per-channel queries take k_pass1");
+    constexpr bool kCh = kMode == kModeChannel;
     __shared__ RegionRec rec[kWave];
     const int lane = threadIdx.x;
     const int nreg = a.total_tiles << a.region_log;
@@ -484,7 +486,7 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
     const float fx0 = (float)ox, fx1 = (float)(ox + kQuad), fy0 = (float)oy, fy1 = (float)(oy + kQuad);
     bool inside[4], scored[4], done[4];
     int64_t ray_local[4];
-    float T[4], A[4];
+    float T[4], A[4], AG[4], AB[4];   // AG, AB: the G and B objectives of per-channel queries
     uint32_t alive = 0u;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -494,6 +496,8 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
         scored[k] = inside[k] && ray_selected(S.ray_mask, V.ray_base + (int64_t)py * V.W + px);
         T[k] = 1.0f;
         A[k] = 0.0f;
+        AG[k] = 0.0f;
+        AB[k] = 0.0f;
         done[k] = !scored[k];
         alive |= (((valid >> k) & 1u) && !__all(done[k])) ? (1u << k) : 0u;
     }
@@ -535,12 +539,19 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
         const int n = __popcll(bal);
         if (h) {
             const int slot = __popcll(bal & lt);
-            const float cb = S.CB[o];
-            const float la = __builtin_amdgcn_logf(r1.w);
             RegionRec &q = rec[slot];
             q.g = make_float4(mx0, my0, r1.x, r1.y);
-            q.c = make_float4(r1.z, la, cb, cut + la);
             q.m1 = make_float2(mx1, my1);
+            if (kCh) {
+                // as stage_raw with kChannel: (g', alpha, c_R, c_G), c_B
+                const float4 c3 = S.R3[o];
+                q.c = make_float4(r1.z, r1.w, c3.x, c3.y);
+                q.cblue = c3.z;
+            } else {
+                const float cb = S.CB[o];
+                const float la = __builtin_amdgcn_logf(r1.w);
+                q.c = make_float4(r1.z, la, cb, cut + la);
+            }
         }
         if (cl && h) __builtin_nontemporal_store(g | (h << 28), &cl[ccnt + (uint32_t)__popcll(bal & lt)]);
         ccnt += (uint32_t)n;
@@ -562,24 +573,31 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
                 const float2 M1 = q.m1;
                 // offsets from the mean per quadrant column and row and the
                 // row's part of the exponent, formed once for the quadrants
-                // that share them (the operations of pair_rho_log2)
+                // that share them (the operations of pair_rho_log2, or of
+                // pair_rho for per-channel queries)
                 const float dxq[2] = {xl - G.x, xl - M1.x};
                 const float dy0 = yl - G.y, dy1 = yl - M1.y;
                 const float dyq[2] = {dy0, dy1};
-                const float tq[2] = {fmaf(C.x, dy0 * dy0, C.y), fmaf(C.x, dy1 * dy1, C.y)};
+                const float tq[2] = {kCh ? C.x * (dy0 * dy0) : fmaf(C.x, dy0 * dy0, C.y),
+                                     kCh ? C.x * (dy1 * dy1) : fmaf(C.x, dy1 * dy1, C.y)};
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (bq[k] & lowbit) {
                         const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
                         const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
                         const float E = __builtin_amdgcn_exp2f(P);
-                        const float rho = P >= C.w ? E : 0.0f;
+                        const float rho = kCh ? (P >= cut ? C.y * E : 0.0f) : (P >= C.w ? E : 0.0f);
                         if (kMode == kModeL1) {
                             const float cr = C.z * rho;
                             A[k] = fmaf(cr, T[k], A[k]);
-                        } else {
+                        } else if (kMode == kModeL2) {
                             const float rt = rho * T[k];
                             A[k] = fmaf(C.z * rt, rt, A[k]);
+                        } else {
+                            const float rt = rho * T[k];
+                            A[k] = fmaf(C.z, rt, A[k]);
+                            AG[k] = fmaf(C.w, rt, AG[k]);
+                            AB[k] = fmaf(q.cblue, rt, AB[k]);
                         }
                         T[k] = fmaf(-rho, T[k], T[k]);
                     }
@@ -590,13 +608,20 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
         for (int k = 0; k < 4; ++k) {
             if (kMode == kModeL1) done[k] = done[k] || (T[k] * cmax < a.share_floor * A[k]);
             if (kMode == kModeL2) done[k] = done[k] || ((T[k] * T[k]) * cmax < a.share_floor * A[k]);
+            if (kCh) done[k] = done[k] || (T[k] * cmax < a.share_floor * fminf(A[k], fminf(AG[k], AB[k])));
             if (((alive >> k) & 1u) && __all(done[k])) alive &= ~(1u << k);
         }
         wave_sync();
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (inside[k]) S.ray_A[ray_local[k]] = scored[k] ? A[k] : 0.0f;
+        if (inside[k]) {
+            S.ray_A[ray_local[k]] = scored[k] ? A[k] : 0.0f;
+            if (kCh) {
+                S.ray_A[S.ray_stride + ray_local[k]] = scored[k] ? AG[k] : 0.0f;
+                S.ray_A[2 * S.ray_stride + ray_local[k]] = scored[k] ? AB[k] : 0.0f;
+            }
+        }
     }
     if (cl && lane == 0) a.ccount[((gt - a.tile_first) << a.quad_log) + R.quad[0]] = ccnt;
 }
@@ -863,7 +888,8 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
 template <bool kStats, int kMode, int kAgg = 0>
 __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(CompositeArgs a,
                                                                          uint64_t *__restrict__ counters) {
-    static_assert(kMode != kModeChannel, "per-channel queries take k_pass2");
+    constexpr bool kCh = kMode == kModeChannel;
+    static_assert(!(kCh && kAgg != 0), "per-channel queries have no aggregated form");
     static_assert(kAgg == 0 || kAgg == 2 || kAgg == 3, "per-tile queries walk the tile lists");
     static_assert(!(kAgg != 0 && kStats), "aggregated queries count no pairs");
     __shared__ RegionRec rec[kWave];
@@ -881,7 +907,9 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
     const float fx0 = (float)ox, fx1 = (float)(ox + kQuad), fy0 = (float)oy, fy1 = (float)(oy + kQuad);
     // per quadrant: the running transmittance scaled as in k_pass2 (by 1/A
     // for L1, 1/sqrt(A) for L2), the stop bar and whether the ray counts
-    float T[4], live_bar[4];
+    // (per-channel queries: T itself, the three objectives' reciprocals and
+    // the smallest objective's bar, as k_pass2)
+    float T[4], live_bar[4], invR[4], invG[4], invB[4];
     bool done[4], positive[4];
     int64_t ray_global[4];
     uint32_t alive = 0u;
@@ -891,9 +919,23 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         const bool inside = ((R.valid >> k) & 1u) && px < V.W && py < V.H;
         ray_global[k] = V.ray_base + (int64_t)py * V.W + px;
         const bool scored = inside && ray_selected(S.ray_mask, ray_global[k]);
-        const float Af = scored ? S.ray_A[V.ray_local + (int64_t)py * V.W + px] : 0.0f;
+        const int64_t rl = V.ray_local + (int64_t)py * V.W + px;
+        const float Af = scored ? S.ray_A[rl] : 0.0f;
         const float invA = Af > 0.0f ? 1.0f / Af : 0.0f;
         positive[k] = invA > 0.0f;
+        if (kCh) {
+            const float AG = scored ? S.ray_A[S.ray_stride + rl] : 0.0f;
+            const float AB = scored ? S.ray_A[2 * S.ray_stride + rl] : 0.0f;
+            invR[k] = invA;
+            invG[k] = AG > 0.0f ? 1.0f / AG : 0.0f;
+            invB[k] = AB > 0.0f ? 1.0f / AB : 0.0f;
+            positive[k] = positive[k] || invG[k] > 0.0f || invB[k] > 0.0f;
+            T[k] = 1.0f;
+            live_bar[k] = a.share_floor * fminf(Af, fminf(AG, AB));
+            done[k] = !positive[k];
+            alive |= (((R.valid >> k) & 1u) && !__all(done[k])) ? (1u << k) : 0u;
+            continue;
+        }
         // the share's denominator: the ray's A, or the A of the ray's query
         float invQ = invA;
         if (kAgg != 0) {
@@ -928,11 +970,19 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             const int64_t o = vbase + g;
             const float4 r0 = S.R[o].m;
             const float4 r1 = S.R[o].q;
-            const float cb = S.CB[o];
-            const float la = __builtin_amdgcn_logf(r1.w);
+            float cb;
             RegionRec &q = rec[__popcll(bal & lt)];
             q.g = make_float4((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);
-            q.c = make_float4(r1.z, la, cb, cut + la);
+            if (kCh) {
+                const float4 c3 = S.R3[o];
+                cb = c3.x;
+                q.c = make_float4(r1.z, r1.w, c3.x, c3.y);
+                q.cblue = c3.z;
+            } else {
+                cb = S.CB[o];
+                const float la = __builtin_amdgcn_logf(r1.w);
+                q.c = make_float4(r1.z, la, cb, cut + la);
+            }
             q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
             q.sid = g;
             if (kAgg == 0) {
@@ -942,7 +992,8 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 // below that by more than the rounding of v_rcp_f32 and the
                 // products (and is 0, which lets every positive x through, for
                 // tiny c)
-                q.bar = (sold > 0.0f && cb >= 0x1p-100f) ? (sold * __builtin_amdgcn_rcpf(cb)) * 0.99999905f : 0.0f;
+                if (!kCh)
+                    q.bar = (sold > 0.0f && cb >= 0x1p-100f) ? (sold * __builtin_amdgcn_rcpf(cb)) * 0.99999905f : 0.0f;
             }
         }
         uint64_t bq[4];
@@ -1003,26 +1054,34 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                         const float dxq[2] = {xl - G.x, xl - M1.x};
                         const float dy0 = yl - G.y, dy1 = yl - M1.y;
                         const float dyq[2] = {dy0, dy1};
-                        const float tq[2] = {fmaf(C.x, dy0 * dy0, C.y), fmaf(C.x, dy1 * dy1, C.y)};
+                        const float tq[2] = {kCh ? C.x * (dy0 * dy0) : fmaf(C.x, dy0 * dy0, C.y),
+                                             kCh ? C.x * (dy1 * dy1) : fmaf(C.x, dy1 * dy1, C.y)};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             if (bq[k] & lowbit) {
                                 const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
                                 const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
                                 const float E = __builtin_amdgcn_exp2f(P);
-                                const bool in_fp = P >= C.w;
-                                const float rho = in_fp ? E : 0.0f;
-                                // the share is c x, and c x is monotone in x:
-                                // the entry's largest share is c times its
-                                // largest x (rounding is monotone too)
+                                const float bar = kCh ? cut : C.w;
+                                const bool in_fp = P >= bar;
+                                const float rho = in_fp ? (kCh ? C.y * E : E) : 0.0f;
                                 const float rt = rho * T[k];
-                                const float x = kMode == kModeL1 ? rt : rt * rt;
+                                float x;
+                                if (kCh) {
+                                    // the share itself, as k_pass2 forms it
+                                    x = rt * fmaxf(C.z * invR[k], fmaxf(C.w * invG[k], q.cblue * invB[k]));
+                                } else {
+                                    // the share is c x, and c x is monotone in
+                                    // x: the entry's largest share is c times
+                                    // its largest x (rounding is monotone too)
+                                    x = kMode == kModeL1 ? rt : rt * rt;
+                                }
                                 m = umax32(m, __float_as_uint(x));
                                 if (kStats) {
                                     const float later = kMode == kModeL2 ? (T[k] * T[k]) * cmax : T[k] * cmax;
                                     n_in += (positive[k] && in_fp) ? 1u : 0u;
                                     n_live += (positive[k] && in_fp && later >= live_bar[k]) ? 1u : 0u;
-                                    const bool am = positive[k] && fabsf(P - C.w) <= amb_band;
+                                    const bool am = positive[k] && fabsf(P - bar) <= amb_band;
                                     n_amb += am ? 1u : 0u;
                                     amb |= am ? (1u << k) : 0u;
                                 }
@@ -1036,13 +1095,13 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 // sensitivity (slots past n hold share 0, which beats none)
                 uint64_t beat = 0ull;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > rec[jb + i].bar);
+                for (int i = 0; i < 16; ++i) beat |= __ballot(sh[i] > (kCh ? rec[jb + i].sold : rec[jb + i].bar));
                 if (beat != 0ull) {
                     const float mx = wave_transpose_max16(sh);
                     const int j = jb + (lane >> 2);
                     if ((lane & 3) == 0 && j < n) {
                         // (a share cannot exceed 1; its rounding can, by an ulp or two)
-                        const float share = fminf(rec[j].c.z * mx, 1.0f);
+                        const float share = fminf(kCh ? mx : rec[j].c.z * mx, 1.0f);
                         if (share > rec[j].sold) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(share));
                     }
                 }
@@ -1102,9 +1161,9 @@ static inline unsigned flat_grid(const CompositeArgs &a) {
     return (unsigned)(((a.total_tiles << a.quad_log) + 7) & ~7);
 }
 
-// The flat form of the one-query modes over every quadrant runs by regions
-// (k_pass1_region, bit-identical); ray-masked runs over a quadrant list, the
-// persistent form and per-channel queries run by quadrants.
+// The flat form over every quadrant runs by regions (k_pass1_region,
+// bit-identical, every query mode); runs over a quadrant list (sparse ray
+// masks) and the persistent form run by quadrants.
 template <int kMode>
 static void pass1_mode(const CompositeArgs &a, hipStream_t st) {
     if constexpr (kMode != kModeChannel) {
@@ -1114,11 +1173,11 @@ static void pass1_mode(const CompositeArgs &a, hipStream_t st) {
             hipLaunchKernelGGL((k_pass1<true, kMode>), dim3(grid), dim3(kWave), 0, st, a);
             return;
         }
-        if (!a.quad_list) {
-            const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
-            hipLaunchKernelGGL((k_pass1_region<kMode>), dim3(grid), dim3(kWave), 0, st, a);
-            return;
-        }
+    }
+    if (!a.quad_list) {
+        const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
+        hipLaunchKernelGGL((k_pass1_region<kMode>), dim3(grid), dim3(kWave), 0, st, a);
+        return;
     }
     hipLaunchKernelGGL((k_pass1<false, kMode>), dim3(flat_grid(a)), dim3(kWave), 0, st, a);
 }
@@ -1172,20 +1231,18 @@ static void pass2_ray(const CompositeArgs &a, bool stats, uint64_t *counters, hi
     }
 }
 
-// With compaction, pass 2 takes the form pass 1 took: the region form
-// (flat one-query launches with no quadrant list) reads the region lists,
-// the others the quadrant lists.
+// With compaction, pass 2 takes the form pass 1 took: the region form (flat
+// launches with no quadrant list) reads the region lists, the others the
+// quadrant lists.
 template <int kMode, bool kPersistentForm>
 static void pass2_ray_any(const CompositeArgs &a, bool stats, uint64_t *counters, hipStream_t st) {
-    if constexpr (kMode != kModeChannel) {
-        if (a.ccount && !a.work && !a.quad_list) {
-            const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
-            if (stats)
-                hipLaunchKernelGGL((k_pass2_region<true, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
-            else
-                hipLaunchKernelGGL((k_pass2_region<false, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
-            return;
-        }
+    if (a.ccount && !a.work && !a.quad_list) {
+        const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
+        if (stats)
+            hipLaunchKernelGGL((k_pass2_region<true, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+        else
+            hipLaunchKernelGGL((k_pass2_region<false, kMode>), dim3(grid), dim3(kWave), 0, st, a, counters);
+        return;
     }
     if (a.ccount)
         pass2_ray<kMode, kPersistentForm, true>(a, stats, counters, st);

@@ -77,6 +77,32 @@ def test_variant_pair_count_without_stop(gs, ora, mode):
     _check(f"nostop/{mode}", s.double().cpu().numpy(), ref["s"])
 
 
+@pytest.mark.parametrize("mode", ["rgbsum", "l2", "channel"])
+def test_sparse_mask_parity(gs, ora, mode):
+    """A sparse ray mask (six 8x8 pixel blocks per view, well under a quarter
+    of the quadrants) makes the library composite only the listed quadrants,
+    one wave each, instead of the region launches that the dense masks of the
+    other tests take; the same bar against the oracle on the same rays."""
+    qm = {"rgbsum": gs.QUERY_RGBSUM, "l2": gs.QUERY_L2, "channel": gs.QUERY_CHANNEL}[mode]
+    sc, vw = _ragged()
+    prm = ora.default_params(query_mode=qm)
+    flag = ora.sensitivity(sc, vw, prm)["flag"]
+    W, H = 200, 136
+    rng = np.random.default_rng(11)
+    sel = np.zeros(3 * W * H, bool)
+    for v in range(3):
+        for _ in range(6):
+            bx, by = int(rng.integers(0, W // 8)), int(rng.integers(0, H // 8))
+            for y in range(8 * by, 8 * by + 8):
+                sel[v * W * H + y * W + 8 * bx: v * W * H + y * W + 8 * bx + 8] = True
+    bits = synth.pack_bits(sel & ~flag)
+    ref = ora.sensitivity(sc, vw, prm, bits)
+    s, st = gs.sensitivity(gs.DeviceScene.from_scene(sc), vw, query_mode=qm, ray_mask=_mask_tensor(bits),
+                           stats=True, count_pairs=True)
+    _check(f"sparse/{mode}", s.double().cpu().numpy(), ref["s"])
+    assert st["n_rays_positive"] == ref["rays_positive"]
+
+
 def test_channel_at_least_rgbsum(gs):
     """A pixel's RGB-sum share is a weighted mean of its channel shares, so
     the per-channel sensitivities bound the RGB-sum ones from above."""
