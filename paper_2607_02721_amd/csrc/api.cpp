@@ -686,6 +686,7 @@ CompositeArgs composite_args(const ChunkRun &r, int total_tiles, const gs_params
                              const Setup &S) {
     CompositeArgs a{};
     a.quad_log = S.quad_log;
+    a.clist_pos = S.agg == GS_AGG_TILE ? 1 : 0;
     a.region_log = region_log_of(S.tsx, S.tsy);
     a.views = r.views_dev;
     a.tile_view = r.tile_view;
@@ -840,10 +841,9 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
     S.nchunks = (int)((S.N + (1 << kChunkBits) - 1) >> kChunkBits);
     S.agg = params->aggregate;
     S.nq = params->query_mode == GS_QUERY_CHANNEL ? 3 : 1;
-    // per-ray, per-image and per-scene queries composite on compacted lists
-    // (per-tile accumulators are indexed by list position: those walk the
-    // tile lists)
-    S.compact = S.agg != GS_AGG_TILE;
+    // every granularity composites on compacted lists (per-tile queries keep
+    // list positions in them: their accumulators are indexed by position)
+    S.compact = true;
     const auto chunks = plan_chunks(views, S, params, scratch_budget());
     launch_fill_u32((uint32_t *)sens, 0u, S.N, st);
     // per-scene queries: the absolute contributions and A summed over chunks

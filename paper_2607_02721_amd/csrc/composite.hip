@@ -553,7 +553,9 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
                 q.c = make_float4(r1.z, la, cb, cut + la);
             }
         }
-        if (cl && h) __builtin_nontemporal_store(g | (h << 28), &cl[ccnt + (uint32_t)__popcll(bal & lt)]);
+        if (cl && h)
+            __builtin_nontemporal_store((a.clist_pos ? (uint32_t)(e - start) : g) | (h << 28),
+                                        &cl[ccnt + (uint32_t)__popcll(bal & lt)]);
         ccnt += (uint32_t)n;
         uint64_t bq[4];
 #pragma unroll
@@ -880,17 +882,19 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
 // and at most one atomic per entry instead of one per (quadrant, entry).
 // The value reduced is x = rho T (L1) or (rho T)^2 (L2), of which the share
 // is c x: one product per entry instead of one per pair.
-// With kAgg (2: per-image, 3: per-scene queries) the shares are against the
-// query's A and summed instead: per quadrant, the 16 entries' shares go
-// through the transposed sum of k_pass2 (the same per-pixel shares and the
-// same sums over each quadrant's 64 pixels), each sum becomes u64 fixed point
-// as there, and the quadrants' integers are added before one atomic per entry.
+// With kAgg (1: per-tile, 2: per-image, 3: per-scene queries) the shares are
+// against the query's A and summed instead: per quadrant, the 16 entries'
+// shares go through the transposed sum of k_pass2 (the same per-pixel shares
+// and the same sums over each quadrant's 64 pixels), each sum becomes u64
+// fixed point as there, and the quadrants' integers are added before one
+// atomic per entry.  Per-tile queries read list positions from the region
+// lists (CompositeArgs::clist_pos) and accumulate per list entry.
 template <bool kStats, int kMode, int kAgg = 0>
 __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(CompositeArgs a,
                                                                          uint64_t *__restrict__ counters) {
     constexpr bool kCh = kMode == kModeChannel;
     static_assert(!(kCh && kAgg != 0), "per-channel queries have no aggregated form");
-    static_assert(kAgg == 0 || kAgg == 2 || kAgg == 3, "per-tile queries walk the tile lists");
+    static_assert(kAgg >= 0 && kAgg <= 3, "query granularities 0 (ray) to 3 (scene)");
     static_assert(!(kAgg != 0 && kStats), "aggregated queries count no pairs");
     __shared__ RegionRec rec[kWave];
     const int lane = threadIdx.x;
@@ -939,7 +943,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         // the share's denominator: the ray's A, or the A of the ray's query
         float invQ = invA;
         if (kAgg != 0) {
-            const double qA = kAgg == 2 ? a.query_A[v] : a.query_A[0];
+            const double qA = kAgg == 1 ? a.query_A[gt] : (kAgg == 2 ? a.query_A[v] : a.query_A[0]);
             invQ = (invA > 0.0f && qA > 0.0) ? (float)(1.0 / qA) : 0.0f;
         }
         T[k] = kMode == kModeL2 ? sqrtf(invQ) : invQ;
@@ -966,7 +970,10 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         const uint64_t bal = __ballot(h != 0u);
         const int n = __popcll(bal);
         if (h) {
-            const uint32_t g = raw & kIndexMask;
+            // (per-tile queries: the list holds the entry's position in the
+            // tile's list, whose entry gives the Gaussian)
+            const uint32_t pos = raw & kIndexMask;
+            const uint32_t g = kAgg == 1 ? S.lists[start + pos] & kIndexMask : pos;
             const int64_t o = vbase + g;
             const float4 r0 = S.R[o].m;
             const float4 r1 = S.R[o].q;
@@ -984,7 +991,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 q.c = make_float4(r1.z, la, cb, cut + la);
             }
             q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
-            q.sid = g;
+            q.sid = kAgg == 1 ? pos : g;
             if (kAgg == 0) {
                 const float sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
                 q.sold = sold;
@@ -1033,7 +1040,8 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 }
                 const int j = jb + (lane >> 2);
                 if ((lane & 3) == 0 && j < n && acc) {
-                    const int64_t idx = kAgg == 2 ? vbase + rec[j].sid : (int64_t)rec[j].sid;
+                    const int64_t idx = kAgg == 1 ? (int64_t)(start + rec[j].sid)
+                                                  : (kAgg == 2 ? vbase + rec[j].sid : (int64_t)rec[j].sid);
                     atomicAdd((unsigned long long *)&a.acc[idx], (unsigned long long)acc);
                 }
             }
@@ -1250,15 +1258,17 @@ static void pass2_ray_any(const CompositeArgs &a, bool stats, uint64_t *counters
         pass2_ray<kMode, kPersistentForm, false>(a, stats, counters, st);
 }
 
-// Aggregated queries run the flat form without pair counters (image and
-// scene queries by regions on the region lists when pass 1 left them);
+// Aggregated queries run the flat form without pair counters (by regions on
+// the region lists when pass 1 left them);
 // per-channel queries have no aggregated or persistent form (the host
 // rejects the first).
 template <int kMode>
 static bool pass2_agg_region(const CompositeArgs &a, hipStream_t st) {
-    if (!(a.ccount && !a.work && !a.quad_list && (a.agg == 2 || a.agg == 3))) return false;
+    if (!(a.ccount && !a.work && !a.quad_list && a.agg >= 1 && a.agg <= 3)) return false;
     const unsigned grid = (unsigned)(((a.total_tiles << a.region_log) + 7) & ~7);
-    if (a.agg == 2)
+    if (a.agg == 1)
+        hipLaunchKernelGGL((k_pass2_region<false, kMode, 1>), dim3(grid), dim3(kWave), 0, st, a, nullptr);
+    else if (a.agg == 2)
         hipLaunchKernelGGL((k_pass2_region<false, kMode, 2>), dim3(grid), dim3(kWave), 0, st, a, nullptr);
     else
         hipLaunchKernelGGL((k_pass2_region<false, kMode, 3>), dim3(grid), dim3(kWave), 0, st, a, nullptr);

@@ -269,6 +269,8 @@ struct CompositeArgs {
                                  // the region form: per region, at the region's first quadrant)
     uint64_t clist_shift;        // subtracted from every compacted-list offset (launches over a tile range
                                  // whose compacted lists fill a pool from its start)
+    int32_t clist_pos;           // 1: the region lists hold each entry's position in its tile's list instead
+                                 // of its Gaussian index (per-tile queries index their accumulators by it)
     const uint32_t *quad_list;   // ray-masked runs: the quadrants ((tile << quad_log) + q) holding a selected ray,
     int32_t n_listed;            // in order; only these are composited (null: every quadrant)
     float report_floor;          // pass 2 reports no share below the share floor: the float just below it, or 0
