@@ -285,59 +285,77 @@ __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const Vie
 }
 
 // nvis[v] = sum, cmax[v] = maximum, kmin[v] / kmax[v] = smallest / largest
-// kept depth key of the per-block values of view v (one block per view); each
-// block's count is replaced by the kept keys of the blocks before it (the
-// offsets launch_key_compact writes at).  Thread t takes a contiguous run of
-// blocks so that a block scan of the runs' sums gives those offsets.
-__global__ __launch_bounds__(256) void k_proj_reduce(uint4 *__restrict__ part, int Vc, int64_t nblk,
-                                                     uint32_t *__restrict__ nvis, uint32_t *__restrict__ cmax_bits,
-                                                     uint32_t *__restrict__ kmin) {
-    __shared__ uint32_t sh[4][4];
-    __shared__ uint32_t pre[256];
+// kept depth key of the per-block values of view v (one block of 1024
+// threads per view); each block's count is replaced by the kept keys of the
+// blocks before it (the offsets launch_key_compact writes at).  Thread t
+// takes a contiguous run of blocks so that a scan of the runs' sums (DPP
+// inside each wave, then the 16 wave sums) gives those offsets.
+constexpr int kReduceThreads = 1024;
+
+__device__ __forceinline__ uint32_t wave_incl_scan_add(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_proj_reduce(uint4 *__restrict__ part, int Vc, int64_t nblk,
+                                                                uint32_t *__restrict__ nvis,
+                                                                uint32_t *__restrict__ cmax_bits,
+                                                                uint32_t *__restrict__ kmin) {
+    constexpr int kW = kReduceThreads / 64;
+    __shared__ uint32_t sh[4][kW];
     const int v = blockIdx.x;
-    const int64_t per = (nblk + 255) / 256;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t per = (nblk + kReduceThreads - 1) / kReduceThreads;
     const int64_t lo = (int64_t)threadIdx.x * per, hi = min(lo + per, nblk);
     uint4 *pv = part + (int64_t)v * nblk;
     uint32_t cnt = 0, cm = 0, klo = 0xFFFFFFFFu, khi = 0;
-    for (int64_t w = lo; w < hi; ++w) {
-        const uint4 q = pv[w];
+    for (int64_t b = lo; b < hi; ++b) {
+        const uint4 q = pv[b];
         cnt += q.x;
         cm = max(cm, q.y);
         klo = min(klo, q.z);
         khi = max(khi, q.w);
     }
-    pre[threadIdx.x] = cnt;
+    const uint32_t incl = wave_incl_scan_add(cnt);
+    if (lane == 63) sh[0][w] = incl;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t x = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
-        __syncthreads();
-        pre[threadIdx.x] += x;
-        __syncthreads();
+    uint32_t run = incl - cnt, total = 0;
+    for (int k = 0; k < kW; ++k) {
+        run += k < w ? sh[0][k] : 0u;
+        total += sh[0][k];
     }
-    uint32_t run = pre[threadIdx.x] - cnt;
-    for (int64_t w = lo; w < hi; ++w) {
-        const uint32_t c = pv[w].x;
-        pv[w].x = run;
+    for (int64_t b = lo; b < hi; ++b) {
+        const uint32_t c = pv[b].x;
+        pv[b].x = run;
         run += c;
     }
     for (int off = 32; off > 0; off >>= 1) {
-        cnt += __shfl_xor(cnt, off);
         cm = max(cm, (uint32_t)__shfl_xor((int)cm, off));
         klo = min(klo, (uint32_t)__shfl_xor((int)klo, off));
         khi = max(khi, (uint32_t)__shfl_xor((int)khi, off));
     }
-    if ((threadIdx.x & 63) == 0) {
-        sh[0][threadIdx.x >> 6] = cnt;
-        sh[1][threadIdx.x >> 6] = cm;
-        sh[2][threadIdx.x >> 6] = klo;
-        sh[3][threadIdx.x >> 6] = khi;
+    if (lane == 0) {
+        sh[1][w] = cm;
+        sh[2][w] = klo;
+        sh[3][w] = khi;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        nvis[v] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-        cmax_bits[v] = max(max(sh[1][0], sh[1][1]), max(sh[1][2], sh[1][3]));
-        kmin[v] = min(min(sh[2][0], sh[2][1]), min(sh[2][2], sh[2][3]));
-        kmin[Vc + v] = max(max(sh[3][0], sh[3][1]), max(sh[3][2], sh[3][3]));
+        uint32_t m = 0, mn = 0xFFFFFFFFu, mx = 0;
+        for (int k = 0; k < kW; ++k) {
+            m = max(m, sh[1][k]);
+            mn = min(mn, sh[2][k]);
+            mx = max(mx, sh[3][k]);
+        }
+        nvis[v] = total;
+        cmax_bits[v] = m;
+        kmin[v] = mn;
+        kmin[Vc + v] = mx;
     }
 }
 
@@ -347,7 +365,7 @@ static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const
     const int64_t blocks = proj_blocks(sc.n);
     hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R,
                        b.CB, b.XY, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
-    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(256), 0, st, (uint4 *)b.proj_part, Vc, blocks,
+    hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(kReduceThreads), 0, st, (uint4 *)b.proj_part, Vc, blocks,
                        b.nvis, b.cmax, b.kmin);
 }
 
