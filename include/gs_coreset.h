@@ -132,10 +132,13 @@ typedef struct {
     /* Binning tile of the pipeline, pixels: 8, 16 or 32 each.  Any shape
      * gives the same sensitivities (the tile only decides which lists a
      * Gaussian enters, never which pairs count); wider tiles mean fewer list
-     * entries per Gaussian and more rays per list.  tile_w = tile_h = 0: the
-     * shape gs_tune_tile last chose in this process for the same size class
-     * (the largest view's pixel count and n, each rounded down to a power of
-     * two; for a plan, its largest view and scene), else 16 x 16; a single 0
+     * entries per Gaussian and more rays per list.  A view may take at most
+     * 8160 tiles (1920 x 1080 at 16 x 16, 3840 x 2160 at 32 x 32); larger
+     * views are GS_ERR_UNSUPPORTED.  tile_w = tile_h = 0: the shape
+     * gs_tune_tile last chose in this process for the same size class (the
+     * largest view's pixel count and n, each rounded down to a power of two;
+     * for a plan, its largest view and scene), else 16 x 16, or the first of
+     * 16 x 32 and 32 x 32 that keeps every view within that limit; a single 0
      * side stands for 16.  GS_AGG_TILE queries need 16 x 16 (0 gives it). */
     int32_t tile_w, tile_h;
 } gs_params;

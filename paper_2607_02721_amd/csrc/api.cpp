@@ -323,8 +323,10 @@ std::pair<int, int> size_class(const gs_views *v, int64_t n) {
 }
 
 // The binning tile of a call, from checked parameters: tile_w = tile_h = 0
-// takes the shape the tuner chose for this size class (16 x 16 if it has
-// not run for it, and for tile queries); a single 0 side stands for 16.
+// takes the shape the tuner chose for this size class; if it has not run for
+// it, 16 x 16, or 16 x 32 and then 32 x 32 for views whose 16 x 16 tiles
+// would exceed the per-view limit (tile queries always take 16 x 16); a
+// single 0 side stands for 16.
 void setup_tiles(const gs_params *p, Setup &S, const gs_views *v = nullptr, int64_t n = 0) {
     S.tsx = tile_shift(p->tile_w);
     S.tsy = tile_shift(p->tile_h);
@@ -334,6 +336,14 @@ void setup_tiles(const gs_params *p, Setup &S, const gs_views *v = nullptr, int6
         if (it != g_tile_cache.end()) {
             S.tsx = it->second.first;
             S.tsy = it->second.second;
+        } else if (v && v->size && v->n_views > 0) {
+            static const int shapes[3][2] = {{4, 4}, {4, 5}, {5, 5}};
+            for (const auto &sh : shapes)
+                if (tiles_fit(v, sh[0], sh[1])) {
+                    S.tsx = sh[0];
+                    S.tsy = sh[1];
+                    break;
+                }
         }
     }
     S.quad_log = S.tsx + S.tsy - 6;

@@ -189,3 +189,21 @@ def test_auto_tile_takes_the_tuned_shape(gs):
     plan.status()
     assert torch.equal(out[0], s_b)
     plan.close()
+
+
+def test_auto_tile_widens_for_large_views(gs):
+    """With no tuned shape for the size class, tile="auto" takes 16x32 for a
+    view whose 16x16 tiles exceed the per-view limit (2560x1440: 14 400 tiles
+    of 16x16, 7 200 of 16x32) instead of rejecting it; the result is the
+    explicit 16x32 run's, bit for bit."""
+    import torch
+    sc = synth.make_cluster_scene(8_000, 45, 1)
+    vw = synth.make_orbit_views(1, 46, 2560, 1440)
+    d = gs.DeviceScene.from_scene(sc)
+    with pytest.raises(gs.GsError, match="tiles of 16x16"):
+        gs.sensitivity(d, vw, tile=(16, 16))
+    s_w, st_w = gs.sensitivity(d, vw, stats=True, tile=(16, 32))
+    s_a, st_a = gs.sensitivity(d, vw, stats=True, tile="auto")
+    assert st_a["n_entries"] == st_w["n_entries"]
+    assert torch.equal(s_a, s_w)
+
