@@ -133,8 +133,8 @@ typedef struct {
      * gives the same sensitivities (the tile only decides which lists a
      * Gaussian enters, never which pairs count); wider tiles mean fewer list
      * entries per Gaussian and more rays per list.  A view may take at most
-     * 8160 tiles (1920 x 1080 at 16 x 16, 3840 x 2160 at 32 x 32); larger
-     * views are GS_ERR_UNSUPPORTED.  tile_w = tile_h = 0: the shape
+     * 38912 cells, (tiles_x + 1)(tiles_y + 1): 3840 x 2160 at 16 x 16, 7680 x
+     * 4320 at 32 x 32; larger views are GS_ERR_UNSUPPORTED.  tile_w = tile_h = 0: the shape
      * gs_tune_tile last chose in this process for the same size class (the
      * largest view's pixel count and n, each rounded down to a power of two;
      * for a plan, its largest view and scene), else 16 x 16, or the first of

@@ -239,20 +239,21 @@ gs_status check_views(const gs_views *v, Setup &S) {
                 return fail(GS_ERR_INVALID_ARGUMENT, "view %d: non-finite extrinsics", i);
         S.tiles_x[i] = (W + (1 << S.tsx) - 1) >> S.tsx;
         S.tiles_y[i] = (H + (1 << S.tsy) - 1) >> S.tsy;
-        if (S.tiles_x[i] * S.tiles_y[i] > kMaxTilesPerView)
-            return fail(GS_ERR_UNSUPPORTED, "view %d: %dx%d needs more than %d tiles of %dx%d", i, W, H,
-                        kMaxTilesPerView, 1 << S.tsx, 1 << S.tsy);
+        if ((int64_t)(S.tiles_x[i] + 1) * (S.tiles_y[i] + 1) > kMaxCellsPerView)
+            return fail(GS_ERR_UNSUPPORTED,
+                        "view %d: %dx%d needs more than %d cells ((tiles_x + 1)(tiles_y + 1)) with tiles of %dx%d",
+                        i, W, H, kMaxCellsPerView, 1 << S.tsx, 1 << S.tsy);
         S.ray_base[i + 1] = S.ray_base[i] + (int64_t)W * H;
     }
     return GS_OK;
 }
 
-// Whether every view (already checked) takes at most kMaxTilesPerView tiles
-// of 2^tsx x 2^tsy.
+// Whether every view (already checked) stays within kMaxCellsPerView with
+// tiles of 2^tsx x 2^tsy.
 bool tiles_fit(const gs_views *v, int tsx, int tsy) {
     for (int i = 0; i < v->n_views; ++i) {
         const int64_t tx = (v->size[2 * i] + (1 << tsx) - 1) >> tsx, ty = (v->size[2 * i + 1] + (1 << tsy) - 1) >> tsy;
-        if (tx * ty > kMaxTilesPerView) return false;
+        if ((tx + 1) * (ty + 1) > kMaxCellsPerView) return false;
     }
     return true;
 }

@@ -502,7 +502,8 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
                 const int tx0 = max(xl >> sx, c0), ty0 = max(yl >> sy, r0);
                 const int nx = min(xh >> sx, c1 - 1) - tx0 + 1;
                 // j / nx as floor((j + 1/2) r) with r within one ulp of 1/nx:
-                // exact for nx * ny <= 8160 (checked exhaustively on the host)
+                // exact for nx * ny <= 8160 (checked exhaustively on the host;
+                // only groups of several tile rows divide)
                 const int dy = kEmitRows == 1 ? 0 : (int)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
                 const int tx = tx0 + (j - dy * nx), ty = kEmitRows == 1 ? r0 : ty0 + dy;
                 const int tc = kEmitRows == 1 ? tx - c0 : (ty - r0) * ncols + (tx - c0);
@@ -587,6 +588,15 @@ void launch_bin_count(const ViewDev *views_dev, int Vc, int64_t N, int nchunks, 
                       const uint32_t *xr, const uint32_t *yr, int max_cells, hipStream_t st) {
     const int64_t run = 8 * kCountGroup;
     const int64_t blocks = ((int64_t)nchunks * Vc + run - 1) / run * run;
+    static const bool lds_ok = [] {
+        // views up to kMaxCellsPerView cells take more than 64 KiB of LDS
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_bin_count),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kMaxCellsPerView * (int)sizeof(int32_t));
+        if (e != hipSuccess) (void)hipGetLastError();
+        return e == hipSuccess;
+    }();
+    (void)lds_ok;
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)blocks), dim3(kBinThreads), (size_t)max_cells * sizeof(int32_t),
                        st, views_dev, Vc, N, nchunks, b.nvis, xr, yr, b.bin_count, b.tile_active, b.rowbits,
                        b.rows_stride);

@@ -12,7 +12,10 @@ namespace gs {
 constexpr int kTileShiftDefault = 4;
 constexpr int kQuad = 8;           // compositing quadrant edge: one wave per 8x8 quadrant
 constexpr int kChunkBits = 14;     // depth ranks are binned in chunks of 2^14 (one list segment per tile)
-constexpr int kMaxTilesPerView = 8160;  // two u32 LDS arrays of this size fit 64 KiB
+// The counting kernel keeps a view's 2D difference array of
+// (tiles_x + 1)(tiles_y + 1) int32 cells in LDS beside its 4 KiB of row
+// words: 38 912 cells (152 KiB) fit the 160 KiB a workgroup may take on CDNA4.
+constexpr int kMaxCellsPerView = 38912;
 constexpr int kSortTile = 4096;    // radix sort: keys per block (4 waves x 16 rounds x 64 lanes)
 constexpr int kBinPositions = 1 << kChunkBits;  // binning: depth-sorted positions per chunk (count block)
 constexpr int kEmitBatch = 1024;   // emission: positions a wave queues at a time

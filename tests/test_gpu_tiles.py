@@ -159,7 +159,7 @@ def test_shape_errors(gs, ragged, base16):
         gs.sensitivity(d, vw, tile=(12, 16))
     with pytest.raises(gs.GsError, match="16x16"):
         gs.sensitivity(d, vw, tile=(32, 32), aggregate=gs.AGG_TILE)
-    big = synth.make_orbit_views(1, 3, 1920, 1080)
+    big = synth.make_orbit_views(1, 3, 3840, 2160)
     with pytest.raises(gs.GsError, match="tiles of 8x8"):
         gs.sensitivity(d, big, tile=(8, 8))
 
@@ -193,12 +193,12 @@ def test_auto_tile_takes_the_tuned_shape(gs):
 
 def test_auto_tile_widens_for_large_views(gs):
     """With no tuned shape for the size class, tile="auto" takes 16x32 for a
-    view whose 16x16 tiles exceed the per-view limit (2560x1440: 14 400 tiles
-    of 16x16, 7 200 of 16x32) instead of rejecting it; the result is the
+    view whose 16x16 tiles exceed the per-view limit (5120x2880: 58 101 cells
+    of 16x16, 29 211 of 16x32) instead of rejecting it; the result is the
     explicit 16x32 run's, bit for bit."""
     import torch
     sc = synth.make_cluster_scene(8_000, 45, 1)
-    vw = synth.make_orbit_views(1, 46, 2560, 1440)
+    vw = synth.make_orbit_views(1, 46, 5120, 2880)
     d = gs.DeviceScene.from_scene(sc)
     with pytest.raises(gs.GsError, match="tiles of 16x16"):
         gs.sensitivity(d, vw, tile=(16, 16))
@@ -207,3 +207,16 @@ def test_auto_tile_widens_for_large_views(gs):
     assert st_a["n_entries"] == st_w["n_entries"]
     assert torch.equal(s_a, s_w)
 
+
+def test_large_view_at_16x16(gs):
+    """A 3840x2160 view at 16x16 tiles (32 776 cells: a 128 KiB difference
+    array in the counting kernel's LDS) gives the same sensitivities as at
+    32x32, bit for bit."""
+    import torch
+    sc = synth.make_cluster_scene(8_000, 47, 1)
+    vw = synth.make_orbit_views(1, 48, 3840, 2160)
+    d = gs.DeviceScene.from_scene(sc)
+    s16, _ = gs.sensitivity(d, vw, tile=(16, 16))
+    s32, _ = gs.sensitivity(d, vw, tile=(32, 32))
+    assert torch.equal(s16, s32)
+    assert float(s16.max()) > 0.0
