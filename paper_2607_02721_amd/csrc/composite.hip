@@ -405,7 +405,9 @@ struct __align__(16) RegionRec {
     float2 m1;
     float sold;
     uint32_t sid;
-    float bar, cblue, pad[2];
+    float bar, cblue;
+    uint32_t hq;   // the entry's quadrant bits
+    float pad;
 };
 
 // Region `logical` of the launch: its tile, view, scene slot, origin and, per
@@ -992,6 +994,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             }
             q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
             q.sid = kAgg == 1 ? pos : g;
+            q.hq = h;
             if (kAgg == 0) {
                 const float sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
                 q.sold = sold;
@@ -1009,21 +1012,23 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         if (kStats) n_eval += (uint64_t)(__popcll(bq[0]) + __popcll(bq[1]) + __popcll(bq[2]) + __popcll(bq[3]));
         wave_sync();
         if constexpr (kAgg != 0) {
+            // per quadrant, its entries as bits in slot order (slot j is the
+            // j-th lane of bal): the loops below test one bit per slot
+            const uint32_t hs = lane < n ? rec[lane].hq : 0u;
+            uint64_t sq[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sq[k] = __ballot((hs >> k) & 1u);
             for (int jb = 0; jb < n; jb += 16) {
                 uint64_t acc = 0ull;   // lane 4 i: entry jb + i's fixed-point sum over the quadrants
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (!(((alive >> k) & 1u) && bq[k])) continue;
-                    // the block's entries in slot order; lowbit walks bal again
-                    uint64_t rk = bal;
-                    for (int x = 0; x < jb; ++x) rk &= rk - 1ull;
+                    const uint32_t m16 = ((alive >> k) & 1u) ? (uint32_t)(sq[k] >> jb) & 0xFFFFu : 0u;
+                    if (!m16) continue;
                     float sh[16];
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        const uint64_t lowbit = rk & (~rk + 1ull);
-                        rk ^= lowbit;
                         float share = 0.0f;
-                        if (bq[k] & lowbit) {
+                        if ((m16 >> i) & 1u) {
                             const RegionRec &q = rec[jb + i];
                             const float4 G = q.g, C = q.c;
                             const float mx = (k & 1) ? q.m1.x : G.x, my = (k >> 1) ? q.m1.y : G.y;
@@ -1046,16 +1051,22 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 }
             }
         } else {
-            // slot j: the j-th lane of bal, its quadrant bits in bq[k]
-            uint64_t rem = bal;
+            // per quadrant, its entries as bits in slot order (slot j is the
+            // j-th lane of bal): one bit test per slot and quadrant
+            const uint32_t hs = lane < n ? rec[lane].hq : 0u;
+            uint64_t sq[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sq[k] = __ballot((hs >> k) & 1u);
             for (int jb = 0; jb < n; jb += 16) {
+                uint32_t mq[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) mq[k] = (uint32_t)(sq[k] >> jb) & 0xFFFFu;
+                const uint32_t mall = mq[0] | mq[1] | mq[2] | mq[3];
                 float sh[16];
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    const uint64_t lowbit = rem & (~rem + 1ull);
-                    rem ^= lowbit;
                     uint32_t m = 0u;
-                    if (lowbit) {
+                    if ((mall >> i) & 1u) {
                         const RegionRec &q = rec[jb + i];
                         const float4 G = q.g, C = q.c;
                         const float2 M1 = q.m1;
@@ -1066,7 +1077,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                                              kCh ? C.x * (dy1 * dy1) : fmaf(C.x, dy1 * dy1, C.y)};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            if (bq[k] & lowbit) {
+                            if ((mq[k] >> i) & 1u) {
                                 const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
                                 const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
                                 const float E = __builtin_amdgcn_exp2f(P);
