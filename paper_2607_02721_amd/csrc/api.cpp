@@ -896,6 +896,11 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
             a.quad_list = r.quad_list;
             a.n_listed = r.n_listed;
         }
+        // per-tile queries composited by regions (every region one whole
+        // 16x16 query): the region lists hold Gaussians and pass 2 takes each
+        // share's maximum itself, with no per-entry accumulators
+        const bool tile_direct = S.agg == GS_AGG_TILE && a.ccount && !a.quad_list && !a.work;
+        if (tile_direct) a.clist_pos = 0;
         if (r.ranges.size() > 1) {
             // per-ray queries through a compaction room that holds part of
             // the chunk's lists: pass 1 and pass 2 of one tile range after
@@ -947,11 +952,11 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
             a.acc = r.acc;
             const int64_t n_acc = S.agg == GS_AGG_TILE ? std::max<int64_t>(r.n_entries, 1)
                                                        : (S.agg == GS_AGG_IMAGE ? (int64_t)c.vc * S.N : S.N);
-            launch_fill_u64(r.acc, 0ull, n_acc, st);
+            if (!tile_direct) launch_fill_u64(r.acc, 0ull, n_acc, st);
         }
         launch_composite_pass2(a, (params->flags & GS_FLAG_COUNT_PAIRS) != 0, r.b.counters, st);
         HIP_TRY(hipGetLastError());
-        if (S.agg != GS_AGG_RAY) {
+        if (S.agg != GS_AGG_RAY && !tile_direct) {
             launch_agg_finalize(S.agg, r.acc, r.b.lists, (uint64_t)r.n_entries, S.N, c.vc, (uint32_t *)sens,
                                 agg_num, agg_den, r.view_A + c.vc, st);
             HIP_TRY(hipGetLastError());

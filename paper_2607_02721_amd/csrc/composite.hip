@@ -889,8 +889,10 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
 // shares go through the transposed sum of k_pass2 (the same per-pixel shares
 // and the same sums over each quadrant's 64 pixels), each sum becomes u64
 // fixed point as there, and the quadrants' integers are added before one
-// atomic per entry.  Per-tile queries read list positions from the region
-// lists (CompositeArgs::clist_pos) and accumulate per list entry.
+// atomic per entry.  Per-tile queries (16x16 binning tiles: one region per
+// tile, so a region is one whole query) take the share's maximum at once when
+// the region lists hold Gaussians; with list positions
+// (CompositeArgs::clist_pos) they accumulate per list entry instead.
 template <bool kStats, int kMode, int kAgg = 0>
 __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(CompositeArgs a,
                                                                          uint64_t *__restrict__ counters) {
@@ -975,7 +977,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             // (per-tile queries: the list holds the entry's position in the
             // tile's list, whose entry gives the Gaussian)
             const uint32_t pos = raw & kIndexMask;
-            const uint32_t g = kAgg == 1 ? S.lists[start + pos] & kIndexMask : pos;
+            const uint32_t g = (kAgg == 1 && a.clist_pos) ? S.lists[start + pos] & kIndexMask : pos;
             const int64_t o = vbase + g;
             const float4 r0 = S.R[o].m;
             const float4 r1 = S.R[o].q;
@@ -993,7 +995,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 q.c = make_float4(r1.z, la, cb, cut + la);
             }
             q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
-            q.sid = kAgg == 1 ? pos : g;
+            q.sid = (kAgg == 1 && a.clist_pos) ? pos : g;
             q.hq = h;
             if (kAgg == 0) {
                 const float sold = fmaxf(__uint_as_float(sens_bits[g]), a.report_floor);
@@ -1045,9 +1047,18 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 }
                 const int j = jb + (lane >> 2);
                 if ((lane & 3) == 0 && j < n && acc) {
-                    const int64_t idx = kAgg == 1 ? (int64_t)(start + rec[j].sid)
-                                                  : (kAgg == 2 ? vbase + rec[j].sid : (int64_t)rec[j].sid);
-                    atomicAdd((unsigned long long *)&a.acc[idx], (unsigned long long)acc);
+                    if (kAgg == 1 && !a.clist_pos) {
+                        // the region is the whole 16x16 query and the list
+                        // holds the Gaussian: the sum is complete, so its share
+                        // raises the sensitivity here (the value k_agg_tile_max
+                        // takes from an accumulator of the same integers)
+                        const float sq_share = (float)((double)acc * (1.0 / kAggScale));
+                        if (sq_share > 0.0f) atomicMax(&sens_bits[rec[j].sid], __float_as_uint(sq_share));
+                    } else {
+                        const int64_t idx = kAgg == 1 ? (int64_t)(start + rec[j].sid)
+                                                      : (kAgg == 2 ? vbase + rec[j].sid : (int64_t)rec[j].sid);
+                        atomicAdd((unsigned long long *)&a.acc[idx], (unsigned long long)acc);
+                    }
                 }
             }
         } else {

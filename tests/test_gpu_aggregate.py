@@ -74,6 +74,25 @@ def test_aggregated_parity(gs, ora, which, level):
     _check(f"{which}/{level}", s.double().cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("level", LEVELS)
+def test_sparse_mask_aggregated_parity(gs, ora, level):
+    """A mask that selects one row of 8x8 quadrants per view (1 of 17) takes
+    the quadrant-list form of both passes (per-tile queries: per-entry
+    accumulators and a separate maximum); the other tests' dense masks take
+    the region form (per-tile queries: the maximum in the region waves).
+    Both score the same rays as the oracle."""
+    sc, vw = _ragged()
+    flag = ora.sensitivity(sc, vw)["flag"]
+    sel = np.zeros((3, 136, 200), bool)
+    sel[:, 16:24, :] = True
+    bits = synth.pack_bits(sel.reshape(-1) & ~flag)
+    ref = ora.sensitivity_agg(sc, vw, getattr(ora, "AGG_" + level.upper()), ray_mask=bits)
+    assert (ref > 0).any()
+    d = gs.DeviceScene.from_scene(sc)
+    s, _ = gs.sensitivity(d, vw, ray_mask=_mask_tensor(bits), aggregate=_level(gs, level))
+    _check(f"sparse/{level}", s.double().cpu().numpy(), ref)
+
+
 def test_views_in_several_chunks(gs, ora):
     """One view per launch: tile and image queries never straddle launches,
     so they are bit-identical to one launch; the per-scene sums are carried
