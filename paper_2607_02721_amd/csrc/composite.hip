@@ -172,11 +172,23 @@ __device__ __forceinline__ bool quad_hit(float mx, float my, float beta, float a
     return best <= C + err;
 }
 
+// The staged geometry of an entry: with u = dx + beta dy and the exponent's
+// coefficient a' < 0, the exponent a' u^2 + t equals t - (s u)^2 for
+// s = sqrt(-a'), and s u = (s x - s mean_x) + (s beta) dy.  Staged as
+// (-s mean_x, mean_y, s beta, s), a pixel's exponent then takes one FMA for
+// s dx, one for s u and one for t - (s u)^2 (instead of a product and an FMA
+// for a' u u).  Every form of both passes and the objectives stage through
+// here, so they form the same exponents.
+__device__ __forceinline__ float4 scaled_geo(float mx, float my, float beta, float a2) {
+    const float sc = __builtin_amdgcn_sqrtf(-a2);
+    return make_float4(-sc * mx, my, sc * beta, sc);
+}
+
 // Stage the slice's entries whose footprint reaches this quadrant (pixel
 // range bit, then the exact test above); returns how many.  With kPad > 1
 // the slots up to the next multiple of kPad hold null entries, so a loop can
 // run in unguarded blocks of kPad pairs.
-// geo = (mean_x, mean_y relative to the quadrant origin, beta, a'),
+// geo = scaled_geo(mean_x, mean_y relative to the quadrant origin, beta, a'),
 // col = (g', alpha, cbar, extra), or with kChannel (g', alpha, c_R, c_G) and
 // c_B in cblue.  With kLog (no extra value, one query per ray) col = (g',
 // log2 alpha, cbar, cut + log2 alpha) for pair_rho_log2; null entries then
@@ -231,7 +243,7 @@ __device__ __forceinline__ int stage_raw(const WaveSetup &w, uint32_t raw, uint6
         } else {
             cb = CB[o];
         }
-        geo[slot] = make_float4(mx, my, r1.x, r1.y);
+        geo[slot] = scaled_geo(mx, my, r1.x, r1.y);
         float extra = 0.0f;
         if (kExtra == 1) {
             sid[slot] = g;
@@ -286,7 +298,7 @@ __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t 
         } else {
             cb = w.CB[o];
         }
-        geo[lane] = make_float4((r0.x - w.qx0) + r0.z, (r0.y - w.qy0) + r0.w, r1.x, r1.y);
+        geo[lane] = scaled_geo((r0.x - w.qx0) + r0.z, (r0.y - w.qy0) + r0.w, r1.x, r1.y);
         if (kLog) {
             const float la = __builtin_amdgcn_logf(r1.w);
             col[lane] = make_float4(r1.z, la, cb, cut + la);
@@ -307,11 +319,11 @@ __device__ __forceinline__ int stage_compact(const WaveSetup &w, const uint32_t 
 // inside the footprint (P >= cut), else 0.
 __device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, float xl, float yl, float cut,
                                           bool &in_fp) {
-    const float dx = xl - G.x;
+    const float dx = fmaf(G.w, xl, G.x);   // s (x - mean_x)
     const float dy = yl - G.y;
-    const float u = fmaf(G.z, dy, dx);
+    const float u = fmaf(G.z, dy, dx);      // s u
     const float t = Cc.x * (dy * dy);
-    const float P = fmaf(G.w * u, u, t);
+    const float P = fmaf(-u, u, t);
     const float E = __builtin_amdgcn_exp2f(P);
     in_fp = P >= cut;
     return in_fp ? Cc.y * E : 0.0f;
@@ -321,11 +333,11 @@ __device__ __forceinline__ float pair_rho(const float4 &G, const float4 &Cc, flo
 // with bar = cut + log2 alpha (stage_slice / stage_compact with kLog), so
 // rho = exp2(P + log2 alpha) inside the footprint (P + log2 alpha >= bar).
 __device__ __forceinline__ float pair_rho_log2(const float4 &G, const float4 &Cc, float xl, float yl, bool &in_fp) {
-    const float dx = xl - G.x;
+    const float dx = fmaf(G.w, xl, G.x);
     const float dy = yl - G.y;
     const float u = fmaf(G.z, dy, dx);
     const float t = fmaf(Cc.x, dy * dy, Cc.y);
-    const float P = fmaf(G.w * u, u, t);
+    const float P = fmaf(-u, u, t);
     const float E = __builtin_amdgcn_exp2f(P);
     in_fp = P >= Cc.w;
     return in_fp ? E : 0.0f;
@@ -542,8 +554,9 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
         if (h) {
             const int slot = __popcll(bal & lt);
             RegionRec &q = rec[slot];
-            q.g = make_float4(mx0, my0, r1.x, r1.y);
-            q.m1 = make_float2(mx1, my1);
+            const float4 sg = scaled_geo(mx0, my0, r1.x, r1.y);
+            q.g = sg;
+            q.m1 = make_float2(-sg.w * mx1, my1);
             if (kCh) {
                 // as stage_raw with kChannel: (g', alpha, c_R, c_G), c_B
                 const float4 c3 = S.R3[o];
@@ -579,7 +592,7 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
                 // row's part of the exponent, formed once for the quadrants
                 // that share them (the operations of pair_rho_log2, or of
                 // pair_rho for per-channel queries)
-                const float dxq[2] = {xl - G.x, xl - M1.x};
+                const float dxq[2] = {fmaf(G.w, xl, G.x), fmaf(G.w, xl, M1.x)};
                 const float dy0 = yl - G.y, dy1 = yl - M1.y;
                 const float dyq[2] = {dy0, dy1};
                 const float tq[2] = {kCh ? C.x * (dy0 * dy0) : fmaf(C.x, dy0 * dy0, C.y),
@@ -588,7 +601,7 @@ __global__ __launch_bounds__(kWave) void k_pass1_region(CompositeArgs a) {
                 for (int k = 0; k < 4; ++k) {
                     if (bq[k] & lowbit) {
                         const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
-                        const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
+                        const float P = fmaf(-uu, uu, tq[k >> 1]);
                         const float E = __builtin_amdgcn_exp2f(P);
                         const float rho = kCh ? (P >= cut ? C.y * E : 0.0f) : (P >= C.w ? E : 0.0f);
                         if (kMode == kModeL1) {
@@ -800,10 +813,10 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
                                 n_live += (real && in_fp && later >= live_bar) ? 1u : 0u;
                                 // the exponent against the cutoff, as pair_rho(_log2) forms
                                 // them: P - bar = -(log2 e / 2)(d^2 - r^2)
-                                const float ddx = w.xl - G.x, ddy = w.yl - G.y;
+                                const float ddx = fmaf(G.w, w.xl, G.x), ddy = w.yl - G.y;
                                 const float uu = fmaf(G.z, ddy, ddx);
                                 const float tt = kCh ? Cc.x * (ddy * ddy) : fmaf(Cc.x, ddy * ddy, Cc.y);
-                                const float PP = fmaf(G.w * uu, uu, tt);
+                                const float PP = fmaf(-uu, uu, tt);
                                 const float bar = kCh ? a.r2_log2 : Cc.w;
                                 n_amb += (real && positive && fabsf(PP - bar) <= amb_band) ? 1u : 0u;
                             }
@@ -983,7 +996,8 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
             const float4 r1 = S.R[o].q;
             float cb;
             RegionRec &q = rec[__popcll(bal & lt)];
-            q.g = make_float4((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);
+            const float4 sg = scaled_geo((r0.x - fx0) + r0.z, (r0.y - fy0) + r0.w, r1.x, r1.y);
+            q.g = sg;
             if (kCh) {
                 const float4 c3 = S.R3[o];
                 cb = c3.x;
@@ -994,7 +1008,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                 const float la = __builtin_amdgcn_logf(r1.w);
                 q.c = make_float4(r1.z, la, cb, cut + la);
             }
-            q.m1 = make_float2((r0.x - fx1) + r0.z, (r0.y - fy1) + r0.w);
+            q.m1 = make_float2(-sg.w * ((r0.x - fx1) + r0.z), (r0.y - fy1) + r0.w);
             q.sid = (kAgg == 1 && a.clist_pos) ? pos : g;
             q.hq = h;
             if (kAgg == 0) {
@@ -1081,7 +1095,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                         const RegionRec &q = rec[jb + i];
                         const float4 G = q.g, C = q.c;
                         const float2 M1 = q.m1;
-                        const float dxq[2] = {xl - G.x, xl - M1.x};
+                        const float dxq[2] = {fmaf(G.w, xl, G.x), fmaf(G.w, xl, M1.x)};
                         const float dy0 = yl - G.y, dy1 = yl - M1.y;
                         const float dyq[2] = {dy0, dy1};
                         const float tq[2] = {kCh ? C.x * (dy0 * dy0) : fmaf(C.x, dy0 * dy0, C.y),
@@ -1090,7 +1104,7 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
                         for (int k = 0; k < 4; ++k) {
                             if ((mq[k] >> i) & 1u) {
                                 const float uu = fmaf(G.z, dyq[k >> 1], dxq[k & 1]);
-                                const float P = fmaf(G.w * uu, uu, tq[k >> 1]);
+                                const float P = fmaf(-uu, uu, tq[k >> 1]);
                                 const float E = __builtin_amdgcn_exp2f(P);
                                 const float bar = kCh ? cut : C.w;
                                 const bool in_fp = P >= bar;
