@@ -154,7 +154,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project(SceneDev sc, const Vie
     const double r = pp.footprint_sigma;
     const float cut_pad = 0.01f;
 
-    for (int v = 0; v < Vc; ++v) {
+    // this block's views: group blockIdx.y of gridDim.y near-equal groups
+    const int v0 = (int)((int64_t)blockIdx.y * Vc / gridDim.y);
+    const int v1 = (int)((int64_t)(blockIdx.y + 1) * Vc / gridDim.y);
+    for (int v = v0; v < v1; ++v) {
         const ViewDev &V = views[v];
         const double *R = V.R;
         const double px = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + V.t[0];
@@ -363,7 +366,14 @@ template <int kDeg, int kFmt>
 static void launch_t(const SceneDev &sc, const ViewDev *views_dev, int Vc, const ProjParams &pp, const ChunkBufs &b,
                      hipStream_t st) {
     const int64_t blocks = proj_blocks(sc.n);
-    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R,
+    // Each wave projects its 64 Gaussians into a group of about kProjViews
+    // views (the Gaussian's set-up is repeated per group): with one group a
+    // 1M-Gaussian scene is 15 625 waves, five rounds and a nearly empty sixth
+    // at three waves per SIMD; groups of 25 views make the last round a
+    // small part of the whole.
+    constexpr int kProjViews = 25;
+    const int groups = std::max(1, (Vc + kProjViews - 1) / kProjViews);
+    hipLaunchKernelGGL((k_project<kDeg, kFmt>), dim3((unsigned)blocks, (unsigned)groups), dim3(kProjThreads), 0, st, sc, views_dev, Vc, pp, b.R,
                        b.CB, b.XY, b.R3, b.key0, (uint4 *)b.proj_part, b.counters, b.tile_sat);
     hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)Vc), dim3(kReduceThreads), 0, st, (uint4 *)b.proj_part, Vc, blocks,
                        b.nvis, b.cmax, b.kmin);
