@@ -127,6 +127,19 @@ def test_determinism_and_chunking(gs):
     assert np.array_equal(a, c)
 
 
+def test_many_views_in_view_groups(gs, ora):
+    """61 views in one call: the projection takes each block of Gaussians
+    through three groups of views (20, 20 and 21); every ray against the
+    oracle, and bit-identical to calls of 7 views (one group each)."""
+    sc = synth.make_cluster_scene(3000, 23, 2)
+    vw = synth.make_orbit_views(61, 29, 64, 48)
+    _parity(gs, ora, sc, vw, "61 views")
+    dsc = gs.DeviceScene.from_scene(sc)
+    a, _ = gs.sensitivity(dsc, vw)
+    c, _ = gs.sensitivity(dsc, vw, max_views_per_chunk=7)
+    assert np.array_equal(a.cpu().numpy().view(np.uint32), c.cpu().numpy().view(np.uint32))
+
+
 def test_stats_over_view_chunks(gs):
     """Counters are summed over view chunks of different sizes (3 views in
     chunks of 2 and 1), equal those of one chunk, and stay right on repeated
