@@ -253,8 +253,8 @@ def main():
         tile = tuple(int(x) for x in args.tile.lower().split("x"))
 
     def step(stats=False, count_pairs=False, scene_dev=dsc, aggregate=gs.AGG_RAY, query_mode=gs.QUERY_RGBSUM):
-        # tile queries are 16x16 pixel tiles, binned as such
-        t_ = (16, 16) if aggregate == gs.AGG_TILE else tile
+        # tile queries are 16x16 pixel tiles: binning tiles of 16 or 32 per side
+        t_ = tuple(max(x, 16) for x in tile) if aggregate == gs.AGG_TILE else tile
         s, st = gs.sensitivity(scene_dev, views, stats=stats, count_pairs=count_pairs, aggregate=aggregate,
                                query_mode=query_mode, tile=t_)
         counts, w, sup = gs.sample_coreset(s, m, seed)

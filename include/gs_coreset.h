@@ -139,7 +139,9 @@ typedef struct {
      * largest view's pixel count and n, each rounded down to a power of two;
      * for a plan, its largest view and scene), else 16 x 16, or the first of
      * 16 x 32 and 32 x 32 that keeps every view within that limit; a single 0
-     * side stands for 16.  GS_AGG_TILE queries need 16 x 16 (0 gives it). */
+     * side stands for 16.  GS_AGG_TILE queries need sides of 16 or 32
+     * (GS_ERR_UNSUPPORTED for 8; with 0 a side of 8 becomes 16); their
+     * results do not depend on which. */
     int32_t tile_w, tile_h;
 } gs_params;
 

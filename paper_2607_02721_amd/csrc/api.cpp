@@ -196,7 +196,7 @@ size_t chunk_scratch_bytes(const Setup &S, const ChunkPlan &c) {
     add(sizeof(double) * 3 * quads);                        // objective partials
     add(sizeof(double) * (3 * (size_t)c.vc + 1));
     add(sizeof(uint32_t) * quads);                          // compacted entries per quadrant
-    add(sizeof(double) * (size_t)c.total_tiles);            // per-tile A(Q)
+    add(sizeof(double) * quads);                            // per-region A(Q)
     add(sizeof(double) * ((size_t)c.vc + 1));               // per-view A(Q), launch total
     if (S.agg == GS_AGG_IMAGE) add(sizeof(uint64_t) * (size_t)c.vc * N);   // per (view, Gaussian) shares
     if (S.agg == GS_AGG_SCENE) add(sizeof(uint64_t) * (size_t)N);          // per Gaussian shares
@@ -296,8 +296,9 @@ gs_status check_params(const gs_params *p) {
     if (tw < 0 || th < 0)
         return fail(GS_ERR_INVALID_ARGUMENT, "tile %dx%d: each side must be 8, 16 or 32 (or 0 for 16)", p->tile_w,
                     p->tile_h);
-    if (p->aggregate == GS_AGG_TILE && (tw != 4 || th != 4))
-        return fail(GS_ERR_UNSUPPORTED, "tile queries are 16x16 pixel tiles: they need 16x16 binning tiles");
+    if (p->aggregate == GS_AGG_TILE && (tw < 4 || th < 4))
+        return fail(GS_ERR_UNSUPPORTED,
+                    "tile queries are 16x16 pixel tiles: they need binning tiles of 16 or 32 pixels per side");
     return GS_OK;
 }
 
@@ -331,7 +332,7 @@ std::pair<int, int> size_class(const gs_views *v, int64_t n) {
 void setup_tiles(const gs_params *p, Setup &S, const gs_views *v = nullptr, int64_t n = 0) {
     S.tsx = tile_shift(p->tile_w);
     S.tsy = tile_shift(p->tile_h);
-    if (p->tile_w == 0 && p->tile_h == 0 && p->aggregate != GS_AGG_TILE) {
+    if (p->tile_w == 0 && p->tile_h == 0) {
         std::lock_guard<std::mutex> lk(g_tile_lock);
         const auto it = g_tile_cache.find(size_class(v, n));
         if (it != g_tile_cache.end()) {
@@ -345,6 +346,11 @@ void setup_tiles(const gs_params *p, Setup &S, const gs_views *v = nullptr, int6
                     S.tsy = sh[1];
                     break;
                 }
+        }
+        // (per-tile queries need sides of 16 or 32 pixels)
+        if (p->aggregate == GS_AGG_TILE) {
+            S.tsx = std::max(S.tsx, 4);
+            S.tsy = std::max(S.tsy, 4);
         }
     }
     S.quad_log = S.tsx + S.tsy - 6;
@@ -503,7 +509,7 @@ gs_status run_front(const gs_scene *scene, const gs_views *views, const gs_param
     r.tile_sums = cv.take<double>(3 * ((size_t)c.total_tiles << S.quad_log));
     r.view_sums = cv.take<double>(3 * (size_t)c.vc + 1);
     r.ccount = cv.take<uint32_t>((size_t)c.total_tiles << S.quad_log);
-    r.tile_A = cv.take<double>(c.total_tiles);
+    r.tile_A = cv.take<double>((size_t)c.total_tiles << S.quad_log);
     r.view_A = cv.take<double>((size_t)c.vc + 1);
     r.acc = nullptr;
     if (S.agg == GS_AGG_IMAGE) r.acc = cv.take<uint64_t>((size_t)c.vc * N);
@@ -887,7 +893,10 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         sort_passes = std::max(sort_passes, r.passes);
         CompositeArgs a = composite_args(r, c.total_tiles, params, params->share_floor, S);
         a.ccount = r.host_slot.clist ? r.ccount : nullptr;
-        if (r.quad_list && 4 * (int64_t)r.n_listed <= ((int64_t)c.total_tiles << S.quad_log)) {
+        // (per-tile queries keep the quadrant lists only at 16x16 tiles: their
+        // per-entry accumulators would mix a larger tile's four queries)
+        if (r.quad_list && 4 * (int64_t)r.n_listed <= ((int64_t)c.total_tiles << S.quad_log) &&
+            !(S.agg == GS_AGG_TILE && region_log_of(S.tsx, S.tsy) > 0)) {
             // a sparse mask (a quarter of the quadrants or fewer hold a
             // selected ray): only the listed quadrants are composited, one wave
             // each, and the other rays read A = 0; denser masks take the flat
@@ -901,6 +910,8 @@ gs_status gs_sensitivity(const gs_scene *scene, const gs_views *views, const gs_
         // share's maximum itself, with no per-entry accumulators
         const bool tile_direct = S.agg == GS_AGG_TILE && a.ccount && !a.quad_list && !a.work;
         if (tile_direct) a.clist_pos = 0;
+        if (S.agg == GS_AGG_TILE && !tile_direct && region_log_of(S.tsx, S.tsy) > 0)
+            return fail(GS_ERR_UNSUPPORTED, "tile queries on binning tiles above 16x16 need the region form");
         if (r.ranges.size() > 1) {
             // per-ray queries through a compaction room that holds part of
             // the chunk's lists: pass 1 and pass 2 of one tile range after
@@ -2091,7 +2102,7 @@ gs_status gs_tune_tile(const gs_scene *scene, const gs_views *views, const gs_pa
         gs_params p = *params;
         p.tile_w = sides[k / 3];
         p.tile_h = sides[k % 3];
-        if (p.aggregate == GS_AGG_TILE && (p.tile_w != 16 || p.tile_h != 16)) continue;
+        if (p.aggregate == GS_AGG_TILE && (p.tile_w < 16 || p.tile_h < 16)) continue;
         if (!tiles_fit(views, tile_shift(p.tile_w), tile_shift(p.tile_h))) continue;
         if ((s = gs_sensitivity(scene, views, &p, sens, nullptr, stream)) != GS_OK) break;   // warm-up
         if (hipEventRecord(e0, st) != hipSuccess) s = fail(GS_ERR_DEVICE, "hipEventRecord failed");

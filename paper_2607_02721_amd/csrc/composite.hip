@@ -756,6 +756,8 @@ void k_pass2(CompositeArgs a, uint64_t *__restrict__ counters) {
         // the share's denominator: the ray's A, or the A of the lane's query
         float invQ = invA;
         if (kAgg != 0) {
+            // (per-tile queries take this form only with 16x16 binning
+            // tiles, where a tile is one region and its own query)
             const double qA = kAgg == 1 ? a.query_A[w.gt] : (kAgg == 2 ? a.query_A[w.v] : a.query_A[0]);
             invQ = (invA > 0.0f && qA > 0.0) ? (float)(1.0 / qA) : 0.0f;
         }
@@ -960,7 +962,9 @@ __global__ __launch_bounds__(kWave, kStats ? 5 : 7) void k_pass2_region(Composit
         // the share's denominator: the ray's A, or the A of the ray's query
         float invQ = invA;
         if (kAgg != 0) {
-            const double qA = kAgg == 1 ? a.query_A[gt] : (kAgg == 2 ? a.query_A[v] : a.query_A[0]);
+            // (per-tile queries: the region's own A(Q), entry (tile << region_log) + region)
+            const double qA = kAgg == 1 ? a.query_A[((int64_t)gt << a.region_log) + (logical & ((1 << a.region_log) - 1))]
+                                        : (kAgg == 2 ? a.query_A[v] : a.query_A[0]);
             invQ = (invA > 0.0f && qA > 0.0) ? (float)(1.0 / qA) : 0.0f;
         }
         T[k] = kMode == kModeL2 ? sqrtf(invQ) : invQ;
@@ -1343,30 +1347,42 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 
 // One wave per tile: lane l sums the tile's pixels l, l + 64, ... (row-major).
 __global__ __launch_bounds__(kWave) void k_tile_A(CompositeArgs a, double *__restrict__ tile_A) {
-    const int t = blockIdx.x;
+    // one wave per region (up to 2 x 2 quadrants, as setup_region places
+    // them): with binning tiles of 16 or 32 pixels per side a region is a
+    // 16x16 pixel block on 16-pixel boundaries, the query of per-tile
+    // aggregation; entry (tile << region_log) + region
+    const int q = blockIdx.x;
+    const int t = q >> a.region_log, rg = q & ((1 << a.region_log) - 1);
     const int v = a.tile_view[t];
     const SceneSlot &S = a.slots[0];
     const ViewDev &V = a.views[v];
     const int tl = t - V.tile_base;
     const int tx = tl % V.tiles_x, ty = tl / V.tiles_x;
     const int lane = threadIdx.x;
-    const int tw = 1 << V.tsx, area = tw << V.tsy;
+    const int qlx = V.tsx - 3, qly = V.tsy - 3;
+    const int rlx = qlx > 1 ? qlx - 1 : 0;
+    const int kxn = qlx > 0 ? 2 : 1, kyn = qly > 0 ? 2 : 1;
+    const int ox = (tx << V.tsx) + kQuad * kxn * (rg & ((1 << rlx) - 1));
+    const int oy = (ty << V.tsy) + kQuad * kyn * (rg >> rlx);
+    const int rw = kQuad * kxn, area = rw * kQuad * kyn;
     double sum = 0.0;
     for (int k = lane; k < area; k += kWave) {
-        const int px = (tx << V.tsx) + (k & (tw - 1)), py = (ty << V.tsy) + (k >> V.tsx);
+        const int px = ox + k % rw, py = oy + k / rw;
         if (px < V.W && py < V.H) sum += (double)S.ray_A[V.ray_local + (int64_t)py * V.W + px];
     }
     sum = wave_sum_f64(sum);
-    if (lane == 0) tile_A[t] = sum;
+    if (lane == 0) tile_A[q] = sum;
 }
 
-// One wave per view: the sum of its tiles' A(Q).
+// One wave per view: the sum of its regions' A(Q).
 __global__ __launch_bounds__(kWave) void k_view_A(const ViewDev *__restrict__ views,
-                                                  const double *__restrict__ tile_A, double *__restrict__ view_A) {
+                                                  const double *__restrict__ tile_A, double *__restrict__ view_A,
+                                                  int region_log) {
     const ViewDev &V = views[blockIdx.x];
-    const int nt = V.tiles_x * V.tiles_y;
+    const int nt = (V.tiles_x * V.tiles_y) << region_log;
+    const int64_t base = (int64_t)V.tile_base << region_log;
     double sum = 0.0;
-    for (int t = threadIdx.x; t < nt; t += kWave) sum += tile_A[V.tile_base + t];
+    for (int t = threadIdx.x; t < nt; t += kWave) sum += tile_A[base + t];
     sum = wave_sum_f64(sum);
     if (threadIdx.x == 0) view_A[blockIdx.x] = sum;
 }
@@ -1383,8 +1399,9 @@ __global__ __launch_bounds__(kWave) void k_total_A(const double *__restrict__ vi
 void launch_query_sums(const CompositeArgs &a, int Vc, double *tile_A, double *view_A, double *total,
                        hipStream_t st) {
     if (a.total_tiles <= 0 || Vc <= 0) return;
-    hipLaunchKernelGGL(k_tile_A, dim3(a.total_tiles), dim3(kWave), 0, st, a, tile_A);
-    hipLaunchKernelGGL(k_view_A, dim3(Vc), dim3(kWave), 0, st, a.views, (const double *)tile_A, view_A);
+    hipLaunchKernelGGL(k_tile_A, dim3((unsigned)(a.total_tiles << a.region_log)), dim3(kWave), 0, st, a, tile_A);
+    hipLaunchKernelGGL(k_view_A, dim3(Vc), dim3(kWave), 0, st, a.views, (const double *)tile_A, view_A,
+                       a.region_log);
     if (total) hipLaunchKernelGGL(k_total_A, dim3(1), dim3(kWave), 0, st, (const double *)view_A, Vc, total);
 }
 

@@ -93,6 +93,29 @@ def test_sparse_mask_aggregated_parity(gs, ora, level):
     _check(f"sparse/{level}", s.double().cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("tile", [(16, 32), (32, 16), (32, 32)])
+def test_tile_queries_on_larger_binning_tiles(gs, ora, tile):
+    """Per-tile queries binned at 16x32, 32x16 or 32x32: each 16x16 region of
+    a binning tile is one query, composited by its own wave; bit-identical to
+    16x16 binning, dense or sparse mask (the sparse one takes the region
+    form here, the quadrant-list form at 16x16), and the sparse run against
+    the oracle."""
+    import torch
+    sc, vw = _ragged()
+    d = gs.DeviceScene.from_scene(sc)
+    flag = ora.sensitivity(sc, vw)["flag"]
+    sel = np.zeros((3, 136, 200), bool)
+    sel[:, 16:24, :] = True
+    for bits in (synth.pack_bits(~flag), synth.pack_bits(sel.reshape(-1) & ~flag)):
+        m = _mask_tensor(bits)
+        s16, _ = gs.sensitivity(d, vw, ray_mask=m, aggregate=gs.AGG_TILE, tile=(16, 16))
+        s, _ = gs.sensitivity(d, vw, ray_mask=m, aggregate=gs.AGG_TILE, tile=tile)
+        torch.cuda.synchronize()
+        assert torch.equal(s, s16), tile
+    ref = ora.sensitivity_agg(sc, vw, ora.AGG_TILE, ray_mask=bits)
+    _check(f"tile queries at {tile[0]}x{tile[1]}", s.double().cpu().numpy(), ref)
+
+
 def test_views_in_several_chunks(gs, ora):
     """One view per launch: tile and image queries never straddle launches,
     so they are bit-identical to one launch; the per-scene sums are carried
