@@ -425,6 +425,7 @@ __global__ __launch_bounds__(kEmitWave) void k_bin_emit(const ViewDev *__restric
     constexpr int kWords = kBinPositions / 64;
     const uint64_t *rbits =
         rowbits + ((int64_t)v * rows_stride + r0) * ((int64_t)nchunks * kWords) + (int64_t)chunk * kWords;
+    static_assert(kEmitBatch % 64 == 0 && kEmitBatch <= 64 * kEmitWave, "one row-bitmap word per lane");
     for (int b0 = 0; b0 < hi; b0 += kEmitBatch) {
         const int b1 = min(b0 + kEmitBatch, hi);
         // 1. positions of the batch that meet row r0, in order: lane l < 16
