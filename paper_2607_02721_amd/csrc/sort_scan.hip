@@ -116,7 +116,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                  const uint32_t *__restrict__ kbase,
                                                                  const uint32_t *__restrict__ seg_len,
                                                                  uint32_t *__restrict__ status,
-                                                                 uint32_t *__restrict__ extra, int pass) {
+                                                                 uint32_t *__restrict__ extra, int pass,
+                                                                 int n_segs) {
     // per wave and digit: the wave's count while ranking, then (thread d
     // rewrites its own column once it has read it) the block-local start of
     // the wave's run of digit d; one array instead of two keeps the block
@@ -128,8 +129,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     __shared__ uint32_t wsum4[4];        // digit counts of each wave's 64 digits
     __shared__ uint32_t lkey[kSortTile], lval[kSortTile];
     __shared__ int tick;
-    const int seg = blockIdx.y;
-    int b = blockIdx.x;
+    // blocks go to the XCDs in turn (block i to XCD i mod 8): block i works
+    // on segment 8 (i / 8 / nb) + i mod 8, so each segment's scattered lines
+    // are written through one L2; its place in the segment is its ticket
+    const int64_t bi = blockIdx.x;
+    const int seg = (int)(((bi >> 3) / nb) * 8 + (bi & 7));
+    if (seg >= n_segs) return;
+    int b;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t *ex = extra + (int64_t)seg * kSweepExtra;
     // block number in the order the segment's blocks started: every block
@@ -257,9 +263,10 @@ hipError_t radix_sort_segments(uint32_t *key0, uint32_t *val0, uint32_t *key1, u
         const uint32_t *kb = pass == 0 ? kbase : nullptr;
         launch_fill_u32(hist, 0u, nstatus, st);
         // the last pass writes the values only (nothing reads the sorted keys)
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nb, n_segs), dim3(kSortThreads), 0, st, ki, vi,
+        const int64_t blocks = (int64_t)nb * ((n_segs + 7) / 8) * 8;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)blocks), dim3(kSortThreads), 0, st, ki, vi,
                            pass + 1 < passes ? ko : nullptr, vo, n_per_seg, nb, shift,
-                           (pass == 0 && vals_are_iota) ? 1 : 0, kb, seg_len, hist, extra, pass);
+                           (pass == 0 && vals_are_iota) ? 1 : 0, kb, seg_len, hist, extra, pass, n_segs);
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
